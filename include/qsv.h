@@ -1,0 +1,178 @@
+/*
+ * qsv.h -- C ABI of the gfx950 state-vector library (libqsv.so).
+ *
+ * The calls follow the paper's statement of the problem (section III, the
+ * hardware-abstraction layer of a quantum virtual machine; section IV.A, the
+ * XACC accelerator / buffer / instruction model; section V.B, its program
+ * listing): a host program allocates a qubit buffer, executes gate
+ * instructions (name, qubits, parameters) in program order, and reads back
+ * expectation values of Hamiltonian terms or measurement samples.  Here the
+ * buffer is an exact 2^n-amplitude state vector resident in GPU memory
+ * (the "brute-force" representation of section I) and the instructions are
+ * applied in place by hand-written HIP kernels.
+ *
+ * Conventions that hold for every call:
+ *   - Amplitudes are stored contiguously as interleaved (re, im) pairs:
+ *     complex64 (8 bytes) or complex128 (16 bytes) -- the memory layout of
+ *     torch.complex64 / torch.complex128.  Qubit q is bit q of the index.
+ *   - For a k-qubit operation on qubits (q[0], ..., q[k-1]) the local matrix
+ *     index is m = sum_j bit(q[j]) * 2^j, i.e. the FIRST listed qubit is the
+ *     least-significant bit.  CNOT and CPHASE list (control, target).
+ *   - Rotations are R_P(theta) = exp(-i theta P / 2).
+ *   - Matrices are passed in complex128 (row-major, interleaved re, im) and
+ *     rounded once to the state's precision inside the library.
+ *   - Reductions (norm, expectation values, sampling prefix sums) accumulate
+ *     in FP64 in a fixed order, so repeated calls give identical results.
+ *   - No state is ever renormalised.
+ *   - Every function returns a qsv_status; none throws, aborts or exits.
+ *     On failure the thread-local message from qsv_last_error() says why.
+ *
+ * Threading and streams: all work on one state is issued to the HIP stream
+ * given at allocation.  Different states may be used concurrently from
+ * different threads.  Concurrent calls on the same state are a caller error
+ * (detected best-effort, QSV_ERR_STATE).  Calls that return host results
+ * (norm, expval, sample, copies) synchronise that stream before returning;
+ * calls that only apply gates are stream-ordered and return immediately.
+ */
+#ifndef LIBQSV_ABI_H_
+#define LIBQSV_ABI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QSV_OK = 0,
+  QSV_ERR_ARG = -1,          /* invalid argument (range, duplicate qubit, NaN, size) */
+  QSV_ERR_OOM = -2,          /* device allocation failed */
+  QSV_ERR_HIP = -3,          /* HIP runtime error (text in qsv_last_error) */
+  QSV_ERR_UNSUPPORTED = -4,  /* valid request this build does not implement */
+  QSV_ERR_STATE = -5         /* bad or freed handle, or concurrent use of one state */
+} qsv_status;
+
+typedef enum { QSV_C64 = 1, QSV_C128 = 2 } qsv_dtype;
+
+/* Gate identifiers.  Matrices (FP64, then rounded):
+ *   I, X, Y, Z (Pauli), H = [[1,1],[1,-1]]/sqrt2, S = diag(1,i), SDG = S^dag,
+ *   T = diag(1,e^{i pi/4}), TDG = T^dag,
+ *   RX/RY/RZ(theta) = exp(-i theta P/2) (params[0] = theta),
+ *   CNOT(control, target), CZ = diag(1,1,1,-1),
+ *   CPHASE(control, target; params[0] = phi) = diag(1,1,1,e^{i phi}),
+ *   SWAP, and QSV_MAT: an explicit 2^k x 2^k matrix (qsv_op.mat). */
+typedef enum {
+  QSV_I = 0, QSV_X = 1, QSV_Y = 2, QSV_Z = 3, QSV_H = 4, QSV_S = 5, QSV_SDG = 6,
+  QSV_T = 7, QSV_TDG = 8, QSV_RX = 9, QSV_RY = 10, QSV_RZ = 11, QSV_CNOT = 12,
+  QSV_CZ = 13, QSV_CPHASE = 14, QSV_SWAP = 15, QSV_MAT = 16
+} qsv_gate;
+
+#define QSV_MAX_QUBITS 40   /* largest register accepted by qsv_alloc_state */
+#define QSV_MAX_K 6         /* widest explicit matrix (2^6 x 2^6) */
+
+/* Opaque handle of one device-resident state vector. */
+typedef struct qsv_state qsv_state;
+
+/* One instruction of a gate list (paper section IV.A: an instruction is a
+ * name plus the qubits it acts on; section V.B: with angle parameters).
+ * 64 bytes, no padding. */
+typedef struct qsv_op {
+  int32_t gate;        /* qsv_gate */
+  int32_t nq;          /* number of qubits: 1 or 2 for named gates, 1..QSV_MAX_K for QSV_MAT */
+  int32_t q[6];        /* qubits; q[0] is the least-significant bit of the local index */
+  double p[3];         /* angles: RX/RY/RZ/CPHASE read p[0] */
+  const double* mat;   /* QSV_MAT only: 2^nq x 2^nq complex128, row-major, re/im interleaved */
+} qsv_op;
+
+/* Execution strategy of qsv_apply_circuit.
+ *   mode 0 = automatic (fused tile passes), 1 = one kernel per gate
+ *   ("plain per-gate form"), 2 = fused tile passes.
+ *   tile_qubits: qubits per LDS tile in fused mode (0 = library choice).
+ *   Other fields are reserved and must be zero. */
+typedef struct qsv_plan_opts {
+  int32_t mode;
+  int32_t tile_qubits;
+  int32_t reserved[6];
+} qsv_plan_opts;
+
+/* Allocate a state of n_qubits (1..QSV_MAX_QUBITS) initialised to |0...0>.
+ * ext_dev_ptr == NULL: the library allocates (hipMalloc) and owns the memory.
+ * ext_dev_ptr != NULL: the state borrows caller memory of ext_bytes bytes
+ *   (>= 2^n * bytes-per-amplitude, 256-byte aligned, e.g. a torch tensor's
+ *   storage); the caller keeps it alive until qsv_free_state.
+ * stream: hipStream_t for all work on this state (NULL = default stream).
+ * Paper section III: host-managed buffer of the virtual machine.
+ * Errors: QSV_ERR_ARG (n, dtype, size/alignment), QSV_ERR_OOM, QSV_ERR_HIP. */
+qsv_status qsv_alloc_state(int n_qubits, qsv_dtype dtype, void* ext_dev_ptr, size_t ext_bytes,
+                           void* stream, qsv_state** out);
+
+/* Release the handle (and the memory, if the library owns it).  Waits for
+ * the state's pending work.  NULL is accepted and ignored. */
+qsv_status qsv_free_state(qsv_state* s);
+
+/* Query n, dtype and the device pointer of the amplitudes. */
+qsv_status qsv_state_info(const qsv_state* s, int* n_qubits, int* dtype, void** dev_ptr);
+
+/* Reset to the basis state |x> (x < 2^n). */
+qsv_status qsv_set_basis(qsv_state* s, uint64_t x);
+
+/* Apply one named gate in place (paper section IV.A: one instruction visit).
+ * qubits: nq distinct qubits in [0, n); params: np angles (np must equal the
+ * gate's parameter count).  QSV_MAT is not accepted here (use
+ * qsv_apply_fused).  One HBM pass (or less for diagonal / permutation gates).
+ * Errors: QSV_ERR_ARG. */
+qsv_status qsv_apply_gate(qsv_state* s, int gate, const int32_t* qubits, int nq,
+                          const double* params, int np);
+
+/* Apply an explicit 2^k x 2^k matrix (a fused super-gate, paper section II:
+ * gates grouped into aggregates acting as a whole) to k distinct qubits,
+ * 1 <= k <= QSV_MAX_K.  mat: complex128 row-major interleaved, read during
+ * the call only.  k >= 4 runs on the matrix cores.  Errors: QSV_ERR_ARG. */
+qsv_status qsv_apply_fused(qsv_state* s, const int32_t* qubits, int k, const double* mat);
+
+/* Execute a whole gate list in program order (paper section IV.A: the
+ * accelerator's execute() on an IR function).  opts may be NULL (automatic).
+ * The fused mode groups gates into LDS tile passes (paper section II: SWAP
+ * augmentation and super-gate aggregation, done on the index space); the
+ * mathematical result equals per-gate application up to rounding.
+ * Errors: QSV_ERR_ARG for any invalid op (nothing is applied then). */
+qsv_status qsv_apply_circuit(qsv_state* s, const qsv_op* ops, int n_ops,
+                             const qsv_plan_opts* opts);
+
+/* Expectation value of sum_t coeff[t] * P_t (paper section V.B: one
+ * expectation value per Hamiltonian term).  Each Pauli string P_t is given
+ * by bit masks: qubit q carries X if only xmask bit q is set, Z if only zmask
+ * bit q is set, Y if both.  out_total (host, may be NULL) receives the sum;
+ * out_terms (host, may be NULL, n_terms doubles) receives coeff[t] * <P_t>.
+ * Accumulation in FP64.  Errors: QSV_ERR_ARG (masks beyond n, NaN coeff). */
+qsv_status qsv_expval(qsv_state* s, const uint64_t* xmask, const uint64_t* zmask,
+                      const double* coeff, int n_terms, double* out_total, double* out_terms);
+
+/* sum_i |psi_i|^2 in FP64 (host result). */
+qsv_status qsv_norm(qsv_state* s, double* out);
+
+/* Measurement samples of the full register without collapse (paper section
+ * V.B, MEASURE).  For each caller-supplied uniform u in [0, 1) returns the
+ * smallest index i with C_i > u * C_{N-1}, C the FP64 inclusive prefix sum of
+ * |psi_i|^2 (bit q of the index = outcome of qubit q).  uniforms and out are
+ * host arrays of n_shots entries.  Errors: QSV_ERR_ARG (u outside [0,1),
+ * n_shots < 0). */
+qsv_status qsv_sample(qsv_state* s, const double* uniforms, int n_shots, uint64_t* out);
+
+/* Copy the raw amplitudes to / from host memory (bytes must equal the state
+ * size).  Synchronous. */
+qsv_status qsv_copy_to_host(qsv_state* s, void* dst, size_t bytes);
+qsv_status qsv_copy_from_host(qsv_state* s, const void* src, size_t bytes);
+
+/* Wait for all work issued on the state's stream. */
+qsv_status qsv_synchronize(qsv_state* s);
+
+/* Human-readable description of the last failure on this thread (valid until
+ * the next call on this thread). */
+const char* qsv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBQSV_ABI_H_ */

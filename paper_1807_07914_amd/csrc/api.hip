@@ -1,0 +1,551 @@
+// api.hip -- the C ABI of libqsv: argument validation, the library's own
+// FP64 gate table, and dispatch of each instruction to the gfx950 kernels.
+//
+// Paper section IV.A: the accelerator executes an instruction list by a
+// pre-order traversal, dispatching each concrete instruction to its visit
+// method; here dispatch is an opcode switch that selects a specialised
+// kernel (general 2x2, diagonal, 4x4, permutation, dense k-qubit block).
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "internal.hpp"
+#include "plan.hpp"
+
+namespace qsv {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+const char* get_error() { return g_err.c_str(); }
+
+qsv_status fail(qsv_status code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+qsv_status hip_fail(hipError_t e, const char* where) {
+  set_error(std::string("HIP error ") + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ") in " +
+            where);
+  return e == hipErrorOutOfMemory ? QSV_ERR_OOM : QSV_ERR_HIP;
+}
+
+// live-handle registry: rejects freed or foreign pointers
+static std::mutex g_reg_mu;
+static std::unordered_set<const qsv_state*> g_live;
+
+static bool is_live(const qsv_state* s) {
+  std::lock_guard<std::mutex> lk(g_reg_mu);
+  return s && g_live.count(s) && s->magic == kStateMagic;
+}
+
+// RAII guard against concurrent use of one state
+struct Busy {
+  qsv_state* s;
+  bool ok;
+  explicit Busy(qsv_state* st) : s(st) {
+    int expect = 0;
+    ok = s->busy.compare_exchange_strong(expect, 1);
+  }
+  ~Busy() {
+    if (ok) s->busy.store(0);
+  }
+};
+
+#define QSV_ENTER(s)                                                                  \
+  if (!::qsv::is_live(s)) return ::qsv::fail(QSV_ERR_STATE, "invalid or freed state handle"); \
+  ::qsv::Busy busy_guard_(s);                                                         \
+  if (!busy_guard_.ok) return ::qsv::fail(QSV_ERR_STATE, "state is in use by another call");
+
+qsv_status ensure_workspace(qsv_state* s, size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (s->ws_bytes >= bytes) return QSV_OK;
+  if (s->ws) {
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    QSV_HIP(hipFree(s->ws));
+    s->ws = nullptr;
+    s->ws_bytes = 0;
+  }
+  size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+  hipError_t e = hipMalloc(&s->ws, want);
+  if (e != hipSuccess) {
+    s->ws = nullptr;
+    return hip_fail(e, "hipMalloc(workspace)");
+  }
+  s->ws_bytes = want;
+  return QSV_OK;
+}
+
+// ------------------------------------------------------------ gate table
+using cd = std::complex<double>;
+
+int gate_nparams(int g) {
+  return (g == QSV_RX || g == QSV_RY || g == QSV_RZ || g == QSV_CPHASE) ? 1 : 0;
+}
+
+int gate_arity(int g) {
+  if (g >= QSV_I && g <= QSV_RZ) return 1;
+  if (g >= QSV_CNOT && g <= QSV_SWAP) return 2;
+  return -1;
+}
+
+// FP64 matrix of a named gate (row-major, 2^k x 2^k; two-qubit gates use the
+// first listed qubit as the least-significant local bit).
+int gate_matrix(int g, const double* p, cd* m) {
+  const double r = std::sqrt(0.5);
+  for (int i = 0; i < 16; ++i) m[i] = 0.0;
+  const cd I(0.0, 1.0);
+  switch (g) {
+    case QSV_I: m[0] = m[3] = 1.0; return 1;
+    case QSV_X: m[1] = m[2] = 1.0; return 1;
+    case QSV_Y: m[1] = -I; m[2] = I; return 1;
+    case QSV_Z: m[0] = 1.0; m[3] = -1.0; return 1;
+    case QSV_H: m[0] = m[1] = m[2] = r; m[3] = -r; return 1;
+    case QSV_S: m[0] = 1.0; m[3] = I; return 1;
+    case QSV_SDG: m[0] = 1.0; m[3] = -I; return 1;
+    case QSV_T: m[0] = 1.0; m[3] = std::polar(1.0, M_PI / 4); return 1;
+    case QSV_TDG: m[0] = 1.0; m[3] = std::polar(1.0, -M_PI / 4); return 1;
+    case QSV_RX: {
+      const double c = std::cos(p[0] / 2), s = std::sin(p[0] / 2);
+      m[0] = m[3] = c; m[1] = m[2] = cd(0.0, -s); return 1;
+    }
+    case QSV_RY: {
+      const double c = std::cos(p[0] / 2), s = std::sin(p[0] / 2);
+      m[0] = m[3] = c; m[1] = -s; m[2] = s; return 1;
+    }
+    case QSV_RZ:
+      m[0] = std::polar(1.0, -p[0] / 2); m[3] = std::polar(1.0, p[0] / 2); return 1;
+    case QSV_CNOT:  // |c t>: local index = c + 2t; flip t where c = 1
+      m[0] = 1.0; m[2 * 4 + 2] = 1.0; m[1 * 4 + 3] = 1.0; m[3 * 4 + 1] = 1.0; return 2;
+    case QSV_CZ: m[0] = m[5] = m[10] = 1.0; m[15] = -1.0; return 2;
+    case QSV_CPHASE: m[0] = m[5] = m[10] = 1.0; m[15] = std::polar(1.0, p[0]); return 2;
+    case QSV_SWAP: m[0] = m[15] = 1.0; m[1 * 4 + 2] = m[2 * 4 + 1] = 1.0; return 2;
+    default: return -1;
+  }
+}
+
+bool gate_is_diagonal(int g) {
+  return g == QSV_I || g == QSV_Z || g == QSV_S || g == QSV_SDG || g == QSV_T || g == QSV_TDG ||
+         g == QSV_RZ || g == QSV_CZ || g == QSV_CPHASE;
+}
+
+static bool finite_all(const double* p, int np) {
+  for (int i = 0; i < np; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+static qsv_status check_qubits(const qsv_state* s, const int32_t* q, int k) {
+  if (k < 1 || k > QSV_MAX_K) return fail(QSV_ERR_ARG, "qubit count out of range");
+  if (!q) return fail(QSV_ERR_ARG, "qubit list is NULL");
+  uint64_t seen = 0;
+  for (int j = 0; j < k; ++j) {
+    if (q[j] < 0 || q[j] >= s->n)
+      return fail(QSV_ERR_ARG, "qubit " + std::to_string(q[j]) + " outside [0, " +
+                                   std::to_string(s->n) + ")");
+    if (seen & (1ull << q[j])) return fail(QSV_ERR_ARG, "duplicate qubit " + std::to_string(q[j]));
+    seen |= 1ull << q[j];
+  }
+  return QSV_OK;
+}
+
+qsv_status validate_op(const qsv_state* s, const qsv_op& o) {
+  if (o.gate == QSV_MAT) {
+    if (o.nq < 1 || o.nq > QSV_MAX_K) return fail(QSV_ERR_ARG, "matrix op: nq out of range");
+    if (!o.mat) return fail(QSV_ERR_ARG, "matrix op without matrix");
+    qsv_status st = check_qubits(s, o.q, o.nq);
+    if (st) return st;
+    const int D = 1 << o.nq;
+    if (!finite_all(o.mat, 2 * D * D)) return fail(QSV_ERR_ARG, "non-finite matrix entry");
+    return QSV_OK;
+  }
+  const int k = gate_arity(o.gate);
+  if (k < 0) return fail(QSV_ERR_ARG, "unknown gate id " + std::to_string(o.gate));
+  if (o.nq != k) return fail(QSV_ERR_ARG, "wrong qubit count for gate");
+  qsv_status st = check_qubits(s, o.q, k);
+  if (st) return st;
+  if (!finite_all(o.p, gate_nparams(o.gate))) return fail(QSV_ERR_ARG, "non-finite gate parameter");
+  return QSV_OK;
+}
+
+// ------------------------------------------------------------- dispatch
+template <typename T>
+static cpx<T> rnd(cd z) {
+  return cpx<T>{(T)z.real(), (T)z.imag()};
+}
+
+// Reorder a 4x4 matrix given with local bit order (q0, q1) into the order
+// (lo, hi) = sorted qubits.
+static void canon2(const cd* in, int q0, int q1, cd* out) {
+  if (q0 < q1) {
+    for (int i = 0; i < 16; ++i) out[i] = in[i];
+    return;
+  }
+  auto sw = [](int m) { return ((m & 1) << 1) | ((m >> 1) & 1); };
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) out[sw(r) * 4 + sw(c)] = in[r * 4 + c];
+}
+
+template <typename T>
+static qsv_status apply_matrix_T(qsv_state* s, int k, const int32_t* q, const cd* m, size_t ws_off) {
+  cpx<T>* psi = static_cast<cpx<T>*>(s->psi);
+  hipStream_t st = s->stream;
+  if (k == 1) {
+    if (m[1] == 0.0 && m[2] == 0.0) {
+      QSV_HIP(launch_diag1<T>(psi, s->n, q[0], rnd<T>(m[0]), rnd<T>(m[3]), st));
+    } else {
+      M2<T> U;
+      for (int i = 0; i < 4; ++i) U.m[i] = rnd<T>(m[i]);
+      QSV_HIP(launch_gate1<T>(psi, s->n, q[0], U, st));
+    }
+    return QSV_OK;
+  }
+  if (k == 2) {
+    cd c[16];
+    canon2(m, q[0], q[1], c);
+    M4<T> U;
+    for (int i = 0; i < 16; ++i) U.m[i] = rnd<T>(c[i]);
+    const int lo = q[0] < q[1] ? q[0] : q[1], hi = q[0] < q[1] ? q[1] : q[0];
+    QSV_HIP(launch_gate2<T>(psi, s->n, lo, hi, U, st));
+    return QSV_OK;
+  }
+  const int D = 1 << k;
+  std::vector<cpx<T>> h(D * D);
+  for (int i = 0; i < D * D; ++i) h[i] = rnd<T>(m[i]);
+  cpx<T>* dm = reinterpret_cast<cpx<T>*>(static_cast<char*>(s->ws) + ws_off);
+  QSV_HIP(hipMemcpyAsync(dm, h.data(), h.size() * sizeof(cpx<T>), hipMemcpyHostToDevice, st));
+  int qq[6];
+  for (int j = 0; j < k; ++j) qq[j] = q[j];
+  QSV_HIP(launch_dense<T>(psi, s->n, k, qq, dm, st));
+  return QSV_OK;
+}
+
+template <typename T>
+static qsv_status apply_named_T(qsv_state* s, int g, const int32_t* q, const double* p) {
+  cpx<T>* psi = static_cast<cpx<T>*>(s->psi);
+  hipStream_t st = s->stream;
+  cd m[16];
+  const double zero[3] = {0, 0, 0};
+  gate_matrix(g, p ? p : zero, m);
+  switch (g) {
+    case QSV_I: return QSV_OK;
+    case QSV_Z: case QSV_S: case QSV_SDG: case QSV_T: case QSV_TDG: case QSV_RZ:
+      QSV_HIP(launch_diag1<T>(psi, s->n, q[0], rnd<T>(m[0]), rnd<T>(m[3]), st));
+      return QSV_OK;
+    case QSV_X: case QSV_Y: case QSV_H: case QSV_RX: case QSV_RY: {
+      M2<T> U;
+      for (int i = 0; i < 4; ++i) U.m[i] = rnd<T>(m[i]);
+      QSV_HIP(launch_gate1<T>(psi, s->n, q[0], U, st));
+      return QSV_OK;
+    }
+    case QSV_CNOT: QSV_HIP(launch_cnot<T>(psi, s->n, q[0], q[1], st)); return QSV_OK;
+    case QSV_SWAP: QSV_HIP(launch_swap<T>(psi, s->n, q[0], q[1], st)); return QSV_OK;
+    case QSV_CZ: case QSV_CPHASE:
+      QSV_HIP(launch_cphase<T>(psi, s->n, q[0], q[1], rnd<T>(m[15]), st));
+      return QSV_OK;
+    default: return fail(QSV_ERR_ARG, "unknown gate");
+  }
+}
+
+qsv_status apply_op_pergate(qsv_state* s, const qsv_op& o, size_t ws_off) {
+  if (o.gate == QSV_MAT) {
+    const int D = 1 << o.nq;
+    std::vector<cd> m(D * D);
+    for (int i = 0; i < D * D; ++i) m[i] = cd(o.mat[2 * i], o.mat[2 * i + 1]);
+    return s->dt == QSV_C64 ? apply_matrix_T<float>(s, o.nq, o.q, m.data(), ws_off)
+                            : apply_matrix_T<double>(s, o.nq, o.q, m.data(), ws_off);
+  }
+  return s->dt == QSV_C64 ? apply_named_T<float>(s, o.gate, o.q, o.p)
+                          : apply_named_T<double>(s, o.gate, o.q, o.p);
+}
+
+size_t dense_ws_bytes() { return (size_t)64 * 64 * 16; }
+
+}  // namespace qsv
+
+using namespace qsv;
+
+// ====================================================================== ABI
+extern "C" {
+
+qsv_status qsv_alloc_state(int n_qubits, qsv_dtype dtype, void* ext_dev_ptr, size_t ext_bytes,
+                           void* stream, qsv_state** out) {
+  if (!out) return fail(QSV_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_qubits < 1 || n_qubits > QSV_MAX_QUBITS)
+    return fail(QSV_ERR_ARG, "n_qubits must be in [1, " + std::to_string(QSV_MAX_QUBITS) + "]");
+  if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_ERR_ARG, "dtype must be QSV_C64 or QSV_C128");
+  qsv_state* s = new (std::nothrow) qsv_state();
+  if (!s) return fail(QSV_ERR_OOM, "host allocation failed");
+  s->n = n_qubits;
+  s->dt = dtype;
+  s->N = 1ull << n_qubits;
+  s->amp_bytes = dtype == QSV_C64 ? 8 : 16;
+  s->bytes = s->N * s->amp_bytes;
+  s->stream = static_cast<hipStream_t>(stream);
+  if (ext_dev_ptr) {
+    if (ext_bytes < s->bytes) {
+      delete s;
+      return fail(QSV_ERR_ARG, "external buffer smaller than 2^n amplitudes");
+    }
+    if (reinterpret_cast<uintptr_t>(ext_dev_ptr) % 256 != 0) {
+      delete s;
+      return fail(QSV_ERR_ARG, "external buffer must be 256-byte aligned");
+    }
+    s->psi = ext_dev_ptr;
+    s->owns = false;
+  } else {
+    hipError_t e = hipMalloc(&s->psi, s->bytes);
+    if (e != hipSuccess) {
+      delete s;
+      (void)hipGetLastError();
+      return fail(QSV_ERR_OOM, std::string("hipMalloc of state failed: ") + hipGetErrorString(e));
+    }
+    s->owns = true;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    g_live.insert(s);
+  }
+  hipError_t e = s->dt == QSV_C64
+                     ? launch_init_basis<float>(static_cast<cpx<float>*>(s->psi), s->N, 0, s->stream)
+                     : launch_init_basis<double>(static_cast<cpx<double>*>(s->psi), s->N, 0, s->stream);
+  if (e != hipSuccess) {
+    qsv_free_state(s);
+    return hip_fail(e, "init");
+  }
+  *out = s;
+  return QSV_OK;
+}
+
+qsv_status qsv_free_state(qsv_state* s) {
+  if (!s) return QSV_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    if (!g_live.count(s)) return fail(QSV_ERR_STATE, "invalid or freed state handle");
+    g_live.erase(s);
+  }
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (s->ws) (void)hipFree(s->ws);
+  if (s->owns && s->psi) (void)hipFree(s->psi);
+  s->magic = kDeadMagic;
+  delete s;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(free)");
+  return QSV_OK;
+}
+
+qsv_status qsv_state_info(const qsv_state* s, int* n_qubits, int* dtype, void** dev_ptr) {
+  if (!is_live(s)) return fail(QSV_ERR_STATE, "invalid or freed state handle");
+  if (n_qubits) *n_qubits = s->n;
+  if (dtype) *dtype = s->dt;
+  if (dev_ptr) *dev_ptr = s->psi;
+  return QSV_OK;
+}
+
+qsv_status qsv_set_basis(qsv_state* s, uint64_t x) {
+  QSV_ENTER(s);
+  if (x >= s->N) return fail(QSV_ERR_ARG, "basis index out of range");
+  hipError_t e = s->dt == QSV_C64
+                     ? launch_init_basis<float>(static_cast<cpx<float>*>(s->psi), s->N, x, s->stream)
+                     : launch_init_basis<double>(static_cast<cpx<double>*>(s->psi), s->N, x, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "set_basis");
+  return QSV_OK;
+}
+
+qsv_status qsv_apply_gate(qsv_state* s, int gate, const int32_t* qubits, int nq,
+                          const double* params, int np) {
+  QSV_ENTER(s);
+  if (gate == QSV_MAT) return fail(QSV_ERR_ARG, "QSV_MAT needs qsv_apply_fused");
+  const int k = gate_arity(gate);
+  if (k < 0) return fail(QSV_ERR_ARG, "unknown gate id " + std::to_string(gate));
+  if (nq != k) return fail(QSV_ERR_ARG, "wrong qubit count for gate");
+  if (np != gate_nparams(gate)) return fail(QSV_ERR_ARG, "wrong parameter count for gate");
+  if (np && !params) return fail(QSV_ERR_ARG, "params is NULL");
+  qsv_op o{};
+  o.gate = gate;
+  o.nq = nq;
+  if (!qubits) return fail(QSV_ERR_ARG, "qubit list is NULL");
+  for (int j = 0; j < nq; ++j) o.q[j] = qubits[j];
+  for (int j = 0; j < np; ++j) o.p[j] = params[j];
+  qsv_status st = validate_op(s, o);
+  if (st) return st;
+  return apply_op_pergate(s, o, 0);
+}
+
+qsv_status qsv_apply_fused(qsv_state* s, const int32_t* qubits, int k, const double* mat) {
+  QSV_ENTER(s);
+  if (!mat) return fail(QSV_ERR_ARG, "matrix is NULL");
+  qsv_op o{};
+  o.gate = QSV_MAT;
+  o.nq = k;
+  if (!qubits) return fail(QSV_ERR_ARG, "qubit list is NULL");
+  if (k < 1 || k > QSV_MAX_K) return fail(QSV_ERR_ARG, "k out of range [1, 6]");
+  for (int j = 0; j < k; ++j) o.q[j] = qubits[j];
+  o.mat = mat;
+  qsv_status st = validate_op(s, o);
+  if (st) return st;
+  if (k > s->n) return fail(QSV_ERR_ARG, "k exceeds register size");
+  st = ensure_workspace(s, dense_ws_bytes());
+  if (st) return st;
+  return apply_fused_block(s, o);
+}
+
+qsv_status qsv_apply_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const qsv_plan_opts* opts) {
+  QSV_ENTER(s);
+  if (n_ops < 0) return fail(QSV_ERR_ARG, "n_ops < 0");
+  if (n_ops > 0 && !ops) return fail(QSV_ERR_ARG, "ops is NULL");
+  qsv_plan_opts o{};
+  if (opts) o = *opts;
+  if (o.mode < 0 || o.mode > 2) return fail(QSV_ERR_ARG, "mode must be 0, 1 or 2");
+  for (int r = 0; r < 6; ++r)
+    if (o.reserved[r]) return fail(QSV_ERR_ARG, "reserved plan option fields must be zero");
+  for (int i = 0; i < n_ops; ++i) {
+    qsv_status st = validate_op(s, ops[i]);
+    if (st) return fail(st, "op " + std::to_string(i) + ": " + get_error());
+  }
+  if (n_ops == 0) return QSV_OK;
+  return run_circuit(s, ops, n_ops, o);
+}
+
+qsv_status qsv_expval(qsv_state* s, const uint64_t* xmask, const uint64_t* zmask,
+                      const double* coeff, int n_terms, double* out_total, double* out_terms) {
+  QSV_ENTER(s);
+  if (n_terms < 0) return fail(QSV_ERR_ARG, "n_terms < 0");
+  if (n_terms == 0) {
+    if (out_total) *out_total = 0.0;
+    return QSV_OK;
+  }
+  if (!xmask || !zmask || !coeff) return fail(QSV_ERR_ARG, "NULL term array");
+  const uint64_t lim = s->n >= 64 ? ~0ull : ((1ull << s->n) - 1);
+  for (int t = 0; t < n_terms; ++t) {
+    if ((xmask[t] | zmask[t]) & ~lim) return fail(QSV_ERR_ARG, "Pauli mask names a qubit >= n");
+    if (!std::isfinite(coeff[t])) return fail(QSV_ERR_ARG, "non-finite coefficient");
+  }
+  // group terms by X mask (one pass over the state per group)
+  std::vector<int> order(n_terms);
+  for (int t = 0; t < n_terms; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return xmask[a] < xmask[b]; });
+  const size_t part = expval_ws_doubles(s->n, 16);
+  qsv_status st = ensure_workspace(s, (part + (size_t)n_terms) * sizeof(double));
+  if (st) return st;
+  double* ws = static_cast<double*>(s->ws);
+  double* outd = ws + part;
+  std::vector<uint64_t> zs(n_terms);
+  std::vector<int> ny(n_terms);
+  for (int i = 0; i < n_terms; ++i) {
+    zs[i] = zmask[order[i]];
+    ny[i] = __builtin_popcountll(xmask[order[i]] & zmask[order[i]]);
+  }
+  int i = 0;
+  while (i < n_terms) {
+    int j = i;
+    while (j < n_terms && xmask[order[j]] == xmask[order[i]]) ++j;
+    hipError_t e = s->dt == QSV_C64
+                       ? launch_expval_group<float>(static_cast<const cpx<float>*>(s->psi), s->n,
+                                                    xmask[order[i]], j - i, &zs[i], &ny[i], ws,
+                                                    outd + i, s->stream)
+                       : launch_expval_group<double>(static_cast<const cpx<double>*>(s->psi), s->n,
+                                                     xmask[order[i]], j - i, &zs[i], &ny[i], ws,
+                                                     outd + i, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "expval");
+    i = j;
+  }
+  std::vector<double> raw(n_terms);
+  QSV_HIP(hipMemcpyAsync(raw.data(), outd, n_terms * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  QSV_HIP(hipStreamSynchronize(s->stream));
+  std::vector<double> val(n_terms);
+  for (int k = 0; k < n_terms; ++k) {
+    const int t = order[k];
+    double f;
+    if (xmask[t] == 0) {
+      f = 1.0;
+    } else {
+      // 2 * Re(i^{ny}) for even ny (Re w accumulated), 2 * Re(i^{ny+1}) for odd
+      const int m = ny[k] % 4;
+      f = (m == 0) ? 2.0 : (m == 2) ? -2.0 : (m == 1) ? -2.0 : 2.0;
+    }
+    val[t] = coeff[t] * f * raw[k];
+  }
+  if (out_terms)
+    for (int t = 0; t < n_terms; ++t) out_terms[t] = val[t];
+  if (out_total) {
+    // fixed-order pairwise combination
+    std::vector<double> v = val;
+    while (v.size() > 1) {
+      std::vector<double> w;
+      for (size_t a = 0; a < v.size(); a += 2) w.push_back(a + 1 < v.size() ? v[a] + v[a + 1] : v[a]);
+      v.swap(w);
+    }
+    *out_total = v[0];
+  }
+  return QSV_OK;
+}
+
+qsv_status qsv_norm(qsv_state* s, double* out) {
+  QSV_ENTER(s);
+  if (!out) return fail(QSV_ERR_ARG, "out is NULL");
+  qsv_status st = ensure_workspace(s, (1024 + 8) * sizeof(double));
+  if (st) return st;
+  double* ws = static_cast<double*>(s->ws);
+  hipError_t e = s->dt == QSV_C64
+                     ? launch_norm<float>(static_cast<const cpx<float>*>(s->psi), s->N, ws, ws + 1024, s->stream)
+                     : launch_norm<double>(static_cast<const cpx<double>*>(s->psi), s->N, ws, ws + 1024, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "norm");
+  QSV_HIP(hipMemcpyAsync(out, ws + 1024, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  QSV_HIP(hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
+qsv_status qsv_sample(qsv_state* s, const double* uniforms, int n_shots, uint64_t* out) {
+  QSV_ENTER(s);
+  if (n_shots < 0) return fail(QSV_ERR_ARG, "n_shots < 0");
+  if (n_shots == 0) return QSV_OK;
+  if (!uniforms || !out) return fail(QSV_ERR_ARG, "NULL uniforms or output");
+  for (int i = 0; i < n_shots; ++i)
+    if (!(uniforms[i] >= 0.0 && uniforms[i] < 1.0)) return fail(QSV_ERR_ARG, "uniform outside [0, 1)");
+  const size_t nd = sample_ws_doubles(s->n);
+  const size_t bytes = (nd + 2 * (size_t)n_shots) * sizeof(double);
+  qsv_status st = ensure_workspace(s, bytes);
+  if (st) return st;
+  double* ws = static_cast<double*>(s->ws);
+  double* ud = ws + nd;
+  uint64_t* od = reinterpret_cast<uint64_t*>(ud + n_shots);
+  QSV_HIP(hipMemcpyAsync(ud, uniforms, n_shots * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  hipError_t e = s->dt == QSV_C64
+                     ? launch_sample<float>(static_cast<const cpx<float>*>(s->psi), s->n, ud, n_shots, ws, od, s->stream)
+                     : launch_sample<double>(static_cast<const cpx<double>*>(s->psi), s->n, ud, n_shots, ws, od, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "sample");
+  QSV_HIP(hipMemcpyAsync(out, od, n_shots * sizeof(uint64_t), hipMemcpyDeviceToHost, s->stream));
+  QSV_HIP(hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
+qsv_status qsv_copy_to_host(qsv_state* s, void* dst, size_t bytes) {
+  QSV_ENTER(s);
+  if (!dst || bytes != s->bytes) return fail(QSV_ERR_ARG, "destination size must equal the state size");
+  QSV_HIP(hipMemcpyAsync(dst, s->psi, bytes, hipMemcpyDeviceToHost, s->stream));
+  QSV_HIP(hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
+qsv_status qsv_copy_from_host(qsv_state* s, const void* src, size_t bytes) {
+  QSV_ENTER(s);
+  if (!src || bytes != s->bytes) return fail(QSV_ERR_ARG, "source size must equal the state size");
+  QSV_HIP(hipMemcpyAsync(s->psi, src, bytes, hipMemcpyHostToDevice, s->stream));
+  QSV_HIP(hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
+qsv_status qsv_synchronize(qsv_state* s) {
+  QSV_ENTER(s);
+  QSV_HIP(hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
+const char* qsv_last_error(void) { return get_error(); }
+
+}  // extern "C"

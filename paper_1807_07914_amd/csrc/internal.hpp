@@ -1,0 +1,96 @@
+// internal.hpp -- host-side internals of libqsv (state object, error
+// plumbing, kernel launcher declarations).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qsv.h"
+#include "common.hpp"
+
+namespace qsv {
+
+constexpr uint32_t kStateMagic = 0x31565351u;  // "QSV1"
+constexpr uint32_t kDeadMagic = 0xDEADBEEFu;
+
+void set_error(const std::string& msg);
+const char* get_error();
+
+// Status helper: records a message and returns the code.
+qsv_status fail(qsv_status code, const std::string& msg);
+qsv_status hip_fail(hipError_t e, const char* where);
+
+#define QSV_HIP(call)                                      \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return ::qsv::hip_fail(e_, #call); \
+  } while (0)
+
+struct Plan;  // fused-execution plan (planner.cpp)
+
+}  // namespace qsv
+
+struct qsv_state {
+  uint32_t magic = qsv::kStateMagic;
+  int n = 0;
+  qsv_dtype dt = QSV_C64;
+  uint64_t N = 0;           // 2^n amplitudes
+  size_t amp_bytes = 8;     // 8 (complex64) or 16 (complex128)
+  size_t bytes = 0;         // N * amp_bytes
+  void* psi = nullptr;      // device amplitudes
+  bool owns = false;
+  hipStream_t stream = nullptr;
+  // device workspace (reduction partials, staged matrices, sampler scratch)
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::atomic<int> busy{0};
+};
+
+namespace qsv {
+
+// Grow the state's device workspace to at least `bytes` (stream-ordered:
+// waits for the stream before freeing a smaller buffer).
+qsv_status ensure_workspace(qsv_state* s, size_t bytes);
+
+// ---------------------------------------------------------------- launchers
+template <typename T>
+hipError_t launch_init_basis(cpx<T>* psi, uint64_t N, uint64_t x, hipStream_t st);
+template <typename T>
+hipError_t launch_gate1(cpx<T>* psi, int n, int q, const M2<T>& U, hipStream_t st);
+template <typename T>
+hipError_t launch_diag1(cpx<T>* psi, int n, int q, cpx<T> d0, cpx<T> d1, hipStream_t st);
+template <typename T>
+hipError_t launch_gate2(cpx<T>* psi, int n, int qa, int qb, const M4<T>& U, hipStream_t st);
+template <typename T>
+hipError_t launch_cnot(cpx<T>* psi, int n, int c, int t, hipStream_t st);
+template <typename T>
+hipError_t launch_swap(cpx<T>* psi, int n, int a, int b, hipStream_t st);
+template <typename T>
+hipError_t launch_cphase(cpx<T>* psi, int n, int a, int b, cpx<T> ph, hipStream_t st);
+// dense k-qubit matrix (1 <= k <= 6) staged in device memory (row-major
+// 2^k x 2^k, state precision); qubits in listed order.
+template <typename T>
+hipError_t launch_dense(cpx<T>* psi, int n, int k, const int* qubits, const cpx<T>* mat_dev,
+                        hipStream_t st);
+
+// reductions: FP64 partials written to ws, final values to out_dev (doubles)
+template <typename T>
+hipError_t launch_norm(const cpx<T>* psi, uint64_t N, double* ws, double* out_dev, hipStream_t st);
+// nt terms sharing one xmask; zmask[t] and the phase class of each term
+// (n_y mod 4) given; out_dev[t] = Re( i^{ny_t} sum_i conj(psi_{i^x}) (-1)^{|i&z_t|} psi_i )
+template <typename T>
+hipError_t launch_expval_group(const cpx<T>* psi, int n, uint64_t xmask, int nt,
+                               const uint64_t* zmask_host, const int* ny_host, double* ws,
+                               double* out_dev, hipStream_t st);
+size_t expval_ws_doubles(int n, int nt);
+
+// sampler: returns indices into out_dev (uint64) for uniforms_dev
+template <typename T>
+hipError_t launch_sample(const cpx<T>* psi, int n, const double* uniforms_dev, int shots,
+                         double* ws, uint64_t* out_dev, hipStream_t st);
+size_t sample_ws_doubles(int n);
+
+}  // namespace qsv

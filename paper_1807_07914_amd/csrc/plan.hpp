@@ -1,0 +1,26 @@
+// plan.hpp -- host-side execution entry points shared by the ABI layer and
+// the circuit executor (per-gate dispatch, fused tile passes, dense blocks).
+#pragma once
+#include <complex>
+
+#include "internal.hpp"
+
+namespace qsv {
+
+int gate_matrix(int g, const double* p, std::complex<double>* m);
+bool gate_is_diagonal(int g);
+int gate_arity(int g);
+int gate_nparams(int g);
+qsv_status validate_op(const qsv_state* s, const qsv_op& o);
+
+// one instruction through the per-gate kernels (matrix staging at ws_off)
+qsv_status apply_op_pergate(qsv_state* s, const qsv_op& o, size_t ws_off);
+size_t dense_ws_bytes();
+
+// explicit k-qubit matrix (qsv_apply_fused)
+qsv_status apply_fused_block(qsv_state* s, const qsv_op& o);
+
+// whole gate list (qsv_apply_circuit); ops already validated
+qsv_status run_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const qsv_plan_opts& opts);
+
+}  // namespace qsv

@@ -1,0 +1,336 @@
+// reduce.hip -- FP64 reductions over the amplitude array: norm, Pauli-string
+// expectation values and inverse-CDF sampling.
+//
+// Paper section V.B computes one expectation value per Hamiltonian term and
+// uses MEASURE on the register; here both are exact reductions of the state
+// vector.  Every reduction is two-stage and deterministic: a fixed grid of
+// workgroups writes one FP64 partial per (workgroup, term) in a fixed
+// per-thread order and a fixed LDS tree, and a single workgroup combines the
+// partials in a fixed tree.  No floating-point atomics are used.
+#include "internal.hpp"
+
+namespace qsv {
+
+constexpr int kRB = 256;         // reduction workgroup size
+constexpr int kMaxPartials = 1024;
+
+static inline unsigned reduce_grid(uint64_t units) {
+  // enough workgroups to fill the chip, but a fixed function of the size
+  uint64_t g = (units + kRB * 16 - 1) / (kRB * 16);
+  if (g < 1) g = 1;
+  if (g > kMaxPartials) g = kMaxPartials;
+  return (unsigned)g;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kRB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Final stage: out[t] = sum_b part[b * nt + t], one workgroup, fixed tree.
+__global__ __launch_bounds__(kRB) void k_final(const double* __restrict__ part, int nb, int nt,
+                                               double* __restrict__ out) {
+  __shared__ double sh[kRB];
+  for (int t = 0; t < nt; ++t) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kRB) acc += part[(size_t)b * nt + t];
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[t] = s;
+  }
+}
+
+// ---------------------------------------------------------------- norm
+template <typename T>
+__global__ __launch_bounds__(kRB) void k_norm_part(const vec16<T>* __restrict__ v, uint64_t nvec,
+                                                   uint64_t chunk, double* __restrict__ part) {
+  constexpr int A = VecInfo<T>::A;
+  __shared__ double sh[kRB];
+  const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+  const uint64_t hi = lo + chunk < nvec ? lo + chunk : nvec;
+  double acc = 0.0;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kRB) {
+    const vec16<T> x = v[i];
+#pragma unroll
+    for (int e = 0; e < A; ++e) {
+      const double re = (double)x.a[e].x, im = (double)x.a[e].y;
+      acc = fma(re, re, fma(im, im, acc));
+    }
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename T>
+hipError_t launch_norm(const cpx<T>* psi, uint64_t N, double* ws, double* out_dev, hipStream_t st) {
+  constexpr int A = VecInfo<T>::A;
+  const uint64_t nvec = N / A;
+  const unsigned g = reduce_grid(nvec);
+  const uint64_t chunk = (nvec + g - 1) / g;
+  hipLaunchKernelGGL(k_norm_part<T>, dim3(g), dim3(kRB), 0, st,
+                     reinterpret_cast<const vec16<T>*>(psi), nvec, chunk, ws);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kRB), 0, st, ws, (int)g, 1, out_dev);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ expectation values
+// Terms of one launch share the X-mask x.  With n_y = |x & z| (the Y count),
+// <P> = Re( i^{n_y} sum_i conj(psi_{i^x}) (-1)^{|i & z|} psi_i ).
+//  x == 0: accumulate (-1)^{|i&z|} |psi_i|^2.
+//  x != 0: visit each pair (i, j = i^x) once (i has x's top bit clear); with
+//          w = conj(psi_j) psi_i the pair contributes s_i (w + (-1)^{n_y} conj w),
+//          i.e. 2 s_i Re w (n_y even) or 2i s_i Im w (n_y odd); the host applies
+//          the factor 2 * Re(i^{n_y}) or 2 * Re(i^{n_y + 1}).
+constexpr int kMaxTermsPerLaunch = 16;
+struct ZTerms {
+  uint64_t z[kMaxTermsPerLaunch];
+  int odd[kMaxTermsPerLaunch];  // n_y odd -> accumulate Im w
+};
+
+template <typename T, bool XZERO>
+__global__ __launch_bounds__(kRB) void k_expval_part(const cpx<T>* __restrict__ psi, uint64_t units,
+                                                     uint64_t chunk, uint64_t x, int top, int nt,
+                                                     ZTerms zt, double* __restrict__ part) {
+  __shared__ double sh[kRB];
+  double acc[kMaxTermsPerLaunch];
+#pragma unroll
+  for (int t = 0; t < kMaxTermsPerLaunch; ++t) acc[t] = 0.0;
+  const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+  const uint64_t hi = lo + chunk < units ? lo + chunk : units;
+  for (uint64_t u = lo + threadIdx.x; u < hi; u += kRB) {
+    if (XZERO) {
+      const cpx<T> a = psi[u];
+      const double p = fma((double)a.x, (double)a.x, (double)a.y * (double)a.y);
+#pragma unroll
+      for (int t = 0; t < kMaxTermsPerLaunch; ++t)
+        if (t < nt) acc[t] += (__popcll(u & zt.z[t]) & 1) ? -p : p;
+    } else {
+      const uint64_t i = insert0(u, top);
+      const uint64_t j = i ^ x;
+      const cpx<T> a = psi[i], b = psi[j];
+      // w = conj(b) * a
+      const double wr = fma((double)b.x, (double)a.x, (double)b.y * (double)a.y);
+      const double wi = fma((double)b.x, (double)a.y, -(double)b.y * (double)a.x);
+#pragma unroll
+      for (int t = 0; t < kMaxTermsPerLaunch; ++t)
+        if (t < nt) {
+          const double w = zt.odd[t] ? wi : wr;
+          acc[t] += (__popcll(i & zt.z[t]) & 1) ? -w : w;
+        }
+    }
+  }
+  for (int t = 0; t < nt; ++t) {
+    const double s = block_sum(acc[t], sh);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * nt + t] = s;
+  }
+}
+
+size_t expval_ws_doubles(int n, int nt) {
+  (void)n;
+  return (size_t)kMaxPartials * (nt < 1 ? 1 : nt);
+}
+
+template <typename T>
+hipError_t launch_expval_group(const cpx<T>* psi, int n, uint64_t xmask, int nt,
+                               const uint64_t* zmask_host, const int* ny_host, double* ws,
+                               double* out_dev, hipStream_t st) {
+  for (int t0 = 0; t0 < nt; t0 += kMaxTermsPerLaunch) {
+    const int cnt = nt - t0 < kMaxTermsPerLaunch ? nt - t0 : kMaxTermsPerLaunch;
+    ZTerms zt{};
+    for (int t = 0; t < cnt; ++t) {
+      zt.z[t] = zmask_host[t0 + t];
+      zt.odd[t] = ny_host[t0 + t] & 1;
+    }
+    const uint64_t N = 1ull << n;
+    if (xmask == 0) {
+      const unsigned g = reduce_grid(N);
+      const uint64_t chunk = (N + g - 1) / g;
+      hipLaunchKernelGGL((k_expval_part<T, true>), dim3(g), dim3(kRB), 0, st, psi, N, chunk,
+                         xmask, 0, cnt, zt, ws);
+      hipLaunchKernelGGL(k_final, dim3(1), dim3(kRB), 0, st, ws, (int)g, cnt, out_dev + t0);
+    } else {
+      const int top = 63 - __builtin_clzll(xmask);
+      const uint64_t units = N / 2;
+      const unsigned g = reduce_grid(units);
+      const uint64_t chunk = (units + g - 1) / g;
+      hipLaunchKernelGGL((k_expval_part<T, false>), dim3(g), dim3(kRB), 0, st, psi, units, chunk,
+                         xmask, top, cnt, zt, ws);
+      hipLaunchKernelGGL(k_final, dim3(1), dim3(kRB), 0, st, ws, (int)g, cnt, out_dev + t0);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------- sampling
+// Block sums of |psi_i|^2 over blocks of kSB amplitudes, their inclusive
+// prefix, then one wavefront per shot: binary search over the block prefix
+// for the first block whose inclusive prefix exceeds t = u * total, and an
+// in-block scan (64 lanes x kSB/64 consecutive amplitudes).
+constexpr int kSB = 4096;
+
+template <typename T>
+__global__ __launch_bounds__(kRB) void k_block_sums(const cpx<T>* __restrict__ psi, uint64_t N,
+                                                    double* __restrict__ bsum) {
+  __shared__ double sh[kRB];
+  const uint64_t lo = (uint64_t)blockIdx.x * kSB;
+  constexpr int per = kSB / kRB;  // 16 consecutive amplitudes per thread
+  double acc = 0.0;
+  const uint64_t s = lo + (uint64_t)threadIdx.x * per;
+  for (int e = 0; e < per; ++e) {
+    const uint64_t i = s + e;
+    if (i < N) {
+      const cpx<T> a = psi[i];
+      acc += fma((double)a.x, (double)a.x, (double)a.y * (double)a.y);
+    }
+  }
+  const double r = block_sum(acc, sh);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = r;
+}
+
+// inclusive prefix of nb block sums, one workgroup: contiguous chunks per
+// thread, sequential within the chunk, then a sequential pass over chunk totals
+__global__ __launch_bounds__(kRB) void k_block_prefix(const double* __restrict__ bsum, uint64_t nb,
+                                                      double* __restrict__ pref) {
+  __shared__ double tot[kRB];
+  const uint64_t per = (nb + kRB - 1) / kRB;
+  const uint64_t lo = threadIdx.x * per;
+  const uint64_t hi = lo + per < nb ? lo + per : nb;
+  double acc = 0.0;
+  for (uint64_t b = lo; b < hi; ++b) acc += bsum[b];
+  tot[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    for (int t = 0; t < kRB; ++t) {
+      const double v = tot[t];
+      tot[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  double run = tot[threadIdx.x];
+  for (uint64_t b = lo; b < hi; ++b) {
+    run += bsum[b];
+    pref[b] = run;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRB) void k_sample_shots(const cpx<T>* __restrict__ psi, uint64_t N,
+                                                      const double* __restrict__ bsum,
+                                                      const double* __restrict__ pref, uint64_t nb,
+                                                      const double* __restrict__ uni, int shots,
+                                                      uint64_t* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int shot = blockIdx.x * (kRB / 64) + (threadIdx.x >> 6);
+  if (shot >= shots) return;  // whole wavefront exits together
+  const double total = pref[nb - 1];
+  const double t = uni[shot] * total;
+  // smallest block b with pref[b] > t
+  uint64_t lo = 0, hi = nb;
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (pref[mid] > t) hi = mid; else lo = mid + 1;
+  }
+  bool clamp = false;
+  uint64_t b = lo;
+  if (b >= nb) {  // rounding left no block above t: last block with mass
+    clamp = true;
+    b = nb - 1;
+    while (b > 0 && !(bsum[b] > 0.0)) --b;
+  }
+  const double base = b == 0 ? 0.0 : pref[b - 1];
+  constexpr int per = kSB / 64;
+  const uint64_t s = b * (uint64_t)kSB + (uint64_t)lane * per;
+  double ls = 0.0;
+  for (int e = 0; e < per; ++e) {
+    const uint64_t i = s + e;
+    if (i < N) {
+      const cpx<T> a = psi[i];
+      ls += fma((double)a.x, (double)a.x, (double)a.y * (double)a.y);
+    }
+  }
+  // inclusive scan over lanes
+  double inc = ls;
+  for (int d = 1; d < 64; d <<= 1) {
+    const double o = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += o;
+  }
+  const double exc = inc - ls;
+  const uint64_t hit = clamp ? 0ull : (uint64_t)__ballot(base + inc > t);
+  // last index with nonzero probability in this block (clamp fallback)
+  uint64_t lastnz = 0;
+  bool any = false;
+  for (int e = 0; e < per; ++e) {
+    const uint64_t i = s + e;
+    if (i < N) {
+      const cpx<T> a = psi[i];
+      if (a.x != T(0) || a.y != T(0)) { lastnz = i; any = true; }
+    }
+  }
+  const uint64_t nzmask = (uint64_t)__ballot(any);
+  uint64_t res;
+  if (hit) {
+    const int L = __ffsll((unsigned long long)hit) - 1;
+    // lane L walks its run sequentially
+    uint64_t found = ~0ull;
+    if (lane == L) {
+      double run = base + exc;
+      for (int e = 0; e < per; ++e) {
+        const uint64_t i = s + e;
+        if (i >= N) break;
+        const cpx<T> a = psi[i];
+        run += fma((double)a.x, (double)a.x, (double)a.y * (double)a.y);
+        if (run > t) { found = i; break; }
+      }
+      if (found == ~0ull) found = any ? lastnz : s;
+    }
+    res = __shfl(found, L, 64);
+  } else {
+    const int L = nzmask ? 63 - __clzll((long long)nzmask) : 0;
+    res = __shfl(lastnz, L, 64);
+  }
+  if (lane == 0) out[shot] = res;
+}
+
+size_t sample_ws_doubles(int n) {
+  const uint64_t N = 1ull << n;
+  const uint64_t nb = (N + kSB - 1) / kSB;
+  return 2 * nb;
+}
+
+template <typename T>
+hipError_t launch_sample(const cpx<T>* psi, int n, const double* uniforms_dev, int shots,
+                         double* ws, uint64_t* out_dev, hipStream_t st) {
+  const uint64_t N = 1ull << n;
+  const uint64_t nb = (N + kSB - 1) / kSB;
+  double* bsum = ws;
+  double* pref = ws + nb;
+  hipLaunchKernelGGL(k_block_sums<T>, dim3((unsigned)nb), dim3(kRB), 0, st, psi, N, bsum);
+  hipLaunchKernelGGL(k_block_prefix, dim3(1), dim3(kRB), 0, st, bsum, nb, pref);
+  if (shots > 0) {
+    const unsigned g = (unsigned)((shots + (kRB / 64) - 1) / (kRB / 64));
+    hipLaunchKernelGGL(k_sample_shots<T>, dim3(g), dim3(kRB), 0, st, psi, N, bsum, pref, nb,
+                       uniforms_dev, shots, out_dev);
+  }
+  return hipGetLastError();
+}
+
+#define QSV_RINST(T)                                                                          \
+  template hipError_t launch_norm<T>(const cpx<T>*, uint64_t, double*, double*, hipStream_t); \
+  template hipError_t launch_expval_group<T>(const cpx<T>*, int, uint64_t, int, const uint64_t*, \
+                                             const int*, double*, double*, hipStream_t);      \
+  template hipError_t launch_sample<T>(const cpx<T>*, int, const double*, int, double*,       \
+                                       uint64_t*, hipStream_t);
+QSV_RINST(float)
+QSV_RINST(double)
+
+}  // namespace qsv

@@ -1,0 +1,263 @@
+"""Thin Python binding of libqsv (ctypes): argument marshalling only.
+
+Every step of the simulation runs in the library's HIP kernels; PyTorch is
+used only to own device memory (the state tensor) and to supply the HIP
+stream.  If ``libqsv.so`` has not been built this module raises on import of
+the library -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsv.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "qsv.h")
+
+QSV_OK, QSV_ERR_ARG, QSV_ERR_OOM, QSV_ERR_HIP, QSV_ERR_UNSUPPORTED, QSV_ERR_STATE = 0, -1, -2, -3, -4, -5
+QSV_C64, QSV_C128 = 1, 2
+GATES = {
+    "I": 0, "X": 1, "Y": 2, "Z": 3, "H": 4, "S": 5, "SDG": 6, "T": 7, "TDG": 8,
+    "RX": 9, "RY": 10, "RZ": 11, "CNOT": 12, "CZ": 13, "CPHASE": 14, "SWAP": 15, "MAT": 16,
+}
+NPARAMS = {"RX": 1, "RY": 1, "RZ": 1, "CPHASE": 1}
+MODES = {"auto": 0, "pergate": 1, "fused": 2}
+
+
+class QsvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("qsv error %d: %s" % (code, msg))
+        self.code = code
+
+
+class QsvOp(ctypes.Structure):
+    _fields_ = [("gate", ctypes.c_int32), ("nq", ctypes.c_int32), ("q", ctypes.c_int32 * 6),
+                ("p", ctypes.c_double * 3), ("mat", ctypes.POINTER(ctypes.c_double))]
+
+
+class QsvPlanOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+assert ctypes.sizeof(QsvOp) == 64
+
+_lib = None
+
+
+def lib():
+    """Load libqsv.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libqsv.so is not built (expected at %s); run "
+                          "paper_1807_07914_amd/csrc/build.py or __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u64p = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)
+    dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "qsv_alloc_state": [i32, i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
+        "qsv_free_state": [vp],
+        "qsv_state_info": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(vp)],
+        "qsv_set_basis": [vp, ctypes.c_uint64],
+        "qsv_apply_gate": [vp, i32, ip, i32, dp, i32],
+        "qsv_apply_fused": [vp, ip, i32, dp],
+        "qsv_apply_circuit": [vp, ctypes.POINTER(QsvOp), i32, ctypes.POINTER(QsvPlanOpts)],
+        "qsv_expval": [vp, u64p, u64p, dp, i32, dp, dp],
+        "qsv_norm": [vp, dp],
+        "qsv_sample": [vp, dp, i32, u64p],
+        "qsv_copy_to_host": [vp, vp, ctypes.c_size_t],
+        "qsv_copy_from_host": [vp, vp, ctypes.c_size_t],
+        "qsv_synchronize": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.qsv_last_error.argtypes = []
+    L.qsv_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def header_functions(path: str = HEADER_PATH) -> list:
+    """Names of the functions declared in include/qsv.h."""
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qsv_[a-z0-9_]+)\s*\(", txt)))
+
+
+def check(rc: int) -> None:
+    if rc != QSV_OK:
+        msg = lib().qsv_last_error()
+        raise QsvError(rc, msg.decode() if msg else "")
+
+
+def _i32(xs):
+    return (ctypes.c_int32 * max(1, len(xs)))(*[int(x) for x in xs])
+
+
+def _f64(xs):
+    return (ctypes.c_double * max(1, len(xs)))(*[float(x) for x in xs])
+
+
+def pauli_masks(hamiltonian) -> tuple:
+    """((coeff, ((P, q), ...)), ...) -> (xmask, zmask, coeff) arrays."""
+    xs, zs, cs = [], [], []
+    for c, term in hamiltonian:
+        x = z = 0
+        for p, q in term:
+            b = 1 << int(q)
+            if (x | z) & b:
+                raise ValueError("qubit repeated within a Pauli string")
+            if p == "X":
+                x |= b
+            elif p == "Z":
+                z |= b
+            elif p == "Y":
+                x |= b
+                z |= b
+            else:
+                raise ValueError("unknown Pauli %r" % (p,))
+        xs.append(x); zs.append(z); cs.append(float(c))
+    return (np.asarray(xs, dtype=np.uint64), np.asarray(zs, dtype=np.uint64),
+            np.asarray(cs, dtype=np.float64))
+
+
+class OpList:
+    """Gate records marshalled into a contiguous qsv_op array (keeps the
+    explicit matrices alive for the duration of the call)."""
+
+    def __init__(self, ops: Iterable):
+        ops = list(ops)
+        self.arr = (QsvOp * max(1, len(ops)))()
+        self.n = len(ops)
+        self._keep = []
+        for i, o in enumerate(ops):
+            r = self.arr[i]
+            name = o.name if o.name != "U" else "MAT"
+            r.gate = GATES[name]
+            r.nq = len(o.qubits)
+            if r.nq > 6:
+                raise ValueError("at most 6 qubits per op")
+            for j, q in enumerate(o.qubits):
+                r.q[j] = int(q)
+            for j, p in enumerate(o.params[:3]):
+                r.p[j] = float(p)
+            if name == "MAT":
+                m = np.ascontiguousarray(np.asarray(o.mat, dtype=np.complex128))
+                self._keep.append(m)
+                r.mat = m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class State:
+    """A device-resident state vector of n qubits (complex64 or complex128)
+    whose storage is a torch CUDA tensor owned by this object (or borrowed)."""
+
+    def __init__(self, n: int, dtype: str = "c64", device: int = 0, tensor=None, stream=None):
+        import torch
+        if dtype not in ("c64", "c128"):
+            raise ValueError("dtype must be 'c64' or 'c128'")
+        self.n = int(n)
+        self.dtype = dtype
+        tdt = torch.complex64 if dtype == "c64" else torch.complex128
+        if tensor is None:
+            tensor = torch.empty(1 << self.n, dtype=tdt, device="cuda:%d" % device)
+        if tensor.dtype != tdt or not tensor.is_cuda or not tensor.is_contiguous():
+            raise ValueError("tensor must be a contiguous CUDA tensor of the state dtype")
+        self.tensor = tensor
+        if stream is None:
+            stream = torch.cuda.current_stream(tensor.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        check(lib().qsv_alloc_state(self.n, QSV_C64 if dtype == "c64" else QSV_C128,
+                                    ctypes.c_void_p(tensor.data_ptr()),
+                                    tensor.numel() * tensor.element_size(),
+                                    ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    # -- lifetime ---------------------------------------------------------
+    @property
+    def handle(self):
+        if self._h is None:
+            raise QsvError(QSV_ERR_STATE, "state already closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            check(lib().qsv_free_state(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- gates ------------------------------------------------------------
+    def set_basis(self, x: int) -> None:
+        check(lib().qsv_set_basis(self.handle, int(x)))
+
+    def apply_gate(self, name: str, qubits: Sequence[int], params: Sequence[float] = ()) -> None:
+        check(lib().qsv_apply_gate(self.handle, GATES[name], _i32(qubits), len(qubits),
+                                   _f64(params), len(params)))
+
+    def apply_fused(self, qubits: Sequence[int], mat) -> None:
+        m = np.ascontiguousarray(np.asarray(mat, dtype=np.complex128))
+        check(lib().qsv_apply_fused(self.handle, _i32(qubits), len(qubits),
+                                    m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def apply_circuit(self, ops, mode: str = "auto", tile_qubits: int = 0) -> None:
+        ol = ops if isinstance(ops, OpList) else OpList(ops)
+        opts = QsvPlanOpts()
+        opts.mode = MODES[mode]
+        opts.tile_qubits = int(tile_qubits)
+        check(lib().qsv_apply_circuit(self.handle, ol.arr, ol.n, ctypes.byref(opts)))
+
+    # -- reductions -------------------------------------------------------
+    def expval(self, hamiltonian, per_term: bool = False):
+        x, z, c = pauli_masks(hamiltonian)
+        tot = ctypes.c_double()
+        terms = np.zeros(max(1, len(c)), dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(lib().qsv_expval(self.handle, x.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                               z.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                               c.ctypes.data_as(dp), len(c), ctypes.byref(tot),
+                               terms.ctypes.data_as(dp)))
+        return terms[: len(c)].tolist() if per_term else tot.value
+
+    def norm(self) -> float:
+        out = ctypes.c_double()
+        check(lib().qsv_norm(self.handle, ctypes.byref(out)))
+        return out.value
+
+    def sample(self, uniforms) -> np.ndarray:
+        u = np.ascontiguousarray(uniforms, dtype=np.float64)
+        out = np.zeros(u.size, dtype=np.uint64)
+        check(lib().qsv_sample(self.handle, u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               int(u.size), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+        return out
+
+    # -- copies -----------------------------------------------------------
+    def to_numpy(self) -> np.ndarray:
+        out = np.empty(1 << self.n, dtype=np.complex64 if self.dtype == "c64" else np.complex128)
+        check(lib().qsv_copy_to_host(self.handle, out.ctypes.data_as(ctypes.c_void_p), out.nbytes))
+        return out
+
+    def from_numpy(self, a: np.ndarray) -> None:
+        a = np.ascontiguousarray(a, dtype=np.complex64 if self.dtype == "c64" else np.complex128)
+        check(lib().qsv_copy_from_host(self.handle, a.ctypes.data_as(ctypes.c_void_p), a.nbytes))
+
+    def synchronize(self) -> None:
+        check(lib().qsv_synchronize(self.handle))

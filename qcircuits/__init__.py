@@ -322,3 +322,10 @@ def dagger(ops: Sequence[Op]) -> list:
         else:
             out.append(Op(inv.get(o.name, o.name), o.qubits, o.params))
     return out
+
+
+def random_state(n: int, seed: int) -> np.ndarray:
+    """Seeded random complex128 input state (Gaussian entries scaled to unit norm)."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    return (v / np.linalg.norm(v)).astype(np.complex128)

@@ -1,0 +1,49 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/qsv.h declares, has the documented struct layout, and
+rejects invalid arguments before touching the device."""
+import ctypes
+
+import pytest
+
+from paper_1807_07914_amd import qsv
+
+
+def test_library_exports_every_header_function():
+    names = qsv.header_functions()
+    assert "qsv_alloc_state" in names and "qsv_sample" in names
+    L = qsv.lib()
+    missing = [f for f in names if not hasattr(L, f)]
+    assert not missing, missing
+
+
+def test_op_struct_is_64_bytes():
+    assert ctypes.sizeof(qsv.QsvOp) == 64
+    assert qsv.QsvOp.mat.offset == 56 and qsv.QsvOp.p.offset == 32
+
+
+@pytest.mark.parametrize("n,dt", [(0, 1), (41, 1), (-3, 2), (10, 0), (10, 3)])
+def test_alloc_rejects_bad_arguments(n, dt):
+    h = ctypes.c_void_p()
+    rc = qsv.lib().qsv_alloc_state(n, dt, None, 0, None, ctypes.byref(h))
+    assert rc == qsv.QSV_ERR_ARG
+    assert h.value is None
+    assert qsv.lib().qsv_last_error()
+
+
+def test_foreign_handles_rejected():
+    L = qsv.lib()
+    bogus = ctypes.c_void_p(0x1234)
+    assert L.qsv_free_state(None) == qsv.QSV_OK
+    assert L.qsv_free_state(bogus) == qsv.QSV_ERR_STATE
+    assert L.qsv_state_info(bogus, None, None, None) == qsv.QSV_ERR_STATE
+    assert L.qsv_set_basis(bogus, 0) == qsv.QSV_ERR_STATE
+    out = ctypes.c_double()
+    assert L.qsv_norm(bogus, ctypes.byref(out)) == qsv.QSV_ERR_STATE
+    assert b"invalid" in L.qsv_last_error()
+
+
+def test_pauli_mask_encoding():
+    x, z, c = qsv.pauli_masks([(0.5, (("X", 0), ("Y", 2), ("Z", 3)))])
+    assert int(x[0]) == 0b0101 and int(z[0]) == 0b1100 and c[0] == 0.5
+    with pytest.raises(ValueError):
+        qsv.pauli_masks([(1.0, (("X", 1), ("Z", 1)))])
