@@ -140,6 +140,14 @@ qsv_status qsv_apply_fused(qsv_state* s, const int32_t* qubits, int k, const dou
 qsv_status qsv_apply_circuit(qsv_state* s, const qsv_op* ops, int n_ops,
                              const qsv_plan_opts* opts);
 
+/* Diagnostics of the fused planner (host only; the device is not touched):
+ * the number of HBM tile passes and of ops executed by separate kernels that
+ * qsv_apply_circuit in fused mode would use for this gate list on a register
+ * of n_qubits of the given dtype (tile_qubits 0 = library choice).
+ * Errors: QSV_ERR_ARG (invalid ops, n or tile size). */
+qsv_status qsv_plan_info(int n_qubits, qsv_dtype dtype, const qsv_op* ops, int n_ops,
+                         int tile_qubits, int* passes, int* separate_ops);
+
 /* Expectation value of sum_t coeff[t] * P_t (paper section V.B: one
  * expectation value per Hamiltonian term).  Each Pauli string P_t is given
  * by bit masks: qubit q carries X if only xmask bit q is set, Z if only zmask

@@ -331,6 +331,7 @@ qsv_status qsv_free_state(qsv_state* s) {
   }
   hipError_t e = hipStreamSynchronize(s->stream);
   if (s->ws) (void)hipFree(s->ws);
+  if (s->pbuf) (void)hipFree(s->pbuf);
   if (s->owns && s->psi) (void)hipFree(s->psi);
   s->magic = kDeadMagic;
   delete s;
@@ -409,6 +410,52 @@ qsv_status qsv_apply_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const q
   }
   if (n_ops == 0) return QSV_OK;
   return run_circuit(s, ops, n_ops, o);
+}
+
+qsv_status qsv_plan_info(int n_qubits, qsv_dtype dtype, const qsv_op* ops, int n_ops,
+                         int tile_qubits, int* passes, int* separate_ops) {
+  if (n_qubits < 1 || n_qubits > QSV_MAX_QUBITS) return fail(QSV_ERR_ARG, "n_qubits out of range");
+  if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_ERR_ARG, "bad dtype");
+  if (n_ops < 0 || (n_ops > 0 && !ops)) return fail(QSV_ERR_ARG, "bad op list");
+  qsv_state tmp;  // shape only: never registered, never touches the device
+  tmp.n = n_qubits;
+  tmp.dt = dtype;
+  tmp.N = 1ull << n_qubits;
+  for (int i = 0; i < n_ops; ++i) {
+    qsv_status st = validate_op(&tmp, ops[i]);
+    if (st) return st;
+  }
+  return plan_passes(&tmp, ops, n_ops, tile_qubits, passes, separate_ops);
+}
+
+// Host-only debug export (not part of the public header): the fused plan's
+// program image, for emulation of the tile kernel on the CPU in tests.
+// Writes up to cap_words words / cap_steps step entries; *n_words and
+// *n_steps receive the full sizes.
+qsv_status qsv_debug_plan_program(int n_qubits, qsv_dtype dtype, const qsv_op* ops, int n_ops,
+                                  int tile_qubits, int32_t* words, int64_t cap_words,
+                                  int64_t* n_words, int64_t* steps, int64_t cap_steps,
+                                  int64_t* n_steps) {
+  if (n_qubits < 1 || n_qubits > QSV_MAX_QUBITS) return fail(QSV_ERR_ARG, "n_qubits out of range");
+  if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_ERR_ARG, "bad dtype");
+  if (n_ops < 0 || (n_ops > 0 && !ops)) return fail(QSV_ERR_ARG, "bad op list");
+  qsv_state tmp;
+  tmp.n = n_qubits;
+  tmp.dt = dtype;
+  tmp.N = 1ull << n_qubits;
+  for (int i = 0; i < n_ops; ++i) {
+    qsv_status st = validate_op(&tmp, ops[i]);
+    if (st) return st;
+  }
+  std::vector<int32_t> prog;
+  std::vector<int64_t> st;
+  qsv_status rc = plan_program(&tmp, ops, n_ops, tile_qubits, prog, st);
+  if (rc) return rc;
+  if (n_words) *n_words = (int64_t)prog.size();
+  if (n_steps) *n_steps = (int64_t)st.size();
+  for (int64_t i = 0; words && i < cap_words && i < (int64_t)prog.size(); ++i) words[i] = prog[i];
+  for (int64_t i = 0; steps && i < cap_steps && i < (int64_t)st.size(); ++i) steps[i] = st[i];
+  return QSV_OK;
 }
 
 qsv_status qsv_expval(qsv_state* s, const uint64_t* xmask, const uint64_t* zmask,

@@ -19,12 +19,16 @@ OUT = os.path.join(PKG, "libqsv.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "gates.hip", "reduce.hip", "circuit.hip"]
+SOURCES = ["api.hip", "gates.hip", "reduce.hip", "circuit.hip", "tile.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep per-case code of register-array switches separate: sinking common
+    # code out of switch cases turns constant register indices into dynamic
+    # ones and pushes the whole array to scratch memory
+    "-mllvm", "-simplifycfg-sink-common=false",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     "-I" + os.path.join(ROOT, "include"),
 ]

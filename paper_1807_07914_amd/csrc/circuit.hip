@@ -1,19 +1,751 @@
-// circuit.hip -- execution of whole gate lists (qsv_apply_circuit) and of
-// explicit fused blocks (qsv_apply_fused).
+// circuit.hip -- execution of whole gate lists (qsv_apply_circuit): the
+// fusion planner and the driver of the tile-pass kernel.
+//
+// The paper's general algorithm (section II) optionally augments the circuit
+// with SWAPs to maximise accelerated gate applications and groups gates into
+// ordered super-gates that are applied as a whole; the ExaTENSOR visitor
+// (section IV.B.2) caches instructions lazily and evaluates them in bulk.
+// On the state vector this becomes: queue the instruction list, then
+// repeatedly choose a tile qubit set S and apply, in one HBM pass, every
+// queued gate that (a) acts only on S, or is diagonal, and (b) does not need
+// a gate that stays queued.  Gates commute when they share no qubit, and
+// diagonal gates commute with each other, which the dependency scan uses.
+// Schedules depend only on the circuit's structure and are cached by a hash
+// of it; matrices are filled in for every call.
+#include <algorithm>
+#include <complex>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
 #include "plan.hpp"
+#include "tile.hpp"
 
 namespace qsv {
 
+template <typename T>
+int tile_max_bits();
+template <typename T>
+int tile_reg_bits();
+template <typename T>
+hipError_t launch_tile_pass(cpx<T>* psi, int n, int t, const int32_t* prog_dev, hipStream_t st);
+
+using cd = std::complex<double>;
+
 qsv_status apply_fused_block(qsv_state* s, const qsv_op& o) { return apply_op_pergate(s, o, 0); }
 
-qsv_status run_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const qsv_plan_opts& opts) {
-  (void)opts;
-  qsv_status st = ensure_workspace(s, dense_ws_bytes());
-  if (st) return st;
-  for (int i = 0; i < n_ops; ++i) {
-    st = apply_op_pergate(s, ops[i], 0);
-    if (st) return st;
+// ------------------------------------------------------------ op classes
+enum PKind { PK_U1 = 0, PK_U2 = 1, PK_D1 = 2, PK_D2 = 3, PK_OTHER = 4, PK_NOOP = 5 };
+
+struct POp {
+  int kind = PK_OTHER;
+  int nq = 0;
+  int q[6] = {0, 0, 0, 0, 0, 0};
+  bool sign = false;  // Z (D1) or CZ (D2): a pure sign pattern
+  cd m[16];           // U1: 2x2, U2: 4x4 (listed order), D1: d0,d1, D2: d[4]
+  uint64_t qmask = 0;
+  bool nondiag() const { return kind == PK_U1 || kind == PK_U2 || kind == PK_OTHER; }
+};
+
+static bool is_zero(cd z) { return z.real() == 0.0 && z.imag() == 0.0; }
+static bool is_one(cd z) { return z.real() == 1.0 && z.imag() == 0.0; }
+static bool is_mone(cd z) { return z.real() == -1.0 && z.imag() == 0.0; }
+
+static POp classify(const qsv_op& o) {
+  POp p;
+  p.nq = o.nq;
+  for (int j = 0; j < o.nq; ++j) {
+    p.q[j] = o.q[j];
+    p.qmask |= 1ull << o.q[j];
   }
+  cd m[16];
+  if (o.gate == QSV_MAT) {
+    if (o.nq > 2) {
+      p.kind = PK_OTHER;
+      return p;
+    }
+    const int D = 1 << o.nq;
+    for (int i = 0; i < D * D; ++i) m[i] = cd(o.mat[2 * i], o.mat[2 * i + 1]);
+  } else {
+    const double zero[3] = {0, 0, 0};
+    gate_matrix(o.gate, o.p ? o.p : zero, m);
+  }
+  if (o.nq == 1) {
+    if (is_zero(m[1]) && is_zero(m[2])) {
+      if (is_one(m[0]) && is_one(m[3])) {
+        p.kind = PK_NOOP;
+        return p;
+      }
+      p.kind = PK_D1;
+      p.m[0] = m[0];
+      p.m[1] = m[3];
+      p.sign = is_one(m[0]) && is_mone(m[3]);
+    } else {
+      p.kind = PK_U1;
+      for (int i = 0; i < 4; ++i) p.m[i] = m[i];
+    }
+    return p;
+  }
+  bool diag = true;
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c)
+      if (r != c && !is_zero(m[r * 4 + c])) diag = false;
+  if (diag) {
+    p.kind = PK_D2;
+    for (int i = 0; i < 4; ++i) p.m[i] = m[i * 5];
+    p.sign = is_one(m[0]) && is_one(m[5]) && is_one(m[10]) && is_mone(m[15]);
+  } else {
+    p.kind = PK_U2;
+    for (int i = 0; i < 16; ++i) p.m[i] = m[i];
+  }
+  return p;
+}
+
+// ------------------------------------------------------------- schedule
+struct Round {
+  int R[8];                 // register local bits (exactly RB entries)
+  std::vector<int> ops;     // op indices in application order
+};
+struct Step {
+  bool tile = true;
+  int op = -1;              // fallback op (tile == false)
+  std::vector<int> S;       // sorted tile qubits
+  std::vector<Round> rounds;
+};
+struct Schedule {
+  int n = 0, t = 0, c = 0, RB = 0;
+  std::vector<uint32_t> key;  // exact structure (guards against hash collisions)
+  std::vector<Step> steps;
+  int passes = 0;
+};
+
+// Dependency scan: the ops a pass over tile set S can apply, in program
+// order.  Returns the weighted count of non-diagonal ops taken.
+static int scan(const std::vector<POp>& P, const std::vector<int>& pending, uint64_t Smask,
+                uint64_t allq, std::vector<int>* take) {
+  uint64_t bnd = 0, bd = 0;
+  int score = 0;
+  for (int i : pending) {
+    const POp& o = P[i];
+    const bool nd = o.nondiag();
+    const bool blocked = (o.qmask & bnd) || (nd && (o.qmask & bd));
+    if (!blocked) {
+      const bool exe = !nd || ((o.kind == PK_U1 || o.kind == PK_U2) && (o.qmask & ~Smask) == 0);
+      if (exe) {
+        if (take) take->push_back(i);
+        if (nd) score += o.nq;
+        continue;
+      }
+    }
+    if (nd)
+      bnd |= o.qmask;
+    else
+      bd |= o.qmask;
+    if (bnd == allq) break;
+  }
+  return score;
+}
+
+static std::shared_ptr<Schedule> build_schedule(const std::vector<POp>& P, int n, int t, int c,
+                                                int RB) {
+  auto sch = std::make_shared<Schedule>();
+  sch->n = n;
+  sch->t = t;
+  sch->c = c;
+  sch->RB = RB;
+  const uint64_t allq = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  std::vector<int> pending;
+  for (int i = 0; i < (int)P.size(); ++i)
+    if (P[i].kind != PK_NOOP) pending.push_back(i);
+  std::vector<char> done(P.size(), 0);
+  while (!pending.empty()) {
+    const POp& f0 = P[pending[0]];
+    if (f0.kind == PK_OTHER) {
+      Step st;
+      st.tile = false;
+      st.op = pending[0];
+      sch->steps.push_back(st);
+      pending.erase(pending.begin());
+      continue;
+    }
+    // choose S: low c qubits + first queued non-diagonal op + greedy growth
+    uint64_t Smask = c >= 64 ? ~0ull : ((1ull << c) - 1);
+    if (n <= t) {
+      Smask = allq;
+    } else {
+      for (int i : pending)
+        if (P[i].kind == PK_U1 || P[i].kind == PK_U2) {
+          Smask |= P[i].qmask;
+          break;
+        } else if (P[i].kind == PK_OTHER) {
+          break;
+        }
+      // first queued non-diagonal op position per qubit (tie-break)
+      std::vector<int> firstpos(n, 1 << 30);
+      for (int k = 0; k < (int)pending.size(); ++k) {
+        const POp& o = P[pending[k]];
+        if (!o.nondiag()) continue;
+        for (int j = 0; j < o.nq; ++j) firstpos[o.q[j]] = std::min(firstpos[o.q[j]], k);
+      }
+      while (__builtin_popcountll(Smask) < t) {
+        int best = -1, bs = -1, bpos = 1 << 30;
+        for (int q = 0; q < n; ++q) {
+          if ((Smask >> q) & 1) continue;
+          const int sc = scan(P, pending, Smask | (1ull << q), allq, nullptr);
+          if (sc > bs || (sc == bs && firstpos[q] < bpos)) {
+            best = q;
+            bs = sc;
+            bpos = firstpos[q];
+          }
+        }
+        Smask |= 1ull << best;
+      }
+    }
+    std::vector<int> take;
+    scan(P, pending, Smask, allq, &take);
+    if (take.empty()) {  // cannot happen: the first queued op is executable
+      Step st;
+      st.tile = false;
+      st.op = pending[0];
+      sch->steps.push_back(st);
+      pending.erase(pending.begin());
+      continue;
+    }
+    Step st;
+    for (int q = 0; q < n; ++q)
+      if ((Smask >> q) & 1) st.S.push_back(q);
+    std::vector<int> lpos(n, -1);
+    for (int j = 0; j < (int)st.S.size(); ++j) lpos[st.S[j]] = j;
+    // rounds: greedy in program order over register-bit sets of size RB
+    uint64_t R = 0;
+    Round cur;
+    bool open = false;
+    for (int i : take) {
+      const POp& o = P[i];
+      if (o.kind == PK_U1 || o.kind == PK_U2) {
+        uint64_t B = 0;
+        for (int j = 0; j < o.nq; ++j) B |= 1ull << lpos[o.q[j]];
+        if (open && __builtin_popcountll(R | B) > RB) {
+          st.rounds.push_back(cur);
+          cur = Round();
+          R = 0;
+        }
+        R |= B;
+        open = true;
+        cur.ops.push_back(i);
+        // remember R in cur (finalised below)
+        int k = 0;
+        for (int b = 0; b < 64 && k < 8; ++b)
+          if ((R >> b) & 1) cur.R[k++] = b;
+        for (; k < 8; ++k) cur.R[k] = -1;
+      } else {
+        if (!open) {
+          for (int k = 0; k < 8; ++k) cur.R[k] = -1;
+          open = true;
+        }
+        cur.ops.push_back(i);
+      }
+      done[i] = 1;
+    }
+    if (open) st.rounds.push_back(cur);
+    // pad every round's register set to exactly RB distinct local bits
+    for (Round& r : st.rounds) {
+      uint64_t used = 0;
+      int k = 0;
+      for (; k < 8 && r.R[k] >= 0; ++k) used |= 1ull << r.R[k];
+      for (int b = 0; k < RB && b < (int)st.S.size(); ++b)
+        if (!((used >> b) & 1)) {
+          r.R[k++] = b;
+          used |= 1ull << b;
+        }
+    }
+    sch->steps.push_back(std::move(st));
+    sch->passes++;
+    std::vector<int> rest;
+    for (int i : pending)
+      if (!done[i]) rest.push_back(i);
+    pending.swap(rest);
+  }
+  return sch;
+}
+
+// ------------------------------------------------------- schedule cache
+static std::mutex g_cache_mu;
+static std::unordered_map<uint64_t, std::shared_ptr<Schedule>> g_cache;
+
+static uint64_t mix(uint64_t h, uint64_t v) {
+  h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+  return h;
+}
+
+static std::vector<uint32_t> structure_key(const std::vector<POp>& P, int n, int t, int c, int RB) {
+  std::vector<uint32_t> k = {(uint32_t)n, (uint32_t)t, (uint32_t)c, (uint32_t)RB, (uint32_t)P.size()};
+  for (const POp& o : P) {
+    k.push_back((uint32_t)o.kind | ((uint32_t)o.sign << 8) | ((uint32_t)o.nq << 16));
+    for (int j = 0; j < o.nq; ++j) k.push_back((uint32_t)o.q[j]);
+  }
+  return k;
+}
+
+static uint64_t key_hash(const std::vector<uint32_t>& k) {
+  uint64_t h = 0x51535631ull;
+  for (uint32_t v : k) h = mix(h, v);
+  return h;
+}
+
+// ------------------------------------------------------- materialisation
+// Writes one pass: header, then one kRoundWords block per round (a round
+// whose ops do not fit one block continues in further blocks with the same
+// register bits).
+template <typename T>
+struct BlockWriter {
+  std::vector<int32_t>& prog;
+  size_t b0;       // start of the current block
+  int k;           // next word within the block
+  int nops;
+  int last_op;     // word offset of the previous op (its length absorbs padding)
+  const int NR;
+  const int RB;
+  std::vector<int32_t> header;  // words 1 .. 2+NR (free mask + LDS offsets)
+
+  BlockWriter(std::vector<int32_t>& p, int nr, int rb) : prog(p), b0(0), k(0), nops(0), last_op(-1), NR(nr), RB(rb) {}
+
+  void open() {
+    b0 = prog.size();
+    prog.resize(b0 + kRoundWords, 0);
+    for (size_t i = 0; i < header.size(); ++i) prog[b0 + 1 + i] = header[i];
+    k = 2 + NR;
+    nops = 0;
+    last_op = -1;
+  }
+  void close() { prog[b0] = nops; }
+
+  // position an op of L words: never straddle a 64-word line when L <= 64,
+  // start on a line when L > 64; open a new block when full
+  int place(int L) {
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      int pos = k;
+      const int in_line = pos & 63;
+      if ((L <= 64 && in_line + L > 64) || (L > 64 && in_line != 0)) pos = (pos + 63) & ~63;
+      if (pos + L <= kRoundWords) {
+        if (pos != k) {
+          if (last_op >= 0) {
+            prog[b0 + last_op + 1] += pos - k;  // previous op skips the padding
+          } else {                               // no op yet: a no-op covers the gap
+            prog[b0 + k] = 0;
+            prog[b0 + k + 1] = pos - k;
+            ++nops;
+          }
+        }
+        return pos;
+      }
+      close();
+      open();
+    }
+    return -1;  // op longer than a block (cannot happen for the op types used)
+  }
+
+  void put_real(int at, double v) {
+    if (sizeof(T) == 4) {
+      float f = (float)v;
+      int32_t w;
+      std::memcpy(&w, &f, 4);
+      prog[b0 + at] = w;
+    } else {
+      int64_t w;
+      std::memcpy(&w, &v, 8);
+      prog[b0 + at] = (int32_t)(w & 0xffffffff);
+      prog[b0 + at + 1] = (int32_t)(w >> 32);
+    }
+  }
+
+  void emit(const std::vector<int32_t>& head, const cd* mat, int ncplx) {
+    const int WT = sizeof(T) == 4 ? 1 : 2;
+    const int L = (int)head.size() + 2 * ncplx * WT;
+    const int pos = place(L);
+    for (size_t i = 0; i < head.size(); ++i) prog[b0 + pos + i] = head[i];
+    prog[b0 + pos + 1] = L;
+    int at = pos + (int)head.size();
+    for (int e = 0; e < ncplx; ++e) {
+      put_real(at, mat[e].real());
+      at += WT;
+      put_real(at, mat[e].imag());
+      at += WT;
+    }
+    last_op = pos;
+    k = pos + L;
+    ++nops;
+  }
+};
+
+template <typename T>
+int tile_swizzle_bits();
+
+template <typename T>
+static void emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, int RB,
+                      std::vector<int32_t>& prog) {
+  const int t = (int)st.S.size();
+  const int NR = 1 << RB;
+  const int SB = tile_swizzle_bits<T>();
+  std::vector<int> lpos(n, -1);
+  for (int j = 0; j < t; ++j) lpos[st.S[j]] = j;
+  std::vector<int> nonS;
+  for (int q = 0; q < n; ++q)
+    if (lpos[q] < 0) nonS.push_back(q);
+  const size_t h0 = prog.size();
+  prog.push_back(t);
+  prog.push_back(c);
+  prog.push_back((int32_t)nonS.size());
+  prog.push_back(0);  // number of round blocks, patched below
+  for (int q : st.S) prog.push_back(q);
+  for (int q : nonS) prog.push_back(q);
+  while ((prog.size() - h0) % 64) prog.push_back(0);
+  const size_t blocks0 = prog.size();
+
+  for (const Round& r : st.rounds) {
+    int regof[64];
+    for (int b = 0; b < 64; ++b) regof[b] = -1;
+    uint32_t rmask = 0;
+    for (int k = 0; k < RB; ++k) {
+      regof[r.R[k]] = k;
+      rmask |= 1u << r.R[k];
+    }
+    const uint32_t tmask = t >= 32 ? ~0u : ((1u << t) - 1u);
+    BlockWriter<T> bw(prog, NR, RB);
+    bw.header.push_back((int32_t)(tmask & ~rmask));
+    for (int m = 0; m < NR; ++m) {
+      uint32_t lm = 0;
+      for (int k = 0; k < RB; ++k)
+        if ((m >> k) & 1) lm |= 1u << r.R[k];
+      bw.header.push_back((int32_t)tile_swizzle(lm, SB));
+    }
+    // mask over the register index m of the combinations with register bit j set
+    auto mbit = [&](int j) {
+      uint32_t mk = 0;
+      for (int m = 0; m < NR; ++m)
+        if ((m >> j) & 1) mk |= 1u << m;
+      return mk;
+    };
+    // operand kind/value of a qubit for diagonal ops
+    auto operand = [&](int q, int& kind, int& val) {
+      const int p = lpos[q];
+      if (p < 0) {
+        kind = TK_OUT;
+        val = q;
+      } else if (regof[p] >= 0) {
+        kind = TK_REG;
+        val = (int)mbit(regof[p]);
+      } else {
+        kind = TK_FREE;
+        val = p;
+      }
+    };
+
+    // working list: fold single-qubit chains and batch sign ops
+    struct W {
+      int type;
+      int j0, j1;
+      cd m[16];
+      int op;
+      std::vector<int> signs;
+    };
+    std::vector<W> work;
+    int last_u1[64];
+    for (int b = 0; b < 64; ++b) last_u1[b] = -1;
+    for (int i : r.ops) {
+      const POp& o = P[i];
+      if (o.kind == PK_U1) {
+        const int p = lpos[o.q[0]];
+        if (last_u1[p] >= 0) {  // U <- U_new * U_old
+          W& w = work[last_u1[p]];
+          cd nm[4];
+          for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) nm[a * 2 + b] = o.m[a * 2 + 0] * w.m[b] + o.m[a * 2 + 1] * w.m[2 + b];
+          for (int e = 0; e < 4; ++e) w.m[e] = nm[e];
+          continue;
+        }
+        W w;
+        w.type = TOP_U1;
+        w.j0 = regof[p];
+        w.j1 = -1;
+        for (int e = 0; e < 4; ++e) w.m[e] = o.m[e];
+        w.op = i;
+        work.push_back(w);
+        last_u1[p] = (int)work.size() - 1;
+        continue;
+      }
+      if (o.kind == PK_D1 && lpos[o.q[0]] >= 0 && last_u1[lpos[o.q[0]]] >= 0) {
+        W& w = work[last_u1[lpos[o.q[0]]]];  // diag(d0, d1) * U
+        w.m[0] *= o.m[0];
+        w.m[1] *= o.m[0];
+        w.m[2] *= o.m[1];
+        w.m[3] *= o.m[1];
+        continue;
+      }
+      for (int j = 0; j < o.nq; ++j)
+        if (lpos[o.q[j]] >= 0) last_u1[lpos[o.q[j]]] = -1;
+      if (o.kind == PK_U2) {
+        W w;
+        w.type = TOP_U2;
+        int ja = regof[lpos[o.q[0]]], jb = regof[lpos[o.q[1]]];
+        if (ja < jb) {
+          for (int e = 0; e < 16; ++e) w.m[e] = o.m[e];
+        } else {
+          auto sw = [](int m) { return ((m & 1) << 1) | ((m >> 1) & 1); };
+          for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) w.m[sw(a) * 4 + sw(b)] = o.m[a * 4 + b];
+          std::swap(ja, jb);
+        }
+        w.j0 = ja;
+        w.j1 = jb;
+        w.op = i;
+        work.push_back(w);
+      } else if (o.sign) {
+        if (!work.empty() && work.back().type == TOP_SIGN) {
+          work.back().signs.push_back(i);
+        } else {
+          W w;
+          w.type = TOP_SIGN;
+          w.op = i;
+          w.signs.push_back(i);
+          work.push_back(w);
+        }
+      } else {
+        W w;
+        w.type = o.kind == PK_D1 ? TOP_PHASE1 : TOP_DIAG2;
+        w.op = i;
+        work.push_back(w);
+      }
+    }
+
+    bw.open();
+    for (const W& w : work) {
+      if (w.type == TOP_U1) {
+        bw.emit({TOP_U1, 0, w.j0}, w.m, 4);
+      } else if (w.type == TOP_U2) {
+        bw.emit({TOP_U2, 0, w.j0, w.j1}, w.m, 16);
+      } else if (w.type == TOP_PHASE1) {
+        const POp& o = P[w.op];
+        int kind, val;
+        operand(o.q[0], kind, val);
+        bw.emit({TOP_PHASE1, 0, kind, val}, o.m, 2);
+      } else if (w.type == TOP_DIAG2) {
+        const POp& o = P[w.op];
+        int ka, va, kb, vb;
+        operand(o.q[0], ka, va);
+        operand(o.q[1], kb, vb);
+        bw.emit({TOP_DIAG2, 0, ka, va, kb, vb}, o.m, 4);
+      } else {  // TOP_SIGN
+        uint32_t Mrr = 0, zfree = 0;
+        std::vector<std::pair<int, uint32_t>> fmix, rcmix;  // (free pos | outside q, mask over m)
+        uint32_t Md[32] = {0};
+        std::vector<int32_t> fc, cc;
+        auto add_mask = [](std::vector<std::pair<int, uint32_t>>& v, int key, uint32_t mk) {
+          for (auto& e : v)
+            if (e.first == key) {
+              e.second ^= mk;
+              return;
+            }
+          v.push_back({key, mk});
+        };
+        for (int i : w.signs) {
+          const POp& o = P[i];
+          if (o.kind == PK_D1) {
+            int kd, vl;
+            operand(o.q[0], kd, vl);
+            if (kd == TK_REG) Mrr ^= (uint32_t)vl;
+            else if (kd == TK_FREE) zfree ^= 1u << vl;
+            else cc.insert(cc.end(), {vl, vl});
+            continue;
+          }
+          int ka, va, kb, vb;
+          operand(o.q[0], ka, va);
+          operand(o.q[1], kb, vb);
+          if (ka > kb) {
+            std::swap(ka, kb);
+            std::swap(va, vb);
+          }
+          if (ka == TK_REG && kb == TK_REG) {
+            Mrr ^= (uint32_t)va & (uint32_t)vb;
+          } else if (ka == TK_REG && kb == TK_FREE) {
+            add_mask(fmix, vb, (uint32_t)va);
+          } else if (ka == TK_REG && kb == TK_OUT) {
+            add_mask(rcmix, vb, (uint32_t)va);
+          } else if (ka == TK_FREE && kb == TK_FREE) {
+            const int lo = std::min(va, vb), hi = std::max(va, vb);
+            Md[hi - lo] ^= 1u << lo;
+          } else if (ka == TK_FREE && kb == TK_OUT) {
+            fc.insert(fc.end(), {vb, va});
+          } else {
+            cc.insert(cc.end(), {va, vb});
+          }
+        }
+        std::vector<int32_t> h = {TOP_SIGN, 0, (int32_t)Mrr, (int32_t)fmix.size()};
+        for (auto& e : fmix) h.insert(h.end(), {e.first, (int32_t)e.second});
+        std::vector<int32_t> loc;
+        for (int d = 1; d < 32; ++d)
+          if (Md[d]) loc.insert(loc.end(), {d, (int32_t)Md[d]});
+        h.push_back((int32_t)loc.size() / 2);
+        h.insert(h.end(), loc.begin(), loc.end());
+        h.push_back((int32_t)zfree);
+        h.push_back((int32_t)rcmix.size());
+        for (auto& e : rcmix) h.insert(h.end(), {e.first, (int32_t)e.second});
+        h.push_back((int32_t)fc.size() / 2);
+        h.insert(h.end(), fc.begin(), fc.end());
+        h.push_back((int32_t)cc.size() / 2);
+        h.insert(h.end(), cc.begin(), cc.end());
+        bw.emit(h, nullptr, 0);
+      }
+    }
+    bw.close();
+  }
+  prog[h0 + 3] = (int32_t)((prog.size() - blocks0) / kRoundWords);
+}
+
+// ------------------------------------------------------------- driver
+template <typename T>
+static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const qsv_plan_opts& opts) {
+  const int RB = tile_reg_bits<T>();
+  const int TBMAX = tile_max_bits<T>();
+  const int n = s->n;
+  if (n < RB) {  // register smaller than one register group: per-gate kernels
+    for (int i = 0; i < n_ops; ++i) {
+      qsv_status st = apply_op_pergate(s, ops[i], 0);
+      if (st) return st;
+    }
+    return QSV_OK;
+  }
+  int t = opts.tile_qubits > 0 ? opts.tile_qubits : TBMAX;
+  if (t > TBMAX) return fail(QSV_ERR_UNSUPPORTED, "tile_qubits exceeds the LDS tile capacity");
+  if (t < RB) return fail(QSV_ERR_ARG, "tile_qubits smaller than the register group");
+  if (t > n) t = n;
+  int c = sizeof(T) == 4 ? 5 : 4;  // 256-byte contiguous segments
+  if (c > t) c = t;
+  if (t - c > TBMAX - 4) return fail(QSV_ERR_UNSUPPORTED, "tile shape exceeds segment table");
+
+  std::vector<POp> P(n_ops);
+  for (int i = 0; i < n_ops; ++i) P[i] = classify(ops[i]);
+  std::vector<uint32_t> key = structure_key(P, n, t, c, RB);
+  const uint64_t h = key_hash(key);
+  std::shared_ptr<Schedule> sch;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(h);
+    if (it != g_cache.end() && it->second->key == key) sch = it->second;
+  }
+  if (!sch) {
+    sch = build_schedule(P, n, t, c, RB);
+    sch->key = std::move(key);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (g_cache.size() > 256) g_cache.clear();
+    g_cache[h] = sch;
+  }
+  // materialise programs for all tile steps
+  std::vector<int32_t>& prog = s->hprog;
+  prog.clear();
+  std::vector<size_t> offs;
+  for (const Step& st : sch->steps) {
+    offs.push_back(prog.size());
+    if (st.tile) emit_pass<T>(st, P, n, c, RB, prog);
+  }
+  const size_t need = prog.size() * sizeof(int32_t) + 256;
+  if (s->pbuf_bytes < need) {
+    if (s->pbuf) {
+      QSV_HIP(hipStreamSynchronize(s->stream));
+      QSV_HIP(hipFree(s->pbuf));
+      s->pbuf = nullptr;
+      s->pbuf_bytes = 0;
+    }
+    const size_t want = need < (1u << 20) ? (1u << 20) : need * 2;
+    QSV_HIP(hipMalloc(&s->pbuf, want));
+    s->pbuf_bytes = want;
+  }
+  int32_t* dprog = static_cast<int32_t*>(s->pbuf);
+  if (!prog.empty())
+    QSV_HIP(hipMemcpyAsync(dprog, prog.data(), prog.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           s->stream));
+  qsv_status st0 = ensure_workspace(s, dense_ws_bytes());
+  if (st0) return st0;
+  for (size_t k = 0; k < sch->steps.size(); ++k) {
+    const Step& st = sch->steps[k];
+    if (!st.tile) {
+      qsv_status e = apply_op_pergate(s, ops[st.op], 0);
+      if (e) return e;
+      continue;
+    }
+    QSV_HIP(launch_tile_pass<T>(static_cast<cpx<T>*>(s->psi), n, (int)st.S.size(), dprog + offs[k],
+                                s->stream));
+  }
+  return QSV_OK;
+}
+
+qsv_status run_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const qsv_plan_opts& opts) {
+  if (opts.mode == 1) {
+    qsv_status st = ensure_workspace(s, dense_ws_bytes());
+    if (st) return st;
+    for (int i = 0; i < n_ops; ++i) {
+      st = apply_op_pergate(s, ops[i], 0);
+      if (st) return st;
+    }
+    return QSV_OK;
+  }
+  return s->dt == QSV_C64 ? run_fused_T<float>(s, ops, n_ops, opts)
+                          : run_fused_T<double>(s, ops, n_ops, opts);
+}
+
+// Program image of the fused plan (diagnostics and host-side emulation):
+// the int32 words of every tile pass concatenated, and per step either the
+// word offset of its pass or -(1 + op index) for an op run by its own kernel.
+qsv_status plan_program(const qsv_state* s, const qsv_op* ops, int n_ops, int tile_qubits,
+                        std::vector<int32_t>& prog, std::vector<int64_t>& steps) {
+  const bool f = s->dt == QSV_C64;
+  const int RB = f ? tile_reg_bits<float>() : tile_reg_bits<double>();
+  const int TBMAX = f ? tile_max_bits<float>() : tile_max_bits<double>();
+  int t = tile_qubits > 0 ? tile_qubits : TBMAX;
+  if (t > TBMAX || t < RB) return fail(QSV_ERR_ARG, "bad tile_qubits");
+  const int n = s->n;
+  if (n < RB) return fail(QSV_ERR_UNSUPPORTED, "register smaller than the register group");
+  if (t > n) t = n;
+  int c = f ? 5 : 4;
+  if (c > t) c = t;
+  std::vector<POp> P(n_ops);
+  for (int i = 0; i < n_ops; ++i) P[i] = classify(ops[i]);
+  auto sch = build_schedule(P, n, t, c, RB);
+  prog.clear();
+  steps.clear();
+  for (const Step& st : sch->steps) {
+    if (!st.tile) {
+      steps.push_back(-(int64_t)(1 + st.op));
+      continue;
+    }
+    steps.push_back((int64_t)prog.size());
+    if (f) emit_pass<float>(st, P, n, c, RB, prog);
+    else emit_pass<double>(st, P, n, c, RB, prog);
+  }
+  return QSV_OK;
+}
+
+// Number of HBM passes the fused planner uses for a gate list (diagnostics).
+qsv_status plan_passes(const qsv_state* s, const qsv_op* ops, int n_ops, int tile_qubits,
+                       int* passes, int* fallback_ops) {
+  const bool f = s->dt == QSV_C64;
+  const int RB = f ? tile_reg_bits<float>() : tile_reg_bits<double>();
+  const int TBMAX = f ? tile_max_bits<float>() : tile_max_bits<double>();
+  int t = tile_qubits > 0 ? tile_qubits : TBMAX;
+  if (t > TBMAX || t < RB) return fail(QSV_ERR_ARG, "bad tile_qubits");
+  const int n = s->n;
+  if (t > n) t = n;
+  int c = f ? 5 : 4;
+  if (c > t) c = t;
+  std::vector<POp> P(n_ops);
+  for (int i = 0; i < n_ops; ++i) P[i] = classify(ops[i]);
+  auto sch = build_schedule(P, n, t, c, RB);
+  int fb = 0;
+  for (const Step& st : sch->steps) fb += st.tile ? 0 : 1;
+  if (passes) *passes = sch->passes;
+  if (fallback_ops) *fallback_ops = fb;
   return QSV_OK;
 }
 

@@ -46,6 +46,10 @@ struct qsv_state {
   // device workspace (reduction partials, staged matrices, sampler scratch)
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // device copy of the current fused program (int32 words + matrix data)
+  void* pbuf = nullptr;
+  size_t pbuf_bytes = 0;
+  std::vector<int32_t> hprog;     // host image kept alive across the async upload
   std::atomic<int> busy{0};
 };
 

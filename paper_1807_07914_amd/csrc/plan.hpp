@@ -2,6 +2,7 @@
 // the circuit executor (per-gate dispatch, fused tile passes, dense blocks).
 #pragma once
 #include <complex>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -22,5 +23,12 @@ qsv_status apply_fused_block(qsv_state* s, const qsv_op& o);
 
 // whole gate list (qsv_apply_circuit); ops already validated
 qsv_status run_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const qsv_plan_opts& opts);
+
+// passes / fallback ops the fused planner would use (diagnostics)
+qsv_status plan_passes(const qsv_state* s, const qsv_op* ops, int n_ops, int tile_qubits,
+                       int* passes, int* fallback_ops);
+
+qsv_status plan_program(const qsv_state* s, const qsv_op* ops, int n_ops, int tile_qubits,
+                        std::vector<int32_t>& prog, std::vector<int64_t>& steps);
 
 }  // namespace qsv

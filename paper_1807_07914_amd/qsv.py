@@ -74,6 +74,8 @@ def lib():
         "qsv_copy_to_host": [vp, vp, ctypes.c_size_t],
         "qsv_copy_from_host": [vp, vp, ctypes.c_size_t],
         "qsv_synchronize": [vp],
+        "qsv_plan_info": [i32, i32, ctypes.POINTER(QsvOp), i32, i32, ctypes.POINTER(i32),
+                          ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -155,6 +157,15 @@ class OpList:
                 r.mat = m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def plan_info(n: int, dtype: str, ops, tile_qubits: int = 0) -> dict:
+    """Tile passes and separately launched ops of the fused plan (host only)."""
+    ol = ops if isinstance(ops, OpList) else OpList(ops)
+    p, f = ctypes.c_int(), ctypes.c_int()
+    check(lib().qsv_plan_info(int(n), QSV_C64 if dtype == "c64" else QSV_C128, ol.arr, ol.n,
+                              int(tile_qubits), ctypes.byref(p), ctypes.byref(f)))
+    return {"passes": p.value, "separate_ops": f.value}
+
+
 class State:
     """A device-resident state vector of n qubits (complex64 or complex128)
     whose storage is a torch CUDA tensor owned by this object (or borrowed)."""
@@ -224,6 +235,9 @@ class State:
         opts.mode = MODES[mode]
         opts.tile_qubits = int(tile_qubits)
         check(lib().qsv_apply_circuit(self.handle, ol.arr, ol.n, ctypes.byref(opts)))
+
+    def plan_info(self, ops, tile_qubits: int = 0) -> dict:
+        return plan_info(self.n, self.dtype, ops, tile_qubits)
 
     # -- reductions -------------------------------------------------------
     def expval(self, hamiltonian, per_term: bool = False):

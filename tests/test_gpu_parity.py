@@ -208,3 +208,60 @@ def test_error_paths_on_device():
     s.close()
     with pytest.raises(QsvError):
         s.norm()
+
+
+# ------------------------------------------------------------ fused passes
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,tile", [(5, 0), (8, 0), (13, 0), (14, 0), (16, 0), (16, 9), (18, 7),
+                                    (17, 12)])
+def test_fused_random_circuits(dtype, n, tile):
+    if dtype == "c128" and tile > 12:
+        tile = 12
+    ops = qc.random_ops(n, 150, 1000 + n + tile, dense_k=(1, 2, 3))
+    psi0 = start(n, dtype, 1100 + n)
+    ref = O.run(ops, n, psi=psi0.copy())
+    got = gpu_run(n, dtype, psi0, ops, "fused", tile_qubits=tile)
+    assert np.abs(got - ref).max() <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("family", ["brickwork", "rounds", "qft", "hea", "rotring", "ghz"])
+def test_fused_families(dtype, family):
+    n = 16
+    rng = np.random.default_rng(5)
+    x0 = 0
+    if family == "brickwork":
+        ops = qc.random_brickwork(n, 12, 77)
+    elif family == "rounds":
+        ops = qc.paper_rounds(n, 6, 78)
+    elif family == "qft":
+        ops = qc.qft(n)
+        x0 = qc.qft_input(n, 79)
+    elif family == "hea":
+        ops = qc.hea_circuit(n, rng.uniform(0, 2 * np.pi, (10, n, 2)))
+    elif family == "rotring":
+        ops = qc.rot_ring_ansatz(n, rng.uniform(0, 2 * np.pi, 3 * 3 * n), 3)
+    else:
+        ops = qc.ghz(n)
+    ref = O.run(ops, n, x0=x0)
+    s = State(n, dtype)
+    s.set_basis(x0)
+    info = s.plan_info(ops)
+    s.apply_circuit(ops, mode="fused")
+    got = s.to_numpy()
+    s.close()
+    assert info["passes"] < len(ops)
+    assert np.abs(got - ref).max() <= TOL[dtype], info
+
+
+def test_fused_plan_is_reused_with_new_matrices():
+    # same structure, different angles: the cached schedule must take the new values
+    n = 15
+    for seed in (1, 2, 3):
+        ops = qc.random_brickwork(n, 6, seed)
+        ref = O.run(ops, n)
+        s = State(n, "c128")
+        s.apply_circuit(ops, mode="fused")
+        got = s.to_numpy()
+        s.close()
+        assert np.abs(got - ref).max() <= 1e-12
