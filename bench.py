@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Benchmark of the state-vector hot path on one MI355X.
+
+Step = one pass of the whole hot path over the headline workload: a 28-qubit
+random circuit of depth 40 (Haar SU(2) on every qubit, then CZ on alternating
+nearest-neighbour pairs; 1660 gates; seed 1002) in complex64, applied in
+place with the fused tile-pass planner, followed by the FP64 reductions
+(sum_i Z_i Z_{i+1} + 0.7 sum_i X_i, the norm) and 1024 measurement samples.
+State initialisation is inside the step.  The value is gates per second.
+
+Prints ONE JSON line (see the field list in ``result``).  With --extras it
+also measures the other forms of the hot path on the same GPU (per-gate form,
+complex128, the 30-qubit QFT, dense fused blocks) and adds them under
+"extras".  The CPU oracle is timed on a bounded sample of the same circuit.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "gates/s + achieved HBM GB/s at 28-30 qubits; batched circuits/s; adjoint grads/s"
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+TILE_SOURCES = ["paper_1807_07914_amd/csrc/tile.hip", "paper_1807_07914_amd/csrc/tile.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_pass_c2_traffic.json")
+
+
+def kernel_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def op_flops(o):
+    """Algorithmic real flops per amplitude of one gate record."""
+    if o.name in ("CZ", "Z", "I"):
+        return 0.0
+    if o.name in ("CNOT", "SWAP", "X"):
+        return 0.0
+    if o.name in ("RZ", "S", "SDG", "T", "TDG"):
+        return 6.0          # one complex multiply per amplitude
+    if o.name == "CPHASE":
+        return 6.0 / 4.0    # a quarter of the amplitudes
+    if o.name == "U":
+        d = 1 << o.k
+        return 8.0 * d - 2.0  # row of a dense complex mat-vec
+    return 14.0             # general 2x2: two complex multiplies and one add
+
+
+class Timer:
+    """HIP events on the state's stream around a region."""
+
+    def __init__(self, stream):
+        import torch
+        self.stream = stream
+        self.e0 = torch.cuda.Event(enable_timing=True)
+        self.e1 = torch.cuda.Event(enable_timing=True)
+
+    def __enter__(self):
+        self.e0.record(self.stream)
+        return self
+
+    def __exit__(self, *a):
+        self.e1.record(self.stream)
+
+    def ms(self):
+        self.e1.synchronize()
+        return self.e0.elapsed_time(self.e1)
+
+
+def cpu_baseline(ops, n, budget_s=15.0, min_gates=3):
+    """The CPU oracle (complex128, as it stands) on the first gates of the
+    same circuit at the same size, until the time budget is used."""
+    from oracle import oracle as O
+    psi = O.zero_state(n)
+    t0 = time.perf_counter()
+    done = 0
+    for o in ops:
+        O.apply(psi, n, o)
+        done += 1
+        if done >= min_gates and time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "gates/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": "first %d of %d gates of the %d-qubit depth-40 random circuit, complex128, "
+                      "%.1f s" % (done, len(ops), n, dt)}
+
+
+def run_step(s, ol, ham, uniforms, mode="fused"):
+    s.set_basis(0)
+    s.apply_circuit(ol, mode=mode)
+    e = s.expval(ham)
+    nrm = s.norm()
+    smp = s.sample(uniforms)
+    return e, nrm, smp
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=28)
+    ap.add_argument("--extras", action="store_true", help="also time the other forms")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="run one plain 2 GiB device copy first (reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import qcircuits as qc
+    from paper_1807_07914_amd import OpList, State
+    from paper_1807_07914_amd import qsv
+
+    n = args.n
+    ops = qc.random_brickwork(n, 40, qc.SEEDS["c2"])
+    ol = OpList(ops)
+    ham = qc.zz_chain(n) + [(0.7, (("X", q),)) for q in range(n)]
+    uniforms = np.random.default_rng(7).random(1024)
+    plan = qsv.plan_info(n, "c64", ol)
+
+    if args.copy_ref:
+        a = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
+
+    s = State(n, "c64")
+    stream = s.stream
+    for _ in range(args.warmup):
+        run_step(s, ol, ham, uniforms)
+    torch.cuda.synchronize()
+
+    # timed region: exactly K steps, bracketed by synchronisations
+    circ_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.set_basis(0)
+        with Timer(stream) as tm:
+            s.apply_circuit(ol, mode="fused")
+        s.expval(ham)           # synchronises the stream
+        s.norm()
+        s.sample(uniforms)
+        circ_ms.append(tm.ms())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    ms_per_step = elapsed * 1e3 / args.steps
+    gates_per_s = len(ops) * args.steps / elapsed
+    nbytes = (1 << n) * 8
+    circ = float(np.median(circ_ms)) / 1e3
+    launch_s = circ / plan["passes"]            # tile kernels run back to back
+    flops_total = sum(op_flops(o) for o in ops) * (1 << n)
+    flops_per_launch = flops_total / plan["passes"]
+    achieved_tflops = flops_per_launch / launch_s / 1e12
+    hbm_gbs = 2 * nbytes / launch_s / 1e9
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == kernel_hash(TILE_SOURCES) and tr.get("n") == n:
+            traffic = tr.get("bytes_per_launch")
+
+    result = {
+        "metric": METRIC,
+        "value": gates_per_s,
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 (f32 pairs), f64 reductions",
+        "data": "synthetic",
+        "config": {"workload": "random brickwork circuit, %d qubits, depth 40, Haar SU(2) + CZ, "
+                               "seed 1002, complex64, fused tile passes, + expval/norm/1024 samples" % n,
+                   "qubits": n, "gates": len(ops), "passes": plan["passes"]},
+        "hbm_gbs_tile_pass": hbm_gbs,
+        "roofline": {"bound": "alu", "kernel": "k_tile<float,13,5>",
+                     "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": traffic,
+                     "launch_ms": launch_s * 1e3, "algorithmic_bytes_per_launch": 2 * nbytes,
+                     "hbm_frac": hbm_gbs / HBM_PEAK_GBS},
+    }
+
+    if args.extras:
+        ex = {}
+        # per-gate form of the same circuit, complex64
+        s.set_basis(0)
+        torch.cuda.synchronize()
+        with Timer(stream) as tm:
+            s.apply_circuit(ol, mode="pergate")
+        t = tm.ms() / 1e3
+        ex["c64_pergate"] = {"gates_per_s": len(ops) / t, "ms": t * 1e3,
+                             "hbm_gbs_equiv_full_pass": len(ops) * 2 * nbytes / t / 1e9}
+        ex["c64_fused"] = {"gates_per_s": len(ops) / circ, "ms": circ * 1e3, "passes": plan["passes"]}
+        s.close()
+        torch.cuda.empty_cache()
+        s2 = State(n, "c128")
+        p2 = qsv.plan_info(n, "c128", ol)
+        s2.apply_circuit(ol, mode="fused")  # warm-up (plan cache, code objects)
+        for mode in ("fused", "pergate"):
+            s2.set_basis(0)
+            torch.cuda.synchronize()
+            with Timer(s2.stream) as tm:
+                s2.apply_circuit(ol, mode=mode)
+            t = tm.ms() / 1e3
+            ex["c128_" + mode] = {"gates_per_s": len(ops) / t, "ms": t * 1e3,
+                                  "norm_drift": abs(s2.norm() - 1.0)}
+        ex["c128_fused"]["passes"] = p2["passes"]
+        s2.close()
+        torch.cuda.empty_cache()
+        # 30-qubit QFT on a seeded basis state (complex64)
+        nq = 30
+        qops = qc.qft(nq)
+        qol = OpList(qops)
+        x = qc.qft_input(nq, qc.SEEDS["c3"])
+        s3 = State(nq, "c64")
+        s3.set_basis(x)
+        s3.apply_circuit(qol)
+        s3.set_basis(x)
+        torch.cuda.synchronize()
+        with Timer(s3.stream) as tm:
+            s3.apply_circuit(qol)
+        t = tm.ms() / 1e3
+        psi = s3.tensor[:4096].cpu().numpy()
+        y = np.arange(4096, dtype=np.int64)
+        ref = np.exp(2j * np.pi * ((x * y) % (1 << nq)) / (1 << nq)) / 2 ** (nq / 2)
+        ex["qft30_c64"] = {"gates_per_s": len(qops) / t, "ms": t * 1e3,
+                           "passes": qsv.plan_info(nq, "c64", qol)["passes"],
+                           "max_abs_err_first4096": float(np.abs(psi - ref).max())}
+        s3.close()
+        result["extras"] = ex
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(ops, n, budget_s=args.cpu_budget)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -213,13 +213,21 @@ static qsv_status apply_matrix_T(qsv_state* s, int k, const int32_t* q, const cd
     QSV_HIP(launch_gate2<T>(psi, s->n, lo, hi, U, st));
     return QSV_OK;
   }
+  int qq[6];
+  for (int j = 0; j < k; ++j) qq[j] = q[j];
+  if (k >= 4) {  // matrix cores
+    std::vector<T> frag;
+    dense_mfma_fragments<T>(k, m, frag);
+    T* df = reinterpret_cast<T*>(static_cast<char*>(s->ws) + ws_off);
+    QSV_HIP(hipMemcpyAsync(df, frag.data(), frag.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    QSV_HIP(launch_dense_mfma<T>(psi, s->n, k, qq, df, st));
+    return QSV_OK;
+  }
   const int D = 1 << k;
   std::vector<cpx<T>> h(D * D);
   for (int i = 0; i < D * D; ++i) h[i] = rnd<T>(m[i]);
   cpx<T>* dm = reinterpret_cast<cpx<T>*>(static_cast<char*>(s->ws) + ws_off);
   QSV_HIP(hipMemcpyAsync(dm, h.data(), h.size() * sizeof(cpx<T>), hipMemcpyHostToDevice, st));
-  int qq[6];
-  for (int j = 0; j < k; ++j) qq[j] = q[j];
   QSV_HIP(launch_dense<T>(psi, s->n, k, qq, dm, st));
   return QSV_OK;
 }
@@ -263,7 +271,7 @@ qsv_status apply_op_pergate(qsv_state* s, const qsv_op& o, size_t ws_off) {
                           : apply_named_T<double>(s, o.gate, o.q, o.p);
 }
 
-size_t dense_ws_bytes() { return (size_t)64 * 64 * 16; }
+size_t dense_ws_bytes() { return (size_t)256 * 1024; }
 
 }  // namespace qsv
 

@@ -80,6 +80,12 @@ template <typename T>
 hipError_t launch_dense(cpx<T>* psi, int n, int k, const int* qubits, const cpx<T>* mat_dev,
                         hipStream_t st);
 
+// dense k-qubit block (k = 4..6) on the matrix cores; frag_dev holds the
+// real embedding of the matrix in MFMA operand order (dense_mfma_fragments)
+template <typename T>
+hipError_t launch_dense_mfma(cpx<T>* psi, int n, int k, const int* qubits, const T* frag_dev,
+                             hipStream_t st);
+
 // reductions: FP64 partials written to ws, final values to out_dev (doubles)
 template <typename T>
 hipError_t launch_norm(const cpx<T>* psi, uint64_t N, double* ws, double* out_dev, hipStream_t st);

@@ -18,6 +18,10 @@ qsv_status validate_op(const qsv_state* s, const qsv_op& o);
 qsv_status apply_op_pergate(qsv_state* s, const qsv_op& o, size_t ws_off);
 size_t dense_ws_bytes();
 
+// real embedding of a 2^k x 2^k matrix in MFMA operand order
+template <typename T>
+void dense_mfma_fragments(int k, const std::complex<double>* mat, std::vector<T>& frag);
+
 // explicit k-qubit matrix (qsv_apply_fused)
 qsv_status apply_fused_block(qsv_state* s, const qsv_op& o);
 

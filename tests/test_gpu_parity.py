@@ -265,3 +265,37 @@ def test_fused_plan_is_reused_with_new_matrices():
         got = s.to_numpy()
         s.close()
         assert np.abs(got - ref).max() <= 1e-12
+
+
+# ------------------------------------------------------- dense blocks, MFMA
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("k", [4, 5, 6])
+@pytest.mark.parametrize("n", [6, 9, 17])
+def test_dense_blocks_on_matrix_cores(dtype, k, n):
+    if k > n:
+        pytest.skip("block wider than register")
+    rng = np.random.default_rng(100 * k + n)
+    layouts = [list(range(k)), list(range(n - 1, n - 1 - k, -1)),
+               [int(q) for q in rng.permutation(n)[:k]]]
+    for qs in layouts:
+        U = qc.haar_unitary(k, rng)
+        psi0 = start(n, dtype, 7 * k + n)
+        ref = psi0.copy()
+        O.apply_matrix(ref, n, qs, U)
+        s = State(n, dtype)
+        s.from_numpy(psi0)
+        s.apply_fused(qs, U)
+        got = s.to_numpy()
+        s.close()
+        assert np.abs(got - ref).max() <= TOL[dtype], (qs, np.abs(got - ref).max())
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("mode", ["pergate", "fused"])
+def test_circuits_with_wide_blocks(dtype, mode):
+    n = 14
+    ops = qc.random_ops(n, 60, 4242, dense_k=(3, 4, 5, 6), p_dense=0.3)
+    psi0 = start(n, dtype, 4243)
+    ref = O.run(ops, n, psi=psi0.copy())
+    got = gpu_run(n, dtype, psi0, ops, mode)
+    assert np.abs(got - ref).max() <= TOL[dtype]
