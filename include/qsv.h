@@ -157,6 +157,24 @@ qsv_status qsv_plan_info(int n_qubits, qsv_dtype dtype, const qsv_op* ops, int n
 qsv_status qsv_expval(qsv_state* s, const uint64_t* xmask, const uint64_t* zmask,
                       const double* coeff, int n_terms, double* out_total, double* out_terms);
 
+/* Gradient of E(theta) = <psi_L| H |psi_L>, psi_L = U_L ... U_1 psi_0, with
+ * respect to the angle of every RX / RY / RZ op (R_P(theta) = exp(-i theta P/2)),
+ * by one adjoint (reverse) sweep: dE/dtheta_k = Im <lambda_k| P |psi_k> with
+ * lambda_k = U_{k+1}^dag ... U_L^dag H psi_L.  psi_0 is the state's current
+ * content; the ops are applied as by qsv_apply_circuit(opts), E is computed
+ * as by qsv_expval, then a second state-sized device buffer (allocated on
+ * first use, kept with the state) holds lambda while every op is undone in
+ * reverse on both vectors, each rotation's gradient and both inverse updates
+ * sharing one kernel.  energy (host, may be NULL) receives E; grad (host,
+ * n_ops doubles) receives dE/dtheta per op, 0 for ops that are not rotations.
+ * On return the state holds psi_0 again (recomputed by the sweep, up to
+ * rounding).  Gradients accumulate in FP64.  (A parameter-gradient of the
+ * paper's section V.B variational use case; not a computation of the paper.)
+ * Errors: QSV_ERR_ARG (ops, masks, coefficients), QSV_ERR_OOM. */
+qsv_status qsv_adjoint(qsv_state* s, const qsv_op* ops, int n_ops, const uint64_t* xmask,
+                       const uint64_t* zmask, const double* coeff, int n_terms,
+                       const qsv_plan_opts* opts, double* energy, double* grad);
+
 /* sum_i |psi_i|^2 in FP64 (host result). */
 qsv_status qsv_norm(qsv_state* s, double* out);
 
@@ -167,6 +185,34 @@ qsv_status qsv_norm(qsv_state* s, double* out);
  * host arrays of n_shots entries.  Errors: QSV_ERR_ARG (u outside [0,1),
  * n_shots < 0). */
 qsv_status qsv_sample(qsv_state* s, const double* uniforms, int n_shots, uint64_t* out);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent circuits (each from |0...0>, uneven widths) evaluated in
+ * one persistent kernel launch that a HIP graph replays.  Circuit i has
+ * widths[i] qubits (1..30), ops[op_offsets[i] .. op_offsets[i+1]) (gates on
+ * at most 2 qubits) and the diagonal Hamiltonian sum_t coeff[t] Z(zmask[t])
+ * over terms [term_offsets[i], term_offsets[i+1]) (Z-strings only).  Each
+ * workgroup pulls the next circuit (largest first) from a device counter and
+ * runs it alone: circuits that fit one LDS tile never touch HBM, wider ones
+ * stream tile passes through a scratch region owned by the batch.  Energies
+ * accumulate in FP64.  tile_qubits 0 lets the autotuner time the candidate
+ * tile widths on this batch and keep the fastest (cached per structure).
+ * The parameter-sweep loop of the paper's VQE listing (section V.B) is the
+ * use case.  Creation allocates all device memory; runs allocate nothing.
+ * Errors: QSV_ERR_ARG, QSV_ERR_UNSUPPORTED (wider gates), QSV_ERR_OOM. */
+typedef struct qsv_batch qsv_batch;
+qsv_status qsv_batch_create(qsv_dtype dtype, int n_circuits, const int32_t* widths,
+                            const int32_t* op_offsets, const qsv_op* ops,
+                            const int32_t* term_offsets, const uint64_t* zmask, const double* coeff,
+                            int tile_qubits, qsv_batch** out);
+/* New parameter values (angles, matrices) for the same gate structure. */
+qsv_status qsv_batch_update(qsv_batch* b, const qsv_op* ops);
+/* Launch the captured graph; energies (host, n_circuits doubles) on return. */
+qsv_status qsv_batch_run(qsv_batch* b, double* energies);
+/* Chosen tile width, total tile passes over all circuits, scratch bytes. */
+qsv_status qsv_batch_info(const qsv_batch* b, int* tile_qubits, int* total_passes,
+                          int64_t* scratch_bytes);
+qsv_status qsv_batch_free(qsv_batch* b);
 
 /* Copy the raw amplitudes to / from host memory (bytes must equal the state
  * size).  Synchronous. */

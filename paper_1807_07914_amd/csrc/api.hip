@@ -191,8 +191,9 @@ static void canon2(const cd* in, int q0, int q1, cd* out) {
 }
 
 template <typename T>
-static qsv_status apply_matrix_T(qsv_state* s, int k, const int32_t* q, const cd* m, size_t ws_off) {
-  cpx<T>* psi = static_cast<cpx<T>*>(s->psi);
+static qsv_status apply_matrix_data(qsv_state* s, void* data, int k, const int32_t* q, const cd* m,
+                                    size_t ws_off) {
+  cpx<T>* psi = static_cast<cpx<T>*>(data);
   hipStream_t st = s->stream;
   if (k == 1) {
     if (m[1] == 0.0 && m[2] == 0.0) {
@@ -205,6 +206,14 @@ static qsv_status apply_matrix_T(qsv_state* s, int k, const int32_t* q, const cd
     return QSV_OK;
   }
   if (k == 2) {
+    bool diag = true;
+    for (int r = 0; r < 4; ++r)
+      for (int cc = 0; cc < 4; ++cc)
+        if (r != cc && m[r * 4 + cc] != 0.0) diag = false;
+    if (diag && m[0] == 1.0 && m[5] == 1.0 && m[10] == 1.0) {  // phase on |11> only
+      QSV_HIP(launch_cphase<T>(psi, s->n, q[0], q[1], rnd<T>(m[15]), st));
+      return QSV_OK;
+    }
     cd c[16];
     canon2(m, q[0], q[1], c);
     M4<T> U;
@@ -230,6 +239,30 @@ static qsv_status apply_matrix_T(qsv_state* s, int k, const int32_t* q, const cd
   QSV_HIP(hipMemcpyAsync(dm, h.data(), h.size() * sizeof(cpx<T>), hipMemcpyHostToDevice, st));
   QSV_HIP(launch_dense<T>(psi, s->n, k, qq, dm, st));
   return QSV_OK;
+}
+
+template <typename T>
+static qsv_status apply_matrix_T(qsv_state* s, int k, const int32_t* q, const cd* m, size_t ws_off) {
+  return apply_matrix_data<T>(s, s->psi, k, q, m, ws_off);
+}
+
+// The inverse of one instruction (conjugate transpose of its matrix) applied
+// to an arbitrary buffer of the state's shape.
+qsv_status apply_op_inverse(qsv_state* s, void* data, const qsv_op& o, size_t ws_off) {
+  const int k = o.nq;
+  const int D = 1 << k;
+  std::vector<cd> m(D * D), mi(D * D);
+  if (o.gate == QSV_MAT) {
+    for (int i = 0; i < D * D; ++i) m[i] = cd(o.mat[2 * i], o.mat[2 * i + 1]);
+  } else {
+    cd g[16];
+    gate_matrix(o.gate, o.p, g);
+    for (int i = 0; i < D * D; ++i) m[i] = g[i];
+  }
+  for (int r = 0; r < D; ++r)
+    for (int c = 0; c < D; ++c) mi[r * D + c] = std::conj(m[c * D + r]);
+  return s->dt == QSV_C64 ? apply_matrix_data<float>(s, data, k, o.q, mi.data(), ws_off)
+                          : apply_matrix_data<double>(s, data, k, o.q, mi.data(), ws_off);
 }
 
 template <typename T>
@@ -340,6 +373,7 @@ qsv_status qsv_free_state(qsv_state* s) {
   hipError_t e = hipStreamSynchronize(s->stream);
   if (s->ws) (void)hipFree(s->ws);
   if (s->pbuf) (void)hipFree(s->pbuf);
+  if (s->aux) (void)hipFree(s->aux);
   if (s->owns && s->psi) (void)hipFree(s->psi);
   s->magic = kDeadMagic;
   delete s;
@@ -469,6 +503,15 @@ qsv_status qsv_debug_plan_program(int n_qubits, qsv_dtype dtype, const qsv_op* o
 qsv_status qsv_expval(qsv_state* s, const uint64_t* xmask, const uint64_t* zmask,
                       const double* coeff, int n_terms, double* out_total, double* out_terms) {
   QSV_ENTER(s);
+  return expval_impl(s, s->psi, xmask, zmask, coeff, n_terms, out_total, out_terms);
+}
+
+}  // extern "C"
+
+namespace qsv {
+
+qsv_status expval_impl(qsv_state* s, const void* data, const uint64_t* xmask, const uint64_t* zmask,
+                       const double* coeff, int n_terms, double* out_total, double* out_terms) {
   if (n_terms < 0) return fail(QSV_ERR_ARG, "n_terms < 0");
   if (n_terms == 0) {
     if (out_total) *out_total = 0.0;
@@ -500,10 +543,10 @@ qsv_status qsv_expval(qsv_state* s, const uint64_t* xmask, const uint64_t* zmask
     int j = i;
     while (j < n_terms && xmask[order[j]] == xmask[order[i]]) ++j;
     hipError_t e = s->dt == QSV_C64
-                       ? launch_expval_group<float>(static_cast<const cpx<float>*>(s->psi), s->n,
+                       ? launch_expval_group<float>(static_cast<const cpx<float>*>(data), s->n,
                                                     xmask[order[i]], j - i, &zs[i], &ny[i], ws,
                                                     outd + i, s->stream)
-                       : launch_expval_group<double>(static_cast<const cpx<double>*>(s->psi), s->n,
+                       : launch_expval_group<double>(static_cast<const cpx<double>*>(data), s->n,
                                                      xmask[order[i]], j - i, &zs[i], &ny[i], ws,
                                                      outd + i, s->stream);
     if (e != hipSuccess) return hip_fail(e, "expval");
@@ -538,6 +581,133 @@ qsv_status qsv_expval(qsv_state* s, const uint64_t* xmask, const uint64_t* zmask
     *out_total = v[0];
   }
   return QSV_OK;
+}
+
+
+static qsv_status check_terms(const qsv_state* s, const uint64_t* xmask, const uint64_t* zmask,
+                              const double* coeff, int n_terms) {
+  if (n_terms < 0) return fail(QSV_ERR_ARG, "n_terms < 0");
+  if (n_terms > 0 && (!xmask || !zmask || !coeff)) return fail(QSV_ERR_ARG, "NULL term array");
+  const uint64_t lim = s->n >= 64 ? ~0ull : ((1ull << s->n) - 1);
+  for (int t = 0; t < n_terms; ++t) {
+    if ((xmask[t] | zmask[t]) & ~lim) return fail(QSV_ERR_ARG, "Pauli mask names a qubit >= n");
+    if (!std::isfinite(coeff[t])) return fail(QSV_ERR_ARG, "non-finite coefficient");
+  }
+  return QSV_OK;
+}
+
+template <typename T>
+static qsv_status adjoint_sweep(qsv_state* s, const qsv_op* ops, int n_ops, const uint64_t* xmask,
+                                const uint64_t* zmask, const double* coeff, int n_terms,
+                                double* grad) {
+  const size_t stage = dense_ws_bytes();
+  const size_t npart = adjoint_partials();
+  qsv_status st = ensure_workspace(s, stage + (npart + (size_t)n_ops + 1) * sizeof(double));
+  if (st) return st;
+  if (s->aux_bytes < s->bytes) {
+    if (s->aux) {
+      QSV_HIP(hipStreamSynchronize(s->stream));
+      QSV_HIP(hipFree(s->aux));
+      s->aux = nullptr;
+      s->aux_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&s->aux, s->bytes);
+    if (e != hipSuccess) {
+      s->aux = nullptr;
+      return hip_fail(e, "hipMalloc(adjoint buffer)");
+    }
+    s->aux_bytes = s->bytes;
+  }
+  cpx<T>* psi = static_cast<cpx<T>*>(s->psi);
+  cpx<T>* lam = static_cast<cpx<T>*>(s->aux);
+  double* part = reinterpret_cast<double*>(static_cast<char*>(s->ws) + stage);
+  double* gdev = part + npart;
+  // lambda = H psi, terms grouped by X mask, weights c * i^{n_y}
+  std::vector<int> order(n_terms);
+  for (int t = 0; t < n_terms; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return xmask[a] < xmask[b]; });
+  std::vector<uint64_t> xs(n_terms), zs(n_terms);
+  std::vector<double> wr(n_terms), wi(n_terms);
+  for (int k = 0; k < n_terms; ++k) {
+    const int t = order[k];
+    xs[k] = xmask[t];
+    zs[k] = zmask[t];
+    const int ny = __builtin_popcountll(xmask[t] & zmask[t]) & 3;
+    const double re[4] = {1, 0, -1, 0}, im[4] = {0, 1, 0, -1};
+    wr[k] = coeff[t] * re[ny];
+    wi[k] = coeff[t] * im[ny];
+  }
+  QSV_HIP(launch_hpsi<T>(psi, lam, s->n, xs.data(), zs.data(), wr.data(), wi.data(), n_terms,
+                         s->stream));
+  std::vector<double> gh(n_ops + 1, 0.0);
+  QSV_HIP(hipMemcpyAsync(gdev, gh.data(), (n_ops + 1) * sizeof(double), hipMemcpyHostToDevice,
+                         s->stream));
+  const cd I(0.0, 1.0);
+  for (int k = n_ops - 1; k >= 0; --k) {
+    const qsv_op& o = ops[k];
+    if (o.gate == QSV_I) continue;
+    if (o.gate == QSV_RX || o.gate == QSV_RY || o.gate == QSV_RZ) {
+      cd m[16];
+      const double back[3] = {-o.p[0], 0, 0};
+      gate_matrix(o.gate, back, m);  // R_P(-theta) = R_P(theta)^dag
+      M2<T> V;
+      for (int e = 0; e < 4; ++e) V.m[e] = cpx<T>{(T)m[e].real(), (T)m[e].imag()};
+      M2<double> G{};
+      if (o.gate == QSV_RX) {
+        G.m[1] = {1, 0};
+        G.m[2] = {1, 0};
+      } else if (o.gate == QSV_RY) {
+        G.m[1] = {0, -1};
+        G.m[2] = {0, 1};
+      } else {
+        G.m[0] = {1, 0};
+        G.m[3] = {-1, 0};
+      }
+      QSV_HIP(launch_adj_rot<T>(psi, lam, s->n, o.q[0], V, G, part, gdev + k, s->stream));
+      continue;
+    }
+    st = apply_op_inverse(s, s->psi, o, 0);
+    if (st) return st;
+    st = apply_op_inverse(s, s->aux, o, 0);
+    if (st) return st;
+  }
+  QSV_HIP(hipMemcpyAsync(grad, gdev, n_ops * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  QSV_HIP(hipStreamSynchronize(s->stream));
+  (void)I;
+  return QSV_OK;
+}
+
+}  // namespace qsv
+
+extern "C" {
+
+qsv_status qsv_adjoint(qsv_state* s, const qsv_op* ops, int n_ops, const uint64_t* xmask,
+                       const uint64_t* zmask, const double* coeff, int n_terms,
+                       const qsv_plan_opts* opts, double* energy, double* grad) {
+  QSV_ENTER(s);
+  if (n_ops < 0 || (n_ops > 0 && (!ops || !grad))) return fail(QSV_ERR_ARG, "bad op list or grad");
+  qsv_status st = check_terms(s, xmask, zmask, coeff, n_terms);
+  if (st) return st;
+  qsv_plan_opts o{};
+  if (opts) o = *opts;
+  if (o.mode < 0 || o.mode > 2) return fail(QSV_ERR_ARG, "mode must be 0, 1 or 2");
+  for (int r = 0; r < 6; ++r)
+    if (o.reserved[r]) return fail(QSV_ERR_ARG, "reserved plan option fields must be zero");
+  for (int i = 0; i < n_ops; ++i) {
+    st = validate_op(s, ops[i]);
+    if (st) return fail(st, "op " + std::to_string(i) + ": " + get_error());
+  }
+  if (n_ops > 0) {
+    st = run_circuit(s, ops, n_ops, o);
+    if (st) return st;
+  }
+  double e = 0.0;
+  st = expval_impl(s, s->psi, xmask, zmask, coeff, n_terms, &e, nullptr);
+  if (st) return st;
+  if (energy) *energy = e;
+  if (n_ops == 0) return QSV_OK;
+  return s->dt == QSV_C64 ? adjoint_sweep<float>(s, ops, n_ops, xmask, zmask, coeff, n_terms, grad)
+                          : adjoint_sweep<double>(s, ops, n_ops, xmask, zmask, coeff, n_terms, grad);
 }
 
 qsv_status qsv_norm(qsv_state* s, double* out) {

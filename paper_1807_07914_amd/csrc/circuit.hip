@@ -17,7 +17,9 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <cmath>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "plan.hpp"
@@ -501,6 +503,21 @@ static void emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
         w.j0 = ja;
         w.j1 = jb;
         w.op = i;
+        // CNOT / SWAP patterns become register permutations
+        static const int pats[3][4] = {{0, 3, 2, 1}, {0, 1, 3, 2}, {0, 2, 1, 3}};
+        for (int code = 0; code < 3; ++code) {
+          bool ok = true;
+          for (int r = 0; r < 4 && ok; ++r)
+            for (int c2 = 0; c2 < 4 && ok; ++c2) {
+              const cd want = (c2 == pats[code][r]) ? cd(1.0, 0.0) : cd(0.0, 0.0);
+              if (w.m[r * 4 + c2] != want) ok = false;
+            }
+          if (ok) {
+            w.type = TOP_PERM2;
+            w.m[0] = cd((double)code, 0.0);
+            break;
+          }
+        }
         work.push_back(w);
       } else if (o.sign) {
         if (!work.empty() && work.back().type == TOP_SIGN) {
@@ -526,6 +543,8 @@ static void emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
         bw.emit({TOP_U1, 0, w.j0}, w.m, 4);
       } else if (w.type == TOP_U2) {
         bw.emit({TOP_U2, 0, w.j0, w.j1}, w.m, 16);
+      } else if (w.type == TOP_PERM2) {
+        bw.emit({TOP_PERM2, 0, w.j0, w.j1, (int32_t)w.m[0].real()}, nullptr, 0);
       } else if (w.type == TOP_PHASE1) {
         const POp& o = P[w.op];
         int kind, val;
@@ -750,3 +769,465 @@ qsv_status plan_passes(const qsv_state* s, const qsv_op* ops, int n_ops, int til
 }
 
 }  // namespace qsv
+
+// ====================================================================
+// Batches of independent circuits: one persistent launch, captured as a
+// hipGraph, with the tile width chosen by timing (autotuner).
+// ====================================================================
+namespace qsv {
+
+template <typename T>
+hipError_t launch_batch(cpx<T>* scratch, const int32_t* progs, const int64_t* passoff,
+                        const int64_t* jobs, const uint64_t* zt, const double* ct, double* out,
+                        int* counter, int njobs, int grid, hipStream_t st);
+
+}  // namespace qsv
+
+struct qsv_batch {
+  uint32_t magic = 0x48544142u;  // "BATH"
+  qsv_dtype dt = QSV_C64;
+  hipStream_t stream = nullptr;
+  int ncirc = 0;
+  std::vector<int> width, op_off, term_off;
+  std::vector<qsv_op> ops;                 // structure copy (matrix pointers cleared)
+  std::vector<uint64_t> op_sig;            // per-op class and qubits (update checks)
+  std::vector<uint32_t> key;               // exact structure of all circuits
+  int tile_bits = 0;
+  int grid = 0;
+  int njobs = 0;
+  int total_passes = 0;
+  size_t scratch_amps = 0;
+  std::vector<int64_t> job_words, passoff;
+  std::vector<int32_t> hprog;
+  std::vector<uint64_t> hz;
+  std::vector<double> hc;
+  // device buffers
+  int32_t* d_prog = nullptr;
+  int64_t* d_passoff = nullptr;
+  int64_t* d_jobs = nullptr;
+  uint64_t* d_z = nullptr;
+  double* d_c = nullptr;
+  void* d_scratch = nullptr;
+  double* d_out = nullptr;
+  int* d_counter = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace qsv {
+
+static std::mutex g_batch_mu;
+static std::unordered_set<const qsv_batch*> g_batches;
+static std::unordered_map<uint64_t, int> g_tuned;  // structure hash -> tile bits
+
+static void batch_release_device(qsv_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  void* ptrs[] = {b->d_prog, b->d_passoff, b->d_jobs, b->d_z, b->d_c, b->d_scratch, b->d_out,
+                  b->d_counter};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  b->d_prog = nullptr;
+  b->d_passoff = nullptr;
+  b->d_jobs = nullptr;
+  b->d_z = nullptr;
+  b->d_c = nullptr;
+  b->d_scratch = nullptr;
+  b->d_out = nullptr;
+  b->d_counter = nullptr;
+}
+
+// Programs of every circuit for tile width t (host images only).
+template <typename T>
+static qsv_status batch_materialise(qsv_batch* b, int t, bool check_only_structure) {
+  const int RB = tile_reg_bits<T>();
+  b->hprog.clear();
+  b->passoff.clear();
+  std::vector<int64_t> first(b->ncirc), npass(b->ncirc);
+  std::vector<int> neff(b->ncirc);
+  for (int ci = 0; ci < b->ncirc; ++ci) {
+    const int n = std::max(b->width[ci], RB);
+    neff[ci] = n;
+    const int tc = std::min(t, n);
+    int c = sizeof(T) == 4 ? 5 : 4;
+    if (c > tc) c = tc;
+    const int o0 = b->op_off[ci], o1 = b->op_off[ci + 1];
+    std::vector<POp> P(o1 - o0);
+    for (int i = o0; i < o1; ++i) P[i - o0] = classify(b->ops[i]);
+    std::vector<uint32_t> key = structure_key(P, n, tc, c, RB);
+    const uint64_t h = key_hash(key);
+    std::shared_ptr<Schedule> sch;
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      auto it = g_cache.find(h);
+      if (it != g_cache.end() && it->second->key == key) sch = it->second;
+    }
+    if (!sch) {
+      sch = build_schedule(P, n, tc, c, RB);
+      sch->key = std::move(key);
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      if (g_cache.size() > 4096) g_cache.clear();
+      g_cache[h] = sch;
+    }
+    first[ci] = (int64_t)b->passoff.size();
+    int np = 0;
+    for (const Step& st : sch->steps) {
+      if (!st.tile)
+        return fail(QSV_ERR_UNSUPPORTED,
+                    "batched circuits support gates on at most 2 qubits (circuit " +
+                        std::to_string(ci) + ")");
+      b->passoff.push_back((int64_t)b->hprog.size());
+      emit_pass<T>(st, P, n, c, RB, b->hprog);
+      ++np;
+    }
+    if (np == 0) {  // empty circuit: one pass with no rounds still builds and reduces the state
+      Step st;
+      for (int q = 0; q < tc; ++q) st.S.push_back(q);
+      b->passoff.push_back((int64_t)b->hprog.size());
+      emit_pass<T>(st, P, n, c, RB, b->hprog);
+      np = 1;
+    }
+    npass[ci] = np;
+  }
+  if (check_only_structure) return QSV_OK;
+  // jobs, largest first
+  std::vector<int> order(b->ncirc);
+  for (int i = 0; i < b->ncirc; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const double cx = std::ldexp((double)(b->op_off[x + 1] - b->op_off[x] + 1), neff[x]);
+    const double cy = std::ldexp((double)(b->op_off[y + 1] - b->op_off[y] + 1), neff[y]);
+    return cx > cy;
+  });
+  b->job_words.assign((size_t)b->ncirc * 8, 0);
+  b->scratch_amps = 0;
+  b->total_passes = 0;
+  for (int k = 0; k < b->ncirc; ++k) {
+    const int ci = order[k];
+    int64_t* J = &b->job_words[(size_t)k * 8];
+    J[0] = neff[ci];
+    J[1] = npass[ci];
+    J[2] = first[ci];
+    J[3] = (int64_t)b->scratch_amps;
+    J[4] = b->term_off[ci];
+    J[5] = b->term_off[ci + 1] - b->term_off[ci];
+    J[6] = ci;
+    if (npass[ci] > 1) b->scratch_amps += (size_t)1 << neff[ci];
+    b->total_passes += (int)npass[ci];
+  }
+  b->njobs = b->ncirc;
+  return QSV_OK;
+}
+
+template <typename T>
+static qsv_status batch_build(qsv_batch* b, int t) {
+  batch_release_device(b);
+  qsv_status st = batch_materialise<T>(b, t, false);
+  if (st) return st;
+  b->tile_bits = t;
+  auto dalloc = [&](void** p, size_t bytes) -> qsv_status {
+    hipError_t e = hipMalloc(p, bytes < 256 ? 256 : bytes);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return hip_fail(e, "hipMalloc(batch)");
+    }
+    return QSV_OK;
+  };
+  if ((st = dalloc((void**)&b->d_prog, b->hprog.size() * 4))) return st;
+  if ((st = dalloc((void**)&b->d_passoff, b->passoff.size() * 8))) return st;
+  if ((st = dalloc((void**)&b->d_jobs, b->job_words.size() * 8))) return st;
+  if ((st = dalloc((void**)&b->d_z, b->hz.size() * 8))) return st;
+  if ((st = dalloc((void**)&b->d_c, b->hc.size() * 8))) return st;
+  if ((st = dalloc(&b->d_scratch, b->scratch_amps * sizeof(cpx<T>)))) return st;
+  if ((st = dalloc((void**)&b->d_out, (size_t)b->ncirc * 8))) return st;
+  if ((st = dalloc((void**)&b->d_counter, 256))) return st;
+  QSV_HIP(hipMemcpy(b->d_prog, b->hprog.data(), b->hprog.size() * 4, hipMemcpyHostToDevice));
+  QSV_HIP(hipMemcpy(b->d_passoff, b->passoff.data(), b->passoff.size() * 8, hipMemcpyHostToDevice));
+  QSV_HIP(hipMemcpy(b->d_jobs, b->job_words.data(), b->job_words.size() * 8, hipMemcpyHostToDevice));
+  if (!b->hz.empty()) {
+    QSV_HIP(hipMemcpy(b->d_z, b->hz.data(), b->hz.size() * 8, hipMemcpyHostToDevice));
+    QSV_HIP(hipMemcpy(b->d_c, b->hc.data(), b->hc.size() * 8, hipMemcpyHostToDevice));
+  }
+  int dev = 0, cus = 0;
+  QSV_HIP(hipGetDevice(&dev));
+  QSV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  b->grid = std::max(1, std::min(b->njobs, 2 * cus));  // two 64 KiB-LDS workgroups per CU
+  // capture reset + persistent kernel once; runs replay the graph
+  QSV_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = launch_batch<T>(static_cast<cpx<T>*>(b->d_scratch), b->d_prog, b->d_passoff,
+                                 b->d_jobs, b->d_z, b->d_c, b->d_out, b->d_counter, b->njobs,
+                                 b->grid, b->stream);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+  if (e != hipSuccess) return hip_fail(e, "batch launch capture");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+  b->graph = g;
+  QSV_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return QSV_OK;
+}
+
+static qsv_status batch_time(qsv_batch* b, float* ms) {
+  hipEvent_t e0, e1;
+  QSV_HIP(hipEventCreate(&e0));
+  QSV_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  for (int r = 0; r < 2; ++r) {
+    QSV_HIP(hipEventRecord(e0, b->stream));
+    QSV_HIP(hipGraphLaunch(b->exec, b->stream));
+    QSV_HIP(hipEventRecord(e1, b->stream));
+    QSV_HIP(hipEventSynchronize(e1));
+    float t = 0;
+    QSV_HIP(hipEventElapsedTime(&t, e0, e1));
+    if (r > 0 || true) best = std::min(best, t);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = best;
+  return QSV_OK;
+}
+
+template <typename T>
+static qsv_status batch_create_T(qsv_batch* b, int tile_qubits) {
+  const int TBMAX = tile_max_bits<T>(), RB = tile_reg_bits<T>();
+  if (tile_qubits > 0) {
+    if (tile_qubits > TBMAX || tile_qubits < RB)
+      return fail(QSV_ERR_ARG, "tile_qubits outside [register group, LDS capacity]");
+    return batch_build<T>(b, tile_qubits);
+  }
+  // autotuner: candidate tile widths timed on the real batch, cached by structure
+  const uint64_t h = key_hash(b->key);
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    auto it = g_tuned.find(h);
+    if (it != g_tuned.end()) return batch_build<T>(b, it->second);
+  }
+  int maxw = 0;
+  for (int w : b->width) maxw = std::max(maxw, w);
+  std::vector<int> cands;
+  for (int t = TBMAX; t >= std::max(RB, TBMAX - 2); --t) cands.push_back(t);
+  if (maxw <= TBMAX - 2) cands = {TBMAX};  // every circuit fits one tile at any candidate
+  int best_t = cands[0];
+  float best_ms = 1e30f;
+  for (int t : cands) {
+    qsv_status st = batch_build<T>(b, t);
+    if (st) return st;
+    float ms = 0;
+    st = batch_time(b, &ms);
+    if (st) return st;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_t = t;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    g_tuned[h] = best_t;
+  }
+  if (best_t != b->tile_bits) return batch_build<T>(b, best_t);
+  return QSV_OK;
+}
+
+}  // namespace qsv
+
+using namespace qsv;
+
+extern "C" {
+
+qsv_status qsv_batch_create(qsv_dtype dtype, int n_circuits, const int32_t* widths,
+                            const int32_t* op_offsets, const qsv_op* ops,
+                            const int32_t* term_offsets, const uint64_t* zmask, const double* coeff,
+                            int tile_qubits, qsv_batch** out) {
+  if (!out) return fail(QSV_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_ERR_ARG, "bad dtype");
+  if (n_circuits < 1 || !widths || !op_offsets || !term_offsets)
+    return fail(QSV_ERR_ARG, "need at least one circuit and its offsets");
+  if (op_offsets[0] != 0 || term_offsets[0] != 0) return fail(QSV_ERR_ARG, "offsets must start at 0");
+  for (int i = 0; i < n_circuits; ++i) {
+    if (widths[i] < 1 || widths[i] > 30) return fail(QSV_ERR_ARG, "batch widths must be in [1, 30]");
+    if (op_offsets[i + 1] < op_offsets[i] || term_offsets[i + 1] < term_offsets[i])
+      return fail(QSV_ERR_ARG, "offsets must be non-decreasing");
+  }
+  const int nops = op_offsets[n_circuits], nterms = term_offsets[n_circuits];
+  if (nops > 0 && !ops) return fail(QSV_ERR_ARG, "ops is NULL");
+  if (nterms > 0 && (!zmask || !coeff)) return fail(QSV_ERR_ARG, "term arrays are NULL");
+  std::unique_ptr<qsv_batch> b(new qsv_batch());
+  b->dt = dtype;
+  b->ncirc = n_circuits;
+  b->width.assign(widths, widths + n_circuits);
+  b->op_off.assign(op_offsets, op_offsets + n_circuits + 1);
+  b->term_off.assign(term_offsets, term_offsets + n_circuits + 1);
+  for (int ci = 0; ci < n_circuits; ++ci) {
+    qsv_state tmp;
+    tmp.n = widths[ci];
+    tmp.dt = dtype;
+    tmp.N = 1ull << widths[ci];
+    for (int i = op_offsets[ci]; i < op_offsets[ci + 1]; ++i) {
+      qsv_status st = validate_op(&tmp, ops[i]);
+      if (st) return fail(st, "circuit " + std::to_string(ci) + " op " + std::to_string(i) + ": " + get_error());
+    }
+    const uint64_t lim = (1ull << widths[ci]) - 1;
+    for (int t = term_offsets[ci]; t < term_offsets[ci + 1]; ++t) {
+      if (zmask[t] & ~lim) return fail(QSV_ERR_ARG, "Z mask names a qubit beyond the circuit width");
+      if (!std::isfinite(coeff[t])) return fail(QSV_ERR_ARG, "non-finite coefficient");
+    }
+  }
+  b->ops.assign(ops, ops + nops);
+  b->hz.assign(zmask, zmask + nterms);
+  b->hc.assign(coeff, coeff + nterms);
+  // per-op structural signature, and the exact structure of the whole batch
+  // (autotuner cache key)
+  auto sig = [](const POp& p) {
+    uint64_t v = (uint64_t)p.kind | ((uint64_t)p.sign << 4) | ((uint64_t)p.nq << 5);
+    for (int j = 0; j < p.nq && j < 6; ++j) v |= (uint64_t)(p.q[j] & 63) << (8 + 6 * j);
+    return v;
+  };
+  b->op_sig.resize(nops);
+  for (int i = 0; i < nops; ++i) b->op_sig[i] = sig(classify(ops[i]));
+  b->key = {(uint32_t)dtype, (uint32_t)n_circuits};
+  for (int ci = 0; ci < n_circuits; ++ci) {
+    b->key.push_back((uint32_t)widths[ci]);
+    for (int i = op_offsets[ci]; i < op_offsets[ci + 1]; ++i) {
+      const POp p = classify(ops[i]);
+      b->key.push_back((uint32_t)p.kind | ((uint32_t)p.sign << 8) | ((uint32_t)p.nq << 16));
+      for (int j = 0; j < p.nq; ++j) b->key.push_back((uint32_t)p.q[j]);
+    }
+  }
+  hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreate(batch)");
+  // matrices are copied into the programs; keep only the structure afterwards
+  qsv_status st = dtype == QSV_C64 ? batch_create_T<float>(b.get(), tile_qubits)
+                                   : batch_create_T<double>(b.get(), tile_qubits);
+  for (qsv_op& o : b->ops) o.mat = nullptr;
+  if (st) {
+    batch_release_device(b.get());
+    (void)hipStreamDestroy(b->stream);
+    return st;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    g_batches.insert(b.get());
+  }
+  *out = b.release();
+  return QSV_OK;
+}
+
+static bool batch_live(const qsv_batch* b) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  return b && g_batches.count(b);
+}
+
+qsv_status qsv_batch_update(qsv_batch* b, const qsv_op* ops) {
+  if (!batch_live(b)) return fail(QSV_ERR_STATE, "invalid or freed batch handle");
+  const int nops = b->op_off[b->ncirc];
+  if (nops > 0 && !ops) return fail(QSV_ERR_ARG, "ops is NULL");
+  for (int ci = 0; ci < b->ncirc; ++ci) {
+    qsv_state tmp;
+    tmp.n = b->width[ci];
+    tmp.dt = b->dt;
+    tmp.N = 1ull << b->width[ci];
+    for (int i = b->op_off[ci]; i < b->op_off[ci + 1]; ++i) {
+      qsv_status st = validate_op(&tmp, ops[i]);
+      if (st) return st;
+      const POp a = classify(ops[i]);
+      uint64_t v = (uint64_t)a.kind | ((uint64_t)a.sign << 4) | ((uint64_t)a.nq << 5);
+      for (int j = 0; j < a.nq && j < 6; ++j) v |= (uint64_t)(a.q[j] & 63) << (8 + 6 * j);
+      if (v != b->op_sig[i])
+        return fail(QSV_ERR_ARG, "op " + std::to_string(i) + " changes the batch structure");
+    }
+  }
+  std::vector<qsv_op> keep = b->ops;
+  b->ops.assign(ops, ops + nops);
+  const size_t words = b->hprog.size();
+  qsv_status st = b->dt == QSV_C64 ? batch_materialise<float>(b, b->tile_bits, true)
+                                   : batch_materialise<double>(b, b->tile_bits, true);
+  b->ops = keep;
+  if (st) return st;
+  if (b->hprog.size() != words) return fail(QSV_ERR_STATE, "program size changed on update");
+  QSV_HIP(hipMemcpyAsync(b->d_prog, b->hprog.data(), words * 4, hipMemcpyHostToDevice, b->stream));
+  QSV_HIP(hipStreamSynchronize(b->stream));
+  return QSV_OK;
+}
+
+qsv_status qsv_batch_run(qsv_batch* b, double* energies) {
+  if (!batch_live(b)) return fail(QSV_ERR_STATE, "invalid or freed batch handle");
+  QSV_HIP(hipGraphLaunch(b->exec, b->stream));
+  if (energies)
+    QSV_HIP(hipMemcpyAsync(energies, b->d_out, (size_t)b->ncirc * 8, hipMemcpyDeviceToHost,
+                           b->stream));
+  QSV_HIP(hipStreamSynchronize(b->stream));
+  return QSV_OK;
+}
+
+qsv_status qsv_batch_info(const qsv_batch* b, int* tile_qubits, int* total_passes,
+                          int64_t* scratch_bytes) {
+  if (!batch_live(b)) return fail(QSV_ERR_STATE, "invalid or freed batch handle");
+  if (tile_qubits) *tile_qubits = b->tile_bits;
+  if (total_passes) *total_passes = b->total_passes;
+  if (scratch_bytes) *scratch_bytes = (int64_t)(b->scratch_amps * (b->dt == QSV_C64 ? 8 : 16));
+  return QSV_OK;
+}
+
+qsv_status qsv_batch_free(qsv_batch* b) {
+  if (!b) return QSV_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    if (!g_batches.count(b)) return fail(QSV_ERR_STATE, "invalid or freed batch handle");
+    g_batches.erase(b);
+  }
+  (void)hipStreamSynchronize(b->stream);
+  batch_release_device(b);
+  (void)hipStreamDestroy(b->stream);
+  b->magic = 0;
+  delete b;
+  return QSV_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+// Host-only debug export (not in the public header): the program image, pass
+// offsets and job table qsv_batch_create would upload for tile width
+// tile_qubits, for emulation and checks on the CPU.  Sizes are returned in
+// n_words / n_passes; buffers may be NULL for a size query.
+qsv_status qsv_debug_batch_program(qsv_dtype dtype, int n_circuits, const int32_t* widths,
+                                   const int32_t* op_offsets, const qsv_op* ops,
+                                   const int32_t* term_offsets, int tile_qubits, int32_t* words,
+                                   int64_t cap_words, int64_t* n_words, int64_t* passoff,
+                                   int64_t cap_passes, int64_t* n_passes, int64_t* jobs) {
+  if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_ERR_ARG, "bad dtype");
+  if (n_circuits < 1) return fail(QSV_ERR_ARG, "no circuits");
+  qsv_batch b;
+  b.dt = dtype;
+  b.ncirc = n_circuits;
+  b.width.assign(widths, widths + n_circuits);
+  b.op_off.assign(op_offsets, op_offsets + n_circuits + 1);
+  b.term_off.assign(term_offsets, term_offsets + n_circuits + 1);
+  b.ops.assign(ops, ops + op_offsets[n_circuits]);
+  for (int ci = 0; ci < n_circuits; ++ci) {
+    qsv_state tmp;
+    tmp.n = widths[ci];
+    tmp.dt = dtype;
+    tmp.N = 1ull << widths[ci];
+    for (int i = op_offsets[ci]; i < op_offsets[ci + 1]; ++i) {
+      qsv_status st = validate_op(&tmp, ops[i]);
+      if (st) return st;
+    }
+  }
+  const int t = tile_qubits > 0 ? tile_qubits : (dtype == QSV_C64 ? 13 : 12);
+  qsv_status st = dtype == QSV_C64 ? batch_materialise<float>(&b, t, false)
+                                   : batch_materialise<double>(&b, t, false);
+  if (st) return st;
+  if (n_words) *n_words = (int64_t)b.hprog.size();
+  if (n_passes) *n_passes = (int64_t)b.passoff.size();
+  for (int64_t i = 0; words && i < cap_words && i < (int64_t)b.hprog.size(); ++i) words[i] = b.hprog[i];
+  for (int64_t i = 0; passoff && i < cap_passes && i < (int64_t)b.passoff.size(); ++i)
+    passoff[i] = b.passoff[i];
+  if (jobs)
+    for (size_t i = 0; i < b.job_words.size(); ++i) jobs[i] = b.job_words[i];
+  return QSV_OK;
+}
+
+}  // extern "C"

@@ -50,6 +50,9 @@ struct qsv_state {
   void* pbuf = nullptr;
   size_t pbuf_bytes = 0;
   std::vector<int32_t> hprog;     // host image kept alive across the async upload
+  // second state-sized buffer (adjoint sweep: lambda)
+  void* aux = nullptr;
+  size_t aux_bytes = 0;
   std::atomic<int> busy{0};
 };
 
@@ -85,6 +88,15 @@ hipError_t launch_dense(cpx<T>* psi, int n, int k, const int* qubits, const cpx<
 template <typename T>
 hipError_t launch_dense_mfma(cpx<T>* psi, int n, int k, const int* qubits, const T* frag_dev,
                              hipStream_t st);
+
+// adjoint: lambda = H psi, and one reverse step of a rotation (gradient into out_dev)
+template <typename T>
+hipError_t launch_hpsi(const cpx<T>* psi, cpx<T>* lam, int n, const uint64_t* x, const uint64_t* z,
+                       const double* wr, const double* wi, int nt, hipStream_t st);
+template <typename T>
+hipError_t launch_adj_rot(cpx<T>* psi, cpx<T>* lam, int n, int q, const M2<T>& V, const M2<double>& G,
+                          double* part, double* out_dev, hipStream_t st);
+size_t adjoint_partials();
 
 // reductions: FP64 partials written to ws, final values to out_dev (doubles)
 template <typename T>

@@ -22,6 +22,13 @@ size_t dense_ws_bytes();
 template <typename T>
 void dense_mfma_fragments(int k, const std::complex<double>* mat, std::vector<T>& frag);
 
+// inverse of one instruction applied to an arbitrary buffer of the state's shape
+qsv_status apply_op_inverse(qsv_state* s, void* data, const qsv_op& o, size_t ws_off);
+
+// expectation value of a Pauli sum on an arbitrary buffer (host results)
+qsv_status expval_impl(qsv_state* s, const void* data, const uint64_t* xmask, const uint64_t* zmask,
+                       const double* coeff, int n_terms, double* out_total, double* out_terms);
+
 // explicit k-qubit matrix (qsv_apply_fused)
 qsv_status apply_fused_block(qsv_state* s, const qsv_op& o);
 

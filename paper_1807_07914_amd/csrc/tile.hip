@@ -166,14 +166,84 @@ __device__ __forceinline__ void dispatch_u2(cpx<T> (&a)[1 << RB], int j0, int j1
   }
 }
 
+// CNOT / SWAP on register bits: pure register renaming
+template <typename T, int RB, int J0, int J1, int CODE>
+__device__ __forceinline__ void perm2(cpx<T> (&a)[1 << RB]) {
+#pragma unroll
+  for (int m = 0; m < (1 << RB); ++m) {
+    if (((m >> J0) & 1) || ((m >> J1) & 1)) continue;
+    const int i1 = m | (1 << J0), i2 = m | (1 << J1), i3 = m | (1 << J0) | (1 << J1);
+    if (CODE == 0) {
+      const cpx<T> x = a[i1];
+      a[i1] = a[i3];
+      a[i3] = x;
+    } else if (CODE == 1) {
+      const cpx<T> x = a[i2];
+      a[i2] = a[i3];
+      a[i3] = x;
+    } else {
+      const cpx<T> x = a[i1];
+      a[i1] = a[i2];
+      a[i2] = x;
+    }
+  }
+}
+
+template <typename T, int RB, int J0, int J1>
+__device__ __forceinline__ void perm2_code(cpx<T> (&a)[1 << RB], int code) {
+  if (code == 0) perm2<T, RB, J0, J1, 0>(a);
+  else if (code == 1) perm2<T, RB, J0, J1, 1>(a);
+  else perm2<T, RB, J0, J1, 2>(a);
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ void dispatch_perm2(cpx<T> (&a)[1 << RB], int j0, int j1, int code) {
+  const int key = j0 * 8 + j1;
+  switch (key) {
+    case 0 * 8 + 1: perm2_code<T, RB, 0, 1>(a, code); break;
+    case 0 * 8 + 2: perm2_code<T, RB, 0, 2>(a, code); break;
+    case 0 * 8 + 3: perm2_code<T, RB, 0, 3>(a, code); break;
+    case 1 * 8 + 2: perm2_code<T, RB, 1, 2>(a, code); break;
+    case 1 * 8 + 3: perm2_code<T, RB, 1, 3>(a, code); break;
+    case 2 * 8 + 3: perm2_code<T, RB, 2, 3>(a, code); break;
+    default:
+      if constexpr (RB > 4) {
+        constexpr int H = RB > 4 ? 4 : 3;
+        switch (key) {
+          case 0 * 8 + H: perm2_code<T, RB, 0, H>(a, code); break;
+          case 1 * 8 + H: perm2_code<T, RB, 1, H>(a, code); break;
+          case 2 * 8 + H: perm2_code<T, RB, 2, H>(a, code); break;
+          case 3 * 8 + H: perm2_code<T, RB, 3, H>(a, code); break;
+          default: break;
+        }
+      }
+      break;
+  }
+}
+
 // value of a diagonal operand bit that does not depend on m (free / outside)
 __device__ __forceinline__ int const_bit(int kind, int val, uint32_t lg, uint64_t base) {
   return kind == TK_FREE ? (int)((lg >> val) & 1u) : (int)((base >> val) & 1ull);
 }
 
+// What one call of the tile body does around the rounds: take the tile from
+// the state (or build |0...0> in it), write it back, and/or accumulate the
+// FP64 value of sum_t c_t <Z-string_t> over the tile's amplitudes.
+struct TileIO {
+  int init;             // tile starts as the part of |0...0> (no load)
+  int store;            // write the tile back to the state
+  int reduce;           // accumulate the Z-string sum
+  const uint64_t* z;    // Z masks of the terms (reduce)
+  const double* coef;   // coefficients (reduce)
+  int nt;
+};
+
+// One fused tile pass over tile `tid` of the pass program `prog`; returns the
+// thread's partial of the Z-string sum (0 unless io.reduce).  Ends with a
+// barrier so that the caller can start another tile at once.
 template <typename T, int TBMAX, int RB>
-__global__ __launch_bounds__(kTileThreads) void k_tile(cpx<T>* __restrict__ psi,
-                                                        const int32_t* __restrict__ prog) {
+__device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int32_t* __restrict__ prog,
+                                            uint64_t tid, const TileIO& io) {
   constexpr int A = VecInfo<T>::A;
   constexpr int NR = 1 << RB;
   constexpr int VPT = (1 << TBMAX) / A / kTileThreads;  // 16-byte vectors per thread
@@ -187,7 +257,6 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(cpx<T>* __restrict__ psi,
   const int32_t* S = prog + 4;
   const int32_t* nonS = S + t;
   const int32_t* blocks = prog + ((4 + t + nns + 63) & ~63);
-  const uint64_t tid = blockIdx.x;
   uint64_t base = 0;
   for (int i = 0; i < nns; ++i) base |= ((tid >> i) & 1ull) << nonS[i];
   const int nseg = 1 << (t - c);
@@ -211,15 +280,25 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(cpx<T>* __restrict__ psi,
   vec16<T>* gv = reinterpret_cast<vec16<T>*>(psi);
   const int nvec = (1 << t) / A;
   const uint32_t cmask = (1u << c) - 1u;
-#pragma unroll
-  for (int k = 0; k < VPT; ++k) {
-    const int i = threadIdx.x + k * kTileThreads;
-    if (i < nvec) {
+  if (io.init) {
+    for (int i = threadIdx.x; i < nvec; i += kTileThreads) {
       const uint32_t l = (uint32_t)i * A;
       const uint64_t g = base | segoff[l >> c] | (l & cmask);
-      const vec16<T> x = gv[g / A];
 #pragma unroll
-      for (int e = 0; e < A; ++e) tile[tile_swizzle(l + e, SB)] = x.a[e];
+      for (int e = 0; e < A; ++e)
+        tile[tile_swizzle(l + e, SB)] = cpx<T>{(g + e == 0) ? T(1) : T(0), T(0)};
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const int i = threadIdx.x + k * kTileThreads;
+      if (i < nvec) {
+        const uint32_t l = (uint32_t)i * A;
+        const uint64_t g = base | segoff[l >> c] | (l & cmask);
+        const vec16<T> x = gv[g / A];
+#pragma unroll
+        for (int e = 0; e < A; ++e) tile[tile_swizzle(l + e, SB)] = x.a[e];
+      }
     }
   }
   __syncthreads();
@@ -268,6 +347,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(cpx<T>* __restrict__ psi,
           for (int e = 0; e < 16; ++e)
             U.m[e] = cpx<T>{b.real<T>(k + 4 + 2 * e * WT), b.real<T>(k + 4 + (2 * e + 1) * WT)};
           dispatch_u2<T, RB>(a, j0, j1, U);
+        } else if (type == TOP_PERM2) {
+          int wv[3];
+          b.readn<3>(k + 2, wv);
+          dispatch_perm2<T, RB>(a, wv[0], wv[1], wv[2]);
         } else if (type == TOP_SIGN) {
           int p = k + 2;
           uint32_t neg = (uint32_t)b.word(p++);
@@ -329,18 +412,101 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(cpx<T>* __restrict__ psi,
     __syncthreads();
   }
 
-  // ---- store the tile back
-#pragma unroll
-  for (int k = 0; k < VPT; ++k) {
-    const int i = threadIdx.x + k * kTileThreads;
-    if (i < nvec) {
-      const uint32_t l = (uint32_t)i * A;
-      vec16<T> x;
-#pragma unroll
-      for (int e = 0; e < A; ++e) x.a[e] = tile[tile_swizzle(l + e, SB)];
-      const uint64_t g = base | segoff[l >> c] | (l & cmask);
-      gv[g / A] = x;
+  // ---- Z-string sum over the tile (FP64)
+  double acc = 0.0;
+  if (io.reduce) {
+    for (int l = threadIdx.x; l < (1 << t); l += kTileThreads) {
+      const uint64_t g = base | segoff[(uint32_t)l >> c] | ((uint32_t)l & cmask);
+      const cpx<T> x = tile[tile_swizzle((uint32_t)l, SB)];
+      const double pr = fma((double)x.x, (double)x.x, (double)x.y * (double)x.y);
+      double f = 0.0;
+      for (int q = 0; q < io.nt; ++q) f += (__popcll(g & io.z[q]) & 1) ? -io.coef[q] : io.coef[q];
+      acc = fma(pr, f, acc);
     }
+  }
+
+  // ---- store the tile back
+  if (io.store) {
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const int i = threadIdx.x + k * kTileThreads;
+      if (i < nvec) {
+        const uint32_t l = (uint32_t)i * A;
+        vec16<T> x;
+#pragma unroll
+        for (int e = 0; e < A; ++e) x.a[e] = tile[tile_swizzle(l + e, SB)];
+        const uint64_t g = base | segoff[l >> c] | (l & cmask);
+        gv[g / A] = x;
+      }
+    }
+  }
+  __syncthreads();
+  return acc;
+}
+
+template <typename T, int TBMAX, int RB>
+__global__ __launch_bounds__(kTileThreads) void k_tile(cpx<T>* __restrict__ psi,
+                                                        const int32_t* __restrict__ prog) {
+  const TileIO io{0, 1, 0, nullptr, nullptr, 0};
+  (void)tile_body<T, TBMAX, RB>(psi, prog, blockIdx.x, io);
+}
+
+// ------------------------------------------------------------ batches
+// Persistent kernel over many independent circuits.  Each workgroup takes
+// the next job from an atomic counter (jobs are sorted largest first) and
+// runs the whole circuit by itself: every pass of its plan, every tile of a
+// pass in turn.  A circuit that fits one tile lives only in LDS (built as
+// |0...0>, transformed, reduced); wider circuits keep their state in a
+// scratch region of HBM between passes.  The last pass accumulates the
+// circuit's Z-string energy instead of storing the state.
+// Job record (int64 x 8): width, n_passes, first pass index, scratch offset
+// (amplitudes), first term, n_terms, output slot, unused.
+constexpr int kJobWords = 8;
+
+__global__ void k_batch_reset(int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+template <typename T, int TBMAX, int RB>
+__global__ __launch_bounds__(kTileThreads) void k_batch(cpx<T>* __restrict__ scratch,
+                                                         const int32_t* __restrict__ progs,
+                                                         const int64_t* __restrict__ passoff,
+                                                         const int64_t* __restrict__ jobs,
+                                                         const uint64_t* __restrict__ zt,
+                                                         const double* __restrict__ ct,
+                                                         double* __restrict__ out,
+                                                         int* __restrict__ counter, int njobs) {
+  __shared__ int jid;
+  __shared__ double red[kTileThreads];
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) jid = atomicAdd(counter, 1);
+    __syncthreads();
+    // The job index must be a scalar: with a per-lane copy the compiler takes
+    // the exit test for divergent and may nest the loop so that lane 0 (the
+    // only lane that fetches new jobs) leaves while the others spin on the
+    // stale index.
+    const int j = __builtin_amdgcn_readfirstlane(jid);
+    if (j >= njobs) break;
+    const int64_t* J = jobs + (size_t)kJobWords * j;
+    const int w = (int)J[0], np = (int)J[1];
+    const int64_t p0 = J[2], soff = J[3], t0 = J[4], nt = J[5], outi = J[6];
+    double acc = 0.0;
+    for (int p = 0; p < np; ++p) {
+      const int32_t* prog = progs + passoff[p0 + p];
+      const int t = prog[0];
+      const uint64_t ntiles = 1ull << (w - t);
+      const TileIO io{p == 0, p + 1 < np, p + 1 == np, zt + t0, ct + t0, (int)nt};
+      for (uint64_t tid = 0; tid < ntiles; ++tid)
+        acc += tile_body<T, TBMAX, RB>(scratch + soff, prog, tid, io);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s2 = kTileThreads / 2; s2 > 0; s2 >>= 1) {
+      if ((int)threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[outi] = red[0];
   }
 }
 
@@ -375,6 +541,22 @@ hipError_t launch_tile_pass(cpx<T>* psi, int n, int t, const int32_t* prog_dev, 
                      dim3(kTileThreads), 0, st, psi, prog_dev);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_batch(cpx<T>* scratch, const int32_t* progs, const int64_t* passoff,
+                        const int64_t* jobs, const uint64_t* zt, const double* ct, double* out,
+                        int* counter, int njobs, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
+  hipLaunchKernelGGL((k_batch<T, TileCfg<T>::TBMAX, TileCfg<T>::RB>), dim3(grid), dim3(kTileThreads),
+                     0, st, scratch, progs, passoff, jobs, zt, ct, out, counter, njobs);
+  return hipGetLastError();
+}
+template hipError_t launch_batch<float>(cpx<float>*, const int32_t*, const int64_t*, const int64_t*,
+                                        const uint64_t*, const double*, double*, int*, int, int,
+                                        hipStream_t);
+template hipError_t launch_batch<double>(cpx<double>*, const int32_t*, const int64_t*,
+                                         const int64_t*, const uint64_t*, const double*, double*,
+                                         int*, int, int, hipStream_t);
 
 template int tile_max_bits<float>();
 template int tile_max_bits<double>();

@@ -30,6 +30,7 @@
 //     U2     : j0, j1, U[4x4]                4x4 on register bits j0 < j1 (j0 = LSB)
 //     PHASE1 : kind, val, d0, d1             factor d0 / d1 by the qubit's bit
 //     DIAG2  : kindA, valA, kindB, valB, d[4]  factor d[bitA + 2 bitB]
+//     PERM2  : j0, j1, code                 CNOT / SWAP as a register permutation
 //     SIGN   : Mrr, nf, (f, mask)*nf, nd, (d, M)*nd, zfree,
 //              nrc, (q, mask)*nrc, nfc, (q, f)*nfc, ncc, (qa, qb)*ncc
 //              negation pattern over m:  Mrr ^ [mask for every free bit f
@@ -52,6 +53,9 @@ enum TileOpType : int32_t {
   TOP_SIGN = 3,
   TOP_PHASE1 = 4,
   TOP_DIAG2 = 5,
+  TOP_PERM2 = 6,  // j0, j1, code: register permutation on bits j0 < j1 (m = b0 + 2 b1):
+                  // code 0 swaps m = 1 <-> 3 (CNOT, control j0), 1 swaps 2 <-> 3
+                  // (CNOT, control j1), 2 swaps 1 <-> 2 (SWAP)
 };
 
 enum TileOperandKind : int32_t { TK_REG = 0, TK_FREE = 1, TK_OUT = 2 };

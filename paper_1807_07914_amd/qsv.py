@@ -76,6 +76,15 @@ def lib():
         "qsv_synchronize": [vp],
         "qsv_plan_info": [i32, i32, ctypes.POINTER(QsvOp), i32, i32, ctypes.POINTER(i32),
                           ctypes.POINTER(i32)],
+        "qsv_adjoint": [vp, ctypes.POINTER(QsvOp), i32, u64p, u64p, dp, i32,
+                        ctypes.POINTER(QsvPlanOpts), dp, dp],
+        "qsv_batch_create": [i32, i32, ip, ip, ctypes.POINTER(QsvOp), ip, u64p, dp, i32,
+                             ctypes.POINTER(vp)],
+        "qsv_batch_update": [vp, ctypes.POINTER(QsvOp)],
+        "qsv_batch_run": [vp, dp],
+        "qsv_batch_info": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                           ctypes.POINTER(ctypes.c_int64)],
+        "qsv_batch_free": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -251,6 +260,23 @@ class State:
                                terms.ctypes.data_as(dp)))
         return terms[: len(c)].tolist() if per_term else tot.value
 
+    def adjoint(self, ops, hamiltonian, mode: str = "auto", tile_qubits: int = 0):
+        """Apply ops to the current state, return (E, dE/dtheta per op) from
+        one adjoint sweep; the state holds its input again afterwards."""
+        ol = ops if isinstance(ops, OpList) else OpList(ops)
+        x, z, c = pauli_masks(hamiltonian)
+        opts = QsvPlanOpts()
+        opts.mode = MODES[mode]
+        opts.tile_qubits = int(tile_qubits)
+        e = ctypes.c_double()
+        g = np.zeros(max(1, ol.n), dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        u64 = ctypes.POINTER(ctypes.c_uint64)
+        check(lib().qsv_adjoint(self.handle, ol.arr, ol.n, x.ctypes.data_as(u64),
+                                z.ctypes.data_as(u64), c.ctypes.data_as(dp), len(c),
+                                ctypes.byref(opts), ctypes.byref(e), g.ctypes.data_as(dp)))
+        return e.value, g[: ol.n]
+
     def norm(self) -> float:
         out = ctypes.c_double()
         check(lib().qsv_norm(self.handle, ctypes.byref(out)))
@@ -275,3 +301,72 @@ class State:
 
     def synchronize(self) -> None:
         check(lib().qsv_synchronize(self.handle))
+
+
+class Batch:
+    """Many independent circuits (uneven widths, each from |0...0>) evaluated
+    by one persistent kernel replayed from a HIP graph.  ``hamiltonians[i]``
+    must contain Z-strings only; ``run()`` returns one FP64 energy per circuit."""
+
+    def __init__(self, circuits, widths, hamiltonians, dtype: str = "c64", tile_qubits: int = 0):
+        circuits = [list(c) for c in circuits]
+        self.n = len(circuits)
+        self.dtype = dtype
+        self._offsets = np.zeros(self.n + 1, dtype=np.int32)
+        flat = []
+        for i, c in enumerate(circuits):
+            flat += c
+            self._offsets[i + 1] = len(flat)
+        toff = np.zeros(self.n + 1, dtype=np.int32)
+        zs, cs = [], []
+        for i, ham in enumerate(hamiltonians):
+            x, z, c = pauli_masks(ham)
+            if np.any(x != 0):
+                raise ValueError("batched Hamiltonians must be diagonal (Z-strings only)")
+            zs += list(z)
+            cs += list(c)
+            toff[i + 1] = len(zs)
+        self._z = np.ascontiguousarray(zs, dtype=np.uint64) if zs else np.zeros(1, np.uint64)
+        self._c = np.ascontiguousarray(cs, dtype=np.float64) if cs else np.zeros(1, np.float64)
+        self._toff = toff
+        self._w = np.ascontiguousarray(widths, dtype=np.int32)
+        ol = OpList(flat)
+        h = ctypes.c_void_p()
+        check(lib().qsv_batch_create(QSV_C64 if dtype == "c64" else QSV_C128, self.n,
+                                     _ptr_i32(self._w), _ptr_i32(self._offsets), ol.arr,
+                                     _ptr_i32(self._toff),
+                                     self._z.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                     self._c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     int(tile_qubits), ctypes.byref(h)))
+        self._h = h
+
+    def update(self, circuits) -> None:
+        flat = [o for c in circuits for o in c]
+        if len(flat) != int(self._offsets[-1]):
+            raise ValueError("op count differs from the batch structure")
+        check(lib().qsv_batch_update(self._h, OpList(flat).arr))
+
+    def run(self) -> np.ndarray:
+        out = np.zeros(self.n, dtype=np.float64)
+        check(lib().qsv_batch_run(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def info(self) -> dict:
+        t, p, sb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        check(lib().qsv_batch_info(self._h, ctypes.byref(t), ctypes.byref(p), ctypes.byref(sb)))
+        return {"tile_qubits": t.value, "passes": p.value, "scratch_bytes": sb.value}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            check(lib().qsv_batch_free(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr_i32(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))

@@ -1,0 +1,106 @@
+"""Adjoint gradients (through the C ABI) against the CPU oracle's
+parameter-shift rule, which is exact for exp(-i theta P / 2) rotations."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import qcircuits as qc
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+GTOL = {"c128": 1e-10, "c64": 2e-4}
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def State(*a, **k):
+    from paper_1807_07914_amd import State as S
+    return S(*a, **k)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,layers,mode", [(2, 2, "pergate"), (4, 2, "auto"), (7, 3, "fused"),
+                                           (12, 2, "auto")])
+def test_adjoint_matches_parameter_shift(dtype, n, layers, mode):
+    params, ham = qc.gradient_workload(n, layers, 900 + n)
+    build = lambda p: qc.rot_ring_ansatz(n, p, layers)
+    idx = qc.rot_ring_param_index(n, layers)
+    s = State(n, dtype)
+    e, g_ops = s.adjoint(build(params), ham, mode=mode)
+    back = s.to_numpy()
+    s.close()
+    g = np.zeros(params.size)
+    np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
+    ref = O.param_shift_grad(build, params, ham, n)
+    assert abs(e - O.energy(build, params, ham, n)) <= GTOL[dtype] * max(1, len(ham))
+    assert np.abs(g - ref).max() <= GTOL[dtype] * max(1, len(ham))
+    assert np.all(g_ops[idx < 0] == 0)
+    # the sweep returns the state to its input |0...0>
+    assert abs(back[0] - 1) < (1e-10 if dtype == "c128" else 1e-4)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_adjoint_with_mixed_gates(dtype):
+    # rotations interleaved with fixed gates of every other kind
+    n = 6
+    rng = np.random.default_rng(31)
+    fixed = qc.random_ops(n, 30, 32, dense_k=(1, 2, 3, 4))
+    nrot = 14
+    theta = rng.uniform(-np.pi, np.pi, nrot)
+    slots = sorted(rng.choice(len(fixed) + nrot, nrot, replace=False))
+
+    def build(p):
+        ops, it_f, k = [], iter(fixed), 0
+        for i in range(len(fixed) + nrot):
+            if k < nrot and i == slots[k]:
+                ops.append(qc.op(("RX", "RY", "RZ")[k % 3], k % n, params=(p[k],)))
+                k += 1
+            else:
+                ops.append(next(it_f))
+        return ops
+
+    idx = np.array([-1] * (len(fixed) + nrot))
+    for k, sl in enumerate(slots):
+        idx[sl] = k
+    ham = qc.random_hamiltonian(n, 10, 33)
+    s = State(n, dtype)
+    e, g_ops = s.adjoint(build(theta), ham)
+    s.close()
+    g = np.zeros(nrot)
+    np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
+    ref = O.param_shift_grad(build, theta, ham, n)
+    assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham)
+
+
+def test_autograd_function():
+    import torch
+    from paper_1807_07914_amd.autograd import expectation
+    n, layers = 5, 2
+    params, ham = qc.gradient_workload(n, layers, 77)
+    build = lambda p: qc.rot_ring_ansatz(n, p, layers)
+    idx = qc.rot_ring_param_index(n, layers)
+    th = torch.tensor(params, dtype=torch.float64, requires_grad=True)
+    e = expectation(th, build, idx, n, ham, dtype="c128")
+    (2.0 * e).backward()
+    ref = O.param_shift_grad(build, params, ham, n)
+    assert abs(e.item() - O.energy(build, params, ham, n)) < 1e-10
+    assert np.abs(th.grad.numpy() - 2.0 * ref).max() < 1e-9
+
+
+def test_gradient_workload_24q_against_golden():
+    # 24 qubits, 6 layers of RX/RY/RZ + CZ ring (432 parameters), complex64 with
+    # FP64 reductions; selected derivatives by the oracle's parameter shift
+    path = os.path.join(HERE, "golden", "c5_gradients.json")
+    gold = json.load(open(path))
+    n, layers = gold["n"], gold["layers"]
+    params, ham = qc.gradient_workload(n, layers, qc.SEEDS["c5"])
+    idx = qc.rot_ring_param_index(n, layers)
+    s = State(n, "c64")
+    e, g_ops = s.adjoint(qc.rot_ring_ansatz(n, params, layers), ham)
+    s.close()
+    g = np.zeros(params.size)
+    np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
+    assert abs(e - gold["energy"]) < 1e-4
+    for k, ref in zip(gold["indices"], gold["grad"]):
+        assert abs(g[k] - ref) < 2e-4, (k, g[k], ref)

@@ -18,7 +18,7 @@ import numpy as np
 from paper_1807_07914_amd import qsv
 
 ROUND_WORDS = 256
-TOP_U1, TOP_U2, TOP_SIGN, TOP_PHASE1, TOP_DIAG2 = 1, 2, 3, 4, 5
+TOP_U1, TOP_U2, TOP_SIGN, TOP_PHASE1, TOP_DIAG2, TOP_PERM2 = 1, 2, 3, 4, 5, 6
 TK_REG, TK_FREE, TK_OUT = 0, 1, 2
 CFG = {"c64": dict(RB=5, SB=5, WT=1), "c128": dict(RB=4, SB=4, WT=2)}
 
@@ -139,6 +139,16 @@ def run_pass(psi, n, words, off, cfg):
                             y = U @ np.array([a[x] for x in ii])
                             for x, v in zip(ii, y):
                                 a[x] = v
+                    elif typ == TOP_PERM2:
+                        j0, j1, code = blk[k + 2:k + 5]
+                        assert j0 < j1 and code in (0, 1, 2)
+                        sw = {0: (1, 3), 1: (2, 3), 2: (1, 2)}[code]
+                        for m in range(NR):
+                            if (m >> j0) & 1 or (m >> j1) & 1:
+                                continue
+                            ii = [m, m | (1 << j0), m | (1 << j1), m | (1 << j0) | (1 << j1)]
+                            x, y = ii[sw[0]], ii[sw[1]]
+                            a[x], a[y] = a[y], a[x]
                     elif typ == TOP_SIGN:
                         p = k + 2
                         neg = blk[p] & 0xffffffff; p += 1
@@ -215,4 +225,44 @@ def emulate(n, dtype, ops, psi0, tile=0, matrix_of=None):
             _apply_dense(psi, n, list(o.qubits), np.asarray(o.mat, dtype=np.complex128))
         else:
             run_pass(psi, n, words, int(st), cfg)
+    return psi
+
+
+def batch_program(dtype, circuits, widths, tile):
+    flat = [o for c in circuits for o in c]
+    offs = np.zeros(len(circuits) + 1, dtype=np.int32)
+    for i, c in enumerate(circuits):
+        offs[i + 1] = offs[i] + len(c)
+    toff = np.zeros(len(circuits) + 1, dtype=np.int32)
+    w = np.asarray(widths, dtype=np.int32)
+    ol = qsv.OpList(flat)
+    fn = qsv.lib().qsv_debug_batch_program
+    fn.restype = ctypes.c_int
+    i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+    fn.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, ctypes.POINTER(qsv.QsvOp), i32p,
+                   ctypes.c_int, i32p, ctypes.c_int64, i64p, i64p, ctypes.c_int64, i64p, i64p]
+    dt = qsv.QSV_C64 if dtype == "c64" else qsv.QSV_C128
+    nw, npz = ctypes.c_int64(), ctypes.c_int64()
+    args = (dt, len(circuits), w.ctypes.data_as(i32p), offs.ctypes.data_as(i32p), ol.arr,
+            toff.ctypes.data_as(i32p), tile)
+    qsv.check(fn(*args, None, 0, ctypes.byref(nw), None, 0, ctypes.byref(npz), None))
+    words = np.zeros(max(1, nw.value), dtype=np.int32)
+    passoff = np.zeros(max(1, npz.value), dtype=np.int64)
+    jobs = np.zeros(8 * len(circuits), dtype=np.int64)
+    qsv.check(fn(*args, words.ctypes.data_as(i32p), nw.value, ctypes.byref(nw),
+                 passoff.ctypes.data_as(i64p), npz.value, ctypes.byref(npz),
+                 jobs.ctypes.data_as(i64p)))
+    return words, passoff, jobs.reshape(-1, 8)
+
+
+def emulate_batch_job(dtype, words, passoff, job):
+    """Final state of one batch job (init from |0...0> in the first pass)."""
+    w, np_, p0 = int(job[0]), int(job[1]), int(job[2])
+    psi = np.zeros(1 << w, dtype=np.complex128)
+    psi[0] = 1.0
+    for p in range(np_):
+        off = int(passoff[p0 + p])
+        t = int(words[off])
+        assert 1 <= t <= w, (t, w)
+        run_pass(psi, w, words, off, CFG[dtype])
     return psi
