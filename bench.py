@@ -96,6 +96,92 @@ def cpu_baseline(ops, n, budget_s=15.0, min_gates=3):
                       "%.1f s" % (done, len(ops), n, dt)}
 
 
+def bench_batched(np, torch, qc, qsv, count=4096, reps=5, sample=128):
+    """4096 hardware-efficient-ansatz circuits (widths 8..20, 10 layers of
+    RY, RZ + CNOT ladder, seed 1004), <sum Z_i Z_{i+1}> each, complex64, one
+    graph-replayed persistent launch per run.  The per-circuit forms (plain
+    per-gate kernels, and fused tile passes) are timed on a sample of
+    circuits drawn uniformly from the batch and scaled to circuits/s."""
+    b = qc.hea_batch(count, qc.SEEDS["c4"])
+    circs = [b.circuit(i) for i in range(count)]
+    hams = [b.hamiltonian(i) for i in range(count)]
+    widths = [int(w) for w in b.widths]
+    t0 = time.perf_counter()
+    bt = qsv.Batch(circs, widths, hams, dtype="c64")
+    t_create = time.perf_counter() - t0
+    bt.run()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        e = bt.run()
+    t_run = (time.perf_counter() - t0) / reps
+    info = bt.info()
+    bt.close()
+    rng = np.random.default_rng(0)
+    pick = rng.choice(count, sample, replace=False)
+    forms = {}
+    for mode in ("pergate", "fused"):
+        st = {}
+        for i in pick:
+            w = widths[i]
+            if w not in st:
+                st[w] = qsv.State(w, "c64")
+        for s in st.values():          # warm-up (code objects, plans)
+            s.set_basis(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in pick:
+            s = st[widths[i]]
+            s.set_basis(0)
+            s.apply_circuit(circs[i], mode=mode)
+            s.expval(hams[i])
+        dt = time.perf_counter() - t0
+        for s in st.values():
+            s.close()
+        forms[mode] = sample / dt
+    return {"circuits_per_s": count / t_run, "ms_per_batch": t_run * 1e3,
+            "create_and_autotune_s": t_create, "tile_qubits": info["tile_qubits"],
+            "tile_passes": info["passes"], "scratch_gb": info["scratch_bytes"] / 1e9,
+            "energy_checksum": float(np.sum(e)),
+            "pergate_circuits_per_s": forms["pergate"], "fused_circuits_per_s": forms["fused"],
+            "speedup_vs_pergate": count / t_run / forms["pergate"]}
+
+
+def bench_adjoint(np, torch, qc, qsv, reps=3):
+    """24 qubits, 6 layers of RX, RY, RZ + CZ ring (432 parameters, seed
+    1005), H = sum Z_i Z_{i+1} + 0.7 sum X_i, complex64 with FP64 reductions:
+    one forward pass plus one adjoint sweep per gradient vector."""
+    n, layers = 24, 6
+    params, ham = qc.gradient_workload(n, layers, qc.SEEDS["c5"])
+    ops = qsv.OpList(qc.rot_ring_ansatz(n, params, layers))
+    s = qsv.State(n, "c64")
+    s.set_basis(0)
+    s.adjoint(ops, ham)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.set_basis(0)
+        e, g = s.adjoint(ops, ham)
+    t_adj = (time.perf_counter() - t0) / reps
+    fwd = {}
+    for mode in ("fused", "pergate"):
+        s.set_basis(0)
+        s.apply_circuit(ops, mode=mode)
+        s.expval(ham)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_basis(0)
+        s.apply_circuit(ops, mode=mode)
+        s.expval(ham)
+        fwd[mode] = time.perf_counter() - t0
+    s.close()
+    nparam = params.size
+    return {"grads_per_s": 1.0 / t_adj, "params_per_s": nparam / t_adj, "ms_per_gradient": t_adj * 1e3,
+            "energy": e, "forward_fused_ms": fwd["fused"] * 1e3, "forward_pergate_ms": fwd["pergate"] * 1e3,
+            "gradient_cost_in_fused_forwards": t_adj / fwd["fused"],
+            "parameter_shift_equiv_ms": 2 * nparam * fwd["fused"] * 1e3,
+            "speedup_vs_parameter_shift": 2 * nparam * fwd["fused"] / t_adj}
+
+
 def run_step(s, ol, ham, uniforms, mode="fused"):
     s.set_basis(0)
     s.apply_circuit(ol, mode=mode)
@@ -254,6 +340,9 @@ def main():
                            "passes": qsv.plan_info(nq, "c64", qol)["passes"],
                            "max_abs_err_first4096": float(np.abs(psi - ref).max())}
         s3.close()
+        torch.cuda.empty_cache()
+        ex["c4_batched"] = bench_batched(np, torch, qc, qsv)
+        ex["c5_adjoint"] = bench_adjoint(np, torch, qc, qsv)
         result["extras"] = ex
 
     if not args.no_cpu_baseline:
