@@ -105,6 +105,9 @@ static POp classify(const qsv_op& o) {
   return p;
 }
 
+// kinds of the planner's per-round work items
+enum WorkType { TOP_U1 = 1, TOP_U2, TOP_SIGN, TOP_PHASE1, TOP_DIAG2, TOP_PERM2, TOP_GIVENS };
+
 // ------------------------------------------------------------- schedule
 struct Round {
   int R[8];                 // register local bits (exactly RB entries)
@@ -299,98 +302,156 @@ static uint64_t key_hash(const std::vector<uint32_t>& k) {
 
 // ------------------------------------------------------- materialisation
 // Writes one pass: header, then one kRoundWords block per round (a round
-// whose ops do not fit one block continues in further blocks with the same
-// register bits).
+// whose layers do not fit one block continues in further blocks with the
+// same register bits).  Layers fill a block from the front, table lines are
+// taken from the back (lines kRoundLines-1 down to kTableLine0).
 template <typename T>
 struct BlockWriter {
   std::vector<int32_t>& prog;
-  size_t b0;       // start of the current block
-  int k;           // next word within the block
-  int nops;
-  int last_op;     // word offset of the previous op (its length absorbs padding)
+  size_t b0 = 0;      // start of the current block
+  int k = 0;          // next word for a layer
+  int nlayers = 0;
+  int next_line = 0;  // next free table line (counting down)
   const int NR;
-  const int RB;
-  std::vector<int32_t> header;  // words 1 .. 2+NR (free mask + LDS offsets)
+  bool failed = false;          // a layer did not fit an empty block (nothing written)
+  std::vector<int32_t> header;  // words 1 .. 2+NR (free mask + LDS byte offsets)
 
-  BlockWriter(std::vector<int32_t>& p, int nr, int rb) : prog(p), b0(0), k(0), nops(0), last_op(-1), NR(nr), RB(rb) {}
+  BlockWriter(std::vector<int32_t>& p, int nr) : prog(p), NR(nr) {}
 
   void open() {
     b0 = prog.size();
     prog.resize(b0 + kRoundWords, 0);
     for (size_t i = 0; i < header.size(); ++i) prog[b0 + 1 + i] = header[i];
     k = 2 + NR;
-    nops = 0;
-    last_op = -1;
+    nlayers = 0;
+    next_line = kRoundLines - 1;
   }
-  void close() { prog[b0] = nops; }
+  // word 0: number of layers | offset of the first layer << 16
+  void close() { prog[b0] = nlayers | ((2 + NR) << 16); }
 
-  // position an op of L words: never straddle a 64-word line when L <= 64,
-  // start on a line when L > 64; open a new block when full
-  int place(int L) {
-    for (int attempt = 0; attempt < 2; ++attempt) {
-      int pos = k;
-      const int in_line = pos & 63;
-      if ((L <= 64 && in_line + L > 64) || (L > 64 && in_line != 0)) pos = (pos + 63) & ~63;
-      if (pos + L <= kRoundWords) {
-        if (pos != k) {
-          if (last_op >= 0) {
-            prog[b0 + last_op + 1] += pos - k;  // previous op skips the padding
-          } else {                               // no op yet: a no-op covers the gap
-            prog[b0 + k] = 0;
-            prog[b0 + k + 1] = pos - k;
-            ++nops;
-          }
-        }
-        return pos;
-      }
-      close();
-      open();
-    }
-    return -1;  // op longer than a block (cannot happen for the op types used)
-  }
-
-  void put_real(int at, double v) {
+  static void real_words(double v, std::vector<int32_t>& out) {
     if (sizeof(T) == 4) {
       float f = (float)v;
       int32_t w;
       std::memcpy(&w, &f, 4);
-      prog[b0 + at] = w;
+      out.push_back(w);
     } else {
       int64_t w;
       std::memcpy(&w, &v, 8);
-      prog[b0 + at] = (int32_t)(w & 0xffffffff);
-      prog[b0 + at + 1] = (int32_t)(w >> 32);
+      out.push_back((int32_t)(w & 0xffffffff));
+      out.push_back((int32_t)(w >> 32));
     }
   }
 
-  void emit(const std::vector<int32_t>& head, const cd* mat, int ncplx) {
-    const int WT = sizeof(T) == 4 ? 1 : 2;
-    const int L = (int)head.size() + 2 * ncplx * WT;
-    const int pos = place(L);
-    for (size_t i = 0; i < head.size(); ++i) prog[b0 + pos + i] = head[i];
-    prog[b0 + pos + 1] = L;
-    int at = pos + (int)head.size();
-    for (int e = 0; e < ncplx; ++e) {
-      put_real(at, mat[e].real());
-      at += WT;
-      put_real(at, mat[e].imag());
-      at += WT;
+  // A layer of L words that needs n_lines table lines, filled by
+  // fill(words, lines[]) once its lines are known.
+  template <typename F>
+  void layer(int n_lines, F&& fill) {
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      int lines[2] = {-1, -1};
+      bool ok = next_line - n_lines + 1 >= kTableLine0;
+      for (int i = 0; i < n_lines && ok; ++i) lines[i] = next_line - i;
+      std::vector<int32_t> w;
+      fill(w, lines);
+      const int lowest = n_lines > 0 ? lines[n_lines - 1] : next_line + 1;
+      if (ok && k + (int)w.size() <= 64 * lowest) {
+        w[1] = (int32_t)w.size();
+        for (size_t i = 0; i < w.size(); ++i) prog[b0 + k + i] = w[i];
+        k += (int)w.size();
+        next_line -= n_lines;
+        ++nlayers;
+        return;
+      }
+      if (attempt == 1) {
+        failed = true;
+        return;
+      }
+      close();
+      open();
     }
-    last_op = pos;
-    k = pos + L;
-    ++nops;
+  }
+  void put_line(int line, const std::vector<int32_t>& words) {
+    for (size_t i = 0; i < words.size() && i < 64; ++i) prog[b0 + 64 * line + i] = words[i];
   }
 };
 
 template <typename T>
 int tile_swizzle_bits();
 
+// ---------------------------------------------------- gate algebra (host)
+// A 2x2 that is a unitary times a positive scale k factors as
+//     U = diag(l0, l1) . k R . diag(1, r1),   |l0| = |l1| = |r1| = 1,
+// with R a real rotation by theta in [0, pi/2] (cos = c/k, sin = s/k, c and s
+// the moduli of the diagonal and off-diagonal entries).  R runs as three
+// in-place shears (GIVENS op):
+//     R = [[1, -h], [0, 1]] . [[1, 0], [sin, 1]] . [[1, -h], [0, 1]],
+//     h = tan(theta / 2) in [0, 1], sin in [0, 1].
+// (Two shears would do with a deferred diag(1, 1 + tan^2); its moduli then
+// have to be applied before the next rotation on the qubit, which costs more
+// than the third shear.)  Diagonal factors commute with all other diagonal
+// gates and with gates on other qubits, so a tile pass carries them per
+// qubit and applies them in bulk: one 2^RB-entry table per layer of
+// rotations, and a per-group factor for qubits that are not register bits.
+struct Split {
+  int kind;         // 0 diagonal (d0, d1 carry the whole gate), 1 rotation, -1 no factorisation
+  int form;         // 1: three shears (the only form emitted)
+  double p, q;      // shear coefficients
+  cd d0, d1;        // diagonal factor after the rotation (carried)
+  cd r1;            // diagonal factor diag(1, r1) before the rotation
+};
+
+static cd unit_phase(cd z) { return z / std::abs(z); }
+
+static Split split_u1(const cd* u) {
+  Split sp{-1, 0, 0.0, 0.0, cd(1.0), cd(1.0), cd(1.0)};
+  const double a00 = std::abs(u[0]), a01 = std::abs(u[1]), a10 = std::abs(u[2]), a11 = std::abs(u[3]);
+  const double k2 = 0.5 * (a00 * a00 + a01 * a01 + a10 * a10 + a11 * a11);
+  if (!(k2 > 0.0) || !std::isfinite(k2)) return sp;
+  if (a01 == 0.0 && a10 == 0.0) {
+    if (a00 == 0.0 || a11 == 0.0) return sp;  // singular: kept as a 2x2
+    sp.kind = 0;
+    sp.d0 = u[0];
+    sp.d1 = u[3];
+    return sp;
+  }
+  // a scaled unitary has orthogonal columns of equal norm
+  if (std::abs(a00 * a00 + a10 * a10 - k2) > 1e-12 * k2 || std::abs(a01 * a01 + a11 * a11 - k2) > 1e-12 * k2 ||
+      std::abs(std::conj(u[0]) * u[1] + std::conj(u[2]) * u[3]) > 1e-12 * k2 || a10 == 0.0 || a01 == 0.0)
+    return sp;
+  const double c = 0.5 * (a00 + a11), s = 0.5 * (a01 + a10), kap = std::sqrt(c * c + s * s);
+  const cd l1 = unit_phase(u[2]);
+  cd l0, r1;
+  if (a00 > 0.0 && a11 > 0.0) {
+    l0 = unit_phase(u[0]);
+    r1 = unit_phase(u[3]) / l1;
+  } else {
+    l0 = -unit_phase(u[1]);
+    r1 = 1.0;
+  }
+  // accept only an exact factorisation (to rounding)
+  const cd v[4] = {l0 * c, -l0 * s * r1, l1 * s, l1 * c * r1};
+  for (int e = 0; e < 4; ++e)
+    if (std::abs(v[e] - u[e]) > 1e-12 * std::sqrt(k2)) return sp;
+  sp.kind = 1;
+  sp.r1 = r1;
+  // unit rotation by theta in [0, pi/2] as three shears
+  sp.form = 1;
+  sp.p = -s / (kap + c);  // -tan(theta / 2)
+  sp.q = s / kap;         // sin(theta)
+  sp.d0 = kap * l0;
+  sp.d1 = kap * l1;
+  return sp;
+}
+
+// Returns false if a layer does not fit a round block (cannot happen for the
+// layer sizes the planner forms; checked so that nothing is written past it).
 template <typename T>
-static void emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, int RB,
+static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, int RB,
                       std::vector<int32_t>& prog) {
   const int t = (int)st.S.size();
   const int NR = 1 << RB;
   const int SB = tile_swizzle_bits<T>();
+  const int WT = sizeof(T) == 4 ? 1 : 2;
   std::vector<int> lpos(n, -1);
   for (int j = 0; j < t; ++j) lpos[st.S[j]] = j;
   std::vector<int> nonS;
@@ -406,43 +467,218 @@ static void emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
   while ((prog.size() - h0) % 64) prog.push_back(0);
   const size_t blocks0 = prog.size();
 
-  for (const Round& r : st.rounds) {
+  // Diagonal factors not yet applied, per tile-local qubit (diag(pd0, pd1)),
+  // and a scalar for the whole tile.
+  std::vector<cd> pd0(t, cd(1.0)), pd1(t, cd(1.0));
+  cd gscale = 1.0;
+
+  struct PhTerm {
+    uint32_t lgm;
+    uint64_t om;
+    cd r;
+  };
+  // diagonal work that runs between two non-diagonal ops of a round
+  struct DGroup {
+    bool tab = false;
+    cd tb[32];
+    uint32_t Mrr = 0, zfree = 0;
+    std::vector<std::pair<int, uint32_t>> fmix, rcmix;  // (free pos | outside q, mask over m)
+    uint32_t Md[32] = {0};
+    std::vector<int32_t> fc, cc;
+    std::vector<std::pair<int, std::vector<PhTerm>>> phl;  // register bit (-1: every m) -> terms
+    std::vector<int> raw;                                  // PHASE1 / DIAG2 ops kept as they are
+  };
+  struct NdItem {
+    int type = 0;
+    int j0 = -1, j1 = -1;
+    cd m[16];
+    int jf = 0;
+    double p = 0.0, q = 0.0;
+    int code = 0;
+  };
+  struct RPlan {
+    int R[8];
     int regof[64];
-    for (int b = 0; b < 64; ++b) regof[b] = -1;
-    uint32_t rmask = 0;
-    for (int k = 0; k < RB; ++k) {
-      regof[r.R[k]] = k;
-      rmask |= 1u << r.R[k];
+    std::vector<NdItem> nd;
+    std::vector<DGroup> g;  // g[i] runs before nd[i], g.back() after the last one
+    int last[8];            // first group after the last non-diagonal op on register bit j
+  };
+  std::vector<RPlan> plans;
+
+  auto mbit = [&](int j) {
+    uint32_t mk = 0;
+    for (int m = 0; m < NR; ++m)
+      if ((m >> j) & 1) mk |= 1u << m;
+    return mk;
+  };
+  auto table_of = [&](DGroup& g) -> cd* {
+    if (!g.tab) {
+      for (int m = 0; m < NR; ++m) g.tb[m] = 1.0;
+      g.tab = true;
     }
-    const uint32_t tmask = t >= 32 ? ~0u : ((1u << t) - 1u);
-    BlockWriter<T> bw(prog, NR, RB);
-    bw.header.push_back((int32_t)(tmask & ~rmask));
-    for (int m = 0; m < NR; ++m) {
-      uint32_t lm = 0;
-      for (int k = 0; k < RB; ++k)
-        if ((m >> k) & 1) lm |= 1u << r.R[k];
-      bw.header.push_back((int32_t)tile_swizzle(lm, SB));
-    }
-    // mask over the register index m of the combinations with register bit j set
-    auto mbit = [&](int j) {
-      uint32_t mk = 0;
-      for (int m = 0; m < NR; ++m)
-        if ((m >> j) & 1) mk |= 1u << m;
-      return mk;
-    };
-    // operand kind/value of a qubit for diagonal ops
-    auto operand = [&](int q, int& kind, int& val) {
-      const int p = lpos[q];
-      if (p < 0) {
-        kind = TK_OUT;
-        val = q;
-      } else if (regof[p] >= 0) {
-        kind = TK_REG;
-        val = (int)mbit(regof[p]);
-      } else {
-        kind = TK_FREE;
-        val = p;
+    return g.tb;
+  };
+  auto has_sign = [](const DGroup& g) {
+    if (g.Mrr || g.zfree || !g.fmix.empty() || !g.rcmix.empty() || !g.fc.empty() || !g.cc.empty()) return true;
+    for (int d = 0; d < 32; ++d)
+      if (g.Md[d]) return true;
+    return false;
+  };
+  auto has_key = [](const DGroup& g, int key) {
+    for (auto& e : g.phl)
+      if (e.first == key) return true;
+    return false;
+  };
+  // Diagonal work may run anywhere after the last non-diagonal op on its
+  // register bits (group lo) up to the current point (the last group): take
+  // the latest group that already holds work of the same kind, else the last.
+  auto pick = [](RPlan& rp, int lo, auto pred) -> DGroup& {
+    const int hi = (int)rp.g.size() - 1;
+    for (int gi = hi; gi >= lo; --gi)
+      if (pred(rp.g[gi])) return rp.g[gi];
+    return rp.g[hi];
+  };
+  // diag(e0, e1) on register bit j
+  auto tab_bit = [&](RPlan& rp, int j, cd e0, cd e1) {
+    if (e0 == cd(1.0) && e1 == cd(1.0)) return;
+    cd* tbl = table_of(pick(rp, rp.last[j], [](const DGroup& g) { return g.tab; }));
+    for (int m = 0; m < NR; ++m) tbl[m] *= ((m >> j) & 1) ? e1 : e0;
+  };
+  auto add_term = [&](DGroup& g, int key, uint32_t lgm, uint64_t om, cd rr) {
+    for (auto& e : g.phl)
+      if (e.first == key) {
+        for (auto& tm : e.second)
+          if (tm.lgm == lgm && tm.om == om) {
+            tm.r *= rr;
+            return;
+          }
+        e.second.push_back({lgm, om, rr});
+        return;
       }
+    g.phl.push_back({key, {{lgm, om, rr}}});
+  };
+  auto add_mask = [](std::vector<std::pair<int, uint32_t>>& v, int key, uint32_t mk) {
+    for (auto& e : v)
+      if (e.first == key) {
+        e.second ^= mk;
+        return;
+      }
+    v.push_back({key, mk});
+  };
+  // operand kind/value of a qubit for the ops kept as they are
+  auto operand = [&](const RPlan& rp, int q, int& kind, int& val) {
+    const int p = lpos[q];
+    if (p < 0) {
+      kind = TK_OUT;
+      val = q;
+    } else if (rp.regof[p] >= 0) {
+      kind = TK_REG;
+      val = (int)mbit(rp.regof[p]);
+    } else {
+      kind = TK_FREE;
+      val = p;
+    }
+  };
+
+  for (const Round& r : st.rounds) {
+    plans.emplace_back();
+    RPlan& rp = plans.back();
+    for (int b = 0; b < 64; ++b) rp.regof[b] = -1;
+    for (int k = 0; k < RB; ++k) {
+      rp.R[k] = r.R[k];
+      rp.regof[r.R[k]] = k;
+      rp.last[k] = 0;
+    }
+    rp.g.emplace_back();
+    const int* regof = rp.regof;
+
+    // diag(e0, e1) on qubit q: carried while q is in the tile, else a factor
+    // per tile
+    auto phase1 = [&](int q, cd e0, cd e1) {
+      const int p = lpos[q];
+      if (p >= 0) {
+        pd0[p] *= e0;
+        pd1[p] *= e1;
+      } else {
+        gscale *= e0;
+        if (e1 != e0) add_term(pick(rp, 0, [&](const DGroup& g) { return has_key(g, -1); }), -1, 0u, 1ull << q, e1 / e0);
+      }
+    };
+    // factor rr where both qubits are 1
+    auto interaction = [&](int qa, int qb, cd rr) {
+      if (rr == cd(1.0)) return;
+      int pa = lpos[qa], pb = lpos[qb];
+      int ja = pa >= 0 ? regof[pa] : -1, jb = pb >= 0 ? regof[pb] : -1;
+      if (ja >= 0 && jb >= 0) {
+        cd* tbl = table_of(pick(rp, std::max(rp.last[ja], rp.last[jb]), [](const DGroup& g) { return g.tab; }));
+        for (int m = 0; m < NR; ++m)
+          if (((m >> ja) & 1) && ((m >> jb) & 1)) tbl[m] *= rr;
+        return;
+      }
+      if (ja < 0 && jb >= 0) {
+        std::swap(qa, qb);
+        std::swap(pa, pb);
+        std::swap(ja, jb);
+      }
+      uint32_t lgm = 0;
+      uint64_t om = 0;
+      auto other = [&](int q, int p) {
+        if (p >= 0) lgm |= 1u << p;
+        else om |= 1ull << q;
+      };
+      if (ja >= 0) {
+        other(qb, pb);
+        add_term(pick(rp, rp.last[ja], [&](const DGroup& g) { return has_key(g, ja); }), ja, lgm, om, rr);
+      } else {
+        other(qa, pa);
+        other(qb, pb);
+        add_term(pick(rp, 0, [&](const DGroup& g) { return has_key(g, -1); }), -1, lgm, om, rr);
+      }
+    };
+    // CZ as a sign pattern
+    auto cz = [&](int qa, int qb) {
+      int pa = lpos[qa], pb = lpos[qb];
+      int ja = pa >= 0 ? regof[pa] : -1, jb = pb >= 0 ? regof[pb] : -1;
+      if (ja < 0 && jb >= 0) {
+        std::swap(qa, qb);
+        std::swap(pa, pb);
+        std::swap(ja, jb);
+      }
+      auto sg = [&](const DGroup& g) { return has_sign(g) || g.tab; };
+      if (ja >= 0 && jb >= 0) {
+        pick(rp, std::max(rp.last[ja], rp.last[jb]), sg).Mrr ^= mbit(ja) & mbit(jb);
+      } else if (ja >= 0 && pb >= 0) {
+        add_mask(pick(rp, rp.last[ja], has_sign).fmix, pb, mbit(ja));
+      } else if (ja >= 0) {
+        add_mask(pick(rp, rp.last[ja], has_sign).rcmix, qb, mbit(ja));
+      } else {
+        DGroup& g = pick(rp, 0, has_sign);
+        if (pa >= 0 && pb >= 0) {
+          const int lo = std::min(pa, pb), hi = std::max(pa, pb);
+          g.Md[hi - lo] ^= 1u << lo;
+        } else if (pa >= 0 || pb >= 0) {
+          if (pa >= 0) g.fc.insert(g.fc.end(), {qb, pa});
+          else g.fc.insert(g.fc.end(), {qa, pb});
+        } else {
+          g.cc.insert(g.cc.end(), {qa, qb});
+        }
+      }
+    };
+    // an op kept as it is: after the last non-diagonal op on its register bits
+    auto raw = [&](int i) {
+      const POp& o = P[i];
+      int gi = 0;
+      for (int j = 0; j < o.nq; ++j) {
+        const int p = lpos[o.q[j]];
+        if (p >= 0 && regof[p] >= 0) gi = std::max(gi, rp.last[regof[p]]);
+      }
+      rp.g[gi].raw.push_back(i);
+    };
+    auto push_nd = [&](const NdItem& it, int ja, int jb) {
+      rp.nd.push_back(it);
+      rp.g.emplace_back();
+      rp.last[ja] = (int)rp.nd.size();
+      if (jb >= 0) rp.last[jb] = (int)rp.nd.size();
     };
 
     // working list: fold single-qubit chains and batch sign ops
@@ -537,90 +773,363 @@ static void emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
       }
     }
 
-    bw.open();
+
     for (const W& w : work) {
       if (w.type == TOP_U1) {
-        bw.emit({TOP_U1, 0, w.j0}, w.m, 4);
+        const int j = w.j0, p = rp.R[j];
+        // the carried factor's moduli are applied first (real table entries:
+        // every scale stays close to 1 rather than piling up in one scalar);
+        // its phases go into the gate, which keeps a unitary gate unitary
+        const double mu0 = std::abs(pd0[p]), mu1 = std::abs(pd1[p]);
+        cd e0 = pd0[p], e1 = pd1[p];
+        if (mu0 > 0.0 && mu1 > 0.0 && std::isfinite(mu0) && std::isfinite(mu1)) {
+          tab_bit(rp, j, cd(mu0), cd(mu1));
+          e0 /= mu0;
+          e1 /= mu1;
+        }
+        const cd U[4] = {w.m[0] * e0, w.m[1] * e1, w.m[2] * e0, w.m[3] * e1};
+        const Split sp = split_u1(U);
+        if (sp.kind == 0) {
+          pd0[p] = sp.d0;
+          pd1[p] = sp.d1;
+          continue;
+        }
+        NdItem it;
+        it.j0 = j;
+        if (sp.kind == 1) {
+          tab_bit(rp, j, cd(1.0), sp.r1);
+          it.type = TOP_GIVENS;
+          it.jf = j | (sp.form << 8);
+          it.p = sp.p;
+          it.q = sp.q;
+          pd0[p] = sp.d0;
+          pd1[p] = sp.d1;
+        } else {
+          it.type = TOP_U1;
+          for (int e = 0; e < 4; ++e) it.m[e] = U[e];
+          pd0[p] = pd1[p] = 1.0;
+        }
+        push_nd(it, j, -1);
       } else if (w.type == TOP_U2) {
-        bw.emit({TOP_U2, 0, w.j0, w.j1}, w.m, 16);
+        const int p0 = rp.R[w.j0], p1 = rp.R[w.j1];
+        NdItem it;
+        it.type = TOP_U2;
+        it.j0 = w.j0;
+        it.j1 = w.j1;
+        for (int a = 0; a < 4; ++a)
+          for (int b = 0; b < 4; ++b)
+            it.m[a * 4 + b] = w.m[a * 4 + b] * ((b & 1) ? pd1[p0] : pd0[p0]) * ((b >> 1) ? pd1[p1] : pd0[p1]);
+        pd0[p0] = pd1[p0] = pd0[p1] = pd1[p1] = 1.0;
+        push_nd(it, w.j0, w.j1);
       } else if (w.type == TOP_PERM2) {
-        bw.emit({TOP_PERM2, 0, w.j0, w.j1, (int32_t)w.m[0].real()}, nullptr, 0);
+        const int p0 = rp.R[w.j0], p1 = rp.R[w.j1];
+        const int code = (int)w.m[0].real();
+        if (code == 0) {  // CNOT, control j0: the control's factor commutes
+          tab_bit(rp, w.j1, pd0[p1], pd1[p1]);
+          pd0[p1] = pd1[p1] = 1.0;
+        } else if (code == 1) {
+          tab_bit(rp, w.j0, pd0[p0], pd1[p0]);
+          pd0[p0] = pd1[p0] = 1.0;
+        } else {  // SWAP exchanges the carried factors
+          std::swap(pd0[p0], pd0[p1]);
+          std::swap(pd1[p0], pd1[p1]);
+        }
+        NdItem it;
+        it.type = TOP_PERM2;
+        it.j0 = w.j0;
+        it.j1 = w.j1;
+        it.code = code;
+        push_nd(it, w.j0, w.j1);
       } else if (w.type == TOP_PHASE1) {
         const POp& o = P[w.op];
-        int kind, val;
-        operand(o.q[0], kind, val);
-        bw.emit({TOP_PHASE1, 0, kind, val}, o.m, 2);
+        if (!is_zero(o.m[0]) && !is_zero(o.m[1])) phase1(o.q[0], o.m[0], o.m[1]);
+        else raw(w.op);
       } else if (w.type == TOP_DIAG2) {
         const POp& o = P[w.op];
-        int ka, va, kb, vb;
-        operand(o.q[0], ka, va);
-        operand(o.q[1], kb, vb);
-        bw.emit({TOP_DIAG2, 0, ka, va, kb, vb}, o.m, 4);
+        const cd* d = o.m;
+        if (!is_zero(d[0]) && !is_zero(d[1]) && !is_zero(d[2]) && !is_zero(d[3])) {
+          // d(a, b) = d0 ra^a rb^b rab^(ab)
+          gscale *= d[0];
+          phase1(o.q[0], cd(1.0), d[1] / d[0]);
+          phase1(o.q[1], cd(1.0), d[2] / d[0]);
+          interaction(o.q[0], o.q[1], d[3] * d[0] / (d[1] * d[2]));
+        } else {
+          raw(w.op);
+        }
       } else {  // TOP_SIGN
-        uint32_t Mrr = 0, zfree = 0;
-        std::vector<std::pair<int, uint32_t>> fmix, rcmix;  // (free pos | outside q, mask over m)
-        uint32_t Md[32] = {0};
-        std::vector<int32_t> fc, cc;
-        auto add_mask = [](std::vector<std::pair<int, uint32_t>>& v, int key, uint32_t mk) {
-          for (auto& e : v)
-            if (e.first == key) {
-              e.second ^= mk;
-              return;
-            }
-          v.push_back({key, mk});
-        };
         for (int i : w.signs) {
           const POp& o = P[i];
-          if (o.kind == PK_D1) {
-            int kd, vl;
-            operand(o.q[0], kd, vl);
-            if (kd == TK_REG) Mrr ^= (uint32_t)vl;
-            else if (kd == TK_FREE) zfree ^= 1u << vl;
-            else cc.insert(cc.end(), {vl, vl});
-            continue;
-          }
-          int ka, va, kb, vb;
-          operand(o.q[0], ka, va);
-          operand(o.q[1], kb, vb);
-          if (ka > kb) {
-            std::swap(ka, kb);
-            std::swap(va, vb);
-          }
-          if (ka == TK_REG && kb == TK_REG) {
-            Mrr ^= (uint32_t)va & (uint32_t)vb;
-          } else if (ka == TK_REG && kb == TK_FREE) {
-            add_mask(fmix, vb, (uint32_t)va);
-          } else if (ka == TK_REG && kb == TK_OUT) {
-            add_mask(rcmix, vb, (uint32_t)va);
-          } else if (ka == TK_FREE && kb == TK_FREE) {
-            const int lo = std::min(va, vb), hi = std::max(va, vb);
-            Md[hi - lo] ^= 1u << lo;
-          } else if (ka == TK_FREE && kb == TK_OUT) {
-            fc.insert(fc.end(), {vb, va});
-          } else {
-            cc.insert(cc.end(), {va, vb});
+          if (o.kind == PK_D1) phase1(o.q[0], cd(1.0), cd(-1.0));
+          else cz(o.q[0], o.q[1]);
+        }
+      }
+    }
+  }
+
+  // every carried factor is applied by the end of the pass
+  if (!plans.empty()) {
+    RPlan& rp = plans.back();
+    for (int p = 0; p < t; ++p) {
+      if (pd0[p] == cd(1.0) && pd1[p] == cd(1.0)) continue;
+      const int j = rp.regof[p];
+      if (j >= 0) {
+        tab_bit(rp, j, pd0[p], pd1[p]);
+      } else {
+        gscale *= pd0[p];
+        const cd rr = pd1[p] / pd0[p];
+        if (rr != cd(1.0)) add_term(pick(rp, 0, [&](const DGroup& g) { return has_key(g, -1); }), -1, 1u << p, 0ull, rr);
+      }
+    }
+    if (gscale != cd(1.0)) {
+      cd* tbl = table_of(pick(rp, 0, [](const DGroup& g) { return g.tab; }));
+      for (int m = 0; m < NR; ++m) tbl[m] *= gscale;
+    }
+  }
+
+  // (p, q, c) of a diagonal factor d = (1 + c) exp(i phi), |phi| <= pi/2:
+  // p = -tan(phi / 2), q = sin(phi); a negative real part goes into c
+  auto factor_pqc = [](cd d, double& fp, double& fq, double& fc) {
+    const double r = std::abs(d);
+    if (r == 0.0) {
+      fp = fq = 0.0;
+      fc = -1.0;
+      return;
+    }
+    cd u = d / r;
+    double sg = 1.0;
+    if (u.real() < 0.0) {
+      u = -u;
+      sg = -1.0;
+    }
+    fp = -u.imag() / (1.0 + u.real());
+    fq = u.imag();
+    fc = sg * r - 1.0;
+  };
+  for (RPlan& rp : plans) {
+    uint32_t rmask = 0;
+    for (int k = 0; k < RB; ++k) rmask |= 1u << rp.R[k];
+    const uint32_t tmask = t >= 32 ? ~0u : ((1u << t) - 1u);
+    BlockWriter<T> bw(prog, NR);
+    bw.header.push_back((int32_t)(tmask & ~rmask));
+    for (int m = 0; m < NR; ++m) {
+      uint32_t lm = 0;
+      for (int k = 0; k < RB; ++k)
+        if ((m >> k) & 1) lm |= 1u << rp.R[k];
+      bw.header.push_back((int32_t)(tile_swizzle(lm, SB) * (uint32_t)(2 * sizeof(T))));
+    }
+    bw.open();
+
+    // layers: the diagonal work of a group, then rotations on distinct
+    // register bits with nothing diagonal between them, then at most one
+    // permutation or general matrix
+    struct Layer {
+      int group = -1;
+      std::vector<int> rots;
+      int tail = -1;
+    };
+    auto group_empty = [&](const DGroup& g) { return !g.tab && !has_sign(g) && g.phl.empty() && g.raw.empty(); };
+    std::vector<Layer> layers;
+    Layer cur;
+    cur.group = 0;
+    uint32_t used = 0;
+    auto flush = [&]() {
+      const bool diag = cur.group >= 0 && !group_empty(rp.g[cur.group]);
+      if (diag || !cur.rots.empty() || cur.tail >= 0) layers.push_back(cur);
+      cur = Layer();
+      used = 0;
+    };
+    for (size_t i = 0; i < rp.nd.size(); ++i) {
+      const NdItem& it = rp.nd[i];
+      if (it.type == TOP_GIVENS) {
+        if (cur.tail >= 0 || ((used >> it.j0) & 1u)) flush();
+        cur.rots.push_back((int)i);
+        used |= 1u << it.j0;
+      } else {
+        if (cur.tail >= 0) flush();
+        cur.tail = (int)i;
+      }
+      if (!group_empty(rp.g[i + 1])) {
+        flush();
+        cur.group = (int)i + 1;
+      } else if (cur.tail >= 0) {
+        flush();
+      }
+    }
+    flush();
+
+    for (const Layer& L : layers) {
+      DGroup empty_group;
+      DGroup& g = L.group >= 0 ? rp.g[L.group] : empty_group;
+      // the diagonal table: unit phases with a sign pattern, magnitudes apart
+      bool tab = false, mag = false;
+      uint32_t smask = 0;
+      std::vector<int32_t> tline, mline;
+      if (g.tab) {
+        for (int m = 0; m < NR; ++m)
+          if ((g.Mrr >> m) & 1) g.tb[m] = -g.tb[m];
+        g.Mrr = 0;
+        bool ident = true;
+        for (int m = 0; m < NR; ++m)
+          if (g.tb[m] != cd(1.0)) ident = false;
+        if (!ident) {
+          tab = true;
+          for (int m = 0; m < NR; ++m) {
+            const double r = std::abs(g.tb[m]);  // > 0: tables hold invertible factors only
+            cd u = g.tb[m] / r;
+            if (u.real() < 0.0) {
+              u = -u;
+              smask |= 1u << m;
+            }
+            if (std::abs(r - 1.0) > 1e-15) mag = true;
+            BlockWriter<T>::real_words(-u.imag() / (1.0 + u.real()), tline);
+            BlockWriter<T>::real_words(u.imag(), tline);
+            BlockWriter<T>::real_words(r - 1.0, mline);
           }
         }
-        std::vector<int32_t> h = {TOP_SIGN, 0, (int32_t)Mrr, (int32_t)fmix.size()};
-        for (auto& e : fmix) h.insert(h.end(), {e.first, (int32_t)e.second});
-        std::vector<int32_t> loc;
-        for (int d = 1; d < 32; ++d)
-          if (Md[d]) loc.insert(loc.end(), {d, (int32_t)Md[d]});
-        h.push_back((int32_t)loc.size() / 2);
-        h.insert(h.end(), loc.begin(), loc.end());
-        h.push_back((int32_t)zfree);
-        h.push_back((int32_t)rcmix.size());
-        for (auto& e : rcmix) h.insert(h.end(), {e.first, (int32_t)e.second});
-        h.push_back((int32_t)fc.size() / 2);
-        h.insert(h.end(), fc.begin(), fc.end());
-        h.push_back((int32_t)cc.size() / 2);
-        h.insert(h.end(), cc.begin(), cc.end());
-        bw.emit(h, nullptr, 0);
       }
+      std::vector<int32_t> loc;
+      for (int d = 1; d < 32; ++d)
+        if (g.Md[d]) loc.insert(loc.end(), {d, (int32_t)g.Md[d]});
+      const bool sign = g.Mrr || g.zfree || !g.fmix.empty() || !g.rcmix.empty() || !loc.empty() ||
+                        !g.fc.empty() || !g.cc.empty();
+      // extra per-group phases and raw diagonals run as diagonal-only layers first
+      struct Extra {
+        int kind;  // 0 phasel, 1 raw
+        int idx;
+      };
+      std::vector<Extra> extras;
+      // per-group phase entries, at most kTermsPerLayer terms each
+      constexpr size_t kTermsPerLayer = 24;
+      std::vector<std::pair<int, std::vector<PhTerm>>> phl;
+      for (auto& e : g.phl) {
+        std::vector<PhTerm> terms;
+        for (auto& tm : e.second)
+          if (tm.r != cd(1.0)) terms.push_back(tm);
+        for (size_t t0 = 0; t0 < terms.size(); t0 += kTermsPerLayer)
+          phl.push_back({e.first, std::vector<PhTerm>(terms.begin() + t0,
+                                                      terms.begin() + std::min(terms.size(), t0 + kTermsPerLayer))});
+      }
+      for (size_t e = 0; e < phl.size(); ++e) extras.push_back({0, (int)e});
+      for (size_t e = 0; e < g.raw.size(); ++e) extras.push_back({1, (int)e});
+      auto phasel_words = [&](std::vector<int32_t>& w, int e) {
+        const std::vector<PhTerm>& terms = phl[e].second;
+        w.push_back(phl[e].first);
+        w.push_back((int32_t)terms.size());
+        for (auto& tm : terms) {
+          w.push_back((int32_t)tm.lgm);
+          w.push_back((int32_t)(tm.om & 0xffffffffull));
+          w.push_back((int32_t)(tm.om >> 32));
+          BlockWriter<T>::real_words(tm.r.real(), w);
+          BlockWriter<T>::real_words(tm.r.imag(), w);
+        }
+      };
+      auto raw_words = [&](std::vector<int32_t>& w, int e) {
+        const POp& o = P[g.raw[e]];
+        int ka, va;
+        operand(rp, o.q[0], ka, va);
+        const int nfac = o.kind == PK_D1 ? 2 : 4;
+        if (o.kind == PK_D1) {
+          w.insert(w.end(), {RAW_PHASE1, ka, va});
+        } else {
+          int kb, vb;
+          operand(rp, o.q[1], kb, vb);
+          w.insert(w.end(), {RAW_DIAG2, ka, va, kb, vb});
+        }
+        for (int f = 0; f < nfac; ++f) {
+          double fp, fq, fc;
+          factor_pqc(o.m[f], fp, fq, fc);
+          BlockWriter<T>::real_words(fp, w);
+          BlockWriter<T>::real_words(fq, w);
+          BlockWriter<T>::real_words(fc, w);
+        }
+      };
+      const size_t n_extra_layers = extras.size() > 1 ? extras.size() - 1 : 0;
+      for (size_t x = 0; x < n_extra_layers; ++x) {
+        bw.layer(0, [&](std::vector<int32_t>& w, const int*) {
+          const Extra& E = extras[x];
+          w = {E.kind == 0 ? LT_PHASEL : LT_RAWD, 0};
+          if (E.kind == 0) phasel_words(w, E.idx);
+          else raw_words(w, E.idx);
+        });
+      }
+      const int nl = tab ? 1 : 0;
+      bw.layer(nl, [&](std::vector<int32_t>& w, const int* lines) {
+        int32_t flags = 0;
+        w = {0, 0};
+        if (tab) {
+          flags |= LT_TAB;
+          w.push_back(lines[0]);
+          w.push_back((int32_t)smask);
+        }
+        if (mag) {
+          flags |= LT_MAG;
+          w.insert(w.end(), mline.begin(), mline.end());
+        }
+        if (sign) {
+          flags |= LT_SIGN;
+          w.push_back((int32_t)g.Mrr);
+          w.push_back((int32_t)g.fmix.size());
+          for (auto& e : g.fmix) w.insert(w.end(), {e.first, (int32_t)e.second});
+          w.push_back((int32_t)loc.size() / 2);
+          w.insert(w.end(), loc.begin(), loc.end());
+          w.push_back((int32_t)g.zfree);
+          w.push_back((int32_t)g.rcmix.size());
+          for (auto& e : g.rcmix) w.insert(w.end(), {e.first, (int32_t)e.second});
+          w.push_back((int32_t)g.fc.size() / 2);
+          w.insert(w.end(), g.fc.begin(), g.fc.end());
+          w.push_back((int32_t)g.cc.size() / 2);
+          w.insert(w.end(), g.cc.begin(), g.cc.end());
+        }
+        if (!extras.empty()) {
+          const Extra& E = extras.back();
+          if (E.kind == 0) {
+            flags |= LT_PHASEL;
+            phasel_words(w, E.idx);
+          } else {
+            flags |= LT_RAWD;
+            raw_words(w, E.idx);
+          }
+        }
+        // rotations, ascending register bit
+        std::vector<int> rots(L.rots);
+        std::sort(rots.begin(), rots.end(), [&](int x, int y) { return rp.nd[x].j0 < rp.nd[y].j0; });
+        for (int i : rots) {
+          const NdItem& it = rp.nd[i];
+          flags |= LT_ROT0 << it.j0;
+          if (it.jf >> 8) flags |= LT_SHEAR3 << it.j0;
+          BlockWriter<T>::real_words(it.p, w);
+          BlockWriter<T>::real_words(it.q, w);
+        }
+        if (L.tail >= 0) {
+          const NdItem& it = rp.nd[L.tail];
+          if (it.type == TOP_PERM2) {
+            flags |= LT_PERM2;
+            w.insert(w.end(), {it.j0, it.j1, it.code});
+          } else if (it.type == TOP_U2) {
+            flags |= LT_U2;
+            w.insert(w.end(), {it.j0, it.j1});
+            for (int e = 0; e < 16; ++e) {
+              BlockWriter<T>::real_words(it.m[e].real(), w);
+              BlockWriter<T>::real_words(it.m[e].imag(), w);
+            }
+          } else {
+            flags |= LT_U1;
+            w.push_back(it.j0);
+            for (int e = 0; e < 4; ++e) {
+              BlockWriter<T>::real_words(it.m[e].real(), w);
+              BlockWriter<T>::real_words(it.m[e].imag(), w);
+            }
+          }
+        }
+        w[0] = flags;
+      });
+      if (bw.failed) return false;
+      if (tab) bw.put_line(bw.next_line + 1, tline);
     }
     bw.close();
   }
   prog[h0 + 3] = (int32_t)((prog.size() - blocks0) / kRoundWords);
+  return true;
 }
 
 // ------------------------------------------------------------- driver
@@ -667,7 +1176,7 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
   std::vector<size_t> offs;
   for (const Step& st : sch->steps) {
     offs.push_back(prog.size());
-    if (st.tile) emit_pass<T>(st, P, n, c, RB, prog);
+    if (st.tile && !emit_pass<T>(st, P, n, c, RB, prog)) return fail(QSV_ERR_UNSUPPORTED, "a fused tile layer does not fit a round block");
   }
   const size_t need = prog.size() * sizeof(int32_t) + 256;
   if (s->pbuf_bytes < need) {
@@ -740,8 +1249,8 @@ qsv_status plan_program(const qsv_state* s, const qsv_op* ops, int n_ops, int ti
       continue;
     }
     steps.push_back((int64_t)prog.size());
-    if (f) emit_pass<float>(st, P, n, c, RB, prog);
-    else emit_pass<double>(st, P, n, c, RB, prog);
+    const bool ok = f ? emit_pass<float>(st, P, n, c, RB, prog) : emit_pass<double>(st, P, n, c, RB, prog);
+    if (!ok) return fail(QSV_ERR_UNSUPPORTED, "a fused tile layer does not fit a round block");
   }
   return QSV_OK;
 }
@@ -879,14 +1388,14 @@ static qsv_status batch_materialise(qsv_batch* b, int t, bool check_only_structu
                     "batched circuits support gates on at most 2 qubits (circuit " +
                         std::to_string(ci) + ")");
       b->passoff.push_back((int64_t)b->hprog.size());
-      emit_pass<T>(st, P, n, c, RB, b->hprog);
+      if (!emit_pass<T>(st, P, n, c, RB, b->hprog)) return fail(QSV_ERR_UNSUPPORTED, "a fused tile layer does not fit a round block");
       ++np;
     }
     if (np == 0) {  // empty circuit: one pass with no rounds still builds and reduces the state
       Step st;
       for (int q = 0; q < tc; ++q) st.S.push_back(q);
       b->passoff.push_back((int64_t)b->hprog.size());
-      emit_pass<T>(st, P, n, c, RB, b->hprog);
+      if (!emit_pass<T>(st, P, n, c, RB, b->hprog)) return fail(QSV_ERR_UNSUPPORTED, "a fused tile layer does not fit a round block");
       np = 1;
     }
     npass[ci] = np;

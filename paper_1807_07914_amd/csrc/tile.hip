@@ -7,18 +7,19 @@
 // state through LDS one tile (all 2^t amplitudes with fixed non-S bits) at a
 // time, and apply every gate whose support lies in S -- plus every diagonal
 // gate, whose factor is computable from the index alone -- before writing the
-// tile back.  The host planner (circuit.hip) chooses S and the gate order.
+// tile back.  The host planner (circuit.hip) chooses S and the gate order,
+// and rewrites the gates into real rotations and diagonal factors applied in
+// bulk (see the layer encoding in tile.hpp).
 //
 // gfx950 mapping: 256 threads per workgroup, tile of up to 2^13 complex64 /
 // 2^12 complex128 amplitudes (64 KiB LDS).  Global loads and stores are
 // 16-byte vectors over contiguous segments of 2^c amplitudes.  LDS uses an
 // XOR swizzle of the amplitude index so that power-of-two strides between
 // the lanes of a round do not hit one bank.  Within a round each thread holds
-// 2^RB amplitudes in registers and applies 1- and 2-qubit matrices on the
-// round's register bits with fully unrolled code.  The round's program (ops,
-// matrices, LDS offsets) is one 256-word block that every wavefront loads
-// into four VGPRs one round ahead and reads with v_readlane, so the op
-// stream never waits on memory.
+// 2^RB amplitudes in registers and applies the round's layers with fully
+// unrolled code.  The round's program is one block of kRoundWords words that
+// every wavefront loads into kRoundLines VGPRs one round ahead and reads with
+// v_readlane, so the op stream never waits on memory.
 #include "internal.hpp"
 #include "tile.hpp"
 
@@ -37,43 +38,42 @@ struct SwzBits<double> {
 
 __device__ __forceinline__ int rl(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
-// matrix entries stored in round blocks: one word per float, two per double
+// words per real: one per float, two per double
 template <typename T>
 struct WordsPer {
   static constexpr int W = sizeof(T) / 4;
 };
 
-// Round block held in four VGPRs (64 words each), written under a full exec
-// mask.  Every read is a v_readlane of one of these four registers with the
-// line chosen on the scalar side: the op loop may run with some lanes off
+// Round block held in kRoundLines VGPRs (64 words each), written under a full
+// exec mask.  Every read is a v_readlane of one of these registers with the
+// line chosen on the scalar side: the layer loop may run with some lanes off
 // (fewer groups than threads), and a VGPR computed there would hold stale
 // values in the lanes that readlane addresses.
 struct Blk {
-  int l0, l1, l2, l3;
+  int l[kRoundLines];
   __device__ __forceinline__ int word(int k) const {
-    const int i = k & 63, ln = k >> 6;
-    if (ln == 0) return rl(l0, i);
-    if (ln == 1) return rl(l1, i);
-    if (ln == 2) return rl(l2, i);
-    return rl(l3, i);
-  }
-  // C consecutive words of one line (the encoder never splits such a run)
-  template <int C>
-  __device__ __forceinline__ void readn(int k, int (&o)[C]) const {
-    const int i = k & 63, ln = k >> 6;
-    if (ln == 0) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) o[c] = rl(l0, i + c);
-    } else if (ln == 1) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) o[c] = rl(l1, i + c);
-    } else if (ln == 2) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) o[c] = rl(l2, i + c);
-    } else {
-#pragma unroll
-      for (int c = 0; c < C; ++c) o[c] = rl(l3, i + c);
+    const int i = k & 63;
+    switch (k >> 6) {
+      case 0: return rl(l[0], i);
+      case 1: return rl(l[1], i);
+      case 2: return rl(l[2], i);
+      case 3: return rl(l[3], i);
+      case 4: return rl(l[4], i);
+      case 5: return rl(l[5], i);
+      case 6: return rl(l[6], i);
+      default: return rl(l[7], i);
     }
+  }
+  // f(line VGPR) for a table line (kTableLine0 .. kRoundLines - 1)
+  template <typename F>
+  __device__ __forceinline__ void on_table_line(int ln, F&& f) const {
+    static_assert(kTableLine0 == 2 && kRoundLines == 8, "table lines 2 .. 7");
+    if (ln == 2) f(l[2]);
+    else if (ln == 3) f(l[3]);
+    else if (ln == 4) f(l[4]);
+    else if (ln == 5) f(l[5]);
+    else if (ln == 6) f(l[6]);
+    else f(l[7]);
   }
   template <typename T>
   __device__ __forceinline__ T real(int k) const;
@@ -87,22 +87,104 @@ __device__ __forceinline__ double Blk::real<double>(int k) const {
   return __hiloint2double(word(k + 1), word(k));
 }
 
+// entry e of a table line (one real per word for float, two for double)
 template <typename T>
-__device__ __forceinline__ T word_real(const int* w);
+__device__ __forceinline__ T line_real(int v, int e);
 template <>
-__device__ __forceinline__ float word_real<float>(const int* w) {
-  return __int_as_float(w[0]);
+__device__ __forceinline__ float line_real<float>(int v, int e) {
+  return __int_as_float(rl(v, e));
 }
 template <>
-__device__ __forceinline__ double word_real<double>(const int* w) {
-  return __hiloint2double(w[1], w[0]);
+__device__ __forceinline__ double line_real<double>(int v, int e) {
+  return __hiloint2double(rl(v, 2 * e + 1), rl(v, 2 * e));
 }
 
+// x <- (1 + c) x, in place (c = -2 negates, c = 0 leaves x as it is)
+template <typename T>
+__device__ __forceinline__ void scale1(cpx<T>& x, T c) {
+  x.x = fma(c, x.x, x.x);
+  x.y = fma(c, x.y, x.y);
+}
+
+// x <- exp(i phi) x as three shears of (re, im): p = -tan(phi/2), q = sin(phi)
+template <typename T>
+__device__ __forceinline__ void phase_shears(cpx<T>& x, T p, T q) {
+  x.x = fma(p, x.y, x.x);
+  x.y = fma(q, x.x, x.y);
+  x.x = fma(p, x.y, x.x);
+}
+
+// Real rotation on register bit J as in-place shears (bounded coefficients):
+// x0 += p x1; x1 += q x0; and x0 += p x1 again when three.
+template <typename T, int RB, int J>
+__device__ __forceinline__ void shears(cpx<T> (&a)[1 << RB], T p, T q, bool three) {
+#pragma unroll
+  for (int m = 0; m < (1 << RB); ++m) {
+    if ((m >> J) & 1) continue;
+    cpx<T>& x0 = a[m];
+    cpx<T>& x1 = a[m | (1 << J)];
+    x0.x = fma(p, x1.x, x0.x);
+    x0.y = fma(p, x1.y, x0.y);
+    x1.x = fma(q, x0.x, x1.x);
+    x1.y = fma(q, x0.y, x1.y);
+  }
+  if (three) {
+#pragma unroll
+    for (int m = 0; m < (1 << RB); ++m) {
+      if ((m >> J) & 1) continue;
+      cpx<T>& x0 = a[m];
+      const cpx<T> x1 = a[m | (1 << J)];
+      x0.x = fma(p, x1.x, x0.x);
+      x0.y = fma(p, x1.y, x0.y);
+    }
+  }
+}
+
+// Table step: amplitude m times sign(m) exp(i phi_m); (p_m, q_m) at entries
+// 2m, 2m + 1 of table line tl, the sign as bit m of sm.  The entries are read
+// into scalar registers a few at a time under the line switch, and the
+// amplitudes are updated outside it (updates inside the switch cases would be
+// merged from four paths, which costs a copy of every amplitude).
+template <typename T, int RB>
+__device__ __forceinline__ void table_step(cpx<T> (&a)[1 << RB], const Blk& b, int tl, uint32_t sm) {
+  constexpr int W = WordsPer<T>::W;
+  constexpr int CH = 8 / W;  // entries (p, q pairs) per chunk: 16 words
+#pragma unroll
+  for (int m0 = 0; m0 < (1 << RB); m0 += CH) {
+    int wv[16];
+    b.on_table_line(tl, [&](int v) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) wv[e] = rl(v, 2 * W * m0 + e);
+    });
+#pragma unroll
+    for (int e = 0; e < CH; ++e) {
+      const int m = m0 + e;
+      T pm, qm;
+      if constexpr (W == 1) {
+        pm = __int_as_float(wv[2 * e]);
+        qm = __int_as_float(wv[2 * e + 1]);
+      } else {
+        pm = __hiloint2double(wv[4 * e + 1], wv[4 * e]);
+        qm = __hiloint2double(wv[4 * e + 3], wv[4 * e + 2]);
+      }
+      phase_shears(a[m], pm, qm);
+      if ((sm >> m) & 1u) scale1(a[m], T(-2));
+    }
+  }
+}
+
+// 2x2 and 4x4 matrices (general, rare): accumulated column by column.
 template <typename T, int RB, int J>
 __device__ __forceinline__ void u1(cpx<T> (&a)[1 << RB], const M2<T>& U) {
 #pragma unroll
-  for (int m = 0; m < (1 << RB); ++m)
-    if (!((m >> J) & 1)) apply2(U, a[m], a[m | (1 << J)]);
+  for (int m = 0; m < (1 << RB); ++m) {
+    if ((m >> J) & 1) continue;
+    cpx<T>& x0 = a[m];
+    cpx<T>& x1 = a[m | (1 << J)];
+    const cpx<T> t0 = cmul(U.m[0], x0), t1 = cmul(U.m[2], x0);
+    x0 = cfma(U.m[1], x1, t0);
+    x1 = cfma(U.m[3], x1, t1);
+  }
 }
 
 template <typename T, int RB, int J0, int J1>
@@ -110,59 +192,16 @@ __device__ __forceinline__ void u2(cpx<T> (&a)[1 << RB], const M4<T>& U) {
 #pragma unroll
   for (int m = 0; m < (1 << RB); ++m) {
     if (((m >> J0) & 1) || ((m >> J1) & 1)) continue;
-    const int i0 = m, i1 = m | (1 << J0), i2 = m | (1 << J1), i3 = m | (1 << J0) | (1 << J1);
-    const cpx<T> x0 = a[i0], x1 = a[i1], x2 = a[i2], x3 = a[i3];
-    cpx<T> y[4];
+    const int i[4] = {m, m | (1 << J0), m | (1 << J1), m | (1 << J0) | (1 << J1)};
+    cpx<T> acc[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      cpx<T> acc = cmul(U.m[4 * r + 0], x0);
-      acc = cfma(U.m[4 * r + 1], x1, acc);
-      acc = cfma(U.m[4 * r + 2], x2, acc);
-      acc = cfma(U.m[4 * r + 3], x3, acc);
-      y[r] = acc;
-    }
-    a[i0] = y[0];
-    a[i1] = y[1];
-    a[i2] = y[2];
-    a[i3] = y[3];
-  }
-}
-
-template <typename T, int RB>
-__device__ __forceinline__ void dispatch_u1(cpx<T> (&a)[1 << RB], int j, const M2<T>& U) {
-  switch (j) {
-    case 0: u1<T, RB, 0>(a, U); break;
-    case 1: u1<T, RB, 1>(a, U); break;
-    case 2: u1<T, RB, 2>(a, U); break;
-    case 3: u1<T, RB, 3>(a, U); break;
-    default:
-      if constexpr (RB > 4) u1<T, RB, (RB > 4 ? 4 : 0)>(a, U);
-      break;
-  }
-}
-
-template <typename T, int RB>
-__device__ __forceinline__ void dispatch_u2(cpx<T> (&a)[1 << RB], int j0, int j1, const M4<T>& U) {
-  const int key = j0 * 8 + j1;
-  switch (key) {
-    case 0 * 8 + 1: u2<T, RB, 0, 1>(a, U); break;
-    case 0 * 8 + 2: u2<T, RB, 0, 2>(a, U); break;
-    case 0 * 8 + 3: u2<T, RB, 0, 3>(a, U); break;
-    case 1 * 8 + 2: u2<T, RB, 1, 2>(a, U); break;
-    case 1 * 8 + 3: u2<T, RB, 1, 3>(a, U); break;
-    case 2 * 8 + 3: u2<T, RB, 2, 3>(a, U); break;
-    default:
-      if constexpr (RB > 4) {
-        constexpr int H = RB > 4 ? 4 : 3;
-        switch (key) {
-          case 0 * 8 + H: u2<T, RB, 0, H>(a, U); break;
-          case 1 * 8 + H: u2<T, RB, 1, H>(a, U); break;
-          case 2 * 8 + H: u2<T, RB, 2, H>(a, U); break;
-          case 3 * 8 + H: u2<T, RB, 3, H>(a, U); break;
-          default: break;
-        }
-      }
-      break;
+    for (int r = 0; r < 4; ++r) acc[r] = cmul(U.m[4 * r], a[i[0]]);
+#pragma unroll
+    for (int c = 1; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = cfma(U.m[4 * r + c], a[i[c]], acc[r]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[i[r]] = acc[r];
   }
 }
 
@@ -189,35 +228,63 @@ __device__ __forceinline__ void perm2(cpx<T> (&a)[1 << RB]) {
   }
 }
 
+// Dispatchers on register bits.  Each variant is an independent `if`
+// rather than one arm of an else-if chain: arms of a chain that all rewrite
+// the amplitudes are merged in one place, and the register allocator then
+// copies every amplitude on the paths that skip the step.
+template <typename T, int RB>
+__device__ __forceinline__ void dispatch_u1(cpx<T> (&a)[1 << RB], int j, const M2<T>& U) {
+  if (j == 0) u1<T, RB, 0>(a, U);
+  if (j == 1) u1<T, RB, 1>(a, U);
+  if (j == 2) u1<T, RB, 2>(a, U);
+  if (j == 3) u1<T, RB, 3>(a, U);
+  if constexpr (RB > 4) {
+    if (j == 4) u1<T, RB, (RB > 4 ? 4 : 3)>(a, U);
+  }
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ void dispatch_u2(cpx<T> (&a)[1 << RB], int j0, int j1, const M4<T>& U) {
+  constexpr int H = RB > 4 ? 4 : 3;
+  const int key = j0 * 8 + j1;
+  if (key == 0 * 8 + 1) u2<T, RB, 0, 1>(a, U);
+  if (key == 0 * 8 + 2) u2<T, RB, 0, 2>(a, U);
+  if (key == 0 * 8 + 3) u2<T, RB, 0, 3>(a, U);
+  if (key == 1 * 8 + 2) u2<T, RB, 1, 2>(a, U);
+  if (key == 1 * 8 + 3) u2<T, RB, 1, 3>(a, U);
+  if (key == 2 * 8 + 3) u2<T, RB, 2, 3>(a, U);
+  if constexpr (RB > 4) {
+    if (key == 0 * 8 + H) u2<T, RB, 0, H>(a, U);
+    if (key == 1 * 8 + H) u2<T, RB, 1, H>(a, U);
+    if (key == 2 * 8 + H) u2<T, RB, 2, H>(a, U);
+    if (key == 3 * 8 + H) u2<T, RB, 3, H>(a, U);
+  }
+}
+
 template <typename T, int RB, int J0, int J1>
-__device__ __forceinline__ void perm2_code(cpx<T> (&a)[1 << RB], int code) {
-  if (code == 0) perm2<T, RB, J0, J1, 0>(a);
-  else if (code == 1) perm2<T, RB, J0, J1, 1>(a);
-  else perm2<T, RB, J0, J1, 2>(a);
+__device__ __forceinline__ void perm2_code(cpx<T> (&a)[1 << RB], int key, int code) {
+  if (key == J0 * 8 + J1) {
+    if (code == 0) perm2<T, RB, J0, J1, 0>(a);
+    if (code == 1) perm2<T, RB, J0, J1, 1>(a);
+    if (code == 2) perm2<T, RB, J0, J1, 2>(a);
+  }
 }
 
 template <typename T, int RB>
 __device__ __forceinline__ void dispatch_perm2(cpx<T> (&a)[1 << RB], int j0, int j1, int code) {
+  constexpr int H = RB > 4 ? 4 : 3;
   const int key = j0 * 8 + j1;
-  switch (key) {
-    case 0 * 8 + 1: perm2_code<T, RB, 0, 1>(a, code); break;
-    case 0 * 8 + 2: perm2_code<T, RB, 0, 2>(a, code); break;
-    case 0 * 8 + 3: perm2_code<T, RB, 0, 3>(a, code); break;
-    case 1 * 8 + 2: perm2_code<T, RB, 1, 2>(a, code); break;
-    case 1 * 8 + 3: perm2_code<T, RB, 1, 3>(a, code); break;
-    case 2 * 8 + 3: perm2_code<T, RB, 2, 3>(a, code); break;
-    default:
-      if constexpr (RB > 4) {
-        constexpr int H = RB > 4 ? 4 : 3;
-        switch (key) {
-          case 0 * 8 + H: perm2_code<T, RB, 0, H>(a, code); break;
-          case 1 * 8 + H: perm2_code<T, RB, 1, H>(a, code); break;
-          case 2 * 8 + H: perm2_code<T, RB, 2, H>(a, code); break;
-          case 3 * 8 + H: perm2_code<T, RB, 3, H>(a, code); break;
-          default: break;
-        }
-      }
-      break;
+  perm2_code<T, RB, 0, 1>(a, key, code);
+  perm2_code<T, RB, 0, 2>(a, key, code);
+  perm2_code<T, RB, 0, 3>(a, key, code);
+  perm2_code<T, RB, 1, 2>(a, key, code);
+  perm2_code<T, RB, 1, 3>(a, key, code);
+  perm2_code<T, RB, 2, 3>(a, key, code);
+  if constexpr (RB > 4) {
+    perm2_code<T, RB, 0, H>(a, key, code);
+    perm2_code<T, RB, 1, H>(a, key, code);
+    perm2_code<T, RB, 2, H>(a, key, code);
+    perm2_code<T, RB, 3, H>(a, key, code);
   }
 }
 
@@ -267,13 +334,9 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
     segoff[h] = o;
   }
   // first round block (prefetched while the tile loads)
-  Blk nb{0, 0, 0, 0};
-  if (nrounds > 0) {
-    nb.l0 = blocks[lane];
-    nb.l1 = blocks[64 + lane];
-    nb.l2 = blocks[128 + lane];
-    nb.l3 = blocks[192 + lane];
-  }
+  Blk nb;
+#pragma unroll
+  for (int i = 0; i < kRoundLines; ++i) nb.l[i] = nrounds > 0 ? blocks[64 * i + lane] : 0;
   __syncthreads();
 
   // ---- load the tile (coalesced 16-byte vectors) into LDS
@@ -305,17 +368,17 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
 
   // ---- rounds
   const int ng = 1 << (t - RB);
+  char* const tb = reinterpret_cast<char*>(tile);
   for (int r = 0; r < nrounds; ++r) {
     const Blk b = nb;
     if (r + 1 < nrounds) {  // prefetch the next round's block
       const int32_t* nbp = blocks + (size_t)(r + 1) * kRoundWords;
-      nb.l0 = nbp[lane];
-      nb.l1 = nbp[64 + lane];
-      nb.l2 = nbp[128 + lane];
-      nb.l3 = nbp[192 + lane];
+#pragma unroll
+      for (int i = 0; i < kRoundLines; ++i) nb.l[i] = nbp[64 * i + lane];
     }
-    const int nops = rl(b.l0, 0);
-    const uint32_t free_mask = (uint32_t)rl(b.l0, 1);
+    const int w0 = rl(b.l[0], 0);
+    const int nlayers = w0 & 0xffff;  // the first layer starts at word w0 >> 16
+    const uint32_t free_mask = (uint32_t)rl(b.l[0], 1);
     for (int gi = threadIdx.x; gi < ng; gi += kTileThreads) {
       // deposit gi into the free local bits
       uint32_t lg = 0, fm = free_mask;
@@ -324,35 +387,28 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
         if ((gi >> bit) & 1) lg |= low;
         fm ^= low;
       }
-      const uint32_t sg = tile_swizzle(lg, SB);
+      const uint32_t sgb = tile_swizzle(lg, SB) * (uint32_t)sizeof(cpx<T>);
       cpx<T> a[NR];
 #pragma unroll
-      for (int m = 0; m < NR; ++m) a[m] = tile[sg ^ (uint32_t)rl(b.l0, 2 + m)];
+      for (int m = 0; m < NR; ++m)
+        a[m] = *reinterpret_cast<const cpx<T>*>(tb + (sgb ^ (uint32_t)rl(b.l[0], 2 + m)));
 
-      int k = 2 + NR;
-      for (int o = 0; o < nops; ++o) {
-        const int type = b.word(k), len = b.word(k + 1);
-        if (type == TOP_U1) {
-          int wv[1 + 8 * WT];
-          b.readn<1 + 8 * WT>(k + 2, wv);
-          M2<T> U;
+      int k = w0 >> 16;
+      for (int o = 0; o < nlayers; ++o) {
+        const int flags = b.word(k), len = b.word(k + 1);
+        int p = k + 2;
+        if (flags & LT_TAB) {
+          const int tl = b.word(p);
+          const uint32_t sm = (uint32_t)b.word(p + 1);
+          p += 2;
+          table_step<T, RB>(a, b, tl, sm);
+        }
+        if (flags & LT_MAG) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            U.m[e] = cpx<T>{word_real<T>(wv + 1 + 2 * e * WT), word_real<T>(wv + 1 + (2 * e + 1) * WT)};
-          dispatch_u1<T, RB>(a, wv[0], U);
-        } else if (type == TOP_U2) {
-          const int j0 = b.word(k + 2), j1 = b.word(k + 3);
-          M4<T> U;
-#pragma unroll
-          for (int e = 0; e < 16; ++e)
-            U.m[e] = cpx<T>{b.real<T>(k + 4 + 2 * e * WT), b.real<T>(k + 4 + (2 * e + 1) * WT)};
-          dispatch_u2<T, RB>(a, j0, j1, U);
-        } else if (type == TOP_PERM2) {
-          int wv[3];
-          b.readn<3>(k + 2, wv);
-          dispatch_perm2<T, RB>(a, wv[0], wv[1], wv[2]);
-        } else if (type == TOP_SIGN) {
-          int p = k + 2;
+          for (int m = 0; m < NR; ++m) scale1(a[m], b.real<T>(p + m * WT));
+          p += NR * WT;
+        }
+        if (flags & LT_SIGN) {
           uint32_t neg = (uint32_t)b.word(p++);
           const int nf = b.word(p++);
           for (int q = 0; q < nf; ++q, p += 2)
@@ -373,41 +429,101 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
             par ^= (int)((base >> b.word(p)) & (base >> b.word(p + 1)) & 1ull);
           if (par & 1) neg = ~neg;
 #pragma unroll
-          for (int m = 0; m < NR; ++m)
-            if ((neg >> m) & 1u) a[m] = cpx<T>{-a[m].x, -a[m].y};
-        } else if (type == TOP_PHASE1) {
-          int wv[2 + 4 * WT];
-          b.readn<2 + 4 * WT>(k + 2, wv);
-          const int kind = wv[0], val = wv[1];
-          const cpx<T> d0{word_real<T>(wv + 2), word_real<T>(wv + 2 + WT)};
-          const cpx<T> d1{word_real<T>(wv + 2 + 2 * WT), word_real<T>(wv + 2 + 3 * WT)};
-          if (kind == TK_REG) {
+          for (int m = 0; m < NR; ++m) scale1(a[m], ((neg >> m) & 1u) ? T(-2) : T(0));
+        }
+        if (flags & LT_PHASEL) {
+          {
+            const int j = b.word(p), nt = b.word(p + 1);
+            p += 2;
+            cpx<T> w{T(1), T(0)};
+            for (int q = 0; q < nt; ++q, p += 3 + 2 * WT) {
+              const uint32_t lgm = (uint32_t)b.word(p);
+              const uint64_t om = ((uint64_t)(uint32_t)b.word(p + 2) << 32) | (uint32_t)b.word(p + 1);
+              const cpx<T> rr{b.real<T>(p + 3), b.real<T>(p + 3 + WT)};
+              if ((lg & lgm) == lgm && (base & om) == om) w = cmul(rr, w);
+            }
+            // w = (+-|w|) exp(i phi), |phi| <= pi/2: three shears and a scale
+            const T mag = sqrt(w.x * w.x + w.y * w.y);
+            const T sg = w.x < T(0) ? T(-1) : T(1);
+            const T wx = sg * w.x, wy = sg * w.y;
+            const T ps = -wy / (mag + wx), qs = wy / mag, cs = sg * mag - T(1);
 #pragma unroll
-            for (int m = 0; m < NR; ++m) a[m] = cmul(((val >> m) & 1) ? d1 : d0, a[m]);
-          } else {
-            const cpx<T> d = const_bit(kind, val, lg, base) ? d1 : d0;
-#pragma unroll
-            for (int m = 0; m < NR; ++m) a[m] = cmul(d, a[m]);
+            for (int m = 0; m < NR; ++m) {
+              if (j < 0 || ((m >> j) & 1)) {
+                phase_shears(a[m], ps, qs);
+                scale1(a[m], cs);
+              }
+            }
           }
-        } else if (type == TOP_DIAG2) {
-          const int ka = b.word(k + 2), va = b.word(k + 3), kb = b.word(k + 4), vb = b.word(k + 5);
-          cpx<T> d[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            d[e] = cpx<T>{b.real<T>(k + 6 + 2 * e * WT), b.real<T>(k + 6 + (2 * e + 1) * WT)};
+        }
+        if (flags & LT_RAWD) {
+          // a diagonal factor d = (1 + c) exp(i phi) per operand value, as
+          // (p, q, c) triples: PHASE1 two (by the qubit's bit), DIAG2 four
+          const int type = b.word(p), ka = b.word(p + 1), va = b.word(p + 2);
+          const int kb = type == RAW_DIAG2 ? b.word(p + 3) : TK_REG;
+          const int vb = type == RAW_DIAG2 ? b.word(p + 4) : 0;
+          const int f0 = p + (type == RAW_DIAG2 ? 5 : 3);
           const uint32_t ma = ka == TK_REG ? (uint32_t)va : (const_bit(ka, va, lg, base) ? ~0u : 0u);
           const uint32_t mb = kb == TK_REG ? (uint32_t)vb : (const_bit(kb, vb, lg, base) ? ~0u : 0u);
+          const int nfac = type == RAW_DIAG2 ? 4 : 2;
+          p = f0 + 3 * nfac * WT;
+          T fp[4], fq[4], fc[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int at = f0 + 3 * (e < nfac ? e : 0) * WT;
+            fp[e] = b.real<T>(at);
+            fq[e] = b.real<T>(at + WT);
+            fc[e] = b.real<T>(at + 2 * WT);
+          }
 #pragma unroll
           for (int m = 0; m < NR; ++m) {
-            const int ba = (ma >> m) & 1, bb = (mb >> m) & 1;
-            const cpx<T> f = bb ? (ba ? d[3] : d[2]) : (ba ? d[1] : d[0]);
-            a[m] = cmul(f, a[m]);
+            const int sel = (int)((ma >> m) & 1u) + 2 * (int)((mb >> m) & 1u);  // per lane
+            const T pm = sel == 0 ? fp[0] : sel == 1 ? fp[1] : sel == 2 ? fp[2] : fp[3];
+            const T qm = sel == 0 ? fq[0] : sel == 1 ? fq[1] : sel == 2 ? fq[2] : fq[3];
+            const T cm = sel == 0 ? fc[0] : sel == 1 ? fc[1] : sel == 2 ? fc[2] : fc[3];
+            phase_shears(a[m], pm, qm);
+            scale1(a[m], cm);
           }
+        }
+        // rotations on register bits, ascending
+#define QSV_ROT(J)                                                                    \
+  if ((J) < RB && (flags & (LT_ROT0 << (J)))) {                                       \
+    const T pj = b.real<T>(p), qj = b.real<T>(p + WT);                                \
+    p += 2 * WT;                                                                      \
+    shears<T, RB, ((J) < RB ? (J) : 0)>(a, pj, qj, (flags & (LT_SHEAR3 << (J))) != 0); \
+  }
+        QSV_ROT(0)
+        QSV_ROT(1)
+        QSV_ROT(2)
+        QSV_ROT(3)
+        QSV_ROT(4)
+#undef QSV_ROT
+        if (flags & LT_PERM2) {
+          dispatch_perm2<T, RB>(a, b.word(p), b.word(p + 1), b.word(p + 2));
+          p += 3;
+        }
+        if (flags & LT_U2) {
+          const int j0 = b.word(p), j1 = b.word(p + 1);
+          M4<T> U;
+#pragma unroll
+          for (int e = 0; e < 16; ++e)
+            U.m[e] = cpx<T>{b.real<T>(p + 2 + 2 * e * WT), b.real<T>(p + 2 + (2 * e + 1) * WT)};
+          p += 2 + 32 * WT;
+          dispatch_u2<T, RB>(a, j0, j1, U);
+        }
+        if (flags & LT_U1) {
+          const int j = b.word(p);
+          M2<T> U;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            U.m[e] = cpx<T>{b.real<T>(p + 1 + 2 * e * WT), b.real<T>(p + 1 + (2 * e + 1) * WT)};
+          dispatch_u1<T, RB>(a, j, U);
         }
         k += len;
       }
 #pragma unroll
-      for (int m = 0; m < NR; ++m) tile[sg ^ (uint32_t)rl(b.l0, 2 + m)] = a[m];
+      for (int m = 0; m < NR; ++m)
+        *reinterpret_cast<cpx<T>*>(tb + (sgb ^ (uint32_t)rl(b.l[0], 2 + m))) = a[m];
     }
     __syncthreads();
   }
@@ -445,7 +561,7 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
 }
 
 template <typename T, int TBMAX, int RB>
-__global__ __launch_bounds__(kTileThreads) void k_tile(cpx<T>* __restrict__ psi,
+__global__ __launch_bounds__(kTileThreads, 2) void k_tile(cpx<T>* __restrict__ psi,
                                                         const int32_t* __restrict__ prog) {
   const TileIO io{0, 1, 0, nullptr, nullptr, 0};
   (void)tile_body<T, TBMAX, RB>(psi, prog, blockIdx.x, io);
@@ -468,7 +584,7 @@ __global__ void k_batch_reset(int* counter) {
 }
 
 template <typename T, int TBMAX, int RB>
-__global__ __launch_bounds__(kTileThreads) void k_batch(cpx<T>* __restrict__ scratch,
+__global__ __launch_bounds__(kTileThreads, 2) void k_batch(cpx<T>* __restrict__ scratch,
                                                          const int32_t* __restrict__ progs,
                                                          const int64_t* __restrict__ passoff,
                                                          const int64_t* __restrict__ jobs,

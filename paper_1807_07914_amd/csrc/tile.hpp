@@ -9,60 +9,91 @@
 //
 // The pass body is a sequence of rounds.  In a round every thread takes
 // groups of 2^RB amplitudes that differ only in the round's RB "register"
-// local bits, applies the round's ops to them in registers and writes them
-// back to LDS.  The other t - RB local bits ("free" bits) select the group.
-// Diagonal ops may act on any qubit: for a register bit their value is a
-// mask over the register index m, for a free bit it is a per-group constant,
-// and for a qubit outside S it is constant over the tile (read from the tile
-// base index).
+// local bits, applies the round's layers to them in registers and writes
+// them back to LDS.  The other t - RB local bits ("free" bits) select the
+// group.  Diagonal work may involve any qubit: a register bit varies over
+// the amplitudes of a group, a free bit is constant per group, and a qubit
+// outside S is constant per tile (read from the tile base index).
 //
 // Program layout (int32 words):
-//   pass header : t, c, n_nonS, n_rounds, S[t], nonS[n_nonS], padded to a
+//   pass header : t, c, n_nonS, n_blocks, S[t], nonS[n_nonS], padded to a
 //                 multiple of 64 words
-//   round block : exactly kRoundWords words (read by each wavefront into
-//                 registers, 64 words per VGPR, and accessed with readlane):
-//                 [0] n_ops  [1] free-bit mask  [2 .. 2+2^RB) swizzled LDS
-//                 offsets of the register combinations m, then the ops.
-//                 An op never straddles a 64-word line unless it is longer
-//                 than a line.
-//   op          : type, n_words, payload...
-//     U1     : j, U[2x2]                     2x2 on register bit j
-//     U2     : j0, j1, U[4x4]                4x4 on register bits j0 < j1 (j0 = LSB)
-//     PHASE1 : kind, val, d0, d1             factor d0 / d1 by the qubit's bit
-//     DIAG2  : kindA, valA, kindB, valB, d[4]  factor d[bitA + 2 bitB]
-//     PERM2  : j0, j1, code                 CNOT / SWAP as a register permutation
-//     SIGN   : Mrr, nf, (f, mask)*nf, nd, (d, M)*nd, zfree,
-//              nrc, (q, mask)*nrc, nfc, (q, f)*nfc, ncc, (qa, qb)*ncc
-//              negation pattern over m:  Mrr ^ [mask for every free bit f
-//              set in the group] ^ [mask for every outside qubit q set in
-//              the tile], complemented when the group parity
-//              popcount(lg & zfree) + sum_d popcount(lg & (lg >> d) & M)
-//              + sum_(q,f) bit(q) bit(lg, f) + sum_(qa,qb) bit(qa) bit(qb) is odd.
+//   round block : exactly kRoundWords words, held by every wavefront in
+//                 kRoundLines VGPRs (64 words each) and read with readlane.
+//                 [0] n_layers | (word offset of the first layer) << 16
+//                 [1] free-bit mask  [2 .. 2+2^RB) swizzled LDS byte offsets
+//                 of the register combinations m, then the layers; lines
+//                 kTableLine0 .. kRoundLines-1 may hold tables instead.
+//   layer       : flags, n_words, then the payload of every step present,
+//                 in this order (all steps are optional):
+//     LT_TAB    : table line, sign mask.  Amplitude m is multiplied by
+//                 sign(m) * exp(i phi_m): the rotation of (re, im) by phi_m,
+//                 |phi_m| <= pi/2, as three shears x += p y; y += q x; x += p y
+//                 with (p_m, q_m) = (-tan(phi_m / 2), sin(phi_m)) at entry m
+//                 of the table line (one word per float, two per double).
+//     LT_MAG    : c_m for every m: amplitude m multiplied by (1 + c_m).
+//     LT_SIGN   : Mrr, nf, (f, mask)*nf, nd, (d, M)*nd, zfree,
+//                 nrc, (q, mask)*nrc, nfc, (q, f)*nfc, ncc, (qa, qb)*ncc
+//                 negation pattern over m:  Mrr ^ [mask for every free bit f
+//                 set in the group] ^ [mask for every outside qubit q set in
+//                 the tile], complemented when the group parity
+//                 popcount(lg & zfree) + sum_d popcount(lg & (lg >> d) & M)
+//                 + sum_(q,f) bit(q) bit(lg, f) + sum_(qa,qb) bit(qa) bit(qb) is odd.
+//     LT_PHASEL : j, nt, (lgmask, omask_lo, omask_hi, r)*nt:
+//                 per-group factor w = product of r over the terms whose free
+//                 bits lgmask are all set in the group and whose outside
+//                 qubits omask are all set in the tile, applied to the
+//                 amplitudes with register bit j set (every amplitude if j < 0)
+//     LT_RAWD   : type, payload, for diagonal factors that may be zero:
+//                 RAW_PHASE1 : kind, val, f[2]          factor f[bit of the qubit]
+//                 RAW_DIAG2  : kindA, valA, kindB, valB, f[4]  factor f[bitA + 2 bitB]
+//                 each factor (1 + c) exp(i phi) stored as p, q, c
+//                 (p = -tan(phi / 2), q = sin(phi), |phi| <= pi/2)
+//     rotations : for every flagged register bit j, ascending: p, q.  Real
+//                 rotation as in-place shears x0 += p x1, x1 += q x0, and a
+//                 third x0 += p x1 when the three-shear flag of j is set.
+//     LT_PERM2  : j0, j1, code     CNOT / SWAP as a register permutation on
+//                 bits j0 < j1 (m = b0 + 2 b1): code 0 swaps m = 1 <-> 3
+//                 (CNOT, control j0), 1 swaps 2 <-> 3 (CNOT, control j1),
+//                 2 swaps 1 <-> 2 (SWAP)
+//     LT_U2     : j0, j1, U[4x4]   4x4 on register bits j0 < j1 (j0 = LSB)
+//     LT_U1     : j, U[2x2]        2x2 on register bit j
 //   Operand kinds: 0 register (val = mask over m), 1 free (val = local bit),
-//   2 outside (val = global qubit).  Matrix entries are stored in the
-//   state's precision, one word per float, two words per double.
+//   2 outside (val = global qubit).  Reals are stored in the state's
+//   precision, one word per float, two words (low, high) per double.
+//
+// Every step except the rare LT_RAWD / LT_U2 / LT_U1 updates the amplitudes
+// in place with FMAs whose addend is the amplitude itself.  A layer is a
+// fixed sequence of optional steps rather than one of several op kinds:
+// merging several mutually exclusive op bodies made the register allocator
+// keep a second copy of all amplitudes and copy them on every op.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace qsv {
 
-enum TileOpType : int32_t {
-  TOP_U1 = 1,
-  TOP_U2 = 2,
-  TOP_SIGN = 3,
-  TOP_PHASE1 = 4,
-  TOP_DIAG2 = 5,
-  TOP_PERM2 = 6,  // j0, j1, code: register permutation on bits j0 < j1 (m = b0 + 2 b1):
-                  // code 0 swaps m = 1 <-> 3 (CNOT, control j0), 1 swaps 2 <-> 3
-                  // (CNOT, control j1), 2 swaps 1 <-> 2 (SWAP)
+enum LayerFlag : int32_t {
+  LT_TAB = 1 << 0,
+  LT_MAG = 1 << 1,
+  LT_SIGN = 1 << 2,
+  LT_PHASEL = 1 << 3,
+  LT_RAWD = 1 << 4,
+  LT_ROT0 = 1 << 8,     // rotation on register bit j: LT_ROT0 << j
+  LT_SHEAR3 = 1 << 16,  // three shears on bit j: LT_SHEAR3 << j
+  LT_PERM2 = 1 << 24,
+  LT_U2 = 1 << 25,
+  LT_U1 = 1 << 26,
 };
+
+enum RawDiagType : int32_t { RAW_PHASE1 = 4, RAW_DIAG2 = 5 };
 
 enum TileOperandKind : int32_t { TK_REG = 0, TK_FREE = 1, TK_OUT = 2 };
 
 constexpr int kTileThreads = 256;
-constexpr int kRoundLines = 4;                 // VGPRs per lane holding a round block
+constexpr int kRoundLines = 8;                 // VGPRs per lane holding a round block
 constexpr int kRoundWords = 64 * kRoundLines;  // words per round block
+constexpr int kTableLine0 = 2;                 // lines that may hold tables: 2 .. 7
 
 // XOR-linear bijection on tile-local amplitude indices that spreads
 // power-of-two strides over the LDS banks: B = 5 for 8-byte amplitudes

@@ -41,6 +41,19 @@ def test_emulated_fused_plans_match_oracle(dtype, n, tile):
         assert np.abs(got - ref).max() <= TOL[dtype], name
 
 
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 2e-6)])
+def test_emulated_deep_circuit_one_pass(dtype, tol):
+    # 290 gates in one tile pass (10 qubits, depth 20): every scale factor the
+    # planner defers must stay well conditioned over the whole pass
+    n = 10
+    ops = qc.random_brickwork(n, 20, qc.SEEDS["c1"])
+    psi0 = np.zeros(1 << n, dtype=complex)
+    psi0[0] = 1.0
+    ref = O.run(ops, n)
+    got = E.emulate(n, dtype, ops, psi0)
+    assert np.abs(got - ref).max() <= tol
+
+
 def test_pass_counts_fuse_gates():
     ops = qc.random_brickwork(28, 40, qc.SEEDS["c2"])
     a = qsv.plan_info(28, "c64", ops)
@@ -57,3 +70,74 @@ def test_plan_info_rejects_bad_input():
         qsv.plan_info(4, "c64", [qc.op("H", 4)])
     with pytest.raises(qsv.QsvError):
         qsv.plan_info(10, "c64", qc.ghz(10), tile_qubits=20)
+
+
+def _algebra_family(n, seed):
+    """Gates that exercise the planner's diagonal bookkeeping: scaled and
+    non-unitary 2x2 matrices, projectors, anti-diagonal gates, and general
+    2-qubit diagonals with and without zero entries, on every kind of qubit
+    (register, free and outside a tile)."""
+    rng = np.random.default_rng(seed)
+    cplx = lambda *s: rng.normal(size=s) + 1j * rng.normal(size=s)
+    ops = []
+    for _ in range(60):
+        kind = int(rng.integers(0, 11))
+        q = [int(x) for x in rng.permutation(n)[:2]]
+        if kind == 0:
+            ops.append(qc.op("U", q[0], mat=qc.haar_unitary(1, rng) * rng.uniform(0.5, 2.0)))
+        elif kind == 1:
+            ops.append(qc.op("U", q[0], mat=cplx(2, 2)))
+        elif kind == 2:
+            ops.append(qc.op("U", q[0], mat=np.diag([1.0, 0.0]).astype(complex)))
+        elif kind == 3:
+            ops.append(qc.op("U", q[0], mat=np.array([[0, 1], [1, 0]]) * np.exp(1j * rng.uniform(0, 6, (2, 2)))))
+        elif kind == 4:
+            ops.append(qc.op("U", *q, mat=np.diag(np.exp(1j * rng.uniform(0, 6, 4)))))
+        elif kind == 5:
+            d = cplx(4)
+            d[int(rng.integers(0, 4))] = 0.0
+            ops.append(qc.op("U", *q, mat=np.diag(d)))
+        elif kind == 6:
+            ops.append(qc.op("U", q[0], mat=np.diag(cplx(2))))
+        elif kind == 7:
+            ops.append(qc.op("CPHASE", *q, params=(float(rng.uniform(-3, 3)),)))
+        elif kind == 8:
+            ops.append(qc.op(("CZ", "CNOT", "SWAP")[int(rng.integers(0, 3))], *q))
+        elif kind == 9:
+            ops.append(qc.op(("RZ", "RX", "RY")[int(rng.integers(0, 3))], q[0],
+                             params=(float(rng.uniform(-3, 3)),)))
+        else:
+            ops.append(qc.op(("H", "S", "T", "Z", "X", "Y")[int(rng.integers(0, 6))], q[0]))
+    return ops
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,tile,seed", [(6, 5, 1), (7, 6, 2), (9, 7, 3), (9, 6, 4)])
+def test_emulated_gate_algebra_edge_cases(dtype, n, tile, seed):
+    ops = _algebra_family(n, 100 + seed)
+    psi0 = qc.random_state(n, 7 + seed)
+    ref = O.run(ops, n, psi=psi0.copy())
+    got = E.emulate(n, dtype, ops, psi0, tile)
+    scale = max(1.0, float(np.abs(ref).max()))
+    assert np.abs(got - ref).max() <= TOL[dtype] * 10 * scale
+
+
+def test_givens_split_counts():
+    """Unitary 2x2 gates become real rotations (shears), pure phases are
+    carried (no step of their own), and diagonal factors are applied in bulk:
+    one table per layer of rotations at most."""
+    n = 12
+    ops = qc.random_brickwork(n, 8, 5)
+    words, steps = E.program(n, "c64", ops)
+    counts = E.op_counts(words, steps, "c64")
+    n_u1 = sum(1 for o in ops if o.name == "U")
+    # consecutive 2x2 gates on one qubit are multiplied first, so there are
+    # at most as many rotations as 2x2 gates
+    assert n_u1 // 2 < counts.get("ROT", 0) <= n_u1
+    assert counts.get("U1", 0) == 0 and counts.get("RAWD", 0) == 0
+    assert counts.get("TAB", 0) < n_u1 // 2
+    assert counts["layers"] < n_u1 // 2
+    rz = [qc.op("RZ", q, params=(0.3 * q + 0.1,)) for q in range(n)]
+    words, steps = E.program(n, "c64", rz)
+    counts = E.op_counts(words, steps, "c64")
+    assert counts.get("ROT", 0) == 0 and counts.get("RAWD", 0) == 0

@@ -17,8 +17,13 @@ import numpy as np
 
 from paper_1807_07914_amd import qsv
 
-ROUND_WORDS = 256
-TOP_U1, TOP_U2, TOP_SIGN, TOP_PHASE1, TOP_DIAG2, TOP_PERM2 = 1, 2, 3, 4, 5, 6
+LINES = 8
+ROUND_WORDS = 64 * LINES
+TABLE_LINE0 = 2
+LT_TAB, LT_MAG, LT_SIGN, LT_PHASEL, LT_RAWD = 1, 2, 4, 8, 16
+LT_ROT0, LT_SHEAR3 = 1 << 8, 1 << 16
+LT_PERM2, LT_U2, LT_U1 = 1 << 24, 1 << 25, 1 << 26
+RAW_PHASE1, RAW_DIAG2 = 4, 5
 TK_REG, TK_FREE, TK_OUT = 0, 1, 2
 CFG = {"c64": dict(RB=5, SB=5, WT=1), "c128": dict(RB=4, SB=4, WT=2)}
 
@@ -90,6 +95,15 @@ def _apply_dense(psi, n, qubits, U):
         psi[idx] = U @ psi[idx]
 
 
+def _shear3(x, p, q):
+    """exp(i phi) x as three shears of (re, im), as the kernel does."""
+    re, im = x.real, x.imag
+    re = re + p * im
+    im = im + q * re
+    re = re + p * im
+    return complex(re, im)
+
+
 def run_pass(psi, n, words, off, cfg):
     RB, SB, WT = cfg["RB"], cfg["SB"], cfg["WT"]
     NR = 1 << RB
@@ -98,6 +112,7 @@ def run_pass(psi, n, words, off, cfg):
     nonS = [int(x) for x in words[off + 4 + t:off + 4 + t + nns]]
     assert S == sorted(S) and S[:c] == list(range(c))
     b0 = off + ((4 + t + nns + 63) & ~63)
+    esz = 8 * WT  # bytes per amplitude: the header holds LDS byte offsets
     for tid in range(1 << (n - t)):
         base = deposit(tid, nonS)
         lds = np.zeros(1 << t, dtype=np.complex128)
@@ -106,51 +121,37 @@ def run_pass(psi, n, words, off, cfg):
             lds[swizzle(l, SB)] = psi[gidx[l]]
         for r in range(nblocks):
             blk = [int(x) for x in words[b0 + r * ROUND_WORDS: b0 + (r + 1) * ROUND_WORDS]]
-            nops, free_mask = blk[0], blk[1] & 0xffffffff
-            lmsw = [blk[2 + m] & 0xffffffff for m in range(NR)]
+            nlay, k0, free_mask = blk[0] & 0xffff, blk[0] >> 16, blk[1] & 0xffffffff
+            assert k0 == 2 + NR
+            assert all((blk[2 + m] & 0xffffffff) % esz == 0 for m in range(NR))
+            lmsw = [(blk[2 + m] & 0xffffffff) // esz for m in range(NR)]
             for gi in range(1 << (t - RB)):
                 lg = pdep_mask(gi, free_mask)
                 sg = swizzle(lg, SB)
                 a = [lds[sg ^ lmsw[m]] for m in range(NR)]
-                k = 2 + NR
-                for _ in range(nops):
-                    typ, ln = blk[k], blk[k + 1]
+                k = k0
+                low_table = LINES
+                for _ in range(nlay):
+                    flags, ln = blk[k], blk[k + 1]
                     assert ln >= 2 and k + ln <= ROUND_WORDS
-                    if typ in (TOP_U1, TOP_PHASE1) or ln <= 64:
-                        assert (k & 63) + min(ln, 64) <= 64 or ln > 64, (typ, k, ln)
-                    else:
-                        assert k & 63 == 0
-                    if typ == TOP_U1:
-                        j = blk[k + 2]
-                        U = np.array(_cplx(blk, k + 3, WT, 4)).reshape(2, 2)
+                    p = k + 2
+                    if flags & LT_TAB:
+                        tl, sm = blk[p], blk[p + 1] & 0xffffffff
+                        p += 2
+                        assert TABLE_LINE0 <= tl < LINES
+                        low_table = min(low_table, tl)
                         for m in range(NR):
-                            if not (m >> j) & 1:
-                                m2 = m | (1 << j)
-                                a[m], a[m2] = (U[0, 0] * a[m] + U[0, 1] * a[m2],
-                                               U[1, 0] * a[m] + U[1, 1] * a[m2])
-                    elif typ == TOP_U2:
-                        j0, j1 = blk[k + 2], blk[k + 3]
-                        assert j0 < j1
-                        U = np.array(_cplx(blk, k + 4, WT, 16)).reshape(4, 4)
+                            pm = _real(blk, 64 * tl + 2 * m * WT, WT)
+                            qm = _real(blk, 64 * tl + (2 * m + 1) * WT, WT)
+                            assert abs(pm) <= 1.0 + 1e-12 and abs(qm) <= 1.0 + 1e-12
+                            a[m] = _shear3(a[m], pm, qm)
+                            if (sm >> m) & 1:
+                                a[m] = -a[m]
+                    if flags & LT_MAG:
                         for m in range(NR):
-                            if (m >> j0) & 1 or (m >> j1) & 1:
-                                continue
-                            ii = [m, m | (1 << j0), m | (1 << j1), m | (1 << j0) | (1 << j1)]
-                            y = U @ np.array([a[x] for x in ii])
-                            for x, v in zip(ii, y):
-                                a[x] = v
-                    elif typ == TOP_PERM2:
-                        j0, j1, code = blk[k + 2:k + 5]
-                        assert j0 < j1 and code in (0, 1, 2)
-                        sw = {0: (1, 3), 1: (2, 3), 2: (1, 2)}[code]
-                        for m in range(NR):
-                            if (m >> j0) & 1 or (m >> j1) & 1:
-                                continue
-                            ii = [m, m | (1 << j0), m | (1 << j1), m | (1 << j0) | (1 << j1)]
-                            x, y = ii[sw[0]], ii[sw[1]]
-                            a[x], a[y] = a[y], a[x]
-                    elif typ == TOP_SIGN:
-                        p = k + 2
+                            a[m] *= 1.0 + _real(blk, p + m * WT, WT)
+                        p += NR * WT
+                    if flags & LT_SIGN:
                         neg = blk[p] & 0xffffffff; p += 1
                         nf = blk[p]; p += 1
                         for _ in range(nf):
@@ -176,26 +177,37 @@ def run_pass(psi, n, words, off, cfg):
                         for _ in range(ncc):
                             par ^= (base >> blk[p]) & (base >> blk[p + 1]) & 1
                             p += 2
-                        assert p <= k + ln
                         if par & 1:
                             neg = ~neg & 0xffffffff
                         for m in range(NR):
                             if (neg >> m) & 1:
                                 a[m] = -a[m]
-                    elif typ == TOP_PHASE1:
-                        kind, val = blk[k + 2], blk[k + 3]
-                        d0, d1 = _cplx(blk, k + 4, WT, 2)
+                    if flags & LT_PHASEL:
+                        j, nt = blk[p], blk[p + 1]
+                        p += 2
+                        assert -1 <= j < RB
+                        w = 1.0 + 0j
+                        for _ in range(nt):
+                            lgm = blk[p] & 0xffffffff
+                            om = (blk[p + 1] & 0xffffffff) | ((blk[p + 2] & 0xffffffff) << 32)
+                            r_ = _cplx(blk, p + 3, WT, 1)[0]
+                            if (lg & lgm) == lgm and (base & om) == om:
+                                w *= r_
+                            p += 3 + 2 * WT
                         for m in range(NR):
-                            if kind == TK_REG:
-                                bit = (val >> m) & 1
-                            elif kind == TK_FREE:
-                                bit = (lg >> val) & 1
-                            else:
-                                bit = (base >> val) & 1
-                            a[m] *= d1 if bit else d0
-                    elif typ == TOP_DIAG2:
-                        ka, va, kb, vb = blk[k + 2:k + 6]
-                        d = _cplx(blk, k + 6, WT, 4)
+                            if j < 0 or (m >> j) & 1:
+                                a[m] *= w
+                    if flags & LT_RAWD:
+                        typ = blk[p]
+                        assert typ in (RAW_PHASE1, RAW_DIAG2)
+                        ops_ = blk[p + 1:p + (5 if typ == RAW_DIAG2 else 3)]
+                        p += 5 if typ == RAW_DIAG2 else 3
+                        nfac = 4 if typ == RAW_DIAG2 else 2
+                        fac = []
+                        for f in range(nfac):
+                            fp_, fq_, fc_ = (_real(blk, p + (3 * f + e) * WT, WT) for e in range(3))
+                            fac.append((fp_, fq_, fc_))
+                        p += 3 * nfac * WT
 
                         def bit(kind, val, m):
                             if kind == TK_REG:
@@ -204,10 +216,60 @@ def run_pass(psi, n, words, off, cfg):
                                 return (lg >> val) & 1
                             return (base >> val) & 1
                         for m in range(NR):
-                            a[m] *= d[bit(ka, va, m) + 2 * bit(kb, vb, m)]
-                    else:
-                        assert typ == 0, typ
+                            sel = bit(ops_[0], ops_[1], m)
+                            if typ == RAW_DIAG2:
+                                sel += 2 * bit(ops_[2], ops_[3], m)
+                            fp_, fq_, fc_ = fac[sel]
+                            a[m] = _shear3(a[m], fp_, fq_) * (1.0 + fc_)
+                    for j in range(RB):
+                        if flags & (LT_ROT0 << j):
+                            p_, q_ = _real(blk, p, WT), _real(blk, p + WT, WT)
+                            p += 2 * WT
+                            assert abs(p_) <= 1.0 + 1e-12 and abs(q_) <= 1.0 + 1e-12
+                            three = bool(flags & (LT_SHEAR3 << j))
+                            for m in range(NR):
+                                if not (m >> j) & 1:
+                                    m2 = m | (1 << j)
+                                    a[m] += p_ * a[m2]
+                                    a[m2] += q_ * a[m]
+                                    if three:
+                                        a[m] += p_ * a[m2]
+                    if flags & LT_PERM2:
+                        j0, j1, code = blk[p:p + 3]
+                        p += 3
+                        assert j0 < j1 and code in (0, 1, 2)
+                        sw = {0: (1, 3), 1: (2, 3), 2: (1, 2)}[code]
+                        for m in range(NR):
+                            if (m >> j0) & 1 or (m >> j1) & 1:
+                                continue
+                            ii = [m, m | (1 << j0), m | (1 << j1), m | (1 << j0) | (1 << j1)]
+                            x, y = ii[sw[0]], ii[sw[1]]
+                            a[x], a[y] = a[y], a[x]
+                    if flags & LT_U2:
+                        j0, j1 = blk[p], blk[p + 1]
+                        assert j0 < j1
+                        U = np.array(_cplx(blk, p + 2, WT, 16)).reshape(4, 4)
+                        p += 2 + 32 * WT
+                        for m in range(NR):
+                            if (m >> j0) & 1 or (m >> j1) & 1:
+                                continue
+                            ii = [m, m | (1 << j0), m | (1 << j1), m | (1 << j0) | (1 << j1)]
+                            y = U @ np.array([a[x] for x in ii])
+                            for x, v in zip(ii, y):
+                                a[x] = v
+                    if flags & LT_U1:
+                        j = blk[p]
+                        U = np.array(_cplx(blk, p + 1, WT, 4)).reshape(2, 2)
+                        p += 1 + 8 * WT
+                        for m in range(NR):
+                            if not (m >> j) & 1:
+                                m2 = m | (1 << j)
+                                a[m], a[m2] = (U[0, 0] * a[m] + U[0, 1] * a[m2],
+                                               U[1, 0] * a[m] + U[1, 1] * a[m2])
+                    assert p == k + ln, (hex(flags), p, k, ln)
                     k += ln
+                # the layers never run into a table line
+                assert k <= 64 * low_table
                 for m in range(NR):
                     lds[sg ^ lmsw[m]] = a[m]
         for l in range(1 << t):
@@ -266,3 +328,37 @@ def emulate_batch_job(dtype, words, passoff, job):
         assert 1 <= t <= w, (t, w)
         run_pass(psi, w, words, off, CFG[dtype])
     return psi
+
+
+STEP_NAMES = [(LT_TAB, "TAB"), (LT_MAG, "MAG"), (LT_SIGN, "SIGN"), (LT_PHASEL, "PHASEL"),
+              (LT_RAWD, "RAWD"), (LT_PERM2, "PERM2"), (LT_U2, "U2"), (LT_U1, "U1")]
+
+
+def op_counts(words, steps, dtype):
+    """Number of layers, blocks and steps of each kind in a plan's tile
+    programs ('ROT' counts rotations)."""
+    RB = CFG[dtype]["RB"]
+    out = {}
+
+    def add(key, v=1):
+        out[key] = out.get(key, 0) + v
+    for st in steps:
+        if st < 0:
+            add("separate")
+            continue
+        off = int(st)
+        t, c, nns, nblocks = (int(x) for x in words[off:off + 4])
+        b0 = off + ((4 + t + nns + 63) & ~63)
+        add("blocks", nblocks)
+        for r in range(nblocks):
+            blk = words[b0 + r * ROUND_WORDS: b0 + (r + 1) * ROUND_WORDS]
+            k = int(blk[0]) >> 16
+            for _ in range(int(blk[0]) & 0xffff):
+                flags = int(blk[k])
+                add("layers")
+                for bitv, name in STEP_NAMES:
+                    if flags & bitv:
+                        add(name)
+                add("ROT", bin((flags >> 8) & ((1 << RB) - 1)).count("1"))
+                k += int(blk[k + 1])
+    return out
