@@ -354,7 +354,7 @@ struct BlockWriter {
       std::vector<int32_t> w;
       fill(w, lines);
       const int lowest = n_lines > 0 ? lines[n_lines - 1] : next_line + 1;
-      if (ok && k + (int)w.size() <= 64 * lowest) {
+      if (ok && k + (int)w.size() <= std::min(kLayerWords, 64 * lowest)) {
         w[1] = (int32_t)w.size();
         for (size_t i = 0; i < w.size(); ++i) prog[b0 + k + i] = w[i];
         k += (int)w.size();
@@ -999,7 +999,7 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
       };
       std::vector<Extra> extras;
       // per-group phase entries, at most kTermsPerLayer terms each
-      constexpr size_t kTermsPerLayer = 24;
+      constexpr size_t kTermsPerLayer = 8;
       std::vector<std::pair<int, std::vector<PhTerm>>> phl;
       for (auto& e : g.phl) {
         std::vector<PhTerm> terms;
@@ -1043,88 +1043,129 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
           BlockWriter<T>::real_words(fc, w);
         }
       };
-      const size_t n_extra_layers = extras.size() > 1 ? extras.size() - 1 : 0;
-      for (size_t x = 0; x < n_extra_layers; ++x) {
-        bw.layer(0, [&](std::vector<int32_t>& w, const int*) {
-          const Extra& E = extras[x];
-          w = {E.kind == 0 ? LT_PHASEL : LT_RAWD, 0};
-          if (E.kind == 0) phasel_words(w, E.idx);
-          else raw_words(w, E.idx);
-        });
+      // Steps in the order a layer applies them, each as (flag, payload
+      // words); consecutive steps are packed into layers of at most
+      // kLayerWords words, one step of each kind per layer.
+      struct Blob {
+        int32_t flag;
+        std::vector<int32_t> w;
+      };
+      std::vector<Blob> blobs;
+      if (tab) blobs.push_back({LT_TAB, {0, (int32_t)smask}});  // line filled in at packing
+      if (mag) blobs.push_back({LT_MAG, mline});
+      if (sign) {
+        // the sign lists compose by XOR: long ones are split over several steps
+        std::vector<std::pair<int, uint32_t>> fm = g.fmix, rc = g.rcmix;
+        std::vector<int32_t> lc = loc, fcl = g.fc, ccl = g.cc;
+        uint32_t Mrr = g.Mrr, zf = g.zfree;
+        constexpr size_t kPairs = 12;  // list entries per sign step
+        do {
+          std::vector<int32_t> w = {(int32_t)Mrr};
+          auto take_pairs = [&](auto& v) {
+            const size_t n = std::min(v.size(), kPairs);
+            w.push_back((int32_t)n);
+            for (size_t i = 0; i < n; ++i) w.insert(w.end(), {v[i].first, (int32_t)v[i].second});
+            v.erase(v.begin(), v.begin() + n);
+          };
+          auto take_flat = [&](std::vector<int32_t>& v) {
+            const size_t n = std::min(v.size() / 2, kPairs);
+            w.push_back((int32_t)n);
+            w.insert(w.end(), v.begin(), v.begin() + 2 * n);
+            v.erase(v.begin(), v.begin() + 2 * n);
+          };
+          take_pairs(fm);
+          take_flat(lc);
+          w.push_back((int32_t)zf);
+          take_pairs(rc);
+          take_flat(fcl);
+          take_flat(ccl);
+          blobs.push_back({LT_SIGN, w});
+          Mrr = 0;
+          zf = 0;
+        } while (!fm.empty() || !rc.empty() || !lc.empty() || !fcl.empty() || !ccl.empty());
       }
-      const int nl = tab ? 1 : 0;
-      bw.layer(nl, [&](std::vector<int32_t>& w, const int* lines) {
-        int32_t flags = 0;
-        w = {0, 0};
-        if (tab) {
-          flags |= LT_TAB;
-          w.push_back(lines[0]);
-          w.push_back((int32_t)smask);
-        }
-        if (mag) {
-          flags |= LT_MAG;
-          w.insert(w.end(), mline.begin(), mline.end());
-        }
-        if (sign) {
-          flags |= LT_SIGN;
-          w.push_back((int32_t)g.Mrr);
-          w.push_back((int32_t)g.fmix.size());
-          for (auto& e : g.fmix) w.insert(w.end(), {e.first, (int32_t)e.second});
-          w.push_back((int32_t)loc.size() / 2);
-          w.insert(w.end(), loc.begin(), loc.end());
-          w.push_back((int32_t)g.zfree);
-          w.push_back((int32_t)g.rcmix.size());
-          for (auto& e : g.rcmix) w.insert(w.end(), {e.first, (int32_t)e.second});
-          w.push_back((int32_t)g.fc.size() / 2);
-          w.insert(w.end(), g.fc.begin(), g.fc.end());
-          w.push_back((int32_t)g.cc.size() / 2);
-          w.insert(w.end(), g.cc.begin(), g.cc.end());
-        }
-        if (!extras.empty()) {
-          const Extra& E = extras.back();
-          if (E.kind == 0) {
-            flags |= LT_PHASEL;
-            phasel_words(w, E.idx);
-          } else {
-            flags |= LT_RAWD;
-            raw_words(w, E.idx);
-          }
-        }
-        // rotations, ascending register bit
+      for (const Extra& E : extras) {
+        std::vector<int32_t> w;
+        if (E.kind == 0) phasel_words(w, E.idx);
+        else raw_words(w, E.idx);
+        blobs.push_back({E.kind == 0 ? LT_PHASEL : LT_RAWD, w});
+      }
+      {
         std::vector<int> rots(L.rots);
         std::sort(rots.begin(), rots.end(), [&](int x, int y) { return rp.nd[x].j0 < rp.nd[y].j0; });
         for (int i : rots) {
           const NdItem& it = rp.nd[i];
-          flags |= LT_ROT0 << it.j0;
-          if (it.jf >> 8) flags |= LT_SHEAR3 << it.j0;
-          BlockWriter<T>::real_words(it.p, w);
-          BlockWriter<T>::real_words(it.q, w);
+          Blob bl{LT_ROT0 << it.j0, {}};
+          if (it.jf >> 8) bl.flag |= LT_SHEAR3 << it.j0;
+          BlockWriter<T>::real_words(it.p, bl.w);
+          BlockWriter<T>::real_words(it.q, bl.w);
+          blobs.push_back(bl);
         }
-        if (L.tail >= 0) {
-          const NdItem& it = rp.nd[L.tail];
-          if (it.type == TOP_PERM2) {
-            flags |= LT_PERM2;
-            w.insert(w.end(), {it.j0, it.j1, it.code});
-          } else if (it.type == TOP_U2) {
-            flags |= LT_U2;
-            w.insert(w.end(), {it.j0, it.j1});
-            for (int e = 0; e < 16; ++e) {
-              BlockWriter<T>::real_words(it.m[e].real(), w);
-              BlockWriter<T>::real_words(it.m[e].imag(), w);
-            }
-          } else {
-            flags |= LT_U1;
-            w.push_back(it.j0);
-            for (int e = 0; e < 4; ++e) {
-              BlockWriter<T>::real_words(it.m[e].real(), w);
-              BlockWriter<T>::real_words(it.m[e].imag(), w);
-            }
+      }
+      if (L.tail >= 0) {
+        const NdItem& it = rp.nd[L.tail];
+        Blob bl{0, {}};
+        if (it.type == TOP_PERM2) {
+          bl.flag = LT_PERM2;
+          bl.w = {it.j0, it.j1, it.code};
+        } else if (it.type == TOP_U2) {
+          bl.flag = LT_U2;
+          bl.w = {it.j0, it.j1};
+          for (int e = 0; e < 16; ++e) {
+            BlockWriter<T>::real_words(it.m[e].real(), bl.w);
+            BlockWriter<T>::real_words(it.m[e].imag(), bl.w);
+          }
+        } else {
+          bl.flag = LT_U1;
+          bl.w = {it.j0};
+          for (int e = 0; e < 4; ++e) {
+            BlockWriter<T>::real_words(it.m[e].real(), bl.w);
+            BlockWriter<T>::real_words(it.m[e].imag(), bl.w);
           }
         }
-        w[0] = flags;
-      });
-      if (bw.failed) return false;
-      if (tab) bw.put_line(bw.next_line + 1, tline);
+        blobs.push_back(bl);
+      }
+      // step kinds in application order (rotations: one kind per register bit)
+      auto order = [](int32_t flag) {
+        if (flag & LT_TAB) return 0;
+        if (flag & LT_MAG) return 1;
+        if (flag & LT_SIGN) return 2;
+        if (flag & LT_PHASEL) return 3;
+        if (flag & LT_RAWD) return 4;
+        for (int j = 0; j < 8; ++j)
+          if (flag & (LT_ROT0 << j)) return 5 + j;
+        return 13;
+      };
+      const int budget = kLayerWords - (2 + NR) - 2;
+      size_t bi = 0;
+      while (bi < blobs.size()) {
+        size_t be = bi;
+        int words = 0, last = -1;
+        while (be < blobs.size() && order(blobs[be].flag) > last &&
+               words + (int)blobs[be].w.size() <= budget) {
+          words += (int)blobs[be].w.size();
+          last = order(blobs[be].flag);
+          ++be;
+        }
+        if (be == bi) {  // a single step longer than a layer may be (not formed by the planner)
+          return false;
+        }
+        const bool has_tab = (blobs[bi].flag & LT_TAB) != 0;
+        bw.layer(has_tab ? 1 : 0, [&](std::vector<int32_t>& w, const int* lines) {
+          int32_t flags = 0;
+          w = {0, 0};
+          for (size_t x = bi; x < be; ++x) {
+            flags |= blobs[x].flag;
+            const size_t at = w.size();
+            w.insert(w.end(), blobs[x].w.begin(), blobs[x].w.end());
+            if (blobs[x].flag & LT_TAB) w[at] = lines[0];
+          }
+          w[0] = flags;
+        });
+        if (bw.failed) return false;
+        if (has_tab) bw.put_line(bw.next_line + 1, tline);
+        bi = be;
+      }
     }
     bw.close();
   }

@@ -51,18 +51,9 @@ struct WordsPer {
 // values in the lanes that readlane addresses.
 struct Blk {
   int l[kRoundLines];
+  // layer words lie in lines 0 and 1
   __device__ __forceinline__ int word(int k) const {
-    const int i = k & 63;
-    switch (k >> 6) {
-      case 0: return rl(l[0], i);
-      case 1: return rl(l[1], i);
-      case 2: return rl(l[2], i);
-      case 3: return rl(l[3], i);
-      case 4: return rl(l[4], i);
-      case 5: return rl(l[5], i);
-      case 6: return rl(l[6], i);
-      default: return rl(l[7], i);
-    }
+    return k < 64 ? rl(l[0], k) : rl(l[1], k & 63);
   }
   // f(line VGPR) for a table line (kTableLine0 .. kRoundLines - 1)
   template <typename F>

@@ -22,8 +22,8 @@
 //                 kRoundLines VGPRs (64 words each) and read with readlane.
 //                 [0] n_layers | (word offset of the first layer) << 16
 //                 [1] free-bit mask  [2 .. 2+2^RB) swizzled LDS byte offsets
-//                 of the register combinations m, then the layers; lines
-//                 kTableLine0 .. kRoundLines-1 may hold tables instead.
+//                 of the register combinations m, then the layers, all within
+//                 lines 0 and 1; lines kTableLine0 .. kRoundLines-1 hold tables.
 //   layer       : flags, n_words, then the payload of every step present,
 //                 in this order (all steps are optional):
 //     LT_TAB    : table line, sign mask.  Amplitude m is multiplied by
@@ -93,6 +93,7 @@ enum TileOperandKind : int32_t { TK_REG = 0, TK_FREE = 1, TK_OUT = 2 };
 constexpr int kTileThreads = 256;
 constexpr int kRoundLines = 8;                 // VGPRs per lane holding a round block
 constexpr int kRoundWords = 64 * kRoundLines;  // words per round block
+constexpr int kLayerWords = 128;               // layers lie in words [2 + 2^RB, 128): lines 0, 1
 constexpr int kTableLine0 = 2;                 // lines that may hold tables: 2 .. 7
 
 // XOR-linear bijection on tile-local amplitude indices that spreads

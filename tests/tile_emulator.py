@@ -20,6 +20,7 @@ from paper_1807_07914_amd import qsv
 LINES = 8
 ROUND_WORDS = 64 * LINES
 TABLE_LINE0 = 2
+LAYER_WORDS = 128
 LT_TAB, LT_MAG, LT_SIGN, LT_PHASEL, LT_RAWD = 1, 2, 4, 8, 16
 LT_ROT0, LT_SHEAR3 = 1 << 8, 1 << 16
 LT_PERM2, LT_U2, LT_U1 = 1 << 24, 1 << 25, 1 << 26
@@ -268,8 +269,8 @@ def run_pass(psi, n, words, off, cfg):
                                                U[1, 0] * a[m] + U[1, 1] * a[m2])
                     assert p == k + ln, (hex(flags), p, k, ln)
                     k += ln
-                # the layers never run into a table line
-                assert k <= 64 * low_table
+                # the layers lie in lines 0 and 1 and never run into a table line
+                assert k <= min(LAYER_WORDS, 64 * low_table)
                 for m in range(NR):
                     lds[sg ^ lmsw[m]] = a[m]
         for l in range(1 << t):
