@@ -538,23 +538,83 @@ qsv_status expval_impl(qsv_state* s, const void* data, const uint64_t* xmask, co
     zs[i] = zmask[order[i]];
     ny[i] = __builtin_popcountll(xmask[order[i]] & zmask[order[i]]);
   }
-  int i = 0;
-  while (i < n_terms) {
+  // Terms with X masks are reduced tile by tile where their masks fit a
+  // tile (the low qubits plus up to 8 others, first fit, at most 16 terms a
+  // tile); the others, and the Z-only terms, one pass per distinct X mask.
+  // Device outputs go to consecutive slots; slot_of[k] maps them back.
+  std::vector<int> slot_of(n_terms, -1);
+  int next_slot = 0;
+  const bool f32 = s->dt == QSV_C64;
+  const int TB = std::min(s->n, f32 ? xtile_max_bits<float>() : xtile_max_bits<double>());
+  const int cT = std::min(TB, f32 ? xtile_low_bits<float>() : xtile_low_bits<double>());
+  const uint64_t lowq = (1ull << cT) - 1ull;
+  struct XTile {
+    uint64_t hi = 0;
+    std::vector<int> ks;
+  };
+  std::vector<XTile> xtiles;
+  std::vector<std::pair<int, int>> plain;  // [i, j) groups on the per-mask path
+  for (int i = 0; i < n_terms;) {
     int j = i;
     while (j < n_terms && xmask[order[j]] == xmask[order[i]]) ++j;
-    hipError_t e = s->dt == QSV_C64
-                       ? launch_expval_group<float>(static_cast<const cpx<float>*>(data), s->n,
-                                                    xmask[order[i]], j - i, &zs[i], &ny[i], ws,
-                                                    outd + i, s->stream)
-                       : launch_expval_group<double>(static_cast<const cpx<double>*>(data), s->n,
-                                                     xmask[order[i]], j - i, &zs[i], &ny[i], ws,
-                                                     outd + i, s->stream);
-    if (e != hipSuccess) return hip_fail(e, "expval");
+    const uint64_t x = xmask[order[i]];
+    const uint64_t hi = x & ~lowq;
+    if (x == 0 || __builtin_popcountll(hi) > TB - cT) {
+      plain.push_back({i, j});
+    } else {
+      for (int k = i; k < j; ++k) {
+        size_t a = 0;
+        for (; a < xtiles.size(); ++a)
+          if (__builtin_popcountll(xtiles[a].hi | hi) <= TB - cT &&
+              xtiles[a].ks.size() < (size_t)16)
+            break;
+        if (a == xtiles.size()) xtiles.emplace_back();
+        xtiles[a].hi |= hi;
+        xtiles[a].ks.push_back(k);
+      }
+    }
     i = j;
   }
-  std::vector<double> raw(n_terms);
-  QSV_HIP(hipMemcpyAsync(raw.data(), outd, n_terms * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  for (const XTile& xt : xtiles) {
+    std::vector<int> S;
+    for (int q = 0; q < cT; ++q) S.push_back(q);
+    for (int q = cT; q < s->n; ++q)
+      if ((xt.hi >> q) & 1) S.push_back(q);
+    const int nt = (int)xt.ks.size();
+    std::vector<uint64_t> xs(nt), zz(nt);
+    std::vector<int> yy(nt);
+    for (int e = 0; e < nt; ++e) {
+      const int k = xt.ks[e];
+      xs[e] = xmask[order[k]];
+      zz[e] = zs[k];
+      yy[e] = ny[k];
+      slot_of[k] = next_slot + e;
+    }
+    hipError_t e = f32 ? launch_expval_tile<float>(static_cast<const cpx<float>*>(data), s->n, S.data(),
+                                                  (int)S.size(), cT, xs.data(), zz.data(), yy.data(), nt,
+                                                  ws, outd + next_slot, s->stream)
+                       : launch_expval_tile<double>(static_cast<const cpx<double>*>(data), s->n, S.data(),
+                                                   (int)S.size(), cT, xs.data(), zz.data(), yy.data(), nt,
+                                                   ws, outd + next_slot, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "expval (tiles)");
+    next_slot += nt;
+  }
+  for (const auto& gr : plain) {
+    const int i = gr.first, j = gr.second;
+    for (int k = i; k < j; ++k) slot_of[k] = next_slot + (k - i);
+    hipError_t e = f32 ? launch_expval_group<float>(static_cast<const cpx<float>*>(data), s->n,
+                                                    xmask[order[i]], j - i, &zs[i], &ny[i], ws,
+                                                    outd + next_slot, s->stream)
+                       : launch_expval_group<double>(static_cast<const cpx<double>*>(data), s->n,
+                                                     xmask[order[i]], j - i, &zs[i], &ny[i], ws,
+                                                     outd + next_slot, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "expval");
+    next_slot += j - i;
+  }
+  std::vector<double> dev_out(n_terms), raw(n_terms);
+  QSV_HIP(hipMemcpyAsync(dev_out.data(), outd, n_terms * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   QSV_HIP(hipStreamSynchronize(s->stream));
+  for (int k = 0; k < n_terms; ++k) raw[k] = dev_out[slot_of[k]];
   std::vector<double> val(n_terms);
   for (int k = 0; k < n_terms; ++k) {
     const int t = order[k];

@@ -108,6 +108,16 @@ hipError_t launch_expval_group(const cpx<T>* psi, int n, uint64_t xmask, int nt,
                                const uint64_t* zmask_host, const int* ny_host, double* ws,
                                double* out_dev, hipStream_t st);
 size_t expval_ws_doubles(int n, int nt);
+// nt <= 16 terms whose X masks lie in the tile qubits S (ascending, t of
+// them, S[0..c) = 0..c-1): out_dev[k] as launch_expval_group gives for term k
+template <typename T>
+hipError_t launch_expval_tile(const cpx<T>* psi, int n, const int* S, int t, int c,
+                              const uint64_t* xmask, const uint64_t* zmask, const int* ny, int nt,
+                              double* ws, double* out_dev, hipStream_t st);
+template <typename T>
+int xtile_max_bits();
+template <typename T>
+int xtile_low_bits();
 
 // sampler: returns indices into out_dev (uint64) for uniforms_dev
 template <typename T>

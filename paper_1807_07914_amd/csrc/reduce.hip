@@ -131,6 +131,145 @@ __global__ __launch_bounds__(kRB) void k_expval_part(const cpx<T>* __restrict__ 
   }
 }
 
+// ------------------------------------------------- X-mask terms by tiles
+// Terms whose X masks lie in a set S of at most TB qubits (the low c qubits
+// always included, so that the tile is read as contiguous segments) are
+// reduced from one read of the state: each workgroup stages a tile (the 2^t
+// amplitudes with fixed non-S bits) in LDS and evaluates every term on it.
+// Per term this is the same sum as k_expval_part over i with bit top(x) = 0
+// of (-1)^{|i & z|} conj(psi_{i^x}) psi_i (real or imaginary part), taken
+// tile by tile; the sign splits into the tile's outside bits and its local
+// bits.
+struct XTileDesc {
+  int t, c, nns;
+  int S[16];      // tile qubits, ascending (S[j] = local bit j)
+  int nonS[48];   // other qubits, ascending
+};
+struct XTileTerms {
+  uint64_t z[kMaxTermsPerLaunch];     // global Z masks (outside bits give the tile parity)
+  uint32_t x[kMaxTermsPerLaunch];     // local X masks
+  uint32_t zloc[kMaxTermsPerLaunch];  // local Z masks
+  int top[kMaxTermsPerLaunch];        // local position of the highest X bit
+  int odd[kMaxTermsPerLaunch];        // imaginary part (odd number of Y)
+};
+
+template <typename T, int TB>
+__global__ __launch_bounds__(kRB) void k_expval_tile(const cpx<T>* __restrict__ psi, XTileDesc d,
+                                                     XTileTerms tt, int nt, uint64_t ntiles,
+                                                     double* __restrict__ part) {
+  __shared__ cpx<T> tile[1 << TB];
+  __shared__ uint64_t segoff[256];
+  __shared__ double sh[kRB];
+  constexpr int A = VecInfo<T>::A;
+  const int t = d.t, c = d.c;
+  const int nseg = 1 << (t - c);
+  for (int h = threadIdx.x; h < nseg; h += kRB) {
+    uint64_t o = 0;
+    for (int j = 0; j < t - c; ++j)
+      if ((h >> j) & 1) o |= 1ull << d.S[c + j];
+    segoff[h] = o;
+  }
+  double acc[kMaxTermsPerLaunch];
+#pragma unroll
+  for (int k = 0; k < kMaxTermsPerLaunch; ++k) acc[k] = 0.0;
+  const vec16<T>* gv = reinterpret_cast<const vec16<T>*>(psi);
+  const int nvec = (1 << t) / A;
+  const uint32_t cmask = (1u << c) - 1u;
+  const int half = 1 << (t - 1);
+  __syncthreads();
+  for (uint64_t tid = blockIdx.x; tid < ntiles; tid += gridDim.x) {
+    uint64_t base = 0;
+    for (int i = 0; i < d.nns; ++i) base |= ((tid >> i) & 1ull) << d.nonS[i];
+    for (int i = threadIdx.x; i < nvec; i += kRB) {
+      const uint32_t l = (uint32_t)i * A;
+      const uint64_t g = base | segoff[l >> c] | (l & cmask);
+      const vec16<T> x = gv[g / A];
+#pragma unroll
+      for (int e = 0; e < A; ++e) tile[l + e] = x.a[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kMaxTermsPerLaunch; ++k) {
+      if (k < nt) {
+        const int pb = __popcll(base & tt.z[k]) & 1;
+        const uint32_t xm = tt.x[k], zl = tt.zloc[k];
+        const int top = tt.top[k];
+        const uint32_t lowm = (1u << top) - 1u;
+        for (int u = threadIdx.x; u < half; u += kRB) {
+          const uint32_t l = (((uint32_t)u >> top) << (top + 1)) | ((uint32_t)u & lowm);
+          const cpx<T> a = tile[l], b = tile[l ^ xm];
+          const double wr = fma((double)b.x, (double)a.x, (double)b.y * (double)a.y);
+          const double wi = fma((double)b.x, (double)a.y, -(double)b.y * (double)a.x);
+          const double w = tt.odd[k] ? wi : wr;
+          acc[k] += ((__popc(l & zl) ^ pb) & 1) ? -w : w;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < nt; ++k) {
+    const double r = block_sum(acc[k], sh);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * nt + k] = r;
+  }
+}
+
+template <typename T>
+int xtile_max_bits() {
+  return sizeof(T) == 4 ? 13 : 12;
+}
+template <typename T>
+int xtile_low_bits() {
+  return sizeof(T) == 4 ? 5 : 4;
+}
+
+// out_dev[k] for terms k < nt (nt <= kMaxTermsPerLaunch) whose X masks lie in
+// the tile qubits S (ascending, S[0..c) = 0..c-1); same values as
+// launch_expval_group for each term.
+template <typename T>
+hipError_t launch_expval_tile(const cpx<T>* psi, int n, const int* S, int t, int c,
+                              const uint64_t* xmask, const uint64_t* zmask, const int* ny, int nt,
+                              double* ws, double* out_dev, hipStream_t st) {
+  if (nt < 1 || nt > kMaxTermsPerLaunch || t < 1 || t > xtile_max_bits<T>() || c > t || t - c > 8 ||
+      (1 << c) < VecInfo<T>::A)
+    return hipErrorInvalidValue;
+  XTileDesc d{};
+  d.t = t;
+  d.c = c;
+  int pos[64];
+  for (int q = 0; q < 64; ++q) pos[q] = -1;
+  uint64_t Smask = 0;
+  for (int j = 0; j < t; ++j) {
+    d.S[j] = S[j];
+    pos[S[j]] = j;
+    Smask |= 1ull << S[j];
+  }
+  for (int q = 0; q < n; ++q)
+    if (!((Smask >> q) & 1)) d.nonS[d.nns++] = q;
+  XTileTerms tt{};
+  auto compress = [&](uint64_t m) {
+    uint32_t r = 0;
+    for (int q = 0; q < n; ++q)
+      if (((m >> q) & 1) && pos[q] >= 0) r |= 1u << pos[q];
+    return r;
+  };
+  for (int k = 0; k < nt; ++k) {
+    if (xmask[k] == 0 || (xmask[k] & ~Smask)) return hipErrorInvalidValue;
+    tt.x[k] = compress(xmask[k]);
+    tt.zloc[k] = compress(zmask[k]);
+    tt.z[k] = zmask[k] & ~Smask;
+    tt.top[k] = 31 - __builtin_clz(tt.x[k]);
+    tt.odd[k] = ny[k] & 1;
+  }
+  const uint64_t ntiles = 1ull << (n - t);
+  const unsigned g = (unsigned)(ntiles < (uint64_t)kMaxPartials ? ntiles : (uint64_t)kMaxPartials);
+  if (sizeof(T) == 4)
+    hipLaunchKernelGGL((k_expval_tile<T, 13>), dim3(g), dim3(kRB), 0, st, psi, d, tt, nt, ntiles, ws);
+  else
+    hipLaunchKernelGGL((k_expval_tile<T, 12>), dim3(g), dim3(kRB), 0, st, psi, d, tt, nt, ntiles, ws);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kRB), 0, st, ws, (int)g, nt, out_dev);
+  return hipGetLastError();
+}
+
 size_t expval_ws_doubles(int n, int nt) {
   (void)n;
   return (size_t)kMaxPartials * (nt < 1 ? 1 : nt);
@@ -179,16 +318,22 @@ constexpr int kSB = 4096;
 template <typename T>
 __global__ __launch_bounds__(kRB) void k_block_sums(const cpx<T>* __restrict__ psi, uint64_t N,
                                                     double* __restrict__ bsum) {
+  // block b = amplitudes [b kSB, (b + 1) kSB), read as coalesced 16-byte
+  // vectors (thread t takes vectors t, t + kRB, ...); the order of the sum
+  // inside a block is free: the shot rescan recomputes its own running sum
   __shared__ double sh[kRB];
-  const uint64_t lo = (uint64_t)blockIdx.x * kSB;
-  constexpr int per = kSB / kRB;  // 16 consecutive amplitudes per thread
+  constexpr int A = VecInfo<T>::A;
+  const vec16<T>* v = reinterpret_cast<const vec16<T>*>(psi);
+  const uint64_t nvec = N / A, v0 = (uint64_t)blockIdx.x * (kSB / A);
   double acc = 0.0;
-  const uint64_t s = lo + (uint64_t)threadIdx.x * per;
-  for (int e = 0; e < per; ++e) {
-    const uint64_t i = s + e;
-    if (i < N) {
-      const cpx<T> a = psi[i];
-      acc += fma((double)a.x, (double)a.x, (double)a.y * (double)a.y);
+#pragma unroll
+  for (int e = 0; e < kSB / A / kRB; ++e) {
+    const uint64_t i = v0 + (uint64_t)e * kRB + threadIdx.x;
+    if (i < nvec) {
+      const vec16<T> x = v[i];
+#pragma unroll
+      for (int q = 0; q < A; ++q)
+        acc += fma((double)x.a[q].x, (double)x.a[q].x, (double)x.a[q].y * (double)x.a[q].y);
     }
   }
   const double r = block_sum(acc, sh);
@@ -329,7 +474,12 @@ hipError_t launch_sample(const cpx<T>* psi, int n, const double* uniforms_dev, i
   template hipError_t launch_expval_group<T>(const cpx<T>*, int, uint64_t, int, const uint64_t*, \
                                              const int*, double*, double*, hipStream_t);      \
   template hipError_t launch_sample<T>(const cpx<T>*, int, const double*, int, double*,       \
-                                       uint64_t*, hipStream_t);
+                                       uint64_t*, hipStream_t);                                   \
+  template hipError_t launch_expval_tile<T>(const cpx<T>*, int, const int*, int, int,             \
+                                            const uint64_t*, const uint64_t*, const int*, int,    \
+                                            double*, double*, hipStream_t);                       \
+  template int xtile_max_bits<T>();                                                              \
+  template int xtile_low_bits<T>();
 QSV_RINST(float)
 QSV_RINST(double)
 

@@ -123,6 +123,28 @@ def test_expval_and_norm(dtype, n):
     s.close()
 
 
+@pytest.mark.parametrize("dtype,n", [("c64", 17), ("c128", 16)])
+def test_expval_tiled_x_terms(dtype, n):
+    """Terms with X masks are reduced tile by tile when their masks fit a
+    tile (more than 16 of them here, so several tiles), the rest one pass per
+    mask; per-term values against the oracle, with Y terms, X masks on high
+    qubits, masks too wide for a tile, and Z-only terms mixed in."""
+    psi0 = start(n, dtype, 900 + n)
+    ham = [(0.3 + 0.01 * q, (("X", q),)) for q in range(n)]
+    ham += [(-0.2, (("X", q), ("Y", q + 1))) for q in range(0, n - 1, 2)]
+    ham += [(0.15, (("Y", q), ("Z", (q + 3) % n))) for q in range(1, n, 3)]
+    ham += [(0.5, tuple(("X", q) for q in range(5, 15)))]                       # 10 high qubits
+    ham += [(0.25, (("Y", 0), ("X", n - 1), ("Z", n // 2)))]
+    ham += [(0.7, (("Z", q), ("Z", q + 1))) for q in range(n - 1)]
+    s = State(n, dtype)
+    s.from_numpy(psi0)
+    terms = s.expval(ham, per_term=True)
+    ref_terms = O.expval(psi0.astype(np.complex128), ham, per_term=True)
+    assert np.abs(np.asarray(terms) - ref_terms).max() <= 10 * TOL[dtype]
+    assert abs(s.expval(ham) - O.expval(psi0.astype(np.complex128), ham)) <= 10 * TOL[dtype] * len(ham)
+    s.close()
+
+
 def test_h2_listing_on_gpu():
     for t0 in qc.h2_sweep()[::7]:
         ops = qc.h2_ansatz(t0)
