@@ -29,10 +29,17 @@ namespace qsv {
 
 template <typename T>
 int tile_max_bits();
+// Default tile width of a single-state plan: the full LDS tile for complex64,
+// the half-size one for complex128, whose lean kernel fits four workgroups
+// per compute unit (measured faster at 28 qubits than the full tile).
+template <typename T>
+static int default_tile_bits() {
+  return sizeof(T) == 4 ? tile_max_bits<T>() : tile_max_bits<T>() - 1;
+}
 template <typename T>
 int tile_reg_bits();
 template <typename T>
-hipError_t launch_tile_pass(cpx<T>* psi, int n, int t, const int32_t* prog_dev, hipStream_t st);
+hipError_t launch_tile_pass(cpx<T>* psi, int n, int t, const int32_t* prog_dev, bool full, hipStream_t st);
 
 using cd = std::complex<double>;
 
@@ -1173,6 +1180,22 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
   return true;
 }
 
+// Whether a pass program uses steps beyond the lean tile body (tables,
+// magnitudes, signs, per-group phases, rotations).
+static bool program_needs_full(const int32_t* pass) {
+  const int t = pass[0], nns = pass[2], nblocks = pass[3];
+  const int32_t* blocks = pass + ((4 + t + nns + 63) & ~63);
+  for (int r = 0; r < nblocks; ++r) {
+    const int32_t* b = blocks + (size_t)r * kRoundWords;
+    int k = b[0] >> 16;
+    for (int l = 0; l < (b[0] & 0xffff); ++l) {
+      if (b[k] & (LT_RAWD | LT_PERM2 | LT_U2 | LT_U1)) return true;
+      k += b[k + 1];
+    }
+  }
+  return false;
+}
+
 // ------------------------------------------------------------- driver
 template <typename T>
 static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const qsv_plan_opts& opts) {
@@ -1186,7 +1209,7 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
     }
     return QSV_OK;
   }
-  int t = opts.tile_qubits > 0 ? opts.tile_qubits : TBMAX;
+  int t = opts.tile_qubits > 0 ? opts.tile_qubits : default_tile_bits<T>();
   if (t > TBMAX) return fail(QSV_ERR_UNSUPPORTED, "tile_qubits exceeds the LDS tile capacity");
   if (t < RB) return fail(QSV_ERR_ARG, "tile_qubits smaller than the register group");
   if (t > n) t = n;
@@ -1245,7 +1268,7 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
       continue;
     }
     QSV_HIP(launch_tile_pass<T>(static_cast<cpx<T>*>(s->psi), n, (int)st.S.size(), dprog + offs[k],
-                                s->stream));
+                                program_needs_full(prog.data() + offs[k]), s->stream));
   }
   return QSV_OK;
 }
@@ -1272,7 +1295,7 @@ qsv_status plan_program(const qsv_state* s, const qsv_op* ops, int n_ops, int ti
   const bool f = s->dt == QSV_C64;
   const int RB = f ? tile_reg_bits<float>() : tile_reg_bits<double>();
   const int TBMAX = f ? tile_max_bits<float>() : tile_max_bits<double>();
-  int t = tile_qubits > 0 ? tile_qubits : TBMAX;
+  int t = tile_qubits > 0 ? tile_qubits : (f ? default_tile_bits<float>() : default_tile_bits<double>());
   if (t > TBMAX || t < RB) return fail(QSV_ERR_ARG, "bad tile_qubits");
   const int n = s->n;
   if (n < RB) return fail(QSV_ERR_UNSUPPORTED, "register smaller than the register group");
@@ -1302,7 +1325,7 @@ qsv_status plan_passes(const qsv_state* s, const qsv_op* ops, int n_ops, int til
   const bool f = s->dt == QSV_C64;
   const int RB = f ? tile_reg_bits<float>() : tile_reg_bits<double>();
   const int TBMAX = f ? tile_max_bits<float>() : tile_max_bits<double>();
-  int t = tile_qubits > 0 ? tile_qubits : TBMAX;
+  int t = tile_qubits > 0 ? tile_qubits : (f ? default_tile_bits<float>() : default_tile_bits<double>());
   if (t > TBMAX || t < RB) return fail(QSV_ERR_ARG, "bad tile_qubits");
   const int n = s->n;
   if (t > n) t = n;

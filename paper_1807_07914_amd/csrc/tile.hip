@@ -97,6 +97,16 @@ __device__ __forceinline__ void scale1(cpx<T>& x, T c) {
   x.y = fma(c, x.y, x.y);
 }
 
+// x <- -x if the uniform mask is the sign bit (1 << 31), else x
+__device__ __forceinline__ void flip_sign(cpx<float>& x, uint32_t s) {
+  x.x = __int_as_float(__float_as_int(x.x) ^ (int)s);
+  x.y = __int_as_float(__float_as_int(x.y) ^ (int)s);
+}
+__device__ __forceinline__ void flip_sign(cpx<double>& x, uint32_t s) {
+  x.x = __hiloint2double(__double2hiint(x.x) ^ (int)s, __double2loint(x.x));
+  x.y = __hiloint2double(__double2hiint(x.y) ^ (int)s, __double2loint(x.y));
+}
+
 // x <- exp(i phi) x as three shears of (re, im): p = -tan(phi/2), q = sin(phi)
 template <typename T>
 __device__ __forceinline__ void phase_shears(cpx<T>& x, T p, T q) {
@@ -132,35 +142,24 @@ __device__ __forceinline__ void shears(cpx<T> (&a)[1 << RB], T p, T q, bool thre
 }
 
 // Table step: amplitude m times sign(m) exp(i phi_m); (p_m, q_m) at entries
-// 2m, 2m + 1 of table line tl, the sign as bit m of sm.  The entries are read
-// into scalar registers a few at a time under the line switch, and the
-// amplitudes are updated outside it (updates inside the switch cases would be
-// merged from four paths, which costs a copy of every amplitude).
+// 2m, 2m + 1 of the table line tp (a line of the round block in memory), the
+// sign as bit m of sm.  The entries are uniform: scalar loads bring them into
+// SGPRs, with no vector instruction per entry.
 template <typename T, int RB>
-__device__ __forceinline__ void table_step(cpx<T> (&a)[1 << RB], const Blk& b, int tl, uint32_t sm) {
+__device__ __forceinline__ void table_step(cpx<T> (&a)[1 << RB], const int32_t* __restrict__ tp, uint32_t sm) {
   constexpr int W = WordsPer<T>::W;
-  constexpr int CH = 8 / W;  // entries (p, q pairs) per chunk: 16 words
 #pragma unroll
-  for (int m0 = 0; m0 < (1 << RB); m0 += CH) {
-    int wv[16];
-    b.on_table_line(tl, [&](int v) {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) wv[e] = rl(v, 2 * W * m0 + e);
-    });
-#pragma unroll
-    for (int e = 0; e < CH; ++e) {
-      const int m = m0 + e;
-      T pm, qm;
-      if constexpr (W == 1) {
-        pm = __int_as_float(wv[2 * e]);
-        qm = __int_as_float(wv[2 * e + 1]);
-      } else {
-        pm = __hiloint2double(wv[4 * e + 1], wv[4 * e]);
-        qm = __hiloint2double(wv[4 * e + 3], wv[4 * e + 2]);
-      }
-      phase_shears(a[m], pm, qm);
-      if ((sm >> m) & 1u) scale1(a[m], T(-2));
+  for (int m = 0; m < (1 << RB); ++m) {
+    T pm, qm;
+    if constexpr (W == 1) {
+      pm = __int_as_float(tp[2 * m]);
+      qm = __int_as_float(tp[2 * m + 1]);
+    } else {
+      pm = __hiloint2double(tp[4 * m + 1], tp[4 * m]);
+      qm = __hiloint2double(tp[4 * m + 3], tp[4 * m + 2]);
     }
+    phase_shears(a[m], pm, qm);
+    flip_sign(a[m], ((sm >> m) & 1u) << 31);
   }
 }
 
@@ -298,8 +297,11 @@ struct TileIO {
 
 // One fused tile pass over tile `tid` of the pass program `prog`; returns the
 // thread's partial of the Z-string sum (0 unless io.reduce).  Ends with a
-// barrier so that the caller can start another tile at once.
-template <typename T, int TBMAX, int RB>
+// barrier so that the caller can start another tile at once.  FULL = false
+// compiles only the table, magnitude, sign, per-group phase and rotation
+// steps (the host uses it for passes without the other steps): far fewer
+// registers, so that more workgroups share a compute unit.
+template <typename T, int TBMAX, int RB, bool FULL>
 __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int32_t* __restrict__ prog,
                                             uint64_t tid, const TileIO& io) {
   constexpr int A = VecInfo<T>::A;
@@ -362,6 +364,7 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
   char* const tb = reinterpret_cast<char*>(tile);
   for (int r = 0; r < nrounds; ++r) {
     const Blk b = nb;
+    const int32_t* bp = blocks + (size_t)r * kRoundWords;
     if (r + 1 < nrounds) {  // prefetch the next round's block
       const int32_t* nbp = blocks + (size_t)(r + 1) * kRoundWords;
 #pragma unroll
@@ -379,10 +382,21 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
         fm ^= low;
       }
       const uint32_t sgb = tile_swizzle(lg, SB) * (uint32_t)sizeof(cpx<T>);
-      cpx<T> a[NR];
+      // The LDS offset of combination m is the XOR of the offsets of its
+      // register bits (deposit and swizzle are XOR-linear): walking m in
+      // Gray-code order takes one XOR per amplitude.
+      uint32_t bofs[RB];
 #pragma unroll
-      for (int m = 0; m < NR; ++m)
-        a[m] = *reinterpret_cast<const cpx<T>*>(tb + (sgb ^ (uint32_t)rl(b.l[0], 2 + m)));
+      for (int j = 0; j < RB; ++j) bofs[j] = (uint32_t)rl(b.l[0], 2 + (1 << j));
+      cpx<T> a[NR];
+      {
+        uint32_t ad = sgb;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          if (i > 0) ad ^= bofs[__builtin_ctz(i)];
+          a[i ^ (i >> 1)] = *reinterpret_cast<const cpx<T>*>(tb + ad);
+        }
+      }
 
       int k = w0 >> 16;
       for (int o = 0; o < nlayers; ++o) {
@@ -392,7 +406,7 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
           const int tl = b.word(p);
           const uint32_t sm = (uint32_t)b.word(p + 1);
           p += 2;
-          table_step<T, RB>(a, b, tl, sm);
+          table_step<T, RB>(a, bp + 64 * tl, sm);
         }
         if (flags & LT_MAG) {
 #pragma unroll
@@ -447,7 +461,7 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
             }
           }
         }
-        if (flags & LT_RAWD) {
+        if (FULL && (flags & LT_RAWD)) {
           // a diagonal factor d = (1 + c) exp(i phi) per operand value, as
           // (p, q, c) triples: PHASE1 two (by the qubit's bit), DIAG2 four
           const int type = b.word(p), ka = b.word(p + 1), va = b.word(p + 2);
@@ -489,11 +503,11 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
         QSV_ROT(3)
         QSV_ROT(4)
 #undef QSV_ROT
-        if (flags & LT_PERM2) {
+        if (FULL && (flags & LT_PERM2)) {
           dispatch_perm2<T, RB>(a, b.word(p), b.word(p + 1), b.word(p + 2));
           p += 3;
         }
-        if (flags & LT_U2) {
+        if (FULL && (flags & LT_U2)) {
           const int j0 = b.word(p), j1 = b.word(p + 1);
           M4<T> U;
 #pragma unroll
@@ -502,7 +516,7 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
           p += 2 + 32 * WT;
           dispatch_u2<T, RB>(a, j0, j1, U);
         }
-        if (flags & LT_U1) {
+        if (FULL && (flags & LT_U1)) {
           const int j = b.word(p);
           M2<T> U;
 #pragma unroll
@@ -512,9 +526,17 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
         }
         k += len;
       }
+      {
+        // recomputed rather than kept from the load walk: 2^RB live
+        // addresses would cost as many registers
+        uint32_t ad = sgb;
+        asm volatile("" : "+v"(ad));
 #pragma unroll
-      for (int m = 0; m < NR; ++m)
-        *reinterpret_cast<cpx<T>*>(tb + (sgb ^ (uint32_t)rl(b.l[0], 2 + m))) = a[m];
+        for (int i = 0; i < NR; ++i) {
+          if (i > 0) ad ^= bofs[__builtin_ctz(i)];
+          *reinterpret_cast<cpx<T>*>(tb + ad) = a[i ^ (i >> 1)];
+        }
+      }
     }
     __syncthreads();
   }
@@ -551,11 +573,11 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
   return acc;
 }
 
-template <typename T, int TBMAX, int RB>
-__global__ __launch_bounds__(kTileThreads, 2) void k_tile(cpx<T>* __restrict__ psi,
-                                                        const int32_t* __restrict__ prog) {
+template <typename T, int TBMAX, int RB, bool FULL, int MINWG>
+__global__ __launch_bounds__(kTileThreads, MINWG) void k_tile(cpx<T>* __restrict__ psi,
+                                                              const int32_t* __restrict__ prog) {
   const TileIO io{0, 1, 0, nullptr, nullptr, 0};
-  (void)tile_body<T, TBMAX, RB>(psi, prog, blockIdx.x, io);
+  (void)tile_body<T, TBMAX, RB, FULL>(psi, prog, blockIdx.x, io);
 }
 
 // ------------------------------------------------------------ batches
@@ -605,7 +627,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_batch(cpx<T>* __restrict__ 
       const uint64_t ntiles = 1ull << (w - t);
       const TileIO io{p == 0, p + 1 < np, p + 1 == np, zt + t0, ct + t0, (int)nt};
       for (uint64_t tid = 0; tid < ntiles; ++tid)
-        acc += tile_body<T, TBMAX, RB>(scratch + soff, prog, tid, io);
+        acc += tile_body<T, TBMAX, RB, true>(scratch + soff, prog, tid, io);
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -641,11 +663,20 @@ int tile_swizzle_bits() {
   return SwzBits<T>::B;
 }
 
+// Tiles of up to 2^12 complex64 / 2^11 complex128 amplitudes use a half-size
+// LDS buffer; with the lean body three workgroups then share a compute unit.
 template <typename T>
-hipError_t launch_tile_pass(cpx<T>* psi, int n, int t, const int32_t* prog_dev, hipStream_t st) {
+hipError_t launch_tile_pass(cpx<T>* psi, int n, int t, const int32_t* prog_dev, bool full, hipStream_t st) {
+  constexpr int TB = TileCfg<T>::TBMAX, RB = TileCfg<T>::RB;
   const uint64_t ntiles = 1ull << (n - t);
-  hipLaunchKernelGGL((k_tile<T, TileCfg<T>::TBMAX, TileCfg<T>::RB>), dim3((unsigned)ntiles),
-                     dim3(kTileThreads), 0, st, psi, prog_dev);
+  const dim3 grid((unsigned)ntiles), block(kTileThreads);
+  if (t <= TB - 1) {
+    if (full) hipLaunchKernelGGL((k_tile<T, TB - 1, RB, true, 2>), grid, block, 0, st, psi, prog_dev);
+    else hipLaunchKernelGGL((k_tile<T, TB - 1, RB, false, 3>), grid, block, 0, st, psi, prog_dev);
+  } else {
+    if (full) hipLaunchKernelGGL((k_tile<T, TB, RB, true, 2>), grid, block, 0, st, psi, prog_dev);
+    else hipLaunchKernelGGL((k_tile<T, TB, RB, false, 2>), grid, block, 0, st, psi, prog_dev);
+  }
   return hipGetLastError();
 }
 
@@ -671,7 +702,7 @@ template int tile_reg_bits<float>();
 template int tile_reg_bits<double>();
 template int tile_swizzle_bits<float>();
 template int tile_swizzle_bits<double>();
-template hipError_t launch_tile_pass<float>(cpx<float>*, int, int, const int32_t*, hipStream_t);
-template hipError_t launch_tile_pass<double>(cpx<double>*, int, int, const int32_t*, hipStream_t);
+template hipError_t launch_tile_pass<float>(cpx<float>*, int, int, const int32_t*, bool, hipStream_t);
+template hipError_t launch_tile_pass<double>(cpx<double>*, int, int, const int32_t*, bool, hipStream_t);
 
 }  // namespace qsv

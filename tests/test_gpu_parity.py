@@ -246,9 +246,12 @@ def test_fused_random_circuits(dtype, n, tile):
     assert np.abs(got - ref).max() <= TOL[dtype]
 
 
+@pytest.mark.parametrize("small_tile", [False, True])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("family", ["brickwork", "rounds", "qft", "hea", "rotring", "ghz"])
-def test_fused_families(dtype, family):
+def test_fused_families(dtype, family, small_tile):
+    # small_tile: 2^12 (complex64) / 2^11 (complex128) tiles, which run on the
+    # half-size LDS kernels (lean or full by the pass's steps)
     n = 16
     rng = np.random.default_rng(5)
     x0 = 0
@@ -268,8 +271,9 @@ def test_fused_families(dtype, family):
     ref = O.run(ops, n, x0=x0)
     s = State(n, dtype)
     s.set_basis(x0)
-    info = s.plan_info(ops)
-    s.apply_circuit(ops, mode="fused")
+    tile = (12 if dtype == "c64" else 11) if small_tile else 0
+    info = s.plan_info(ops, tile_qubits=tile)
+    s.apply_circuit(ops, mode="fused", tile_qubits=tile)
     got = s.to_numpy()
     s.close()
     assert info["passes"] < len(ops)
