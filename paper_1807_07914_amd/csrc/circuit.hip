@@ -230,38 +230,58 @@ static std::shared_ptr<Schedule> build_schedule(const std::vector<POp>& P, int n
       if ((Smask >> q) & 1) st.S.push_back(q);
     std::vector<int> lpos(n, -1);
     for (int j = 0; j < (int)st.S.size(); ++j) lpos[st.S[j]] = j;
-    // rounds: greedy in program order over register-bit sets of size RB
-    uint64_t R = 0;
-    Round cur;
-    bool open = false;
-    for (int i : take) {
-      const POp& o = P[i];
-      if (o.kind == PK_U1 || o.kind == PK_U2) {
-        uint64_t B = 0;
-        for (int j = 0; j < o.nq; ++j) B |= 1ull << lpos[o.q[j]];
-        if (open && __builtin_popcountll(R | B) > RB) {
-          st.rounds.push_back(cur);
-          cur = Round();
-          R = 0;
-        }
-        R |= B;
-        open = true;
-        cur.ops.push_back(i);
-        // remember R in cur (finalised below)
-        int k = 0;
-        for (int b = 0; b < 64 && k < 8; ++b)
-          if ((R >> b) & 1) cur.R[k++] = b;
-        for (; k < 8; ++k) cur.R[k] = -1;
-      } else {
-        if (!open) {
+    // Rounds are chosen like passes, one level down: a register set of RB
+    // tile qubits (starting from the first queued non-diagonal op, grown
+    // greedily by the number of ops the dependency scan can then apply),
+    // and every op the scan admits for it, in program order.  Diagonal ops
+    // run in whichever round reaches them.  Taking every admissible op,
+    // rather than cutting rounds in program order, lets a round apply
+    // several layers of gates and merge runs of 2x2 gates on one qubit.
+    {
+      std::vector<int> rem(take);
+      while (!rem.empty()) {
+        uint64_t Rg = 0;  // register qubits (global mask)
+        for (int i : rem)
+          if (P[i].nondiag()) {
+            Rg = P[i].qmask;
+            break;
+          }
+        if (Rg == 0) {  // only diagonal ops left: one round takes them all
+          Round cur;
           for (int k = 0; k < 8; ++k) cur.R[k] = -1;
-          open = true;
+          cur.ops = rem;
+          st.rounds.push_back(cur);
+          break;
         }
-        cur.ops.push_back(i);
+        const int want = std::min(RB, (int)st.S.size());
+        while (__builtin_popcountll(Rg) < want) {
+          int best = -1, bs = -1;
+          for (int q : st.S) {
+            if ((Rg >> q) & 1) continue;
+            const int sc = scan(P, rem, Rg | (1ull << q), allq, nullptr);
+            if (sc > bs) {
+              best = q;
+              bs = sc;
+            }
+          }
+          Rg |= 1ull << best;
+        }
+        Round cur;
+        scan(P, rem, Rg, allq, &cur.ops);
+        int k = 0;
+        for (int j = 0; j < (int)st.S.size() && k < 8; ++j)
+          if ((Rg >> st.S[j]) & 1) cur.R[k++] = j;
+        for (; k < 8; ++k) cur.R[k] = -1;
+        std::vector<char> in(P.size(), 0);
+        for (int i : cur.ops) in[i] = 1;
+        std::vector<int> left;
+        for (int i : rem)
+          if (!in[i]) left.push_back(i);
+        rem.swap(left);
+        st.rounds.push_back(std::move(cur));
       }
-      done[i] = 1;
+      for (int i : take) done[i] = 1;
     }
-    if (open) st.rounds.push_back(cur);
     // pad every round's register set to exactly RB distinct local bits
     for (Round& r : st.rounds) {
       uint64_t used = 0;
@@ -401,13 +421,17 @@ int tile_swizzle_bits();
 // rotations, and a per-group factor for qubits that are not register bits.
 struct Split {
   int kind;         // 0 diagonal (d0, d1 carry the whole gate), 1 rotation, -1 no factorisation
-  int form;         // 1: three shears (the only form emitted)
+  int form;         // 0: two shears and a carried scale, 1: three shears
   double p, q;      // shear coefficients
   cd d0, d1;        // diagonal factor after the rotation (carried)
   cd r1;            // diagonal factor diag(1, r1) before the rotation
 };
 
 static cd unit_phase(cd z) { return z / std::abs(z); }
+
+// Smallest cos(theta) of a rotation applied as two shears: the carried scale
+// and the first shear's coefficient stay within a factor 1 / 0.3 of 1.
+constexpr double kTwoShearMinCos = 0.3;
 
 static Split split_u1(const cd* u) {
   Split sp{-1, 0, 0.0, 0.0, cd(1.0), cd(1.0), cd(1.0)};
@@ -441,12 +465,24 @@ static Split split_u1(const cd* u) {
     if (std::abs(v[e] - u[e]) > 1e-12 * std::sqrt(k2)) return sp;
   sp.kind = 1;
   sp.r1 = r1;
-  // unit rotation by theta in [0, pi/2] as three shears
-  sp.form = 1;
-  sp.p = -s / (kap + c);  // -tan(theta / 2)
-  sp.q = s / kap;         // sin(theta)
-  sp.d0 = kap * l0;
-  sp.d1 = kap * l1;
+  // Unit rotation by theta in [0, pi/2].  Two shears (p = -tan(theta),
+  // q = sin(theta) cos(theta)) give it up to the scale diag(1/cos, cos)
+  // applied after it, which joins the carried factor; when cos(theta) is
+  // small that scale and p grow, and three shears (p = -tan(theta / 2),
+  // q = sin(theta)) give the rotation exactly.
+  if (c >= kTwoShearMinCos * kap) {
+    sp.form = 0;
+    sp.p = -s / c;
+    sp.q = c * s / (kap * kap);
+    sp.d0 = c * l0;
+    sp.d1 = (kap * kap / c) * l1;
+  } else {
+    sp.form = 1;
+    sp.p = -s / (kap + c);
+    sp.q = s / kap;
+    sp.d0 = kap * l0;
+    sp.d1 = kap * l1;
+  }
   return sp;
 }
 
@@ -763,15 +799,11 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
         }
         work.push_back(w);
       } else if (o.sign) {
-        if (!work.empty() && work.back().type == TOP_SIGN) {
-          work.back().signs.push_back(i);
-        } else {
-          W w;
-          w.type = TOP_SIGN;
-          w.op = i;
-          w.signs.push_back(i);
-          work.push_back(w);
-        }
+        W w;
+        w.type = TOP_SIGN;
+        w.op = i;
+        w.signs.push_back(i);
+        work.push_back(w);
       } else {
         W w;
         w.type = o.kind == PK_D1 ? TOP_PHASE1 : TOP_DIAG2;
@@ -780,6 +812,46 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
       }
     }
 
+    // Order the work by depth: a non-diagonal item runs one level after the
+    // latest item on its register bits, a diagonal item in the gap right
+    // after the last non-diagonal item on its register bits.  Items on
+    // different qubits commute and each qubit keeps its own order, so the
+    // result is unchanged, while a layer can now hold every rotation of one
+    // level instead of breaking at each diagonal op in between.
+    {
+      int lastN[8] = {0}, lastD[8] = {0};
+      std::vector<int> key(work.size()), ord(work.size());
+      for (size_t k = 0; k < work.size(); ++k) {
+        const W& w = work[k];
+        ord[k] = (int)k;
+        if (w.type == TOP_U1 || w.type == TOP_U2 || w.type == TOP_PERM2) {
+          int L = 0;
+          for (int j : {w.j0, w.j1})
+            if (j >= 0) L = std::max(L, std::max(lastN[j], lastD[j]));
+          ++L;
+          for (int j : {w.j0, w.j1})
+            if (j >= 0) lastN[j] = L;
+          key[k] = 2 * L;
+        } else {
+          const POp& o = P[w.op];
+          int gap = 0;
+          for (int e = 0; e < o.nq; ++e) {
+            const int p = lpos[o.q[e]];
+            if (p >= 0 && regof[p] >= 0) gap = std::max(gap, lastN[regof[p]]);
+          }
+          for (int e = 0; e < o.nq; ++e) {
+            const int p = lpos[o.q[e]];
+            if (p >= 0 && regof[p] >= 0) lastD[regof[p]] = std::max(lastD[regof[p]], gap);
+          }
+          key[k] = 2 * gap + 1;
+        }
+      }
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key[a] < key[b]; });
+      std::vector<W> sorted;
+      sorted.reserve(work.size());
+      for (int k : ord) sorted.push_back(std::move(work[k]));
+      work.swap(sorted);
+    }
 
     for (const W& w : work) {
       if (w.type == TOP_U1) {
@@ -967,10 +1039,9 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
     for (const Layer& L : layers) {
       DGroup empty_group;
       DGroup& g = L.group >= 0 ? rp.g[L.group] : empty_group;
-      // the diagonal table: unit phases with a sign pattern, magnitudes apart
-      bool tab = false, mag = false;
-      uint32_t smask = 0;
-      std::vector<int32_t> tline, mline;
+      // the diagonal table: one complex factor per register combination
+      bool tab = false;
+      std::vector<int32_t> tline;
       if (g.tab) {
         for (int m = 0; m < NR; ++m)
           if ((g.Mrr >> m) & 1) g.tb[m] = -g.tb[m];
@@ -981,16 +1052,8 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
         if (!ident) {
           tab = true;
           for (int m = 0; m < NR; ++m) {
-            const double r = std::abs(g.tb[m]);  // > 0: tables hold invertible factors only
-            cd u = g.tb[m] / r;
-            if (u.real() < 0.0) {
-              u = -u;
-              smask |= 1u << m;
-            }
-            if (std::abs(r - 1.0) > 1e-15) mag = true;
-            BlockWriter<T>::real_words(-u.imag() / (1.0 + u.real()), tline);
-            BlockWriter<T>::real_words(u.imag(), tline);
-            BlockWriter<T>::real_words(r - 1.0, mline);
+            BlockWriter<T>::real_words(g.tb[m].real(), tline);
+            BlockWriter<T>::real_words(g.tb[m].imag(), tline);
           }
         }
       }
@@ -1058,8 +1121,7 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
         std::vector<int32_t> w;
       };
       std::vector<Blob> blobs;
-      if (tab) blobs.push_back({LT_TAB, {0, (int32_t)smask}});  // line filled in at packing
-      if (mag) blobs.push_back({LT_MAG, mline});
+      if (tab) blobs.push_back({LT_TAB, {0}});  // line filled in at packing
       if (sign) {
         // the sign lists compose by XOR: long ones are split over several steps
         std::vector<std::pair<int, uint32_t>> fm = g.fmix, rc = g.rcmix;
@@ -1135,7 +1197,6 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
       // step kinds in application order (rotations: one kind per register bit)
       auto order = [](int32_t flag) {
         if (flag & LT_TAB) return 0;
-        if (flag & LT_MAG) return 1;
         if (flag & LT_SIGN) return 2;
         if (flag & LT_PHASEL) return 3;
         if (flag & LT_RAWD) return 4;

@@ -97,14 +97,27 @@ __device__ __forceinline__ void scale1(cpx<T>& x, T c) {
   x.y = fma(c, x.y, x.y);
 }
 
-// x <- -x if the uniform mask is the sign bit (1 << 31), else x
-__device__ __forceinline__ void flip_sign(cpx<float>& x, uint32_t s) {
-  x.x = __int_as_float(__float_as_int(x.x) ^ (int)s);
-  x.y = __int_as_float(__float_as_int(x.y) ^ (int)s);
+// x <- z x for the complex factor z = (zr, zi), in place: four ALU ops and
+// one temporary.  Written as one asm block so that the products land in the
+// amplitude's own registers (left to itself the compiler ties the last FMA
+// to the temporary and copies every amplitude back).
+__device__ __forceinline__ void cmul(cpx<float>& x, float zr, float zi) {
+  float t;
+  asm("v_mul_f32 %2, %4, %1\n\t"
+      "v_mul_f32 %1, %3, %1\n\t"
+      "v_fmac_f32 %1, %4, %0\n\t"
+      "v_fma_f32 %0, %3, %0, -%2"
+      : "+v"(x.x), "+v"(x.y), "=&v"(t)
+      : "s"(zr), "s"(zi));
 }
-__device__ __forceinline__ void flip_sign(cpx<double>& x, uint32_t s) {
-  x.x = __hiloint2double(__double2hiint(x.x) ^ (int)s, __double2loint(x.x));
-  x.y = __hiloint2double(__double2hiint(x.y) ^ (int)s, __double2loint(x.y));
+__device__ __forceinline__ void cmul(cpx<double>& x, double zr, double zi) {
+  double t;
+  asm("v_mul_f64 %2, %4, %1\n\t"
+      "v_mul_f64 %1, %3, %1\n\t"
+      "v_fma_f64 %1, %4, %0, %1\n\t"
+      "v_fma_f64 %0, %3, %0, -%2"
+      : "+v"(x.x), "+v"(x.y), "=&v"(t)
+      : "s"(zr), "s"(zi));
 }
 
 // x <- exp(i phi) x as three shears of (re, im): p = -tan(phi/2), q = sin(phi)
@@ -146,20 +159,19 @@ __device__ __forceinline__ void shears(cpx<T> (&a)[1 << RB], T p, T q, bool thre
 // sign as bit m of sm.  The entries are uniform: scalar loads bring them into
 // SGPRs, with no vector instruction per entry.
 template <typename T, int RB>
-__device__ __forceinline__ void table_step(cpx<T> (&a)[1 << RB], const int32_t* __restrict__ tp, uint32_t sm) {
+__device__ __forceinline__ void table_step(cpx<T> (&a)[1 << RB], const int32_t* __restrict__ tp) {
   constexpr int W = WordsPer<T>::W;
 #pragma unroll
   for (int m = 0; m < (1 << RB); ++m) {
-    T pm, qm;
+    T zr, zi;
     if constexpr (W == 1) {
-      pm = __int_as_float(tp[2 * m]);
-      qm = __int_as_float(tp[2 * m + 1]);
+      zr = __int_as_float(tp[2 * m]);
+      zi = __int_as_float(tp[2 * m + 1]);
     } else {
-      pm = __hiloint2double(tp[4 * m + 1], tp[4 * m]);
-      qm = __hiloint2double(tp[4 * m + 3], tp[4 * m + 2]);
+      zr = __hiloint2double(tp[4 * m + 1], tp[4 * m]);
+      zi = __hiloint2double(tp[4 * m + 3], tp[4 * m + 2]);
     }
-    phase_shears(a[m], pm, qm);
-    flip_sign(a[m], ((sm >> m) & 1u) << 31);
+    cmul(a[m], zr, zi);
   }
 }
 
@@ -402,17 +414,7 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
       for (int o = 0; o < nlayers; ++o) {
         const int flags = b.word(k), len = b.word(k + 1);
         int p = k + 2;
-        if (flags & LT_TAB) {
-          const int tl = b.word(p);
-          const uint32_t sm = (uint32_t)b.word(p + 1);
-          p += 2;
-          table_step<T, RB>(a, bp + 64 * tl, sm);
-        }
-        if (flags & LT_MAG) {
-#pragma unroll
-          for (int m = 0; m < NR; ++m) scale1(a[m], b.real<T>(p + m * WT));
-          p += NR * WT;
-        }
+        if (flags & LT_TAB) table_step<T, RB>(a, bp + 64 * b.word(p++));
         if (flags & LT_SIGN) {
           uint32_t neg = (uint32_t)b.word(p++);
           const int nf = b.word(p++);

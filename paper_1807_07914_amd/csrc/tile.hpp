@@ -26,12 +26,10 @@
 //                 lines 0 and 1; lines kTableLine0 .. kRoundLines-1 hold tables.
 //   layer       : flags, n_words, then the payload of every step present,
 //                 in this order (all steps are optional):
-//     LT_TAB    : table line, sign mask.  Amplitude m is multiplied by
-//                 sign(m) * exp(i phi_m): the rotation of (re, im) by phi_m,
-//                 |phi_m| <= pi/2, as three shears x += p y; y += q x; x += p y
-//                 with (p_m, q_m) = (-tan(phi_m / 2), sin(phi_m)) at entry m
-//                 of the table line (one word per float, two per double).
-//     LT_MAG    : c_m for every m: amplitude m multiplied by (1 + c_m).
+//     LT_TAB    : table line.  Amplitude m is multiplied by the complex
+//                 factor z_m = (re, im) at entry m of the table line (two
+//                 words per entry for float, four for double): phases,
+//                 signs and magnitudes of diagonal factors on register bits.
 //     LT_SIGN   : Mrr, nf, (f, mask)*nf, nd, (d, M)*nd, zfree,
 //                 nrc, (q, mask)*nrc, nfc, (q, f)*nfc, ncc, (qa, qb)*ncc
 //                 negation pattern over m:  Mrr ^ [mask for every free bit f
@@ -49,9 +47,14 @@
 //                 RAW_DIAG2  : kindA, valA, kindB, valB, f[4]  factor f[bitA + 2 bitB]
 //                 each factor (1 + c) exp(i phi) stored as p, q, c
 //                 (p = -tan(phi / 2), q = sin(phi), |phi| <= pi/2)
-//     rotations : for every flagged register bit j, ascending: p, q.  Real
-//                 rotation as in-place shears x0 += p x1, x1 += q x0, and a
-//                 third x0 += p x1 when the three-shear flag of j is set.
+//     rotations : for every flagged register bit j, ascending: p, q.
+//                 In-place shears x0 += p x1, x1 += q x0 on the amplitude
+//                 pairs of bit j, and a third x0 += p x1 when the three-shear
+//                 flag of j is set.  Three shears with p = -tan(theta / 2),
+//                 q = sin(theta) are the rotation by theta; two shears with
+//                 p = -tan(theta), q = sin(theta) cos(theta) are
+//                 diag(1 / cos(theta), cos(theta)) applied after that
+//                 rotation, a scale the planner takes out in a later table.
 //     LT_PERM2  : j0, j1, code     CNOT / SWAP as a register permutation on
 //                 bits j0 < j1 (m = b0 + 2 b1): code 0 swaps m = 1 <-> 3
 //                 (CNOT, control j0), 1 swaps 2 <-> 3 (CNOT, control j1),
@@ -75,7 +78,6 @@ namespace qsv {
 
 enum LayerFlag : int32_t {
   LT_TAB = 1 << 0,
-  LT_MAG = 1 << 1,
   LT_SIGN = 1 << 2,
   LT_PHASEL = 1 << 3,
   LT_RAWD = 1 << 4,

@@ -21,7 +21,7 @@ LINES = 8
 ROUND_WORDS = 64 * LINES
 TABLE_LINE0 = 2
 LAYER_WORDS = 128
-LT_TAB, LT_MAG, LT_SIGN, LT_PHASEL, LT_RAWD = 1, 2, 4, 8, 16
+LT_TAB, LT_SIGN, LT_PHASEL, LT_RAWD = 1, 4, 8, 16
 LT_ROT0, LT_SHEAR3 = 1 << 8, 1 << 16
 LT_PERM2, LT_U2, LT_U1 = 1 << 24, 1 << 25, 1 << 26
 RAW_PHASE1, RAW_DIAG2 = 4, 5
@@ -137,21 +137,14 @@ def run_pass(psi, n, words, off, cfg):
                     assert ln >= 2 and k + ln <= ROUND_WORDS
                     p = k + 2
                     if flags & LT_TAB:
-                        tl, sm = blk[p], blk[p + 1] & 0xffffffff
-                        p += 2
+                        tl = blk[p]
+                        p += 1
                         assert TABLE_LINE0 <= tl < LINES
                         low_table = min(low_table, tl)
                         for m in range(NR):
-                            pm = _real(blk, 64 * tl + 2 * m * WT, WT)
-                            qm = _real(blk, 64 * tl + (2 * m + 1) * WT, WT)
-                            assert abs(pm) <= 1.0 + 1e-12 and abs(qm) <= 1.0 + 1e-12
-                            a[m] = _shear3(a[m], pm, qm)
-                            if (sm >> m) & 1:
-                                a[m] = -a[m]
-                    if flags & LT_MAG:
-                        for m in range(NR):
-                            a[m] *= 1.0 + _real(blk, p + m * WT, WT)
-                        p += NR * WT
+                            zr = _real(blk, 64 * tl + 2 * m * WT, WT)
+                            zi = _real(blk, 64 * tl + (2 * m + 1) * WT, WT)
+                            a[m] = a[m] * complex(zr, zi)
                     if flags & LT_SIGN:
                         neg = blk[p] & 0xffffffff; p += 1
                         nf = blk[p]; p += 1
@@ -226,8 +219,13 @@ def run_pass(psi, n, words, off, cfg):
                         if flags & (LT_ROT0 << j):
                             p_, q_ = _real(blk, p, WT), _real(blk, p + WT, WT)
                             p += 2 * WT
-                            assert abs(p_) <= 1.0 + 1e-12 and abs(q_) <= 1.0 + 1e-12
                             three = bool(flags & (LT_SHEAR3 << j))
+                            # three shears: |tan(theta/2)|, |sin(theta)| <= 1;
+                            # two: |tan(theta)| <= 3.2 (cos >= 0.3), |sin cos| <= 1/2
+                            if three:
+                                assert abs(p_) <= 1.0 + 1e-6 and abs(q_) <= 1.0 + 1e-6, (p_, q_, flags)
+                            else:
+                                assert abs(p_) <= 3.2 and abs(q_) <= 0.5 + 1e-6
                             for m in range(NR):
                                 if not (m >> j) & 1:
                                     m2 = m | (1 << j)
@@ -331,13 +329,13 @@ def emulate_batch_job(dtype, words, passoff, job):
     return psi
 
 
-STEP_NAMES = [(LT_TAB, "TAB"), (LT_MAG, "MAG"), (LT_SIGN, "SIGN"), (LT_PHASEL, "PHASEL"),
+STEP_NAMES = [(LT_TAB, "TAB"), (LT_SIGN, "SIGN"), (LT_PHASEL, "PHASEL"),
               (LT_RAWD, "RAWD"), (LT_PERM2, "PERM2"), (LT_U2, "U2"), (LT_U1, "U1")]
 
 
 def op_counts(words, steps, dtype):
     """Number of layers, blocks and steps of each kind in a plan's tile
-    programs ('ROT' counts rotations)."""
+    programs ('ROT' counts rotations, 'ROT3' those made of three shears)."""
     RB = CFG[dtype]["RB"]
     out = {}
 
@@ -361,5 +359,6 @@ def op_counts(words, steps, dtype):
                     if flags & bitv:
                         add(name)
                 add("ROT", bin((flags >> 8) & ((1 << RB) - 1)).count("1"))
+                add("ROT3", bin((flags >> 16) & ((1 << RB) - 1)).count("1"))
                 k += int(blk[k + 1])
     return out
