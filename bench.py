@@ -285,7 +285,7 @@ def main():
                                "seed 1002, complex64, fused tile passes, + expval/norm/1024 samples" % n,
                    "qubits": n, "gates": len(ops), "passes": plan["passes"]},
         "hbm_gbs_tile_pass": hbm_gbs,
-        "roofline": {"bound": "alu", "kernel": "k_tile<float,13,5>",
+        "roofline": {"bound": "alu", "kernel": "k_tile_pipe<float,13,5>",
                      "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic,

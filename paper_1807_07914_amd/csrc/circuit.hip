@@ -29,17 +29,18 @@ namespace qsv {
 
 template <typename T>
 int tile_max_bits();
-// Default tile width of a single-state plan: the full LDS tile for complex64,
-// the half-size one for complex128, whose lean kernel fits four workgroups
-// per compute unit (measured faster at 28 qubits than the full tile).
+// Default tile width of a single-state plan: the full LDS tile, whose lean
+// passes run on the pipelined kernel (HBM traffic of the next tile overlaps
+// the rounds of the current one).
 template <typename T>
 static int default_tile_bits() {
-  return sizeof(T) == 4 ? tile_max_bits<T>() : tile_max_bits<T>() - 1;
+  return tile_max_bits<T>();
 }
 template <typename T>
 int tile_reg_bits();
 template <typename T>
-hipError_t launch_tile_pass(cpx<T>* psi, int n, int t, const int32_t* prog_dev, bool full, hipStream_t st);
+hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const int32_t* prog_host, bool full,
+                            hipStream_t st);
 
 using cd = std::complex<double>;
 
@@ -1328,7 +1329,7 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
       if (e) return e;
       continue;
     }
-    QSV_HIP(launch_tile_pass<T>(static_cast<cpx<T>*>(s->psi), n, (int)st.S.size(), dprog + offs[k],
+    QSV_HIP(launch_tile_pass<T>(static_cast<cpx<T>*>(s->psi), n, dprog + offs[k], prog.data() + offs[k],
                                 program_needs_full(prog.data() + offs[k]), s->stream));
   }
   return QSV_OK;

@@ -17,9 +17,9 @@
 // XOR swizzle of the amplitude index so that power-of-two strides between
 // the lanes of a round do not hit one bank.  Within a round each thread holds
 // 2^RB amplitudes in registers and applies the round's layers with fully
-// unrolled code.  The round's program is one block of kRoundWords words that
-// every wavefront loads into kRoundLines VGPRs one round ahead and reads with
-// v_readlane, so the op stream never waits on memory.
+// unrolled code.  The round's program is one block of kRoundWords words:
+// every wavefront loads its layer lines into two VGPRs one round ahead and
+// reads them with v_readlane, and reads its table lines with scalar loads.
 #include "internal.hpp"
 #include "tile.hpp"
 
@@ -44,27 +44,16 @@ struct WordsPer {
   static constexpr int W = sizeof(T) / 4;
 };
 
-// Round block held in kRoundLines VGPRs (64 words each), written under a full
-// exec mask.  Every read is a v_readlane of one of these registers with the
-// line chosen on the scalar side: the layer loop may run with some lanes off
-// (fewer groups than threads), and a VGPR computed there would hold stale
-// values in the lanes that readlane addresses.
+// Layer lines of a round block (words 0 .. kLayerWords-1, the first two of
+// its kRoundLines lines) held in two VGPRs, written under a full exec mask.
+// Every read is a v_readlane with the line chosen on the scalar side: the
+// layer loop may run with some lanes off (fewer groups than threads), and a
+// VGPR computed there would hold stale values in the lanes that readlane
+// addresses.  Table lines are read with scalar loads from global memory.
 struct Blk {
-  int l[kRoundLines];
-  // layer words lie in lines 0 and 1
+  int l[2];
   __device__ __forceinline__ int word(int k) const {
     return k < 64 ? rl(l[0], k) : rl(l[1], k & 63);
-  }
-  // f(line VGPR) for a table line (kTableLine0 .. kRoundLines - 1)
-  template <typename F>
-  __device__ __forceinline__ void on_table_line(int ln, F&& f) const {
-    static_assert(kTableLine0 == 2 && kRoundLines == 8, "table lines 2 .. 7");
-    if (ln == 2) f(l[2]);
-    else if (ln == 3) f(l[3]);
-    else if (ln == 4) f(l[4]);
-    else if (ln == 5) f(l[5]);
-    else if (ln == 6) f(l[6]);
-    else f(l[7]);
   }
   template <typename T>
   __device__ __forceinline__ T real(int k) const;
@@ -76,18 +65,6 @@ __device__ __forceinline__ float Blk::real<float>(int k) const {
 template <>
 __device__ __forceinline__ double Blk::real<double>(int k) const {
   return __hiloint2double(word(k + 1), word(k));
-}
-
-// entry e of a table line (one real per word for float, two for double)
-template <typename T>
-__device__ __forceinline__ T line_real(int v, int e);
-template <>
-__device__ __forceinline__ float line_real<float>(int v, int e) {
-  return __int_as_float(rl(v, e));
-}
-template <>
-__device__ __forceinline__ double line_real<double>(int v, int e) {
-  return __hiloint2double(rl(v, 2 * e + 1), rl(v, 2 * e));
 }
 
 // x <- (1 + c) x, in place (c = -2 negates, c = 0 leaves x as it is)
@@ -295,92 +272,27 @@ __device__ __forceinline__ int const_bit(int kind, int val, uint32_t lg, uint64_
   return kind == TK_FREE ? (int)((lg >> val) & 1u) : (int)((base >> val) & 1ull);
 }
 
-// What one call of the tile body does around the rounds: take the tile from
-// the state (or build |0...0> in it), write it back, and/or accumulate the
-// FP64 value of sum_t c_t <Z-string_t> over the tile's amplitudes.
-struct TileIO {
-  int init;             // tile starts as the part of |0...0> (no load)
-  int store;            // write the tile back to the state
-  int reduce;           // accumulate the Z-string sum
-  const uint64_t* z;    // Z masks of the terms (reduce)
-  const double* coef;   // coefficients (reduce)
-  int nt;
-};
-
-// One fused tile pass over tile `tid` of the pass program `prog`; returns the
-// thread's partial of the Z-string sum (0 unless io.reduce).  Ends with a
-// barrier so that the caller can start another tile at once.  FULL = false
-// compiles only the table, magnitude, sign, per-group phase and rotation
-// steps (the host uses it for passes without the other steps): far fewer
-// registers, so that more workgroups share a compute unit.
-template <typename T, int TBMAX, int RB, bool FULL>
-__device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int32_t* __restrict__ prog,
-                                            uint64_t tid, const TileIO& io) {
-  constexpr int A = VecInfo<T>::A;
+// The rounds of one tile pass over the tile held in LDS at `tb`.  `nb` holds
+// the first round's layer lines, already loaded; the later ones are read one
+// round ahead from a copy in LDS (`blds`, kLayerWords words per round) when
+// LDSB, else from the pass program in global memory (`bglob`, where table
+// lines are always read with scalar loads).  Every round ends with a barrier.
+template <typename T, int TBMAX, int RB, bool FULL, bool LDSB>
+__device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t* __restrict__ blds,
+                                           const int32_t* __restrict__ bglob, Blk nb, int nrounds, int t,
+                                           uint64_t base) {
   constexpr int NR = 1 << RB;
-  constexpr int VPT = (1 << TBMAX) / A / kTileThreads;  // 16-byte vectors per thread
   constexpr int SB = SwzBits<T>::B;
-  constexpr int WT = WordsPer<T>::W;                      // words per real
-  __shared__ cpx<T> tile[1 << TBMAX];
-  __shared__ uint64_t segoff[1 << (TBMAX - 4)];
-  const int lane = threadIdx.x & 63;
-
-  const int t = prog[0], c = prog[1], nns = prog[2], nrounds = prog[3];
-  const int32_t* S = prog + 4;
-  const int32_t* nonS = S + t;
-  const int32_t* blocks = prog + ((4 + t + nns + 63) & ~63);
-  uint64_t base = 0;
-  for (int i = 0; i < nns; ++i) base |= ((tid >> i) & 1ull) << nonS[i];
-  const int nseg = 1 << (t - c);
-  for (int h = threadIdx.x; h < nseg; h += kTileThreads) {
-    uint64_t o = 0;
-    for (int j = 0; j < t - c; ++j)
-      if ((h >> j) & 1) o |= 1ull << S[c + j];
-    segoff[h] = o;
-  }
-  // first round block (prefetched while the tile loads)
-  Blk nb;
-#pragma unroll
-  for (int i = 0; i < kRoundLines; ++i) nb.l[i] = nrounds > 0 ? blocks[64 * i + lane] : 0;
-  __syncthreads();
-
-  // ---- load the tile (coalesced 16-byte vectors) into LDS
-  vec16<T>* gv = reinterpret_cast<vec16<T>*>(psi);
-  const int nvec = (1 << t) / A;
-  const uint32_t cmask = (1u << c) - 1u;
-  if (io.init) {
-    for (int i = threadIdx.x; i < nvec; i += kTileThreads) {
-      const uint32_t l = (uint32_t)i * A;
-      const uint64_t g = base | segoff[l >> c] | (l & cmask);
-#pragma unroll
-      for (int e = 0; e < A; ++e)
-        tile[tile_swizzle(l + e, SB)] = cpx<T>{(g + e == 0) ? T(1) : T(0), T(0)};
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < VPT; ++k) {
-      const int i = threadIdx.x + k * kTileThreads;
-      if (i < nvec) {
-        const uint32_t l = (uint32_t)i * A;
-        const uint64_t g = base | segoff[l >> c] | (l & cmask);
-        const vec16<T> x = gv[g / A];
-#pragma unroll
-        for (int e = 0; e < A; ++e) tile[tile_swizzle(l + e, SB)] = x.a[e];
-      }
-    }
-  }
-  __syncthreads();
-
-  // ---- rounds
+  constexpr int WT = WordsPer<T>::W;
   const int ng = 1 << (t - RB);
-  char* const tb = reinterpret_cast<char*>(tile);
+  const int lane = threadIdx.x & 63;
   for (int r = 0; r < nrounds; ++r) {
     const Blk b = nb;
-    const int32_t* bp = blocks + (size_t)r * kRoundWords;
-    if (r + 1 < nrounds) {  // prefetch the next round's block
-      const int32_t* nbp = blocks + (size_t)(r + 1) * kRoundWords;
-#pragma unroll
-      for (int i = 0; i < kRoundLines; ++i) nb.l[i] = nbp[64 * i + lane];
+    const int32_t* bp = bglob + (size_t)r * kRoundWords;
+    if (r + 1 < nrounds) {  // prefetch the next round's layer lines
+      const int32_t* nbp = LDSB ? blds + (size_t)(r + 1) * kLayerWords : bglob + (size_t)(r + 1) * kRoundWords;
+      nb.l[0] = nbp[lane];
+      nb.l[1] = nbp[64 + lane];
     }
     const int w0 = rl(b.l[0], 0);
     const int nlayers = w0 & 0xffff;  // the first layer starts at word w0 >> 16
@@ -543,6 +455,87 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
     __syncthreads();
   }
 
+}
+
+// What one call of the tile body does around the rounds: take the tile from
+// the state (or build |0...0> in it), write it back, and/or accumulate the
+// FP64 value of sum_t c_t <Z-string_t> over the tile's amplitudes.
+struct TileIO {
+  int init;             // tile starts as the part of |0...0> (no load)
+  int store;            // write the tile back to the state
+  int reduce;           // accumulate the Z-string sum
+  const uint64_t* z;    // Z masks of the terms (reduce)
+  const double* coef;   // coefficients (reduce)
+  int nt;
+};
+
+// One fused tile pass over tile `tid` of the pass program `prog`; returns the
+// thread's partial of the Z-string sum (0 unless io.reduce).  Ends with a
+// barrier so that the caller can start another tile at once.  FULL = false
+// compiles only the table, magnitude, sign, per-group phase and rotation
+// steps (the host uses it for passes without the other steps): far fewer
+// registers, so that more workgroups share a compute unit.
+template <typename T, int TBMAX, int RB, bool FULL>
+__device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int32_t* __restrict__ prog,
+                                            uint64_t tid, const TileIO& io) {
+  constexpr int A = VecInfo<T>::A;
+  constexpr int NR = 1 << RB;
+  constexpr int VPT = (1 << TBMAX) / A / kTileThreads;  // 16-byte vectors per thread
+  constexpr int SB = SwzBits<T>::B;
+  constexpr int WT = WordsPer<T>::W;                      // words per real
+  __shared__ cpx<T> tile[1 << TBMAX];
+  __shared__ uint64_t segoff[1 << (TBMAX - 4)];
+  const int lane = threadIdx.x & 63;
+
+  const int t = prog[0], c = prog[1], nns = prog[2], nrounds = prog[3];
+  const int32_t* S = prog + 4;
+  const int32_t* nonS = S + t;
+  const int32_t* blocks = prog + ((4 + t + nns + 63) & ~63);
+  uint64_t base = 0;
+  for (int i = 0; i < nns; ++i) base |= ((tid >> i) & 1ull) << nonS[i];
+  const int nseg = 1 << (t - c);
+  for (int h = threadIdx.x; h < nseg; h += kTileThreads) {
+    uint64_t o = 0;
+    for (int j = 0; j < t - c; ++j)
+      if ((h >> j) & 1) o |= 1ull << S[c + j];
+    segoff[h] = o;
+  }
+  // first round block (prefetched while the tile loads)
+  Blk nb;
+  nb.l[0] = nrounds > 0 ? blocks[lane] : 0;
+  nb.l[1] = nrounds > 0 ? blocks[64 + lane] : 0;
+  __syncthreads();
+
+  // ---- load the tile (coalesced 16-byte vectors) into LDS
+  vec16<T>* gv = reinterpret_cast<vec16<T>*>(psi);
+  const int nvec = (1 << t) / A;
+  const uint32_t cmask = (1u << c) - 1u;
+  if (io.init) {
+    for (int i = threadIdx.x; i < nvec; i += kTileThreads) {
+      const uint32_t l = (uint32_t)i * A;
+      const uint64_t g = base | segoff[l >> c] | (l & cmask);
+#pragma unroll
+      for (int e = 0; e < A; ++e)
+        tile[tile_swizzle(l + e, SB)] = cpx<T>{(g + e == 0) ? T(1) : T(0), T(0)};
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const int i = threadIdx.x + k * kTileThreads;
+      if (i < nvec) {
+        const uint32_t l = (uint32_t)i * A;
+        const uint64_t g = base | segoff[l >> c] | (l & cmask);
+        const vec16<T> x = gv[g / A];
+#pragma unroll
+        for (int e = 0; e < A; ++e) tile[tile_swizzle(l + e, SB)] = x.a[e];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- rounds
+  run_rounds<T, TBMAX, RB, FULL, false>(reinterpret_cast<char*>(tile), nullptr, blocks, nb, nrounds, t, base);
+
   // ---- Z-string sum over the tile (FP64)
   double acc = 0.0;
   if (io.reduce) {
@@ -580,6 +573,125 @@ __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile(cpx<T>* __restrict
                                                               const int32_t* __restrict__ prog) {
   const TileIO io{0, 1, 0, nullptr, nullptr, 0};
   (void)tile_body<T, TBMAX, RB, FULL>(psi, prog, blockIdx.x, io);
+}
+
+// A 16-byte vector of amplitudes (two complex64 or one complex128) as a
+// native vector type, moved between registers and the swizzled LDS tile.
+template <typename T>
+struct StageVec;
+template <>
+struct StageVec<float> {
+  using V = float4;
+  __device__ static void put(cpx<float>* tile, int sb, uint32_t l, const V& v) {
+    tile[tile_swizzle(l, sb)] = cpx<float>{v.x, v.y};
+    tile[tile_swizzle(l + 1, sb)] = cpx<float>{v.z, v.w};
+  }
+  __device__ static V get(const cpx<float>* tile, int sb, uint32_t l) {
+    const cpx<float> a = tile[tile_swizzle(l, sb)], b = tile[tile_swizzle(l + 1, sb)];
+    return V{a.x, a.y, b.x, b.y};
+  }
+};
+template <>
+struct StageVec<double> {
+  using V = double2;
+  __device__ static void put(cpx<double>* tile, int sb, uint32_t l, const V& v) {
+    tile[tile_swizzle(l, sb)] = cpx<double>{v.x, v.y};
+  }
+  __device__ static V get(const cpx<double>* tile, int sb, uint32_t l) {
+    const cpx<double> a = tile[tile_swizzle(l, sb)];
+    return V{a.x, a.y};
+  }
+};
+
+// Pipelined tile pass for one state.  A persistent workgroup walks the tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...  The pass's round blocks are copied
+// to LDS once, and while the rounds of one tile run, each thread already has
+// its share of the next tile in flight from HBM into registers (VPT 16-byte
+// vectors: 64 VGPRs for a 64 KiB tile), so that HBM traffic overlaps the
+// arithmetic instead of alternating with it.  The layer lines of every round
+// are read from LDS so that waiting on them never waits on those loads
+// (loads complete in order).  Used for lean passes over tiles of exactly
+// 2^TBMAX amplitudes with at most kPipeMaxRounds rounds.
+template <typename T, int TBMAX, int RB, bool FULL, int MINWG>
+__global__ __launch_bounds__(kTileThreads, MINWG) void k_tile_pipe(cpx<T>* __restrict__ psi,
+                                                                   const int32_t* __restrict__ prog,
+                                                                   uint64_t ntiles) {
+  constexpr int A = VecInfo<T>::A;
+  constexpr int VPT = (1 << TBMAX) / A / kTileThreads;
+  constexpr int SB = SwzBits<T>::B;
+  constexpr int CMIN = SwzBits<T>::B;  // every pass keeps the low CMIN qubits (fewer only below CMIN qubits)
+  __shared__ cpx<T> tile[1 << TBMAX];
+  __shared__ int32_t blk[kPipeMaxRounds * kLayerWords];
+  __shared__ uint64_t segoff[1 << (TBMAX - CMIN)];
+  const int lane = threadIdx.x & 63;
+
+  const int t = prog[0], c = prog[1], nns = prog[2], nrounds = prog[3];
+  const int32_t* S = prog + 4;
+  const int32_t* nonS = S + t;
+  const int32_t* blocks = prog + ((4 + t + nns + 63) & ~63);
+  for (int i = threadIdx.x; i < nrounds * kLayerWords; i += kTileThreads)
+    blk[i] = blocks[(i / kLayerWords) * kRoundWords + i % kLayerWords];
+  const int nseg = 1 << (t - c);
+  for (int h = threadIdx.x; h < nseg; h += kTileThreads) {
+    uint64_t o = 0;
+    for (int j = 0; j < t - c; ++j)
+      if ((h >> j) & 1) o |= 1ull << S[c + j];
+    segoff[h] = o;
+  }
+  __syncthreads();
+
+  // 16-byte vectors as native vector types (kept in registers)
+  using V = typename StageVec<T>::V;
+  const V* gv = reinterpret_cast<const V*>(psi);
+  V* gw = reinterpret_cast<V*>(psi);
+  const uint32_t cmask = (1u << c) - 1u;
+  auto tile_base = [&](uint64_t tid) {
+    uint64_t base = 0;
+    for (int i = 0; i < nns; ++i) base |= ((tid >> i) & 1ull) << nonS[i];
+    return base;
+  };
+  V stage[VPT];
+  auto fetch = [&](uint64_t tid) {
+    const uint64_t base = tile_base(tid);
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const uint32_t l = (uint32_t)(threadIdx.x + k * kTileThreads) * A;
+      stage[k] = gv[(base | segoff[l >> c] | (l & cmask)) / A];
+    }
+  };
+
+  auto put = [&]() {
+#pragma unroll
+    for (int k = 0; k < VPT; ++k)
+      StageVec<T>::put(tile, SB, (uint32_t)(threadIdx.x + k * kTileThreads) * A, stage[k]);
+  };
+  // The loop is rotated so that every iteration issues the next tile's loads
+  // before this tile's stores: waiting for the loads then never waits for
+  // the stores (memory operations are counted in issue order).
+  uint64_t tid = blockIdx.x;
+  if (tid >= ntiles) return;
+  fetch(tid);
+  put();
+  __syncthreads();
+  if (tid + gridDim.x < ntiles) fetch(tid + gridDim.x);
+  for (;;) {
+    const uint64_t base = tile_base(tid);
+    Blk nb;
+    nb.l[0] = nrounds > 0 ? blk[lane] : 0;
+    nb.l[1] = nrounds > 0 ? blk[64 + lane] : 0;
+    run_rounds<T, TBMAX, RB, FULL, true>(reinterpret_cast<char*>(tile), blk, blocks, nb, nrounds, t, base);
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const uint32_t l = (uint32_t)(threadIdx.x + k * kTileThreads) * A;
+      gw[(base | segoff[l >> c] | (l & cmask)) / A] = StageVec<T>::get(tile, SB, l);
+    }
+    __syncthreads();
+    tid += gridDim.x;
+    if (tid >= ntiles) break;
+    put();
+    __syncthreads();
+    if (tid + gridDim.x < ntiles) fetch(tid + gridDim.x);  // in flight during the rounds
+  }
 }
 
 // ------------------------------------------------------------ batches
@@ -667,19 +779,60 @@ int tile_swizzle_bits() {
 
 // Tiles of up to 2^12 complex64 / 2^11 complex128 amplitudes use a half-size
 // LDS buffer; with the lean body three workgroups then share a compute unit.
-template <typename T>
-hipError_t launch_tile_pass(cpx<T>* psi, int n, int t, const int32_t* prog_dev, bool full, hipStream_t st) {
-  constexpr int TB = TileCfg<T>::TBMAX, RB = TileCfg<T>::RB;
-  const uint64_t ntiles = 1ull << (n - t);
-  const dim3 grid((unsigned)ntiles), block(kTileThreads);
-  if (t <= TB - 1) {
-    if (full) hipLaunchKernelGGL((k_tile<T, TB - 1, RB, true, 2>), grid, block, 0, st, psi, prog_dev);
-    else hipLaunchKernelGGL((k_tile<T, TB - 1, RB, false, 3>), grid, block, 0, st, psi, prog_dev);
-  } else {
-    if (full) hipLaunchKernelGGL((k_tile<T, TB, RB, true, 2>), grid, block, 0, st, psi, prog_dev);
-    else hipLaunchKernelGGL((k_tile<T, TB, RB, false, 2>), grid, block, 0, st, psi, prog_dev);
+
+// Workgroups of a kernel that fit the device at once (cached per device).
+template <typename T, int TB, int RB, bool FULL, int MINWG>
+static int pipe_grid() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cache[dev] == 0) {
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_pipe<T, TB, RB, FULL, MINWG>, kTileThreads, 0) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    cache[dev] = per_cu * ncu;
   }
+  return cache[dev];
+}
+
+template <typename T, int TB, int RB, bool FULL, int MINWG>
+static hipError_t launch_pass(cpx<T>* psi, const int32_t* prog_dev, uint64_t ntiles, bool pipe, hipStream_t st) {
+  if constexpr (!FULL && TB == TileCfg<T>::TBMAX) {
+    const int resident = pipe ? pipe_grid<T, TB, RB, FULL, MINWG>() : 0;
+    if (resident > 0) {
+      const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, (uint64_t)resident);
+      hipLaunchKernelGGL((k_tile_pipe<T, TB, RB, FULL, MINWG>), dim3(grid), dim3(kTileThreads), 0, st, psi,
+                         prog_dev, ntiles);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_tile<T, TB, RB, FULL, MINWG>), dim3((unsigned)ntiles), dim3(kTileThreads), 0, st, psi,
+                     prog_dev);
   return hipGetLastError();
+}
+
+// One fused tile pass.  `prog_host` is the host copy of the pass program
+// (its header is read here).
+template <typename T>
+hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const int32_t* prog_host, bool full,
+                            hipStream_t st) {
+  constexpr int TB = TileCfg<T>::TBMAX, RB = TileCfg<T>::RB;
+  const int t = prog_host[0], c = prog_host[1];
+  const uint64_t ntiles = 1ull << (n - t);
+  const bool small = t <= TB - 1;
+  const int tbits = small ? TB - 1 : TB;
+  // The pipelined kernel holds the next tile in registers: lean passes over
+  // full-size tiles only (for half-size tiles the extra registers and LDS
+  // cost a workgroup per compute unit, more than the overlap gains).
+  const bool pipe = !full && !small && t - c <= tbits - SwzBits<T>::B && prog_host[3] <= kPipeMaxRounds;
+  if (small) {
+    if (full) return launch_pass<T, TB - 1, RB, true, 2>(psi, prog_dev, ntiles, pipe, st);
+    return launch_pass<T, TB - 1, RB, false, 3>(psi, prog_dev, ntiles, pipe, st);
+  }
+  if (full) return launch_pass<T, TB, RB, true, 2>(psi, prog_dev, ntiles, pipe, st);
+  return launch_pass<T, TB, RB, false, 2>(psi, prog_dev, ntiles, pipe, st);
 }
 
 template <typename T>
@@ -704,7 +857,7 @@ template int tile_reg_bits<float>();
 template int tile_reg_bits<double>();
 template int tile_swizzle_bits<float>();
 template int tile_swizzle_bits<double>();
-template hipError_t launch_tile_pass<float>(cpx<float>*, int, int, const int32_t*, bool, hipStream_t);
-template hipError_t launch_tile_pass<double>(cpx<double>*, int, int, const int32_t*, bool, hipStream_t);
+template hipError_t launch_tile_pass<float>(cpx<float>*, int, const int32_t*, const int32_t*, bool, hipStream_t);
+template hipError_t launch_tile_pass<double>(cpx<double>*, int, const int32_t*, const int32_t*, bool, hipStream_t);
 
 }  // namespace qsv

@@ -18,12 +18,14 @@
 // Program layout (int32 words):
 //   pass header : t, c, n_nonS, n_blocks, S[t], nonS[n_nonS], padded to a
 //                 multiple of 64 words
-//   round block : exactly kRoundWords words, held by every wavefront in
-//                 kRoundLines VGPRs (64 words each) and read with readlane.
+//   round block : exactly kRoundWords words in kRoundLines lines of 64.
+//                 Lines 0 and 1 (the layer lines) are held by every wavefront
+//                 in two VGPRs and read with readlane:
 //                 [0] n_layers | (word offset of the first layer) << 16
 //                 [1] free-bit mask  [2 .. 2+2^RB) swizzled LDS byte offsets
-//                 of the register combinations m, then the layers, all within
-//                 lines 0 and 1; lines kTableLine0 .. kRoundLines-1 hold tables.
+//                 of the register combinations m, then the layers.  Lines
+//                 kTableLine0 .. kRoundLines-1 hold tables, read with scalar
+//                 loads.
 //   layer       : flags, n_words, then the payload of every step present,
 //                 in this order (all steps are optional):
 //     LT_TAB    : table line.  Amplitude m is multiplied by the complex
@@ -93,10 +95,11 @@ enum RawDiagType : int32_t { RAW_PHASE1 = 4, RAW_DIAG2 = 5 };
 enum TileOperandKind : int32_t { TK_REG = 0, TK_FREE = 1, TK_OUT = 2 };
 
 constexpr int kTileThreads = 256;
-constexpr int kRoundLines = 8;                 // VGPRs per lane holding a round block
+constexpr int kRoundLines = 8;                 // 64-word lines per round block
 constexpr int kRoundWords = 64 * kRoundLines;  // words per round block
 constexpr int kLayerWords = 128;               // layers lie in words [2 + 2^RB, 128): lines 0, 1
 constexpr int kTableLine0 = 2;                 // lines that may hold tables: 2 .. 7
+constexpr int kPipeMaxRounds = 28;             // rounds whose layer lines the pipelined kernel keeps in LDS
 
 // XOR-linear bijection on tile-local amplitude indices that spreads
 // power-of-two strides over the LDS banks: B = 5 for 8-byte amplitudes
