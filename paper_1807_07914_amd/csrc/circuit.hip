@@ -525,7 +525,7 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
   struct DGroup {
     bool tab = false;
     cd tb[32];
-    uint32_t Mrr = 0, zfree = 0;
+    uint32_t pairs = 0;                                  // CZ between register bits: pair index set
     std::vector<std::pair<int, uint32_t>> fmix, rcmix;  // (free pos | outside q, mask over m)
     uint32_t Md[32] = {0};
     std::vector<int32_t> fc, cc;
@@ -563,7 +563,7 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
     return g.tb;
   };
   auto has_sign = [](const DGroup& g) {
-    if (g.Mrr || g.zfree || !g.fmix.empty() || !g.rcmix.empty() || !g.fc.empty() || !g.cc.empty()) return true;
+    if (g.pairs || !g.fmix.empty() || !g.rcmix.empty() || !g.fc.empty() || !g.cc.empty()) return true;
     for (int d = 0; d < 32; ++d)
       if (g.Md[d]) return true;
     return false;
@@ -690,7 +690,7 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
       }
       auto sg = [&](const DGroup& g) { return has_sign(g) || g.tab; };
       if (ja >= 0 && jb >= 0) {
-        pick(rp, std::max(rp.last[ja], rp.last[jb]), sg).Mrr ^= mbit(ja) & mbit(jb);
+        pick(rp, std::max(rp.last[ja], rp.last[jb]), sg).pairs ^= 1u << cz_pair_index(ja, jb);
       } else if (ja >= 0 && pb >= 0) {
         add_mask(pick(rp, rp.last[ja], has_sign).fmix, pb, mbit(ja));
       } else if (ja >= 0) {
@@ -1045,8 +1045,8 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
       std::vector<int32_t> tline;
       if (g.tab) {
         for (int m = 0; m < NR; ++m)
-          if ((g.Mrr >> m) & 1) g.tb[m] = -g.tb[m];
-        g.Mrr = 0;
+          if (cz_pairs_negate(g.pairs, m)) g.tb[m] = -g.tb[m];
+        g.pairs = 0;
         bool ident = true;
         for (int m = 0; m < NR; ++m)
           if (g.tb[m] != cd(1.0)) ident = false;
@@ -1061,8 +1061,7 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
       std::vector<int32_t> loc;
       for (int d = 1; d < 32; ++d)
         if (g.Md[d]) loc.insert(loc.end(), {d, (int32_t)g.Md[d]});
-      const bool sign = g.Mrr || g.zfree || !g.fmix.empty() || !g.rcmix.empty() || !loc.empty() ||
-                        !g.fc.empty() || !g.cc.empty();
+      const bool sign = !loc.empty() || !g.fc.empty() || !g.cc.empty();
       // extra per-group phases and raw diagonals run as diagonal-only layers first
       struct Extra {
         int kind;  // 0 phasel, 1 raw
@@ -1123,36 +1122,51 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
       };
       std::vector<Blob> blobs;
       if (tab) blobs.push_back({LT_TAB, {0}});  // line filled in at packing
+      if (g.pairs) blobs.push_back({LT_CZR, {(int32_t)g.pairs}});
+      {
+        // conditional Z on register bit j: every register bit of a mask
+        // (an XOR of single-bit masks) with its free / outside qubit
+        std::vector<int32_t> ent;
+        bool bad_mask = false;
+        auto add_entries = [&](const std::vector<std::pair<int, uint32_t>>& v, int kind) {
+          for (auto& e : v) {
+            uint32_t rest = e.second;
+            for (int j = 0; j < RB; ++j)
+              if ((e.second >> (1u << j)) & 1u) {
+                ent.push_back(j | (kind << 4) | (e.first << 8));
+                rest ^= mbit(j);
+              }
+            if (rest) bad_mask = true;
+          }
+        };
+        add_entries(g.fmix, TK_FREE);
+        add_entries(g.rcmix, TK_OUT);
+        if (bad_mask) return false;  // masks are built from single register bits only
+        constexpr size_t kEntries = 16;  // entries per step
+        for (size_t e0 = 0; e0 < ent.size(); e0 += kEntries) {
+          const size_t ne = std::min(kEntries, ent.size() - e0);
+          std::vector<int32_t> w = {(int32_t)ne};
+          w.insert(w.end(), ent.begin() + e0, ent.begin() + e0 + ne);
+          blobs.push_back({LT_CZF, w});
+        }
+      }
       if (sign) {
-        // the sign lists compose by XOR: long ones are split over several steps
-        std::vector<std::pair<int, uint32_t>> fm = g.fmix, rc = g.rcmix;
+        // group parity terms compose by XOR: long lists are split over steps
         std::vector<int32_t> lc = loc, fcl = g.fc, ccl = g.cc;
-        uint32_t Mrr = g.Mrr, zf = g.zfree;
         constexpr size_t kPairs = 12;  // list entries per sign step
         do {
-          std::vector<int32_t> w = {(int32_t)Mrr};
-          auto take_pairs = [&](auto& v) {
-            const size_t n = std::min(v.size(), kPairs);
-            w.push_back((int32_t)n);
-            for (size_t i = 0; i < n; ++i) w.insert(w.end(), {v[i].first, (int32_t)v[i].second});
-            v.erase(v.begin(), v.begin() + n);
-          };
+          std::vector<int32_t> w;
           auto take_flat = [&](std::vector<int32_t>& v) {
             const size_t n = std::min(v.size() / 2, kPairs);
             w.push_back((int32_t)n);
             w.insert(w.end(), v.begin(), v.begin() + 2 * n);
             v.erase(v.begin(), v.begin() + 2 * n);
           };
-          take_pairs(fm);
           take_flat(lc);
-          w.push_back((int32_t)zf);
-          take_pairs(rc);
           take_flat(fcl);
           take_flat(ccl);
           blobs.push_back({LT_SIGN, w});
-          Mrr = 0;
-          zf = 0;
-        } while (!fm.empty() || !rc.empty() || !lc.empty() || !fcl.empty() || !ccl.empty());
+        } while (!fcl.empty() || !lc.empty() || !ccl.empty());
       }
       for (const Extra& E : extras) {
         std::vector<int32_t> w;
@@ -1198,12 +1212,14 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
       // step kinds in application order (rotations: one kind per register bit)
       auto order = [](int32_t flag) {
         if (flag & LT_TAB) return 0;
-        if (flag & LT_SIGN) return 2;
-        if (flag & LT_PHASEL) return 3;
-        if (flag & LT_RAWD) return 4;
+        if (flag & LT_CZR) return 1;
+        if (flag & LT_CZF) return 2;
+        if (flag & LT_SIGN) return 3;
+        if (flag & LT_PHASEL) return 4;
+        if (flag & LT_RAWD) return 5;
         for (int j = 0; j < 8; ++j)
-          if (flag & (LT_ROT0 << j)) return 5 + j;
-        return 13;
+          if (flag & (LT_ROT0 << j)) return 6 + j;
+        return 14;
       };
       const int budget = kLayerWords - (2 + NR) - 2;
       size_t bi = 0;

@@ -211,6 +211,20 @@ __device__ __forceinline__ void perm2(cpx<T> (&a)[1 << RB]) {
 // rather than one arm of an else-if chain: arms of a chain that all rewrite
 // the amplitudes are merged in one place, and the register allocator then
 // copies every amplitude on the paths that skip the step.
+// sign change of the amplitudes with register bits J and K set (CZ)
+template <typename T, int RB, int J, int K>
+__device__ __forceinline__ void cz_pair(cpx<T> (&a)[1 << RB]) {
+#pragma unroll
+  for (int m = 0; m < (1 << RB); ++m)
+    if (((m >> J) & 1) && ((m >> K) & 1)) scale1(a[m], T(-2));
+}
+// x <- (1 + c) x for the amplitudes with register bit J set (c = -2 or 0)
+template <typename T, int RB, int J>
+__device__ __forceinline__ void cond_z(cpx<T> (&a)[1 << RB], T c) {
+#pragma unroll
+  for (int m = 0; m < (1 << RB); ++m)
+    if ((m >> J) & 1) scale1(a[m], c);
+}
 template <typename T, int RB>
 __device__ __forceinline__ void dispatch_u1(cpx<T> (&a)[1 << RB], int j, const M2<T>& U) {
   if (j == 0) u1<T, RB, 0>(a, U);
@@ -327,28 +341,57 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
         const int flags = b.word(k), len = b.word(k + 1);
         int p = k + 2;
         if (flags & LT_TAB) table_step<T, RB>(a, bp + 64 * b.word(p++));
+        if (flags & LT_CZR) {
+          const uint32_t pairs = (uint32_t)b.word(p++);
+#define QSV_CZR(J, K) \
+  if ((K) < RB && ((pairs >> cz_pair_index(J, K)) & 1u)) cz_pair<T, RB, J, ((K) < RB ? (K) : (J) + 1)>(a);
+          QSV_CZR(0, 1)
+          QSV_CZR(0, 2)
+          QSV_CZR(1, 2)
+          QSV_CZR(0, 3)
+          QSV_CZR(1, 3)
+          QSV_CZR(2, 3)
+          QSV_CZR(0, 4)
+          QSV_CZR(1, 4)
+          QSV_CZR(2, 4)
+          QSV_CZR(3, 4)
+#undef QSV_CZR
+        }
+        if (flags & LT_CZF) {
+          // per-lane parity of the conditions for each register bit first,
+          // then one pass over the amplitudes per bit that has entries
+          const int ne = b.word(p++);
+          uint32_t zm = 0, jm = 0;
+          for (int e = 0; e < ne; ++e) {
+            const int w = b.word(p++);
+            const int j = w & 15, val = w >> 8;
+            const uint32_t on = ((w >> 4) & 15) == TK_FREE ? (lg >> val) & 1u : (uint32_t)((base >> val) & 1ull);
+            zm ^= on << j;
+            jm |= 1u << j;
+          }
+#define QSV_CZF(J) \
+  if ((J) < RB && ((jm >> (J)) & 1u)) cond_z<T, RB, ((J) < RB ? (J) : 0)>(a, ((zm >> (J)) & 1u) ? T(-2) : T(0));
+          QSV_CZF(0)
+          QSV_CZF(1)
+          QSV_CZF(2)
+          QSV_CZF(3)
+          QSV_CZF(4)
+#undef QSV_CZF
+        }
         if (flags & LT_SIGN) {
-          uint32_t neg = (uint32_t)b.word(p++);
-          const int nf = b.word(p++);
-          for (int q = 0; q < nf; ++q, p += 2)
-            if ((lg >> b.word(p)) & 1u) neg ^= (uint32_t)b.word(p + 1);
-          const int nd = b.word(p++);
           int par = 0;
+          const int nd = b.word(p++);
           for (int q = 0; q < nd; ++q, p += 2)
             par ^= __popc(lg & (lg >> b.word(p)) & (uint32_t)b.word(p + 1));
-          par ^= __popc(lg & (uint32_t)b.word(p++));
-          const int nrc = b.word(p++);
-          for (int q = 0; q < nrc; ++q, p += 2)
-            if ((base >> b.word(p)) & 1ull) neg ^= (uint32_t)b.word(p + 1);
           const int nfc = b.word(p++);
           for (int q = 0; q < nfc; ++q, p += 2)
             par ^= (int)(((base >> b.word(p)) & 1ull) & ((lg >> b.word(p + 1)) & 1u));
           const int ncc = b.word(p++);
           for (int q = 0; q < ncc; ++q, p += 2)
             par ^= (int)((base >> b.word(p)) & (base >> b.word(p + 1)) & 1ull);
-          if (par & 1) neg = ~neg;
+          const T cg = (par & 1) ? T(-2) : T(0);  // per lane
 #pragma unroll
-          for (int m = 0; m < NR; ++m) scale1(a[m], ((neg >> m) & 1u) ? T(-2) : T(0));
+          for (int m = 0; m < NR; ++m) scale1(a[m], cg);
         }
         if (flags & LT_PHASEL) {
           {

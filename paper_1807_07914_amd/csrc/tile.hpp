@@ -32,13 +32,19 @@
 //                 factor z_m = (re, im) at entry m of the table line (two
 //                 words per entry for float, four for double): phases,
 //                 signs and magnitudes of diagonal factors on register bits.
-//     LT_SIGN   : Mrr, nf, (f, mask)*nf, nd, (d, M)*nd, zfree,
-//                 nrc, (q, mask)*nrc, nfc, (q, f)*nfc, ncc, (qa, qb)*ncc
-//                 negation pattern over m:  Mrr ^ [mask for every free bit f
-//                 set in the group] ^ [mask for every outside qubit q set in
-//                 the tile], complemented when the group parity
-//                 popcount(lg & zfree) + sum_d popcount(lg & (lg >> d) & M)
-//                 + sum_(q,f) bit(q) bit(lg, f) + sum_(qa,qb) bit(qa) bit(qb) is odd.
+//     LT_CZR    : pair set P.  For every CZ pair (j, k) in P (bit
+//                 cz_pair_index(j, k)), amplitudes with register bits j and
+//                 k both set change sign.
+//     LT_CZF    : n, then n words j | kind << 4 | val << 8.  Amplitudes
+//                 with register bit j set change sign when the operand
+//                 (kind 1: free local bit val of the group, kind 2: outside
+//                 qubit val of the tile) is 1: a CZ between a register
+//                 qubit and a qubit that is constant over the group.
+//     LT_SIGN   : nd, (d, M)*nd, nfc, (q, f)*nfc, ncc, (qa, qb)*ncc.
+//                 Every amplitude of the group changes sign when the group
+//                 parity sum_d popcount(lg & (lg >> d) & M)
+//                 + sum_(q,f) bit(q) bit(lg, f) + sum_(qa,qb) bit(qa) bit(qb)
+//                 is odd (CZs among free bits and outside qubits).
 //     LT_PHASEL : j, nt, (lgmask, omask_lo, omask_hi, r)*nt:
 //                 per-group factor w = product of r over the terms whose free
 //                 bits lgmask are all set in the group and whose outside
@@ -80,9 +86,11 @@ namespace qsv {
 
 enum LayerFlag : int32_t {
   LT_TAB = 1 << 0,
+  LT_CZR = 1 << 1,
   LT_SIGN = 1 << 2,
   LT_PHASEL = 1 << 3,
   LT_RAWD = 1 << 4,
+  LT_CZF = 1 << 5,
   LT_ROT0 = 1 << 8,     // rotation on register bit j: LT_ROT0 << j
   LT_SHEAR3 = 1 << 16,  // three shears on bit j: LT_SHEAR3 << j
   LT_PERM2 = 1 << 24,
@@ -100,6 +108,20 @@ constexpr int kRoundWords = 64 * kRoundLines;  // words per round block
 constexpr int kLayerWords = 128;               // layers lie in words [2 + 2^RB, 128): lines 0, 1
 constexpr int kTableLine0 = 2;                 // lines that may hold tables: 2 .. 7
 constexpr int kPipeMaxRounds = 28;             // rounds whose layer lines the pipelined kernel keeps in LDS
+
+// Index of the CZ between register bits j != k in an LT_CZR pair set:
+// (0,1)=0, (0,2)=1, (1,2)=2, (0,3)=3, ... (pairs ordered by the larger bit).
+__host__ __device__ constexpr int cz_pair_index(int j, int k) {
+  return j < k ? k * (k - 1) / 2 + j : j * (j - 1) / 2 + k;
+}
+// Whether register combination m changes sign under the CZ pair set `pairs`.
+__host__ __device__ inline bool cz_pairs_negate(uint32_t pairs, int m) {
+  int par = 0;
+  for (int k = 1; k < 8; ++k)
+    for (int j = 0; j < k; ++j)
+      if (((pairs >> cz_pair_index(j, k)) & 1u) && ((m >> j) & 1) && ((m >> k) & 1)) par ^= 1;
+  return par != 0;
+}
 
 // XOR-linear bijection on tile-local amplitude indices that spreads
 // power-of-two strides over the LDS banks: B = 5 for 8-byte amplitudes

@@ -100,6 +100,21 @@ def random_brickwork(n: int, depth: int, seed: int) -> list:
     return ops
 
 
+def cz_mesh(n: int, depth: int, seed: int) -> list:
+    """Haar SU(2) on every qubit, then CZ on a random pairing of all qubits
+    (any distance), per layer: entanglers between every kind of qubit
+    position a tile pass distinguishes."""
+    rng = np.random.default_rng(seed)
+    ops = []
+    for _ in range(depth):
+        for q in range(n):
+            ops.append(op("U", q, mat=haar_su2(rng)))
+        perm = rng.permutation(n)
+        for i in range(0, n - 1, 2):
+            ops.append(op("CZ", int(perm[i]), int(perm[i + 1])))
+    return ops
+
+
 def qft(n: int) -> list:
     """Quantum Fourier transform with the + phase convention: for j = n-1
     down to 0, H(j) then CPHASE(pi / 2^(j-m)) on (m, j) for m = j-1 .. 0;

@@ -248,7 +248,7 @@ def test_fused_random_circuits(dtype, n, tile):
 
 @pytest.mark.parametrize("small_tile", [False, True])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("family", ["brickwork", "rounds", "qft", "hea", "rotring", "ghz"])
+@pytest.mark.parametrize("family", ["brickwork", "rounds", "qft", "hea", "rotring", "ghz", "cz_mesh"])
 def test_fused_families(dtype, family, small_tile):
     # small_tile: 2^12 (complex64) / 2^11 (complex128) tiles, which run on the
     # half-size LDS kernels (lean or full by the pass's steps)
@@ -266,6 +266,9 @@ def test_fused_families(dtype, family, small_tile):
         ops = qc.hea_circuit(n, rng.uniform(0, 2 * np.pi, (10, n, 2)))
     elif family == "rotring":
         ops = qc.rot_ring_ansatz(n, rng.uniform(0, 2 * np.pi, 3 * 3 * n), 3)
+    elif family == "cz_mesh":
+        allcz = [qc.op("CZ", i, j) for i in range(n) for j in range(i + 1, n)]
+        ops = allcz + qc.cz_mesh(n, 10, 80) + allcz
     else:
         ops = qc.ghz(n)
     ref = O.run(ops, n, x0=x0)

@@ -28,6 +28,7 @@ def families(n, seed):
         "hea": qc.hea_circuit(n, rng.uniform(0, 2 * np.pi, (3, n, 2)), layers=3),
         "rotring": qc.rot_ring_ansatz(n, rng.uniform(0, 2 * np.pi, 2 * 3 * n), 2),
         "ghz": qc.ghz(n),
+        "cz_mesh": qc.cz_mesh(n, 4, seed),
     }
 
 
@@ -120,6 +121,23 @@ def test_emulated_gate_algebra_edge_cases(dtype, n, tile, seed):
     got = E.emulate(n, dtype, ops, psi0, tile)
     scale = max(1.0, float(np.abs(ref).max()))
     assert np.abs(got - ref).max() <= TOL[dtype] * 10 * scale
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_emulated_sign_steps(dtype):
+    # CZs between every kind of qubit position (register, free, outside):
+    # pair negations, conditional Zs and group parities all appear and
+    # match the oracle
+    n, tile = 11, 7
+    allcz = [qc.op("CZ", i, j) for i in range(n) for j in range(i + 1, n)]
+    ops = allcz + qc.cz_mesh(n, 4, 31) + allcz
+    psi0 = qc.random_state(n, 32)
+    words, steps = E.program(n, dtype, ops, tile)
+    counts = E.op_counts(words, steps, dtype)
+    assert counts.get("CZR", 0) > 0 and counts.get("CZF", 0) > 0 and counts.get("SIGN", 0) > 0, counts
+    ref = O.run(ops, n, psi=psi0.copy())
+    got = E.emulate(n, dtype, ops, psi0, tile)
+    assert np.abs(got - ref).max() <= TOL[dtype]
 
 
 def test_givens_split_counts():

@@ -21,7 +21,7 @@ LINES = 8
 ROUND_WORDS = 64 * LINES
 TABLE_LINE0 = 2
 LAYER_WORDS = 128
-LT_TAB, LT_SIGN, LT_PHASEL, LT_RAWD = 1, 4, 8, 16
+LT_TAB, LT_CZR, LT_SIGN, LT_PHASEL, LT_RAWD, LT_CZF = 1, 2, 4, 8, 16, 32
 LT_ROT0, LT_SHEAR3 = 1 << 8, 1 << 16
 LT_PERM2, LT_U2, LT_U1 = 1 << 24, 1 << 25, 1 << 26
 RAW_PHASE1, RAW_DIAG2 = 4, 5
@@ -145,23 +145,31 @@ def run_pass(psi, n, words, off, cfg):
                             zr = _real(blk, 64 * tl + 2 * m * WT, WT)
                             zi = _real(blk, 64 * tl + (2 * m + 1) * WT, WT)
                             a[m] = a[m] * complex(zr, zi)
+                    if flags & LT_CZR:
+                        pairs = blk[p] & 0xffffffff; p += 1
+                        for kk in range(1, RB):
+                            for jj in range(kk):
+                                if (pairs >> (kk * (kk - 1) // 2 + jj)) & 1:
+                                    for m in range(NR):
+                                        if (m >> jj) & 1 and (m >> kk) & 1:
+                                            a[m] = -a[m]
+                        assert pairs >> (RB * (RB - 1) // 2) == 0
+                    if flags & LT_CZF:
+                        ne = blk[p]; p += 1
+                        for _ in range(ne):
+                            w_ = blk[p]; p += 1
+                            jj, kind, val = w_ & 15, (w_ >> 4) & 15, w_ >> 8
+                            assert jj < RB and kind in (TK_FREE, TK_OUT)
+                            on = (lg >> val) & 1 if kind == TK_FREE else (base >> val) & 1
+                            if on:
+                                for m in range(NR):
+                                    if (m >> jj) & 1:
+                                        a[m] = -a[m]
                     if flags & LT_SIGN:
-                        neg = blk[p] & 0xffffffff; p += 1
-                        nf = blk[p]; p += 1
-                        for _ in range(nf):
-                            if (lg >> blk[p]) & 1:
-                                neg ^= blk[p + 1] & 0xffffffff
-                            p += 2
-                        nd = blk[p]; p += 1
                         par = 0
+                        nd = blk[p]; p += 1
                         for _ in range(nd):
                             par ^= bin(lg & (lg >> blk[p]) & (blk[p + 1] & 0xffffffff)).count("1")
-                            p += 2
-                        par ^= bin(lg & (blk[p] & 0xffffffff)).count("1"); p += 1
-                        nrc = blk[p]; p += 1
-                        for _ in range(nrc):
-                            if (base >> blk[p]) & 1:
-                                neg ^= blk[p + 1] & 0xffffffff
                             p += 2
                         nfc = blk[p]; p += 1
                         for _ in range(nfc):
@@ -172,10 +180,7 @@ def run_pass(psi, n, words, off, cfg):
                             par ^= (base >> blk[p]) & (base >> blk[p + 1]) & 1
                             p += 2
                         if par & 1:
-                            neg = ~neg & 0xffffffff
-                        for m in range(NR):
-                            if (neg >> m) & 1:
-                                a[m] = -a[m]
+                            a = [-x for x in a]
                     if flags & LT_PHASEL:
                         j, nt = blk[p], blk[p + 1]
                         p += 2
@@ -329,7 +334,7 @@ def emulate_batch_job(dtype, words, passoff, job):
     return psi
 
 
-STEP_NAMES = [(LT_TAB, "TAB"), (LT_SIGN, "SIGN"), (LT_PHASEL, "PHASEL"),
+STEP_NAMES = [(LT_TAB, "TAB"), (LT_CZR, "CZR"), (LT_CZF, "CZF"), (LT_SIGN, "SIGN"), (LT_PHASEL, "PHASEL"),
               (LT_RAWD, "RAWD"), (LT_PERM2, "PERM2"), (LT_U2, "U2"), (LT_U1, "U1")]
 
 
