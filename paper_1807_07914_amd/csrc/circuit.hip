@@ -329,35 +329,11 @@ static uint64_t key_hash(const std::vector<uint32_t>& k) {
 }
 
 // ------------------------------------------------------- materialisation
-// Writes one pass: header, then one kRoundWords block per round (a round
-// whose layers do not fit one block continues in further blocks with the
-// same register bits).  Layers fill a block from the front, table lines are
-// taken from the back (lines kRoundLines-1 down to kTableLine0).
+// Reals in the state's precision: one word per float, two (low, high) per
+// double.
 template <typename T>
-struct BlockWriter {
-  std::vector<int32_t>& prog;
-  size_t b0 = 0;      // start of the current block
-  int k = 0;          // next word for a layer
-  int nlayers = 0;
-  int next_line = 0;  // next free table line (counting down)
-  const int NR;
-  bool failed = false;          // a layer did not fit an empty block (nothing written)
-  std::vector<int32_t> header;  // words 1 .. 2+NR (free mask + LDS byte offsets)
-
-  BlockWriter(std::vector<int32_t>& p, int nr) : prog(p), NR(nr) {}
-
-  void open() {
-    b0 = prog.size();
-    prog.resize(b0 + kRoundWords, 0);
-    for (size_t i = 0; i < header.size(); ++i) prog[b0 + 1 + i] = header[i];
-    k = 2 + NR;
-    nlayers = 0;
-    next_line = kRoundLines - 1;
-  }
-  // word 0: number of layers | offset of the first layer << 16
-  void close() { prog[b0] = nlayers | ((2 + NR) << 16); }
-
-  static void real_words(double v, std::vector<int32_t>& out) {
+struct RealWords {
+  static void put(double v, std::vector<int32_t>& out) {
     if (sizeof(T) == 4) {
       float f = (float)v;
       int32_t w;
@@ -369,37 +345,6 @@ struct BlockWriter {
       out.push_back((int32_t)(w & 0xffffffff));
       out.push_back((int32_t)(w >> 32));
     }
-  }
-
-  // A layer of L words that needs n_lines table lines, filled by
-  // fill(words, lines[]) once its lines are known.
-  template <typename F>
-  void layer(int n_lines, F&& fill) {
-    for (int attempt = 0; attempt < 2; ++attempt) {
-      int lines[2] = {-1, -1};
-      bool ok = next_line - n_lines + 1 >= kTableLine0;
-      for (int i = 0; i < n_lines && ok; ++i) lines[i] = next_line - i;
-      std::vector<int32_t> w;
-      fill(w, lines);
-      const int lowest = n_lines > 0 ? lines[n_lines - 1] : next_line + 1;
-      if (ok && k + (int)w.size() <= std::min(kLayerWords, 64 * lowest)) {
-        w[1] = (int32_t)w.size();
-        for (size_t i = 0; i < w.size(); ++i) prog[b0 + k + i] = w[i];
-        k += (int)w.size();
-        next_line -= n_lines;
-        ++nlayers;
-        return;
-      }
-      if (attempt == 1) {
-        failed = true;
-        return;
-      }
-      close();
-      open();
-    }
-  }
-  void put_line(int line, const std::vector<int32_t>& words) {
-    for (size_t i = 0; i < words.size() && i < 64; ++i) prog[b0 + 64 * line + i] = words[i];
   }
 };
 
@@ -487,8 +432,9 @@ static Split split_u1(const cd* u) {
   return sp;
 }
 
-// Returns false if a layer does not fit a round block (cannot happen for the
-// layer sizes the planner forms; checked so that nothing is written past it).
+// Writes the program of one tile pass (layout in tile.hpp).  Returns false
+// if a sign mask is not made of single register bits (the planner builds
+// none such; checked so that no wrong program is written).
 template <typename T>
 static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, int RB,
                       std::vector<int32_t>& prog) {
@@ -505,11 +451,12 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
   prog.push_back(t);
   prog.push_back(c);
   prog.push_back((int32_t)nonS.size());
-  prog.push_back(0);  // number of round blocks, patched below
+  prog.push_back((int32_t)st.rounds.size());
   for (int q : st.S) prog.push_back(q);
   for (int q : nonS) prog.push_back(q);
-  while ((prog.size() - h0) % 64) prog.push_back(0);
-  const size_t blocks0 = prog.size();
+  const size_t roff0 = prog.size();  // round offsets, filled in as the rounds are written
+  prog.resize(prog.size() + st.rounds.size(), 0);
+  while ((prog.size() - h0) % 16) prog.push_back(0);
 
   // Diagonal factors not yet applied, per tile-local qubit (diag(pd0, pd1)),
   // and a scalar for the whole tile.
@@ -985,19 +932,22 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
     fq = u.imag();
     fc = sg * r - 1.0;
   };
-  for (RPlan& rp : plans) {
+  constexpr int LR = LayerRec<T>::W;
+  for (size_t ri = 0; ri < plans.size(); ++ri) {
+    RPlan& rp = plans[ri];
     uint32_t rmask = 0;
     for (int k = 0; k < RB; ++k) rmask |= 1u << rp.R[k];
     const uint32_t tmask = t >= 32 ? ~0u : ((1u << t) - 1u);
-    BlockWriter<T> bw(prog, NR);
-    bw.header.push_back((int32_t)(tmask & ~rmask));
-    for (int m = 0; m < NR; ++m) {
-      uint32_t lm = 0;
-      for (int k = 0; k < RB; ++k)
-        if ((m >> k) & 1) lm |= 1u << rp.R[k];
-      bw.header.push_back((int32_t)(tile_swizzle(lm, SB) * (uint32_t)(2 * sizeof(T))));
-    }
-    bw.open();
+    // records of the round: fixed fields, aux words, table index
+    struct Rec {
+      int32_t flags = 0;
+      int tab = -1;
+      int32_t pairs = 0;
+      std::vector<int32_t> aux;
+      std::vector<int32_t> rot = std::vector<int32_t>(LR - kRecRot, 0);
+    };
+    std::vector<Rec> recs;
+    std::vector<std::vector<int32_t>> tables;
 
     // layers: the diagonal work of a group, then rotations on distinct
     // register bits with nothing diagonal between them, then at most one
@@ -1053,8 +1003,8 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
         if (!ident) {
           tab = true;
           for (int m = 0; m < NR; ++m) {
-            BlockWriter<T>::real_words(g.tb[m].real(), tline);
-            BlockWriter<T>::real_words(g.tb[m].imag(), tline);
+            RealWords<T>::put(g.tb[m].real(), tline);
+            RealWords<T>::put(g.tb[m].imag(), tline);
           }
         }
       }
@@ -1089,8 +1039,8 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
           w.push_back((int32_t)tm.lgm);
           w.push_back((int32_t)(tm.om & 0xffffffffull));
           w.push_back((int32_t)(tm.om >> 32));
-          BlockWriter<T>::real_words(tm.r.real(), w);
-          BlockWriter<T>::real_words(tm.r.imag(), w);
+          RealWords<T>::put(tm.r.real(), w);
+          RealWords<T>::put(tm.r.imag(), w);
         }
       };
       auto raw_words = [&](std::vector<int32_t>& w, int e) {
@@ -1108,14 +1058,14 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
         for (int f = 0; f < nfac; ++f) {
           double fp, fq, fc;
           factor_pqc(o.m[f], fp, fq, fc);
-          BlockWriter<T>::real_words(fp, w);
-          BlockWriter<T>::real_words(fq, w);
-          BlockWriter<T>::real_words(fc, w);
+          RealWords<T>::put(fp, w);
+          RealWords<T>::put(fq, w);
+          RealWords<T>::put(fc, w);
         }
       };
       // Steps in the order a layer applies them, each as (flag, payload
-      // words); consecutive steps are packed into layers of at most
-      // kLayerWords words, one step of each kind per layer.
+      // words); consecutive steps become one layer record, one step of each
+      // kind per record.
       struct Blob {
         int32_t flag;
         std::vector<int32_t> w;
@@ -1181,8 +1131,8 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
           const NdItem& it = rp.nd[i];
           Blob bl{LT_ROT0 << it.j0, {}};
           if (it.jf >> 8) bl.flag |= LT_SHEAR3 << it.j0;
-          BlockWriter<T>::real_words(it.p, bl.w);
-          BlockWriter<T>::real_words(it.q, bl.w);
+          RealWords<T>::put(it.p, bl.w);
+          RealWords<T>::put(it.q, bl.w);
           blobs.push_back(bl);
         }
       }
@@ -1196,15 +1146,15 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
           bl.flag = LT_U2;
           bl.w = {it.j0, it.j1};
           for (int e = 0; e < 16; ++e) {
-            BlockWriter<T>::real_words(it.m[e].real(), bl.w);
-            BlockWriter<T>::real_words(it.m[e].imag(), bl.w);
+            RealWords<T>::put(it.m[e].real(), bl.w);
+            RealWords<T>::put(it.m[e].imag(), bl.w);
           }
         } else {
           bl.flag = LT_U1;
           bl.w = {it.j0};
           for (int e = 0; e < 4; ++e) {
-            BlockWriter<T>::real_words(it.m[e].real(), bl.w);
-            BlockWriter<T>::real_words(it.m[e].imag(), bl.w);
+            RealWords<T>::put(it.m[e].real(), bl.w);
+            RealWords<T>::put(it.m[e].imag(), bl.w);
           }
         }
         blobs.push_back(bl);
@@ -1221,55 +1171,71 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
           if (flag & (LT_ROT0 << j)) return 6 + j;
         return 14;
       };
-      const int budget = kLayerWords - (2 + NR) - 2;
-      size_t bi = 0;
-      while (bi < blobs.size()) {
-        size_t be = bi;
-        int words = 0, last = -1;
-        while (be < blobs.size() && order(blobs[be].flag) > last &&
-               words + (int)blobs[be].w.size() <= budget) {
-          words += (int)blobs[be].w.size();
-          last = order(blobs[be].flag);
-          ++be;
+      // consecutive steps go into one record, one step of each kind per record
+      int last = 1 << 30;
+      for (const Blob& bl : blobs) {
+        const int ord = order(bl.flag);
+        if (ord <= last) recs.emplace_back();
+        last = ord;
+        Rec& rc = recs.back();
+        rc.flags |= bl.flag;
+        if (bl.flag & LT_TAB) {
+          rc.tab = (int)tables.size();
+          tables.push_back(tline);
+        } else if (bl.flag & LT_CZR) {
+          rc.pairs = bl.w[0];
+        } else if (ord >= 6 && ord < 6 + RB) {
+          const int j = ord - 6;
+          for (int e = 0; e < 2 * WT; ++e) rc.rot[2 * j * WT + e] = bl.w[e];
+        } else {
+          rc.aux.insert(rc.aux.end(), bl.w.begin(), bl.w.end());
         }
-        if (be == bi) {  // a single step longer than a layer may be (not formed by the planner)
-          return false;
-        }
-        const bool has_tab = (blobs[bi].flag & LT_TAB) != 0;
-        bw.layer(has_tab ? 1 : 0, [&](std::vector<int32_t>& w, const int* lines) {
-          int32_t flags = 0;
-          w = {0, 0};
-          for (size_t x = bi; x < be; ++x) {
-            flags |= blobs[x].flag;
-            const size_t at = w.size();
-            w.insert(w.end(), blobs[x].w.begin(), blobs[x].w.end());
-            if (blobs[x].flag & LT_TAB) w[at] = lines[0];
-          }
-          w[0] = flags;
-        });
-        if (bw.failed) return false;
-        if (has_tab) bw.put_line(bw.next_line + 1, tline);
-        bi = be;
       }
     }
-    bw.close();
+
+    // round block: header, records, aux words, tables
+    const size_t b0 = prog.size();
+    prog[roff0 + ri] = (int32_t)(b0 - h0);
+    std::vector<int32_t> hdr(kRoundHeader, 0);
+    hdr[0] = (int32_t)recs.size();
+    hdr[1] = (int32_t)(tmask & ~rmask);
+    for (int k = 0; k < RB; ++k)
+      hdr[2 + k] = (int32_t)(tile_swizzle(1u << rp.R[k], SB) * (uint32_t)(2 * sizeof(T)));
+    prog.insert(prog.end(), hdr.begin(), hdr.end());
+    const size_t rec0 = prog.size();
+    prog.resize(rec0 + recs.size() * LR, 0);
+    for (size_t i = 0; i < recs.size(); ++i) {
+      int32_t* w = prog.data() + rec0 + i * LR;
+      w[0] = recs[i].flags;
+      w[2] = recs[i].pairs;
+      for (int e = 0; e < LR - kRecRot; ++e) w[kRecRot + e] = recs[i].rot[e];
+    }
+    for (size_t i = 0; i < recs.size(); ++i) {
+      if (recs[i].aux.empty()) continue;
+      prog[rec0 + i * LR + 3] = (int32_t)(prog.size() - b0);
+      prog.insert(prog.end(), recs[i].aux.begin(), recs[i].aux.end());
+    }
+    while ((prog.size() - b0) % 16) prog.push_back(0);
+    for (size_t i = 0; i < recs.size(); ++i) {
+      if (recs[i].tab < 0) continue;
+      prog[rec0 + i * LR + 1] = (int32_t)(prog.size() - b0);
+      const std::vector<int32_t>& tl = tables[recs[i].tab];
+      prog.insert(prog.end(), tl.begin(), tl.end());
+    }
   }
-  prog[h0 + 3] = (int32_t)((prog.size() - blocks0) / kRoundWords);
   return true;
 }
 
-// Whether a pass program uses steps beyond the lean tile body (tables,
-// magnitudes, signs, per-group phases, rotations).
+// Whether a pass program uses steps beyond the lean tile body (tables, CZ
+// signs, group parities, per-group phases, rotations).
+template <typename T>
 static bool program_needs_full(const int32_t* pass) {
-  const int t = pass[0], nns = pass[2], nblocks = pass[3];
-  const int32_t* blocks = pass + ((4 + t + nns + 63) & ~63);
-  for (int r = 0; r < nblocks; ++r) {
-    const int32_t* b = blocks + (size_t)r * kRoundWords;
-    int k = b[0] >> 16;
-    for (int l = 0; l < (b[0] & 0xffff); ++l) {
-      if (b[k] & (LT_RAWD | LT_PERM2 | LT_U2 | LT_U1)) return true;
-      k += b[k + 1];
-    }
+  const int t = pass[0], nns = pass[2], nrounds = pass[3];
+  const int32_t* roff = pass + 4 + t + nns;
+  for (int r = 0; r < nrounds; ++r) {
+    const int32_t* b = pass + roff[r];
+    for (int l = 0; l < b[0]; ++l)
+      if (b[kRoundHeader + l * LayerRec<T>::W] & (LT_RAWD | LT_PERM2 | LT_U2 | LT_U1)) return true;
   }
   return false;
 }
@@ -1318,7 +1284,7 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
   std::vector<size_t> offs;
   for (const Step& st : sch->steps) {
     offs.push_back(prog.size());
-    if (st.tile && !emit_pass<T>(st, P, n, c, RB, prog)) return fail(QSV_ERR_UNSUPPORTED, "a fused tile layer does not fit a round block");
+    if (st.tile && !emit_pass<T>(st, P, n, c, RB, prog)) return fail(QSV_ERR_UNSUPPORTED, "a fused tile pass could not be encoded");
   }
   const size_t need = prog.size() * sizeof(int32_t) + 256;
   if (s->pbuf_bytes < need) {
@@ -1346,7 +1312,7 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
       continue;
     }
     QSV_HIP(launch_tile_pass<T>(static_cast<cpx<T>*>(s->psi), n, dprog + offs[k], prog.data() + offs[k],
-                                program_needs_full(prog.data() + offs[k]), s->stream));
+                                program_needs_full<T>(prog.data() + offs[k]), s->stream));
   }
   return QSV_OK;
 }
@@ -1392,7 +1358,7 @@ qsv_status plan_program(const qsv_state* s, const qsv_op* ops, int n_ops, int ti
     }
     steps.push_back((int64_t)prog.size());
     const bool ok = f ? emit_pass<float>(st, P, n, c, RB, prog) : emit_pass<double>(st, P, n, c, RB, prog);
-    if (!ok) return fail(QSV_ERR_UNSUPPORTED, "a fused tile layer does not fit a round block");
+    if (!ok) return fail(QSV_ERR_UNSUPPORTED, "a fused tile pass could not be encoded");
   }
   return QSV_OK;
 }
@@ -1454,6 +1420,7 @@ struct qsv_batch {
   std::vector<double> hc;
   // device buffers
   int32_t* d_prog = nullptr;
+  size_t prog_cap = 0;  // words allocated for d_prog (updates may change the size)
   int64_t* d_passoff = nullptr;
   int64_t* d_jobs = nullptr;
   uint64_t* d_z = nullptr;
@@ -1530,14 +1497,14 @@ static qsv_status batch_materialise(qsv_batch* b, int t, bool check_only_structu
                     "batched circuits support gates on at most 2 qubits (circuit " +
                         std::to_string(ci) + ")");
       b->passoff.push_back((int64_t)b->hprog.size());
-      if (!emit_pass<T>(st, P, n, c, RB, b->hprog)) return fail(QSV_ERR_UNSUPPORTED, "a fused tile layer does not fit a round block");
+      if (!emit_pass<T>(st, P, n, c, RB, b->hprog)) return fail(QSV_ERR_UNSUPPORTED, "a fused tile pass could not be encoded");
       ++np;
     }
     if (np == 0) {  // empty circuit: one pass with no rounds still builds and reduces the state
       Step st;
       for (int q = 0; q < tc; ++q) st.S.push_back(q);
       b->passoff.push_back((int64_t)b->hprog.size());
-      if (!emit_pass<T>(st, P, n, c, RB, b->hprog)) return fail(QSV_ERR_UNSUPPORTED, "a fused tile layer does not fit a round block");
+      if (!emit_pass<T>(st, P, n, c, RB, b->hprog)) return fail(QSV_ERR_UNSUPPORTED, "a fused tile pass could not be encoded");
       np = 1;
     }
     npass[ci] = np;
@@ -1585,7 +1552,10 @@ static qsv_status batch_build(qsv_batch* b, int t) {
     }
     return QSV_OK;
   };
-  if ((st = dalloc((void**)&b->d_prog, b->hprog.size() * 4))) return st;
+  // Tables and per-group phases that come out as identities are left out,
+  // so new angles can change the program size: keep room for updates.
+  b->prog_cap = b->hprog.size() * 2 + 4096;
+  if ((st = dalloc((void**)&b->d_prog, b->prog_cap * 4))) return st;
   if ((st = dalloc((void**)&b->d_passoff, b->passoff.size() * 8))) return st;
   if ((st = dalloc((void**)&b->d_jobs, b->job_words.size() * 8))) return st;
   if ((st = dalloc((void**)&b->d_z, b->hz.size() * 8))) return st;
@@ -1789,14 +1759,22 @@ qsv_status qsv_batch_update(qsv_batch* b, const qsv_op* ops) {
     }
   }
   std::vector<qsv_op> keep = b->ops;
+  std::vector<int32_t> keep_prog = b->hprog;
+  std::vector<int64_t> keep_off = b->passoff;
   b->ops.assign(ops, ops + nops);
-  const size_t words = b->hprog.size();
+  const size_t npass = b->passoff.size();
   qsv_status st = b->dt == QSV_C64 ? batch_materialise<float>(b, b->tile_bits, true)
                                    : batch_materialise<double>(b, b->tile_bits, true);
   b->ops = keep;
-  if (st) return st;
-  if (b->hprog.size() != words) return fail(QSV_ERR_STATE, "program size changed on update");
-  QSV_HIP(hipMemcpyAsync(b->d_prog, b->hprog.data(), words * 4, hipMemcpyHostToDevice, b->stream));
+  if (!st && (b->passoff.size() != npass || b->hprog.size() > b->prog_cap))
+    st = fail(QSV_ERR_STATE, "the updated programs do not fit the batch's program buffer");
+  if (st) {  // the batch keeps its previous programs
+    b->hprog.swap(keep_prog);
+    b->passoff.swap(keep_off);
+    return st;
+  }
+  QSV_HIP(hipMemcpyAsync(b->d_prog, b->hprog.data(), b->hprog.size() * 4, hipMemcpyHostToDevice, b->stream));
+  QSV_HIP(hipMemcpyAsync(b->d_passoff, b->passoff.data(), npass * 8, hipMemcpyHostToDevice, b->stream));
   QSV_HIP(hipStreamSynchronize(b->stream));
   return QSV_OK;
 }

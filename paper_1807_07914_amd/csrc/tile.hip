@@ -17,9 +17,9 @@
 // XOR swizzle of the amplitude index so that power-of-two strides between
 // the lanes of a round do not hit one bank.  Within a round each thread holds
 // 2^RB amplitudes in registers and applies the round's layers with fully
-// unrolled code.  The round's program is one block of kRoundWords words:
-// every wavefront loads its layer lines into two VGPRs one round ahead and
-// reads them with v_readlane, and reads its table lines with scalar loads.
+// unrolled code.  The round's program (header, one fixed-layout record per
+// layer, aux words and tables) is read with scalar loads: the addresses are
+// uniform, and every field lands in a scalar register.
 #include "internal.hpp"
 #include "tile.hpp"
 
@@ -36,36 +36,12 @@ struct SwzBits<double> {
   static constexpr int B = 4;
 };
 
-__device__ __forceinline__ int rl(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
 // words per real: one per float, two per double
 template <typename T>
 struct WordsPer {
   static constexpr int W = sizeof(T) / 4;
 };
-
-// Layer lines of a round block (words 0 .. kLayerWords-1, the first two of
-// its kRoundLines lines) held in two VGPRs, written under a full exec mask.
-// Every read is a v_readlane with the line chosen on the scalar side: the
-// layer loop may run with some lanes off (fewer groups than threads), and a
-// VGPR computed there would hold stale values in the lanes that readlane
-// addresses.  Table lines are read with scalar loads from global memory.
-struct Blk {
-  int l[2];
-  __device__ __forceinline__ int word(int k) const {
-    return k < 64 ? rl(l[0], k) : rl(l[1], k & 63);
-  }
-  template <typename T>
-  __device__ __forceinline__ T real(int k) const;
-};
-template <>
-__device__ __forceinline__ float Blk::real<float>(int k) const {
-  return __int_as_float(word(k));
-}
-template <>
-__device__ __forceinline__ double Blk::real<double>(int k) const {
-  return __hiloint2double(word(k + 1), word(k));
-}
 
 // x <- (1 + c) x, in place (c = -2 negates, c = 0 leaves x as it is)
 template <typename T>
@@ -286,31 +262,53 @@ __device__ __forceinline__ int const_bit(int kind, int val, uint32_t lg, uint64_
   return kind == TK_FREE ? (int)((lg >> val) & 1u) : (int)((base >> val) & 1ull);
 }
 
-// The rounds of one tile pass over the tile held in LDS at `tb`.  `nb` holds
-// the first round's layer lines, already loaded; the later ones are read one
-// round ahead from a copy in LDS (`blds`, kLayerWords words per round) when
-// LDSB, else from the pass program in global memory (`bglob`, where table
-// lines are always read with scalar loads).  Every round ends with a barrier.
-template <typename T, int TBMAX, int RB, bool FULL, bool LDSB>
-__device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t* __restrict__ blds,
-                                           const int32_t* __restrict__ bglob, Blk nb, int nrounds, int t,
-                                           uint64_t base) {
+// Real k of a layer record held in scalar registers (one word per float,
+// two per double).
+template <typename T>
+__device__ __forceinline__ T rec_real(const int32_t* w, int k);
+template <>
+__device__ __forceinline__ float rec_real<float>(const int32_t* w, int k) {
+  return __int_as_float(w[k]);
+}
+template <>
+__device__ __forceinline__ double rec_real<double>(const int32_t* w, int k) {
+  return __hiloint2double(w[k + 1], w[k]);
+}
+template <typename T>
+__device__ __forceinline__ T aux_real(const int32_t* __restrict__ ap, int k);
+template <>
+__device__ __forceinline__ float aux_real<float>(const int32_t* __restrict__ ap, int k) {
+  return __int_as_float(ap[k]);
+}
+template <>
+__device__ __forceinline__ double aux_real<double>(const int32_t* __restrict__ ap, int k) {
+  return __hiloint2double(ap[k + 1], ap[k]);
+}
+
+// The rounds of one tile pass (program `pass`, layout in tile.hpp) over the
+// tile held in LDS at `tb`.  Round headers, layer records, aux words and
+// tables are read with scalar loads (the addresses are uniform), so every
+// field lands in a scalar register.  Every round ends with a barrier.
+template <typename T, int TBMAX, int RB, bool FULL>
+__device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t* __restrict__ pass, int t,
+                                           int nns, uint64_t base) {
   constexpr int NR = 1 << RB;
   constexpr int SB = SwzBits<T>::B;
   constexpr int WT = WordsPer<T>::W;
+  constexpr int LR = LayerRec<T>::W;
   const int ng = 1 << (t - RB);
-  const int lane = threadIdx.x & 63;
+  const int nrounds = pass[3];
+  const int32_t* roff = pass + 4 + t + nns;
   for (int r = 0; r < nrounds; ++r) {
-    const Blk b = nb;
-    const int32_t* bp = bglob + (size_t)r * kRoundWords;
-    if (r + 1 < nrounds) {  // prefetch the next round's layer lines
-      const int32_t* nbp = LDSB ? blds + (size_t)(r + 1) * kLayerWords : bglob + (size_t)(r + 1) * kRoundWords;
-      nb.l[0] = nbp[lane];
-      nb.l[1] = nbp[64 + lane];
-    }
-    const int w0 = rl(b.l[0], 0);
-    const int nlayers = w0 & 0xffff;  // the first layer starts at word w0 >> 16
-    const uint32_t free_mask = (uint32_t)rl(b.l[0], 1);
+    const int32_t* rb = pass + roff[r];
+    const int nlayers = rb[0];
+    const uint32_t free_mask = (uint32_t)rb[1];
+    // The LDS offset of combination m is the XOR of the offsets of its
+    // register bits (deposit and swizzle are XOR-linear): walking m in
+    // Gray-code order takes one XOR per amplitude.
+    uint32_t bofs[RB];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) bofs[j] = (uint32_t)rb[2 + j];
     for (int gi = threadIdx.x; gi < ng; gi += kTileThreads) {
       // deposit gi into the free local bits
       uint32_t lg = 0, fm = free_mask;
@@ -320,12 +318,6 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
         fm ^= low;
       }
       const uint32_t sgb = tile_swizzle(lg, SB) * (uint32_t)sizeof(cpx<T>);
-      // The LDS offset of combination m is the XOR of the offsets of its
-      // register bits (deposit and swizzle are XOR-linear): walking m in
-      // Gray-code order takes one XOR per amplitude.
-      uint32_t bofs[RB];
-#pragma unroll
-      for (int j = 0; j < RB; ++j) bofs[j] = (uint32_t)rl(b.l[0], 2 + (1 << j));
       cpx<T> a[NR];
       {
         uint32_t ad = sgb;
@@ -336,13 +328,16 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
         }
       }
 
-      int k = w0 >> 16;
       for (int o = 0; o < nlayers; ++o) {
-        const int flags = b.word(k), len = b.word(k + 1);
-        int p = k + 2;
-        if (flags & LT_TAB) table_step<T, RB>(a, bp + 64 * b.word(p++));
+        int32_t w[LR];
+#pragma unroll
+        for (int i = 0; i < LR; ++i) w[i] = rb[kRoundHeader + o * LR + i];
+        const int flags = w[0];
+        const int32_t* __restrict__ ap = rb + w[3];  // aux words of the record
+        int p = 0;
+        if (flags & LT_TAB) table_step<T, RB>(a, rb + w[1]);
         if (flags & LT_CZR) {
-          const uint32_t pairs = (uint32_t)b.word(p++);
+          const uint32_t pairs = (uint32_t)w[2];
 #define QSV_CZR(J, K) \
   if ((K) < RB && ((pairs >> cz_pair_index(J, K)) & 1u)) cz_pair<T, RB, J, ((K) < RB ? (K) : (J) + 1)>(a);
           QSV_CZR(0, 1)
@@ -360,12 +355,12 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
         if (flags & LT_CZF) {
           // per-lane parity of the conditions for each register bit first,
           // then one pass over the amplitudes per bit that has entries
-          const int ne = b.word(p++);
+          const int ne = ap[p++];
           uint32_t zm = 0, jm = 0;
           for (int e = 0; e < ne; ++e) {
-            const int w = b.word(p++);
-            const int j = w & 15, val = w >> 8;
-            const uint32_t on = ((w >> 4) & 15) == TK_FREE ? (lg >> val) & 1u : (uint32_t)((base >> val) & 1ull);
+            const int ew = ap[p++];
+            const int j = ew & 15, val = ew >> 8;
+            const uint32_t on = ((ew >> 4) & 15) == TK_FREE ? (lg >> val) & 1u : (uint32_t)((base >> val) & 1ull);
             zm ^= on << j;
             jm |= 1u << j;
           }
@@ -380,28 +375,28 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
         }
         if (flags & LT_SIGN) {
           int par = 0;
-          const int nd = b.word(p++);
+          const int nd = ap[p++];
           for (int q = 0; q < nd; ++q, p += 2)
-            par ^= __popc(lg & (lg >> b.word(p)) & (uint32_t)b.word(p + 1));
-          const int nfc = b.word(p++);
+            par ^= __popc(lg & (lg >> ap[p]) & (uint32_t)ap[p + 1]);
+          const int nfc = ap[p++];
           for (int q = 0; q < nfc; ++q, p += 2)
-            par ^= (int)(((base >> b.word(p)) & 1ull) & ((lg >> b.word(p + 1)) & 1u));
-          const int ncc = b.word(p++);
+            par ^= (int)(((base >> ap[p]) & 1ull) & ((lg >> ap[p + 1]) & 1u));
+          const int ncc = ap[p++];
           for (int q = 0; q < ncc; ++q, p += 2)
-            par ^= (int)((base >> b.word(p)) & (base >> b.word(p + 1)) & 1ull);
+            par ^= (int)((base >> ap[p]) & (base >> ap[p + 1]) & 1ull);
           const T cg = (par & 1) ? T(-2) : T(0);  // per lane
 #pragma unroll
           for (int m = 0; m < NR; ++m) scale1(a[m], cg);
         }
         if (flags & LT_PHASEL) {
           {
-            const int j = b.word(p), nt = b.word(p + 1);
+            const int j = ap[p], nt = ap[p + 1];
             p += 2;
             cpx<T> w{T(1), T(0)};
             for (int q = 0; q < nt; ++q, p += 3 + 2 * WT) {
-              const uint32_t lgm = (uint32_t)b.word(p);
-              const uint64_t om = ((uint64_t)(uint32_t)b.word(p + 2) << 32) | (uint32_t)b.word(p + 1);
-              const cpx<T> rr{b.real<T>(p + 3), b.real<T>(p + 3 + WT)};
+              const uint32_t lgm = (uint32_t)ap[p];
+              const uint64_t om = ((uint64_t)(uint32_t)ap[p + 2] << 32) | (uint32_t)ap[p + 1];
+              const cpx<T> rr{aux_real<T>(ap, p + 3), aux_real<T>(ap, p + 3 + WT)};
               if ((lg & lgm) == lgm && (base & om) == om) w = cmul(rr, w);
             }
             // w = (+-|w|) exp(i phi), |phi| <= pi/2: three shears and a scale
@@ -421,9 +416,9 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
         if (FULL && (flags & LT_RAWD)) {
           // a diagonal factor d = (1 + c) exp(i phi) per operand value, as
           // (p, q, c) triples: PHASE1 two (by the qubit's bit), DIAG2 four
-          const int type = b.word(p), ka = b.word(p + 1), va = b.word(p + 2);
-          const int kb = type == RAW_DIAG2 ? b.word(p + 3) : TK_REG;
-          const int vb = type == RAW_DIAG2 ? b.word(p + 4) : 0;
+          const int type = ap[p], ka = ap[p + 1], va = ap[p + 2];
+          const int kb = type == RAW_DIAG2 ? ap[p + 3] : TK_REG;
+          const int vb = type == RAW_DIAG2 ? ap[p + 4] : 0;
           const int f0 = p + (type == RAW_DIAG2 ? 5 : 3);
           const uint32_t ma = ka == TK_REG ? (uint32_t)va : (const_bit(ka, va, lg, base) ? ~0u : 0u);
           const uint32_t mb = kb == TK_REG ? (uint32_t)vb : (const_bit(kb, vb, lg, base) ? ~0u : 0u);
@@ -433,9 +428,9 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int at = f0 + 3 * (e < nfac ? e : 0) * WT;
-            fp[e] = b.real<T>(at);
-            fq[e] = b.real<T>(at + WT);
-            fc[e] = b.real<T>(at + 2 * WT);
+            fp[e] = aux_real<T>(ap, at);
+            fq[e] = aux_real<T>(ap, at + WT);
+            fc[e] = aux_real<T>(ap, at + 2 * WT);
           }
 #pragma unroll
           for (int m = 0; m < NR; ++m) {
@@ -450,8 +445,8 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
         // rotations on register bits, ascending
 #define QSV_ROT(J)                                                                    \
   if ((J) < RB && (flags & (LT_ROT0 << (J)))) {                                       \
-    const T pj = b.real<T>(p), qj = b.real<T>(p + WT);                                \
-    p += 2 * WT;                                                                      \
+    const T pj = rec_real<T>(w, kRecRot + 2 * (J) * WT);                              \
+    const T qj = rec_real<T>(w, kRecRot + (2 * (J) + 1) * WT);                        \
     shears<T, RB, ((J) < RB ? (J) : 0)>(a, pj, qj, (flags & (LT_SHEAR3 << (J))) != 0); \
   }
         QSV_ROT(0)
@@ -461,27 +456,26 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
         QSV_ROT(4)
 #undef QSV_ROT
         if (FULL && (flags & LT_PERM2)) {
-          dispatch_perm2<T, RB>(a, b.word(p), b.word(p + 1), b.word(p + 2));
+          dispatch_perm2<T, RB>(a, ap[p], ap[p + 1], ap[p + 2]);
           p += 3;
         }
         if (FULL && (flags & LT_U2)) {
-          const int j0 = b.word(p), j1 = b.word(p + 1);
+          const int j0 = ap[p], j1 = ap[p + 1];
           M4<T> U;
 #pragma unroll
           for (int e = 0; e < 16; ++e)
-            U.m[e] = cpx<T>{b.real<T>(p + 2 + 2 * e * WT), b.real<T>(p + 2 + (2 * e + 1) * WT)};
+            U.m[e] = cpx<T>{aux_real<T>(ap, p + 2 + 2 * e * WT), aux_real<T>(ap, p + 2 + (2 * e + 1) * WT)};
           p += 2 + 32 * WT;
           dispatch_u2<T, RB>(a, j0, j1, U);
         }
         if (FULL && (flags & LT_U1)) {
-          const int j = b.word(p);
+          const int j = ap[p];
           M2<T> U;
 #pragma unroll
           for (int e = 0; e < 4; ++e)
-            U.m[e] = cpx<T>{b.real<T>(p + 1 + 2 * e * WT), b.real<T>(p + 1 + (2 * e + 1) * WT)};
+            U.m[e] = cpx<T>{aux_real<T>(ap, p + 1 + 2 * e * WT), aux_real<T>(ap, p + 1 + (2 * e + 1) * WT)};
           dispatch_u1<T, RB>(a, j, U);
         }
-        k += len;
       }
       {
         // recomputed rather than kept from the load walk: 2^RB live
@@ -528,12 +522,9 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
   constexpr int WT = WordsPer<T>::W;                      // words per real
   __shared__ cpx<T> tile[1 << TBMAX];
   __shared__ uint64_t segoff[1 << (TBMAX - 4)];
-  const int lane = threadIdx.x & 63;
-
-  const int t = prog[0], c = prog[1], nns = prog[2], nrounds = prog[3];
+  const int t = prog[0], c = prog[1], nns = prog[2];
   const int32_t* S = prog + 4;
   const int32_t* nonS = S + t;
-  const int32_t* blocks = prog + ((4 + t + nns + 63) & ~63);
   uint64_t base = 0;
   for (int i = 0; i < nns; ++i) base |= ((tid >> i) & 1ull) << nonS[i];
   const int nseg = 1 << (t - c);
@@ -543,10 +534,6 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
       if ((h >> j) & 1) o |= 1ull << S[c + j];
     segoff[h] = o;
   }
-  // first round block (prefetched while the tile loads)
-  Blk nb;
-  nb.l[0] = nrounds > 0 ? blocks[lane] : 0;
-  nb.l[1] = nrounds > 0 ? blocks[64 + lane] : 0;
   __syncthreads();
 
   // ---- load the tile (coalesced 16-byte vectors) into LDS
@@ -577,7 +564,7 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
   __syncthreads();
 
   // ---- rounds
-  run_rounds<T, TBMAX, RB, FULL, false>(reinterpret_cast<char*>(tile), nullptr, blocks, nb, nrounds, t, base);
+  run_rounds<T, TBMAX, RB, FULL>(reinterpret_cast<char*>(tile), prog, t, nns, base);
 
   // ---- Z-string sum over the tile (FP64)
   double acc = 0.0;
@@ -647,14 +634,14 @@ struct StageVec<double> {
 };
 
 // Pipelined tile pass for one state.  A persistent workgroup walks the tiles
-// blockIdx.x, blockIdx.x + gridDim.x, ...  The pass's round blocks are copied
-// to LDS once, and while the rounds of one tile run, each thread already has
+// blockIdx.x, blockIdx.x + gridDim.x, ...  While the rounds of one tile run,
+// each thread already has
 // its share of the next tile in flight from HBM into registers (VPT 16-byte
 // vectors: 64 VGPRs for a 64 KiB tile), so that HBM traffic overlaps the
-// arithmetic instead of alternating with it.  The layer lines of every round
-// are read from LDS so that waiting on them never waits on those loads
-// (loads complete in order).  Used for lean passes over tiles of exactly
-// 2^TBMAX amplitudes with at most kPipeMaxRounds rounds.
+// arithmetic instead of alternating with it.  The rounds read their program
+// with scalar loads only, so no wait inside them covers those vector loads
+// (which complete in order).  Used for lean passes over tiles of exactly
+// 2^TBMAX amplitudes.
 template <typename T, int TBMAX, int RB, bool FULL, int MINWG>
 __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile_pipe(cpx<T>* __restrict__ psi,
                                                                    const int32_t* __restrict__ prog,
@@ -664,16 +651,10 @@ __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile_pipe(cpx<T>* __res
   constexpr int SB = SwzBits<T>::B;
   constexpr int CMIN = SwzBits<T>::B;  // every pass keeps the low CMIN qubits (fewer only below CMIN qubits)
   __shared__ cpx<T> tile[1 << TBMAX];
-  __shared__ int32_t blk[kPipeMaxRounds * kLayerWords];
   __shared__ uint64_t segoff[1 << (TBMAX - CMIN)];
-  const int lane = threadIdx.x & 63;
-
-  const int t = prog[0], c = prog[1], nns = prog[2], nrounds = prog[3];
+  const int t = prog[0], c = prog[1], nns = prog[2];
   const int32_t* S = prog + 4;
   const int32_t* nonS = S + t;
-  const int32_t* blocks = prog + ((4 + t + nns + 63) & ~63);
-  for (int i = threadIdx.x; i < nrounds * kLayerWords; i += kTileThreads)
-    blk[i] = blocks[(i / kLayerWords) * kRoundWords + i % kLayerWords];
   const int nseg = 1 << (t - c);
   for (int h = threadIdx.x; h < nseg; h += kTileThreads) {
     uint64_t o = 0;
@@ -719,10 +700,7 @@ __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile_pipe(cpx<T>* __res
   if (tid + gridDim.x < ntiles) fetch(tid + gridDim.x);
   for (;;) {
     const uint64_t base = tile_base(tid);
-    Blk nb;
-    nb.l[0] = nrounds > 0 ? blk[lane] : 0;
-    nb.l[1] = nrounds > 0 ? blk[64 + lane] : 0;
-    run_rounds<T, TBMAX, RB, FULL, true>(reinterpret_cast<char*>(tile), blk, blocks, nb, nrounds, t, base);
+    run_rounds<T, TBMAX, RB, FULL>(reinterpret_cast<char*>(tile), prog, t, nns, base);
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
       const uint32_t l = (uint32_t)(threadIdx.x + k * kTileThreads) * A;
@@ -869,7 +847,7 @@ hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const i
   // The pipelined kernel holds the next tile in registers: lean passes over
   // full-size tiles only (for half-size tiles the extra registers and LDS
   // cost a workgroup per compute unit, more than the overlap gains).
-  const bool pipe = !full && !small && t - c <= tbits - SwzBits<T>::B && prog_host[3] <= kPipeMaxRounds;
+  const bool pipe = !full && !small && t - c <= tbits - SwzBits<T>::B;
   if (small) {
     if (full) return launch_pass<T, TB - 1, RB, true, 2>(psi, prog_dev, ntiles, pipe, st);
     return launch_pass<T, TB - 1, RB, false, 3>(psi, prog_dev, ntiles, pipe, st);

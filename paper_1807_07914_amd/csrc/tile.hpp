@@ -16,46 +16,53 @@
 // outside S is constant per tile (read from the tile base index).
 //
 // Program layout (int32 words):
-//   pass header : t, c, n_nonS, n_blocks, S[t], nonS[n_nonS], padded to a
-//                 multiple of 64 words
-//   round block : exactly kRoundWords words in kRoundLines lines of 64.
-//                 Lines 0 and 1 (the layer lines) are held by every wavefront
-//                 in two VGPRs and read with readlane:
-//                 [0] n_layers | (word offset of the first layer) << 16
-//                 [1] free-bit mask  [2 .. 2+2^RB) swizzled LDS byte offsets
-//                 of the register combinations m, then the layers.  Lines
-//                 kTableLine0 .. kRoundLines-1 hold tables, read with scalar
-//                 loads.
-//   layer       : flags, n_words, then the payload of every step present,
-//                 in this order (all steps are optional):
-//     LT_TAB    : table line.  Amplitude m is multiplied by the complex
-//                 factor z_m = (re, im) at entry m of the table line (two
-//                 words per entry for float, four for double): phases,
-//                 signs and magnitudes of diagonal factors on register bits.
-//     LT_CZR    : pair set P.  For every CZ pair (j, k) in P (bit
+//   pass header : t, c, n_nonS, n_rounds, S[t], nonS[n_nonS],
+//                 round_off[n_rounds] (word offset of each round block from
+//                 the start of the pass), padded to a multiple of 16 words.
+//   round block : a header of kRoundHeader words: [0] n_layers, [1] free-bit
+//                 mask, [2 + j] the swizzled LDS byte offset of register bit
+//                 j (the offset of register combination m is the XOR of
+//                 those of its bits); then n_layers layer records of
+//                 LayerRec<T>::W words; then the aux words of the records;
+//                 then the tables, 64 words each.  Offsets in a record count
+//                 words from the start of its round block.
+//   layer record: [0] flags, [1] table offset (LT_TAB), [2] CZ pair set
+//                 (LT_CZR), [3] aux offset: the payloads of the steps LT_CZF,
+//                 LT_SIGN, LT_PHASEL, LT_RAWD and LT_PERM2 / LT_U2 / LT_U1
+//                 that are present follow one another from there, in this
+//                 order; [kRecRot + 2 j W] p_j and [kRecRot + (2 j + 1) W] q_j
+//                 of the rotation on register bit j (W words per real).  Every
+//                 field has a fixed position, so the kernel reads a record
+//                 with scalar loads straight into scalar registers.
+//   steps, in the order a layer applies them (all optional):
+//     LT_TAB    : amplitude m is multiplied by the complex factor
+//                 z_m = (re, im) at entry m of the table (two words per entry
+//                 for float, four for double): phases, signs and magnitudes
+//                 of diagonal factors on register bits.
+//     LT_CZR    : pair set P (record word 2).  For every CZ pair (j, k) in P (bit
 //                 cz_pair_index(j, k)), amplitudes with register bits j and
 //                 k both set change sign.
-//     LT_CZF    : n, then n words j | kind << 4 | val << 8.  Amplitudes
+//     LT_CZF    : aux n, then n words j | kind << 4 | val << 8.  Amplitudes
 //                 with register bit j set change sign when the operand
 //                 (kind 1: free local bit val of the group, kind 2: outside
 //                 qubit val of the tile) is 1: a CZ between a register
 //                 qubit and a qubit that is constant over the group.
-//     LT_SIGN   : nd, (d, M)*nd, nfc, (q, f)*nfc, ncc, (qa, qb)*ncc.
+//     LT_SIGN   : aux nd, (d, M)*nd, nfc, (q, f)*nfc, ncc, (qa, qb)*ncc.
 //                 Every amplitude of the group changes sign when the group
 //                 parity sum_d popcount(lg & (lg >> d) & M)
 //                 + sum_(q,f) bit(q) bit(lg, f) + sum_(qa,qb) bit(qa) bit(qb)
 //                 is odd (CZs among free bits and outside qubits).
-//     LT_PHASEL : j, nt, (lgmask, omask_lo, omask_hi, r)*nt:
+//     LT_PHASEL : aux j, nt, (lgmask, omask_lo, omask_hi, r)*nt:
 //                 per-group factor w = product of r over the terms whose free
 //                 bits lgmask are all set in the group and whose outside
 //                 qubits omask are all set in the tile, applied to the
 //                 amplitudes with register bit j set (every amplitude if j < 0)
-//     LT_RAWD   : type, payload, for diagonal factors that may be zero:
+//     LT_RAWD   : aux type, payload, for diagonal factors that may be zero:
 //                 RAW_PHASE1 : kind, val, f[2]          factor f[bit of the qubit]
 //                 RAW_DIAG2  : kindA, valA, kindB, valB, f[4]  factor f[bitA + 2 bitB]
 //                 each factor (1 + c) exp(i phi) stored as p, q, c
 //                 (p = -tan(phi / 2), q = sin(phi), |phi| <= pi/2)
-//     rotations : for every flagged register bit j, ascending: p, q.
+//     rotations : for every flagged register bit j, ascending: p_j, q_j.
 //                 In-place shears x0 += p x1, x1 += q x0 on the amplitude
 //                 pairs of bit j, and a third x0 += p x1 when the three-shear
 //                 flag of j is set.  Three shears with p = -tan(theta / 2),
@@ -63,12 +70,12 @@
 //                 p = -tan(theta), q = sin(theta) cos(theta) are
 //                 diag(1 / cos(theta), cos(theta)) applied after that
 //                 rotation, a scale the planner takes out in a later table.
-//     LT_PERM2  : j0, j1, code     CNOT / SWAP as a register permutation on
+//     LT_PERM2  : aux j0, j1, code  CNOT / SWAP as a register permutation on
 //                 bits j0 < j1 (m = b0 + 2 b1): code 0 swaps m = 1 <-> 3
 //                 (CNOT, control j0), 1 swaps 2 <-> 3 (CNOT, control j1),
 //                 2 swaps 1 <-> 2 (SWAP)
-//     LT_U2     : j0, j1, U[4x4]   4x4 on register bits j0 < j1 (j0 = LSB)
-//     LT_U1     : j, U[2x2]        2x2 on register bit j
+//     LT_U2     : aux j0, j1, U[4x4]  4x4 on register bits j0 < j1 (j0 = LSB)
+//     LT_U1     : aux j, U[2x2]       2x2 on register bit j
 //   Operand kinds: 0 register (val = mask over m), 1 free (val = local bit),
 //   2 outside (val = global qubit).  Reals are stored in the state's
 //   precision, one word per float, two words (low, high) per double.
@@ -103,11 +110,21 @@ enum RawDiagType : int32_t { RAW_PHASE1 = 4, RAW_DIAG2 = 5 };
 enum TileOperandKind : int32_t { TK_REG = 0, TK_FREE = 1, TK_OUT = 2 };
 
 constexpr int kTileThreads = 256;
-constexpr int kRoundLines = 8;                 // 64-word lines per round block
-constexpr int kRoundWords = 64 * kRoundLines;  // words per round block
-constexpr int kLayerWords = 128;               // layers lie in words [2 + 2^RB, 128): lines 0, 1
-constexpr int kTableLine0 = 2;                 // lines that may hold tables: 2 .. 7
-constexpr int kPipeMaxRounds = 28;             // rounds whose layer lines the pipelined kernel keeps in LDS
+constexpr int kRoundHeader = 16;  // words of a round block header
+constexpr int kRecRot = 4;        // first rotation word of a layer record
+constexpr int kTableWords = 64;   // words of a table
+
+// words of a layer record: 4 + 2 * RB reals (RB = 5 floats, RB = 4 doubles)
+template <typename T>
+struct LayerRec;
+template <>
+struct LayerRec<float> {
+  static constexpr int W = 16;
+};
+template <>
+struct LayerRec<double> {
+  static constexpr int W = 24;
+};
 
 // Index of the CZ between register bits j != k in an LT_CZR pair set:
 // (0,1)=0, (0,2)=1, (1,2)=2, (0,3)=3, ... (pairs ordered by the larger bit).

@@ -2,12 +2,13 @@
 
 Executes the int32 program image that the library's planner emits (exported
 by the debug call ``qsv_debug_plan_program``) on a complex128 NumPy state,
-decoding every word the way the tile kernel does: pass header, 256-word
-round blocks, the XOR-swizzled LDS layout, register groups and the U1 / U2 /
-SIGN / PHASE1 / DIAG2 ops.  Comparing its output with the CPU oracle checks
-the planner and the encoder on machines without a GPU; it also asserts the
-block layout rules the kernel relies on (no op straddles a 64-word line
-unless it is longer than one, block bounds).
+decoding every word the way the tile kernel does: pass header and round
+offsets, round blocks (header, fixed-layout layer records, aux words,
+tables), the XOR-swizzled LDS layout, register groups and every step.
+Comparing its output with the CPU oracle checks the planner and the encoder
+on machines without a GPU; it also asserts the layout rules the kernel
+relies on (record fields in range, aux words consumed exactly, tables inside
+the program).
 """
 from __future__ import annotations
 
@@ -17,16 +18,15 @@ import numpy as np
 
 from paper_1807_07914_amd import qsv
 
-LINES = 8
-ROUND_WORDS = 64 * LINES
-TABLE_LINE0 = 2
-LAYER_WORDS = 128
+ROUND_HEADER = 16   # words of a round block header
+REC_ROT = 4         # first rotation word of a layer record
+TABLE_WORDS = 64
 LT_TAB, LT_CZR, LT_SIGN, LT_PHASEL, LT_RAWD, LT_CZF = 1, 2, 4, 8, 16, 32
 LT_ROT0, LT_SHEAR3 = 1 << 8, 1 << 16
 LT_PERM2, LT_U2, LT_U1 = 1 << 24, 1 << 25, 1 << 26
 RAW_PHASE1, RAW_DIAG2 = 4, 5
 TK_REG, TK_FREE, TK_OUT = 0, 1, 2
-CFG = {"c64": dict(RB=5, SB=5, WT=1), "c128": dict(RB=4, SB=4, WT=2)}
+CFG = {"c64": dict(RB=5, SB=5, WT=1, LR=16), "c128": dict(RB=4, SB=4, WT=2, LR=24)}
 
 
 def program(n, dtype, ops, tile=0):
@@ -105,14 +105,27 @@ def _shear3(x, p, q):
     return complex(re, im)
 
 
+def _round_blocks(words, off, t, nns):
+    """(start, n_layers, free mask, bit offsets) of each round block."""
+    nrounds = int(words[off + 3])
+    roff = [int(x) for x in words[off + 4 + t + nns: off + 4 + t + nns + nrounds]]
+    out = []
+    for r in range(nrounds):
+        rb = off + roff[r]
+        assert roff[r] > 0 and rb + ROUND_HEADER <= len(words)
+        out.append(rb)
+    return out
+
+
 def run_pass(psi, n, words, off, cfg):
-    RB, SB, WT = cfg["RB"], cfg["SB"], cfg["WT"]
+    RB, SB, WT, LR = cfg["RB"], cfg["SB"], cfg["WT"], cfg["LR"]
     NR = 1 << RB
-    t, c, nns, nblocks = (int(x) for x in words[off:off + 4])
+    words = [int(x) for x in words]
+    t, c, nns = (int(x) for x in words[off:off + 3])
     S = [int(x) for x in words[off + 4:off + 4 + t]]
     nonS = [int(x) for x in words[off + 4 + t:off + 4 + t + nns]]
     assert S == sorted(S) and S[:c] == list(range(c))
-    b0 = off + ((4 + t + nns + 63) & ~63)
+    blocks = _round_blocks(words, off, t, nns)
     esz = 8 * WT  # bytes per amplitude: the header holds LDS byte offsets
     for tid in range(1 << (n - t)):
         base = deposit(tid, nonS)
@@ -120,33 +133,37 @@ def run_pass(psi, n, words, off, cfg):
         gidx = [base | deposit(l, S) for l in range(1 << t)]
         for l in range(1 << t):
             lds[swizzle(l, SB)] = psi[gidx[l]]
-        for r in range(nblocks):
-            blk = [int(x) for x in words[b0 + r * ROUND_WORDS: b0 + (r + 1) * ROUND_WORDS]]
-            nlay, k0, free_mask = blk[0] & 0xffff, blk[0] >> 16, blk[1] & 0xffffffff
-            assert k0 == 2 + NR
-            assert all((blk[2 + m] & 0xffffffff) % esz == 0 for m in range(NR))
-            lmsw = [(blk[2 + m] & 0xffffffff) // esz for m in range(NR)]
+        for rb in blocks:
+            blk = words[rb:]  # offsets in a round block count from its start
+            nlay, free_mask = blk[0], blk[1] & 0xffffffff
+            assert all((blk[2 + j] & 0xffffffff) % esz == 0 for j in range(RB))
+            bsw = [(blk[2 + j] & 0xffffffff) // esz for j in range(RB)]
+            lmsw = []
+            for m in range(NR):
+                o_ = 0
+                for j in range(RB):
+                    if (m >> j) & 1:
+                        o_ ^= bsw[j]
+                lmsw.append(o_)
             for gi in range(1 << (t - RB)):
                 lg = pdep_mask(gi, free_mask)
                 sg = swizzle(lg, SB)
                 a = [lds[sg ^ lmsw[m]] for m in range(NR)]
-                k = k0
-                low_table = LINES
-                for _ in range(nlay):
-                    flags, ln = blk[k], blk[k + 1]
-                    assert ln >= 2 and k + ln <= ROUND_WORDS
-                    p = k + 2
+                for li in range(nlay):
+                    rec = blk[ROUND_HEADER + li * LR: ROUND_HEADER + (li + 1) * LR]
+                    flags = rec[0]
+                    p = rec[3]  # aux words
+                    if flags & (LT_CZF | LT_SIGN | LT_PHASEL | LT_RAWD | LT_PERM2 | LT_U2 | LT_U1):
+                        assert p >= ROUND_HEADER + nlay * LR
                     if flags & LT_TAB:
-                        tl = blk[p]
-                        p += 1
-                        assert TABLE_LINE0 <= tl < LINES
-                        low_table = min(low_table, tl)
+                        tl = rec[1]
+                        assert tl >= ROUND_HEADER + nlay * LR and tl + TABLE_WORDS <= len(blk)
                         for m in range(NR):
-                            zr = _real(blk, 64 * tl + 2 * m * WT, WT)
-                            zi = _real(blk, 64 * tl + (2 * m + 1) * WT, WT)
+                            zr = _real(blk, tl + 2 * m * WT, WT)
+                            zi = _real(blk, tl + (2 * m + 1) * WT, WT)
                             a[m] = a[m] * complex(zr, zi)
                     if flags & LT_CZR:
-                        pairs = blk[p] & 0xffffffff; p += 1
+                        pairs = rec[2] & 0xffffffff
                         for kk in range(1, RB):
                             for jj in range(kk):
                                 if (pairs >> (kk * (kk - 1) // 2 + jj)) & 1:
@@ -222,8 +239,8 @@ def run_pass(psi, n, words, off, cfg):
                             a[m] = _shear3(a[m], fp_, fq_) * (1.0 + fc_)
                     for j in range(RB):
                         if flags & (LT_ROT0 << j):
-                            p_, q_ = _real(blk, p, WT), _real(blk, p + WT, WT)
-                            p += 2 * WT
+                            p_ = _real(rec, REC_ROT + 2 * j * WT, WT)
+                            q_ = _real(rec, REC_ROT + (2 * j + 1) * WT, WT)
                             three = bool(flags & (LT_SHEAR3 << j))
                             # three shears: |tan(theta/2)|, |sin(theta)| <= 1;
                             # two: |tan(theta)| <= 3.2 (cos >= 0.3), |sin cos| <= 1/2
@@ -270,10 +287,11 @@ def run_pass(psi, n, words, off, cfg):
                                 m2 = m | (1 << j)
                                 a[m], a[m2] = (U[0, 0] * a[m] + U[0, 1] * a[m2],
                                                U[1, 0] * a[m] + U[1, 1] * a[m2])
-                    assert p == k + ln, (hex(flags), p, k, ln)
-                    k += ln
-                # the layers lie in lines 0 and 1 and never run into a table line
-                assert k <= min(LAYER_WORDS, 64 * low_table)
+                    # the next record's aux words (if any) start where these end
+                    if li + 1 < nlay:
+                        nxt = blk[ROUND_HEADER + (li + 1) * LR + 3]
+                        if nxt and flags & (LT_CZF | LT_SIGN | LT_PHASEL | LT_RAWD | LT_PERM2 | LT_U2 | LT_U1):
+                            assert p == nxt, (hex(flags), p, nxt)
                 for m in range(NR):
                     lds[sg ^ lmsw[m]] = a[m]
         for l in range(1 << t):
@@ -351,19 +369,17 @@ def op_counts(words, steps, dtype):
             add("separate")
             continue
         off = int(st)
-        t, c, nns, nblocks = (int(x) for x in words[off:off + 4])
-        b0 = off + ((4 + t + nns + 63) & ~63)
-        add("blocks", nblocks)
-        for r in range(nblocks):
-            blk = words[b0 + r * ROUND_WORDS: b0 + (r + 1) * ROUND_WORDS]
-            k = int(blk[0]) >> 16
-            for _ in range(int(blk[0]) & 0xffff):
-                flags = int(blk[k])
+        t, c, nns = (int(x) for x in words[off:off + 3])
+        LR = CFG[dtype]["LR"]
+        blocks = _round_blocks(words, off, t, nns)
+        add("blocks", len(blocks))
+        for rb in blocks:
+            for li in range(int(words[rb])):
+                flags = int(words[rb + ROUND_HEADER + li * LR])
                 add("layers")
                 for bitv, name in STEP_NAMES:
                     if flags & bitv:
                         add(name)
                 add("ROT", bin((flags >> 8) & ((1 << RB) - 1)).count("1"))
                 add("ROT3", bin((flags >> 16) & ((1 << RB) - 1)).count("1"))
-                k += int(blk[k + 1])
     return out
