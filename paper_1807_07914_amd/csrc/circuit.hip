@@ -1202,26 +1202,25 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
     for (int k = 0; k < RB; ++k)
       hdr[2 + k] = (int32_t)(tile_swizzle(1u << rp.R[k], SB) * (uint32_t)(2 * sizeof(T)));
     prog.insert(prog.end(), hdr.begin(), hdr.end());
-    const size_t rec0 = prog.size();
-    prog.resize(rec0 + recs.size() * LR, 0);
+    std::vector<size_t> at(recs.size());
     for (size_t i = 0; i < recs.size(); ++i) {
-      int32_t* w = prog.data() + rec0 + i * LR;
+      at[i] = prog.size();
+      prog.resize(at[i] + LR, 0);
+      int32_t* w = prog.data() + at[i];
       w[0] = recs[i].flags;
       w[2] = recs[i].pairs;
       for (int e = 0; e < LR - kRecRot; ++e) w[kRecRot + e] = recs[i].rot[e];
+      if (recs[i].tab >= 0) {
+        const std::vector<int32_t>& tl = tables[recs[i].tab];
+        prog.insert(prog.end(), tl.begin(), tl.end());
+      }
     }
     for (size_t i = 0; i < recs.size(); ++i) {
       if (recs[i].aux.empty()) continue;
-      prog[rec0 + i * LR + 3] = (int32_t)(prog.size() - b0);
+      prog[at[i] + 3] = (int32_t)(prog.size() - b0);
       prog.insert(prog.end(), recs[i].aux.begin(), recs[i].aux.end());
     }
     while ((prog.size() - b0) % 16) prog.push_back(0);
-    for (size_t i = 0; i < recs.size(); ++i) {
-      if (recs[i].tab < 0) continue;
-      prog[rec0 + i * LR + 1] = (int32_t)(prog.size() - b0);
-      const std::vector<int32_t>& tl = tables[recs[i].tab];
-      prog.insert(prog.end(), tl.begin(), tl.end());
-    }
   }
   return true;
 }
@@ -1234,8 +1233,11 @@ static bool program_needs_full(const int32_t* pass) {
   const int32_t* roff = pass + 4 + t + nns;
   for (int r = 0; r < nrounds; ++r) {
     const int32_t* b = pass + roff[r];
-    for (int l = 0; l < b[0]; ++l)
-      if (b[kRoundHeader + l * LayerRec<T>::W] & (LT_RAWD | LT_PERM2 | LT_U2 | LT_U1)) return true;
+    const int32_t* rec = b + kRoundHeader;
+    for (int l = 0; l < b[0]; ++l) {
+      if (rec[0] & (LT_RAWD | LT_PERM2 | LT_U2 | LT_U1)) return true;
+      rec += LayerRec<T>::W + ((rec[0] & LT_TAB) ? kTableWords : 0);
+    }
   }
   return false;
 }

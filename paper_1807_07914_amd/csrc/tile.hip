@@ -328,14 +328,19 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
         }
       }
 
+      // A record's table follows it, so that its address does not wait for
+      // a word of the record.
+      const int32_t* __restrict__ rec = rb + kRoundHeader;
       for (int o = 0; o < nlayers; ++o) {
         int32_t w[LR];
 #pragma unroll
-        for (int i = 0; i < LR; ++i) w[i] = rb[kRoundHeader + o * LR + i];
+        for (int i = 0; i < LR; ++i) w[i] = rec[i];
         const int flags = w[0];
+        const int32_t* __restrict__ tab = rec + LR;
+        rec += LR + ((flags & LT_TAB) ? kTableWords : 0);
         const int32_t* __restrict__ ap = rb + w[3];  // aux words of the record
         int p = 0;
-        if (flags & LT_TAB) table_step<T, RB>(a, rb + w[1]);
+        if (flags & LT_TAB) table_step<T, RB>(a, tab);
         if (flags & LT_CZR) {
           const uint32_t pairs = (uint32_t)w[2];
 #define QSV_CZR(J, K) \

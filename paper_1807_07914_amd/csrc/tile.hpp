@@ -22,11 +22,12 @@
 //   round block : a header of kRoundHeader words: [0] n_layers, [1] free-bit
 //                 mask, [2 + j] the swizzled LDS byte offset of register bit
 //                 j (the offset of register combination m is the XOR of
-//                 those of its bits); then n_layers layer records of
-//                 LayerRec<T>::W words; then the aux words of the records;
-//                 then the tables, 64 words each.  Offsets in a record count
-//                 words from the start of its round block.
-//   layer record: [0] flags, [1] table offset (LT_TAB), [2] CZ pair set
+//                 those of its bits); then the n_layers layer records of
+//                 LayerRec<T>::W words, each followed by its table (64 words)
+//                 if it has LT_TAB; then the aux words of the records.
+//                 Offsets in a record count words from the start of its round
+//                 block.
+//   layer record: [0] flags, [1] unused, [2] CZ pair set
 //                 (LT_CZR), [3] aux offset: the payloads of the steps LT_CZF,
 //                 LT_SIGN, LT_PHASEL, LT_RAWD and LT_PERM2 / LT_U2 / LT_U1
 //                 that are present follow one another from there, in this

@@ -117,6 +117,16 @@ def _round_blocks(words, off, t, nns):
     return out
 
 
+def _record_offsets(blk, nlay, LR):
+    """Offsets of the layer records of a round block (each record is followed
+    by its table if it has one), plus the end of the last one."""
+    out = [ROUND_HEADER]
+    for _ in range(nlay):
+        k = out[-1]
+        out.append(k + LR + (TABLE_WORDS if blk[k] & LT_TAB else 0))
+    return out
+
+
 def run_pass(psi, n, words, off, cfg):
     RB, SB, WT, LR = cfg["RB"], cfg["SB"], cfg["WT"], cfg["LR"]
     NR = 1 << RB
@@ -145,19 +155,21 @@ def run_pass(psi, n, words, off, cfg):
                     if (m >> j) & 1:
                         o_ ^= bsw[j]
                 lmsw.append(o_)
+            recs_at = _record_offsets(blk, nlay, LR)
+            rec_end = recs_at[-1] if recs_at else ROUND_HEADER
             for gi in range(1 << (t - RB)):
                 lg = pdep_mask(gi, free_mask)
                 sg = swizzle(lg, SB)
                 a = [lds[sg ^ lmsw[m]] for m in range(NR)]
                 for li in range(nlay):
-                    rec = blk[ROUND_HEADER + li * LR: ROUND_HEADER + (li + 1) * LR]
+                    rec = blk[recs_at[li]: recs_at[li] + LR]
                     flags = rec[0]
                     p = rec[3]  # aux words
                     if flags & (LT_CZF | LT_SIGN | LT_PHASEL | LT_RAWD | LT_PERM2 | LT_U2 | LT_U1):
-                        assert p >= ROUND_HEADER + nlay * LR
+                        assert p >= rec_end
                     if flags & LT_TAB:
-                        tl = rec[1]
-                        assert tl >= ROUND_HEADER + nlay * LR and tl + TABLE_WORDS <= len(blk)
+                        tl = recs_at[li] + LR  # the table follows its record
+                        assert tl + TABLE_WORDS <= len(blk)
                         for m in range(NR):
                             zr = _real(blk, tl + 2 * m * WT, WT)
                             zi = _real(blk, tl + (2 * m + 1) * WT, WT)
@@ -289,7 +301,7 @@ def run_pass(psi, n, words, off, cfg):
                                                U[1, 0] * a[m] + U[1, 1] * a[m2])
                     # the next record's aux words (if any) start where these end
                     if li + 1 < nlay:
-                        nxt = blk[ROUND_HEADER + (li + 1) * LR + 3]
+                        nxt = blk[recs_at[li + 1] + 3]
                         if nxt and flags & (LT_CZF | LT_SIGN | LT_PHASEL | LT_RAWD | LT_PERM2 | LT_U2 | LT_U1):
                             assert p == nxt, (hex(flags), p, nxt)
                 for m in range(NR):
@@ -374,8 +386,10 @@ def op_counts(words, steps, dtype):
         blocks = _round_blocks(words, off, t, nns)
         add("blocks", len(blocks))
         for rb in blocks:
+            k = rb + ROUND_HEADER
             for li in range(int(words[rb])):
-                flags = int(words[rb + ROUND_HEADER + li * LR])
+                flags = int(words[k])
+                k += LR + (TABLE_WORDS if flags & LT_TAB else 0)
                 add("layers")
                 for bitv, name in STEP_NAMES:
                     if flags & bitv:
