@@ -355,16 +355,18 @@ int tile_swizzle_bits();
 // A 2x2 that is a unitary times a positive scale k factors as
 //     U = diag(l0, l1) . k R . diag(1, r1),   |l0| = |l1| = |r1| = 1,
 // with R a real rotation by theta in [0, pi/2] (cos = c/k, sin = s/k, c and s
-// the moduli of the diagonal and off-diagonal entries).  R runs as three
-// in-place shears (GIVENS op):
+// the moduli of the diagonal and off-diagonal entries).  R runs as in-place
+// shears (GIVENS op), either two with a deferred scale,
+//     [[1, 0], [sin cos, 1]] . [[1, -tan], [0, 1]] = diag(1/cos, cos) . R,
+// the scale joining the factor carried for the qubit (when cos >= 0.3), or
+// three that give R exactly,
 //     R = [[1, -h], [0, 1]] . [[1, 0], [sin, 1]] . [[1, -h], [0, 1]],
 //     h = tan(theta / 2) in [0, 1], sin in [0, 1].
-// (Two shears would do with a deferred diag(1, 1 + tan^2); its moduli then
-// have to be applied before the next rotation on the qubit, which costs more
-// than the third shear.)  Diagonal factors commute with all other diagonal
-// gates and with gates on other qubits, so a tile pass carries them per
-// qubit and applies them in bulk: one 2^RB-entry table per layer of
-// rotations, and a per-group factor for qubits that are not register bits.
+// Diagonal factors commute with all other diagonal gates and with gates on
+// other qubits, so a tile pass carries them per qubit and applies them in
+// bulk: one 2^RB-entry table per layer of rotations (complex entries: phase,
+// sign and magnitude at once), and a per-group factor for qubits that are
+// not register bits.
 struct Split {
   int kind;         // 0 diagonal (d0, d1 carry the whole gate), 1 rotation, -1 no factorisation
   int form;         // 0: two shears and a carried scale, 1: three shears
