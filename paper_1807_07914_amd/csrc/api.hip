@@ -527,7 +527,7 @@ qsv_status expval_impl(qsv_state* s, const void* data, const uint64_t* xmask, co
   std::vector<int> order(n_terms);
   for (int t = 0; t < n_terms; ++t) order[t] = t;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return xmask[a] < xmask[b]; });
-  const size_t part = expval_ws_doubles(s->n, 16);
+  const size_t part = expval_ws_doubles(s->n, 32);
   qsv_status st = ensure_workspace(s, (part + (size_t)n_terms) * sizeof(double));
   if (st) return st;
   double* ws = static_cast<double*>(s->ws);
@@ -602,6 +602,19 @@ qsv_status expval_impl(qsv_state* s, const void* data, const uint64_t* xmask, co
   for (const auto& gr : plain) {
     const int i = gr.first, j = gr.second;
     for (int k = i; k < j; ++k) slot_of[k] = next_slot + (k - i);
+    // Z-only terms: up to 32 from one read of the state (register sums)
+    if (xmask[order[i]] == 0 && s->n >= (f32 ? zreg_min_qubits<float>() : zreg_min_qubits<double>())) {
+      for (int k0 = i; k0 < j; k0 += 32) {
+        const int cnt = std::min(32, j - k0);
+        hipError_t e = f32 ? launch_expval_zreg<float>(static_cast<const cpx<float>*>(data), s->n, &zs[k0], cnt,
+                                                       ws, outd + next_slot + (k0 - i), s->stream)
+                           : launch_expval_zreg<double>(static_cast<const cpx<double>*>(data), s->n, &zs[k0],
+                                                        cnt, ws, outd + next_slot + (k0 - i), s->stream);
+        if (e != hipSuccess) return hip_fail(e, "expval (Z terms)");
+      }
+      next_slot += j - i;
+      continue;
+    }
     hipError_t e = f32 ? launch_expval_group<float>(static_cast<const cpx<float>*>(data), s->n,
                                                     xmask[order[i]], j - i, &zs[i], &ny[i], ws,
                                                     outd + next_slot, s->stream)

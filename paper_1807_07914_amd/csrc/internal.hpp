@@ -108,6 +108,13 @@ hipError_t launch_expval_group(const cpx<T>* psi, int n, uint64_t xmask, int nt,
                                const uint64_t* zmask_host, const int* ny_host, double* ws,
                                double* out_dev, hipStream_t st);
 size_t expval_ws_doubles(int n, int nt);
+// nt <= 32 Z-only terms from one read: out_dev[t] = sum_i (-1)^{|i & z_t|} |psi_i|^2;
+// needs n >= zreg_min_qubits<T>()
+template <typename T>
+hipError_t launch_expval_zreg(const cpx<T>* psi, int n, const uint64_t* zmask, int nt, double* ws,
+                              double* out_dev, hipStream_t st);
+template <typename T>
+int zreg_min_qubits();
 // nt <= 16 terms whose X masks lie in the tile qubits S (ascending, t of
 // them, S[0..c) = 0..c-1): out_dev[k] as launch_expval_group gives for term k
 template <typename T>

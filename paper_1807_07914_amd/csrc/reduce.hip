@@ -308,6 +308,117 @@ hipError_t launch_expval_group(const cpx<T>* psi, int n, uint64_t xmask, int nt,
   return hipSuccess;
 }
 
+// ------------------------------------------- Z-only terms, register sums
+// All Z strings of one launch from one read of the state.  A wavefront reads
+// a unit of 64 x 16 coalesced 16-byte vectors; lane l takes vectors
+// l + 64 k (k < 16), so the NR = 16 A amplitudes a thread holds differ
+// exactly in the index bits {0} + {7..10} (complex64, A = 2) or {6..9}
+// (complex128, A = 1), the register bits.  The sign of a term with Z mask z
+// splits into (-1)^{|r & z_r|} for register combination r (z_r: z on the
+// register bits, the same for every thread, so the signs are scalar
+// constants of the launch) and (-1)^{|i0 & z_hi|} for the thread's index
+// i0 with the register bits clear: per term, NR FP64 FMAs with scalar signs
+// and one sign per thread.
+constexpr int kMaxZTerms = 32;
+struct ZRegTerms {
+  uint64_t zhi[kMaxZTerms];
+  uint32_t sgn[kMaxZTerms];  // bit r set: (-1)^{|r & z_r|} = -1
+};
+
+template <typename T>
+struct ZRegCfg;
+template <>
+struct ZRegCfg<float> {
+  static constexpr int NR = 32;                  // amplitudes per thread
+  static constexpr uint64_t RMASK = 0x781ull;    // index bits {0, 7, 8, 9, 10}
+  static constexpr int UNIT_BITS = 11;           // amplitudes per wavefront unit: 2^11
+};
+template <>
+struct ZRegCfg<double> {
+  static constexpr int NR = 16;
+  static constexpr uint64_t RMASK = 0x3c0ull;    // index bits {6, 7, 8, 9}
+  static constexpr int UNIT_BITS = 10;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kRB) void k_expval_zreg(const vec16<T>* __restrict__ v, uint64_t nunits,
+                                                      ZRegTerms wt, int nt, double* __restrict__ part) {
+  constexpr int A = VecInfo<T>::A;
+  constexpr int NR = ZRegCfg<T>::NR;
+  constexpr int VPT = NR / A;  // 16 vectors per thread
+  __shared__ double sh[kRB];
+  double acc[kMaxZTerms];
+#pragma unroll
+  for (int t = 0; t < kMaxZTerms; ++t) acc[t] = 0.0;
+  const int lane = threadIdx.x & 63;
+  const uint64_t wid = ((uint64_t)blockIdx.x * kRB + threadIdx.x) >> 6;
+  const uint64_t nw = ((uint64_t)gridDim.x * kRB) >> 6;
+  for (uint64_t u = wid; u < nunits; u += nw) {
+    const uint64_t v0 = u * 64 * VPT + lane;
+    double p[NR];
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const vec16<T> x = v[v0 + 64 * k];
+#pragma unroll
+      for (int e = 0; e < A; ++e) {
+        const double re = (double)x.a[e].x, im = (double)x.a[e].y;
+        p[e + A * k] = fma(re, re, im * im);
+      }
+    }
+    const uint64_t i0 = v0 * A;  // index of (lane, k = 0, e = 0): register bits clear
+#pragma unroll
+    for (int t = 0; t < kMaxZTerms; ++t) {
+      if (t < nt) {
+        const uint32_t sg = wt.sgn[t];
+        double w = 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) w = fma(((sg >> r) & 1u) ? -1.0 : 1.0, p[r], w);
+        acc[t] += (__popcll(i0 & wt.zhi[t]) & 1) ? -w : w;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kMaxZTerms; ++t) {
+    if (t < nt) {  // static indices keep acc in registers
+      const double s = block_sum(acc[t], sh);
+      if (threadIdx.x == 0) part[(size_t)blockIdx.x * nt + t] = s;
+    }
+  }
+}
+
+template <typename T>
+int zreg_min_qubits() {
+  return ZRegCfg<T>::UNIT_BITS;
+}
+
+// out_dev[t] = sum_i (-1)^{|i & z_t|} |psi_i|^2 for nt <= kMaxZTerms Z masks;
+// needs 2^n >= one unit (n >= 11 complex64, n >= 10 complex128).
+template <typename T>
+hipError_t launch_expval_zreg(const cpx<T>* psi, int n, const uint64_t* zmask, int nt, double* ws,
+                               double* out_dev, hipStream_t st) {
+  constexpr uint64_t RM = ZRegCfg<T>::RMASK;
+  if (nt < 1 || nt > kMaxZTerms || n < ZRegCfg<T>::UNIT_BITS || n > 62) return hipErrorInvalidValue;
+  ZRegTerms wt{};
+  for (int t = 0; t < nt; ++t) {
+    wt.zhi[t] = zmask[t] & ~RM;
+    int zr = 0, k = 0;
+    for (int q = 0; q < 64; ++q)
+      if ((RM >> q) & 1) {
+        if ((zmask[t] >> q) & 1) zr |= 1 << k;
+        ++k;
+      }
+    for (int r = 0; r < ZRegCfg<T>::NR; ++r)
+      if (__builtin_popcount(r & zr) & 1) wt.sgn[t] |= 1u << r;
+  }
+  const uint64_t nunits = 1ull << (n - ZRegCfg<T>::UNIT_BITS);
+  uint64_t g = (nunits + 3) / 4;  // four wavefronts per workgroup
+  if (g > kMaxPartials) g = kMaxPartials;
+  hipLaunchKernelGGL(k_expval_zreg<T>, dim3((unsigned)g), dim3(kRB), 0, st,
+                     reinterpret_cast<const vec16<T>*>(psi), nunits, wt, nt, ws);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kRB), 0, st, ws, (int)g, nt, out_dev);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- sampling
 // Block sums of |psi_i|^2 over blocks of kSB amplitudes, their inclusive
 // prefix, then one wavefront per shot: binary search over the block prefix
@@ -475,6 +586,9 @@ hipError_t launch_sample(const cpx<T>* psi, int n, const double* uniforms_dev, i
                                              const int*, double*, double*, hipStream_t);      \
   template hipError_t launch_sample<T>(const cpx<T>*, int, const double*, int, double*,       \
                                        uint64_t*, hipStream_t);                                   \
+  template hipError_t launch_expval_zreg<T>(const cpx<T>*, int, const uint64_t*, int, double*,   \
+                                            double*, hipStream_t);                                \
+  template int zreg_min_qubits<T>();                                                             \
   template hipError_t launch_expval_tile<T>(const cpx<T>*, int, const int*, int, int,             \
                                             const uint64_t*, const uint64_t*, const int*, int,    \
                                             double*, double*, hipStream_t);                       \

@@ -123,6 +123,27 @@ def test_expval_and_norm(dtype, n):
     s.close()
 
 
+@pytest.mark.parametrize("dtype,n", [("c64", 11), ("c64", 19), ("c128", 10), ("c128", 18)])
+def test_expval_z_register_sums(dtype, n):
+    """Z-only terms are summed 32 to a read from per-thread register groups
+    (index bits 0, 7..10 complex64 / 6..9 complex128): masks on those bits,
+    on the others and on both, one-qubit and long strings, 45 terms (two
+    launches), at the smallest supported width and a wider one."""
+    psi0 = start(n, dtype, 1300 + n)
+    rng = np.random.default_rng(1400 + n)
+    ham = [(1.0, (("Z", q),)) for q in range(n)]
+    ham += [(0.5, (("Z", q), ("Z", (q + 1) % n))) for q in range(n)]
+    while len(ham) < 45:
+        qs = sorted(set(int(q) for q in rng.integers(0, n, int(rng.integers(2, 7)))))
+        ham.append((float(rng.uniform(-1, 1)), tuple(("Z", q) for q in qs)))
+    s = State(n, dtype)
+    s.from_numpy(psi0)
+    terms = s.expval(ham, per_term=True)
+    ref_terms = O.expval(psi0.astype(np.complex128), ham, per_term=True)
+    assert np.abs(np.asarray(terms) - ref_terms).max() <= 10 * TOL[dtype]
+    s.close()
+
+
 @pytest.mark.parametrize("dtype,n", [("c64", 17), ("c128", 16)])
 def test_expval_tiled_x_terms(dtype, n):
     """Terms with X masks are reduced tile by tile when their masks fit a
