@@ -548,8 +548,12 @@ qsv_status expval_impl(qsv_state* s, const void* data, const uint64_t* xmask, co
   const int TB = std::min(s->n, f32 ? xtile_max_bits<float>() : xtile_max_bits<double>());
   const int cT = std::min(TB, f32 ? xtile_low_bits<float>() : xtile_low_bits<double>());
   const uint64_t lowq = (1ull << cT) - 1ull;
+  // Tiles hold terms of one kind: one-qubit X masks with an even or with an
+  // odd number of Y, on distinct qubits (register rounds, kinds 1 and 2), or
+  // anything else (kind 0, a pass over the tile per term).
   struct XTile {
-    uint64_t hi = 0;
+    uint64_t hi = 0, xs = 0;
+    int kind = 0;
     std::vector<int> ks;
   };
   std::vector<XTile> xtiles;
@@ -563,13 +567,18 @@ qsv_status expval_impl(qsv_state* s, const void* data, const uint64_t* xmask, co
       plain.push_back({i, j});
     } else {
       for (int k = i; k < j; ++k) {
+        const int kind = (x & (x - 1)) ? 0 : 1 + (ny[k] & 1);
         size_t a = 0;
         for (; a < xtiles.size(); ++a)
-          if (__builtin_popcountll(xtiles[a].hi | hi) <= TB - cT &&
-              xtiles[a].ks.size() < (size_t)16)
+          if (xtiles[a].kind == kind && __builtin_popcountll(xtiles[a].hi | hi) <= TB - cT &&
+              xtiles[a].ks.size() < (size_t)16 && (kind == 0 || !(xtiles[a].xs & x)))
             break;
-        if (a == xtiles.size()) xtiles.emplace_back();
+        if (a == xtiles.size()) {
+          xtiles.emplace_back();
+          xtiles[a].kind = kind;
+        }
         xtiles[a].hi |= hi;
+        xtiles[a].xs |= x;
         xtiles[a].ks.push_back(k);
       }
     }
@@ -590,12 +599,20 @@ qsv_status expval_impl(qsv_state* s, const void* data, const uint64_t* xmask, co
       yy[e] = ny[k];
       slot_of[k] = next_slot + e;
     }
-    hipError_t e = f32 ? launch_expval_tile<float>(static_cast<const cpx<float>*>(data), s->n, S.data(),
-                                                  (int)S.size(), cT, xs.data(), zz.data(), yy.data(), nt,
-                                                  ws, outd + next_slot, s->stream)
-                       : launch_expval_tile<double>(static_cast<const cpx<double>*>(data), s->n, S.data(),
-                                                   (int)S.size(), cT, xs.data(), zz.data(), yy.data(), nt,
-                                                   ws, outd + next_slot, s->stream);
+    hipError_t e = hipErrorInvalidValue;
+    if (xt.kind != 0)  // register rounds; it launches nothing for terms it does not take
+      e = f32 ? launch_expval_xreg<float>(static_cast<const cpx<float>*>(data), s->n, S.data(), (int)S.size(),
+                                          cT, xs.data(), zz.data(), yy.data(), nt, ws, outd + next_slot,
+                                          s->stream)
+              : launch_expval_xreg<double>(static_cast<const cpx<double>*>(data), s->n, S.data(), (int)S.size(),
+                                           cT, xs.data(), zz.data(), yy.data(), nt, ws, outd + next_slot,
+                                           s->stream);
+    if (e == hipErrorInvalidValue)
+      e = f32 ? launch_expval_tile<float>(static_cast<const cpx<float>*>(data), s->n, S.data(), (int)S.size(), cT,
+                                          xs.data(), zz.data(), yy.data(), nt, ws, outd + next_slot, s->stream)
+              : launch_expval_tile<double>(static_cast<const cpx<double>*>(data), s->n, S.data(), (int)S.size(),
+                                           cT, xs.data(), zz.data(), yy.data(), nt, ws, outd + next_slot,
+                                           s->stream);
     if (e != hipSuccess) return hip_fail(e, "expval (tiles)");
     next_slot += nt;
   }

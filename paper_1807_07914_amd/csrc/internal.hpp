@@ -121,6 +121,13 @@ template <typename T>
 hipError_t launch_expval_tile(const cpx<T>* psi, int n, const int* S, int t, int c,
                               const uint64_t* xmask, const uint64_t* zmask, const int* ny, int nt,
                               double* ws, double* out_dev, hipStream_t st);
+// the same for nt <= 16 one-qubit X / Y terms on distinct tile qubits, all
+// with the same Y parity, none with Z on its register round's bits, by
+// register rounds; hipErrorInvalidValue (nothing launched) otherwise
+template <typename T>
+hipError_t launch_expval_xreg(const cpx<T>* psi, int n, const int* S, int t, int c,
+                              const uint64_t* xmask, const uint64_t* zmask, const int* ny, int nt,
+                              double* ws, double* out_dev, hipStream_t st);
 template <typename T>
 int xtile_max_bits();
 template <typename T>

@@ -7,7 +7,11 @@
 // workgroups writes one FP64 partial per (workgroup, term) in a fixed
 // per-thread order and a fixed LDS tree, and a single workgroup combines the
 // partials in a fixed tree.  No floating-point atomics are used.
+#include <algorithm>
+#include <vector>
+
 #include "internal.hpp"
+#include "tile.hpp"
 
 namespace qsv {
 
@@ -211,6 +215,232 @@ __global__ __launch_bounds__(kRB) void k_expval_tile(const cpx<T>* __restrict__ 
     const double r = block_sum(acc[k], sh);
     if (threadIdx.x == 0) part[(size_t)blockIdx.x * nt + k] = r;
   }
+}
+
+template <typename T>
+int xtile_max_bits();
+
+// ------------------------------- one-qubit X / Y terms by register rounds
+// Terms whose X mask is a single tile qubit (X_q or Y_q times any Z string,
+// the common shape of a Hamiltonian's transverse terms) are evaluated on
+// register groups, like the rounds of a tile pass: the tile is staged in LDS
+// (XOR-swizzled), and in round r every thread gathers the 2^RB amplitudes
+// that differ in the round's register bits (one XOR per amplitude, Gray
+// order).  A term on register bit j then sums its 2^(RB-1) pairs
+// w = conj(psi_{i^x}) psi_i (real or imaginary part) from registers; its Z
+// string may not touch the round's register bits, so the sign
+// (-1)^{|i & z|} is the parity of the group's free bits times that of the
+// tile's outside qubits.  The pair products of one group are summed in the
+// state's precision (2^(RB-1) of them), the groups in FP64.
+constexpr int kMaxXRounds = 4;
+constexpr int kMaxXSlots = kMaxXRounds * 5;  // one term per (round, register bit)
+struct XRegDesc {
+  int t, c, nns, nrounds;
+  int S[16];
+  int nonS[48];
+  uint32_t free_mask[kMaxXRounds];
+  uint32_t bofs[kMaxXRounds][5];  // swizzled LDS byte offsets of the register bits
+};
+struct XRegTerms {                   // per slot r * RB + j (X on register bit j of round r)
+  uint64_t zout[kMaxXSlots];         // Z mask on the qubits outside the tile
+  uint32_t zloc[kMaxXSlots];         // Z mask on the tile's free bits of the round (a parity)
+  int term[kMaxXSlots];              // output index, -1 for an empty slot
+};
+
+template <typename T, int RB, int J, bool ODD>
+__device__ __forceinline__ T pair_sum(const cpx<T> (&a)[1 << RB]) {
+  T s = T(0);
+#pragma unroll
+  for (int l = 0; l < (1 << RB); ++l) {
+    if ((l >> J) & 1) continue;
+    const cpx<T> x = a[l], b = a[l | (1 << J)];
+    s += ODD ? fma(b.x, x.y, -b.y * x.x) : fma(b.x, x.x, b.y * x.y);
+  }
+  return s;
+}
+
+// rounds unrolled (at most kMaxXRounds) so that every slot index is static;
+// ODD: every term of the launch takes the imaginary part (one Y)
+template <typename T, int RB, bool ODD, int R>
+__device__ __forceinline__ void xreg_round(const char* __restrict__ tb, const XRegDesc& d,
+                                           const XRegTerms& tt, uint64_t base, double (&acc)[kMaxXSlots]) {
+  constexpr int NR = 1 << RB;
+  constexpr int SB = sizeof(T) == 4 ? 5 : 4;
+  if (R >= d.nrounds) return;
+  const int ng = 1 << (d.t - RB);
+  const uint32_t free_mask = d.free_mask[R];
+  for (int gi = threadIdx.x; gi < ng; gi += kRB) {
+    uint32_t lg = 0, fm = free_mask;
+    for (int bit = 0; fm; ++bit) {
+      const uint32_t low = fm & (0u - fm);
+      if ((gi >> bit) & 1) lg |= low;
+      fm ^= low;
+    }
+    cpx<T> a[NR];
+    uint32_t ad = tile_swizzle(lg, SB) * (uint32_t)sizeof(cpx<T>);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      if (i > 0) ad ^= d.bofs[R][__builtin_ctz(i)];
+      a[i ^ (i >> 1)] = *reinterpret_cast<const cpx<T>*>(tb + ad);
+    }
+#define QSV_XSLOT(J)                                                                         \
+  if ((J) < RB && tt.term[R * RB + (J)] >= 0) {                                              \
+    constexpr int JJ = (J) < RB ? (J) : 0;                                                    \
+    const int k = R * RB + JJ;                                                               \
+    const T s = pair_sum<T, RB, JJ, ODD>(a);                                                 \
+    const int par = (__popc(lg & tt.zloc[k]) + __popcll(base & tt.zout[k])) & 1;             \
+    acc[k] += par ? -(double)s : (double)s;                                                  \
+  }
+    QSV_XSLOT(0)
+    QSV_XSLOT(1)
+    QSV_XSLOT(2)
+    QSV_XSLOT(3)
+    QSV_XSLOT(4)
+#undef QSV_XSLOT
+  }
+}
+
+template <typename T, int TB, int RB, bool ODD>
+__global__ __launch_bounds__(kRB) void k_expval_xreg(const cpx<T>* __restrict__ psi, XRegDesc d,
+                                                     XRegTerms tt, int nt, uint64_t ntiles,
+                                                     double* __restrict__ part) {
+  constexpr int A = VecInfo<T>::A;
+  constexpr int SB = sizeof(T) == 4 ? 5 : 4;
+  __shared__ cpx<T> tile[1 << TB];
+  __shared__ uint64_t segoff[256];
+  __shared__ double sh[kRB];
+  const int t = d.t, c = d.c;
+  const int nseg = 1 << (t - c);
+  for (int h = threadIdx.x; h < nseg; h += kRB) {
+    uint64_t o = 0;
+    for (int j = 0; j < t - c; ++j)
+      if ((h >> j) & 1) o |= 1ull << d.S[c + j];
+    segoff[h] = o;
+  }
+  double acc[kMaxXSlots];
+#pragma unroll
+  for (int k = 0; k < kMaxXSlots; ++k) acc[k] = 0.0;
+  const vec16<T>* gv = reinterpret_cast<const vec16<T>*>(psi);
+  const int nvec = (1 << t) / A;
+  const uint32_t cmask = (1u << c) - 1u;
+  const char* tb = reinterpret_cast<const char*>(tile);
+  __syncthreads();
+  for (uint64_t tid = blockIdx.x; tid < ntiles; tid += gridDim.x) {
+    uint64_t base = 0;
+    for (int i = 0; i < d.nns; ++i) base |= ((tid >> i) & 1ull) << d.nonS[i];
+    for (int i = threadIdx.x; i < nvec; i += kRB) {
+      const uint32_t l = (uint32_t)i * A;
+      const vec16<T> x = gv[(base | segoff[l >> c] | (l & cmask)) / A];
+#pragma unroll
+      for (int e = 0; e < A; ++e) tile[tile_swizzle(l + e, SB)] = x.a[e];
+    }
+    __syncthreads();
+    // (the empty asm keeps the compiler from hoisting the LDS gathers of all
+    // rounds together, which would hold every round's amplitudes at once)
+    xreg_round<T, RB, ODD, 0>(tb, d, tt, base, acc);
+    asm volatile("" ::: "memory");
+    xreg_round<T, RB, ODD, 1>(tb, d, tt, base, acc);
+    asm volatile("" ::: "memory");
+    xreg_round<T, RB, ODD, 2>(tb, d, tt, base, acc);
+    asm volatile("" ::: "memory");
+    xreg_round<T, RB, ODD, 3>(tb, d, tt, base, acc);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxXSlots; ++k) {
+    if (k < kMaxXRounds * RB && tt.term[k] >= 0) {
+      const double v = block_sum(acc[k], sh);
+      if (threadIdx.x == 0) part[(size_t)blockIdx.x * nt + tt.term[k]] = v;
+    }
+  }
+}
+
+// The same values as launch_expval_tile for nt <= 16 terms whose X masks are
+// distinct single qubits of the tile S, all with an even or all with an odd
+// number of Y: rounds of RB register bits cover the terms' X qubits (filled
+// up with other tile qubits), at most kMaxXRounds.  Returns
+// hipErrorInvalidValue, launching nothing, for terms outside that shape
+// (or with Z on a register bit of their round).
+template <typename T>
+hipError_t launch_expval_xreg(const cpx<T>* psi, int n, const int* S, int t, int c, const uint64_t* xmask,
+                              const uint64_t* zmask, const int* ny, int nt, double* ws, double* out_dev,
+                              hipStream_t st) {
+  constexpr int RB = sizeof(T) == 4 ? 5 : 4;
+  constexpr int NR = 1 << RB;
+  constexpr int SB = sizeof(T) == 4 ? 5 : 4;
+  if (nt < 1 || nt > kMaxTermsPerLaunch || t < RB || t > xtile_max_bits<T>() || c > t || t - c > 8 ||
+      (1 << c) < VecInfo<T>::A)
+    return hipErrorInvalidValue;
+  XRegDesc d{};
+  d.t = t;
+  d.c = c;
+  int pos[64];
+  for (int q = 0; q < 64; ++q) pos[q] = -1;
+  uint64_t Smask = 0;
+  for (int j = 0; j < t; ++j) {
+    d.S[j] = S[j];
+    pos[S[j]] = j;
+    Smask |= 1ull << S[j];
+  }
+  for (int q = 0; q < n; ++q)
+    if (!((Smask >> q) & 1)) d.nonS[d.nns++] = q;
+  // rounds: the distinct X bits (local positions), RB to a round, filled up
+  std::vector<int> xb;
+  for (int k = 0; k < nt; ++k) {
+    if (xmask[k] == 0 || (xmask[k] & (xmask[k] - 1)) || (xmask[k] & ~Smask)) return hipErrorInvalidValue;
+    const int p = pos[__builtin_ctzll(xmask[k])];
+    if (std::find(xb.begin(), xb.end(), p) == xb.end()) xb.push_back(p);
+  }
+  d.nrounds = (int)((xb.size() + RB - 1) / RB);
+  if (d.nrounds > kMaxXRounds) return hipErrorInvalidValue;
+  std::vector<std::vector<int>> R(d.nrounds);
+  for (size_t i = 0; i < xb.size(); ++i) R[i / RB].push_back(xb[i]);
+  for (auto& reg : R) {
+    for (int p = 0; p < t && (int)reg.size() < RB; ++p)
+      if (std::find(reg.begin(), reg.end(), p) == reg.end()) reg.push_back(p);
+    std::sort(reg.begin(), reg.end());
+  }
+  const uint32_t tmask = (1u << t) - 1u;
+  for (int r = 0; r < d.nrounds; ++r) {
+    uint32_t rm = 0;
+    for (int k = 0; k < RB; ++k) {
+      rm |= 1u << R[r][k];
+      d.bofs[r][k] = tile_swizzle(1u << R[r][k], SB) * (uint32_t)sizeof(cpx<T>);
+    }
+    d.free_mask[r] = tmask & ~rm;
+  }
+  XRegTerms tt{};
+  for (int k = 0; k < kMaxXSlots; ++k) tt.term[k] = -1;
+  for (int k = 0; k < nt; ++k) {
+    const int p = pos[__builtin_ctzll(xmask[k])];
+    int slot = -1, rr = 0;
+    for (int r = 0; r < d.nrounds; ++r)
+      for (int j = 0; j < RB; ++j)
+        if (R[r][j] == p) {
+          slot = r * RB + j;
+          rr = r;
+        }
+    if (slot < 0 || tt.term[slot] >= 0) return hipErrorInvalidValue;  // one term per qubit
+    uint32_t zl = 0;
+    for (int q = 0; q < n; ++q)
+      if (((zmask[k] >> q) & 1) && pos[q] >= 0) zl |= 1u << pos[q];
+    uint32_t rm = 0;
+    for (int j = 0; j < RB; ++j) rm |= 1u << R[rr][j];
+    if (zl & rm) return hipErrorInvalidValue;                      // Z on a register bit of its round
+    if ((ny[k] & 1) != (ny[0] & 1)) return hipErrorInvalidValue;  // one parity of Y per launch
+    tt.term[slot] = k;
+    tt.zout[slot] = zmask[k] & ~Smask;
+    tt.zloc[slot] = zl;
+  }
+  const uint64_t ntiles = 1ull << (n - t);
+  const unsigned g = (unsigned)(ntiles < (uint64_t)kMaxPartials ? ntiles : (uint64_t)kMaxPartials);
+  constexpr int TB = sizeof(T) == 4 ? 13 : 12;
+  if (ny[0] & 1)
+    hipLaunchKernelGGL((k_expval_xreg<T, TB, RB, true>), dim3(g), dim3(kRB), 0, st, psi, d, tt, nt, ntiles, ws);
+  else
+    hipLaunchKernelGGL((k_expval_xreg<T, TB, RB, false>), dim3(g), dim3(kRB), 0, st, psi, d, tt, nt, ntiles, ws);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kRB), 0, st, ws, (int)g, nt, out_dev);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -589,6 +819,9 @@ hipError_t launch_sample(const cpx<T>* psi, int n, const double* uniforms_dev, i
   template hipError_t launch_expval_zreg<T>(const cpx<T>*, int, const uint64_t*, int, double*,   \
                                             double*, hipStream_t);                                \
   template int zreg_min_qubits<T>();                                                             \
+  template hipError_t launch_expval_xreg<T>(const cpx<T>*, int, const int*, int, int,             \
+                                            const uint64_t*, const uint64_t*, const int*, int,    \
+                                            double*, double*, hipStream_t);                       \
   template hipError_t launch_expval_tile<T>(const cpx<T>*, int, const int*, int, int,             \
                                             const uint64_t*, const uint64_t*, const int*, int,    \
                                             double*, double*, hipStream_t);                       \

@@ -144,6 +144,26 @@ def test_expval_z_register_sums(dtype, n):
     s.close()
 
 
+@pytest.mark.parametrize("dtype,n", [("c64", 5), ("c64", 17), ("c128", 4), ("c128", 16)])
+def test_expval_one_qubit_x_y_terms(dtype, n):
+    """One-qubit X / Y terms with Z strings are evaluated on register rounds:
+    every qubit, X and Y, Z on other tile qubits and on qubits outside the
+    tile, two terms on one qubit (separate tiles), against the oracle."""
+    psi0 = start(n, dtype, 1500 + n)
+    rng = np.random.default_rng(1600 + n)
+    ham = [(0.3 + 0.01 * q, (("X", q),)) for q in range(n)]
+    ham += [(-0.4, (("Y", q),)) for q in range(0, n, 2)]
+    for q in range(n):
+        others = [int(p) for p in rng.choice([p for p in range(n) if p != q], size=min(3, n - 1), replace=False)]
+        ham.append((float(rng.uniform(-1, 1)), (("X" if q % 3 else "Y", q),) + tuple(("Z", p) for p in others)))
+    s = State(n, dtype)
+    s.from_numpy(psi0)
+    terms = s.expval(ham, per_term=True)
+    ref_terms = O.expval(psi0.astype(np.complex128), ham, per_term=True)
+    assert np.abs(np.asarray(terms) - ref_terms).max() <= 10 * TOL[dtype]
+    s.close()
+
+
 @pytest.mark.parametrize("dtype,n", [("c64", 17), ("c128", 16)])
 def test_expval_tiled_x_terms(dtype, n):
     """Terms with X masks are reduced tile by tile when their masks fit a
