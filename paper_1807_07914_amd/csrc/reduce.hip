@@ -545,14 +545,15 @@ hipError_t launch_expval_group(const cpx<T>* psi, int n, uint64_t xmask, int nt,
 // exactly in the index bits {0} + {7..10} (complex64, A = 2) or {6..9}
 // (complex128, A = 1), the register bits.  The sign of a term with Z mask z
 // splits into (-1)^{|r & z_r|} for register combination r (z_r: z on the
-// register bits, the same for every thread, so the signs are scalar
-// constants of the launch) and (-1)^{|i0 & z_hi|} for the thread's index
-// i0 with the register bits clear: per term, NR FP64 FMAs with scalar signs
-// and one sign per thread.
+// register bits) and (-1)^{|i0 & z_hi|} for the thread's index i0 with the
+// register bits clear.  With the probabilities p_r in FP64, their
+// Walsh-Hadamard transform W_s = sum_r (-1)^{|r & s|} p_r (NR log NR adds)
+// gives every term's register sum at once: a term costs one read of
+// W_{z_r} and one signed add per thread.
 constexpr int kMaxZTerms = 32;
 struct ZRegTerms {
   uint64_t zhi[kMaxZTerms];
-  uint32_t sgn[kMaxZTerms];  // bit r set: (-1)^{|r & z_r|} = -1
+  int zr[kMaxZTerms];        // z on the register bits, as a register combination
 };
 
 template <typename T>
@@ -577,6 +578,7 @@ __global__ __launch_bounds__(kRB) void k_expval_zreg(const vec16<T>* __restrict_
   constexpr int NR = ZRegCfg<T>::NR;
   constexpr int VPT = NR / A;  // 16 vectors per thread
   __shared__ double sh[kRB];
+  __shared__ double wcol[NR * kRB];  // thread-private columns: [s][thread], conflict-free
   double acc[kMaxZTerms];
 #pragma unroll
   for (int t = 0; t < kMaxZTerms; ++t) acc[t] = 0.0;
@@ -595,14 +597,26 @@ __global__ __launch_bounds__(kRB) void k_expval_zreg(const vec16<T>* __restrict_
         p[e + A * k] = fma(re, re, im * im);
       }
     }
+    // Walsh-Hadamard transform in registers: p[s] = sum_r (-1)^{|r & s|} p_r
+#pragma unroll
+    for (int h = 1; h < NR; h <<= 1)
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (!(r & h)) {
+          const double x = p[r], y = p[r | h];
+          p[r] = x + y;
+          p[r | h] = x - y;
+        }
+    // each term needs the coefficient at its own (uniform) register mask: a
+    // dynamic index, taken from this thread's column in LDS rather than from
+    // registers (which would put the array in scratch memory)
+#pragma unroll
+    for (int s = 0; s < NR; ++s) wcol[s * kRB + threadIdx.x] = p[s];
     const uint64_t i0 = v0 * A;  // index of (lane, k = 0, e = 0): register bits clear
 #pragma unroll
     for (int t = 0; t < kMaxZTerms; ++t) {
       if (t < nt) {
-        const uint32_t sg = wt.sgn[t];
-        double w = 0.0;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) w = fma(((sg >> r) & 1u) ? -1.0 : 1.0, p[r], w);
+        const double w = wcol[wt.zr[t] * kRB + threadIdx.x];
         acc[t] += (__popcll(i0 & wt.zhi[t]) & 1) ? -w : w;
       }
     }
@@ -637,8 +651,7 @@ hipError_t launch_expval_zreg(const cpx<T>* psi, int n, const uint64_t* zmask, i
         if ((zmask[t] >> q) & 1) zr |= 1 << k;
         ++k;
       }
-    for (int r = 0; r < ZRegCfg<T>::NR; ++r)
-      if (__builtin_popcount(r & zr) & 1) wt.sgn[t] |= 1u << r;
+    wt.zr[t] = zr;
   }
   const uint64_t nunits = 1ull << (n - ZRegCfg<T>::UNIT_BITS);
   uint64_t g = (nunits + 3) / 4;  // four wavefronts per workgroup
