@@ -12,6 +12,8 @@
 // gradient is accumulated in FP64 with the fixed two-stage tree used by all
 // reductions.  (Not part of the paper, whose gradients are taken over
 // tensor-network factors; it is the parameter-gradient of its VQE use case.)
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace qsv {
@@ -107,6 +109,247 @@ __global__ __launch_bounds__(kAB) void k_adj_final(const double* __restrict__ pa
   if (threadIdx.x == 0) *out = s;
 }
 
+// ------------------------------------------ fused reverse sweep, by tiles
+// The reverse sweep as tile passes: a workgroup stages the tile of both psi
+// and lambda in LDS (the 2^t amplitudes with fixed non-S bits), applies
+// every inverse gate of the pass to both in order, and at each rotation adds
+// the tile's share of Im <lambda| P |psi> before applying the inverse.  A
+// wavefront reduces its share with shuffles and adds it to its own LDS slot
+// per rotation (no atomics: the order of every addition is fixed); at the
+// end each workgroup writes its per-rotation sums, which one workgroup per
+// rotation then adds in a fixed tree.  One HBM read and write of both
+// states per pass instead of one per rotation.
+//
+// Program (int32 words): [0] t, [1] c, [2] n_nonS, [3] n_ops, [4] n_grad,
+// [5] offset of the op records, [6] offset of the gradient map (the
+// circuit's op index of each gradient slot), S[t] from word 8, nonS after.
+// Op record (kAdjRec words): [0] type, [1] a, [2] b, [3] gradient slot or
+// -1, [4] generator (0 X, 1 Y, 2 Z), then complex doubles (re, im) from
+// word 8:
+//   1 U1  : 2x2 on local bit a (row-major)
+//   2 DIAG: factor d[bit_a + 2 bit_b] per amplitude; operands a, b are
+//           kind << 8 | value (kind 0: local bit, 2: qubit outside the tile),
+//           b = -1 for one qubit (d[0], d[1]); a gradient slot takes Z on a
+//   3 U2  : 4x4 on local bits a < b (a = LSB of the row index)
+constexpr int kAdjRec = 72;
+constexpr int kMaxAdjGrad = 256;
+
+template <typename T>
+__device__ __forceinline__ cpx<T> rec_cpx(const int32_t* r, int e) {
+  const double re = __hiloint2double(r[8 + 4 * e + 1], r[8 + 4 * e]);
+  const double im = __hiloint2double(r[8 + 4 * e + 3], r[8 + 4 * e + 2]);
+  return cpx<T>{(T)re, (T)im};
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Im( conj(l0) (G p)_0 + conj(l1) (G p)_1 ) for G = X, Y or Z, in FP64
+template <typename T>
+__device__ __forceinline__ double grad_pair(int gen, cpx<T> p0, cpx<T> p1, cpx<T> l0, cpx<T> l1) {
+  const double a0r = l0.x, a0i = l0.y, a1r = l1.x, a1i = l1.y;
+  const double b0r = p0.x, b0i = p0.y, b1r = p1.x, b1i = p1.y;
+  if (gen == 0)  // X: Im(conj(l0) p1 + conj(l1) p0)
+    return (a0r * b1i - a0i * b1r) + (a1r * b0i - a1i * b0r);
+  if (gen == 1)  // Y: -Re(conj(l0) p1) + Re(conj(l1) p0)
+    return -(a0r * b1r + a0i * b1i) + (a1r * b0r + a1i * b0i);
+  return (a0r * b0i - a0i * b0r) - (a1r * b1i - a1i * b1r);  // Z
+}
+
+template <typename T, int TB>
+__global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<T>* __restrict__ lam,
+                                                  const int32_t* __restrict__ prog, uint64_t ntiles,
+                                                  double* __restrict__ part) {
+  constexpr int A = VecInfo<T>::A;
+  __shared__ cpx<T> tp[1 << TB];
+  __shared__ cpx<T> tl[1 << TB];
+  __shared__ double gacc[kMaxAdjGrad * (kAB / 64)];
+  __shared__ uint64_t segoff[256];
+  const int t = prog[0], c = prog[1], nns = prog[2], nops = prog[3], ngrad = prog[4];
+  const int32_t* S = prog + 8;
+  const int32_t* nonS = S + t;
+  const int32_t* recs = prog + prog[5];
+  const int nseg = 1 << (t - c);
+  for (int h = threadIdx.x; h < nseg; h += kAB) {
+    uint64_t o = 0;
+    for (int j = 0; j < t - c; ++j)
+      if ((h >> j) & 1) o |= 1ull << S[c + j];
+    segoff[h] = o;
+  }
+  for (int i = threadIdx.x; i < ngrad * (kAB / 64); i += kAB) gacc[i] = 0.0;
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  vec16<T>* gp = reinterpret_cast<vec16<T>*>(psi);
+  vec16<T>* gl = reinterpret_cast<vec16<T>*>(lam);
+  const int nvec = (1 << t) / A;
+  const uint32_t cmask = (1u << c) - 1u;
+  const int half = 1 << (t - 1), full = 1 << t;
+  for (uint64_t tid = blockIdx.x; tid < ntiles; tid += gridDim.x) {
+    uint64_t base = 0;
+    for (int i = 0; i < nns; ++i) base |= ((tid >> i) & 1ull) << nonS[i];
+    for (int i = threadIdx.x; i < nvec; i += kAB) {
+      const uint32_t l = (uint32_t)i * A;
+      const uint64_t g = (base | segoff[l >> c] | (l & cmask)) / A;
+      const vec16<T> x = gp[g], y = gl[g];
+#pragma unroll
+      for (int e = 0; e < A; ++e) {
+        tp[l + e] = x.a[e];
+        tl[l + e] = y.a[e];
+      }
+    }
+    __syncthreads();
+    for (int o = 0; o < nops; ++o) {
+      const int32_t* r = recs + o * kAdjRec;
+      const int type = r[0], ra = r[1], rb = r[2], slot = r[3], gen = r[4];
+      double g = 0.0;
+      if (type == 1) {
+        M2<T> V;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) V.m[e] = rec_cpx<T>(r, e);
+        const uint32_t lowm = (1u << ra) - 1u;
+        for (int u = threadIdx.x; u < half; u += kAB) {
+          const uint32_t i0 = (((uint32_t)u >> ra) << (ra + 1)) | ((uint32_t)u & lowm), i1 = i0 | (1u << ra);
+          cpx<T> p0 = tp[i0], p1 = tp[i1], l0 = tl[i0], l1 = tl[i1];
+          if (slot >= 0) g += grad_pair<T>(gen, p0, p1, l0, l1);
+          apply2(V, p0, p1);
+          apply2(V, l0, l1);
+          tp[i0] = p0;
+          tp[i1] = p1;
+          tl[i0] = l0;
+          tl[i1] = l1;
+        }
+      } else if (type == 2) {
+        cpx<T> d[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d[e] = rec_cpx<T>(r, e);
+        const int ka = ra >> 8, va = ra & 255;
+        const int kb = rb < 0 ? -1 : (rb >> 8), vb = rb < 0 ? 0 : (rb & 255);
+        const int oa = ka == 0 ? -1 : (int)((base >> va) & 1ull);  // outside operands: one bit per tile
+        const int ob = kb < 0 ? 0 : kb == 0 ? -1 : (int)((base >> vb) & 1ull);
+        for (int l = threadIdx.x; l < full; l += kAB) {
+          const int bA = oa >= 0 ? oa : (l >> va) & 1;
+          const int bB = ob >= 0 ? ob : (l >> vb) & 1;
+          const cpx<T> dd = d[bA + 2 * bB];
+          const cpx<T> p = tp[l], q = tl[l];
+          if (slot >= 0) {
+            const double im = (double)q.x * (double)p.y - (double)q.y * (double)p.x;
+            g += bA ? -im : im;
+          }
+          tp[l] = cmul(dd, p);
+          tl[l] = cmul(dd, q);
+        }
+      } else {
+        M4<T> U;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) U.m[e] = rec_cpx<T>(r, e);
+        const int j0 = ra, j1 = rb;
+        for (int u = threadIdx.x; u < (full >> 2); u += kAB) {
+          uint32_t i = (uint32_t)u;
+          i = ((i >> j0) << (j0 + 1)) | (i & ((1u << j0) - 1u));
+          i = ((i >> j1) << (j1 + 1)) | (i & ((1u << j1) - 1u));
+          const uint32_t ix[4] = {i, i | (1u << j0), i | (1u << j1), i | (1u << j0) | (1u << j1)};
+          cpx<T> x[4], y[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            x[e] = tp[ix[e]];
+            y[e] = tl[ix[e]];
+          }
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            cpx<T> ax = cmul(U.m[4 * rr], x[0]), ay = cmul(U.m[4 * rr], y[0]);
+#pragma unroll
+            for (int cc = 1; cc < 4; ++cc) {
+              ax = cfma(U.m[4 * rr + cc], x[cc], ax);
+              ay = cfma(U.m[4 * rr + cc], y[cc], ay);
+            }
+            tp[ix[rr]] = ax;
+            tl[ix[rr]] = ay;
+          }
+        }
+      }
+      if (slot >= 0) {
+        g = wave_sum_d(g);
+        if (lane == 0) gacc[slot * (kAB / 64) + wave] += g;
+      }
+      __syncthreads();
+    }
+    for (int i = threadIdx.x; i < nvec; i += kAB) {
+      const uint32_t l = (uint32_t)i * A;
+      const uint64_t g = (base | segoff[l >> c] | (l & cmask)) / A;
+      vec16<T> x, y;
+#pragma unroll
+      for (int e = 0; e < A; ++e) {
+        x.a[e] = tp[l + e];
+        y.a[e] = tl[l + e];
+      }
+      gp[g] = x;
+      gl[g] = y;
+    }
+    __syncthreads();
+  }
+  for (int sl = threadIdx.x; sl < ngrad; sl += kAB) {
+    double v = 0.0;
+    for (int w = 0; w < kAB / 64; ++w) v += gacc[sl * (kAB / 64) + w];
+    part[(size_t)sl * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// out[map[s]] = sum_b part[s * nb + b], one workgroup per gradient slot
+__global__ __launch_bounds__(kAB) void k_adj_gsum(const double* __restrict__ part, int nb,
+                                                  const int32_t* __restrict__ map, double* __restrict__ out) {
+  __shared__ double sh[kAB];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kAB) acc += part[(size_t)blockIdx.x * nb + b];
+  const double s = block_sum_d(acc, sh);
+  if (threadIdx.x == 0) out[map[blockIdx.x]] = s;
+}
+
+template <typename T>
+int adj_tile_bits() {
+  return sizeof(T) == 4 ? 12 : 11;
+}
+int adj_max_grad() { return kMaxAdjGrad; }
+int adj_rec_words() { return kAdjRec; }
+
+// Workgroups of the sweep kernel resident at once (cached per device).
+template <typename T>
+static int adj_grid() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cache[dev] == 0) {
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_tile<T, (sizeof(T) == 4 ? 12 : 11)>, kAB, 0) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    cache[dev] = per_cu * ncu;
+  }
+  return cache[dev];
+}
+
+// One tile pass of the sweep (program at prog_dev, header in prog_host);
+// part needs n_grad * adj_max_grid() doubles; gradients go to out_dev[map].
+template <typename T>
+hipError_t launch_adj_tile(cpx<T>* psi, cpx<T>* lam, int n, const int32_t* prog_dev, const int32_t* prog_host,
+                           double* part, double* out_dev, hipStream_t st) {
+  constexpr int TB = sizeof(T) == 4 ? 12 : 11;
+  const int t = prog_host[0], ngrad = prog_host[4];
+  if (t > TB || ngrad > kMaxAdjGrad || t - prog_host[1] > 8) return hipErrorInvalidValue;
+  const uint64_t ntiles = 1ull << (n - t);
+  int resident = adj_grid<T>();
+  if (resident <= 0) return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, (uint64_t)std::min(resident, kMaxAdjPartials));
+  hipLaunchKernelGGL((k_adj_tile<T, TB>), dim3(grid), dim3(kAB), 0, st, psi, lam, prog_dev, ntiles, part);
+  if (ngrad > 0)
+    hipLaunchKernelGGL(k_adj_gsum, dim3(ngrad), dim3(kAB), 0, st, part, (int)grid, prog_dev + prog_host[6],
+                       out_dev);
+  return hipGetLastError();
+}
+
 size_t adjoint_partials() { return kMaxAdjPartials; }
 
 template <typename T>
@@ -146,6 +389,9 @@ hipError_t launch_adj_rot(cpx<T>* psi, cpx<T>* lam, int n, int q, const M2<T>& V
 }
 
 #define QSV_AINST(T)                                                                              \
+  template int adj_tile_bits<T>();                                                                \
+  template hipError_t launch_adj_tile<T>(cpx<T>*, cpx<T>*, int, const int32_t*, const int32_t*,    \
+                                         double*, double*, hipStream_t);                          \
   template hipError_t launch_hpsi<T>(const cpx<T>*, cpx<T>*, int, const uint64_t*, const uint64_t*, \
                                      const double*, const double*, int, hipStream_t);             \
   template hipError_t launch_adj_rot<T>(cpx<T>*, cpx<T>*, int, int, const M2<T>&,                  \

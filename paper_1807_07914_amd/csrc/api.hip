@@ -374,6 +374,7 @@ qsv_status qsv_free_state(qsv_state* s) {
   if (s->ws) (void)hipFree(s->ws);
   if (s->pbuf) (void)hipFree(s->pbuf);
   if (s->aux) (void)hipFree(s->aux);
+  if (s->apbuf) (void)hipFree(s->apbuf);
   if (s->owns && s->psi) (void)hipFree(s->psi);
   s->magic = kDeadMagic;
   delete s;
@@ -686,13 +687,175 @@ static qsv_status check_terms(const qsv_state* s, const uint64_t* xmask, const u
   return QSV_OK;
 }
 
+// Reverse sweep by tile passes: the planner groups the inverse gates, each
+// pass becomes one program of op records (layout in adjoint.hip) applied to
+// the tiles of psi and lambda, with one gradient slot per rotation; a pass
+// with more rotations than slots is split into consecutive programs over the
+// same tile qubits.  Ops that no tile takes run as inverse per-gate kernels
+// on both states (they are never rotations: those act on one qubit).
+template <typename T>
+static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops, cpx<T>* psi, cpx<T>* lam,
+                                      double* gdev, double* tpart) {
+  const int n = s->n;
+  const int RB = sizeof(T) == 4 ? 5 : 4;
+  const int t = std::min(n, adj_tile_bits<T>());
+  const int c = std::min(t, sizeof(T) == 4 ? 5 : 4);
+  std::vector<AdjStep> steps;
+  plan_adjoint(ops, n_ops, n, t, c, RB, steps);
+  const int LR = adj_rec_words(), GMAX = adj_max_grad();
+  std::vector<int32_t>& prog = s->ahprog;
+  prog.clear();
+  struct Launch {
+    int step;
+    size_t off;
+  };
+  std::vector<Launch> launches;
+  for (size_t si = 0; si < steps.size(); ++si) {
+    const AdjStep& as = steps[si];
+    if (!as.tile) continue;
+    std::vector<int> lpos(n, -1);
+    for (int j = 0; j < t; ++j) lpos[as.S[j]] = j;
+    std::vector<int> nonS;
+    for (int q = 0; q < n; ++q)
+      if (lpos[q] < 0) nonS.push_back(q);
+    size_t k0 = 0;
+    while (k0 < as.ops.size()) {  // one program per at most GMAX rotations
+      size_t k1 = k0;
+      int ng = 0;
+      while (k1 < as.ops.size()) {
+        const int g = ops[as.ops[k1]].gate;
+        const bool rot = g == QSV_RX || g == QSV_RY || g == QSV_RZ;
+        if (rot && ng == GMAX) break;
+        ng += rot;
+        ++k1;
+      }
+      const size_t off = prog.size();
+      const int nops = (int)(k1 - k0);
+      const int hdr = (8 + t + (int)nonS.size() + 7) & ~7;
+      prog.resize(off + hdr, 0);
+      prog[off] = t;
+      prog[off + 1] = c;
+      prog[off + 2] = (int)nonS.size();
+      prog[off + 3] = nops;
+      prog[off + 4] = ng;
+      prog[off + 5] = hdr;
+      for (int j = 0; j < t; ++j) prog[off + 8 + j] = as.S[j];
+      for (size_t j = 0; j < nonS.size(); ++j) prog[off + 8 + t + j] = nonS[j];
+      std::vector<int32_t> map;
+      for (size_t k = k0; k < k1; ++k) {
+        const qsv_op& o = ops[as.ops[k]];
+        const int D = 1 << o.nq;
+        cd m[16];
+        if (o.gate == QSV_MAT) {
+          for (int i = 0; i < D * D; ++i) m[i] = cd(o.mat[2 * i], o.mat[2 * i + 1]);
+        } else {
+          gate_matrix(o.gate, o.p, m);
+        }
+        cd mi[16];  // the inverse: conjugate transpose
+        for (int r = 0; r < D; ++r)
+          for (int cc = 0; cc < D; ++cc) mi[r * D + cc] = std::conj(m[cc * D + r]);
+        bool diag = true;
+        for (int r = 0; r < D; ++r)
+          for (int cc = 0; cc < D; ++cc)
+            if (r != cc && mi[r * D + cc] != cd(0.0)) diag = false;
+        std::vector<int32_t> rec(LR, 0);
+        rec[3] = -1;
+        const bool rot = o.gate == QSV_RX || o.gate == QSV_RY || o.gate == QSV_RZ;
+        if (rot) {
+          rec[3] = (int32_t)map.size();
+          map.push_back(as.ops[k]);
+          rec[4] = o.gate == QSV_RX ? 0 : o.gate == QSV_RY ? 1 : 2;
+        }
+        cd vals[16];
+        int nv = 0;
+        auto operand = [&](int q) { return lpos[q] >= 0 ? lpos[q] : ((2 << 8) | q); };
+        if (diag) {
+          rec[0] = 2;
+          rec[1] = operand(o.q[0]);
+          rec[2] = o.nq == 2 ? operand(o.q[1]) : -1;
+          for (int e = 0; e < D; ++e) vals[e] = mi[e * D + e];
+          for (int e = D; e < 4; ++e) vals[e] = vals[e - D];  // one qubit: bit_b = 0 only
+          nv = 4;
+        } else if (o.nq == 1) {
+          if (lpos[o.q[0]] < 0) return fail(QSV_ERR_STATE, "adjoint tile op on a qubit outside the tile");
+          rec[0] = 1;
+          rec[1] = lpos[o.q[0]];
+          for (int e = 0; e < 4; ++e) vals[e] = mi[e];
+          nv = 4;
+        } else {
+          int ja = lpos[o.q[0]], jb = lpos[o.q[1]];
+          if (ja < 0 || jb < 0) return fail(QSV_ERR_STATE, "adjoint tile op on a qubit outside the tile");
+          rec[0] = 3;
+          // listed order: q[0] is the matrix index's low bit; the kernel wants a < b
+          cd u[16];
+          for (int e = 0; e < 16; ++e) u[e] = mi[e];
+          if (ja > jb) {
+            auto sw = [](int m2) { return ((m2 & 1) << 1) | ((m2 >> 1) & 1); };
+            for (int a = 0; a < 4; ++a)
+              for (int b = 0; b < 4; ++b) u[sw(a) * 4 + sw(b)] = mi[a * 4 + b];
+            std::swap(ja, jb);
+          }
+          rec[1] = ja;
+          rec[2] = jb;
+          for (int e = 0; e < 16; ++e) vals[e] = u[e];
+          nv = 16;
+        }
+        if (rot && rec[0] == 3) return fail(QSV_ERR_STATE, "rotation as a 2-qubit op");
+        for (int e = 0; e < nv; ++e) {
+          const double re = vals[e].real(), im = vals[e].imag();
+          std::memcpy(&rec[8 + 4 * e], &re, 8);
+          std::memcpy(&rec[8 + 4 * e + 2], &im, 8);
+        }
+        prog.insert(prog.end(), rec.begin(), rec.end());
+      }
+      prog[off + 6] = (int32_t)(prog.size() - off);
+      prog.insert(prog.end(), map.begin(), map.end());
+      while (prog.size() % 8) prog.push_back(0);
+      launches.push_back({(int)si, off});
+      k0 = k1;
+    }
+  }
+  const size_t need = prog.size() * sizeof(int32_t) + 256;
+  if (s->apbuf_bytes < need) {
+    if (s->apbuf) {
+      QSV_HIP(hipStreamSynchronize(s->stream));
+      QSV_HIP(hipFree(s->apbuf));
+      s->apbuf = nullptr;
+      s->apbuf_bytes = 0;
+    }
+    QSV_HIP(hipMalloc(&s->apbuf, need * 2));
+    s->apbuf_bytes = need * 2;
+  }
+  int32_t* dprog = static_cast<int32_t*>(s->apbuf);
+  if (!prog.empty())
+    QSV_HIP(hipMemcpyAsync(dprog, prog.data(), prog.size() * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
+  qsv_status st = QSV_OK;
+  size_t li = 0;
+  for (size_t si = 0; si < steps.size(); ++si) {
+    const AdjStep& as = steps[si];
+    if (!as.tile) {
+      st = apply_op_inverse(s, s->psi, ops[as.op], 0);
+      if (st) return st;
+      st = apply_op_inverse(s, s->aux, ops[as.op], 0);
+      if (st) return st;
+      continue;
+    }
+    for (; li < launches.size() && launches[li].step == (int)si; ++li) {
+      const size_t off = launches[li].off;
+      QSV_HIP(launch_adj_tile<T>(psi, lam, n, dprog + off, prog.data() + off, tpart, gdev, s->stream));
+    }
+  }
+  return QSV_OK;
+}
+
 template <typename T>
 static qsv_status adjoint_sweep(qsv_state* s, const qsv_op* ops, int n_ops, const uint64_t* xmask,
                                 const uint64_t* zmask, const double* coeff, int n_terms,
                                 double* grad) {
   const size_t stage = dense_ws_bytes();
   const size_t npart = adjoint_partials();
-  qsv_status st = ensure_workspace(s, stage + (npart + (size_t)n_ops + 1) * sizeof(double));
+  const size_t tparts = (size_t)adj_max_grad() * 1024;  // per-workgroup sums of the tiled sweep
+  qsv_status st = ensure_workspace(s, stage + (npart + (size_t)n_ops + 1 + tparts) * sizeof(double));
   if (st) return st;
   if (s->aux_bytes < s->bytes) {
     if (s->aux) {
@@ -732,6 +895,15 @@ static qsv_status adjoint_sweep(qsv_state* s, const qsv_op* ops, int n_ops, cons
   std::vector<double> gh(n_ops + 1, 0.0);
   QSV_HIP(hipMemcpyAsync(gdev, gh.data(), (n_ops + 1) * sizeof(double), hipMemcpyHostToDevice,
                          s->stream));
+  // the reverse sweep as tile passes (both states staged in LDS per pass)
+  const int RB = s->dt == QSV_C64 ? 5 : 4;
+  if (s->n >= RB) {
+    st = adjoint_sweep_tiled<T>(s, ops, n_ops, psi, lam, gdev, gdev + n_ops + 1);
+    if (st) return st;
+    QSV_HIP(hipMemcpyAsync(grad, gdev, n_ops * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    return QSV_OK;
+  }
   const cd I(0.0, 1.0);
   for (int k = n_ops - 1; k >= 0; --k) {
     const qsv_op& o = ops[k];

@@ -1321,6 +1321,26 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
   return QSV_OK;
 }
 
+void plan_adjoint(const qsv_op* ops, int n_ops, int n, int t, int c, int RB, std::vector<AdjStep>& steps) {
+  std::vector<POp> P;
+  std::vector<int> orig;
+  for (int k = n_ops - 1; k >= 0; --k) {
+    P.push_back(classify(ops[k]));
+    orig.push_back(k);
+  }
+  auto sch = build_schedule(P, n, t, c, RB);
+  steps.clear();
+  for (const Step& st : sch->steps) {
+    AdjStep a;
+    a.tile = st.tile;
+    a.S = st.S;
+    if (!st.tile) a.op = orig[st.op];
+    for (const Round& r : st.rounds)
+      for (int i : r.ops) a.ops.push_back(orig[i]);
+    steps.push_back(std::move(a));
+  }
+}
+
 qsv_status run_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const qsv_plan_opts& opts) {
   if (opts.mode == 1) {
     qsv_status st = ensure_workspace(s, dense_ws_bytes());

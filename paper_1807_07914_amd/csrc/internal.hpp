@@ -53,6 +53,10 @@ struct qsv_state {
   // second state-sized buffer (adjoint sweep: lambda)
   void* aux = nullptr;
   size_t aux_bytes = 0;
+  // device copy of the adjoint sweep's tile programs and its host image
+  void* apbuf = nullptr;
+  size_t apbuf_bytes = 0;
+  std::vector<int32_t> ahprog;
   std::atomic<int> busy{0};
 };
 
@@ -97,6 +101,15 @@ template <typename T>
 hipError_t launch_adj_rot(cpx<T>* psi, cpx<T>* lam, int n, int q, const M2<T>& V, const M2<double>& G,
                           double* part, double* out_dev, hipStream_t st);
 size_t adjoint_partials();
+// fused reverse sweep (adjoint.hip): one tile pass of the program at
+// prog_dev (host copy prog_host); part holds n_grad * 1024 doubles
+template <typename T>
+hipError_t launch_adj_tile(cpx<T>* psi, cpx<T>* lam, int n, const int32_t* prog_dev, const int32_t* prog_host,
+                           double* part, double* out_dev, hipStream_t st);
+template <typename T>
+int adj_tile_bits();
+int adj_max_grad();
+int adj_rec_words();
 
 // reductions: FP64 partials written to ws, final values to out_dev (doubles)
 template <typename T>

@@ -42,4 +42,16 @@ qsv_status plan_passes(const qsv_state* s, const qsv_op* ops, int n_ops, int til
 qsv_status plan_program(const qsv_state* s, const qsv_op* ops, int n_ops, int tile_qubits,
                         std::vector<int32_t>& prog, std::vector<int64_t>& steps);
 
+// Reverse sweep of the adjoint gradient as tile passes: ops[n_ops-1] .. ops[0]
+// taken as their inverses (the same structure), grouped by the fused
+// planner.  A step is either a tile pass over qubits S with the original op
+// indices in a valid application order, or one op that no tile takes.
+struct AdjStep {
+  bool tile = true;
+  int op = -1;
+  std::vector<int> S;
+  std::vector<int> ops;
+};
+void plan_adjoint(const qsv_op* ops, int n_ops, int n, int t, int c, int RB, std::vector<AdjStep>& steps);
+
 }  // namespace qsv

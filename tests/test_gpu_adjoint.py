@@ -21,7 +21,7 @@ def State(*a, **k):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("n,layers,mode", [(2, 2, "pergate"), (4, 2, "auto"), (7, 3, "fused"),
-                                           (12, 2, "auto")])
+                                           (12, 2, "auto"), (15, 2, "auto")])
 def test_adjoint_matches_parameter_shift(dtype, n, layers, mode):
     params, ham = qc.gradient_workload(n, layers, 900 + n)
     build = lambda p: qc.rot_ring_ansatz(n, p, layers)
