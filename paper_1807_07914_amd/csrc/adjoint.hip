@@ -131,6 +131,19 @@ __global__ __launch_bounds__(kAB) void k_adj_final(const double* __restrict__ pa
 //           kind << 8 | value (kind 0: local bit, 2: qubit outside the tile),
 //           b = -1 for one qubit (d[0], d[1]); a gradient slot takes Z on a
 //   3 U2  : 4x4 on local bits a < b (a = LSB of the row index)
+//   4 CHAIN: [2] count (<= 4) 2x2 matrices on local bit a, applied in turn
+//           to each pair, so that consecutive one-qubit gates on one qubit
+//           share one LDS round trip; [3 + e] gradient slot of element e or
+//           -1, [7] generators (two bits per element), matrix e from word
+//           8 + 16 e
+//   5 SIGNS: a run of CZ and Z gates as one sign pattern; [1] n_dist,
+//           [2] n_lo, [3] n_oo, then from word 8: n_dist pairs (d, M),
+//           n_lo pairs (local bit, outside qubit or -1), n_oo pairs of
+//           outside qubits.  Amplitude l of the tile changes sign when
+//           sum_d popc(l & (l >> d) & M) + popc(l & Mo) + c is odd, with Mo
+//           the local bits whose partner is -1 or a qubit set in the tile's
+//           base index and c the parity of the outside pairs with both
+//           qubits set (a Z outside the tile is the pair (q, q))
 constexpr int kAdjRec = 72;
 constexpr int kMaxAdjGrad = 256;
 
@@ -203,7 +216,7 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
     __syncthreads();
     for (int o = 0; o < nops; ++o) {
       const int32_t* r = recs + o * kAdjRec;
-      const int type = r[0], ra = r[1], rb = r[2], slot = r[3], gen = r[4];
+      const int type = r[0], ra = r[1], rb = r[2], slot = type < 4 ? r[3] : -1, gen = r[4];
       double g = 0.0;
       if (type == 1) {
         M2<T> V;
@@ -240,6 +253,60 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
           }
           tp[l] = cmul(dd, p);
           tl[l] = cmul(dd, q);
+        }
+      } else if (type == 4) {
+        const int cnt = rb, gens = r[7];
+        const uint32_t lowm = (1u << ra) - 1u;
+        M2<T> V[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int f = 0; f < 4; ++f) V[e].m[f] = rec_cpx<T>(r, 4 * e + f);
+        double ge[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int u = threadIdx.x; u < half; u += kAB) {
+          const uint32_t i0 = (((uint32_t)u >> ra) << (ra + 1)) | ((uint32_t)u & lowm), i1 = i0 | (1u << ra);
+          cpx<T> p0 = tp[i0], p1 = tp[i1], l0 = tl[i0], l1 = tl[i1];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if (e < cnt) {
+              if (r[3 + e] >= 0) ge[e] += grad_pair<T>((gens >> (2 * e)) & 3, p0, p1, l0, l1);
+              apply2(V[e], p0, p1);
+              apply2(V[e], l0, l1);
+            }
+          }
+          tp[i0] = p0;
+          tp[i1] = p1;
+          tl[i0] = l0;
+          tl[i1] = l1;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (e < cnt && r[3 + e] >= 0) {
+            const double v = wave_sum_d(ge[e]);
+            if (lane == 0) gacc[r[3 + e] * (kAB / 64) + wave] += v;
+          }
+        }
+      } else if (type == 5) {
+        const int nd = ra, nlo = rb, noo = r[3];
+        const int32_t* w = r + 8;
+        uint32_t Mo = 0;
+        int cpar = 0;
+        for (int i = 0; i < nlo; ++i) {
+          const int oq = w[2 * nd + 2 * i + 1];
+          if (oq < 0 || ((base >> oq) & 1ull)) Mo ^= 1u << w[2 * nd + 2 * i];
+        }
+        for (int i = 0; i < noo; ++i) {
+          const int32_t* pq = w + 2 * (nd + nlo + i);
+          cpar ^= (int)((base >> pq[0]) & (base >> pq[1]) & 1ull);
+        }
+        for (int l = threadIdx.x; l < full; l += kAB) {
+          int par = cpar + __popc((uint32_t)l & Mo);
+          for (int i = 0; i < nd; ++i) par += __popc((uint32_t)l & ((uint32_t)l >> w[2 * i]) & (uint32_t)w[2 * i + 1]);
+          if (par & 1) {
+            const cpx<T> p = tp[l], q = tl[l];
+            tp[l] = cpx<T>{-p.x, -p.y};
+            tl[l] = cpx<T>{-q.x, -q.y};
+          }
         }
       } else {
         M4<T> U;

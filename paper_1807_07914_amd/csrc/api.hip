@@ -5,6 +5,8 @@
 // pre-order traversal, dispatching each concrete instruction to its visit
 // method; here dispatch is an opcode switch that selects a specialised
 // kernel (general 2x2, diagonal, 4x4, permutation, dense k-qubit block).
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -718,15 +720,98 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
     std::vector<int> nonS;
     for (int q = 0; q < n; ++q)
       if (lpos[q] < 0) nonS.push_back(q);
+    // Items of the pass in application order: one op, a chain of one-qubit
+    // ops on one local qubit, or a run of CZ / Z gates.  An op joins an item
+    // that starts earlier only when it commutes with every op it passes
+    // (no shared qubit, or both diagonal), which leaves the product and every
+    // gradient unchanged: a rotation's generator commutes with the same ops.
+    const size_t m = as.ops.size();
+    std::vector<std::array<cd, 16>> inv(m);
+    std::vector<char> isdiag(m), issign(m), used(m, 0);
+    for (size_t k = 0; k < m; ++k) {
+      const qsv_op& o = ops[as.ops[k]];
+      const int D = 1 << o.nq;
+      cd mm[16];
+      if (o.gate == QSV_MAT) {
+        for (int i = 0; i < D * D; ++i) mm[i] = cd(o.mat[2 * i], o.mat[2 * i + 1]);
+      } else {
+        gate_matrix(o.gate, o.p, mm);
+      }
+      for (int r = 0; r < D; ++r)
+        for (int cc = 0; cc < D; ++cc) inv[k][r * D + cc] = std::conj(mm[cc * D + r]);
+      bool dg = true;
+      for (int r = 0; r < D; ++r)
+        for (int cc = 0; cc < D; ++cc)
+          if (r != cc && inv[k][r * D + cc] != cd(0.0)) dg = false;
+      isdiag[k] = dg;
+      const bool rot = o.gate == QSV_RX || o.gate == QSV_RY || o.gate == QSV_RZ;
+      bool sg = dg && !rot && o.nq <= 2;
+      for (int e = 0; sg && e < D; ++e) {
+        const cd want = (e == D - 1) ? cd(-1.0) : cd(1.0);
+        if (inv[k][e * D + e] != want) sg = false;
+      }
+      issign[k] = sg;
+    }
+    auto touches = [&](size_t k, int q) {
+      const qsv_op& o = ops[as.ops[k]];
+      for (int i = 0; i < o.nq; ++i)
+        if (o.q[i] == q) return true;
+      return false;
+    };
+    struct Item {
+      int type;  // 0 one op, 4 chain, 5 signs
+      std::vector<size_t> ks;
+    };
+    std::vector<Item> items;
+    for (size_t i = 0; i < m; ++i) {
+      if (used[i]) continue;
+      used[i] = 1;
+      const qsv_op& oi = ops[as.ops[i]];
+      Item it{0, {i}};
+      if (oi.nq == 1 && lpos[oi.q[0]] >= 0) {
+        const int q = oi.q[0];
+        for (size_t j = i + 1; j < m && it.ks.size() < 4; ++j) {
+          if (used[j] || !touches(j, q)) continue;
+          if (ops[as.ops[j]].nq != 1) break;
+          used[j] = 1;
+          it.ks.push_back(j);
+        }
+        if (it.ks.size() > 1) it.type = 4;
+      } else if (issign[i]) {
+        std::vector<char> blocked(n, 0);
+        for (size_t j = i + 1; j < m && it.ks.size() < 24; ++j) {
+          if (used[j]) continue;
+          const qsv_op& oj = ops[as.ops[j]];
+          bool free = true;
+          for (int e = 0; e < oj.nq; ++e)
+            if (blocked[oj.q[e]]) free = false;
+          if (issign[j] && free) {
+            used[j] = 1;
+            it.ks.push_back(j);
+          } else if (!isdiag[j]) {
+            for (int e = 0; e < oj.nq; ++e) blocked[oj.q[e]] = 1;
+          }
+        }
+        if (it.ks.size() > 1) it.type = 5;
+      }
+      items.push_back(std::move(it));
+    }
+    auto nrot = [&](const Item& it) {
+      int r = 0;
+      for (size_t k : it.ks) {
+        const int g = ops[as.ops[k]].gate;
+        r += g == QSV_RX || g == QSV_RY || g == QSV_RZ;
+      }
+      return r;
+    };
     size_t k0 = 0;
-    while (k0 < as.ops.size()) {  // one program per at most GMAX rotations
+    while (k0 < items.size()) {  // one program per at most GMAX rotations
       size_t k1 = k0;
       int ng = 0;
-      while (k1 < as.ops.size()) {
-        const int g = ops[as.ops[k1]].gate;
-        const bool rot = g == QSV_RX || g == QSV_RY || g == QSV_RZ;
-        if (rot && ng == GMAX) break;
-        ng += rot;
+      while (k1 < items.size()) {
+        const int r = nrot(items[k1]);
+        if (ng + r > GMAX) break;
+        ng += r;
         ++k1;
       }
       const size_t off = prog.size();
@@ -742,29 +827,93 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
       for (int j = 0; j < t; ++j) prog[off + 8 + j] = as.S[j];
       for (size_t j = 0; j < nonS.size(); ++j) prog[off + 8 + t + j] = nonS[j];
       std::vector<int32_t> map;
+      auto put_cd = [](std::vector<int32_t>& rec, int e, cd v) {
+        const double re = v.real(), im = v.imag();
+        std::memcpy(&rec[8 + 4 * e], &re, 8);
+        std::memcpy(&rec[8 + 4 * e + 2], &im, 8);
+      };
+      auto gen_of = [](int g) { return g == QSV_RX ? 0 : g == QSV_RY ? 1 : 2; };
       for (size_t k = k0; k < k1; ++k) {
-        const qsv_op& o = ops[as.ops[k]];
-        const int D = 1 << o.nq;
-        cd m[16];
-        if (o.gate == QSV_MAT) {
-          for (int i = 0; i < D * D; ++i) m[i] = cd(o.mat[2 * i], o.mat[2 * i + 1]);
-        } else {
-          gate_matrix(o.gate, o.p, m);
-        }
-        cd mi[16];  // the inverse: conjugate transpose
-        for (int r = 0; r < D; ++r)
-          for (int cc = 0; cc < D; ++cc) mi[r * D + cc] = std::conj(m[cc * D + r]);
-        bool diag = true;
-        for (int r = 0; r < D; ++r)
-          for (int cc = 0; cc < D; ++cc)
-            if (r != cc && mi[r * D + cc] != cd(0.0)) diag = false;
+        const Item& item = items[k];
         std::vector<int32_t> rec(LR, 0);
+        if (item.type == 4) {
+          rec[0] = 4;
+          rec[1] = lpos[ops[as.ops[item.ks[0]]].q[0]];
+          rec[2] = (int32_t)item.ks.size();
+          for (int e = 0; e < 4; ++e) rec[3 + e] = -1;
+          for (size_t e = 0; e < item.ks.size(); ++e) {
+            const qsv_op& o = ops[as.ops[item.ks[e]]];
+            if (o.gate == QSV_RX || o.gate == QSV_RY || o.gate == QSV_RZ) {
+              rec[3 + e] = (int32_t)map.size();
+              map.push_back(as.ops[item.ks[e]]);
+              rec[7] |= gen_of(o.gate) << (2 * e);
+            }
+            for (int f = 0; f < 4; ++f) put_cd(rec, 4 * (int)e + f, inv[item.ks[e]][f]);
+          }
+          prog.insert(prog.end(), rec.begin(), rec.end());
+          continue;
+        }
+        if (item.type == 5) {
+          std::vector<int> dmask(t, 0);
+          std::vector<std::pair<int, int>> lo, oo;
+          for (size_t kk : item.ks) {
+            const qsv_op& o = ops[as.ops[kk]];
+            if (o.nq == 1) {
+              const int q = o.q[0];
+              if (lpos[q] >= 0)
+                lo.push_back({lpos[q], -1});
+              else
+                oo.push_back({q, q});
+              continue;
+            }
+            const int a = o.q[0], b = o.q[1];
+            if (lpos[a] >= 0 && lpos[b] >= 0) {
+              const int x = std::min(lpos[a], lpos[b]), y = std::max(lpos[a], lpos[b]);
+              dmask[y - x] ^= 1 << x;
+            } else if (lpos[a] >= 0) {
+              lo.push_back({lpos[a], b});
+            } else if (lpos[b] >= 0) {
+              lo.push_back({lpos[b], a});
+            } else {
+              oo.push_back({a, b});
+            }
+          }
+          std::vector<int32_t> w;
+          int nd = 0;
+          for (int d = 1; d < t; ++d)
+            if (dmask[d]) {
+              w.push_back(d);
+              w.push_back(dmask[d]);
+              ++nd;
+            }
+          for (auto& pr : lo) {
+            w.push_back(pr.first);
+            w.push_back(pr.second);
+          }
+          for (auto& pr : oo) {
+            w.push_back(pr.first);
+            w.push_back(pr.second);
+          }
+          if (w.size() > (size_t)(LR - 8)) return fail(QSV_ERR_STATE, "adjoint sign record overflow");
+          rec[0] = 5;
+          rec[1] = nd;
+          rec[2] = (int32_t)lo.size();
+          rec[3] = (int32_t)oo.size();
+          std::copy(w.begin(), w.end(), rec.begin() + 8);
+          prog.insert(prog.end(), rec.begin(), rec.end());
+          continue;
+        }
+        const size_t kk = item.ks[0];
+        const qsv_op& o = ops[as.ops[kk]];
+        const int D = 1 << o.nq;
+        const cd* mi = inv[kk].data();
+        const bool diag = isdiag[kk];
         rec[3] = -1;
         const bool rot = o.gate == QSV_RX || o.gate == QSV_RY || o.gate == QSV_RZ;
         if (rot) {
           rec[3] = (int32_t)map.size();
-          map.push_back(as.ops[k]);
-          rec[4] = o.gate == QSV_RX ? 0 : o.gate == QSV_RY ? 1 : 2;
+          map.push_back(as.ops[kk]);
+          rec[4] = gen_of(o.gate);
         }
         cd vals[16];
         int nv = 0;
@@ -791,8 +940,8 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
           for (int e = 0; e < 16; ++e) u[e] = mi[e];
           if (ja > jb) {
             auto sw = [](int m2) { return ((m2 & 1) << 1) | ((m2 >> 1) & 1); };
-            for (int a = 0; a < 4; ++a)
-              for (int b = 0; b < 4; ++b) u[sw(a) * 4 + sw(b)] = mi[a * 4 + b];
+            for (int a2 = 0; a2 < 4; ++a2)
+              for (int b2 = 0; b2 < 4; ++b2) u[sw(a2) * 4 + sw(b2)] = mi[a2 * 4 + b2];
             std::swap(ja, jb);
           }
           rec[1] = ja;
@@ -801,11 +950,7 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
           nv = 16;
         }
         if (rot && rec[0] == 3) return fail(QSV_ERR_STATE, "rotation as a 2-qubit op");
-        for (int e = 0; e < nv; ++e) {
-          const double re = vals[e].real(), im = vals[e].imag();
-          std::memcpy(&rec[8 + 4 * e], &re, 8);
-          std::memcpy(&rec[8 + 4 * e + 2], &im, 8);
-        }
+        for (int e = 0; e < nv; ++e) put_cd(rec, e, vals[e]);
         prog.insert(prog.end(), rec.begin(), rec.end());
       }
       prog[off + 6] = (int32_t)(prog.size() - off);

@@ -73,6 +73,50 @@ def test_adjoint_with_mixed_gates(dtype):
     assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_adjoint_chains_and_sign_runs(dtype):
+    # four one-qubit gates per qubit between entanglers (merged into one LDS
+    # pass per qubit), CZ rings reaching qubits outside a tile, Z gates, and a
+    # CZ that cancels one of the ring's
+    n, layers = 14, 2
+    rng = np.random.default_rng(41)
+    nrot = n * 2 * layers
+    theta = rng.uniform(-np.pi, np.pi, nrot)
+
+    def build(p):
+        ops, k = [], 0
+        for l in range(layers):
+            for q in range(n):
+                ops += [qc.op("H", q), qc.op("RZ", q, params=(p[k],)), qc.op("S", q),
+                        qc.op("RX" if q % 2 else "RY", q, params=(p[k + 1],))]
+                k += 2
+            for q in range(n):
+                ops.append(qc.op("CZ", q, (q + 1 + 5 * l) % n))
+            ops += [qc.op("Z", q) for q in range(0, n, 3)]
+            ops.append(qc.op("CZ", 0, n - 1))
+        return ops
+
+    ops = build(theta)
+    idx = np.array([-1] * len(ops))
+    k = 0
+    for i, o in enumerate(ops):
+        if o.name in ("RX", "RY", "RZ"):
+            idx[i] = k
+            k += 1
+    ham = qc.random_hamiltonian(n, 10, 43)
+    s = State(n, dtype)
+    e, g_ops = s.adjoint(ops, ham)
+    back = s.to_numpy()
+    s.close()
+    g = np.zeros(nrot)
+    np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
+    ref = O.param_shift_grad(build, theta, ham, n)
+    assert abs(e - O.energy(build, theta, ham, n)) <= GTOL[dtype] * len(ham)
+    assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham)
+    assert np.all(g_ops[idx < 0] == 0)
+    assert abs(back[0] - 1) < (1e-10 if dtype == "c128" else 1e-4)
+
+
 def test_autograd_function():
     import torch
     from paper_1807_07914_amd.autograd import expectation
