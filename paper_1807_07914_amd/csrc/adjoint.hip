@@ -131,11 +131,6 @@ __global__ __launch_bounds__(kAB) void k_adj_final(const double* __restrict__ pa
 //           kind << 8 | value (kind 0: local bit, 2: qubit outside the tile),
 //           b = -1 for one qubit (d[0], d[1]); a gradient slot takes Z on a
 //   3 U2  : 4x4 on local bits a < b (a = LSB of the row index)
-//   4 CHAIN: [2] count (<= 4) 2x2 matrices on local bit a, applied in turn
-//           to each pair, so that consecutive one-qubit gates on one qubit
-//           share one LDS round trip; [3 + e] gradient slot of element e or
-//           -1, [7] generators (two bits per element), matrix e from word
-//           8 + 16 e
 //   5 SIGNS: a run of CZ and Z gates as one sign pattern; [1] n_dist,
 //           [2] n_lo, [3] n_oo, then from word 8: n_dist pairs (d, M),
 //           n_lo pairs (local bit, outside qubit or -1), n_oo pairs of
@@ -144,14 +139,34 @@ __global__ __launch_bounds__(kAB) void k_adj_final(const double* __restrict__ pa
 //           the local bits whose partner is -1 or a qubit set in the tile's
 //           base index and c the parity of the outside pairs with both
 //           qubits set (a Z outside the tile is the pair (q, q))
+//   6 ROUND: one-qubit gates on K local qubits applied in registers: each
+//           thread holds the 2^K amplitudes of both states that differ in
+//           those bits and applies every gate of the record to them in turn
+//           (gates on different qubits commute, gates on one qubit keep
+//           their order), taking each rotation's term first.  [2] n_gates,
+//           [3] record length in words, [4 + j] local bit j (ascending),
+//           gates from word 8, kAdjGate words each: [0] j | shape << 4 |
+//           generator << 8, [1] gradient slot or -1, matrix from word 4
+// Records of types 1-5 are kAdjRec words long.
 constexpr int kAdjRec = 72;
+constexpr int kAdjGate = 20;
+
+template <typename T>
+struct AdjRound {
+  static constexpr int K = sizeof(T) == 4 ? 4 : 3;  // register bits per round
+};
 constexpr int kMaxAdjGrad = 256;
 
 template <typename T>
-__device__ __forceinline__ cpx<T> rec_cpx(const int32_t* r, int e) {
-  const double re = __hiloint2double(r[8 + 4 * e + 1], r[8 + 4 * e]);
-  const double im = __hiloint2double(r[8 + 4 * e + 3], r[8 + 4 * e + 2]);
+__device__ __forceinline__ cpx<T> cpx_at(const int32_t* w, int e) {
+  const double re = __hiloint2double(w[4 * e + 1], w[4 * e]);
+  const double im = __hiloint2double(w[4 * e + 3], w[4 * e + 2]);
   return cpx<T>{(T)re, (T)im};
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> rec_cpx(const int32_t* r, int e) {
+  return cpx_at<T>(r + 8, e);
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -160,16 +175,93 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// Im( conj(l0) (G p)_0 + conj(l1) (G p)_1 ) for G = X, Y or Z, in FP64
+// Im( conj(l0) (G p)_0 + conj(l1) (G p)_1 ) for G = X, Y or Z: one pair's
+// term, formed in the amplitudes' own precision and handed to the FP64 sums
 template <typename T>
 __device__ __forceinline__ double grad_pair(int gen, cpx<T> p0, cpx<T> p1, cpx<T> l0, cpx<T> l1) {
-  const double a0r = l0.x, a0i = l0.y, a1r = l1.x, a1i = l1.y;
-  const double b0r = p0.x, b0i = p0.y, b1r = p1.x, b1i = p1.y;
+  T v;
   if (gen == 0)  // X: Im(conj(l0) p1 + conj(l1) p0)
-    return (a0r * b1i - a0i * b1r) + (a1r * b0i - a1i * b0r);
-  if (gen == 1)  // Y: -Re(conj(l0) p1) + Re(conj(l1) p0)
-    return -(a0r * b1r + a0i * b1i) + (a1r * b0r + a1i * b0i);
-  return (a0r * b0i - a0i * b0r) - (a1r * b1i - a1i * b1r);  // Z
+    v = (l0.x * p1.y - l0.y * p1.x) + (l1.x * p0.y - l1.y * p0.x);
+  else if (gen == 1)  // Y: -Re(conj(l0) p1) + Re(conj(l1) p0)
+    v = (l1.x * p0.x + l1.y * p0.y) - (l0.x * p1.x + l0.y * p1.y);
+  else  // Z
+    v = (l0.x * p0.y - l0.y * p0.x) - (l1.x * p1.y - l1.y * p1.x);
+  return (double)v;
+}
+
+// 2x2 on a pair by the matrix's shape (uniform per record): 1 diagonal,
+// 2 real, 3 real diagonal with imaginary off-diagonal (RX), 0 general
+template <typename T>
+__device__ __forceinline__ void apply_form(int form, const M2<T>& V, cpx<T>& a, cpx<T>& b) {
+  const cpx<T> x = a, y = b;
+  if (form == 1) {
+    a = cmul(V.m[0], x);
+    b = cmul(V.m[3], y);
+  } else if (form == 2) {
+    a = cpx<T>{V.m[0].x * x.x + V.m[1].x * y.x, V.m[0].x * x.y + V.m[1].x * y.y};
+    b = cpx<T>{V.m[2].x * x.x + V.m[3].x * y.x, V.m[2].x * x.y + V.m[3].x * y.y};
+  } else if (form == 3) {
+    a = cpx<T>{V.m[0].x * x.x - V.m[1].y * y.y, V.m[0].x * x.y + V.m[1].y * y.x};
+    b = cpx<T>{V.m[3].x * y.x - V.m[2].y * x.y, V.m[3].x * y.y + V.m[2].y * x.x};
+  } else {
+    apply2(V, a, b);
+  }
+}
+
+// LDS position of tile amplitude l: the bits that select a 256-byte row are
+// XORed into the position within the row, so lanes whose amplitudes differ
+// only above the row (register groups over low qubits) fall in distinct banks
+template <typename T>
+__device__ __forceinline__ uint32_t swz(uint32_t l) {
+  constexpr int SB = sizeof(T) == 4 ? 5 : 4;
+  return l ^ ((l >> SB) & ((1u << SB) - 1u));
+}
+
+// A ROUND gate on register bit J of the 2^K amplitudes x (psi) and y
+// (lambda) that one thread holds: the rotation's term over its pairs (before
+// the gate), then the gate; shape and generator are template arguments so
+// the pair loops carry no branches
+template <typename T, int K, int J, int G>
+__device__ __forceinline__ double round_grad(const cpx<T>* x, const cpx<T>* y) {
+  double g = 0.0;
+#pragma unroll
+  for (int q = 0; q < (1 << (K - 1)); ++q) {
+    const int i0 = ((q >> J) << (J + 1)) | (q & ((1 << J) - 1)), i1 = i0 | (1 << J);
+    g += grad_pair<T>(G, x[i0], x[i1], y[i0], y[i1]);
+  }
+  return g;
+}
+
+template <typename T, int K, int J, int F>
+__device__ __forceinline__ void round_apply(const M2<T>& V, cpx<T>* x, cpx<T>* y) {
+#pragma unroll
+  for (int q = 0; q < (1 << (K - 1)); ++q) {
+    const int i0 = ((q >> J) << (J + 1)) | (q & ((1 << J) - 1)), i1 = i0 | (1 << J);
+    apply_form(F, V, x[i0], x[i1]);
+    apply_form(F, V, y[i0], y[i1]);
+  }
+}
+
+template <typename T, int K, int J>
+__device__ __forceinline__ double round_gate(int form, int gen, bool grad, const M2<T>& V, cpx<T>* x, cpx<T>* y) {
+  double g = 0.0;
+  if (grad) {
+    if (gen == 0)
+      g = round_grad<T, K, J, 0>(x, y);
+    else if (gen == 1)
+      g = round_grad<T, K, J, 1>(x, y);
+    else
+      g = round_grad<T, K, J, 2>(x, y);
+  }
+  if (form == 1)
+    round_apply<T, K, J, 1>(V, x, y);
+  else if (form == 2)
+    round_apply<T, K, J, 2>(V, x, y);
+  else if (form == 3)
+    round_apply<T, K, J, 3>(V, x, y);
+  else
+    round_apply<T, K, J, 0>(V, x, y);
+  return g;
 }
 
 template <typename T, int TB>
@@ -209,13 +301,13 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
       const vec16<T> x = gp[g], y = gl[g];
 #pragma unroll
       for (int e = 0; e < A; ++e) {
-        tp[l + e] = x.a[e];
-        tl[l + e] = y.a[e];
+        tp[swz<T>(l + e)] = x.a[e];
+        tl[swz<T>(l + e)] = y.a[e];
       }
     }
     __syncthreads();
-    for (int o = 0; o < nops; ++o) {
-      const int32_t* r = recs + o * kAdjRec;
+    const int32_t* r = recs;
+    for (int o = 0; o < nops; ++o, r += r[0] == 6 ? r[3] : kAdjRec) {
       const int type = r[0], ra = r[1], rb = r[2], slot = type < 4 ? r[3] : -1, gen = r[4];
       double g = 0.0;
       if (type == 1) {
@@ -225,19 +317,17 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
         const uint32_t lowm = (1u << ra) - 1u;
         for (int u = threadIdx.x; u < half; u += kAB) {
           const uint32_t i0 = (((uint32_t)u >> ra) << (ra + 1)) | ((uint32_t)u & lowm), i1 = i0 | (1u << ra);
-          cpx<T> p0 = tp[i0], p1 = tp[i1], l0 = tl[i0], l1 = tl[i1];
+          cpx<T> p0 = tp[swz<T>(i0)], p1 = tp[swz<T>(i1)], l0 = tl[swz<T>(i0)], l1 = tl[swz<T>(i1)];
           if (slot >= 0) g += grad_pair<T>(gen, p0, p1, l0, l1);
           apply2(V, p0, p1);
           apply2(V, l0, l1);
-          tp[i0] = p0;
-          tp[i1] = p1;
-          tl[i0] = l0;
-          tl[i1] = l1;
+          tp[swz<T>(i0)] = p0;
+          tp[swz<T>(i1)] = p1;
+          tl[swz<T>(i0)] = l0;
+          tl[swz<T>(i1)] = l1;
         }
       } else if (type == 2) {
-        cpx<T> d[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) d[e] = rec_cpx<T>(r, e);
+        const cpx<T> d0 = rec_cpx<T>(r, 0), d1 = rec_cpx<T>(r, 1), d2 = rec_cpx<T>(r, 2), d3 = rec_cpx<T>(r, 3);
         const int ka = ra >> 8, va = ra & 255;
         const int kb = rb < 0 ? -1 : (rb >> 8), vb = rb < 0 ? 0 : (rb & 255);
         const int oa = ka == 0 ? -1 : (int)((base >> va) & 1ull);  // outside operands: one bit per tile
@@ -245,45 +335,65 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
         for (int l = threadIdx.x; l < full; l += kAB) {
           const int bA = oa >= 0 ? oa : (l >> va) & 1;
           const int bB = ob >= 0 ? ob : (l >> vb) & 1;
-          const cpx<T> dd = d[bA + 2 * bB];
-          const cpx<T> p = tp[l], q = tl[l];
+          const cpx<T> dd = bB ? (bA ? d3 : d2) : (bA ? d1 : d0);
+          const cpx<T> p = tp[swz<T>(l)], q = tl[swz<T>(l)];
           if (slot >= 0) {
             const double im = (double)q.x * (double)p.y - (double)q.y * (double)p.x;
             g += bA ? -im : im;
           }
-          tp[l] = cmul(dd, p);
-          tl[l] = cmul(dd, q);
+          tp[swz<T>(l)] = cmul(dd, p);
+          tl[swz<T>(l)] = cmul(dd, q);
         }
-      } else if (type == 4) {
-        const int cnt = rb, gens = r[7];
-        const uint32_t lowm = (1u << ra) - 1u;
-        M2<T> V[4];
+      } else if (type == 6) {
+        constexpr int K = AdjRound<T>::K, NR = 1 << K;
+        const int ngate = rb;
+        uint32_t off[NR];
+        off[0] = 0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int m = 1; m < NR; ++m) off[m] = off[m & (m - 1)] | (1u << r[4 + __builtin_ctz(m)]);
+        const int ngroups = full >> K;
+        for (int g0 = 0; g0 < ngroups; g0 += kAB) {  // every lane runs every group step (shuffles below)
+          const int gi = g0 + (int)threadIdx.x;
+          const bool valid = gi < ngroups;
+          uint32_t b = (uint32_t)gi;
 #pragma unroll
-          for (int f = 0; f < 4; ++f) V[e].m[f] = rec_cpx<T>(r, 4 * e + f);
-        double ge[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int u = threadIdx.x; u < half; u += kAB) {
-          const uint32_t i0 = (((uint32_t)u >> ra) << (ra + 1)) | ((uint32_t)u & lowm), i1 = i0 | (1u << ra);
-          cpx<T> p0 = tp[i0], p1 = tp[i1], l0 = tl[i0], l1 = tl[i1];
+          for (int j = 0; j < K; ++j) {
+            const int bj = r[4 + j];
+            b = ((b >> bj) << (bj + 1)) | (b & ((1u << bj) - 1u));
+          }
+          cpx<T> x[NR], y[NR];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            if (e < cnt) {
-              if (r[3 + e] >= 0) ge[e] += grad_pair<T>((gens >> (2 * e)) & 3, p0, p1, l0, l1);
-              apply2(V[e], p0, p1);
-              apply2(V[e], l0, l1);
+          for (int m = 0; m < NR; ++m) {
+            x[m] = valid ? tp[swz<T>(b | off[m])] : cpx<T>{0, 0};
+            y[m] = valid ? tl[swz<T>(b | off[m])] : cpx<T>{0, 0};
+          }
+          const int32_t* gw = r + 8;
+          for (int e = 0; e < ngate; ++e, gw += kAdjGate) {
+            const int info = gw[0], gslot = gw[1];
+            const int j = info & 15, form = (info >> 4) & 3, gn = (info >> 8) & 3;
+            M2<T> V;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) V.m[f] = cpx_at<T>(gw + 4, f);
+            double gv;
+            if (j == 0)
+              gv = round_gate<T, K, 0>(form, gn, gslot >= 0, V, x, y);
+            else if (j == 1)
+              gv = round_gate<T, K, 1>(form, gn, gslot >= 0, V, x, y);
+            else if (j == 2 || K == 3)
+              gv = round_gate<T, K, 2>(form, gn, gslot >= 0, V, x, y);
+            else
+              gv = round_gate<T, K, (K > 3 ? 3 : 2)>(form, gn, gslot >= 0, V, x, y);
+            if (gslot >= 0) {
+              gv = wave_sum_d(gv);
+              if (lane == 0) gacc[gslot * (kAB / 64) + wave] += gv;
             }
           }
-          tp[i0] = p0;
-          tp[i1] = p1;
-          tl[i0] = l0;
-          tl[i1] = l1;
-        }
+          if (valid) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (e < cnt && r[3 + e] >= 0) {
-            const double v = wave_sum_d(ge[e]);
-            if (lane == 0) gacc[r[3 + e] * (kAB / 64) + wave] += v;
+            for (int m = 0; m < NR; ++m) {
+              tp[swz<T>(b | off[m])] = x[m];
+              tl[swz<T>(b | off[m])] = y[m];
+            }
           }
         }
       } else if (type == 5) {
@@ -303,9 +413,9 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
           int par = cpar + __popc((uint32_t)l & Mo);
           for (int i = 0; i < nd; ++i) par += __popc((uint32_t)l & ((uint32_t)l >> w[2 * i]) & (uint32_t)w[2 * i + 1]);
           if (par & 1) {
-            const cpx<T> p = tp[l], q = tl[l];
-            tp[l] = cpx<T>{-p.x, -p.y};
-            tl[l] = cpx<T>{-q.x, -q.y};
+            const cpx<T> p = tp[swz<T>(l)], q = tl[swz<T>(l)];
+            tp[swz<T>(l)] = cpx<T>{-p.x, -p.y};
+            tl[swz<T>(l)] = cpx<T>{-q.x, -q.y};
           }
         }
       } else {
@@ -321,8 +431,8 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
           cpx<T> x[4], y[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            x[e] = tp[ix[e]];
-            y[e] = tl[ix[e]];
+            x[e] = tp[swz<T>(ix[e])];
+            y[e] = tl[swz<T>(ix[e])];
           }
 #pragma unroll
           for (int rr = 0; rr < 4; ++rr) {
@@ -332,8 +442,8 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
               ax = cfma(U.m[4 * rr + cc], x[cc], ax);
               ay = cfma(U.m[4 * rr + cc], y[cc], ay);
             }
-            tp[ix[rr]] = ax;
-            tl[ix[rr]] = ay;
+            tp[swz<T>(ix[rr])] = ax;
+            tl[swz<T>(ix[rr])] = ay;
           }
         }
       }
@@ -349,8 +459,8 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
       vec16<T> x, y;
 #pragma unroll
       for (int e = 0; e < A; ++e) {
-        x.a[e] = tp[l + e];
-        y.a[e] = tl[l + e];
+        x.a[e] = tp[swz<T>(l + e)];
+        y.a[e] = tl[swz<T>(l + e)];
       }
       gp[g] = x;
       gl[g] = y;
@@ -380,6 +490,13 @@ int adj_tile_bits() {
 }
 int adj_max_grad() { return kMaxAdjGrad; }
 int adj_rec_words() { return kAdjRec; }
+int adj_gate_words() { return kAdjGate; }
+template <typename T>
+int adj_round_bits() {
+  return AdjRound<T>::K;
+}
+template int adj_round_bits<float>();
+template int adj_round_bits<double>();
 
 // Workgroups of the sweep kernel resident at once (cached per device).
 template <typename T>

@@ -705,6 +705,8 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
   std::vector<AdjStep> steps;
   plan_adjoint(ops, n_ops, n, t, c, RB, steps);
   const int LR = adj_rec_words(), GMAX = adj_max_grad();
+  const int RK = adj_round_bits<T>(), kGateWords = adj_gate_words();
+  constexpr int kRoundGates = 24;  // gates per round record
   std::vector<int32_t>& prog = s->ahprog;
   prog.clear();
   struct Launch {
@@ -759,15 +761,16 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
       return false;
     };
     struct Item {
-      int type;  // 0 one op, 4 chain, 5 signs
+      int type;  // 0 one op, 4 chain, 5 signs, 6 register round
       std::vector<size_t> ks;
+      std::vector<int> bits;  // round: local bits, ascending
     };
     std::vector<Item> items;
     for (size_t i = 0; i < m; ++i) {
       if (used[i]) continue;
       used[i] = 1;
       const qsv_op& oi = ops[as.ops[i]];
-      Item it{0, {i}};
+      Item it{0, {i}, {}};
       if (oi.nq == 1 && lpos[oi.q[0]] >= 0) {
         const int q = oi.q[0];
         for (size_t j = i + 1; j < m && it.ks.size() < 4; ++j) {
@@ -795,6 +798,57 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
         if (it.ks.size() > 1) it.type = 5;
       }
       items.push_back(std::move(it));
+    }
+    // Runs of items that are one-qubit ops on local qubits become register
+    // rounds over K of the run's qubits each (ops on different qubits
+    // commute; ops on one qubit keep their order); a round with fewer qubits
+    // carries other local bits along.
+    {
+      std::vector<Item> merged;
+      std::vector<size_t> run;
+      auto one_local = [&](const Item& it) {
+        if (it.type == 4) return true;
+        const qsv_op& o = ops[as.ops[it.ks[0]]];
+        return it.type == 0 && o.nq == 1 && lpos[o.q[0]] >= 0;
+      };
+      auto flush = [&]() {
+        if (run.empty()) return;
+        std::vector<int> order;  // qubits by first appearance
+        for (size_t k : run) {
+          const int q = ops[as.ops[k]].q[0];
+          if (std::find(order.begin(), order.end(), q) == order.end()) order.push_back(q);
+        }
+        for (size_t g0 = 0; g0 < order.size(); g0 += RK) {
+          const size_t g1 = std::min(order.size(), g0 + (size_t)RK);
+          std::vector<int> bits;
+          for (size_t g = g0; g < g1; ++g) bits.push_back(lpos[order[g]]);
+          for (int j = 0; (int)bits.size() < RK; ++j)
+            if (std::find(bits.begin(), bits.end(), j) == bits.end()) bits.push_back(j);
+          std::sort(bits.begin(), bits.end());
+          Item it{6, {}, bits};
+          for (size_t k : run) {
+            const int q = ops[as.ops[k]].q[0];
+            if (std::find(order.begin() + g0, order.begin() + g1, q) == order.begin() + g1) continue;
+            it.ks.push_back(k);
+            if ((int)it.ks.size() == kRoundGates) {
+              merged.push_back(it);
+              it.ks.clear();
+            }
+          }
+          if (!it.ks.empty()) merged.push_back(it);
+        }
+        run.clear();
+      };
+      for (Item& it : items) {
+        if (one_local(it)) {
+          run.insert(run.end(), it.ks.begin(), it.ks.end());
+        } else {
+          flush();
+          merged.push_back(std::move(it));
+        }
+      }
+      flush();
+      items.swap(merged);
     }
     auto nrot = [&](const Item& it) {
       int r = 0;
@@ -836,21 +890,40 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
       for (size_t k = k0; k < k1; ++k) {
         const Item& item = items[k];
         std::vector<int32_t> rec(LR, 0);
-        if (item.type == 4) {
-          rec[0] = 4;
-          rec[1] = lpos[ops[as.ops[item.ks[0]]].q[0]];
-          rec[2] = (int32_t)item.ks.size();
-          for (int e = 0; e < 4; ++e) rec[3 + e] = -1;
+        if (item.type == 6) {
+          std::vector<int32_t> rr(8 + kGateWords * item.ks.size(), 0);
+          rr[0] = 6;
+          rr[2] = (int32_t)item.ks.size();
+          rr[3] = (int32_t)rr.size();
+          for (int j = 0; j < RK; ++j) rr[4 + j] = item.bits[j];
           for (size_t e = 0; e < item.ks.size(); ++e) {
-            const qsv_op& o = ops[as.ops[item.ks[e]]];
+            const size_t kk = item.ks[e];
+            const qsv_op& o = ops[as.ops[kk]];
+            int32_t* gw = rr.data() + 8 + kGateWords * e;
+            const int j = (int)(std::find(item.bits.begin(), item.bits.end(), lpos[o.q[0]]) - item.bits.begin());
+            const cd* u = inv[kk].data();
+            int form = 0;  // shape of the 2x2, so the kernel skips its zero parts
+            if (u[1] == cd(0.0) && u[2] == cd(0.0))
+              form = 1;
+            else if (u[0].imag() == 0.0 && u[1].imag() == 0.0 && u[2].imag() == 0.0 && u[3].imag() == 0.0)
+              form = 2;
+            else if (u[0].imag() == 0.0 && u[3].imag() == 0.0 && u[1].real() == 0.0 && u[2].real() == 0.0)
+              form = 3;
+            int gen = 0;
+            gw[1] = -1;
             if (o.gate == QSV_RX || o.gate == QSV_RY || o.gate == QSV_RZ) {
-              rec[3 + e] = (int32_t)map.size();
-              map.push_back(as.ops[item.ks[e]]);
-              rec[7] |= gen_of(o.gate) << (2 * e);
+              gw[1] = (int32_t)map.size();
+              map.push_back(as.ops[kk]);
+              gen = gen_of(o.gate);
             }
-            for (int f = 0; f < 4; ++f) put_cd(rec, 4 * (int)e + f, inv[item.ks[e]][f]);
+            gw[0] = j | (form << 4) | (gen << 8);
+            for (int f = 0; f < 4; ++f) {
+              const double re = u[f].real(), im = u[f].imag();
+              std::memcpy(gw + 4 + 4 * f, &re, 8);
+              std::memcpy(gw + 4 + 4 * f + 2, &im, 8);
+            }
           }
-          prog.insert(prog.end(), rec.begin(), rec.end());
+          prog.insert(prog.end(), rr.begin(), rr.end());
           continue;
         }
         if (item.type == 5) {

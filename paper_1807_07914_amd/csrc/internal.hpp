@@ -110,6 +110,9 @@ template <typename T>
 int adj_tile_bits();
 int adj_max_grad();
 int adj_rec_words();
+int adj_gate_words();
+template <typename T>
+int adj_round_bits();
 
 // reductions: FP64 partials written to ws, final values to out_dev (doubles)
 template <typename T>
