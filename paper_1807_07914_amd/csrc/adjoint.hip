@@ -146,7 +146,8 @@ __global__ __launch_bounds__(kAB) void k_adj_final(const double* __restrict__ pa
 //           their order), taking each rotation's term first.  [2] n_gates,
 //           [3] record length in words, [4 + j] local bit j (ascending),
 //           gates from word 8, kAdjGate words each: [0] j | shape << 4 |
-//           generator << 8, [1] gradient slot or -1, matrix from word 4
+//           generator << 8, [1] gradient slot or -1, from word 4 the
+//           matrix (m00, m01, m10, m11 as re, im) in the state's precision
 // Records of types 1-5 are kAdjRec words long.
 constexpr int kAdjRec = 72;
 constexpr int kAdjGate = 20;
@@ -169,10 +170,28 @@ __device__ __forceinline__ cpx<T> rec_cpx(const int32_t* r, int e) {
   return cpx_at<T>(r + 8, e);
 }
 
+// One DPP step of a sum: v + v taken from the lane that CTRL selects (both
+// 32-bit halves moved with the same pattern)
+template <int CTRL>
+__device__ __forceinline__ double dpp_add(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return v + __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_d(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the 64 lanes, the same in every lane (all lanes active): lane
+// pairs, quads, then rows of 16 by DPP, and the four row sums in a fixed order
 __device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x124>(v);  // row_ror 4
+  v = dpp_add<0x128>(v);  // row_ror 8
+  return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
 // Im( conj(l0) (G p)_0 + conj(l1) (G p)_1 ) for G = X, Y or Z: one pair's
@@ -189,24 +208,110 @@ __device__ __forceinline__ double grad_pair(int gen, cpx<T> p0, cpx<T> p1, cpx<T
   return (double)v;
 }
 
-// 2x2 on a pair by the matrix's shape (uniform per record): 1 diagonal,
-// 2 real, 3 real diagonal with imaginary off-diagonal (RX), 0 general
-template <typename T>
-__device__ __forceinline__ void apply_form(int form, const M2<T>& V, cpx<T>& a, cpx<T>& b) {
-  const cpx<T> x = a, y = b;
-  if (form == 1) {
-    a = cmul(V.m[0], x);
-    b = cmul(V.m[3], y);
-  } else if (form == 2) {
-    a = cpx<T>{V.m[0].x * x.x + V.m[1].x * y.x, V.m[0].x * x.y + V.m[1].x * y.y};
-    b = cpx<T>{V.m[2].x * x.x + V.m[3].x * y.x, V.m[2].x * x.y + V.m[3].x * y.y};
-  } else if (form == 3) {
-    a = cpx<T>{V.m[0].x * x.x - V.m[1].y * y.y, V.m[0].x * x.y + V.m[1].y * y.x};
-    b = cpx<T>{V.m[3].x * y.x - V.m[2].y * x.y, V.m[3].x * y.y + V.m[2].y * x.x};
-  } else {
-    apply2(V, a, b);
+// 2x2 on the pair (a0, a1) of psi and the pair (b0, b1) of lambda by the
+// matrix's shape, in place: m holds the uniform entries (m00, m01, m10, m11
+// as re, im).  Shape 1 diagonal, 2 real, 3 real diagonal with imaginary
+// off-diagonal (RX, Y), 0 general.  One asm block per pair of both states
+// whose results land in the amplitudes' own registers, so that the shapes'
+// code paths leave the register arrays where they were (left to itself the
+// compiler ties results to temporaries and copies arrays back at merges).
+#define QSV_F32_DIAG(X, Y)            \
+  "v_mul_f32 %[t0], %[m01], " Y "\n\t"  \
+  "v_mul_f32 " Y ", %[m00], " Y "\n\t"  \
+  "v_fmac_f32 " Y ", %[m01], " X "\n\t" \
+  "v_fma_f32 " X ", %[m00], " X ", -%[t0]\n\t"
+#define QSV_F32_REAL(A, B)            \
+  "v_mul_f32 %[t0], %[m01], " B "\n\t"  \
+  "v_mul_f32 " B ", %[m11], " B "\n\t"  \
+  "v_fmac_f32 " B ", %[m10], " A "\n\t" \
+  "v_fma_f32 " A ", %[m00], " A ", %[t0]\n\t"
+#define QSV_F32_RX(AX, AY, BX, BY)        \
+  "v_mul_f32 %[t0], %[m01], " BY "\n\t"     \
+  "v_mul_f32 %[t1], %[m10], " AY "\n\t"     \
+  "v_mul_f32 " AY ", %[m00], " AY "\n\t"    \
+  "v_fmac_f32 " AY ", %[m01], " BX "\n\t"   \
+  "v_mul_f32 " BY ", %[m11], " BY "\n\t"    \
+  "v_fmac_f32 " BY ", %[m10], " AX "\n\t"   \
+  "v_fma_f32 " AX ", %[m00], " AX ", -%[t0]\n\t" \
+  "v_fma_f32 " BX ", %[m11], " BX ", -%[t1]\n\t"
+#define QSV_F64_DIAG(X, Y)                  \
+  "v_mul_f64 %[t0], %[m01], " Y "\n\t"        \
+  "v_mul_f64 " Y ", %[m00], " Y "\n\t"        \
+  "v_fma_f64 " Y ", %[m01], " X ", " Y "\n\t" \
+  "v_fma_f64 " X ", %[m00], " X ", -%[t0]\n\t"
+#define QSV_F64_REAL(A, B)                  \
+  "v_mul_f64 %[t0], %[m01], " B "\n\t"        \
+  "v_mul_f64 " B ", %[m11], " B "\n\t"        \
+  "v_fma_f64 " B ", %[m10], " A ", " B "\n\t" \
+  "v_fma_f64 " A ", %[m00], " A ", %[t0]\n\t"
+#define QSV_F64_RX(AX, AY, BX, BY)                \
+  "v_mul_f64 %[t0], %[m01], " BY "\n\t"             \
+  "v_mul_f64 %[t1], %[m10], " AY "\n\t"             \
+  "v_mul_f64 " AY ", %[m00], " AY "\n\t"            \
+  "v_fma_f64 " AY ", %[m01], " BX ", " AY "\n\t"    \
+  "v_mul_f64 " BY ", %[m11], " BY "\n\t"            \
+  "v_fma_f64 " BY ", %[m10], " AX ", " BY "\n\t"    \
+  "v_fma_f64 " AX ", %[m00], " AX ", -%[t0]\n\t"    \
+  "v_fma_f64 " BX ", %[m11], " BX ", -%[t1]\n\t"
+
+template <int F, typename T>
+__device__ __forceinline__ void form_apply2(const T* m, cpx<T>& a0, cpx<T>& a1, cpx<T>& b0, cpx<T>& b1) {
+  constexpr bool D = sizeof(T) == 8;
+  T t0, t1;
+  if (F == 1) {  // a0 *= m00, a1 *= m11 (complex), the same for b
+    if (D) {
+      asm(QSV_F64_DIAG("%[a0x]", "%[a0y]") QSV_F64_DIAG("%[b0x]", "%[b0y]")
+          : [a0x] "+v"(a0.x), [a0y] "+v"(a0.y), [b0x] "+v"(b0.x), [b0y] "+v"(b0.y), [t0] "=&v"(t0)
+          : [m00] "s"(m[0]), [m01] "s"(m[1]));
+      asm(QSV_F64_DIAG("%[a1x]", "%[a1y]") QSV_F64_DIAG("%[b1x]", "%[b1y]")
+          : [a1x] "+v"(a1.x), [a1y] "+v"(a1.y), [b1x] "+v"(b1.x), [b1y] "+v"(b1.y), [t0] "=&v"(t0)
+          : [m00] "s"(m[6]), [m01] "s"(m[7]));
+    } else {
+      asm(QSV_F32_DIAG("%[a0x]", "%[a0y]") QSV_F32_DIAG("%[b0x]", "%[b0y]")
+          : [a0x] "+v"(a0.x), [a0y] "+v"(a0.y), [b0x] "+v"(b0.x), [b0y] "+v"(b0.y), [t0] "=&v"(t0)
+          : [m00] "s"(m[0]), [m01] "s"(m[1]));
+      asm(QSV_F32_DIAG("%[a1x]", "%[a1y]") QSV_F32_DIAG("%[b1x]", "%[b1y]")
+          : [a1x] "+v"(a1.x), [a1y] "+v"(a1.y), [b1x] "+v"(b1.x), [b1y] "+v"(b1.y), [t0] "=&v"(t0)
+          : [m00] "s"(m[6]), [m01] "s"(m[7]));
+    }
+  } else if (F == 2) {  // real entries: each component of (a0, a1) by the real 2x2
+    if (D)
+      asm(QSV_F64_REAL("%[a0x]", "%[a1x]") QSV_F64_REAL("%[a0y]", "%[a1y]")
+          QSV_F64_REAL("%[b0x]", "%[b1x]") QSV_F64_REAL("%[b0y]", "%[b1y]")
+          : [a0x] "+v"(a0.x), [a0y] "+v"(a0.y), [a1x] "+v"(a1.x), [a1y] "+v"(a1.y), [b0x] "+v"(b0.x),
+            [b0y] "+v"(b0.y), [b1x] "+v"(b1.x), [b1y] "+v"(b1.y), [t0] "=&v"(t0)
+          : [m00] "s"(m[0]), [m01] "s"(m[2]), [m10] "s"(m[4]), [m11] "s"(m[6]));
+    else
+      asm(QSV_F32_REAL("%[a0x]", "%[a1x]") QSV_F32_REAL("%[a0y]", "%[a1y]")
+          QSV_F32_REAL("%[b0x]", "%[b1x]") QSV_F32_REAL("%[b0y]", "%[b1y]")
+          : [a0x] "+v"(a0.x), [a0y] "+v"(a0.y), [a1x] "+v"(a1.x), [a1y] "+v"(a1.y), [b0x] "+v"(b0.x),
+            [b0y] "+v"(b0.y), [b1x] "+v"(b1.x), [b1y] "+v"(b1.y), [t0] "=&v"(t0)
+          : [m00] "s"(m[0]), [m01] "s"(m[2]), [m10] "s"(m[4]), [m11] "s"(m[6]));
+  } else if (F == 3) {  // real diagonal (m00, m11), imaginary off-diagonal (m01, m10)
+    if (D)
+      asm(QSV_F64_RX("%[a0x]", "%[a0y]", "%[a1x]", "%[a1y]") QSV_F64_RX("%[b0x]", "%[b0y]", "%[b1x]", "%[b1y]")
+          : [a0x] "+v"(a0.x), [a0y] "+v"(a0.y), [a1x] "+v"(a1.x), [a1y] "+v"(a1.y), [b0x] "+v"(b0.x),
+            [b0y] "+v"(b0.y), [b1x] "+v"(b1.x), [b1y] "+v"(b1.y), [t0] "=&v"(t0), [t1] "=&v"(t1)
+          : [m00] "s"(m[0]), [m01] "s"(m[3]), [m10] "s"(m[5]), [m11] "s"(m[6]));
+    else
+      asm(QSV_F32_RX("%[a0x]", "%[a0y]", "%[a1x]", "%[a1y]") QSV_F32_RX("%[b0x]", "%[b0y]", "%[b1x]", "%[b1y]")
+          : [a0x] "+v"(a0.x), [a0y] "+v"(a0.y), [a1x] "+v"(a1.x), [a1y] "+v"(a1.y), [b0x] "+v"(b0.x),
+            [b0y] "+v"(b0.y), [b1x] "+v"(b1.x), [b1y] "+v"(b1.y), [t0] "=&v"(t0), [t1] "=&v"(t1)
+          : [m00] "s"(m[0]), [m01] "s"(m[3]), [m10] "s"(m[5]), [m11] "s"(m[6]));
+  } else {  // general: rare (explicit one-qubit matrices), plain code
+    M2<T> V;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) V.m[f] = cpx<T>{m[2 * f], m[2 * f + 1]};
+    apply2(V, a0, a1);
+    apply2(V, b0, b1);
   }
 }
+#undef QSV_F32_DIAG
+#undef QSV_F32_REAL
+#undef QSV_F32_RX
+#undef QSV_F64_DIAG
+#undef QSV_F64_REAL
+#undef QSV_F64_RX
 
 // LDS position of tile amplitude l: the bits that select a 256-byte row are
 // XORed into the position within the row, so lanes whose amplitudes differ
@@ -233,17 +338,16 @@ __device__ __forceinline__ double round_grad(const cpx<T>* x, const cpx<T>* y) {
 }
 
 template <typename T, int K, int J, int F>
-__device__ __forceinline__ void round_apply(const M2<T>& V, cpx<T>* x, cpx<T>* y) {
+__device__ __forceinline__ void round_apply(const T* m, cpx<T>* x, cpx<T>* y) {
 #pragma unroll
   for (int q = 0; q < (1 << (K - 1)); ++q) {
     const int i0 = ((q >> J) << (J + 1)) | (q & ((1 << J) - 1)), i1 = i0 | (1 << J);
-    apply_form(F, V, x[i0], x[i1]);
-    apply_form(F, V, y[i0], y[i1]);
+    form_apply2<F>(m, x[i0], x[i1], y[i0], y[i1]);
   }
 }
 
 template <typename T, int K, int J>
-__device__ __forceinline__ double round_gate(int form, int gen, bool grad, const M2<T>& V, cpx<T>* x, cpx<T>* y) {
+__device__ __forceinline__ double round_gate(int form, int gen, bool grad, const T* V, cpx<T>* x, cpx<T>* y) {
   double g = 0.0;
   if (grad) {
     if (gen == 0)
@@ -253,14 +357,16 @@ __device__ __forceinline__ double round_gate(int form, int gen, bool grad, const
     else
       g = round_grad<T, K, J, 2>(x, y);
   }
-  if (form == 1)
-    round_apply<T, K, J, 1>(V, x, y);
-  else if (form == 2)
-    round_apply<T, K, J, 2>(V, x, y);
-  else if (form == 3)
-    round_apply<T, K, J, 3>(V, x, y);
-  else
-    round_apply<T, K, J, 0>(V, x, y);
+  // one if per shape, each opaque to the others (an if-else chain over the
+  // shapes makes the compiler copy the register arrays at every merge)
+  asm volatile("" : "+s"(form));
+  if (form == 1) round_apply<T, K, J, 1>(V, x, y);
+  asm volatile("" : "+s"(form));
+  if (form == 2) round_apply<T, K, J, 2>(V, x, y);
+  asm volatile("" : "+s"(form));
+  if (form == 3) round_apply<T, K, J, 3>(V, x, y);
+  asm volatile("" : "+s"(form));
+  if (form == 0) round_apply<T, K, J, 0>(V, x, y);
   return g;
 }
 
@@ -371,18 +477,20 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
           for (int e = 0; e < ngate; ++e, gw += kAdjGate) {
             const int info = gw[0], gslot = gw[1];
             const int j = info & 15, form = (info >> 4) & 3, gn = (info >> 8) & 3;
-            M2<T> V;
+            T V[8];
+            const T* gm = reinterpret_cast<const T*>(gw + 4);
 #pragma unroll
-            for (int f = 0; f < 4; ++f) V.m[f] = cpx_at<T>(gw + 4, f);
-            double gv;
-            if (j == 0)
-              gv = round_gate<T, K, 0>(form, gn, gslot >= 0, V, x, y);
-            else if (j == 1)
-              gv = round_gate<T, K, 1>(form, gn, gslot >= 0, V, x, y);
-            else if (j == 2 || K == 3)
-              gv = round_gate<T, K, 2>(form, gn, gslot >= 0, V, x, y);
-            else
-              gv = round_gate<T, K, (K > 3 ? 3 : 2)>(form, gn, gslot >= 0, V, x, y);
+            for (int f = 0; f < 8; ++f) V[f] = gm[f];
+            double gv = 0.0;
+            int jj = j;  // one opaque if per register bit, as for the shapes
+            asm volatile("" : "+s"(jj));
+            if (jj == 0) gv = round_gate<T, K, 0>(form, gn, gslot >= 0, V, x, y);
+            asm volatile("" : "+s"(jj));
+            if (jj == 1) gv = round_gate<T, K, 1>(form, gn, gslot >= 0, V, x, y);
+            asm volatile("" : "+s"(jj));
+            if (jj == 2) gv = round_gate<T, K, 2>(form, gn, gslot >= 0, V, x, y);
+            asm volatile("" : "+s"(jj));
+            if (K > 3 && jj == 3) gv = round_gate<T, K, (K > 3 ? 3 : 2)>(form, gn, gslot >= 0, V, x, y);
             if (gslot >= 0) {
               gv = wave_sum_d(gv);
               if (lane == 0) gacc[gslot * (kAB / 64) + wave] += gv;

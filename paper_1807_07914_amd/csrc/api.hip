@@ -917,11 +917,12 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
               gen = gen_of(o.gate);
             }
             gw[0] = j | (form << 4) | (gen << 8);
+            T mt[8];  // the state's precision, read by the kernel as uniform values
             for (int f = 0; f < 4; ++f) {
-              const double re = u[f].real(), im = u[f].imag();
-              std::memcpy(gw + 4 + 4 * f, &re, 8);
-              std::memcpy(gw + 4 + 4 * f + 2, &im, 8);
+              mt[2 * f] = (T)u[f].real();
+              mt[2 * f + 1] = (T)u[f].imag();
             }
+            std::memcpy(gw + 4, mt, sizeof(mt));
           }
           prog.insert(prog.end(), rr.begin(), rr.end());
           continue;
