@@ -143,9 +143,10 @@ __global__ __launch_bounds__(kAB) void k_adj_final(const double* __restrict__ pa
 //           thread holds the 2^K amplitudes of both states that differ in
 //           those bits and applies every gate of the record to them in turn
 //           (gates on different qubits commute, gates on one qubit keep
-//           their order), taking each rotation's term first.  [2] n_gates,
+//           their order), taking each rotation's term first.  [2] the gate
+//           count of each register bit, 8 bits per bit j from bit 8 j,
 //           [3] record length in words, [4 + j] local bit j (ascending),
-//           gates from word 8, kAdjGate words each: [0] j | shape << 4 |
+//           gates from word 8 ordered by bit, kAdjGate words each: [0] j | shape << 4 |
 //           generator << 8, [1] gradient slot or -1, from word 4 the
 //           matrix (m00, m01, m10, m11 as re, im) in the state's precision
 // Records of types 1-5 are kAdjRec words long.
@@ -370,6 +371,26 @@ __device__ __forceinline__ double round_gate(int form, int gen, bool grad, const
   return g;
 }
 
+// The gates of a round on register bit J (cnt of them, at gw, which moves
+// past them), each with its rotation's wave sum added to its slot
+template <typename T, int K, int J>
+__device__ __forceinline__ void round_bit(int cnt, const int32_t*& gw, cpx<T>* x, cpx<T>* y, double* gacc,
+                                          int wave, int lane) {
+  for (int e = 0; e < cnt; ++e, gw += kAdjGate) {
+    const int info = gw[0], gslot = gw[1];
+    const int form = (info >> 4) & 3, gn = (info >> 8) & 3;
+    T V[8];
+    const T* gm = reinterpret_cast<const T*>(gw + 4);
+#pragma unroll
+    for (int f = 0; f < 8; ++f) V[f] = gm[f];
+    double gv = round_gate<T, K, J>(form, gn, gslot >= 0, V, x, y);
+    if (gslot >= 0) {
+      gv = wave_sum_d(gv);
+      if (lane == 0) gacc[gslot * (kAB / 64) + wave] += gv;
+    }
+  }
+}
+
 template <typename T, int TB>
 __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<T>* __restrict__ lam,
                                                   const int32_t* __restrict__ prog, uint64_t ntiles,
@@ -474,28 +495,10 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
             y[m] = valid ? tl[swz<T>(b | off[m])] : cpx<T>{0, 0};
           }
           const int32_t* gw = r + 8;
-          for (int e = 0; e < ngate; ++e, gw += kAdjGate) {
-            const int info = gw[0], gslot = gw[1];
-            const int j = info & 15, form = (info >> 4) & 3, gn = (info >> 8) & 3;
-            T V[8];
-            const T* gm = reinterpret_cast<const T*>(gw + 4);
-#pragma unroll
-            for (int f = 0; f < 8; ++f) V[f] = gm[f];
-            double gv = 0.0;
-            int jj = j;  // one opaque if per register bit, as for the shapes
-            asm volatile("" : "+s"(jj));
-            if (jj == 0) gv = round_gate<T, K, 0>(form, gn, gslot >= 0, V, x, y);
-            asm volatile("" : "+s"(jj));
-            if (jj == 1) gv = round_gate<T, K, 1>(form, gn, gslot >= 0, V, x, y);
-            asm volatile("" : "+s"(jj));
-            if (jj == 2) gv = round_gate<T, K, 2>(form, gn, gslot >= 0, V, x, y);
-            asm volatile("" : "+s"(jj));
-            if (K > 3 && jj == 3) gv = round_gate<T, K, (K > 3 ? 3 : 2)>(form, gn, gslot >= 0, V, x, y);
-            if (gslot >= 0) {
-              gv = wave_sum_d(gv);
-              if (lane == 0) gacc[gslot * (kAB / 64) + wave] += gv;
-            }
-          }
+          round_bit<T, K, 0>((ngate >> 0) & 255, gw, x, y, gacc, wave, lane);
+          round_bit<T, K, 1>((ngate >> 8) & 255, gw, x, y, gacc, wave, lane);
+          round_bit<T, K, 2>((ngate >> 16) & 255, gw, x, y, gacc, wave, lane);
+          if (K > 3) round_bit<T, K, (K > 3 ? 3 : 2)>((ngate >> 24) & 255, gw, x, y, gacc, wave, lane);
           if (valid) {
 #pragma unroll
             for (int m = 0; m < NR; ++m) {

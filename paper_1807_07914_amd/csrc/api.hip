@@ -893,14 +893,22 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
         if (item.type == 6) {
           std::vector<int32_t> rr(8 + kGateWords * item.ks.size(), 0);
           rr[0] = 6;
-          rr[2] = (int32_t)item.ks.size();
           rr[3] = (int32_t)rr.size();
           for (int j = 0; j < RK; ++j) rr[4 + j] = item.bits[j];
-          for (size_t e = 0; e < item.ks.size(); ++e) {
-            const size_t kk = item.ks[e];
+          // gates grouped by register bit (stable: one qubit's gates keep
+          // their order; different qubits commute)
+          auto bit_of = [&](size_t kk) {
+            return (int)(std::find(item.bits.begin(), item.bits.end(), lpos[ops[as.ops[kk]].q[0]]) -
+                         item.bits.begin());
+          };
+          std::vector<size_t> order(item.ks.begin(), item.ks.end());
+          std::stable_sort(order.begin(), order.end(), [&](size_t a2, size_t b2) { return bit_of(a2) < bit_of(b2); });
+          for (size_t kk : order) rr[2] += 1 << (8 * bit_of(kk));
+          for (size_t e = 0; e < order.size(); ++e) {
+            const size_t kk = order[e];
             const qsv_op& o = ops[as.ops[kk]];
             int32_t* gw = rr.data() + 8 + kGateWords * e;
-            const int j = (int)(std::find(item.bits.begin(), item.bits.end(), lpos[o.q[0]]) - item.bits.begin());
+            const int j = bit_of(kk);
             const cd* u = inv[kk].data();
             int form = 0;  // shape of the 2x2, so the kernel skips its zero parts
             if (u[1] == cd(0.0) && u[2] == cd(0.0))
