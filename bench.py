@@ -146,6 +146,42 @@ def bench_batched(np, torch, qc, qsv, count=4096, reps=5, sample=128):
             "speedup_vs_pergate": count / t_run / forms["pergate"]}
 
 
+def bench_rounds(np, torch, qc, qsv, circuits=10):
+    """The paper's random-round family on its grid: n = 5..30 step 5, rounds
+    2..10 step 2, ten seeded circuits each (complex64, fused passes, plan
+    built per circuit and included in the time).  For n <= 20 the first
+    circuit's state is checked for Schmidt rank <= 2^rounds across the middle
+    cut (host SVD of the GPU state)."""
+    out = {}
+    for n in range(5, 31, 5):
+        s = qsv.State(n, "c64")
+        row = {}
+        for rounds in range(2, 11, 2):
+            gates, t_tot, chi = 0, 0.0, None
+            for c in range(circuits):
+                lst = qc.paper_rounds(n, rounds, 2000 + 100 * n + 10 * rounds + c)
+                ops = qsv.OpList(lst)
+                s.set_basis(0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.apply_circuit(ops, mode="fused")
+                torch.cuda.synchronize()
+                t_tot += time.perf_counter() - t0
+                gates += len(lst)
+                if c == 0 and n <= 20:
+                    psi = s.to_numpy().reshape(1 << (n - n // 2), 1 << (n // 2))
+                    sv = np.linalg.svd(psi, compute_uv=False)
+                    chi = int(np.sum(sv > 1e-4 * sv[0]))
+            row[rounds] = {"gates_per_s": gates / t_tot, "ms_per_circuit": t_tot / circuits * 1e3}
+            if chi is not None:
+                row[rounds]["schmidt_rank"] = chi
+                row[rounds]["schmidt_bound_ok"] = chi <= min(2 ** rounds, 1 << (n // 2))
+        out[n] = row
+        s.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_adjoint(np, torch, qc, qsv, reps=3):
     """24 qubits, 6 layers of RX, RY, RZ + CZ ring (432 parameters, seed
     1005), H = sum Z_i Z_{i+1} + 0.7 sum X_i, complex64 with FP64 reductions:
@@ -343,6 +379,7 @@ def main():
         torch.cuda.empty_cache()
         ex["c4_batched"] = bench_batched(np, torch, qc, qsv)
         ex["c5_adjoint"] = bench_adjoint(np, torch, qc, qsv)
+        ex["f1_paper_rounds"] = bench_rounds(np, torch, qc, qsv)
         result["extras"] = ex
 
     if not args.no_cpu_baseline:
