@@ -182,6 +182,28 @@ def bench_rounds(np, torch, qc, qsv, circuits=10):
     return out
 
 
+def bench_h2_sweep(np, torch, qc, qsv, reps=20):
+    """The paper's VQE sweep: 100 values of t0 times five terms = 500
+    two-qubit circuits (basis changes for X0X1 and Y0Y1) in one batched
+    launch, complex64; deviation from the closed forms."""
+    circs, widths, hams, keys = qc.h2_term_batch(qc.h2_sweep())
+    t0 = time.perf_counter()
+    bt = qsv.Batch(circs, widths, hams, dtype="c64")
+    t_create = time.perf_counter() - t0
+    e = bt.run()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        e = bt.run()
+    t_run = (time.perf_counter() - t0) / reps
+    info = bt.info()
+    bt.close()
+    cf = np.array([qc.h2_closed_forms(t)[k] for t, k in keys])
+    return {"circuits": len(circs), "points": 100, "ms_per_sweep": t_run * 1e3,
+            "points_per_s": 100 / t_run, "circuits_per_s": len(circs) / t_run,
+            "create_and_autotune_s": t_create, "tile_qubits": info["tile_qubits"],
+            "max_abs_dev_closed_form": float(np.abs(e - cf).max())}
+
+
 def bench_adjoint(np, torch, qc, qsv, reps=3):
     """24 qubits, 6 layers of RX, RY, RZ + CZ ring (432 parameters, seed
     1005), H = sum Z_i Z_{i+1} + 0.7 sum X_i, complex64 with FP64 reductions:
@@ -380,6 +402,7 @@ def main():
         ex["c4_batched"] = bench_batched(np, torch, qc, qsv)
         ex["c5_adjoint"] = bench_adjoint(np, torch, qc, qsv)
         ex["f1_paper_rounds"] = bench_rounds(np, torch, qc, qsv)
+        ex["f2_h2_sweep"] = bench_h2_sweep(np, torch, qc, qsv)
         result["extras"] = ex
 
     if not args.no_cpu_baseline:

@@ -283,6 +283,36 @@ def h2_sweep(points: int = 100) -> np.ndarray:
     return np.linspace(-np.pi, np.pi, points)
 
 
+def h2_term_batch(t0s):
+    """One circuit per (t0, term) of the H2 sweep, for a batch that measures
+    Z-strings only: the ansatz, then the basis change that turns the term
+    into a Z-string (H for X; S^dag then H for Y), and that Z-string as the
+    circuit's one-term Hamiltonian.  Returns (circuits, widths, hamiltonians,
+    keys) with keys[i] = (t0, term name)."""
+    circuits, widths, hams, keys = [], [], [], []
+    for t0 in t0s:
+        for key, term in H2_TERMS.items():
+            ops = h2_ansatz(float(t0))
+            zterm = []
+            for p, q in term:
+                if p == "X":
+                    ops.append(op("H", q))
+                elif p == "Y":
+                    ops += [op("SDG", q), op("H", q)]
+                zterm.append(("Z", q))
+            circuits.append(ops)
+            widths.append(2)
+            hams.append([(1.0, tuple(zterm))])
+            keys.append((float(t0), key))
+    return circuits, widths, hams, keys
+
+
+def h2_closed_forms(t0: float) -> dict:
+    """Per-term values of the listing's ansatz with exact pi constants."""
+    return {"Z0": np.cos(t0), "Z1": -np.cos(t0), "Z0Z1": -1.0,
+            "X0X1": -np.sin(t0), "Y0Y1": -np.sin(t0)}
+
+
 # --------------------------------------------------------------------------
 # fuzz circuits for parity tests
 # --------------------------------------------------------------------------

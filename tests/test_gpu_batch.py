@@ -112,3 +112,19 @@ def test_batch_rejects_unsupported():
     U = qc.haar_unitary(3, np.random.default_rng(0))
     with pytest.raises(QsvError):
         Batch([[qc.op("U", 0, 1, 2, mat=U)]], [6], [[(1.0, (("Z", 0),))]])
+
+
+@pytest.mark.parametrize("dtype,tol", [("c64", 1e-5), ("c128", 1e-9)])
+def test_h2_vqe_sweep_batched(dtype, tol):
+    # the paper's VQE sweep (section V.B): 100 values of t0, five terms each,
+    # one batched launch; X and Y terms through basis changes
+    circs, widths, hams, keys = qc.h2_term_batch(qc.h2_sweep())
+    bt = Batch(circs, widths, hams, dtype=dtype)
+    e = bt.run()
+    bt.close()
+    assert len(e) == 500
+    for v, (t0, key) in zip(e, keys):
+        assert abs(v - qc.h2_closed_forms(t0)[key]) <= tol, (t0, key, v)
+    # and against the oracle run of each measured circuit
+    ref = np.array([O.expval(O.run(c, w), h) for c, w, h in zip(circs, widths, hams)])
+    assert np.abs(e - ref).max() <= (1e-5 if dtype == "c64" else 1e-12)

@@ -151,6 +151,17 @@ def test_h2_listing_closed_forms():
             assert abs(v[key].imag) < 1e-15
 
 
+def test_h2_term_batch_basis_changes():
+    # the batched sweep measures X0X1 and Y0Y1 as Z0Z1 after H (X) or S^dag
+    # then H (Y) on both qubits: on the oracle every measured circuit gives
+    # the closed form of its term
+    circs, widths, hams, keys = qc.h2_term_batch(qc.h2_sweep())
+    assert len(circs) == 500
+    for c, w, h, (t0, key) in zip(circs, widths, hams, keys):
+        v = O.expval(O.run(c, w), h)
+        assert abs(v - qc.h2_closed_forms(t0)[key]) < 1e-9, (t0, key)
+
+
 # ------------------------------------------------------ paper's chi claim
 def schmidt_ranks(psi, n, tol=1e-10):
     out = []
