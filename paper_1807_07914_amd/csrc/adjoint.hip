@@ -669,6 +669,161 @@ hipError_t launch_hpsi(const cpx<T>* psi, cpx<T>* lam, int n, const uint64_t* x,
   return hipSuccess;
 }
 
+// ------------------------------------------- lambda = H psi by tile passes
+// Terms whose X mask lies in a tile's qubit set S are applied by one pass
+// over the tiles of S: the psi tile is staged in LDS (swizzled), and each
+// thread forms lambda_j = sum_t w_t (-1)^{|(j ^ x_t) & z_t|} psi_{j ^ x_t}
+// for its amplitudes in FP64 registers, term by term, adding to the lambda
+// already stored when the pass is not the first.  With j = base | loc(l)
+// the sign's parity splits into parity(l & zl_t) over the tile's local bits
+// and parity(base & z_t) ^ parity(x_t & z_t), uniform per tile.  The last
+// pass also sums Re(conj(psi_j) lambda_j) = <psi|H|psi> from the FP64 values.
+//
+// Program (int32 words): [0] t, [1] c, [2] n_nonS, [3] n_terms, [4] add to
+// lambda, [5] sum the energy, [6] offset of the terms, S[t] from word 8,
+// nonS after.  Term (kHTermWords words): [0] local X mask, [1] local Z mask,
+// [2..3] Z mask, [4] parity(x & z), [6..7] weight re, [8..9] weight im
+// (w = c i^{n_y}).
+constexpr int kHTermWords = 10;
+
+// One term on a thread's amplitudes l = threadIdx.x + i * kAB: partner from
+// registers (X-free) or LDS, the sign (-1)^{|l & zl|} flipped into the
+// weight's sign bit, two FMAs for a real weight and four otherwise
+template <typename T, int PER, bool LDSX, bool REAL>
+__device__ __forceinline__ void hpsi_term(const cpx<T>* tp, const cpx<T>* own, uint32_t xl, uint32_t zl, double wr,
+                                          double wi, int full, double* ar, double* ai) {
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const uint32_t l = threadIdx.x + (uint32_t)i * kAB;
+    if (LDSX && (int)l >= full) continue;
+    const cpx<T> p = LDSX ? tp[swz<T>(l ^ xl)] : own[i];
+    const double pr = (double)p.x, pi = (double)p.y;
+    const int sb = (__popc(l & zl) & 1) << 31;
+    const double sr = __hiloint2double(__double2hiint(wr) ^ sb, __double2loint(wr));
+    if (REAL) {
+      ar[i] = fma(sr, pr, ar[i]);
+      ai[i] = fma(sr, pi, ai[i]);
+    } else {
+      const double si = __hiloint2double(__double2hiint(wi) ^ sb, __double2loint(wi));
+      ar[i] = fma(sr, pr, fma(-si, pi, ar[i]));
+      ai[i] = fma(sr, pi, fma(si, pr, ai[i]));
+    }
+  }
+}
+
+template <typename T, int TB>
+__global__ __launch_bounds__(kAB) void k_hpsi_tile(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ lam,
+                                                   const int32_t* __restrict__ prog, uint64_t ntiles,
+                                                   double* __restrict__ part) {
+  constexpr int A = VecInfo<T>::A;
+  constexpr int PER = (1 << TB) / kAB;  // amplitudes per thread in a full tile
+  __shared__ cpx<T> tp[1 << TB];
+  __shared__ uint64_t segoff[256];
+  __shared__ double sh[kAB];
+  const int t = prog[0], c = prog[1], nns = prog[2], nterms = prog[3], add = prog[4], energy = prog[5];
+  const int32_t* S = prog + 8;
+  const int32_t* nonS = S + t;
+  const int32_t* terms = prog + prog[6];
+  const int nseg = 1 << (t - c);
+  for (int h = threadIdx.x; h < nseg; h += kAB) {
+    uint64_t o = 0;
+    for (int j = 0; j < t - c; ++j)
+      if ((h >> j) & 1) o |= 1ull << S[c + j];
+    segoff[h] = o;
+  }
+  __syncthreads();
+  const vec16<T>* gp = reinterpret_cast<const vec16<T>*>(psi);
+  const int nvec = (1 << t) / A, full = 1 << t;
+  const uint32_t cmask = (1u << c) - 1u;
+  double eacc = 0.0;
+  for (uint64_t tid = blockIdx.x; tid < ntiles; tid += gridDim.x) {
+    uint64_t base = 0;
+    for (int i = 0; i < nns; ++i) base |= ((tid >> i) & 1ull) << nonS[i];
+    for (int i = threadIdx.x; i < nvec; i += kAB) {
+      const uint32_t l = (uint32_t)i * A;
+      const vec16<T> x = gp[(base | segoff[l >> c] | (l & cmask)) / A];
+#pragma unroll
+      for (int e = 0; e < A; ++e) tp[swz<T>(l + e)] = x.a[e];
+    }
+    __syncthreads();
+    double ar[PER], ai[PER];
+    cpx<T> own[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const uint32_t l = threadIdx.x + (uint32_t)i * kAB;
+      ar[i] = 0.0;
+      ai[i] = 0.0;
+      own[i] = cpx<T>{0, 0};
+      if ((int)l < full) {
+        own[i] = tp[swz<T>(l)];
+        if (add) {
+          const cpx<T> v = lam[base | segoff[l >> c] | (l & cmask)];
+          ar[i] = (double)v.x;
+          ai[i] = (double)v.y;
+        }
+      }
+    }
+    for (int k = 0; k < nterms; ++k) {
+      const int32_t* w = terms + k * kHTermWords;
+      const uint32_t xl = (uint32_t)w[0], zl = (uint32_t)w[1];
+      const uint64_t zg = ((uint64_t)(uint32_t)w[3] << 32) | (uint32_t)w[2];
+      const int ts = (__popcll(base & zg) + w[4]) & 1;
+      const double wr0 = __hiloint2double(w[7], w[6]), wi0 = __hiloint2double(w[9], w[8]);
+      const double wr = ts ? -wr0 : wr0, wi = ts ? -wi0 : wi0;
+      // X-free terms use the amplitudes held in registers, the others read
+      // their partners from LDS; real weights take two FMAs.  One opaque if
+      // per case (an if-else would have the compiler copy the accumulators
+      // at the merge)
+      uint32_t xo = xl;
+      const int real = (w[8] | (w[9] & 0x7fffffff)) == 0;  // wi == +-0 from its bits (scalar)
+      int kind = __builtin_amdgcn_readfirstlane((xo != 0) * 2 + real);  // uniform
+      asm volatile("" : "+s"(kind));
+      if (kind == 1) hpsi_term<T, PER, false, true>(tp, own, xo, zl, wr, wi, full, ar, ai);
+      asm volatile("" : "+s"(kind));
+      if (kind == 0) hpsi_term<T, PER, false, false>(tp, own, xo, zl, wr, wi, full, ar, ai);
+      asm volatile("" : "+s"(kind));
+      if (kind == 3) hpsi_term<T, PER, true, true>(tp, own, xo, zl, wr, wi, full, ar, ai);
+      asm volatile("" : "+s"(kind));
+      if (kind == 2) hpsi_term<T, PER, true, false>(tp, own, xo, zl, wr, wi, full, ar, ai);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const uint32_t l = threadIdx.x + (uint32_t)i * kAB;
+      if ((int)l < full) {
+        if (energy) eacc = fma((double)own[i].x, ar[i], fma((double)own[i].y, ai[i], eacc));
+        lam[base | segoff[l >> c] | (l & cmask)] = cpx<T>{(T)ar[i], (T)ai[i]};
+      }
+    }
+    __syncthreads();
+  }
+  if (energy) {
+    const double v = block_sum_d(eacc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+  }
+}
+
+template <typename T>
+int hpsi_tile_bits() {
+  return sizeof(T) == 4 ? 12 : 11;
+}
+int hpsi_term_words() { return kHTermWords; }
+
+// One pass of lambda = H psi (program at prog_dev, header in prog_host); with
+// the energy flag set, *energy_dev receives <psi|H|psi> (part holds one
+// double per workgroup, adjoint_partials() of them)
+template <typename T>
+hipError_t launch_hpsi_tile(const cpx<T>* psi, cpx<T>* lam, int n, const int32_t* prog_dev,
+                            const int32_t* prog_host, double* part, double* energy_dev, hipStream_t st) {
+  constexpr int TB = sizeof(T) == 4 ? 12 : 11;
+  const int t = prog_host[0];
+  if (t > TB || t - prog_host[1] > 8 || t > n) return hipErrorInvalidValue;
+  const uint64_t ntiles = 1ull << (n - t);
+  const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, (uint64_t)kMaxAdjPartials);
+  hipLaunchKernelGGL((k_hpsi_tile<T, TB>), dim3(grid), dim3(kAB), 0, st, psi, lam, prog_dev, ntiles, part);
+  if (prog_host[5]) hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(kAB), 0, st, part, (int)grid, energy_dev);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_adj_rot(cpx<T>* psi, cpx<T>* lam, int n, int q, const M2<T>& V, const M2<double>& G,
                           double* part, double* out_dev, hipStream_t st) {
@@ -685,6 +840,9 @@ hipError_t launch_adj_rot(cpx<T>* psi, cpx<T>* lam, int n, int q, const M2<T>& V
 
 #define QSV_AINST(T)                                                                              \
   template int adj_tile_bits<T>();                                                                \
+  template int hpsi_tile_bits<T>();                                                               \
+  template hipError_t launch_hpsi_tile<T>(const cpx<T>*, cpx<T>*, int, const int32_t*,             \
+                                          const int32_t*, double*, double*, hipStream_t);          \
   template hipError_t launch_adj_tile<T>(cpx<T>*, cpx<T>*, int, const int32_t*, const int32_t*,    \
                                          double*, double*, hipStream_t);                          \
   template hipError_t launch_hpsi<T>(const cpx<T>*, cpx<T>*, int, const uint64_t*, const uint64_t*, \

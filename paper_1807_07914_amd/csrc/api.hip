@@ -377,6 +377,7 @@ qsv_status qsv_free_state(qsv_state* s) {
   if (s->pbuf) (void)hipFree(s->pbuf);
   if (s->aux) (void)hipFree(s->aux);
   if (s->apbuf) (void)hipFree(s->apbuf);
+  if (s->hpbuf) (void)hipFree(s->hpbuf);
   if (s->owns && s->psi) (void)hipFree(s->psi);
   s->magic = kDeadMagic;
   delete s;
@@ -1075,14 +1076,131 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
   return QSV_OK;
 }
 
+// lambda = H psi by tile passes when every term's X mask fits a tile (the
+// low c qubits plus at most t - c others): terms are dealt greedily to
+// passes by the qubits above c of their X masks, the X-free terms go to the
+// first pass, and the last pass also writes <psi|H|psi> to energy_dev.
+// Returns false (nothing launched) when some term does not fit.
+template <typename T>
+static qsv_status hpsi_tiled(qsv_state* s, const cpx<T>* psi, cpx<T>* lam, const std::vector<uint64_t>& xs,
+                             const std::vector<uint64_t>& zs, const std::vector<double>& wr,
+                             const std::vector<double>& wi, double* part, double* energy_dev, bool* used) {
+  *used = false;
+  const int n = s->n, nt = (int)xs.size();
+  const int t = std::min(n, hpsi_tile_bits<T>());
+  const int c = std::min(t, sizeof(T) == 4 ? 5 : 4);
+  const uint64_t low = (1ull << c) - 1ull;
+  if (nt == 0) return QSV_OK;
+  std::vector<uint64_t> passes;  // qubits above c of each pass
+  std::vector<int> pass_of(nt, -1);
+  for (int k = 0; k < nt; ++k) {
+    const uint64_t hi = xs[k] & ~low;
+    if (__builtin_popcountll(hi) > t - c) return QSV_OK;
+    for (size_t p = 0; p < passes.size() && pass_of[k] < 0; ++p)
+      if (__builtin_popcountll(passes[p] | hi) <= t - c) {
+        passes[p] |= hi;
+        pass_of[k] = (int)p;
+      }
+    if (pass_of[k] < 0) {
+      passes.push_back(hi);
+      pass_of[k] = (int)passes.size() - 1;
+    }
+  }
+  const int TW = hpsi_term_words();
+  std::vector<int32_t>& prog = s->hhprog;
+  prog.clear();
+  std::vector<size_t> offs;
+  for (size_t p = 0; p < passes.size(); ++p) {
+    std::vector<int> S;
+    for (int q = 0; q < c; ++q) S.push_back(q);
+    for (int q = c; q < n; ++q)
+      if ((passes[p] >> q) & 1ull) S.push_back(q);
+    for (int q = c; q < n && (int)S.size() < t; ++q)
+      if (!((passes[p] >> q) & 1ull)) S.push_back(q);
+    std::vector<int> lpos(n, -1), nonS;
+    for (int j = 0; j < t; ++j) lpos[S[j]] = j;
+    for (int q = 0; q < n; ++q)
+      if (lpos[q] < 0) nonS.push_back(q);
+    std::vector<int> mine;
+    for (int k = 0; k < nt; ++k)
+      if (pass_of[k] == (int)p) mine.push_back(k);
+    std::vector<uint32_t> xl(nt, 0), zl(nt, 0);
+    std::vector<uint64_t> zout(nt, 0);  // Z bits outside the tile
+    for (int k : mine)
+      for (int q = 0; q < n; ++q) {
+        if ((xs[k] >> q) & 1ull) xl[k] |= 1u << lpos[q];
+        if ((zs[k] >> q) & 1ull) {
+          if (lpos[q] >= 0)
+            zl[k] |= 1u << lpos[q];
+          else
+            zout[k] |= 1ull << q;
+        }
+      }
+    const size_t off = prog.size();
+    const int hdr = (8 + t + (int)nonS.size() + 7) & ~7;
+    prog.resize(off + hdr, 0);
+    prog[off] = t;
+    prog[off + 1] = c;
+    prog[off + 2] = (int)nonS.size();
+    prog[off + 3] = (int)mine.size();
+    prog[off + 4] = p > 0;
+    prog[off + 5] = p + 1 == passes.size();
+    prog[off + 6] = hdr;
+    for (int j = 0; j < t; ++j) prog[off + 8 + j] = S[j];
+    for (size_t j = 0; j < nonS.size(); ++j) prog[off + 8 + t + j] = nonS[j];
+    for (int k : mine) {
+      int32_t w[16] = {0};
+      w[0] = (int32_t)xl[k];
+      w[1] = (int32_t)zl[k];
+      std::memcpy(w + 2, &zout[k], 8);
+      w[4] = __builtin_popcountll(xs[k] & zs[k]) & 1;
+      std::memcpy(w + 6, &wr[k], 8);
+      std::memcpy(w + 8, &wi[k], 8);
+      prog.insert(prog.end(), w, w + TW);
+    }
+    while (prog.size() % 8) prog.push_back(0);
+    offs.push_back(off);
+  }
+  const size_t need = prog.size() * sizeof(int32_t);
+  if (s->hpbuf_bytes < need) {
+    if (s->hpbuf) {
+      QSV_HIP(hipStreamSynchronize(s->stream));
+      QSV_HIP(hipFree(s->hpbuf));
+      s->hpbuf = nullptr;
+      s->hpbuf_bytes = 0;
+    }
+    QSV_HIP(hipMalloc(&s->hpbuf, need * 2));
+    s->hpbuf_bytes = need * 2;
+  }
+  int32_t* dprog = static_cast<int32_t*>(s->hpbuf);
+  QSV_HIP(hipMemcpyAsync(dprog, prog.data(), need, hipMemcpyHostToDevice, s->stream));
+  for (size_t off : offs)
+    QSV_HIP(launch_hpsi_tile<T>(psi, lam, n, dprog + off, prog.data() + off, part, energy_dev, s->stream));
+  *used = true;
+  return QSV_OK;
+}
+
 template <typename T>
 static qsv_status adjoint_sweep(qsv_state* s, const qsv_op* ops, int n_ops, const uint64_t* xmask,
                                 const uint64_t* zmask, const double* coeff, int n_terms,
-                                double* grad) {
+                                double* energy, double* grad) {
+  // the energy comes from lambda = H psi when that runs as tile passes (every
+  // X mask fits a tile), else from the expectation kernels, before the sweep
+  bool tiled_h = n_terms > 0;
+  {
+    const int t = std::min(s->n, hpsi_tile_bits<T>());
+    const int c = std::min(t, sizeof(T) == 4 ? 5 : 4);
+    for (int k = 0; k < n_terms; ++k)
+      if (__builtin_popcountll(xmask[k] & ~((1ull << c) - 1ull)) > t - c) tiled_h = false;
+  }
+  if (!tiled_h) {
+    qsv_status se = expval_impl(s, s->psi, xmask, zmask, coeff, n_terms, energy, nullptr);
+    if (se) return se;
+  }
   const size_t stage = dense_ws_bytes();
   const size_t npart = adjoint_partials();
   const size_t tparts = (size_t)adj_max_grad() * 1024;  // per-workgroup sums of the tiled sweep
-  qsv_status st = ensure_workspace(s, stage + (npart + (size_t)n_ops + 1 + tparts) * sizeof(double));
+  qsv_status st = ensure_workspace(s, stage + (npart + (size_t)n_ops + 2 + tparts) * sizeof(double));
   if (st) return st;
   if (s->aux_bytes < s->bytes) {
     if (s->aux) {
@@ -1117,8 +1235,19 @@ static qsv_status adjoint_sweep(qsv_state* s, const qsv_op* ops, int n_ops, cons
     wr[k] = coeff[t] * re[ny];
     wi[k] = coeff[t] * im[ny];
   }
-  QSV_HIP(launch_hpsi<T>(psi, lam, s->n, xs.data(), zs.data(), wr.data(), wi.data(), n_terms,
-                         s->stream));
+  double* edev = gdev + n_ops + 1 + tparts;
+  if (tiled_h) {
+    bool used = false;
+    st = hpsi_tiled<T>(s, psi, lam, xs, zs, wr, wi, part, edev, &used);
+    if (st) return st;
+    if (!used) return fail(QSV_ERR_STATE, "tiled H psi plan rejected a fitting term");
+  } else {
+    QSV_HIP(launch_hpsi<T>(psi, lam, s->n, xs.data(), zs.data(), wr.data(), wi.data(), n_terms, s->stream));
+  }
+  auto fetch_energy = [&]() -> qsv_status {
+    if (tiled_h) QSV_HIP(hipMemcpyAsync(energy, edev, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    return QSV_OK;
+  };
   std::vector<double> gh(n_ops + 1, 0.0);
   QSV_HIP(hipMemcpyAsync(gdev, gh.data(), (n_ops + 1) * sizeof(double), hipMemcpyHostToDevice,
                          s->stream));
@@ -1126,6 +1255,8 @@ static qsv_status adjoint_sweep(qsv_state* s, const qsv_op* ops, int n_ops, cons
   const int RB = s->dt == QSV_C64 ? 5 : 4;
   if (s->n >= RB) {
     st = adjoint_sweep_tiled<T>(s, ops, n_ops, psi, lam, gdev, gdev + n_ops + 1);
+    if (st) return st;
+    st = fetch_energy();
     if (st) return st;
     QSV_HIP(hipMemcpyAsync(grad, gdev, n_ops * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     QSV_HIP(hipStreamSynchronize(s->stream));
@@ -1160,6 +1291,8 @@ static qsv_status adjoint_sweep(qsv_state* s, const qsv_op* ops, int n_ops, cons
     st = apply_op_inverse(s, s->aux, o, 0);
     if (st) return st;
   }
+  st = fetch_energy();
+  if (st) return st;
   QSV_HIP(hipMemcpyAsync(grad, gdev, n_ops * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   QSV_HIP(hipStreamSynchronize(s->stream));
   (void)I;
@@ -1191,12 +1324,17 @@ qsv_status qsv_adjoint(qsv_state* s, const qsv_op* ops, int n_ops, const uint64_
     if (st) return st;
   }
   double e = 0.0;
-  st = expval_impl(s, s->psi, xmask, zmask, coeff, n_terms, &e, nullptr);
+  if (n_ops == 0) {
+    st = expval_impl(s, s->psi, xmask, zmask, coeff, n_terms, &e, nullptr);
+    if (st) return st;
+    if (energy) *energy = e;
+    return QSV_OK;
+  }
+  st = s->dt == QSV_C64 ? adjoint_sweep<float>(s, ops, n_ops, xmask, zmask, coeff, n_terms, &e, grad)
+                        : adjoint_sweep<double>(s, ops, n_ops, xmask, zmask, coeff, n_terms, &e, grad);
   if (st) return st;
   if (energy) *energy = e;
-  if (n_ops == 0) return QSV_OK;
-  return s->dt == QSV_C64 ? adjoint_sweep<float>(s, ops, n_ops, xmask, zmask, coeff, n_terms, grad)
-                          : adjoint_sweep<double>(s, ops, n_ops, xmask, zmask, coeff, n_terms, grad);
+  return QSV_OK;
 }
 
 qsv_status qsv_norm(qsv_state* s, double* out) {

@@ -57,6 +57,9 @@ struct qsv_state {
   void* apbuf = nullptr;
   size_t apbuf_bytes = 0;
   std::vector<int32_t> ahprog;
+  void* hpbuf = nullptr;  // programs of lambda = H psi by tile passes
+  size_t hpbuf_bytes = 0;
+  std::vector<int32_t> hhprog;
   std::atomic<int> busy{0};
 };
 
@@ -101,6 +104,15 @@ template <typename T>
 hipError_t launch_adj_rot(cpx<T>* psi, cpx<T>* lam, int n, int q, const M2<T>& V, const M2<double>& G,
                           double* part, double* out_dev, hipStream_t st);
 size_t adjoint_partials();
+// lambda = H psi by tile passes (adjoint.hip): one pass of the program at
+// prog_dev (host copy prog_host); the pass with the energy flag writes
+// <psi|H|psi> to *energy_dev (part: adjoint_partials() doubles)
+template <typename T>
+hipError_t launch_hpsi_tile(const cpx<T>* psi, cpx<T>* lam, int n, const int32_t* prog_dev,
+                            const int32_t* prog_host, double* part, double* energy_dev, hipStream_t st);
+template <typename T>
+int hpsi_tile_bits();
+int hpsi_term_words();
 // fused reverse sweep (adjoint.hip): one tile pass of the program at
 // prog_dev (host copy prog_host); part holds n_grad * 1024 doubles
 template <typename T>

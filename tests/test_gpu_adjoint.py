@@ -117,6 +117,28 @@ def test_adjoint_chains_and_sign_runs(dtype):
     assert abs(back[0] - 1) < (1e-10 if dtype == "c128" else 1e-4)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_adjoint_energy_paths(dtype):
+    # lambda = H psi by tile passes (every X mask fits a tile) or by the
+    # gather kernel (an X string over 9 qubits above the tile's low ones):
+    # both give the parameter-shift gradient and the oracle energy
+    n, layers = 14, 1
+    params = np.random.default_rng(51).uniform(0, 2 * np.pi, 3 * n * layers)
+    build = lambda p: qc.rot_ring_ansatz(n, p, layers)
+    idx = qc.rot_ring_param_index(n, layers)
+    fits = qc.zz_chain(n) + [(0.3, (("X", 2), ("Y", 9))), (0.5, (("Y", 0), ("X", 4)))]
+    wide = fits + [(0.2, tuple(("X", q) for q in range(4, 13)))]
+    for ham in (fits, wide):
+        s = State(n, dtype)
+        e, g_ops = s.adjoint(build(params), ham)
+        s.close()
+        g = np.zeros(params.size)
+        np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
+        ref = O.param_shift_grad(build, params, ham, n)
+        assert abs(e - O.energy(build, params, ham, n)) <= GTOL[dtype] * len(ham)
+        assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham)
+
+
 def test_autograd_function():
     import torch
     from paper_1807_07914_amd.autograd import expectation
