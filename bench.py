@@ -260,6 +260,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-ref", action="store_true",
                     help="run one plain 2 GiB device copy first (reference for HBM counters)")
+    ap.add_argument("--only", choices=["c4_batched", "c5_adjoint", "f1_paper_rounds", "f2_h2_sweep"],
+                    help="run one of the extra workloads alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -272,6 +274,12 @@ def main():
     import qcircuits as qc
     from paper_1807_07914_amd import OpList, State
     from paper_1807_07914_amd import qsv
+
+    if args.only:
+        fn = {"c4_batched": bench_batched, "c5_adjoint": bench_adjoint,
+              "f1_paper_rounds": bench_rounds, "f2_h2_sweep": bench_h2_sweep}[args.only]
+        print(json.dumps({args.only: fn(np, torch, qc, qsv)}))
+        return
 
     n = args.n
     ops = qc.random_brickwork(n, 40, qc.SEEDS["c2"])
