@@ -696,25 +696,26 @@ static qsv_status check_terms(const qsv_state* s, const uint64_t* xmask, const u
 // with more rotations than slots is split into consecutive programs over the
 // same tile qubits.  Ops that no tile takes run as inverse per-gate kernels
 // on both states (they are never rotations: those act on one qubit).
+struct AdjLaunch {
+  int step;    // index into the sweep's steps
+  size_t off;  // program offset in words
+};
+
+// The sweep's steps and programs (host only): prog receives every program,
+// launches the program offsets of each tile step in order.
 template <typename T>
-static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops, cpx<T>* psi, cpx<T>* lam,
-                                      double* gdev, double* tpart) {
-  const int n = s->n;
+static qsv_status build_adjoint_programs(int n, const qsv_op* ops, int n_ops, std::vector<AdjStep>& steps,
+                                         std::vector<int32_t>& prog, std::vector<AdjLaunch>& launches) {
   const int RB = sizeof(T) == 4 ? 5 : 4;
   const int t = std::min(n, adj_tile_bits<T>());
   const int c = std::min(t, sizeof(T) == 4 ? 5 : 4);
-  std::vector<AdjStep> steps;
+  steps.clear();
   plan_adjoint(ops, n_ops, n, t, c, RB, steps);
   const int LR = adj_rec_words(), GMAX = adj_max_grad();
   const int RK = adj_round_bits<T>(), kGateWords = adj_gate_words();
   constexpr int kRoundGates = 24;  // gates per round record
-  std::vector<int32_t>& prog = s->ahprog;
   prog.clear();
-  struct Launch {
-    int step;
-    size_t off;
-  };
-  std::vector<Launch> launches;
+  launches.clear();
   for (size_t si = 0; si < steps.size(); ++si) {
     const AdjStep& as = steps[si];
     if (!as.tile) continue;
@@ -1043,6 +1044,18 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
       k0 = k1;
     }
   }
+  return QSV_OK;
+}
+
+template <typename T>
+static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops, cpx<T>* psi, cpx<T>* lam,
+                                      double* gdev, double* tpart) {
+  const int n = s->n;
+  std::vector<AdjStep> steps;
+  std::vector<AdjLaunch> launches;
+  std::vector<int32_t>& prog = s->ahprog;
+  qsv_status bst = build_adjoint_programs<T>(n, ops, n_ops, steps, prog, launches);
+  if (bst) return bst;
   const size_t need = prog.size() * sizeof(int32_t) + 256;
   if (s->apbuf_bytes < need) {
     if (s->apbuf) {
@@ -1302,6 +1315,46 @@ static qsv_status adjoint_sweep(qsv_state* s, const qsv_op* ops, int n_ops, cons
 }  // namespace qsv
 
 extern "C" {
+
+// Host-only debug export (not part of the public header): the adjoint
+// sweep's programs, for emulation on the CPU in tests.  steps[i] is the
+// program offset of the i-th action (>= 0) or -(op + 1) for an op applied
+// as its inverse by the per-gate kernels; sizes as for the plan export.
+qsv_status qsv_debug_adjoint_program(int n_qubits, qsv_dtype dtype, const qsv_op* ops, int n_ops,
+                                     int32_t* words, int64_t cap_words, int64_t* n_words, int64_t* steps,
+                                     int64_t cap_steps, int64_t* n_steps) {
+  if (n_qubits < 1 || n_qubits > QSV_MAX_QUBITS) return fail(QSV_ERR_ARG, "n_qubits out of range");
+  if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_ERR_ARG, "bad dtype");
+  if (n_ops < 0 || (n_ops > 0 && !ops)) return fail(QSV_ERR_ARG, "bad op list");
+  qsv_state tmp;
+  tmp.n = n_qubits;
+  tmp.dt = dtype;
+  tmp.N = 1ull << n_qubits;
+  for (int i = 0; i < n_ops; ++i) {
+    qsv_status st = validate_op(&tmp, ops[i]);
+    if (st) return st;
+  }
+  std::vector<AdjStep> sv;
+  std::vector<int32_t> prog;
+  std::vector<AdjLaunch> launches;
+  qsv_status rc = dtype == QSV_C64 ? build_adjoint_programs<float>(n_qubits, ops, n_ops, sv, prog, launches)
+                                   : build_adjoint_programs<double>(n_qubits, ops, n_ops, sv, prog, launches);
+  if (rc) return rc;
+  std::vector<int64_t> acts;
+  size_t li = 0;
+  for (size_t si = 0; si < sv.size(); ++si) {
+    if (!sv[si].tile) {
+      acts.push_back(-(int64_t)sv[si].op - 1);
+      continue;
+    }
+    for (; li < launches.size() && launches[li].step == (int)si; ++li) acts.push_back((int64_t)launches[li].off);
+  }
+  if (n_words) *n_words = (int64_t)prog.size();
+  if (n_steps) *n_steps = (int64_t)acts.size();
+  for (int64_t i = 0; words && i < cap_words && i < (int64_t)prog.size(); ++i) words[i] = prog[i];
+  for (int64_t i = 0; steps && i < cap_steps && i < (int64_t)acts.size(); ++i) steps[i] = acts[i];
+  return QSV_OK;
+}
 
 qsv_status qsv_adjoint(qsv_state* s, const qsv_op* ops, int n_ops, const uint64_t* xmask,
                        const uint64_t* zmask, const double* coeff, int n_terms,

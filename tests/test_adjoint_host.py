@@ -1,0 +1,121 @@
+"""CPU checks of the adjoint sweep's program encoding.
+
+The adjoint emulator (tests/adjoint_emulator.py) decodes the exact programs
+the library would upload for the sweep kernel (op records, CZ/Z sign runs,
+register rounds of one-qubit gates, gradient slot maps, non-tile ops) and
+applies them to complex128 vectors.  Its gradients must equal the oracle's
+parameter-shift gradients and the sweep must return the state to its start,
+for both precisions, including circuits wider than one sweep tile so that
+operands outside the tile occur.
+"""
+import numpy as np
+import pytest
+
+import qcircuits as qc
+from oracle import oracle as O
+
+import adjoint_emulator as AE
+
+GTOL = {"c64": 2e-6, "c128": 1e-11}
+
+
+def check(n, dtype, build, params, ham, idx, others_zero=True):
+    ops = build(params)
+    e, g_ops, back = AE.emulate(n, dtype, ops, ham)
+    g = np.zeros(params.size)
+    np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
+    ref = O.param_shift_grad(build, params, ham, n)
+    assert abs(e - O.energy(build, params, ham, n)) < 1e-12
+    assert np.abs(g - ref).max() <= GTOL[dtype] * max(1, len(ham)), np.abs(g - ref).max()
+    if others_zero:  # no other rotations in the circuit
+        assert np.all(g_ops[idx < 0] == 0)
+    assert abs(back[0] - 1) < 1e-6 and np.abs(back[1:]).max() < 1e-6
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,layers", [(5, 2), (8, 3)])
+def test_rotation_ring(dtype, n, layers):
+    params, ham = qc.gradient_workload(n, layers, 700 + n)
+    idx = qc.rot_ring_param_index(n, layers)
+    check(n, dtype, lambda p: qc.rot_ring_ansatz(n, p, layers), params, ham, idx)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_chains_and_sign_runs_beyond_a_tile(dtype):
+    # 14 qubits > the sweep tile (12 / 11 qubits): CZ rings reach outside
+    # qubits; four one-qubit gates per qubit between entanglers; Z gates; a
+    # CZ that cancels one of the ring's
+    n, layers = 14, 2
+    rng = np.random.default_rng(41)
+    theta = rng.uniform(-np.pi, np.pi, n * 2 * layers)
+
+    def build(p):
+        ops, k = [], 0
+        for l in range(layers):
+            for q in range(n):
+                ops += [qc.op("H", q), qc.op("RZ", q, params=(p[k],)), qc.op("S", q),
+                        qc.op("RX" if q % 2 else "RY", q, params=(p[k + 1],))]
+                k += 2
+            for q in range(n):
+                ops.append(qc.op("CZ", q, (q + 1 + 5 * l) % n))
+            ops += [qc.op("Z", q) for q in range(0, n, 3)]
+            ops.append(qc.op("CZ", 0, n - 1))
+        return ops
+
+    ops = build(theta)
+    idx = np.array([-1] * len(ops))
+    k = 0
+    for i, o in enumerate(ops):
+        if o.name in ("RX", "RY", "RZ"):
+            idx[i] = k
+            k += 1
+    check(n, dtype, build, theta, qc.random_hamiltonian(n, 8, 43), idx)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_mixed_gates(dtype):
+    # rotations between fixed gates of every kind, including dense blocks
+    # on up to 4 qubits
+    n = 7
+    rng = np.random.default_rng(31)
+    fixed = qc.random_ops(n, 40, 32, dense_k=(1, 2, 3, 4))
+    nrot = 16
+    theta = rng.uniform(-np.pi, np.pi, nrot)
+    slots = sorted(rng.choice(len(fixed) + nrot, nrot, replace=False))
+
+    def build(p):
+        ops, it_f, k = [], iter(fixed), 0
+        for i in range(len(fixed) + nrot):
+            if k < nrot and i == slots[k]:
+                ops.append(qc.op(("RX", "RY", "RZ")[k % 3], k % n, params=(p[k],)))
+                k += 1
+            else:
+                ops.append(next(it_f))
+        return ops
+
+    idx = np.array([-1] * (len(fixed) + nrot))
+    for k, sl in enumerate(slots):
+        idx[sl] = k
+    # the fixed gates include rotations of their own, which get gradients too
+    check(n, dtype, build, theta, qc.random_hamiltonian(n, 10, 33), idx, others_zero=False)
+
+
+def test_program_uses_rounds_and_sign_runs():
+    # the 24-qubit gradient workload's programs hold register rounds and
+    # sign runs, not one record per gate (576 gates)
+    n, layers = 24, 6
+    params, _ = qc.gradient_workload(n, layers, qc.SEEDS["c5"])
+    ops = qc.rot_ring_ansatz(n, params, layers)
+    words, acts = AE.program(n, "c64", ops)
+    kinds = {}
+    for off in acts:
+        assert off >= 0
+        nops, roff = int(words[off + 3]), int(words[off + 5])
+        r = off + roff
+        for _ in range(nops):
+            typ = int(words[r])
+            kinds[typ] = kinds.get(typ, 0) + 1
+            r += int(words[r + 3]) if typ == 6 else AE.REC_WORDS
+    # 2: diagonal gates on qubits outside a pass's tile (RZ), 5: sign runs, 6: rounds
+    assert set(kinds) <= {2, 5, 6} and kinds.get(6, 0) > 0 and kinds.get(5, 0) > 0, kinds
+    assert sum(kinds.values()) < len(ops) // 3, (kinds, len(ops))
