@@ -300,6 +300,27 @@ __device__ __forceinline__ void xreg_round(const char* __restrict__ tb, const XR
   }
 }
 
+__device__ __forceinline__ uint64_t xreg_tile_base(const XRegDesc& d, uint64_t id) {
+  uint64_t b = 0;
+  for (int i = 0; i < d.nns; ++i) b |= ((id >> i) & 1ull) << d.nonS[i];
+  return b;
+}
+
+// this thread's vectors of the tile with base index b, into registers
+template <typename T, int NV>
+__device__ __forceinline__ void xreg_fetch(vec16<T> (&stage)[NV], const vec16<T>* __restrict__ gv, uint64_t b,
+                                           const uint64_t* segoff, int c, uint32_t cmask, int nvec) {
+  constexpr int A = VecInfo<T>::A;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int i = (int)threadIdx.x + v * kRB;
+    if (i < nvec) {
+      const uint32_t l = (uint32_t)i * A;
+      stage[v] = gv[(b | segoff[l >> c] | (l & cmask)) / A];
+    }
+  }
+}
+
 template <typename T, int TB, int RB, bool ODD>
 __global__ __launch_bounds__(kRB) void k_expval_xreg(const cpx<T>* __restrict__ psi, XRegDesc d,
                                                      XRegTerms tt, int nt, uint64_t ntiles,
@@ -325,16 +346,37 @@ __global__ __launch_bounds__(kRB) void k_expval_xreg(const cpx<T>* __restrict__ 
   const uint32_t cmask = (1u << c) - 1u;
   const char* tb = reinterpret_cast<const char*>(tile);
   __syncthreads();
+  // Software pipeline: the next tile's vectors are loaded into registers
+  // while the rounds of the current one run, so HBM reads overlap the math
+  // (complex64 only: the complex128 variant's staging array went to scratch)
+  constexpr bool PIPE = sizeof(T) == 4;
+  constexpr int NV = PIPE ? (1 << TB) / A / kRB : 1;  // vectors per thread of a full tile
+  vec16<T> stage[NV];
+  if (PIPE && (uint64_t)blockIdx.x < ntiles)
+    xreg_fetch<T, NV>(stage, gv, xreg_tile_base(d, blockIdx.x), segoff, c, cmask, nvec);
   for (uint64_t tid = blockIdx.x; tid < ntiles; tid += gridDim.x) {
-    uint64_t base = 0;
-    for (int i = 0; i < d.nns; ++i) base |= ((tid >> i) & 1ull) << d.nonS[i];
-    for (int i = threadIdx.x; i < nvec; i += kRB) {
-      const uint32_t l = (uint32_t)i * A;
-      const vec16<T> x = gv[(base | segoff[l >> c] | (l & cmask)) / A];
+    const uint64_t base = xreg_tile_base(d, tid);
+    if constexpr (PIPE) {
 #pragma unroll
-      for (int e = 0; e < A; ++e) tile[tile_swizzle(l + e, SB)] = x.a[e];
+      for (int v = 0; v < NV; ++v) {
+        const int i = (int)threadIdx.x + v * kRB;
+        if (i < nvec) {
+          const uint32_t l = (uint32_t)i * A;
+#pragma unroll
+          for (int e = 0; e < A; ++e) tile[tile_swizzle(l + e, SB)] = stage[v].a[e];
+        }
+      }
+    } else {
+      for (int i = threadIdx.x; i < nvec; i += kRB) {
+        const uint32_t l = (uint32_t)i * A;
+        const vec16<T> x = gv[(base | segoff[l >> c] | (l & cmask)) / A];
+#pragma unroll
+        for (int e = 0; e < A; ++e) tile[tile_swizzle(l + e, SB)] = x.a[e];
+      }
     }
     __syncthreads();
+    if (PIPE && tid + gridDim.x < ntiles)
+      xreg_fetch<T, NV>(stage, gv, xreg_tile_base(d, tid + gridDim.x), segoff, c, cmask, nvec);
     // (the empty asm keeps the compiler from hoisting the LDS gathers of all
     // rounds together, which would hold every round's amplitudes at once)
     xreg_round<T, RB, ODD, 0>(tb, d, tt, base, acc);
