@@ -725,7 +725,9 @@ static qsv_status build_adjoint_programs(int n, const qsv_op* ops, int n_ops, st
     for (int q = 0; q < n; ++q)
       if (lpos[q] < 0) nonS.push_back(q);
     // Items of the pass in application order: one op, a chain of one-qubit
-    // ops on one local qubit, or a run of CZ / Z gates.  An op joins an item
+    // ops on one local qubit (an intermediate grouping: runs of chains and
+    // one-qubit ops become register rounds below), or a run of CZ / Z
+    // gates.  An op joins an item
     // that starts earlier only when it commutes with every op it passes
     // (no shared qubit, or both diagonal), which leaves the product and every
     // gradient unchanged: a rotation's generator commutes with the same ops.
@@ -763,7 +765,7 @@ static qsv_status build_adjoint_programs(int n, const qsv_op* ops, int n_ops, st
       return false;
     };
     struct Item {
-      int type;  // 0 one op, 4 chain, 5 signs, 6 register round
+      int type;  // 0 one op, 4 chain (until rounds form), 5 signs, 6 register round
       std::vector<size_t> ks;
       std::vector<int> bits;  // round: local bits, ascending
     };
