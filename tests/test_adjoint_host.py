@@ -119,3 +119,17 @@ def test_program_uses_rounds_and_sign_runs():
     # 2: diagonal gates on qubits outside a pass's tile (RZ), 5: sign runs, 6: rounds
     assert set(kinds) <= {2, 5, 6} and kinds.get(6, 0) > 0 and kinds.get(5, 0) > 0, kinds
     assert sum(kinds.values()) < len(ops) // 3, (kinds, len(ops))
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_pass_with_more_rotations_than_slots(dtype):
+    # 6 qubits fit one tile, so all 360 rotations fall in one pass: the
+    # encoder splits it into programs of at most 256 gradient slots
+    n, layers = 6, 20
+    params, ham = qc.gradient_workload(n, layers, 707)
+    idx = qc.rot_ring_param_index(n, layers)
+    build = lambda p: qc.rot_ring_ansatz(n, p, layers)
+    words, acts = AE.program(n, dtype, build(params))
+    assert len(acts) >= 2 and all(int(words[a + 4]) <= 256 for a in acts)
+    assert sum(int(words[a + 4]) for a in acts) == params.size
+    check(n, dtype, build, params, ham, idx)

@@ -139,6 +139,22 @@ def test_adjoint_energy_paths(dtype):
         assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_adjoint_pass_split_over_programs(dtype):
+    # 360 rotations in one tile pass: split into programs of <= 256 slots
+    n, layers = 6, 20
+    params, ham = qc.gradient_workload(n, layers, 707)
+    build = lambda p: qc.rot_ring_ansatz(n, p, layers)
+    idx = qc.rot_ring_param_index(n, layers)
+    s = State(n, dtype)
+    e, g_ops = s.adjoint(build(params), ham)
+    s.close()
+    g = np.zeros(params.size)
+    np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
+    ref = O.param_shift_grad(build, params, ham, n)
+    assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham)
+
+
 def test_autograd_function():
     import torch
     from paper_1807_07914_amd.autograd import expectation
