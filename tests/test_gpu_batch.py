@@ -128,3 +128,29 @@ def test_h2_vqe_sweep_batched(dtype, tol):
     # and against the oracle run of each measured circuit
     ref = np.array([O.expval(O.run(c, w), h) for c, w, h in zip(circs, widths, hams)])
     assert np.abs(e - ref).max() <= (1e-5 if dtype == "c64" else 1e-12)
+
+
+def test_c4_full_batch_matches_pergate():
+    # all 4096 circuits of the batched workload (widths 8..20) in one launch
+    # against the per-gate kernels run circuit by circuit (complex64)
+    from paper_1807_07914_amd import State
+    b = qc.hea_batch(4096, qc.SEEDS["c4"])
+    circs = [b.circuit(i) for i in range(4096)]
+    hams = [b.hamiltonian(i) for i in range(4096)]
+    widths = [int(w) for w in b.widths]
+    say("creating the 4096-circuit batch")
+    bt = Batch(circs, widths, hams, dtype="c64")
+    e = bt.run()
+    bt.close()
+    say("batch done; per-gate reference")
+    states = {w: State(w, "c64") for w in sorted(set(widths))}
+    ref = np.empty(4096)
+    for i in range(4096):
+        s = states[widths[i]]
+        s.set_basis(0)
+        s.apply_circuit(circs[i], mode="pergate")
+        ref[i] = s.expval(hams[i])
+    for s in states.values():
+        s.close()
+    say("reference done")
+    assert np.abs(e - ref).max() <= 1e-4
