@@ -33,6 +33,9 @@ qsv_status fail(qsv_status code, const std::string& msg) {
 qsv_status hip_fail(hipError_t e, const char* where) {
   set_error(std::string("HIP error ") + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ") in " +
             where);
+  // clear the runtime's last-error slot, which the failed call also set:
+  // the launch checks of later calls read it and would report this error
+  (void)hipGetLastError();
   return e == hipErrorOutOfMemory ? QSV_ERR_OOM : QSV_ERR_HIP;
 }
 

@@ -1251,6 +1251,8 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
   const int TBMAX = tile_max_bits<T>();
   const int n = s->n;
   if (n < RB) {  // register smaller than one register group: per-gate kernels
+    qsv_status sw = ensure_workspace(s, dense_ws_bytes());  // dense blocks stage their matrix there
+    if (sw) return sw;
     for (int i = 0; i < n_ops; ++i) {
       qsv_status st = apply_op_pergate(s, ops[i], 0);
       if (st) return st;

@@ -399,3 +399,33 @@ def test_paper_rounds_schmidt_bound_on_gpu(n, rounds):
     assert int(np.sum(sv > 1e-4 * sv[0])) <= 2 ** rounds
     # and the bound is not vacuous: the rank reaches it for these seeds
     assert int(np.sum(sv > 1e-4 * sv[0])) >= 2
+
+
+# ------------------------------------------------------------ degenerate inputs
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_degenerate_sizes_and_empty_inputs(dtype, n):
+    # states smaller than a register group, in every apply mode; the empty
+    # circuit, an empty Hamiltonian and zero shots leave or return nothing
+    ops = qc.random_ops(n, 25, 500 + n, dense_k=tuple(k for k in (1, 2, 3) if k <= n))
+    ref = O.run(ops, n)
+    for mode in ("fused", "pergate", "auto"):
+        s = State(n, dtype)
+        s.apply_circuit(ops, mode=mode)
+        got = s.to_numpy().astype(np.complex128)
+        assert np.abs(got - ref).max() <= TOL[dtype], mode
+        s.apply_circuit([], mode=mode)
+        assert np.array_equal(s.to_numpy().astype(np.complex128), got)
+        assert s.expval([]) == 0.0
+        assert s.sample(np.zeros(0)).size == 0
+        s.close()
+    # an adjoint sweep over no ops: the energy of the current state, no gradients
+    ham = qc.random_hamiltonian(n, 3, 600 + n, max_weight=min(n, 2))
+    s = State(n, dtype)
+    s.from_numpy(ref)
+    e, g = s.adjoint([], ham)
+    back = s.to_numpy().astype(np.complex128)
+    s.close()
+    assert g.size == 0
+    assert abs(e - O.expval(ref, ham)) <= 10 * TOL[dtype] * len(ham)
+    assert np.abs(back - ref).max() <= TOL[dtype]
