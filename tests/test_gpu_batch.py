@@ -154,3 +154,28 @@ def test_c4_full_batch_matches_pergate():
         s.close()
     say("reference done")
     assert np.abs(e - ref).max() <= 1e-4
+
+
+@pytest.mark.parametrize("dtype,tol", [("c64", 1e-5), ("c128", 1e-11)])
+def test_batch_degenerate_circuits(dtype, tol):
+    # widths 1..5 and beyond one tile, an empty circuit, a circuit without
+    # Hamiltonian terms, and a batch of a single circuit
+    rng = np.random.default_rng(77)
+    widths = [1, 2, 3, 5, 14, 4, 15]
+    circs = []
+    for w in widths:
+        names = [g for g in ("H", "RX", "RY", "RZ", "S", "CZ", "CNOT") if qc.GATE_ARITY[g] <= w]
+        circs.append(qc.random_ops(w, 30, int(rng.integers(1 << 30)), names=names, dense_k=(1, 2) if w >= 2 else (1,)))
+    circs[5] = []                                  # the empty circuit
+    hams = [qc.zz_chain(w) if w >= 2 else [(0.5, (("Z", 0),))] for w in widths]
+    hams[3] = []                                   # no terms: energy 0
+    bt = Batch(circs, widths, hams, dtype=dtype)
+    e = bt.run()
+    bt.close()
+    ref = np.array([O.expval(O.run(c, w), h) if h else 0.0 for c, w, h in zip(circs, widths, hams)])
+    assert np.abs(e - ref).max() <= tol
+    assert e[3] == 0.0 and abs(e[5] - (widths[5] - 1)) <= tol  # |0000>: every ZZ is +1
+    bt1 = Batch(circs[4:5], widths[4:5], hams[4:5], dtype=dtype)
+    e1 = bt1.run()
+    bt1.close()
+    assert abs(e1[0] - ref[4]) <= tol
