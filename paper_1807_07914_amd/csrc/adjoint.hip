@@ -7,11 +7,14 @@
 // psi_k = U_k ... U_1 psi_0 and lambda_k = U_{k+1}^dag ... U_L^dag H psi_L.
 // One reverse sweep yields every derivative: start from psi_L and
 // lambda = H psi_L, and for k = L .. 1 accumulate the gradient of gate k,
-// then apply U_k^dag to both states.  A rotation's gradient and both inverse
-// updates share one kernel and one HBM pass over the two states; the
-// gradient is accumulated in FP64 with the fixed two-stage tree used by all
-// reductions.  (Not part of the paper, whose gradients are taken over
-// tensor-network factors; it is the parameter-gradient of its VQE use case.)
+// then apply U_k^dag to both states.  Here lambda = H psi is formed by tile
+// passes (or by gathers for X masks wider than a tile), and the sweep runs
+// as tile passes over both states in LDS that apply each pass's inverse
+// gates and take every rotation's term on the way (states below five qubits
+// use one kernel per rotation).  Gradients are accumulated in FP64 in a
+// fixed order (no floating-point atomics).  (Not part of the paper, whose
+// gradients are taken over tensor-network factors; it is the
+// parameter-gradient of its VQE use case.)
 #include <algorithm>
 
 #include "internal.hpp"
@@ -114,7 +117,7 @@ __global__ __launch_bounds__(kAB) void k_adj_final(const double* __restrict__ pa
 // and lambda in LDS (the 2^t amplitudes with fixed non-S bits), applies
 // every inverse gate of the pass to both in order, and at each rotation adds
 // the tile's share of Im <lambda| P |psi> before applying the inverse.  A
-// wavefront reduces its share with shuffles and adds it to its own LDS slot
+// wavefront reduces its share (DPP steps) and adds it to its own LDS slot
 // per rotation (no atomics: the order of every addition is fixed); at the
 // end each workgroup writes its per-rotation sums, which one workgroup per
 // rotation then adds in a fixed tree.  One HBM read and write of both
@@ -146,9 +149,10 @@ __global__ __launch_bounds__(kAB) void k_adj_final(const double* __restrict__ pa
 //           their order), taking each rotation's term first.  [2] the gate
 //           count of each register bit, 8 bits per bit j from bit 8 j,
 //           [3] record length in words, [4 + j] local bit j (ascending),
-//           gates from word 8 ordered by bit, kAdjGate words each: [0] j | shape << 4 |
-//           generator << 8, [1] gradient slot or -1, from word 4 the
-//           matrix (m00, m01, m10, m11 as re, im) in the state's precision
+//           gates from word 8 ordered by bit, kAdjGate words each:
+//           [0] j | shape << 4 | generator << 8, [1] gradient slot or -1,
+//           from word 4 the matrix (m00, m01, m10, m11 as re, im) in the
+//           state's precision
 // Records of types 1-5 are kAdjRec words long.
 constexpr int kAdjRec = 72;
 constexpr int kAdjGate = 20;
