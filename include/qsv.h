@@ -49,7 +49,7 @@ typedef enum {
   QSV_ERR_ARG = -1,          /* invalid argument (range, duplicate qubit, NaN, size) */
   QSV_ERR_OOM = -2,          /* device allocation failed */
   QSV_ERR_HIP = -3,          /* HIP runtime error (text in qsv_last_error) */
-  QSV_ERR_UNSUPPORTED = -4,  /* valid request this build does not implement */
+  QSV_ERR_UNSUPPORTED = -4,  /* valid request the library does not implement */
   QSV_ERR_STATE = -5         /* bad or freed handle, or concurrent use of one state */
 } qsv_status;
 

@@ -1,5 +1,5 @@
 // circuit.hip -- execution of whole gate lists (qsv_apply_circuit): the
-// fusion planner and the driver of the tile-pass kernel.
+// fusion planner and the host side of the tile-pass kernel.
 //
 // The paper's general algorithm (section II) optionally augments the circuit
 // with SWAPs to maximise accelerated gate applications and groups gates into
