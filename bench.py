@@ -155,6 +155,8 @@ def bench_rounds(np, torch, qc, qsv, circuits=10):
     out = {}
     for n in range(5, 31, 5):
         s = qsv.State(n, "c64")
+        s.apply_circuit(qsv.OpList(qc.paper_rounds(n, 2, 1999)), mode="fused")  # warm-up, untimed
+        torch.cuda.synchronize()
         row = {}
         for rounds in range(2, 11, 2):
             gates, t_tot, chi = 0, 0.0, None

@@ -63,6 +63,35 @@ static bool is_zero(cd z) { return z.real() == 0.0 && z.imag() == 0.0; }
 static bool is_one(cd z) { return z.real() == 1.0 && z.imag() == 0.0; }
 static bool is_mone(cd z) { return z.real() == -1.0 && z.imag() == 0.0; }
 
+// Tile passes take CNOT(c, t) as H_t CZ(c, t) H_t: the Hadamards become
+// rotations (merged with the target's neighbouring one-qubit gates) and the
+// CZ a sign step, all in the lean tile body, where the permutation step a
+// CNOT needs otherwise exists only in the full body (more registers, slower
+// per layer).  Other ops are kept as they are.
+static void expand_cnots(const qsv_op* ops, int n_ops, std::vector<qsv_op>& out) {
+  out.clear();
+  out.reserve((size_t)n_ops);
+  for (int i = 0; i < n_ops; ++i) {
+    const qsv_op& o = ops[i];
+    if (o.gate != QSV_CNOT) {
+      out.push_back(o);
+      continue;
+    }
+    qsv_op h{};
+    h.gate = QSV_H;
+    h.nq = 1;
+    h.q[0] = o.q[1];
+    qsv_op cz{};
+    cz.gate = QSV_CZ;
+    cz.nq = 2;
+    cz.q[0] = o.q[0];
+    cz.q[1] = o.q[1];
+    out.push_back(h);
+    out.push_back(cz);
+    out.push_back(h);
+  }
+}
+
 static POp classify(const qsv_op& o) {
   POp p;
   p.nq = o.nq;
@@ -1259,6 +1288,10 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
     }
     return QSV_OK;
   }
+  std::vector<qsv_op> xops;  // the list the plan and its per-gate steps refer to
+  expand_cnots(ops, n_ops, xops);
+  ops = xops.data();
+  n_ops = (int)xops.size();
   int t = opts.tile_qubits > 0 ? opts.tile_qubits : default_tile_bits<T>();
   if (t > TBMAX) return fail(QSV_ERR_UNSUPPORTED, "tile_qubits exceeds the LDS tile capacity");
   if (t < RB) return fail(QSV_ERR_ARG, "tile_qubits smaller than the register group");
@@ -1372,6 +1405,10 @@ qsv_status plan_program(const qsv_state* s, const qsv_op* ops, int n_ops, int ti
   if (t > n) t = n;
   int c = f ? 5 : 4;
   if (c > t) c = t;
+  std::vector<qsv_op> xops;  // per-gate steps index this list (CNOTs expanded)
+  expand_cnots(ops, n_ops, xops);
+  ops = xops.data();
+  n_ops = (int)xops.size();
   std::vector<POp> P(n_ops);
   for (int i = 0; i < n_ops; ++i) P[i] = classify(ops[i]);
   auto sch = build_schedule(P, n, t, c, RB);
@@ -1401,8 +1438,10 @@ qsv_status plan_passes(const qsv_state* s, const qsv_op* ops, int n_ops, int til
   if (t > n) t = n;
   int c = f ? 5 : 4;
   if (c > t) c = t;
-  std::vector<POp> P(n_ops);
-  for (int i = 0; i < n_ops; ++i) P[i] = classify(ops[i]);
+  std::vector<qsv_op> xops;
+  expand_cnots(ops, n_ops, xops);
+  std::vector<POp> P(xops.size());
+  for (size_t i = 0; i < xops.size(); ++i) P[i] = classify(xops[i]);
   auto sch = build_schedule(P, n, t, c, RB);
   int fb = 0;
   for (const Step& st : sch->steps) fb += st.tile ? 0 : 1;

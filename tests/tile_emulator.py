@@ -16,6 +16,7 @@ import ctypes
 
 import numpy as np
 
+import qcircuits as qc
 from paper_1807_07914_amd import qsv
 
 ROUND_HEADER = 16   # words of a round block header
@@ -310,9 +311,23 @@ def run_pass(psi, n, words, off, cfg):
             psi[gidx[l]] = lds[swizzle(l, SB)]
 
 
+def expand_cnots(ops):
+    """The op list the library's fused plan indexes: each CNOT(c, t) taken as
+    H(t), CZ(c, t), H(t)."""
+    out = []
+    for o in ops:
+        if o.name == "CNOT":
+            c, t = o.qubits
+            out += [qc.op("H", t), qc.op("CZ", c, t), qc.op("H", t)]
+        else:
+            out.append(o)
+    return out
+
+
 def emulate(n, dtype, ops, psi0, tile=0, matrix_of=None):
     """Run the fused plan of ``ops`` on psi0 (complex128, copied)."""
     words, steps = program(n, dtype, ops, tile)
+    ops = expand_cnots(list(ops))
     psi = np.array(psi0, dtype=np.complex128)
     cfg = CFG[dtype]
     for st in steps:
