@@ -1537,8 +1537,10 @@ static qsv_status batch_materialise(qsv_batch* b, int t, bool check_only_structu
     int c = sizeof(T) == 4 ? 5 : 4;
     if (c > tc) c = tc;
     const int o0 = b->op_off[ci], o1 = b->op_off[ci + 1];
-    std::vector<POp> P(o1 - o0);
-    for (int i = o0; i < o1; ++i) P[i - o0] = classify(b->ops[i]);
+    std::vector<qsv_op> xops;  // CNOTs as H CZ H, as in the single-state passes
+    expand_cnots(b->ops.data() + o0, o1 - o0, xops);
+    std::vector<POp> P(xops.size());
+    for (size_t i = 0; i < xops.size(); ++i) P[i] = classify(xops[i]);
     std::vector<uint32_t> key = structure_key(P, n, tc, c, RB);
     const uint64_t h = key_hash(key);
     std::shared_ptr<Schedule> sch;
