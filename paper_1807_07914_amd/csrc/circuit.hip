@@ -1461,7 +1461,7 @@ namespace qsv {
 template <typename T>
 hipError_t launch_batch(cpx<T>* scratch, const int32_t* progs, const int64_t* passoff,
                         const int64_t* jobs, const uint64_t* zt, const double* ct, double* out,
-                        int* counter, int njobs, int grid, hipStream_t st);
+                        int* counter, int njobs, int grid, bool full, hipStream_t st);
 
 }  // namespace qsv
 
@@ -1643,9 +1643,11 @@ static qsv_status batch_build(qsv_batch* b, int t) {
   b->grid = std::max(1, std::min(b->njobs, 2 * cus));  // two 64 KiB-LDS workgroups per CU
   // capture reset + persistent kernel once; runs replay the graph
   QSV_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  bool full = false;  // the lean kernel unless some pass needs the full tile body
+  for (int64_t off : b->passoff) full = full || program_needs_full<T>(b->hprog.data() + off);
   hipError_t e = launch_batch<T>(static_cast<cpx<T>*>(b->d_scratch), b->d_prog, b->d_passoff,
                                  b->d_jobs, b->d_z, b->d_c, b->d_out, b->d_counter, b->njobs,
-                                 b->grid, b->stream);
+                                 b->grid, full, b->stream);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->stream, &g);
   if (e != hipSuccess) return hip_fail(e, "batch launch capture");

@@ -721,6 +721,116 @@ __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile_pipe(cpx<T>* __res
 }
 
 // ------------------------------------------------------------ batches
+// Every tile of one pass of one batched circuit (state at psi), lean body,
+// by one workgroup: the segment table once per pass, and half of each
+// thread's share of the next tile loading into registers while the current
+// tile's rounds run (a batch often has about one workgroup per compute unit,
+// so other workgroups do not hide the load latency; a whole tile of staging
+// would not fit the registers).  The first pass builds |0...0> in the tile
+// instead of loading; the last reduces the Z-string sum instead of storing.
+// Returns the thread's partial of that sum.
+template <typename T, int TBMAX, int RB>
+__device__ __forceinline__ double batch_pass(cpx<T>* __restrict__ psi, const int32_t* __restrict__ prog,
+                                             uint64_t ntiles, const TileIO& io) {
+  constexpr int A = VecInfo<T>::A;
+  constexpr int VPT = (1 << TBMAX) / A / kTileThreads;  // 16-byte vectors per thread
+  constexpr int PF = VPT / 2;                           // of which prefetched
+  constexpr int SB = SwzBits<T>::B;
+  using V = typename StageVec<T>::V;
+  __shared__ cpx<T> tile[1 << TBMAX];
+  __shared__ uint64_t segoff[1 << (TBMAX - 4)];
+  const int t = prog[0], c = prog[1], nns = prog[2];
+  const int32_t* S = prog + 4;
+  const int32_t* nonS = S + t;
+  const int nseg = 1 << (t - c);
+  for (int h = threadIdx.x; h < nseg; h += kTileThreads) {
+    uint64_t o = 0;
+    for (int j = 0; j < t - c; ++j)
+      if ((h >> j) & 1) o |= 1ull << S[c + j];
+    segoff[h] = o;
+  }
+  __syncthreads();
+  V* gv = reinterpret_cast<V*>(psi);
+  const int nvec = (1 << t) / A;
+  const uint32_t cmask = (1u << c) - 1u;
+  V stage[PF];
+  double acc = 0.0;
+  uint64_t nb = 0;  // base index of the tile whose first half is in stage (tile 0: 0)
+  if (!io.init) {
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int i = threadIdx.x + k * kTileThreads;
+      if (i < nvec) {
+        const uint32_t l = (uint32_t)i * A;
+        stage[k] = gv[(nb | segoff[l >> c] | (l & cmask)) / A];
+      }
+    }
+  }
+  for (uint64_t tid = 0; tid < ntiles; ++tid) {
+    uint64_t base = 0;
+    for (int i = 0; i < nns; ++i) base |= ((tid >> i) & 1ull) << nonS[i];
+    if (io.init) {
+      for (int i = threadIdx.x; i < nvec; i += kTileThreads) {
+        const uint32_t l = (uint32_t)i * A;
+        const uint64_t g = base | segoff[l >> c] | (l & cmask);
+#pragma unroll
+        for (int e = 0; e < A; ++e)
+          tile[tile_swizzle(l + e, SB)] = cpx<T>{(g + e == 0) ? T(1) : T(0), T(0)};
+      }
+    } else {
+#pragma unroll
+      for (int k = PF; k < VPT; ++k) {  // the other half now
+        const int i = threadIdx.x + k * kTileThreads;
+        if (i < nvec) {
+          const uint32_t l = (uint32_t)i * A;
+          StageVec<T>::put(tile, SB, l, gv[(base | segoff[l >> c] | (l & cmask)) / A]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const int i = threadIdx.x + k * kTileThreads;
+        if (i < nvec) StageVec<T>::put(tile, SB, (uint32_t)i * A, stage[k]);
+      }
+    }
+    __syncthreads();
+    if (!io.init && tid + 1 < ntiles) {  // first half of the next tile, in flight during the rounds
+      nb = 0;
+      for (int i = 0; i < nns; ++i) nb |= (((tid + 1) >> i) & 1ull) << nonS[i];
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const int i = threadIdx.x + k * kTileThreads;
+        if (i < nvec) {
+          const uint32_t l = (uint32_t)i * A;
+          stage[k] = gv[(nb | segoff[l >> c] | (l & cmask)) / A];
+        }
+      }
+    }
+    run_rounds<T, TBMAX, RB, false>(reinterpret_cast<char*>(tile), prog, t, nns, base);
+    if (io.reduce) {
+      for (int l = threadIdx.x; l < (1 << t); l += kTileThreads) {
+        const uint64_t g = base | segoff[(uint32_t)l >> c] | ((uint32_t)l & cmask);
+        const cpx<T> x = tile[tile_swizzle((uint32_t)l, SB)];
+        const double pr = fma((double)x.x, (double)x.x, (double)x.y * (double)x.y);
+        double f = 0.0;
+        for (int q = 0; q < io.nt; ++q) f += (__popcll(g & io.z[q]) & 1) ? -io.coef[q] : io.coef[q];
+        acc = fma(pr, f, acc);
+      }
+    }
+    if (io.store) {
+#pragma unroll
+      for (int k = 0; k < VPT; ++k) {
+        const int i = threadIdx.x + k * kTileThreads;
+        if (i < nvec) {
+          const uint32_t l = (uint32_t)i * A;
+          gv[(base | segoff[l >> c] | (l & cmask)) / A] = StageVec<T>::get(tile, SB, l);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return acc;
+}
+
 // Persistent kernel over many independent circuits.  Each workgroup takes
 // the next job from an atomic counter (jobs are sorted largest first) and
 // runs the whole circuit by itself: every pass of its plan, every tile of a
@@ -736,7 +846,7 @@ __global__ void k_batch_reset(int* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
-template <typename T, int TBMAX, int RB>
+template <typename T, int TBMAX, int RB, bool FULL>
 __global__ __launch_bounds__(kTileThreads, 2) void k_batch(cpx<T>* __restrict__ scratch,
                                                          const int32_t* __restrict__ progs,
                                                          const int64_t* __restrict__ passoff,
@@ -766,8 +876,12 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_batch(cpx<T>* __restrict__ 
       const int t = prog[0];
       const uint64_t ntiles = 1ull << (w - t);
       const TileIO io{p == 0, p + 1 < np, p + 1 == np, zt + t0, ct + t0, (int)nt};
-      for (uint64_t tid = 0; tid < ntiles; ++tid)
-        acc += tile_body<T, TBMAX, RB, true>(scratch + soff, prog, tid, io);
+      if constexpr (FULL) {
+        for (uint64_t tid = 0; tid < ntiles; ++tid)
+          acc += tile_body<T, TBMAX, RB, true>(scratch + soff, prog, tid, io);
+      } else {
+        acc += batch_pass<T, TBMAX, RB>(scratch + soff, prog, ntiles, io);
+      }
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -864,18 +978,22 @@ hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const i
 template <typename T>
 hipError_t launch_batch(cpx<T>* scratch, const int32_t* progs, const int64_t* passoff,
                         const int64_t* jobs, const uint64_t* zt, const double* ct, double* out,
-                        int* counter, int njobs, int grid, hipStream_t st) {
+                        int* counter, int njobs, int grid, bool full, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
-  hipLaunchKernelGGL((k_batch<T, TileCfg<T>::TBMAX, TileCfg<T>::RB>), dim3(grid), dim3(kTileThreads),
-                     0, st, scratch, progs, passoff, jobs, zt, ct, out, counter, njobs);
+  if (full)
+    hipLaunchKernelGGL((k_batch<T, TileCfg<T>::TBMAX, TileCfg<T>::RB, true>), dim3(grid), dim3(kTileThreads),
+                       0, st, scratch, progs, passoff, jobs, zt, ct, out, counter, njobs);
+  else  // every program of the batch uses only the lean steps
+    hipLaunchKernelGGL((k_batch<T, TileCfg<T>::TBMAX, TileCfg<T>::RB, false>), dim3(grid), dim3(kTileThreads),
+                       0, st, scratch, progs, passoff, jobs, zt, ct, out, counter, njobs);
   return hipGetLastError();
 }
 template hipError_t launch_batch<float>(cpx<float>*, const int32_t*, const int64_t*, const int64_t*,
-                                        const uint64_t*, const double*, double*, int*, int, int,
+                                        const uint64_t*, const double*, double*, int*, int, int, bool,
                                         hipStream_t);
 template hipError_t launch_batch<double>(cpx<double>*, const int32_t*, const int64_t*,
                                          const int64_t*, const uint64_t*, const double*, double*,
-                                         int*, int, int, hipStream_t);
+                                         int*, int, int, bool, hipStream_t);
 
 template int tile_max_bits<float>();
 template int tile_max_bits<double>();
