@@ -707,8 +707,15 @@ struct AdjLaunch {
 // The sweep's steps and programs (host only): prog receives every program,
 // launches the program offsets of each tile step in order.
 template <typename T>
-static qsv_status build_adjoint_programs(int n, const qsv_op* ops, int n_ops, std::vector<AdjStep>& steps,
-                                         std::vector<int32_t>& prog, std::vector<AdjLaunch>& launches) {
+static qsv_status build_adjoint_programs(int n, const qsv_op* in_ops, int n_in, std::vector<AdjStep>& steps,
+                                         std::vector<int32_t>& prog, std::vector<AdjLaunch>& launches,
+                                         std::vector<qsv_op>& xops) {
+  // the sweep plans the list with CNOT as H CZ H (steps and records index it);
+  // gradient slots name the ops of the input list through origin
+  std::vector<int> origin;
+  expand_cnots(in_ops, n_in, xops, &origin);
+  const qsv_op* ops = xops.data();
+  const int n_ops = (int)xops.size();
   const int RB = sizeof(T) == 4 ? 5 : 4;
   const int t = std::min(n, adj_tile_bits<T>());
   const int c = std::min(t, sizeof(T) == 4 ? 5 : 4);
@@ -928,7 +935,7 @@ static qsv_status build_adjoint_programs(int n, const qsv_op* ops, int n_ops, st
             gw[1] = -1;
             if (o.gate == QSV_RX || o.gate == QSV_RY || o.gate == QSV_RZ) {
               gw[1] = (int32_t)map.size();
-              map.push_back(as.ops[kk]);
+              map.push_back(origin[as.ops[kk]]);
               gen = gen_of(o.gate);
             }
             gw[0] = j | (form << 4) | (gen << 8);
@@ -1001,7 +1008,7 @@ static qsv_status build_adjoint_programs(int n, const qsv_op* ops, int n_ops, st
         const bool rot = o.gate == QSV_RX || o.gate == QSV_RY || o.gate == QSV_RZ;
         if (rot) {
           rec[3] = (int32_t)map.size();
-          map.push_back(as.ops[kk]);
+          map.push_back(origin[as.ops[kk]]);
           rec[4] = gen_of(o.gate);
         }
         cd vals[16];
@@ -1058,8 +1065,9 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
   const int n = s->n;
   std::vector<AdjStep> steps;
   std::vector<AdjLaunch> launches;
+  std::vector<qsv_op> xops;  // the list the steps index
   std::vector<int32_t>& prog = s->ahprog;
-  qsv_status bst = build_adjoint_programs<T>(n, ops, n_ops, steps, prog, launches);
+  qsv_status bst = build_adjoint_programs<T>(n, ops, n_ops, steps, prog, launches, xops);
   if (bst) return bst;
   const size_t need = prog.size() * sizeof(int32_t) + 256;
   if (s->apbuf_bytes < need) {
@@ -1080,9 +1088,9 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
   for (size_t si = 0; si < steps.size(); ++si) {
     const AdjStep& as = steps[si];
     if (!as.tile) {
-      st = apply_op_inverse(s, s->psi, ops[as.op], 0);
+      st = apply_op_inverse(s, s->psi, xops[as.op], 0);
       if (st) return st;
-      st = apply_op_inverse(s, s->aux, ops[as.op], 0);
+      st = apply_op_inverse(s, s->aux, xops[as.op], 0);
       if (st) return st;
       continue;
     }
@@ -1324,7 +1332,8 @@ extern "C" {
 // Host-only debug export (not part of the public header): the adjoint
 // sweep's programs, for emulation on the CPU in tests.  steps[i] is the
 // program offset of the i-th action (>= 0) or -(op + 1) for an op applied
-// as its inverse by the per-gate kernels; sizes as for the plan export.
+// as its inverse by the per-gate kernels, op indexing the list with each
+// CNOT taken as H CZ H; sizes as for the plan export.
 qsv_status qsv_debug_adjoint_program(int n_qubits, qsv_dtype dtype, const qsv_op* ops, int n_ops,
                                      int32_t* words, int64_t cap_words, int64_t* n_words, int64_t* steps,
                                      int64_t cap_steps, int64_t* n_steps) {
@@ -1342,8 +1351,10 @@ qsv_status qsv_debug_adjoint_program(int n_qubits, qsv_dtype dtype, const qsv_op
   std::vector<AdjStep> sv;
   std::vector<int32_t> prog;
   std::vector<AdjLaunch> launches;
-  qsv_status rc = dtype == QSV_C64 ? build_adjoint_programs<float>(n_qubits, ops, n_ops, sv, prog, launches)
-                                   : build_adjoint_programs<double>(n_qubits, ops, n_ops, sv, prog, launches);
+  std::vector<qsv_op> xops;
+  qsv_status rc = dtype == QSV_C64
+                      ? build_adjoint_programs<float>(n_qubits, ops, n_ops, sv, prog, launches, xops)
+                      : build_adjoint_programs<double>(n_qubits, ops, n_ops, sv, prog, launches, xops);
   if (rc) return rc;
   std::vector<int64_t> acts;
   size_t li = 0;

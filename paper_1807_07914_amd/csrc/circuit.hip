@@ -68,15 +68,18 @@ static bool is_mone(cd z) { return z.real() == -1.0 && z.imag() == 0.0; }
 // CZ a sign step, all in the lean tile body, where the permutation step a
 // CNOT needs otherwise exists only in the full body (more registers, slower
 // per layer).  Other ops are kept as they are.
-static void expand_cnots(const qsv_op* ops, int n_ops, std::vector<qsv_op>& out) {
+void expand_cnots(const qsv_op* ops, int n_ops, std::vector<qsv_op>& out, std::vector<int>* origin) {
   out.clear();
   out.reserve((size_t)n_ops);
+  if (origin) origin->clear();
   for (int i = 0; i < n_ops; ++i) {
     const qsv_op& o = ops[i];
     if (o.gate != QSV_CNOT) {
       out.push_back(o);
+      if (origin) origin->push_back(i);
       continue;
     }
+    if (origin) origin->insert(origin->end(), 3, i);
     qsv_op h{};
     h.gate = QSV_H;
     h.nq = 1;

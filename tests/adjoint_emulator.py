@@ -16,6 +16,7 @@ import numpy as np
 
 from oracle import oracle as O
 from paper_1807_07914_amd import qsv
+from tile_emulator import expand_cnots
 
 REC_WORDS, GATE_WORDS = 72, 20
 ROUND_BITS = {"c64": 4, "c128": 3}
@@ -173,11 +174,12 @@ def emulate(n, dtype, ops, ham, x0=0):
     energy = float(np.vdot(psi, lam).real)
     words, acts = program(n, dtype, ops)
     grads = np.zeros(len(ops))
+    xops = expand_cnots(list(ops))  # per-gate steps index the list with CNOT as H CZ H
     for a in acts:
         if a >= 0:
             run_program(words, a, n, dtype, psi, lam, grads)
         else:
-            o = ops[-a - 1]
+            o = xops[-a - 1]
             M = o.mat if o.mat is not None else O.gate_matrix(o.name, o.params)
             _apply(psi, lam, n, o.qubits, np.conj(np.asarray(M)).T)
     return energy, grads, psi

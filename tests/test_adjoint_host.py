@@ -133,3 +133,21 @@ def test_pass_with_more_rotations_than_slots(dtype):
     assert len(acts) >= 2 and all(int(words[a + 4]) <= 256 for a in acts)
     assert sum(int(words[a + 4]) for a in acts) == params.size
     check(n, dtype, build, params, ham, idx)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_cnot_ladders(dtype):
+    # HEA layers (RY, RZ, CNOT ladder): the sweep plans each CNOT as H CZ H and
+    # maps the gradient slots back to the listed rotations; 13 qubits so that
+    # passes have qubits outside their tile
+    n, layers = 13, 2
+    theta = np.random.default_rng(61).uniform(0, 2 * np.pi, (layers, n, 2))
+    build = lambda p: qc.hea_circuit(n, np.asarray(p).reshape(layers, n, 2), layers)
+    ops = build(theta)
+    idx = np.array([-1] * len(ops))
+    k = 0
+    for i, o in enumerate(ops):
+        if o.name in ("RY", "RZ"):
+            idx[i] = k
+            k += 1
+    check(n, dtype, build, theta.ravel(), qc.random_hamiltonian(n, 6, 62), idx)

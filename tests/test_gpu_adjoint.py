@@ -155,6 +155,33 @@ def test_adjoint_pass_split_over_programs(dtype):
     assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_adjoint_cnot_ladders(dtype):
+    # HEA layers with CNOT ladders (planned as H CZ H in the sweep), 13 qubits
+    n, layers = 13, 2
+    theta = np.random.default_rng(61).uniform(0, 2 * np.pi, (layers, n, 2))
+    build = lambda p: qc.hea_circuit(n, np.asarray(p).reshape(layers, n, 2), layers)
+    ops = build(theta)
+    idx = np.array([-1] * len(ops))
+    k = 0
+    for i, o in enumerate(ops):
+        if o.name in ("RY", "RZ"):
+            idx[i] = k
+            k += 1
+    ham = qc.random_hamiltonian(n, 6, 62)
+    s = State(n, dtype)
+    e, g_ops = s.adjoint(ops, ham)
+    back = s.to_numpy()
+    s.close()
+    g = np.zeros(theta.size)
+    np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
+    ref = O.param_shift_grad(build, theta.ravel(), ham, n)
+    assert abs(e - O.energy(build, theta.ravel(), ham, n)) <= GTOL[dtype] * len(ham)
+    assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham)
+    assert np.all(g_ops[idx < 0] == 0)
+    assert abs(back[0] - 1) < (1e-10 if dtype == "c128" else 1e-4)
+
+
 def test_autograd_function():
     import torch
     from paper_1807_07914_amd.autograd import expectation
