@@ -939,7 +939,7 @@ static int pipe_grid() {
 
 template <typename T, int TB, int RB, bool FULL, int MINWG>
 static hipError_t launch_pass(cpx<T>* psi, const int32_t* prog_dev, uint64_t ntiles, bool pipe, hipStream_t st) {
-  if constexpr (!FULL && TB == TileCfg<T>::TBMAX) {
+  if constexpr (TB == TileCfg<T>::TBMAX && (!FULL || sizeof(T) == 4)) {
     const int resident = pipe ? pipe_grid<T, TB, RB, FULL, MINWG>() : 0;
     if (resident > 0) {
       const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, (uint64_t)resident);
@@ -963,10 +963,11 @@ hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const i
   const uint64_t ntiles = 1ull << (n - t);
   const bool small = t <= TB - 1;
   const int tbits = small ? TB - 1 : TB;
-  // The pipelined kernel holds the next tile in registers: lean passes over
+  // The pipelined kernel holds the next tile in registers: passes over
   // full-size tiles only (for half-size tiles the extra registers and LDS
-  // cost a workgroup per compute unit, more than the overlap gains).
-  const bool pipe = !full && !small && t - c <= tbits - SwzBits<T>::B;
+  // cost a workgroup per compute unit, more than the overlap gains); full
+  // body only for complex64 (the complex128 one would spill heavily).
+  const bool pipe = (!full || sizeof(T) == 4) && !small && t - c <= tbits - SwzBits<T>::B;
   if (small) {
     if (full) return launch_pass<T, TB - 1, RB, true, 2>(psi, prog_dev, ntiles, pipe, st);
     return launch_pass<T, TB - 1, RB, false, 3>(psi, prog_dev, ntiles, pipe, st);
