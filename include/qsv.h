@@ -214,6 +214,54 @@ qsv_status qsv_batch_info(const qsv_batch* b, int* tile_qubits, int* total_passe
                           int64_t* scratch_bytes);
 qsv_status qsv_batch_free(qsv_batch* b);
 
+/* ---------------------------------------------------------------------
+ * Matrix-product-state path (paper section III, gate application on an MPS
+ * by contraction and SVD; section IV.B, the MPS visitor with its cutoff on
+ * singular values).  The register is n site tensors B_l (chi_l x 2 x chi_l+1,
+ * complex128, right-canonical) and n+1 bond vectors of Schmidt coefficients
+ * on the device; qubit q lives at site q.  A two-qubit gate on adjacent sites
+ * contracts the two site tensors, applies the 4x4 gate, scales the rows by the
+ * left bond's coefficients and splits the (2 chi_l) x (2 chi_l+2) block by a
+ * one-sided Jacobi SVD in LDS; singular values not above `cutoff`, or not above
+ * 1e-12 of the largest, are dropped, and at most chi_max are kept (at least
+ * one); the state is not renormalised.  Gates on distant qubits are routed by
+ * SWAP updates that bring the higher qubit next to the lower one and back.
+ * One-qubit gates are folded into the next two-qubit update of their qubit.
+ * Updates on disjoint sites run in one launch (one workgroup each).
+ * ------------------------------------------------------------------- */
+#define QSV_MPS_MAX_CHI 32      /* largest bond dimension (LDS-resident SVD) */
+#define QSV_MPS_MAX_QUBITS 1024
+
+typedef struct qsv_mps qsv_mps;
+
+/* |0...0> on n_qubits (1..QSV_MPS_MAX_QUBITS); chi_max in 1..QSV_MPS_MAX_CHI;
+ * cutoff >= 0 (the paper's default is 1e-4).  hip_stream NULL = the null
+ * stream.  The library owns all device memory.  Errors: QSV_ERR_ARG,
+ * QSV_ERR_OOM. */
+qsv_status qsv_mps_alloc(int n_qubits, int chi_max, double cutoff, void* hip_stream,
+                         qsv_mps** out);
+qsv_status qsv_mps_free(qsv_mps* m);
+
+/* Apply one- and two-qubit instructions in program order (qsv_op as for
+ * states; QSV_MAT with nq <= 2).  Stream-ordered; host arrays are read during
+ * the call.  Errors: QSV_ERR_ARG (qubits, parameters), QSV_ERR_UNSUPPORTED
+ * (instructions on three or more qubits). */
+qsv_status qsv_mps_apply_circuit(qsv_mps* m, const qsv_op* ops, int n_ops);
+
+/* Amplitudes <x|psi> for host indices idx[0..count) (bit q = qubit q), written
+ * as complex128 pairs to the host array out (2 * count doubles).  Synchronous.
+ * Errors: QSV_ERR_ARG (index >= 2^n), QSV_ERR_UNSUPPORTED (n > 63). */
+qsv_status qsv_mps_amplitudes(qsv_mps* m, const uint64_t* idx, int64_t count, double* out);
+
+/* Bond dimensions (host, n+1 ints; dims[0] = dims[n] = 1) and, if schmidt is
+ * not NULL, the Schmidt coefficients (host, (n+1) rows of QSV_MPS_MAX_CHI
+ * doubles; row b holds dims[b] values in descending order, zeros after).
+ * Synchronous. */
+qsv_status qsv_mps_bonds(qsv_mps* m, int32_t* dims, double* schmidt);
+
+/* Two-site updates and kernel launches issued since allocation. */
+qsv_status qsv_mps_info(const qsv_mps* m, int64_t* bond_updates, int64_t* launches);
+
 /* Copy the raw amplitudes to / from host memory (bytes must equal the state
  * size).  Synchronous. */
 qsv_status qsv_copy_to_host(qsv_state* s, void* dst, size_t bytes);

@@ -98,6 +98,13 @@ class MPS:
             v = w.reshape(-1, w.shape[2])
         return v[:, 0] * self.lam[self.n][0]
 
+    def amplitude(self, x: int) -> complex:
+        """One amplitude <x|psi>, site by site (for registers too wide to expand)."""
+        v = np.ones(1, dtype=np.complex128)
+        for l in range(self.n):
+            v = (v * self.lam[l]) @ self.gam[l][:, (x >> l) & 1, :]
+        return complex(v[0] * self.lam[self.n][0])
+
     def bond_dims(self) -> list:
         return [len(x) for x in self.lam]
 

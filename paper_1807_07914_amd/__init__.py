@@ -5,4 +5,4 @@ blocks on the matrix cores, FP64 reductions and sampling -- lives in the HIP
 library ``libqsv.so`` behind the C ABI of ``include/qsv.h``; this package is
 its thin ctypes binding (``qsv``).
 """
-from .qsv import Batch, OpList, QsvError, State, lib, pauli_masks, plan_info  # noqa: F401
+from .qsv import MPS, Batch, OpList, QsvError, State, lib, pauli_masks, plan_info  # noqa: F401

@@ -19,7 +19,7 @@ OUT = os.path.join(PKG, "libqsv.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "gates.hip", "reduce.hip", "circuit.hip", "tile.hip", "dense_mfma.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "gates.hip", "reduce.hip", "circuit.hip", "tile.hip", "dense_mfma.hip", "adjoint.hip", "mps.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = [

@@ -85,6 +85,12 @@ def lib():
         "qsv_batch_info": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                            ctypes.POINTER(ctypes.c_int64)],
         "qsv_batch_free": [vp],
+        "qsv_mps_alloc": [i32, i32, ctypes.c_double, vp, ctypes.POINTER(vp)],
+        "qsv_mps_free": [vp],
+        "qsv_mps_apply_circuit": [vp, ctypes.POINTER(QsvOp), i32],
+        "qsv_mps_amplitudes": [vp, u64p, ctypes.c_int64, dp],
+        "qsv_mps_bonds": [vp, ip, dp],
+        "qsv_mps_info": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -360,6 +366,73 @@ class Batch:
         if getattr(self, "_h", None) is not None:
             check(lib().qsv_batch_free(self._h))
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+MPS_MAX_CHI = 32
+
+
+class MPS:
+    """Matrix-product state on the GPU (complex128 site tensors, Schmidt
+    coefficients per bond); qubit q lives at site q.  Gates are applied by
+    two-site SVD updates with the given cutoff and bond-dimension cap."""
+
+    def __init__(self, n: int, chi_max: int = MPS_MAX_CHI, cutoff: float = 1e-4, stream=None):
+        self.n = n
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(stream.cuda_stream if stream is not None else None)
+        check(lib().qsv_mps_alloc(int(n), int(chi_max), float(cutoff), st, ctypes.byref(h)))
+        self._h = h
+
+    def apply_circuit(self, ops) -> None:
+        ol = ops if isinstance(ops, OpList) else OpList(ops)
+        check(lib().qsv_mps_apply_circuit(self._h, ol.arr, ol.n))
+
+    def amplitudes(self, idx) -> np.ndarray:
+        idx = np.ascontiguousarray(idx, dtype=np.uint64)
+        out = np.zeros(2 * max(1, idx.size), dtype=np.float64)
+        check(lib().qsv_mps_amplitudes(self._h, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                       idx.size, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out[: 2 * idx.size].view(np.complex128)
+
+    def to_numpy(self) -> np.ndarray:
+        return self.amplitudes(np.arange(1 << self.n, dtype=np.uint64))
+
+    def bonds(self):
+        """(dims list of n+1, Schmidt coefficients per bond as a list of arrays)."""
+        dims = np.zeros(self.n + 1, dtype=np.int32)
+        lam = np.zeros((self.n + 1) * MPS_MAX_CHI, dtype=np.float64)
+        check(lib().qsv_mps_bonds(self._h, _ptr_i32(dims),
+                                  lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        lam = lam.reshape(self.n + 1, MPS_MAX_CHI)
+        return [int(d) for d in dims], [lam[b, : dims[b]].copy() for b in range(self.n + 1)]
+
+    def info(self) -> dict:
+        b, l = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().qsv_mps_info(self._h, ctypes.byref(b), ctypes.byref(l)))
+        return {"bond_updates": b.value, "launches": l.value}
+
+    def memory_bytes(self) -> int:
+        """Bytes of the site tensors and Schmidt vectors at their current
+        dimensions (complex128 / float64), the paper's O(n chi^2) measure."""
+        d, _ = self.bonds()
+        return sum(d[l] * 2 * d[l + 1] * 16 for l in range(self.n)) + sum(8 * x for x in d)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            check(lib().qsv_mps_free(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
     def __del__(self):
         try:

@@ -55,6 +55,8 @@ def test_exact_mps_equals_state_vector(n, seed):
     psi = O.run(ops, n)
     assert np.abs(m.to_state() - psi).max() < 1e-10
     assert m.discarded < 1e-20
+    for x in (0, (1 << n) - 1, (0x5A5A5 % (1 << n))):
+        assert abs(m.amplitude(x) - psi[x]) < 1e-10
 
 
 @pytest.mark.parametrize("n,seed", [(6, 11), (8, 12)])
