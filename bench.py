@@ -206,6 +206,55 @@ def bench_h2_sweep(np, torch, qc, qsv, reps=20):
             "max_abs_dev_closed_form": float(np.abs(e - cf).max())}
 
 
+def bench_mps(np, torch, qc, qsv, circuits=10, chi_max=32, cutoff=1e-4):
+    """The paper's MPS experiment (section V.A) on the GPU MPS path: the
+    random-round family for n = 5..85 step 5 and rounds 2..10 step 2, ten
+    seeded circuits each, bond cap chi_max and the paper's cutoff 1e-4.
+    Reports time per circuit, the largest bond dimension and the MPS memory
+    (mean and standard deviation over the circuits, the paper's measure), and
+    for n <= 20 the fidelity of the first circuit against the complex128
+    state-vector path."""
+    out = {}
+    m = qsv.MPS(10, chi_max, cutoff)    # warm-up (code objects, buffers)
+    m.apply_circuit(qc.paper_rounds(10, 2, 1))
+    m.bonds()
+    m.close()
+    for n in range(5, 86, 5):
+        row = {}
+        for rounds in range(2, 11, 2):
+            ts, chis, mems, upd = [], [], [], 0
+            fid = None
+            for c in range(circuits):
+                lst = qc.paper_rounds(n, rounds, 5000 + 100 * n + 10 * rounds + c)
+                ops = qsv.OpList(lst)
+                m = qsv.MPS(n, chi_max, cutoff)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                m.apply_circuit(ops)
+                dims, _ = m.bonds()          # synchronises
+                ts.append(time.perf_counter() - t0)
+                chis.append(max(dims))
+                mems.append(m.memory_bytes())
+                upd += m.info()["bond_updates"]
+                if c == 0 and n <= 20:
+                    amp = m.amplitudes(np.arange(1 << n, dtype=np.uint64))
+                    s = qsv.State(n, "c128")
+                    s.apply_circuit(ops)
+                    psi = s.to_numpy()
+                    s.close()
+                    fid = float(abs(np.vdot(psi, amp)) ** 2 / np.vdot(amp, amp).real)
+                m.close()
+            t = float(np.sum(ts))
+            row[rounds] = {"ms_per_circuit": t / circuits * 1e3, "gates_per_s": len(lst) * circuits / t,
+                           "us_per_bond_update": t / upd * 1e6,
+                           "max_chi_mean": float(np.mean(chis)), "max_chi_std": float(np.std(chis)),
+                           "memory_bytes_mean": float(np.mean(mems)), "memory_bytes_std": float(np.std(mems))}
+            if fid is not None:
+                row[rounds]["fidelity_vs_sv"] = fid
+        out[n] = row
+    return out
+
+
 def bench_adjoint(np, torch, qc, qsv, reps=3):
     """24 qubits, 6 layers of RX, RY, RZ + CZ ring (432 parameters, seed
     1005), H = sum Z_i Z_{i+1} + 0.7 sum X_i, complex64 with FP64 reductions:
@@ -262,7 +311,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-ref", action="store_true",
                     help="run one plain 2 GiB device copy first (reference for HBM counters)")
-    ap.add_argument("--only", choices=["c4_batched", "c5_adjoint", "f1_paper_rounds", "f2_h2_sweep"],
+    ap.add_argument("--mps-circuits", type=int, default=10, help="circuits per cell of the MPS grid")
+    ap.add_argument("--only", choices=["c4_batched", "c5_adjoint", "f1_paper_rounds", "f2_h2_sweep",
+                                       "f3_mps"],
                     help="run one of the extra workloads alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -279,8 +330,10 @@ def main():
 
     if args.only:
         fn = {"c4_batched": bench_batched, "c5_adjoint": bench_adjoint,
-              "f1_paper_rounds": bench_rounds, "f2_h2_sweep": bench_h2_sweep}[args.only]
-        print(json.dumps({args.only: fn(np, torch, qc, qsv)}))
+              "f1_paper_rounds": bench_rounds, "f2_h2_sweep": bench_h2_sweep,
+              "f3_mps": bench_mps}[args.only]
+        kw = {"circuits": args.mps_circuits} if args.only == "f3_mps" else {}
+        print(json.dumps({args.only: fn(np, torch, qc, qsv, **kw)}))
         return
 
     n = args.n
@@ -413,6 +466,7 @@ def main():
         ex["c5_adjoint"] = bench_adjoint(np, torch, qc, qsv)
         ex["f1_paper_rounds"] = bench_rounds(np, torch, qc, qsv)
         ex["f2_h2_sweep"] = bench_h2_sweep(np, torch, qc, qsv)
+        ex["f3_mps"] = bench_mps(np, torch, qc, qsv, circuits=args.mps_circuits)
         result["extras"] = ex
 
     if not args.no_cpu_baseline:

@@ -45,8 +45,8 @@ namespace {
 constexpr int kChi = QSV_MPS_MAX_CHI;         // slot stride and largest bond
 constexpr int kRows = 2 * kChi;               // largest row / column count of M
 constexpr int kSlot = 2 * kChi * kChi;        // complex entries per site slot
-constexpr int kThreads = 256;
-constexpr int kPairLanes = 8;                 // lanes per Jacobi row pair
+constexpr int kThreads = 512;
+constexpr int kPairLanes = 16;                // lanes per Jacobi row pair (one DPP row)
 constexpr int kMaxSweeps = 48;                // bound on Jacobi sweeps
 constexpr double kOrthTol = 1e-14;            // rotate while |<r_p,r_q>| > tol |r_p||r_q|
 constexpr double kZeroRel = 1e-12;            // numerical-zero rule for singular values
@@ -54,6 +54,7 @@ constexpr double kZeroRow = 1e-13;            // rows below this fraction of |M|
 constexpr uint32_t kMpsMagic = 0x5053514du;   // "MQSP"
 
 static_assert(kThreads / kPairLanes >= kRows / 2, "one lane group per row pair");
+static_assert(kPairLanes == 16, "the DPP group sum spans one 16-lane row");
 
 struct z2 {
   double x, y;
@@ -76,6 +77,19 @@ __device__ __forceinline__ void zfma(z2& acc, z2 a, z2 b) {
 __device__ __forceinline__ void zfmac(z2& acc, z2 a, z2 b) {
   acc.x = fma(a.x, b.x, fma(a.y, b.y, acc.x));
   acc.y = fma(a.y, b.x, fma(-a.x, b.y, acc.y));
+}
+
+// Sum over each 16-lane DPP row (xor 1, xor 2, half-row mirror, row
+// mirror).  Every lane of a row ends with the bitwise-same value: at each
+// stage the two partners add the same two numbers, in either order.
+template <int CTRL>
+__device__ __forceinline__ double dpp_sum(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return v + __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double group_sum(double v) {
+  return dpp_sum<0x140>(dpp_sum<0x141>(dpp_sum<0x4E>(dpp_sum<0xB1>(v))));
 }
 
 __global__ void k_mps_init(z2* __restrict__ sites, double* __restrict__ lam, int* __restrict__ dims,
@@ -176,7 +190,6 @@ __global__ __launch_bounds__(kThreads) void k_mps_bond(z2* __restrict__ sites, d
   // one-sided Jacobi on the rows of M, round-robin pairing: in each step
   // every row belongs to one pair; a sweep of R-1 steps meets every pair once
   const int grp = tid / kPairLanes, lane = tid % kPairLanes;
-  const int lead = (tid & 63) & ~(kPairLanes - 1);
   const int npairs = R / 2;
   for (int sw = 0; sw < kMaxSweeps; ++sw) {
     for (int step = 0; step < R - 1; ++step) {
@@ -199,25 +212,24 @@ __global__ __launch_bounds__(kThreads) void k_mps_bond(z2* __restrict__ sites, d
           gr = fma(x.x, y.x, fma(x.y, y.y, gr));
           gi = fma(x.y, y.x, fma(-x.x, y.y, gi));
         }
-        for (int off = 1; off < kPairLanes; off <<= 1) {
-          al += __shfl_xor(al, off);
-          be += __shfl_xor(be, off);
-          gr += __shfl_xor(gr, off);
-          gi += __shfl_xor(gi, off);
-        }
-        // the group's lead lane decides for all eight (bitwise-equal inputs)
-        al = __shfl(al, lead);
-        be = __shfl(be, lead);
-        gr = __shfl(gr, lead);
-        gi = __shfl(gi, lead);
-        const double ag = hypot(gr, gi);
+        // all lanes of the pair get bitwise-equal sums, so they take one decision
+        al = group_sum(al);
+        be = group_sum(be);
+        gr = group_sum(gr);
+        gi = group_sum(gi);
+        const double ag = sqrt(gr * gr + gi * gi);
         if (al >= zthr && be >= zthr && ag > kOrthTol * sqrt(al * be)) {
           // y = e^{i arg g} r_q makes the pair's Gram matrix real; then the
-          // symmetric 2x2 Jacobi rotation with the smaller angle
-          const double tau = (be - al) / (2.0 * ag);
-          const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + hypot(1.0, tau));
+          // symmetric 2x2 Jacobi rotation with the smaller angle.  The row
+          // floor zthr bounds |tau| by about 5e39, so tau^2 cannot overflow.
+          // The test is relative only: kept rows of small norm must still come
+          // out orthonormal to the others, or the right site loses its
+          // canonical form.
+          const double iag = 1.0 / ag;
+          const double tau = 0.5 * (be - al) * iag;
+          const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          const double er = gr / ag, ei = gi / ag;
+          const double er = gr * iag, ei = gi * iag;
           for (int c = lane; c < L; c += kPairLanes) {
             const z2 x = rp[c], y0 = rq[c];
             const z2 y{er * y0.x - ei * y0.y, er * y0.y + ei * y0.x};
