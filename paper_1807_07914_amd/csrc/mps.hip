@@ -204,9 +204,15 @@ __global__ __launch_bounds__(kThreads) void k_mps_bond(z2* __restrict__ sites, d
         }
         z2* rp = mr + p * kRows;
         z2* rq = mr + q * kRows;
+        constexpr int kCols = kRows / kPairLanes;   // columns per lane at most
+        z2 xs[kCols], ys[kCols];
         double al = 0, be = 0, gr = 0, gi = 0;   // |r_p|^2, |r_q|^2, sum r_p conj(r_q)
-        for (int c = lane; c < L; c += kPairLanes) {
-          const z2 x = rp[c], y = rq[c];
+#pragma unroll
+        for (int k = 0; k < kCols; ++k) {
+          const int c = lane + k * kPairLanes;
+          xs[k] = c < L ? rp[c] : z2{0, 0};
+          ys[k] = c < L ? rq[c] : z2{0, 0};
+          const z2 x = xs[k], y = ys[k];
           al = fma(x.x, x.x, fma(x.y, x.y, al));
           be = fma(y.x, y.x, fma(y.y, y.y, be));
           gr = fma(x.x, y.x, fma(x.y, y.y, gr));
@@ -217,24 +223,28 @@ __global__ __launch_bounds__(kThreads) void k_mps_bond(z2* __restrict__ sites, d
         be = group_sum(be);
         gr = group_sum(gr);
         gi = group_sum(gi);
-        const double ag = sqrt(gr * gr + gi * gi);
-        if (al >= zthr && be >= zthr && ag > kOrthTol * sqrt(al * be)) {
+        const double g2 = gr * gr + gi * gi;
+        if (al >= zthr && be >= zthr && g2 > kOrthTol * kOrthTol * al * be) {
           // y = e^{i arg g} r_q makes the pair's Gram matrix real; then the
           // symmetric 2x2 Jacobi rotation with the smaller angle.  The row
           // floor zthr bounds |tau| by about 5e39, so tau^2 cannot overflow.
           // The test is relative only: kept rows of small norm must still come
           // out orthonormal to the others, or the right site loses its
           // canonical form.
-          const double iag = 1.0 / ag;
+          const double iag = rsqrt(g2);
           const double tau = 0.5 * (be - al) * iag;
           const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          const double cs = rsqrt(1.0 + t * t), sn = cs * t;
           const double er = gr * iag, ei = gi * iag;
-          for (int c = lane; c < L; c += kPairLanes) {
-            const z2 x = rp[c], y0 = rq[c];
-            const z2 y{er * y0.x - ei * y0.y, er * y0.y + ei * y0.x};
-            rp[c] = z2{cs * x.x - sn * y.x, cs * x.y - sn * y.y};
-            rq[c] = z2{sn * x.x + cs * y.x, sn * x.y + cs * y.y};
+#pragma unroll
+          for (int k = 0; k < kCols; ++k) {
+            const int c = lane + k * kPairLanes;
+            if (c < L) {
+              const z2 x = xs[k], y0 = ys[k];
+              const z2 y{er * y0.x - ei * y0.y, er * y0.y + ei * y0.x};
+              rp[c] = z2{cs * x.x - sn * y.x, cs * x.y - sn * y.y};
+              rq[c] = z2{sn * x.x + cs * y.x, sn * x.y + cs * y.y};
+            }
           }
           if (lane == 0) flags[sw] = 1;
         }
