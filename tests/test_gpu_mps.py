@@ -132,6 +132,13 @@ def test_edge_cases_and_errors():
     with pytest.raises(QsvError):
         m.amplitudes(np.array([1 << n], dtype=np.uint64))
     m.close()
+    # a Haar gate and its inverse: rounding-level singular values are dropped
+    U = qc.haar_unitary(2, np.random.default_rng(5))
+    m = gpu_mps([qc.op("U", 2, 3, mat=U), qc.op("U", 3, 2, mat=U.conj().T)], 5, 4, 0.0)
+    dims, _ = m.bonds()
+    m.close()
+    swapped = M.run([qc.op("U", 2, 3, mat=U), qc.op("U", 3, 2, mat=U.conj().T)], 5, cutoff=0.0)
+    assert dims == swapped.bond_dims()
     for bad in ((0, 4, 0.0), (4, 0, 0.0), (4, 33, 0.0), (4, 4, -1.0)):
         with pytest.raises(QsvError):
             MPS(*bad)

@@ -6,7 +6,8 @@ mathematics fix, independent of the oracle's own arithmetic:
   random circuits with adjacent and distant two-qubit gates in both operand
   orders;
 - the bond matrices are the Schmidt coefficients: the singular values of the
-  state vector reshaped across each cut (a library SVD of a different matrix);
+  state vector reshaped across each cut (a library SVD of a different matrix),
+  and without truncation the bond dimension is that cut's numerical rank;
 - GHZ and product states have the bond dimensions and coefficients of their
   closed forms, and the Bell pair its amplitudes;
 - the paper's two-round random circuits keep chi <= 4 at any width
@@ -66,9 +67,9 @@ def test_bond_matrices_are_schmidt_coefficients(n, seed):
     psi = O.run(ops, n)
     for b in range(1, n):
         ref = schmidt_of_state(psi, n, b)
+        assert m.bond_dims()[b] == len(ref), b   # numerical zeros are not kept
         got = np.sort(m.lam[b])[::-1]
-        got = got[got > 1e-10 * got[0]]
-        assert len(got) == len(ref) and np.abs(got - ref).max() < 1e-10, b
+        assert np.abs(got - ref).max() < 1e-10, b
 
 
 def test_ghz_product_and_bell():
@@ -79,6 +80,11 @@ def test_ghz_product_and_bell():
         assert np.allclose(m.lam[b], [2 ** -0.5] * 2)
     p = M.run([qc.op("H", q) for q in range(n)] + [qc.op("RY", q, params=(0.3 * q,)) for q in range(n)], n)
     assert p.bond_dims() == [1] * (n + 1)
+    # a Haar gate and its inverse leave rounding-level singular values, which
+    # the numerical-zero rule drops even with no cutoff: back to chi = 1
+    U = qc.haar_unitary(2, np.random.default_rng(5))
+    back = M.run([qc.op("U", 2, 3, mat=U), qc.op("U", 2, 3, mat=U.conj().T)], 5, cutoff=0.0)
+    assert back.bond_dims() == [1] * 6
     bell = M.run([qc.op("H", 0), qc.op("CNOT", 0, 1)], 2).to_state()
     assert np.allclose(bell, [2 ** -0.5, 0, 0, 2 ** -0.5])
     # control on the higher qubit, routed past two sites
