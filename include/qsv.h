@@ -240,6 +240,8 @@ typedef struct qsv_mps qsv_mps;
  * QSV_ERR_OOM. */
 qsv_status qsv_mps_alloc(int n_qubits, int chi_max, double cutoff, void* hip_stream,
                          qsv_mps** out);
+/* Release an MPS (waits for its stream); NULL is accepted and ignored.
+ * Errors: QSV_ERR_STATE (freed or foreign handle). */
 qsv_status qsv_mps_free(qsv_mps* m);
 
 /* Apply one- and two-qubit instructions in program order (qsv_op as for

@@ -493,6 +493,7 @@ extern "C" qsv_status qsv_mps_alloc(int n_qubits, int chi_max, double cutoff, vo
 }
 
 extern "C" qsv_status qsv_mps_free(qsv_mps* m) {
+  if (!m) return QSV_OK;
   if (!mps_live(m)) return fail(QSV_ERR_STATE, "invalid or freed MPS handle");
   {
     std::lock_guard<std::mutex> lk(g_mps_mu);

@@ -42,6 +42,28 @@ def test_foreign_handles_rejected():
     assert b"invalid" in L.qsv_last_error()
 
 
+@pytest.mark.parametrize("n,chi,cut", [(0, 4, 1e-4), (1025, 4, 1e-4), (8, 0, 1e-4), (8, 33, 1e-4),
+                                       (8, 4, -1.0), (8, 4, float("nan")), (8, 4, float("inf"))])
+def test_mps_alloc_rejects_bad_arguments(n, chi, cut):
+    # argument checks come before any device call, so they run without a GPU
+    h = ctypes.c_void_p()
+    rc = qsv.lib().qsv_mps_alloc(n, chi, cut, None, ctypes.byref(h))
+    assert rc == qsv.QSV_ERR_ARG and h.value is None
+    assert qsv.lib().qsv_last_error()
+
+
+def test_mps_foreign_handles_rejected():
+    L = qsv.lib()
+    bogus = ctypes.c_void_p(0x1234)
+    assert L.qsv_mps_free(None) == qsv.QSV_OK
+    assert L.qsv_mps_free(bogus) == qsv.QSV_ERR_STATE
+    assert L.qsv_mps_apply_circuit(bogus, None, 0) == qsv.QSV_ERR_STATE
+    dims = (ctypes.c_int32 * 4)()
+    assert L.qsv_mps_bonds(bogus, dims, None) == qsv.QSV_ERR_STATE
+    assert L.qsv_mps_info(bogus, None, None) == qsv.QSV_ERR_STATE
+    assert b"invalid" in L.qsv_last_error()
+
+
 def test_pauli_mask_encoding():
     x, z, c = qsv.pauli_masks([(0.5, (("X", 0), ("Y", 2), ("Z", 3)))])
     assert int(x[0]) == 0b0101 and int(z[0]) == 0b1100 and c[0] == 0.5
