@@ -428,15 +428,15 @@ MpsJob make_job(int site, const cd* g, int dim) {
 
 const cd kSwap[16] = {1, 0, 0, 0, 0, 0, 1, 0, 0, 1, 0, 0, 0, 0, 0, 1};
 
-qsv_status check_mps_op(const qsv_mps* m, const qsv_op& o) {
+qsv_status check_mps_op(int n, const qsv_op& o) {
   const int k = o.gate == QSV_MAT ? o.nq : gate_arity(o.gate);
   if (o.gate != QSV_MAT && k < 0) return fail(QSV_ERR_ARG, "unknown gate id " + std::to_string(o.gate));
   if (o.gate == QSV_MAT && (o.nq < 1 || o.nq > QSV_MAX_K)) return fail(QSV_ERR_ARG, "matrix op: nq out of range");
   if (o.nq != k) return fail(QSV_ERR_ARG, "wrong qubit count for gate");
   if (k > 2) return fail(QSV_ERR_UNSUPPORTED, "the MPS path takes one- and two-qubit instructions");
   for (int j = 0; j < k; ++j)
-    if (o.q[j] < 0 || o.q[j] >= m->n)
-      return fail(QSV_ERR_ARG, "qubit " + std::to_string(o.q[j]) + " outside [0, " + std::to_string(m->n) + ")");
+    if (o.q[j] < 0 || o.q[j] >= n)
+      return fail(QSV_ERR_ARG, "qubit " + std::to_string(o.q[j]) + " outside [0, " + std::to_string(n) + ")");
   if (k == 2 && o.q[0] == o.q[1]) return fail(QSV_ERR_ARG, "duplicate qubit " + std::to_string(o.q[0]));
   if (o.gate == QSV_MAT) {
     if (!o.mat) return fail(QSV_ERR_ARG, "matrix op without matrix");
@@ -448,6 +448,83 @@ qsv_status check_mps_op(const qsv_mps* m, const qsv_op& o) {
       if (!std::isfinite(o.p[e])) return fail(QSV_ERR_ARG, "non-finite gate parameter");
   }
   return QSV_OK;
+}
+
+// Host encoder: the job list and its launches for one instruction list (ops
+// already validated).  launches hold (offset, count); a negative count marks
+// the one-site launch.
+void encode_mps(int n, const qsv_op* ops, int n_ops, std::vector<MpsJob>& jobs,
+                std::vector<std::pair<size_t, int>>& launches) {
+  // pending one-qubit products per qubit (folded into the next two-site update)
+  std::vector<std::array<cd, 4>> pend(n, std::array<cd, 4>{1, 0, 0, 1});
+  std::vector<char> has(n, 0);
+  // two-site jobs with their ASAP level: a job waits for the last job on either site
+  std::vector<std::pair<int, MpsJob>> bond;
+  std::vector<int> last(n, 0);
+  auto push = [&](int site, const cd* g) {
+    const int lv = std::max(last[site], last[site + 1]) + 1;
+    last[site] = last[site + 1] = lv;
+    bond.emplace_back(lv, make_job(site, g, 4));
+  };
+  cd mat[64];
+  for (int i = 0; i < n_ops; ++i) {
+    const qsv_op& o = ops[i];
+    const int k = o.gate == QSV_MAT ? o.nq : gate_arity(o.gate);
+    if (o.gate == QSV_MAT) {
+      for (int e = 0; e < (1 << (2 * k)); ++e) mat[e] = cd(o.mat[2 * e], o.mat[2 * e + 1]);
+    } else {
+      gate_matrix(o.gate, o.p, mat);
+    }
+    if (k == 1) {
+      const int q = o.q[0];
+      const std::array<cd, 4> P = pend[q];
+      for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) pend[q][2 * r + c] = mat[2 * r] * P[c] + mat[2 * r + 1] * P[2 + c];
+      has[q] = 1;
+      continue;
+    }
+    const int q0 = o.q[0], q1 = o.q[1];
+    // G (K), K = pending one-qubit products, index bit(q0) + 2 bit(q1)
+    cd G[16];
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) {
+        cd acc = 0;
+        for (int x = 0; x < 4; ++x)
+          acc += mat[4 * r + x] * pend[q0][2 * (x & 1) + (c & 1)] * pend[q1][2 * (x >> 1) + (c >> 1)];
+        G[4 * r + c] = acc;
+      }
+    pend[q0] = pend[q1] = std::array<cd, 4>{1, 0, 0, 1};
+    has[q0] = has[q1] = 0;
+    const int lo = std::min(q0, q1), hi = std::max(q0, q1);
+    if (q0 != lo) {
+      cd Gs[16];
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) Gs[4 * r + c] = G[4 * swap_bits(r) + swap_bits(c)];
+      std::copy(Gs, Gs + 16, G);
+    }
+    for (int b = hi - 1; b > lo; --b) push(b, kSwap);   // bring qubit hi next to lo
+    push(lo, G);
+    for (int b = lo + 1; b < hi; ++b) push(b, kSwap);   // and back
+  }
+  std::stable_sort(bond.begin(), bond.end(),
+                   [](const std::pair<int, MpsJob>& a, const std::pair<int, MpsJob>& b) { return a.first < b.first; });
+  // launches: one per level of two-site jobs, then one for the leftover one-site gates
+  jobs.clear();
+  launches.clear();
+  for (size_t i = 0; i < bond.size();) {
+    size_t j = i;
+    while (j < bond.size() && bond[j].first == bond[i].first) jobs.push_back(bond[j++].second);
+    launches.emplace_back(i, (int)(j - i));
+    i = j;
+  }
+  const size_t n_bond = jobs.size();
+  int n_site = 0;
+  for (int q = 0; q < n; ++q)
+    if (has[q]) {
+      jobs.push_back(make_job(q, pend[q].data(), 2));
+      ++n_site;
+    }
+  if (n_site) launches.emplace_back(n_bond, -n_site);
 }
 
 }  // namespace
@@ -510,81 +587,12 @@ extern "C" qsv_status qsv_mps_apply_circuit(qsv_mps* m, const qsv_op* ops, int n
   QSV_MPS_ENTER(m);
   if (n_ops < 0 || (n_ops > 0 && !ops)) return fail(QSV_ERR_ARG, "bad op list");
   for (int i = 0; i < n_ops; ++i) {
-    qsv_status st = check_mps_op(m, ops[i]);
+    qsv_status st = check_mps_op(m->n, ops[i]);
     if (st) return fail(st, "op " + std::to_string(i) + ": " + get_error());
   }
-  const int n = m->n;
-  // pending one-qubit products per qubit (folded into the next two-site update)
-  std::vector<std::array<cd, 4>> pend(n, std::array<cd, 4>{1, 0, 0, 1});
-  std::vector<char> has(n, 0);
-  // two-site jobs with their ASAP level: a job waits for the last job on either site
-  std::vector<std::pair<int, MpsJob>> bond;
-  std::vector<int> last(n, 0);
-  auto push = [&](int site, const cd* g) {
-    const int lv = std::max(last[site], last[site + 1]) + 1;
-    last[site] = last[site + 1] = lv;
-    bond.emplace_back(lv, make_job(site, g, 4));
-  };
-  cd mat[64];
-  for (int i = 0; i < n_ops; ++i) {
-    const qsv_op& o = ops[i];
-    const int k = o.gate == QSV_MAT ? o.nq : gate_arity(o.gate);
-    if (o.gate == QSV_MAT) {
-      for (int e = 0; e < (1 << (2 * k)); ++e) mat[e] = cd(o.mat[2 * e], o.mat[2 * e + 1]);
-    } else {
-      gate_matrix(o.gate, o.p, mat);
-    }
-    if (k == 1) {
-      const int q = o.q[0];
-      const std::array<cd, 4> P = pend[q];
-      for (int r = 0; r < 2; ++r)
-        for (int c = 0; c < 2; ++c) pend[q][2 * r + c] = mat[2 * r] * P[c] + mat[2 * r + 1] * P[2 + c];
-      has[q] = 1;
-      continue;
-    }
-    const int q0 = o.q[0], q1 = o.q[1];
-    // G (K), K = pending one-qubit products, index bit(q0) + 2 bit(q1)
-    cd G[16];
-    for (int r = 0; r < 4; ++r)
-      for (int c = 0; c < 4; ++c) {
-        cd acc = 0;
-        for (int x = 0; x < 4; ++x)
-          acc += mat[4 * r + x] * pend[q0][2 * (x & 1) + (c & 1)] * pend[q1][2 * (x >> 1) + (c >> 1)];
-        G[4 * r + c] = acc;
-      }
-    pend[q0] = pend[q1] = std::array<cd, 4>{1, 0, 0, 1};
-    has[q0] = has[q1] = 0;
-    const int lo = std::min(q0, q1), hi = std::max(q0, q1);
-    if (q0 != lo) {
-      cd Gs[16];
-      for (int r = 0; r < 4; ++r)
-        for (int c = 0; c < 4; ++c) Gs[4 * r + c] = G[4 * swap_bits(r) + swap_bits(c)];
-      std::copy(Gs, Gs + 16, G);
-    }
-    for (int b = hi - 1; b > lo; --b) push(b, kSwap);   // bring qubit hi next to lo
-    push(lo, G);
-    for (int b = lo + 1; b < hi; ++b) push(b, kSwap);   // and back
-  }
-  std::stable_sort(bond.begin(), bond.end(),
-                   [](const std::pair<int, MpsJob>& a, const std::pair<int, MpsJob>& b) { return a.first < b.first; });
-  // launches: one per level of two-site jobs, then one for the leftover one-site gates
   std::vector<std::pair<size_t, int>> launches;   // (offset, count), negative count = one-site
   QSV_HIP(hipStreamSynchronize(m->stream));       // the previous upload's source is reused
-  m->jobs_host.clear();
-  for (size_t i = 0; i < bond.size();) {
-    size_t j = i;
-    while (j < bond.size() && bond[j].first == bond[i].first) m->jobs_host.push_back(bond[j++].second);
-    launches.emplace_back(i, (int)(j - i));
-    i = j;
-  }
-  const size_t n_bond = m->jobs_host.size();
-  int n_site = 0;
-  for (int q = 0; q < n; ++q)
-    if (has[q]) {
-      m->jobs_host.push_back(make_job(q, pend[q].data(), 2));
-      ++n_site;
-    }
-  if (n_site) launches.emplace_back(n_bond, -n_site);
+  encode_mps(m->n, ops, n_ops, m->jobs_host, launches);
   if (m->jobs_host.empty()) return QSV_OK;
   if (m->jobs_host.size() > m->jobs_cap) {
     (void)hipFree(m->jobs_dev);
@@ -659,5 +667,34 @@ extern "C" qsv_status qsv_mps_info(const qsv_mps* m, int64_t* bond_updates, int6
   if (!mps_live(m)) return fail(QSV_ERR_STATE, "invalid or freed MPS handle");
   if (bond_updates) *bond_updates = m->bond_updates;
   if (launches) *launches = m->launches;
+  return QSV_OK;
+}
+
+// Host-only debug export (not in the public header): the encoder's job list
+// for an instruction list, for the CPU emulator in the tests.  Arrays are
+// filled when their capacity suffices; the counts are always reported.
+// gates holds 32 doubles per job (a 4x4, or a 2x2 in the first 8, complex).
+extern "C" qsv_status qsv_debug_mps_program(int n, const qsv_op* ops, int n_ops, int32_t* sites,
+                                            double* gates, int64_t cap_jobs, int64_t* n_jobs,
+                                            int32_t* launch_counts, int64_t cap_launches,
+                                            int64_t* n_launches) {
+  if (n < 1 || n > QSV_MPS_MAX_QUBITS) return fail(QSV_ERR_ARG, "n out of range");
+  if (n_ops < 0 || (n_ops > 0 && !ops)) return fail(QSV_ERR_ARG, "bad op list");
+  for (int i = 0; i < n_ops; ++i) {
+    qsv_status st = check_mps_op(n, ops[i]);
+    if (st) return st;
+  }
+  std::vector<MpsJob> jobs;
+  std::vector<std::pair<size_t, int>> launches;
+  encode_mps(n, ops, n_ops, jobs, launches);
+  if (n_jobs) *n_jobs = (int64_t)jobs.size();
+  if (n_launches) *n_launches = (int64_t)launches.size();
+  if (sites && gates && (int64_t)jobs.size() <= cap_jobs)
+    for (size_t j = 0; j < jobs.size(); ++j) {
+      sites[j] = jobs[j].site;
+      std::memcpy(gates + 32 * j, jobs[j].g, sizeof(jobs[j].g));
+    }
+  if (launch_counts && (int64_t)launches.size() <= cap_launches)
+    for (size_t j = 0; j < launches.size(); ++j) launch_counts[j] = launches[j].second;
   return QSV_OK;
 }
