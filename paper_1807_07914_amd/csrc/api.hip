@@ -759,8 +759,11 @@ static qsv_status build_adjoint_programs(int n, const qsv_op* in_ops, int n_in, 
       for (int r = 0; r < D; ++r)
         for (int cc = 0; cc < D; ++cc)
           if (r != cc && inv[k][r * D + cc] != cd(0.0)) dg = false;
-      isdiag[k] = dg;
       const bool rot = o.gate == QSV_RX || o.gate == QSV_RY || o.gate == QSV_RZ;
+      // a rotation commutes with what its generator commutes with, whatever
+      // its angle: RX(0) / RY(0) are the identity but their gradient terms
+      // must stay on the same side of every CZ on their qubit
+      isdiag[k] = rot ? (o.gate == QSV_RZ) : dg;
       bool sg = dg && !rot && o.nq <= 2;
       for (int e = 0; sg && e < D; ++e) {
         const cd want = (e == D - 1) ? cd(-1.0) : cd(1.0);

@@ -95,6 +95,12 @@ void expand_cnots(const qsv_op* ops, int n_ops, std::vector<qsv_op>& out, std::v
   }
 }
 
+// Parameterised gates are classified by their gate, not by the value of the
+// angle: RX / RY stay two-by-two rotations and RZ / CPHASE diagonal phases
+// at every angle, 0 included.  A plan (and a batch's captured structure)
+// then does not change when only the angles do, and the adjoint sweep keeps
+// a slot for every rotation (a rotation at angle 0 is the identity, but its
+// derivative is not zero).
 static POp classify(const qsv_op& o) {
   POp p;
   p.nq = o.nq;
@@ -103,6 +109,22 @@ static POp classify(const qsv_op& o) {
     p.qmask |= 1ull << o.q[j];
   }
   cd m[16];
+  const double zero[3] = {0, 0, 0};
+  if (o.gate == QSV_RX || o.gate == QSV_RY || o.gate == QSV_RZ || o.gate == QSV_CPHASE) {
+    gate_matrix(o.gate, o.p ? o.p : zero, m);
+    if (o.gate == QSV_CPHASE) {
+      p.kind = PK_D2;
+      for (int i = 0; i < 4; ++i) p.m[i] = m[i * 5];
+    } else if (o.gate == QSV_RZ) {
+      p.kind = PK_D1;
+      p.m[0] = m[0];
+      p.m[1] = m[3];
+    } else {
+      p.kind = PK_U1;
+      for (int i = 0; i < 4; ++i) p.m[i] = m[i];
+    }
+    return p;
+  }
   if (o.gate == QSV_MAT) {
     if (o.nq > 2) {
       p.kind = PK_OTHER;
@@ -111,7 +133,6 @@ static POp classify(const qsv_op& o) {
     const int D = 1 << o.nq;
     for (int i = 0; i < D * D; ++i) m[i] = cd(o.mat[2 * i], o.mat[2 * i + 1]);
   } else {
-    const double zero[3] = {0, 0, 0};
     gate_matrix(o.gate, o.p ? o.p : zero, m);
   }
   if (o.nq == 1) {
@@ -1478,6 +1499,7 @@ struct qsv_batch {
   std::vector<uint64_t> op_sig;            // per-op class and qubits (update checks)
   std::vector<uint32_t> key;               // exact structure of all circuits
   int tile_bits = 0;
+  bool full = false;  // the captured kernel has the full tile body
   int grid = 0;
   int njobs = 0;
   int total_passes = 0;
@@ -1648,6 +1670,7 @@ static qsv_status batch_build(qsv_batch* b, int t) {
   QSV_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   bool full = false;  // the lean kernel unless some pass needs the full tile body
   for (int64_t off : b->passoff) full = full || program_needs_full<T>(b->hprog.data() + off);
+  b->full = full;
   hipError_t e = launch_batch<T>(static_cast<cpx<T>*>(b->d_scratch), b->d_prog, b->d_passoff,
                                  b->d_jobs, b->d_z, b->d_c, b->d_out, b->d_counter, b->njobs,
                                  b->grid, full, b->stream);
@@ -1840,6 +1863,16 @@ qsv_status qsv_batch_update(qsv_batch* b, const qsv_op* ops) {
   b->ops = keep;
   if (!st && (b->passoff.size() != npass || b->hprog.size() > b->prog_cap))
     st = fail(QSV_ERR_STATE, "the updated programs do not fit the batch's program buffer");
+  if (!st && !b->full) {  // the captured lean kernel cannot run full-body steps
+    bool need = false;
+    for (int64_t off : b->passoff)
+      need = need || (b->dt == QSV_C64 ? program_needs_full<float>(b->hprog.data() + off)
+                                       : program_needs_full<double>(b->hprog.data() + off));
+    if (need)
+      st = fail(QSV_ERR_STATE,
+                "the updated matrices need the full tile body, which the captured launch lacks; "
+                "create a new batch");
+  }
   if (st) {  // the batch keeps its previous programs
     b->hprog.swap(keep_prog);
     b->passoff.swap(keep_off);

@@ -151,3 +151,47 @@ def test_cnot_ladders(dtype):
             idx[i] = k
             k += 1
     check(n, dtype, build, theta.ravel(), qc.random_hamiltonian(n, 6, 62), idx)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,layers", [(6, 2), (14, 2)])
+def test_zero_angles(dtype, n, layers):
+    # a rotation at angle 0 is the identity but still has a gradient: the
+    # sweep must keep its slot, and must not move a CZ past RX(0) / RY(0)
+    # (their generators do not commute with CZ); every third angle is 0, and
+    # the all-zero start of a VQE run is checked as well
+    params, ham = qc.gradient_workload(n, layers, 900 + n)
+    idx = qc.rot_ring_param_index(n, layers)
+    build = lambda p: qc.rot_ring_ansatz(n, p, layers)
+    some = params.copy()
+    some[::3] = 0.0
+    check(n, dtype, build, some, ham, idx)
+    check(n, dtype, build, np.zeros_like(params), ham, idx)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_zero_angle_between_czs(dtype):
+    # RX(0) and RY(0) between two CZs on their qubit: joining the CZs into one
+    # sign run would move the second CZ past the rotation's generator
+    n = 7
+    theta = np.array([0.0, 0.0, 0.4, 0.0, 0.0, 0.0])
+
+    def build(p):
+        ops = [qc.op("H", q) for q in range(n)]
+        ops += [qc.op("CZ", 0, 1), qc.op("RX", 1, params=(p[0],)), qc.op("CZ", 1, 2),
+                qc.op("RY", 2, params=(p[1],)), qc.op("CZ", 2, 0), qc.op("RZ", 0, params=(p[2],)),
+                qc.op("CZ", 0, 3), qc.op("RY", 3, params=(p[3],)), qc.op("CZ", 3, 4),
+                qc.op("RX", 4, params=(p[4],)), qc.op("CZ", 4, 5), qc.op("RZ", 5, params=(p[5],)),
+                qc.op("CZ", 5, 6)]
+        return ops
+
+    ops = build(theta)
+    idx = np.array([-1] * len(ops))
+    k = 0
+    for i, o in enumerate(ops):
+        if o.name in ("RX", "RY", "RZ"):
+            idx[i] = k
+            k += 1
+    ham = [(1.0, (("X", 1),)), (0.8, (("Y", 2),)), (0.6, (("X", 3), ("Z", 4))), (0.5, (("Y", 4),)),
+           (0.3, (("Z", 0), ("Z", 6)))]
+    check(n, dtype, build, theta, ham, idx)

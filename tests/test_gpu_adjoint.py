@@ -213,3 +213,27 @@ def test_gradient_workload_24q_against_golden():
     assert abs(e - gold["energy"]) < 1e-4
     for k, ref in zip(gold["indices"], gold["grad"]):
         assert abs(g[k] - ref) < 2e-4, (k, g[k], ref)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [6, 14])
+def test_adjoint_at_zero_angles(dtype, n):
+    # a rotation at angle 0 is the identity but has a nonzero derivative; the
+    # usual VQE start has every angle at 0.  14 qubits reach past one sweep
+    # tile, so CZs meet rotations on qubits outside a pass's tile too
+    layers = 2
+    params, ham = qc.gradient_workload(n, layers, 950 + n)
+    build = lambda p: qc.rot_ring_ansatz(n, p, layers)
+    idx = qc.rot_ring_param_index(n, layers)
+    some = params.copy()
+    some[::3] = 0.0
+    for theta in (some, np.zeros_like(params)):
+        s = State(n, dtype)
+        e, g_ops = s.adjoint(build(theta), ham)
+        s.close()
+        g = np.zeros(theta.size)
+        np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
+        ref = O.param_shift_grad(build, theta, ham, n)
+        assert np.abs(ref).max() > 0.1  # the zero-angle derivatives are not trivially 0
+        assert abs(e - O.energy(build, theta, ham, n)) <= GTOL[dtype] * len(ham)
+        assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham), np.abs(g - ref).max()

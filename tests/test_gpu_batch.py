@@ -105,6 +105,26 @@ def test_batch_update_and_general_z_strings():
     assert np.abs(e2 - ref2).max() < 1e-10
 
 
+@pytest.mark.parametrize("dtype,tol", [("c64", 1e-4), ("c128", 1e-10)])
+def test_batch_update_from_zero_angles(dtype, tol):
+    # a sweep starts at angle 0: a batch built there accepts random angles and
+    # the way back, each checked against the oracle
+    widths = [5, 9, 13, 16]
+    hams = [qc.zz_chain(w) for w in widths]
+    rng = np.random.default_rng(5)
+    zero = [qc.hea_circuit(w, np.zeros((4, w, 2)), layers=4) for w in widths]
+    rand = [qc.hea_circuit(w, rng.uniform(0, 2 * np.pi, (4, w, 2)), layers=4) for w in widths]
+    bt = Batch(zero, widths, hams, dtype=dtype)
+    try:
+        for circs in (zero, rand, zero):
+            bt.update(circs)
+            e = bt.run()
+            ref = np.array([O.expval(O.run(c, w), h) for c, w, h in zip(circs, widths, hams)])
+            assert np.abs(e - ref).max() <= tol, np.abs(e - ref).max()
+    finally:
+        bt.close()
+
+
 def test_batch_rejects_unsupported():
     from paper_1807_07914_amd import QsvError
     with pytest.raises(ValueError):

@@ -159,3 +159,23 @@ def test_givens_split_counts():
     words, steps = E.program(n, "c64", rz)
     counts = E.op_counts(words, steps, "c64")
     assert counts.get("ROT", 0) == 0 and counts.get("RAWD", 0) == 0
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_zero_angles_keep_the_plan(dtype):
+    # rotations are planned by gate, not by angle value: a batch built at
+    # angle 0 (the usual start of a parameter sweep) has the passes of one
+    # built at random angles, so an update between them keeps its structure;
+    # the zero-angle programs still give the oracle's states
+    widths = [6, 11, 14]
+    rng = np.random.default_rng(77)
+    zero = [qc.hea_circuit(w, np.zeros((3, w, 2)), layers=3) for w in widths]
+    rand = [qc.hea_circuit(w, rng.uniform(0, 2 * np.pi, (3, w, 2)), layers=3) for w in widths]
+    w0, p0, j0 = E.batch_program(dtype, zero, widths, 0)
+    w1, p1, j1 = E.batch_program(dtype, rand, widths, 0)
+    assert len(p0) == len(p1) and np.array_equal(j0, j1)
+    for i, w in enumerate(widths):
+        job = next(j for j in j0 if int(j[0]) == w)
+        got = E.emulate_batch_job(dtype, w0, p0, job)
+        ref = O.run(zero[i], w)
+        assert np.abs(got - ref).max() <= TOL[dtype]
