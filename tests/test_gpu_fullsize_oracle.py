@@ -118,8 +118,10 @@ def test_headline_28_qubits_against_the_oracle():
     ops = qc.random_brickwork(n, 40, qc.SEEDS["c2"])
     say("28q oracle run: %d gates on %d threads" % (len(ops), O.num_threads()))
     t0 = time.time()
-    ref = O.run(ops, n)
-    say("28q oracle done in %.1f s" % (time.time() - t0))
+    ref = O.zero_state(n)
+    for a in range(0, len(ops), 200):  # progress lines while the oracle runs
+        O.run(ops[a:a + 200], n, psi=ref)
+        say("28q oracle: %d gates, %.1f s" % (min(a + 200, len(ops)), time.time() - t0))
     for dtype, mode in (("c64", "fused"), ("c128", "fused"), ("c64", "pergate")):
         say("28q", dtype, mode)
         got = run_gpu(n, dtype, ops, mode=mode)
