@@ -68,7 +68,11 @@ typedef enum {
   QSV_CZ = 13, QSV_CPHASE = 14, QSV_SWAP = 15, QSV_MAT = 16
 } qsv_gate;
 
-#define QSV_MAX_QUBITS 40   /* largest register accepted by qsv_alloc_state */
+/* Largest registers accepted by qsv_alloc_state: 2^35 complex64 or 2^34
+ * complex128 amplitudes (256 GiB, what one GPU's HBM holds); every launch
+ * stays within the dispatch limits up to these sizes. */
+#define QSV_MAX_QUBITS 35
+#define QSV_MAX_QUBITS_C128 34
 #define QSV_MAX_K 6         /* widest explicit matrix (2^6 x 2^6) */
 
 /* Opaque handle of one device-resident state vector. */

@@ -49,7 +49,7 @@ struct HTerms {
 template <typename T>
 __global__ __launch_bounds__(kAB) void k_hpsi(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ lam,
                                               uint64_t N, HTerms h, int accumulate) {
-  const uint64_t j = (uint64_t)blockIdx.x * kAB + threadIdx.x;
+  const uint64_t j = block_index() * kAB + threadIdx.x;
   if (j >= N) return;
   double ar = 0.0, ai = 0.0;
   if (accumulate) {
@@ -655,7 +655,7 @@ template <typename T>
 hipError_t launch_hpsi(const cpx<T>* psi, cpx<T>* lam, int n, const uint64_t* x, const uint64_t* z,
                        const double* wr, const double* wi, int nt, hipStream_t st) {
   const uint64_t N = 1ull << n;
-  const unsigned grid = (unsigned)((N + kAB - 1) / kAB);
+  const dim3 grid = grid_for((N + kAB - 1) / kAB);
   for (int t0 = 0; t0 < nt || t0 == 0; t0 += kMaxHTerms) {
     HTerms h{};
     h.nt = nt - t0 < kMaxHTerms ? nt - t0 : kMaxHTerms;
@@ -665,7 +665,7 @@ hipError_t launch_hpsi(const cpx<T>* psi, cpx<T>* lam, int n, const uint64_t* x,
       h.wr[t] = wr[t0 + t];
       h.wi[t] = wi[t0 + t];
     }
-    hipLaunchKernelGGL(k_hpsi<T>, dim3(grid), dim3(kAB), 0, st, psi, lam, N, h, t0 > 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_hpsi<T>, grid, dim3(kAB), 0, st, psi, lam, N, h, t0 > 0 ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (nt == 0) break;

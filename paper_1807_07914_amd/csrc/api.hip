@@ -322,9 +322,9 @@ qsv_status qsv_alloc_state(int n_qubits, qsv_dtype dtype, void* ext_dev_ptr, siz
                            void* stream, qsv_state** out) {
   if (!out) return fail(QSV_ERR_ARG, "out is NULL");
   *out = nullptr;
-  if (n_qubits < 1 || n_qubits > QSV_MAX_QUBITS)
-    return fail(QSV_ERR_ARG, "n_qubits must be in [1, " + std::to_string(QSV_MAX_QUBITS) + "]");
   if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_ERR_ARG, "dtype must be QSV_C64 or QSV_C128");
+  if (n_qubits < 1 || n_qubits > max_qubits(dtype))
+    return fail(QSV_ERR_ARG, "n_qubits must be in [1, " + std::to_string(max_qubits(dtype)) + "] for this dtype");
   qsv_state* s = new (std::nothrow) qsv_state();
   if (!s) return fail(QSV_ERR_OOM, "host allocation failed");
   s->n = n_qubits;
@@ -463,8 +463,8 @@ qsv_status qsv_apply_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const q
 
 qsv_status qsv_plan_info(int n_qubits, qsv_dtype dtype, const qsv_op* ops, int n_ops,
                          int tile_qubits, int* passes, int* separate_ops) {
-  if (n_qubits < 1 || n_qubits > QSV_MAX_QUBITS) return fail(QSV_ERR_ARG, "n_qubits out of range");
   if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_ERR_ARG, "bad dtype");
+  if (n_qubits < 1 || n_qubits > max_qubits(dtype)) return fail(QSV_ERR_ARG, "n_qubits out of range");
   if (n_ops < 0 || (n_ops > 0 && !ops)) return fail(QSV_ERR_ARG, "bad op list");
   qsv_state tmp;  // shape only: never registered, never touches the device
   tmp.n = n_qubits;
@@ -485,8 +485,8 @@ qsv_status qsv_debug_plan_program(int n_qubits, qsv_dtype dtype, const qsv_op* o
                                   int tile_qubits, int32_t* words, int64_t cap_words,
                                   int64_t* n_words, int64_t* steps, int64_t cap_steps,
                                   int64_t* n_steps) {
-  if (n_qubits < 1 || n_qubits > QSV_MAX_QUBITS) return fail(QSV_ERR_ARG, "n_qubits out of range");
   if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_ERR_ARG, "bad dtype");
+  if (n_qubits < 1 || n_qubits > max_qubits(dtype)) return fail(QSV_ERR_ARG, "n_qubits out of range");
   if (n_ops < 0 || (n_ops > 0 && !ops)) return fail(QSV_ERR_ARG, "bad op list");
   qsv_state tmp;
   tmp.n = n_qubits;
@@ -1340,8 +1340,8 @@ extern "C" {
 qsv_status qsv_debug_adjoint_program(int n_qubits, qsv_dtype dtype, const qsv_op* ops, int n_ops,
                                      int32_t* words, int64_t cap_words, int64_t* n_words, int64_t* steps,
                                      int64_t cap_steps, int64_t* n_steps) {
-  if (n_qubits < 1 || n_qubits > QSV_MAX_QUBITS) return fail(QSV_ERR_ARG, "n_qubits out of range");
   if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_ERR_ARG, "bad dtype");
+  if (n_qubits < 1 || n_qubits > max_qubits(dtype)) return fail(QSV_ERR_ARG, "n_qubits out of range");
   if (n_ops < 0 || (n_ops > 0 && !ops)) return fail(QSV_ERR_ARG, "bad op list");
   qsv_state tmp;
   tmp.n = n_qubits;

@@ -1320,6 +1320,9 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
   if (t > TBMAX) return fail(QSV_ERR_UNSUPPORTED, "tile_qubits exceeds the LDS tile capacity");
   if (t < RB) return fail(QSV_ERR_ARG, "tile_qubits smaller than the register group");
   if (t > n) t = n;
+  // one workgroup per tile in the non-persistent tile kernel: the launch's
+  // work-items (2^(n-t) * 256) must stay below 2^32
+  if (n - t > 23) return fail(QSV_ERR_UNSUPPORTED, "tile_qubits too small for this register (over 2^23 tiles)");
   int c = sizeof(T) == 4 ? 5 : 4;  // 256-byte contiguous segments
   if (c > t) c = t;
   if (t - c > TBMAX - 4) return fail(QSV_ERR_UNSUPPORTED, "tile shape exceeds segment table");

@@ -57,6 +57,24 @@ __device__ __forceinline__ uint64_t insert00(uint64_t x, int a, int b) {
   return insert0(insert0(x, a), b);
 }
 
+// Launch geometry of a one-dimensional range of nblk workgroups.  A dispatch
+// keeps the global size of each grid dimension below 2^32 work-items, which
+// a one-dimensional grid over the largest states HBM holds (2^35 complex64
+// amplitudes, one work-item per 16-byte vector) would pass.  Ranges longer
+// than kGridX workgroups therefore take a second grid dimension; kernels
+// read their position in the range with block_index() and return when it is
+// at or past nblk (the last row of a two-dimensional grid may overhang).
+constexpr uint32_t kGridX = 1u << 16;
+
+inline dim3 grid_for(uint64_t nblk) {
+  if (nblk <= kGridX) return dim3((unsigned)(nblk ? nblk : 1), 1, 1);
+  return dim3(kGridX, (unsigned)((nblk + kGridX - 1) / kGridX), 1);
+}
+
+__device__ __forceinline__ uint64_t block_index() {
+  return (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
+}
+
 template <typename T>
 __device__ __forceinline__ void apply2(const M2<T>& U, cpx<T>& a0, cpx<T>& a1) {
   cpx<T> y0 = cfma(U.m[1], a1, cmul(U.m[0], a0));

@@ -11,13 +11,40 @@
 namespace qsv {
 
 constexpr int kBlock = 256;
+constexpr int kGate1Items = 2, kDiag1Items = 4, kGate2Items = 2, kPerm2Items = 4;
+
+// Workgroups each per-gate launch covers (grid_for turns them into a grid).
+template <typename T>
+static uint64_t init_blocks(uint64_t N) {
+  return (N / VecInfo<T>::A + kBlock - 1) / kBlock;
+}
+template <typename T>
+static uint64_t gate1_blocks(int n) {
+  const uint64_t items = (1ull << n) / (2 * VecInfo<T>::A);
+  return (items + kBlock * kGate1Items - 1) / (kBlock * kGate1Items);
+}
+template <typename T>
+static uint64_t diag1_blocks(int n) {
+  const uint64_t nvec = (1ull << n) / VecInfo<T>::A;
+  return (nvec + kBlock * kDiag1Items - 1) / (kBlock * kDiag1Items);
+}
+static uint64_t gate2_blocks(int n) {
+  return ((1ull << n) / 4 + kBlock * kGate2Items - 1) / (kBlock * kGate2Items);
+}
+static uint64_t perm2_blocks(int n) {
+  return ((1ull << n) / 4 + kBlock * kPerm2Items - 1) / (kBlock * kPerm2Items);
+}
+static uint64_t dense_blocks(int n, int k) {
+  const uint64_t G = kBlock >> k;
+  return (((1ull << n) >> k) + G - 1) / G;
+}
 
 // ---------------------------------------------------------------- init
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init_basis(vec16<T>* __restrict__ v, uint64_t nvec,
                                                         uint64_t x) {
   constexpr int A = VecInfo<T>::A;
-  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint64_t i = block_index() * kBlock + threadIdx.x;
   if (i >= nvec) return;
   vec16<T> z;
 #pragma unroll
@@ -32,8 +59,7 @@ template <typename T>
 hipError_t launch_init_basis(cpx<T>* psi, uint64_t N, uint64_t x, hipStream_t st) {
   constexpr int A = VecInfo<T>::A;
   const uint64_t nvec = N / A;
-  const uint64_t grid = (nvec + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_init_basis<T>, dim3((unsigned)grid), dim3(kBlock), 0, st,
+  hipLaunchKernelGGL(k_init_basis<T>, grid_for(init_blocks<T>(N)), dim3(kBlock), 0, st,
                      reinterpret_cast<vec16<T>*>(psi), nvec, x);
   return hipGetLastError();
 }
@@ -47,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_gate1(vec16<T>* __restrict__ v, uint
                                                    M2<T> U) {
   constexpr int A = VecInfo<T>::A;
   constexpr int LA = VecInfo<T>::LOG_A;
-  const uint64_t base = (uint64_t)blockIdx.x * (kBlock * IPT) + threadIdx.x;
+  const uint64_t base = block_index() * (kBlock * IPT) + threadIdx.x;
   vec16<T> lo[IPT], hi[IPT];
   uint64_t il[IPT], ih[IPT];
 #pragma unroll
@@ -97,15 +123,14 @@ __global__ void k_gate1_scalar(cpx<T>* __restrict__ psi, uint64_t pairs, int q, 
 template <typename T>
 hipError_t launch_gate1(cpx<T>* psi, int n, int q, const M2<T>& U, hipStream_t st) {
   constexpr int A = VecInfo<T>::A;
-  constexpr int IPT = 2;
+  constexpr int IPT = kGate1Items;
   const uint64_t N = 1ull << n;
   if (N < 4 * (uint64_t)A) {
     hipLaunchKernelGGL(k_gate1_scalar<T>, dim3(1), dim3(64), 0, st, psi, N / 2, q, U);
     return hipGetLastError();
   }
   const uint64_t items = N / (2 * A);
-  const uint64_t grid = (items + kBlock * IPT - 1) / (kBlock * IPT);
-  hipLaunchKernelGGL((k_gate1<T, IPT>), dim3((unsigned)grid), dim3(kBlock), 0, st,
+  hipLaunchKernelGGL((k_gate1<T, IPT>), grid_for(gate1_blocks<T>(n)), dim3(kBlock), 0, st,
                      reinterpret_cast<vec16<T>*>(psi), items, q, U);
   return hipGetLastError();
 }
@@ -115,7 +140,7 @@ template <typename T, int IPT>
 __global__ __launch_bounds__(kBlock) void k_diag1(vec16<T>* __restrict__ v, uint64_t nvec, int q,
                                                    cpx<T> d0, cpx<T> d1) {
   constexpr int A = VecInfo<T>::A;
-  const uint64_t base = (uint64_t)blockIdx.x * (kBlock * IPT) + threadIdx.x;
+  const uint64_t base = block_index() * (kBlock * IPT) + threadIdx.x;
   vec16<T> x[IPT];
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
@@ -138,10 +163,9 @@ __global__ __launch_bounds__(kBlock) void k_diag1(vec16<T>* __restrict__ v, uint
 template <typename T>
 hipError_t launch_diag1(cpx<T>* psi, int n, int q, cpx<T> d0, cpx<T> d1, hipStream_t st) {
   constexpr int A = VecInfo<T>::A;
-  constexpr int IPT = 4;
+  constexpr int IPT = kDiag1Items;
   const uint64_t nvec = (1ull << n) / A;
-  const uint64_t grid = (nvec + kBlock * IPT - 1) / (kBlock * IPT);
-  hipLaunchKernelGGL((k_diag1<T, IPT>), dim3((unsigned)grid), dim3(kBlock), 0, st,
+  hipLaunchKernelGGL((k_diag1<T, IPT>), grid_for(diag1_blocks<T>(n)), dim3(kBlock), 0, st,
                      reinterpret_cast<vec16<T>*>(psi), nvec, q, d0, d1);
   return hipGetLastError();
 }
@@ -152,7 +176,7 @@ hipError_t launch_diag1(cpx<T>* psi, int n, int q, cpx<T> d0, cpx<T> d1, hipStre
 template <typename T, int IPT>
 __global__ __launch_bounds__(kBlock) void k_gate2(cpx<T>* __restrict__ psi, uint64_t items, int qa,
                                                    int qb, M4<T> U) {
-  const uint64_t base = (uint64_t)blockIdx.x * (kBlock * IPT) + threadIdx.x;
+  const uint64_t base = block_index() * (kBlock * IPT) + threadIdx.x;
   const uint64_t A = 1ull << qa, B = 1ull << qb;
   cpx<T> x[IPT][4];
   uint64_t i0[IPT];
@@ -189,10 +213,9 @@ __global__ __launch_bounds__(kBlock) void k_gate2(cpx<T>* __restrict__ psi, uint
 
 template <typename T>
 hipError_t launch_gate2(cpx<T>* psi, int n, int qa, int qb, const M4<T>& U, hipStream_t st) {
-  constexpr int IPT = 2;
+  constexpr int IPT = kGate2Items;
   const uint64_t items = (1ull << n) / 4;
-  const uint64_t grid = (items + kBlock * IPT - 1) / (kBlock * IPT);
-  hipLaunchKernelGGL((k_gate2<T, IPT>), dim3((unsigned)grid), dim3(kBlock), 0, st, psi, items, qa,
+  hipLaunchKernelGGL((k_gate2<T, IPT>), grid_for(gate2_blocks(n)), dim3(kBlock), 0, st, psi, items, qa,
                      qb, U);
   return hipGetLastError();
 }
@@ -202,7 +225,7 @@ hipError_t launch_gate2(cpx<T>* psi, int n, int qa, int qb, const M4<T>& U, hipS
 template <typename T, int MODE, int IPT>
 __global__ __launch_bounds__(kBlock) void k_perm2(cpx<T>* __restrict__ psi, uint64_t items, int lo,
                                                    int hi, uint64_t P, uint64_t Q, cpx<T> ph) {
-  const uint64_t base = (uint64_t)blockIdx.x * (kBlock * IPT) + threadIdx.x;
+  const uint64_t base = block_index() * (kBlock * IPT) + threadIdx.x;
   cpx<T> a[IPT], b[IPT];
   uint64_t ia[IPT], ib[IPT];
 #pragma unroll
@@ -232,11 +255,10 @@ __global__ __launch_bounds__(kBlock) void k_perm2(cpx<T>* __restrict__ psi, uint
 template <typename T, int MODE>
 static hipError_t launch_perm2(cpx<T>* psi, int n, int a, int b, uint64_t P, uint64_t Q, cpx<T> ph,
                                hipStream_t st) {
-  constexpr int IPT = 4;
+  constexpr int IPT = kPerm2Items;
   const int lo = a < b ? a : b, hi = a < b ? b : a;
   const uint64_t items = (1ull << n) / 4;
-  const uint64_t grid = (items + kBlock * IPT - 1) / (kBlock * IPT);
-  hipLaunchKernelGGL((k_perm2<T, MODE, IPT>), dim3((unsigned)grid), dim3(kBlock), 0, st, psi, items,
+  hipLaunchKernelGGL((k_perm2<T, MODE, IPT>), grid_for(perm2_blocks(n)), dim3(kBlock), 0, st, psi, items,
                      lo, hi, P, Q, ph);
   return hipGetLastError();
 }
@@ -284,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_dense(cpx<T>* __restrict__ psi, int 
       sUt[c * D + r] = mat[e];
     }
   const int gl = threadIdx.x / D, r = threadIdx.x % D;
-  const uint64_t g = (uint64_t)blockIdx.x * G + gl;
+  const uint64_t g = block_index() * G + gl;
   const bool ok = g < groups;
   uint64_t b = g;
   for (int j = 0; j < k; ++j) b = insert0(b, ql.sorted[j]);
@@ -318,10 +340,9 @@ hipError_t launch_dense(cpx<T>* psi, int n, int k, const int* qubits, const cpx<
   const int D = 1 << k;
   const int G = kBlock / D;
   const uint64_t groups = (1ull << n) >> k;
-  const uint64_t grid = (groups + G - 1) / G;
   const int lds_mat = (size_t)D * D * sizeof(cpx<T>) <= 32768;
   const size_t shmem = (size_t)((lds_mat ? D * D : 0) + G * D) * sizeof(cpx<T>);
-  hipLaunchKernelGGL(k_dense<T>, dim3((unsigned)grid), dim3(kBlock), shmem, st, psi, k, ql, mat_dev,
+  hipLaunchKernelGGL(k_dense<T>, grid_for(dense_blocks(n, k)), dim3(kBlock), shmem, st, psi, k, ql, mat_dev,
                      groups, lds_mat);
   return hipGetLastError();
 }
@@ -340,3 +361,30 @@ QSV_INST(float)
 QSV_INST(double)
 
 }  // namespace qsv
+
+// Host-only debug export (not in the public header): the launch shapes the
+// per-gate kernels use on an n-qubit register, one row of four int64 per
+// kernel (grid x, grid y, threads per workgroup, workgroups the range needs)
+// in the order init, 1-qubit, diagonal, 2-qubit, permutation / phase, dense
+// k = 1..6 (11 rows), for checks of the geometry on the CPU.
+extern "C" qsv_status qsv_debug_launch_dims(qsv_dtype dt, int n, int64_t* out) {
+  using namespace qsv;
+  if (dt != QSV_C64 && dt != QSV_C128) return fail(QSV_ERR_ARG, "bad dtype");
+  if (n < 7 || n > max_qubits(dt)) return fail(QSV_ERR_ARG, "n out of range");
+  if (!out) return fail(QSV_ERR_ARG, "out is NULL");
+  const bool f = dt == QSV_C64;
+  const uint64_t nb[11] = {f ? init_blocks<float>(1ull << n) : init_blocks<double>(1ull << n),
+                           f ? gate1_blocks<float>(n) : gate1_blocks<double>(n),
+                           f ? diag1_blocks<float>(n) : diag1_blocks<double>(n),
+                           gate2_blocks(n), perm2_blocks(n),
+                           dense_blocks(n, 1), dense_blocks(n, 2), dense_blocks(n, 3),
+                           dense_blocks(n, 4), dense_blocks(n, 5), dense_blocks(n, 6)};
+  for (int r = 0; r < 11; ++r) {
+    const dim3 g = grid_for(nb[r]);
+    out[4 * r] = g.x;
+    out[4 * r + 1] = g.y;
+    out[4 * r + 2] = kBlock;
+    out[4 * r + 3] = (int64_t)nb[r];
+  }
+  return QSV_OK;
+}

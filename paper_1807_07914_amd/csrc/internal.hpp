@@ -29,7 +29,7 @@ qsv_status hip_fail(hipError_t e, const char* where);
     if (e_ != hipSuccess) return ::qsv::hip_fail(e_, #call); \
   } while (0)
 
-struct Plan;  // fused-execution plan (planner.cpp)
+inline int max_qubits(qsv_dtype dt) { return dt == QSV_C128 ? QSV_MAX_QUBITS_C128 : QSV_MAX_QUBITS; }
 
 }  // namespace qsv
 

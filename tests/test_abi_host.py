@@ -3,6 +3,8 @@ every function include/qsv.h declares, has the documented struct layout, and
 rejects invalid arguments before touching the device."""
 import ctypes
 
+import numpy as np
+
 import pytest
 
 from paper_1807_07914_amd import qsv
@@ -69,3 +71,28 @@ def test_pauli_mask_encoding():
     assert int(x[0]) == 0b0101 and int(z[0]) == 0b1100 and c[0] == 0.5
     with pytest.raises(ValueError):
         qsv.pauli_masks([(1.0, (("X", 1), ("Z", 1)))])
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_launch_geometry_up_to_the_largest_register(dtype):
+    # every per-gate launch covers its whole range with a grid whose
+    # dimensions each stay below 2^32 work-items, up to 2^35 complex64 /
+    # 2^34 complex128 amplitudes (256 GiB); larger registers are refused
+    import ctypes
+    from paper_1807_07914_amd import qsv
+    fn = qsv.lib().qsv_debug_launch_dims
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+    dt = qsv.QSV_C64 if dtype == "c64" else qsv.QSV_C128
+    top = 35 if dtype == "c64" else 34
+    out = np.zeros(44, dtype=np.int64)
+    ptr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    for n in range(7, top + 1):
+        assert fn(dt, n, ptr) == 0
+        rows = out.reshape(11, 4)
+        for gx, gy, threads, need in rows:
+            assert 1 <= gx <= 65536 and gy >= 1
+            assert gx * threads < 2 ** 32 and gy < 2 ** 32
+            assert gx * gy >= need and gx * (gy - 1) < need  # covers the range, one row at most overhangs
+    assert fn(dt, top + 1, ptr) != 0
+    assert qsv.lib().qsv_alloc_state(top + 1, dt, None, 0, None, ctypes.byref(ctypes.c_void_p())) != 0
