@@ -112,13 +112,19 @@ qsv_status qsv_alloc_state(int n_qubits, qsv_dtype dtype, void* ext_dev_ptr, siz
                            void* stream, qsv_state** out);
 
 /* Release the handle (and the memory, if the library owns it).  Waits for
- * the state's pending work.  NULL is accepted and ignored. */
+ * the state's pending work.  NULL is accepted and ignored.  Paper section
+ * III: the host manages the buffers of the virtual machine.
+ * Errors: QSV_ERR_STATE (freed or foreign handle), QSV_ERR_HIP. */
 qsv_status qsv_free_state(qsv_state* s);
 
-/* Query n, dtype and the device pointer of the amplitudes. */
+/* Query n, dtype and the device pointer of the amplitudes (any output may
+ * be NULL).  Plumbing: no passage of the paper.  Errors: QSV_ERR_STATE. */
 qsv_status qsv_state_info(const qsv_state* s, int* n_qubits, int* dtype, void** dev_ptr);
 
-/* Reset to the basis state |x> (x < 2^n). */
+/* Reset to the computational basis state |x> (x < 2^n), stream-ordered.
+ * Paper section V.B: a buffer is created in |0...0> before the program runs
+ * (createBuffer); a basis state other than 0 is the QFT workload's input.
+ * Errors: QSV_ERR_ARG (x >= 2^n), QSV_ERR_STATE, QSV_ERR_HIP. */
 qsv_status qsv_set_basis(qsv_state* s, uint64_t x);
 
 /* Apply one named gate in place (paper section IV.A: one instruction visit).
@@ -179,7 +185,10 @@ qsv_status qsv_adjoint(qsv_state* s, const qsv_op* ops, int n_ops, const uint64_
                        const uint64_t* zmask, const double* coeff, int n_terms,
                        const qsv_plan_opts* opts, double* energy, double* grad);
 
-/* sum_i |psi_i|^2 in FP64 (host result). */
+/* sum_i |psi_i|^2 in FP64 (host result; synchronises the state's stream).
+ * Paper section V.B: MEASURE reads the probabilities |psi_i|^2, whose sum is
+ * 1 for a normalised state; the path never renormalises, so this reports
+ * the drift.  Errors: QSV_ERR_ARG (out NULL), QSV_ERR_STATE, QSV_ERR_HIP. */
 qsv_status qsv_norm(qsv_state* s, double* out);
 
 /* Measurement samples of the full register without collapse (paper section
@@ -209,13 +218,23 @@ qsv_status qsv_batch_create(qsv_dtype dtype, int n_circuits, const int32_t* widt
                             const int32_t* op_offsets, const qsv_op* ops,
                             const int32_t* term_offsets, const uint64_t* zmask, const double* coeff,
                             int tile_qubits, qsv_batch** out);
-/* New parameter values (angles, matrices) for the same gate structure. */
+/* New parameter values (angles, matrices) for the same gate structure
+ * (the same gates on the same qubits; an angle of 0 is a structure like any
+ * other angle).  ops: host array of all circuits' ops, read during the call.
+ * Paper section V.B: the optimiser's next point of the parameter sweep.
+ * Errors: QSV_ERR_ARG (a different structure), QSV_ERR_STATE (freed handle,
+ * or matrices that would need a tile body the captured launch lacks). */
 qsv_status qsv_batch_update(qsv_batch* b, const qsv_op* ops);
-/* Launch the captured graph; energies (host, n_circuits doubles) on return. */
+/* Launch the captured graph; energies (host, n_circuits doubles, may be
+ * NULL) on return.  Paper section V.B: one energy per point of the sweep.
+ * Errors: QSV_ERR_STATE, QSV_ERR_HIP. */
 qsv_status qsv_batch_run(qsv_batch* b, double* energies);
-/* Chosen tile width, total tile passes over all circuits, scratch bytes. */
+/* Chosen tile width, total tile passes over all circuits, scratch bytes
+ * (outputs may be NULL).  Plumbing: no passage.  Errors: QSV_ERR_STATE. */
 qsv_status qsv_batch_info(const qsv_batch* b, int* tile_qubits, int* total_passes,
                           int64_t* scratch_bytes);
+/* Release a batch and its device memory; NULL is accepted.  Plumbing.
+ * Errors: QSV_ERR_STATE (freed or foreign handle). */
 qsv_status qsv_batch_free(qsv_batch* b);
 
 /* ---------------------------------------------------------------------
@@ -269,15 +288,20 @@ qsv_status qsv_mps_bonds(qsv_mps* m, int32_t* dims, double* schmidt);
 qsv_status qsv_mps_info(const qsv_mps* m, int64_t* bond_updates, int64_t* launches);
 
 /* Copy the raw amplitudes to / from host memory (bytes must equal the state
- * size).  Synchronous. */
+ * size; interleaved re/im of the state's dtype).  Synchronous.  Paper
+ * section III: hybrid programs transfer memory buffers between the host and
+ * the accelerator.  Errors: QSV_ERR_ARG (size, NULL), QSV_ERR_STATE,
+ * QSV_ERR_HIP. */
 qsv_status qsv_copy_to_host(qsv_state* s, void* dst, size_t bytes);
 qsv_status qsv_copy_from_host(qsv_state* s, const void* src, size_t bytes);
 
-/* Wait for all work issued on the state's stream. */
+/* Wait for all work issued on the state's stream.  Paper section IV.A:
+ * XACC follows the co-processor model of OpenCL / CUDA, where the host waits
+ * for the work it offloaded.  Errors: QSV_ERR_STATE, QSV_ERR_HIP. */
 qsv_status qsv_synchronize(qsv_state* s);
 
 /* Human-readable description of the last failure on this thread (valid until
- * the next call on this thread). */
+ * the next call on this thread; never NULL).  Plumbing: no passage. */
 const char* qsv_last_error(void);
 
 #ifdef __cplusplus

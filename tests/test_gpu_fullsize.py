@@ -8,12 +8,26 @@ sampled amplitudes; the 30-qubit QFT matches its closed form on sampled
 amplitudes; the headline Hamiltonian's expectation at 28 qubits matches a
 reduction written with plain torch operations on the same state.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
 import qcircuits as qc
 
 pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def record(name, rec):
+    """Measured deviations go to gpurun_out/ when that folder exists."""
+    out = os.path.join(os.path.dirname(HERE), "gpurun_out")
+    rec = {k: float(v) for k, v in rec.items()}
+    print(name, json.dumps(rec), flush=True)
+    if os.path.isdir(out):
+        with open(os.path.join(out, "fullsize_errors.jsonl"), "a") as f:
+            f.write(json.dumps({"case": name, **rec}) + "\n")
 
 
 def State(*a, **k):
@@ -45,7 +59,9 @@ def sample_index(n, seed, count=4096):
     return torch.as_tensor(idx, dtype=torch.int64, device="cuda"), idx
 
 
-@pytest.mark.parametrize("dtype,tol", [("c64", 1e-3), ("c128", 1e-10)])
+# |<0|back> - 1| and the other sampled amplitudes times 2^(n/2); complex64
+# keeps ~2e-6 relative error per direction (the 28-qubit oracle comparison)
+@pytest.mark.parametrize("dtype,tol", [("c64", (1e-4, 1e-4)), ("c128", (1e-11, 1e-10))])
 def test_c2_fused_then_pergate_inverse_returns_to_zero(dtype, tol):
     n = 28
     ops = qc.random_brickwork(n, 40, qc.SEEDS["c2"])
@@ -57,8 +73,10 @@ def test_c2_fused_then_pergate_inverse_returns_to_zero(dtype, tol):
     ti, _ = sample_index(n, 11)
     back = s.tensor[ti].cpu().numpy()
     s.close()
-    assert abs(back[0] - 1.0) < tol
-    assert np.abs(back[1:]).max() < tol
+    d0, rest = abs(back[0] - 1.0), float(np.abs(back[1:]).max()) * 2.0 ** (n / 2)
+    record("n28_fused_then_inverse_%s" % dtype, {"abs_err_at_0": d0, "max_other_x2^(n/2)": rest})
+    assert d0 < tol[0]
+    assert rest < tol[1]
 
 
 def test_c2_fused_and_pergate_agree_on_samples():
@@ -74,7 +92,10 @@ def test_c2_fused_and_pergate_agree_on_samples():
         s.close()
     scale = np.abs(got["pergate"]).max()
     assert scale > 0
-    assert np.abs(got["fused"] - got["pergate"]).max() <= 1e-6
+    d = float(np.abs(got["fused"] - got["pergate"]).max()) * 2.0 ** (n / 2)
+    record("n28_fused_vs_pergate_c64_samples", {"max_abs_x2^(n/2)": d})
+    # each is within ~8e-6 (normalised) of the complex128 oracle state
+    assert d <= 1e-4
 
 
 def test_c3_qft30_closed_form_on_samples():
@@ -88,7 +109,9 @@ def test_c3_qft30_closed_form_on_samples():
     s.close()
     N = 1 << n
     ref = np.exp(2j * np.pi * ((x * idx.astype(np.int64)) % N) / N) / 2 ** (n / 2)
-    assert np.abs(got - ref).max() <= 1e-6
+    d = float(np.abs(got - ref).max()) * 2.0 ** (n / 2)
+    record("n30_qft_closed_form_c64_samples", {"max_abs_x2^(n/2)": d})
+    assert d <= 1e-4
 
 
 def test_c2_energy_matches_torch_reduction():
