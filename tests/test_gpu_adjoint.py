@@ -10,8 +10,30 @@ import qcircuits as qc
 from oracle import oracle as O
 
 pytestmark = pytest.mark.gpu
-GTOL = {"c128": 1e-10, "c64": 2e-4}
+# bar on |gradient error| and |energy error| per unit of sum_k |c_k| (the
+# Hamiltonian's coefficient 1-norm bounds |lambda| = |H psi|)
+GBAR = {"c128": 1e-10, "c64": 2e-4}
 HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def record(name, rec):
+    """Measured gradient errors go to gpurun_out/ when that folder exists."""
+    out = os.path.join(os.path.dirname(HERE), "gpurun_out")
+    rec = {k: float(v) for k, v in rec.items()}
+    print(name, json.dumps(rec), flush=True)
+    if os.path.isdir(out):
+        with open(os.path.join(out, "gradient_errors.jsonl"), "a") as f:
+            f.write(json.dumps({"case": name, **rec}) + "\n")
+
+
+def check_grad(name, dtype, ham, e, e_ref, g, g_ref):
+    """Records and bounds the energy and gradient errors against the oracle."""
+    de, dg = abs(e - e_ref), float(np.abs(np.asarray(g) - np.asarray(g_ref)).max())
+    norm1 = sum(abs(c) for c, _ in ham)
+    record(name, {"energy_err": de, "max_grad_err": dg, "coeff_l1": norm1,
+                  "max_grad_err_per_l1": dg / norm1})
+    assert de <= GBAR[dtype] * norm1, (name, de)
+    assert dg <= GBAR[dtype] * norm1, (name, dg)
 
 
 def State(*a, **k):
@@ -33,8 +55,8 @@ def test_adjoint_matches_parameter_shift(dtype, n, layers, mode):
     g = np.zeros(params.size)
     np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
     ref = O.param_shift_grad(build, params, ham, n)
-    assert abs(e - O.energy(build, params, ham, n)) <= GTOL[dtype] * max(1, len(ham))
-    assert np.abs(g - ref).max() <= GTOL[dtype] * max(1, len(ham))
+    check_grad("ring_n%d_l%d_%s_%s" % (n, layers, mode, dtype), dtype, ham, e,
+               O.energy(build, params, ham, n), g, ref)
     assert np.all(g_ops[idx < 0] == 0)
     # the sweep returns the state to its input |0...0>
     assert abs(back[0] - 1) < (1e-10 if dtype == "c128" else 1e-4)
@@ -70,7 +92,7 @@ def test_adjoint_with_mixed_gates(dtype):
     g = np.zeros(nrot)
     np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
     ref = O.param_shift_grad(build, theta, ham, n)
-    assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham)
+    check_grad("mixed_gates_%s" % dtype, dtype, ham, e, O.energy(build, theta, ham, n), g, ref)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -111,8 +133,7 @@ def test_adjoint_chains_and_sign_runs(dtype):
     g = np.zeros(nrot)
     np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
     ref = O.param_shift_grad(build, theta, ham, n)
-    assert abs(e - O.energy(build, theta, ham, n)) <= GTOL[dtype] * len(ham)
-    assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham)
+    check_grad("chains_signs_%s" % dtype, dtype, ham, e, O.energy(build, theta, ham, n), g, ref)
     assert np.all(g_ops[idx < 0] == 0)
     assert abs(back[0] - 1) < (1e-10 if dtype == "c128" else 1e-4)
 
@@ -135,8 +156,8 @@ def test_adjoint_energy_paths(dtype):
         g = np.zeros(params.size)
         np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
         ref = O.param_shift_grad(build, params, ham, n)
-        assert abs(e - O.energy(build, params, ham, n)) <= GTOL[dtype] * len(ham)
-        assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham)
+        check_grad("energy_paths_%d_%s" % (len(ham), dtype), dtype, ham, e, O.energy(build, params, ham, n),
+                   g, ref)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -152,7 +173,7 @@ def test_adjoint_pass_split_over_programs(dtype):
     g = np.zeros(params.size)
     np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
     ref = O.param_shift_grad(build, params, ham, n)
-    assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham)
+    check_grad("split_programs_%s" % dtype, dtype, ham, e, O.energy(build, params, ham, n), g, ref)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -176,8 +197,7 @@ def test_adjoint_cnot_ladders(dtype):
     g = np.zeros(theta.size)
     np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
     ref = O.param_shift_grad(build, theta.ravel(), ham, n)
-    assert abs(e - O.energy(build, theta.ravel(), ham, n)) <= GTOL[dtype] * len(ham)
-    assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham)
+    check_grad("cnot_ladders_%s" % dtype, dtype, ham, e, O.energy(build, theta.ravel(), ham, n), g, ref)
     assert np.all(g_ops[idx < 0] == 0)
     assert abs(back[0] - 1) < (1e-10 if dtype == "c128" else 1e-4)
 
@@ -197,22 +217,32 @@ def test_autograd_function():
     assert np.abs(th.grad.numpy() - 2.0 * ref).max() < 1e-9
 
 
-def test_gradient_workload_24q_against_golden():
-    # 24 qubits, 6 layers of RX/RY/RZ + CZ ring (432 parameters), complex64 with
-    # FP64 reductions; selected derivatives by the oracle's parameter shift
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_gradient_workload_24q_against_golden(dtype):
+    # 24 qubits, 6 layers of RX/RY/RZ + CZ ring (432 parameters); 16 of the
+    # derivatives (every 27th: all layers, all three axes) by the oracle's
+    # parameter shift and by its central finite differences
     path = os.path.join(HERE, "golden", "c5_gradients.json")
     gold = json.load(open(path))
     n, layers = gold["n"], gold["layers"]
     params, ham = qc.gradient_workload(n, layers, qc.SEEDS["c5"])
     idx = qc.rot_ring_param_index(n, layers)
-    s = State(n, "c64")
+    s = State(n, dtype)
     e, g_ops = s.adjoint(qc.rot_ring_ansatz(n, params, layers), ham)
     s.close()
     g = np.zeros(params.size)
     np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
-    assert abs(e - gold["energy"]) < 1e-4
-    for k, ref in zip(gold["indices"], gold["grad"]):
-        assert abs(g[k] - ref) < 2e-4, (k, g[k], ref)
+    k = np.asarray(gold["indices"])
+    d_ps = np.abs(g[k] - np.asarray(gold["grad"])).max()
+    d_fd = np.abs(g[k] - np.asarray(gold["fd"])).max()
+    record("c5_24q_golden_%s" % dtype, {"energy_err": abs(e - gold["energy"]), "max_err_vs_param_shift": d_ps,
+                                        "max_err_vs_finite_diff": d_fd})
+    bar = GBAR[dtype] * sum(abs(c) for c, _ in ham)
+    assert len(k) == 16
+    assert abs(e - gold["energy"]) <= bar
+    assert d_ps <= bar, d_ps
+    # finite differences carry their own O(h^2) and rounding error (~1e-10)
+    assert d_fd <= bar + 1e-8, d_fd
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -235,5 +265,4 @@ def test_adjoint_at_zero_angles(dtype, n):
         np.add.at(g, idx[idx >= 0], g_ops[idx >= 0])
         ref = O.param_shift_grad(build, theta, ham, n)
         assert np.abs(ref).max() > 0.1  # the zero-angle derivatives are not trivially 0
-        assert abs(e - O.energy(build, theta, ham, n)) <= GTOL[dtype] * len(ham)
-        assert np.abs(g - ref).max() <= GTOL[dtype] * len(ham), np.abs(g - ref).max()
+        check_grad("zero_angles_n%d_%s" % (n, dtype), dtype, ham, e, O.energy(build, theta, ham, n), g, ref)

@@ -270,3 +270,15 @@ def test_param_shift_matches_finite_differences():
     fd = O.finite_diff_grad(build, params, ham, n, h=1e-5)
     assert np.abs(ps - fd).max() < 1e-8
     assert np.abs(ps).max() > 1e-2
+
+
+def test_c5_golden_parameter_shift_agrees_with_finite_differences():
+    # the stored 24-qubit derivatives were written by the oracle by two
+    # routes: the exact parameter-shift rule and central differences
+    # (h = 1e-5, error O(h^2) plus rounding ~1e-11); they must agree
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_gradients.json")))
+    assert len(gold["indices"]) == 16 and len(gold["grad"]) == 16 and len(gold["fd"]) == 16
+    assert np.abs(np.asarray(gold["grad"]) - np.asarray(gold["fd"])).max() < 1e-9
+    assert np.abs(np.asarray(gold["grad"])).max() > 0.1
