@@ -378,6 +378,39 @@ def bench_qft30(np, torch, qc, qsv, reps=3):
             "max_abs_err_closed_form_4096": float(np.abs(psi - ref).max())}
 
 
+def bench_dense_blocks(np, torch, qc, qsv, n=28, reps=5):
+    """Explicit dense k-qubit blocks (qsv_apply_fused, k = 4..6, Haar U(2^k))
+    on a 28-qubit state: k >= 4 runs on the matrix cores (real embedding of
+    the complex block).  Blocks on the low k qubits and on k high qubits;
+    median time per block, with its algorithmic flops (8 * 2^k per
+    amplitude) against the dense MFMA peak of the dtype and its bytes
+    (one read and one write of the state) against HBM."""
+    rng = np.random.default_rng(77)
+    out = {}
+    for dtype, peak in (("c64", 157.3), ("c128", 78.6)):
+        s = qsv.State(n, dtype)
+        s.set_basis(0)
+        nbytes = (1 << n) * (8 if dtype == "c64" else 16)
+        for k in (4, 5, 6):
+            U = qc.haar_unitary(k, rng)
+            for where, qs in (("low", list(range(k))), ("high", list(range(n - k, n)))):
+                s.apply_fused(qs, U)  # warm-up (staged matrix, code object)
+                ts = []
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    with Timer(s.stream) as tm:
+                        s.apply_fused(qs, U)
+                    ts.append(tm.ms() / 1e3)
+                t = float(np.median(ts))
+                fl = 8.0 * (1 << k) * (1 << n)
+                out["%s_k%d_%s" % (dtype, k, where)] = {
+                    "ms": t * 1e3, "tflops": fl / t / 1e12, "mfma_frac": fl / t / 1e12 / peak,
+                    "hbm_gbs": 2 * nbytes / t / 1e9, "hbm_frac": 2 * nbytes / t / 1e9 / HBM_PEAK_GBS}
+        s.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_c2_forms(np, torch, qc, qsv, ol, ngates, n, psi64):
     """The headline circuit in its other forms: complex128 fused and
     per-gate, complex64 per-gate; the complex64 fused state's deviation from
@@ -432,7 +465,7 @@ def main():
     ap.add_argument("--copy-ref", action="store_true",
                     help="run one plain 2 GiB device copy first (reference for HBM counters)")
     ap.add_argument("--mps-circuits", type=int, default=10, help="circuits per cell of the MPS grid")
-    ap.add_argument("--only", choices=["c3_qft30", "c4_batched", "c5_adjoint", "f1_paper_rounds", "f2_h2_sweep",
+    ap.add_argument("--only", choices=["c3_qft30", "dense_blocks", "c4_batched", "c5_adjoint", "f1_paper_rounds", "f2_h2_sweep",
                                        "f3_mps"],
                     help="run one of the extra workloads alone and print its JSON (for profiling)")
     args = ap.parse_args()
@@ -449,7 +482,7 @@ def main():
     from paper_1807_07914_amd import qsv
 
     if args.only:
-        fn = {"c3_qft30": bench_qft30, "c4_batched": bench_batched, "c5_adjoint": bench_adjoint,
+        fn = {"c3_qft30": bench_qft30, "dense_blocks": bench_dense_blocks, "c4_batched": bench_batched, "c5_adjoint": bench_adjoint,
               "f1_paper_rounds": bench_rounds, "f2_h2_sweep": bench_h2_sweep,
               "f3_mps": bench_mps}[args.only]
         kw = {"circuits": args.mps_circuits} if args.only == "f3_mps" else {}
