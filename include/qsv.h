@@ -167,6 +167,24 @@ qsv_status qsv_plan_info(int n_qubits, qsv_dtype dtype, const qsv_op* ops, int n
 qsv_status qsv_expval(qsv_state* s, const uint64_t* xmask, const uint64_t* zmask,
                       const double* coeff, int n_terms, double* out_total, double* out_terms);
 
+/* qsv_expval without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  amps_dev: the caller's device
+ * array of 2^n_qubits amplitudes (interleaved re/im of dtype, 16-byte
+ * aligned, on the current device); it is read only.  Terms and outputs as
+ * for qsv_expval (host arrays; the call synchronises hip_stream, NULL = the
+ * null stream).  The reduction partials live in a fixed scratch array of
+ * QSV_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends; at most QSV_NOALLOC_MAX_TERMS terms per call.
+ * Calls that overlap on one GPU share that array and race: the caller
+ * serialises them.  Errors: QSV_ERR_ARG (NULL or misaligned amps_dev, n,
+ * dtype, masks beyond n, NaN coefficients, too many terms), QSV_ERR_HIP. */
+#define QSV_NOALLOC_SCRATCH_BYTES (512u * 1024u)
+#define QSV_NOALLOC_MAX_TERMS 32768
+qsv_status qsv_expval_noalloc(const void* amps_dev, int n_qubits, qsv_dtype dtype,
+                              const uint64_t* xmask, const uint64_t* zmask, const double* coeff,
+                              int n_terms, void* hip_stream, double* out_total, double* out_terms);
+
 /* Gradient of E(theta) = <psi_L| H |psi_L>, psi_L = U_L ... U_1 psi_0, with
  * respect to the angle of every RX / RY / RZ op (R_P(theta) = exp(-i theta P/2)),
  * by one adjoint (reverse) sweep: dE/dtheta_k = Im <lambda_k| P |psi_k> with

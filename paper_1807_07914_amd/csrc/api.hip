@@ -515,6 +515,75 @@ qsv_status qsv_expval(qsv_state* s, const uint64_t* xmask, const uint64_t* zmask
 
 }  // extern "C"
 
+// ------------------------------------------------- allocation-free expval
+// qsv_expval_noalloc keeps the reduction partials and per-term sums of a
+// call in `scratch`, a fixed array each GPU holds from the library's load
+// until the process ends.  In host code the array's name is only a host-side
+// stand-in: the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current, and only that address is passed to the
+// kernels.  Every partial is written before it is read, so nothing in the
+// array has to start at zero; calls that overlap on one GPU share the array
+// and race.
+namespace qsv {
+
+constexpr size_t kNoAllocScratchBytes = QSV_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices] = {};
+
+static qsv_status scratch_address(void** out) {
+  int dev = 0;
+  QSV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(QSV_ERR_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return QSV_OK;
+}
+
+}  // namespace qsv
+
+extern "C" qsv_status qsv_expval_noalloc(const void* amps_dev, int n_qubits, qsv_dtype dtype,
+                                         const uint64_t* xmask, const uint64_t* zmask, const double* coeff,
+                                         int n_terms, void* hip_stream, double* out_total, double* out_terms) {
+  using namespace qsv;
+  if (!amps_dev) return fail(QSV_ERR_ARG, "amps_dev is NULL");
+  if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_ERR_ARG, "dtype must be QSV_C64 or QSV_C128");
+  if (n_qubits < 1 || n_qubits > max_qubits(dtype)) return fail(QSV_ERR_ARG, "n_qubits out of range");
+  if (n_terms < 0) return fail(QSV_ERR_ARG, "n_terms < 0");
+  if (n_terms > QSV_NOALLOC_MAX_TERMS)
+    return fail(QSV_ERR_ARG, "n_terms exceeds the allocation-free scratch (at most " +
+                                 std::to_string(QSV_NOALLOC_MAX_TERMS) + " terms)");
+  const size_t need = (expval_ws_doubles(n_qubits, 32) + (size_t)n_terms) * sizeof(double);
+  if (need > kNoAllocScratchBytes) return fail(QSV_ERR_ARG, "the terms do not fit the allocation-free scratch");
+  if ((reinterpret_cast<uintptr_t>(amps_dev) & 15u) != 0) return fail(QSV_ERR_ARG, "amps_dev must be 16-byte aligned");
+  void* ws = nullptr;
+  qsv_status st = scratch_address(&ws);
+  if (st) return st;
+  // a view of the caller's amplitudes: no memory of its own, never freed
+  qsv_state view;
+  view.n = n_qubits;
+  view.dt = dtype;
+  view.N = 1ull << n_qubits;
+  view.amp_bytes = dtype == QSV_C64 ? 8 : 16;
+  view.bytes = view.N * view.amp_bytes;
+  view.psi = const_cast<void*>(amps_dev);
+  view.owns = false;
+  view.stream = static_cast<hipStream_t>(hip_stream);
+  view.ws = ws;
+  view.ws_bytes = kNoAllocScratchBytes;
+  st = expval_impl(&view, amps_dev, xmask, zmask, coeff, n_terms, out_total, out_terms);
+  view.ws = nullptr;  // the workspace check found room: nothing was allocated
+  view.psi = nullptr;
+  return st;
+}
+
 namespace qsv {
 
 qsv_status expval_impl(qsv_state* s, const void* data, const uint64_t* xmask, const uint64_t* zmask,

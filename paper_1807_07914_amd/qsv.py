@@ -69,6 +69,7 @@ def lib():
         "qsv_apply_fused": [vp, ip, i32, dp],
         "qsv_apply_circuit": [vp, ctypes.POINTER(QsvOp), i32, ctypes.POINTER(QsvPlanOpts)],
         "qsv_expval": [vp, u64p, u64p, dp, i32, dp, dp],
+        "qsv_expval_noalloc": [vp, i32, i32, u64p, u64p, dp, i32, vp, dp, dp],
         "qsv_norm": [vp, dp],
         "qsv_sample": [vp, dp, i32, u64p],
         "qsv_copy_to_host": [vp, vp, ctypes.c_size_t],
@@ -100,6 +101,24 @@ def lib():
     L.qsv_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
+
+
+def expval_noalloc(amps_dev_ptr: int, n_qubits: int, dtype: str, hamiltonian, stream_ptr: int = 0,
+                   per_term: bool = False):
+    """qsv_expval_noalloc: the expectation value of a Pauli sum on caller-owned
+    device amplitudes (a device address, e.g. a tensor's data_ptr()), with
+    no device allocation by the library."""
+    x, z, c = pauli_masks(hamiltonian)
+    tot = ctypes.c_double()
+    terms = np.zeros(max(1, len(c)), dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    u64 = ctypes.POINTER(ctypes.c_uint64)
+    check(lib().qsv_expval_noalloc(ctypes.c_void_p(int(amps_dev_ptr)), int(n_qubits),
+                                   QSV_C64 if dtype == "c64" else QSV_C128, x.ctypes.data_as(u64),
+                                   z.ctypes.data_as(u64), c.ctypes.data_as(dp), len(c),
+                                   ctypes.c_void_p(int(stream_ptr)), ctypes.byref(tot),
+                                   terms.ctypes.data_as(dp)))
+    return terms[: len(c)].tolist() if per_term else tot.value
 
 
 def header_functions(path: str = HEADER_PATH) -> list:

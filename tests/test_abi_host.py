@@ -96,3 +96,23 @@ def test_launch_geometry_up_to_the_largest_register(dtype):
             assert gx * gy >= need and gx * (gy - 1) < need  # covers the range, one row at most overhangs
     assert fn(dt, top + 1, ptr) != 0
     assert qsv.lib().qsv_alloc_state(top + 1, dt, None, 0, None, ctypes.byref(ctypes.c_void_p())) != 0
+
+
+def test_noalloc_expval_checks_arguments_on_the_host():
+    # argument errors are reported before any device work
+    import ctypes
+    L = qsv.lib()
+    z = np.zeros(1, dtype=np.uint64)
+    c = np.ones(1)
+    u64 = ctypes.POINTER(ctypes.c_uint64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    tot = ctypes.c_double()
+    args = (z.ctypes.data_as(u64), z.ctypes.data_as(u64), c.ctypes.data_as(dp))
+    assert L.qsv_expval_noalloc(None, 10, qsv.QSV_C64, *args, 1, None, ctypes.byref(tot), None) == qsv.QSV_ERR_ARG
+    assert L.qsv_expval_noalloc(ctypes.c_void_p(256), 10, 7, *args, 1, None, ctypes.byref(tot), None) == qsv.QSV_ERR_ARG
+    assert L.qsv_expval_noalloc(ctypes.c_void_p(256), 36, qsv.QSV_C64, *args, 1, None, ctypes.byref(tot),
+                                None) == qsv.QSV_ERR_ARG
+    assert L.qsv_expval_noalloc(ctypes.c_void_p(256), 10, qsv.QSV_C64, *args, 40000, None, ctypes.byref(tot),
+                                None) == qsv.QSV_ERR_ARG
+    assert L.qsv_expval_noalloc(ctypes.c_void_p(8), 10, qsv.QSV_C64, *args, 1, None, ctypes.byref(tot),
+                                None) == qsv.QSV_ERR_ARG  # misaligned
