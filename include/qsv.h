@@ -93,11 +93,16 @@ typedef struct qsv_op {
  *   mode 0 = automatic (fused tile passes), 1 = one kernel per gate
  *   ("plain per-gate form"), 2 = fused tile passes.
  *   tile_qubits: qubits per LDS tile in fused mode (0 = library choice).
+ *   state_is_output (qsv_adjoint only, 0 or 1): 1 = the state already holds
+ *   the circuit's output (an earlier qsv_apply_circuit of the same ops), so
+ *   qsv_adjoint starts from it instead of applying the ops first; other
+ *   calls require 0.
  *   Other fields are reserved and must be zero. */
 typedef struct qsv_plan_opts {
   int32_t mode;
   int32_t tile_qubits;
-  int32_t reserved[6];
+  int32_t state_is_output;
+  int32_t reserved[5];
 } qsv_plan_opts;
 
 /* Allocate a state of n_qubits (1..QSV_MAX_QUBITS) initialised to |0...0>.
@@ -189,7 +194,9 @@ qsv_status qsv_expval_noalloc(const void* amps_dev, int n_qubits, qsv_dtype dtyp
  * respect to the angle of every RX / RY / RZ op (R_P(theta) = exp(-i theta P/2)),
  * by one adjoint (reverse) sweep: dE/dtheta_k = Im <lambda_k| P |psi_k> with
  * lambda_k = U_{k+1}^dag ... U_L^dag H psi_L.  psi_0 is the state's current
- * content; the ops are applied as by qsv_apply_circuit(opts), E is computed
+ * content (or, with opts->state_is_output = 1, the content is psi_L and psi_0
+ * is what the sweep recomputes); the ops are applied as by
+ * qsv_apply_circuit(opts), E is computed
  * as by qsv_expval, then a second state-sized device buffer (allocated on
  * first use, kept with the state) holds lambda while every op is undone in
  * reverse on both vectors, each rotation's gradient and both inverse updates

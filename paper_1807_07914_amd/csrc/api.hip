@@ -451,7 +451,8 @@ qsv_status qsv_apply_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const q
   qsv_plan_opts o{};
   if (opts) o = *opts;
   if (o.mode < 0 || o.mode > 2) return fail(QSV_ERR_ARG, "mode must be 0, 1 or 2");
-  for (int r = 0; r < 6; ++r)
+  if (o.state_is_output) return fail(QSV_ERR_ARG, "state_is_output applies to qsv_adjoint only");
+  for (int r = 0; r < 5; ++r)
     if (o.reserved[r]) return fail(QSV_ERR_ARG, "reserved plan option fields must be zero");
   for (int i = 0; i < n_ops; ++i) {
     qsv_status st = validate_op(s, ops[i]);
@@ -1454,13 +1455,14 @@ qsv_status qsv_adjoint(qsv_state* s, const qsv_op* ops, int n_ops, const uint64_
   qsv_plan_opts o{};
   if (opts) o = *opts;
   if (o.mode < 0 || o.mode > 2) return fail(QSV_ERR_ARG, "mode must be 0, 1 or 2");
-  for (int r = 0; r < 6; ++r)
+  if (o.state_is_output != 0 && o.state_is_output != 1) return fail(QSV_ERR_ARG, "state_is_output must be 0 or 1");
+  for (int r = 0; r < 5; ++r)
     if (o.reserved[r]) return fail(QSV_ERR_ARG, "reserved plan option fields must be zero");
   for (int i = 0; i < n_ops; ++i) {
     st = validate_op(s, ops[i]);
     if (st) return fail(st, "op " + std::to_string(i) + ": " + get_error());
   }
-  if (n_ops > 0) {
+  if (n_ops > 0 && !o.state_is_output) {
     st = run_circuit(s, ops, n_ops, o);
     if (st) return st;
   }

@@ -523,6 +523,7 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
     uint64_t om;
     cd r;
   };
+  std::vector<std::vector<PhTerm>> tfac;  // the pass's tile-factor slots
   // diagonal work that runs between two non-diagonal ops of a round
   struct DGroup {
     bool tab = false;
@@ -1073,22 +1074,36 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
         int idx;
       };
       std::vector<Extra> extras;
-      // per-group phase entries, at most kTermsPerLayer terms each
-      constexpr size_t kTermsPerLayer = 8;
+      // per-group phase steps: all terms of one register bit (or of every
+      // amplitude) in one step, applied once
       std::vector<std::pair<int, std::vector<PhTerm>>> phl;
       for (auto& e : g.phl) {
         std::vector<PhTerm> terms;
         for (auto& tm : e.second)
           if (tm.r != cd(1.0)) terms.push_back(tm);
-        for (size_t t0 = 0; t0 < terms.size(); t0 += kTermsPerLayer)
-          phl.push_back({e.first, std::vector<PhTerm>(terms.begin() + t0,
-                                                      terms.begin() + std::min(terms.size(), t0 + kTermsPerLayer))});
+        if (!terms.empty()) phl.push_back({e.first, terms});
       }
       for (size_t e = 0; e < phl.size(); ++e) extras.push_back({0, (int)e});
       for (size_t e = 0; e < g.raw.size(); ++e) extras.push_back({1, (int)e});
       auto phasel_words = [&](std::vector<int32_t>& w, int e) {
-        const std::vector<PhTerm>& terms = phl[e].second;
+        // terms on outside qubits only depend on the tile: their product is
+        // taken once per tile into a slot of the pass's tile-factor list
+        std::vector<PhTerm> terms, outside;
+        bool unit = true;
+        for (const PhTerm& tm : phl[e].second) {
+          if (std::abs(std::abs(tm.r) - 1.0) > 1e-12) unit = false;
+          (tm.lgm == 0 ? outside : terms).push_back(tm);
+        }
+        int slot = -1;
+        if (!outside.empty() && tfac.size() < (size_t)kMaxTileFactors) {
+          slot = (int)tfac.size();
+          tfac.push_back(outside);
+        } else {
+          terms.insert(terms.end(), outside.begin(), outside.end());
+        }
         w.push_back(phl[e].first);
+        w.push_back(slot);
+        w.push_back(unit ? 1 : 0);
         w.push_back((int32_t)terms.size());
         for (auto& tm : terms) {
           w.push_back((int32_t)tm.lgm);
@@ -1276,6 +1291,27 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
       prog.insert(prog.end(), recs[i].aux.begin(), recs[i].aux.end());
     }
     while ((prog.size() - b0) % 16) prog.push_back(0);
+  }
+  if (!tfac.empty()) {
+    // the tile-factor list after the round blocks; the first round's header
+    // points to it
+    const size_t l0 = prog.size();
+    const size_t K = tfac.size();
+    prog.resize(l0 + K, 0);
+    for (size_t k = 0; k < K; ++k) {
+      prog[l0 + k] = (int32_t)(prog.size() - l0);
+      prog.push_back((int32_t)tfac[k].size());
+      for (const PhTerm& tm : tfac[k]) {
+        prog.push_back((int32_t)(tm.om & 0xffffffffull));
+        prog.push_back((int32_t)(tm.om >> 32));
+        RealWords<T>::put(tm.r.real(), prog);
+        RealWords<T>::put(tm.r.imag(), prog);
+      }
+    }
+    const size_t rb0 = h0 + (size_t)prog[roff0];
+    prog[rb0 + kHdrTileFac] = (int32_t)(l0 - h0);
+    prog[rb0 + kHdrTileFac + 1] = (int32_t)K;
+    while ((prog.size() - h0) % 16) prog.push_back(0);
   }
   return true;
 }

@@ -73,6 +73,26 @@ __device__ __forceinline__ void cmul(cpx<double>& x, double zr, double zi) {
       : "s"(zr), "s"(zi));
 }
 
+// The same product for a factor that differs between lanes (VGPR operands).
+__device__ __forceinline__ void cmul_lane(cpx<float>& x, float zr, float zi) {
+  float t;
+  asm("v_mul_f32 %2, %4, %1\n\t"
+      "v_mul_f32 %1, %3, %1\n\t"
+      "v_fmac_f32 %1, %4, %0\n\t"
+      "v_fma_f32 %0, %3, %0, -%2"
+      : "+v"(x.x), "+v"(x.y), "=&v"(t)
+      : "v"(zr), "v"(zi));
+}
+__device__ __forceinline__ void cmul_lane(cpx<double>& x, double zr, double zi) {
+  double t;
+  asm("v_mul_f64 %2, %4, %1\n\t"
+      "v_mul_f64 %1, %3, %1\n\t"
+      "v_fma_f64 %1, %4, %0, %1\n\t"
+      "v_fma_f64 %0, %3, %0, -%2"
+      : "+v"(x.x), "+v"(x.y), "=&v"(t)
+      : "v"(zr), "v"(zi));
+}
+
 // x <- exp(i phi) x as three shears of (re, im): p = -tan(phi/2), q = sin(phi)
 template <typename T>
 __device__ __forceinline__ void phase_shears(cpx<T>& x, T p, T q) {
@@ -299,6 +319,28 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
   const int ng = 1 << (t - RB);
   const int nrounds = pass[3];
   const int32_t* roff = pass + 4 + t + nns;
+  // the tile's factors of the per-group phase steps that depend on the tile
+  // only: one thread per slot, once per tile
+  __shared__ cpx<T> tfac[kMaxTileFactors];
+  if (nrounds > 0) {
+    const int32_t* rb0 = pass + roff[0];
+    const int nk = rb0[kHdrTileFac + 1];
+    if (nk > 0) {
+      const int32_t* lst = pass + rb0[kHdrTileFac];
+      for (int k = threadIdx.x; k < nk; k += kTileThreads) {
+        const int32_t* e = lst + lst[k];
+        const int nt = e[0];
+        cpx<T> w{T(1), T(0)};
+        for (int q = 0; q < nt; ++q) {
+          const int32_t* tm = e + 1 + q * (2 + 2 * WT);
+          const uint64_t om = ((uint64_t)(uint32_t)tm[1] << 32) | (uint32_t)tm[0];
+          if ((base & om) == om) w = cmul(cpx<T>{aux_real<T>(tm, 2), aux_real<T>(tm, 2 + WT)}, w);
+        }
+        tfac[k] = w;
+      }
+      __syncthreads();
+    }
+  }
   for (int r = 0; r < nrounds; ++r) {
     const int32_t* rb = pass + roff[r];
     const int nlayers = rb[0];
@@ -395,27 +437,29 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
         }
         if (flags & LT_PHASEL) {
           {
-            const int j = ap[p], nt = ap[p + 1];
-            p += 2;
+            const int j = ap[p], slot = ap[p + 1], unit = ap[p + 2], nt = ap[p + 3];
+            p += 4;
             cpx<T> w{T(1), T(0)};
+            if (slot >= 0) w = tfac[slot];  // uniform address: one broadcast read
             for (int q = 0; q < nt; ++q, p += 3 + 2 * WT) {
               const uint32_t lgm = (uint32_t)ap[p];
               const uint64_t om = ((uint64_t)(uint32_t)ap[p + 2] << 32) | (uint32_t)ap[p + 1];
               const cpx<T> rr{aux_real<T>(ap, p + 3), aux_real<T>(ap, p + 3 + WT)};
               if ((lg & lgm) == lgm && (base & om) == om) w = cmul(rr, w);
             }
-            // w = (+-|w|) exp(i phi), |phi| <= pi/2: three shears and a scale
-            const T mag = sqrt(w.x * w.x + w.y * w.y);
-            const T sg = w.x < T(0) ? T(-1) : T(1);
-            const T wx = sg * w.x, wy = sg * w.y;
-            const T ps = -wy / (mag + wx), qs = wy / mag, cs = sg * mag - T(1);
-#pragma unroll
-            for (int m = 0; m < NR; ++m) {
-              if (j < 0 || ((m >> j) & 1)) {
-                phase_shears(a[m], ps, qs);
-                scale1(a[m], cs);
-              }
+            // one in-place complex product per amplitude (a single body: two
+            // alternative bodies made the compiler keep a second copy of the
+            // amplitudes); a pure phase is renormalised first, so that the
+            // rounding of the factor product cannot change the norm
+            T zr = w.x, zi = w.y;
+            if (unit) {
+              const T inv = T(1) / sqrt(w.x * w.x + w.y * w.y);
+              zr *= inv;
+              zi *= inv;
             }
+#pragma unroll
+            for (int m = 0; m < NR; ++m)
+              if (j < 0 || ((m >> j) & 1)) cmul_lane(a[m], zr, zi);
           }
         }
         if (FULL && (flags & LT_RAWD)) {

@@ -22,7 +22,11 @@
 //   round block : a header of kRoundHeader words: [0] n_layers, [1] free-bit
 //                 mask, [2 + j] the swizzled LDS byte offset of register bit
 //                 j (the offset of register combination m is the XOR of
-//                 those of its bits); then the n_layers layer records of
+//                 those of its bits), and in the first round block only
+//                 [kHdrTileFac] the word offset (from the start of the pass)
+//                 of the pass's tile-factor list, 0 if it has none, and
+//                 [kHdrTileFac + 1] its number of slots K; then the n_layers
+//                 layer records of
 //                 LayerRec<T>::W words, each followed by its table (64 words)
 //                 if it has LT_TAB; then the aux words of the records.
 //                 Offsets in a record count words from the start of its round
@@ -53,11 +57,21 @@
 //                 parity sum_d popcount(lg & (lg >> d) & M)
 //                 + sum_(q,f) bit(q) bit(lg, f) + sum_(qa,qb) bit(qa) bit(qb)
 //                 is odd (CZs among free bits and outside qubits).
-//     LT_PHASEL : aux j, nt, (lgmask, omask_lo, omask_hi, r)*nt:
-//                 per-group factor w = product of r over the terms whose free
-//                 bits lgmask are all set in the group and whose outside
-//                 qubits omask are all set in the tile, applied to the
-//                 amplitudes with register bit j set (every amplitude if j < 0)
+//     LT_PHASEL : aux j, slot, unit, nt, (lgmask, omask_lo, omask_hi, r)*nt:
+//                 per-group factor w = f_slot (1 if slot < 0) times the
+//                 product of r over the terms whose free bits lgmask are all
+//                 set in the group and whose outside qubits omask are all set
+//                 in the tile, applied to the amplitudes with register bit j
+//                 set (every amplitude if j < 0).  unit = 1: every factor has
+//                 modulus 1, so w is applied as a pure phase.
+//   tile-factor list (one per pass, optional): K word offsets of the entries
+//                 (from the list's start), then each entry nt,
+//                 (omask_lo, omask_hi, r)*nt.  At the start of every tile,
+//                 f_k = product of r over the terms of entry k whose outside
+//                 qubits omask are all set in the tile: the factors of a
+//                 per-group phase step that depend only on the tile, taken
+//                 once per tile (K <= kMaxTileFactors) instead of once per
+//                 register group.
 //     LT_RAWD   : aux type, payload, for diagonal factors that may be zero:
 //                 RAW_PHASE1 : kind, val, f[2]          factor f[bit of the qubit]
 //                 RAW_DIAG2  : kindA, valA, kindB, valB, f[4]  factor f[bitA + 2 bitB]
@@ -114,6 +128,8 @@ constexpr int kTileThreads = 256;
 constexpr int kRoundHeader = 16;  // words of a round block header
 constexpr int kRecRot = 4;        // first rotation word of a layer record
 constexpr int kTableWords = 64;   // words of a table
+constexpr int kHdrTileFac = 8;    // round-header word of the tile-factor list offset
+constexpr int kMaxTileFactors = 128;  // tile-factor slots of one pass
 
 // words of a layer record: 4 + 2 * RB reals (RB = 5 floats, RB = 4 doubles)
 template <typename T>

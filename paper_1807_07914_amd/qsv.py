@@ -41,7 +41,7 @@ class QsvOp(ctypes.Structure):
 
 class QsvPlanOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("state_is_output", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 assert ctypes.sizeof(QsvOp) == 64
@@ -285,14 +285,18 @@ class State:
                                terms.ctypes.data_as(dp)))
         return terms[: len(c)].tolist() if per_term else tot.value
 
-    def adjoint(self, ops, hamiltonian, mode: str = "auto", tile_qubits: int = 0):
+    def adjoint(self, ops, hamiltonian, mode: str = "auto", tile_qubits: int = 0,
+                state_is_output: bool = False):
         """Apply ops to the current state, return (E, dE/dtheta per op) from
-        one adjoint sweep; the state holds its input again afterwards."""
+        one adjoint sweep; the state holds its input again afterwards.  With
+        state_is_output the state already holds the ops' output (an earlier
+        apply_circuit of the same ops) and the ops are not applied again."""
         ol = ops if isinstance(ops, OpList) else OpList(ops)
         x, z, c = pauli_masks(hamiltonian)
         opts = QsvPlanOpts()
         opts.mode = MODES[mode]
         opts.tile_qubits = int(tile_qubits)
+        opts.state_is_output = 1 if state_is_output else 0
         e = ctypes.c_double()
         g = np.zeros(max(1, ol.n), dtype=np.float64)
         dp = ctypes.POINTER(ctypes.c_double)

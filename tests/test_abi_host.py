@@ -18,6 +18,11 @@ def test_library_exports_every_header_function():
     assert not missing, missing
 
 
+def test_plan_opts_layout():
+    assert ctypes.sizeof(qsv.QsvPlanOpts) == 32
+    assert qsv.QsvPlanOpts.state_is_output.offset == 8 and qsv.QsvPlanOpts.reserved.offset == 12
+
+
 def test_op_struct_is_64_bytes():
     assert ctypes.sizeof(qsv.QsvOp) == 64
     assert qsv.QsvOp.mat.offset == 56 and qsv.QsvOp.p.offset == 32

@@ -221,6 +221,52 @@ def test_autograd_function():
     assert np.abs(th.grad.numpy() - 2.0 * ref).max() < 1e-9
 
 
+def test_autograd_forward_then_backward_from_the_output_state():
+    # the forward pass applies the circuit only; backward sweeps back from
+    # the output it left on the GPU.  14 qubits reach past one sweep tile.
+    import torch
+    from paper_1807_07914_amd.autograd import expectation
+    n, layers = 14, 2
+    params, ham = qc.gradient_workload(n, layers, 78)
+    build = lambda p: qc.rot_ring_ansatz(n, p, layers)
+    idx = qc.rot_ring_param_index(n, layers)
+    ref = O.param_shift_grad(build, params, ham, n)
+    e_ref = O.energy(build, params, ham, n)
+    with torch.no_grad():  # a forward pass without a gradient
+        e0 = expectation(torch.tensor(params), build, idx, n, ham)
+    assert abs(e0.item() - e_ref) <= GBAR["c64"] * sum(abs(c) for c, _ in ham)
+    s = State(n, "c64")  # a caller-provided state, reused by two steps
+    for step in range(2):
+        th = torch.tensor(params, dtype=torch.float64, requires_grad=True)
+        e = expectation(th, build, idx, n, ham, dtype="c64", state=s)
+        e.backward(retain_graph=True)
+        check_grad("autograd_n14_step%d" % step, "c64", ham, e.item(), e_ref, th.grad.numpy(), ref)
+        with pytest.raises(RuntimeError):  # a second backward of the same node
+            e.backward()
+    # the sweep left |0...0> behind
+    back = s.to_numpy()
+    s.close()
+    assert abs(back[0] - 1) < 1e-4
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_adjoint_from_the_output_state(dtype):
+    # qsv_adjoint on a state that already holds the circuit's output gives
+    # what it gives when it applies the circuit itself
+    n, layers = 9, 2
+    params, ham = qc.gradient_workload(n, layers, 79)
+    ops = qc.rot_ring_ansatz(n, params, layers)
+    s = State(n, dtype)
+    e1, g1 = s.adjoint(ops, ham)
+    s.set_basis(0)  # the sweep's recomputed input is |0...0> only up to rounding
+    s.apply_circuit(ops)
+    e2, g2 = s.adjoint(ops, ham, state_is_output=True)
+    back = s.to_numpy()
+    s.close()
+    assert abs(e1 - e2) <= 1e-12 and np.abs(g1 - g2).max() <= 1e-12
+    assert abs(back[0] - 1) < (1e-10 if dtype == "c128" else 1e-4)
+
+
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 def test_gradient_workload_24q_against_golden(dtype):
     # 24 qubits, 6 layers of RX/RY/RZ + CZ ring (432 parameters); 16 of the

@@ -28,6 +28,7 @@ LT_PERM2, LT_U2, LT_U1 = 1 << 24, 1 << 25, 1 << 26
 RAW_PHASE1, RAW_DIAG2 = 4, 5
 TK_REG, TK_FREE, TK_OUT = 0, 1, 2
 CFG = {"c64": dict(RB=5, SB=5, WT=1, LR=16), "c128": dict(RB=4, SB=4, WT=2, LR=24)}
+TILE_FAC_HDR, MAX_TILE_FACTORS = 8, 128  # round-header word of the tile-factor list; slot cap
 
 
 def program(n, dtype, ops, tile=0):
@@ -138,8 +139,28 @@ def run_pass(psi, n, words, off, cfg):
     assert S == sorted(S) and S[:c] == list(range(c))
     blocks = _round_blocks(words, off, t, nns)
     esz = 8 * WT  # bytes per amplitude: the header holds LDS byte offsets
+    # the pass's tile-factor list (pointed to by the first round's header)
+    tfl = []
+    if blocks:
+        lo, nk = words[blocks[0] + TILE_FAC_HDR], words[blocks[0] + TILE_FAC_HDR + 1]
+        assert 0 <= nk <= MAX_TILE_FACTORS and (nk == 0 or lo > 0)
+        for k in range(nk):
+            e = off + lo + words[off + lo + k]
+            terms = []
+            for q in range(words[e]):
+                tm = e + 1 + q * (2 + 2 * WT)
+                om = (words[tm] & 0xffffffff) | ((words[tm + 1] & 0xffffffff) << 32)
+                terms.append((om, _cplx(words, tm + 2, WT, 1)[0]))
+            tfl.append(terms)
     for tid in range(1 << (n - t)):
         base = deposit(tid, nonS)
+        tfac = []
+        for terms in tfl:
+            f = 1.0 + 0j
+            for om, r_ in terms:
+                if (base & om) == om:
+                    f *= r_
+            tfac.append(f)
         lds = np.zeros(1 << t, dtype=np.complex128)
         gidx = [base | deposit(l, S) for l in range(1 << t)]
         for l in range(1 << t):
@@ -212,10 +233,10 @@ def run_pass(psi, n, words, off, cfg):
                         if par & 1:
                             a = [-x for x in a]
                     if flags & LT_PHASEL:
-                        j, nt = blk[p], blk[p + 1]
-                        p += 2
-                        assert -1 <= j < RB
-                        w = 1.0 + 0j
+                        j, slot, unit, nt = blk[p], blk[p + 1], blk[p + 2], blk[p + 3]
+                        p += 4
+                        assert -1 <= j < RB and -1 <= slot < len(tfl) and unit in (0, 1)
+                        w = tfac[slot] if slot >= 0 else 1.0 + 0j
                         for _ in range(nt):
                             lgm = blk[p] & 0xffffffff
                             om = (blk[p + 1] & 0xffffffff) | ((blk[p + 2] & 0xffffffff) << 32)
@@ -223,6 +244,8 @@ def run_pass(psi, n, words, off, cfg):
                             if (lg & lgm) == lgm and (base & om) == om:
                                 w *= r_
                             p += 3 + 2 * WT
+                        if unit:
+                            assert abs(abs(w) - 1.0) < 1e-6  # factors stored in the state precision
                         for m in range(NR):
                             if j < 0 or (m >> j) & 1:
                                 a[m] *= w
