@@ -320,23 +320,33 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
   const int nrounds = pass[3];
   const int32_t* roff = pass + 4 + t + nns;
   // the tile's factors of the per-group phase steps that depend on the tile
-  // only: one thread per slot, once per tile
+  // only, once per tile: wave w takes slots w, w + 4, ...  A slot index that
+  // is uniform over the wave keeps every program read a scalar load: a vector
+  // load here would have to wait for the next tile's prefetch (loads and
+  // stores complete in order) and end the overlap of memory and arithmetic.
   __shared__ cpx<T> tfac[kMaxTileFactors];
   if (nrounds > 0) {
     const int32_t* rb0 = pass + roff[0];
     const int nk = rb0[kHdrTileFac + 1];
     if (nk > 0) {
       const int32_t* lst = pass + rb0[kHdrTileFac];
-      for (int k = threadIdx.x; k < nk; k += kTileThreads) {
-        const int32_t* e = lst + lst[k];
-        const int nt = e[0];
+      const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+      for (int k = wave; k < nk; k += kTileThreads / 64) {
+        const int32_t* e = lst + __builtin_amdgcn_readfirstlane(lst[k]);
+        const int nt = __builtin_amdgcn_readfirstlane(e[0]);
         cpx<T> w{T(1), T(0)};
         for (int q = 0; q < nt; ++q) {
           const int32_t* tm = e + 1 + q * (2 + 2 * WT);
-          const uint64_t om = ((uint64_t)(uint32_t)tm[1] << 32) | (uint32_t)tm[0];
-          if ((base & om) == om) w = cmul(cpx<T>{aux_real<T>(tm, 2), aux_real<T>(tm, 2 + WT)}, w);
+          const uint32_t olo = (uint32_t)__builtin_amdgcn_readfirstlane(tm[0]);
+          const uint32_t ohi = (uint32_t)__builtin_amdgcn_readfirstlane(tm[1]);
+          const uint64_t om = ((uint64_t)ohi << 32) | olo;
+          const cpx<T> rr{aux_real<T>(tm, 2), aux_real<T>(tm, 2 + WT)};
+          const cpx<T> wn = cmul(rr, w);
+          const bool on = (base & om) == om;  // uniform condition
+          w.x = on ? wn.x : w.x;
+          w.y = on ? wn.y : w.y;
         }
-        tfac[k] = w;
+        if ((threadIdx.x & 63) == 0) tfac[k] = w;
       }
       __syncthreads();
     }
@@ -442,10 +452,16 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
             cpx<T> w{T(1), T(0)};
             if (slot >= 0) w = tfac[slot];  // uniform address: one broadcast read
             for (int q = 0; q < nt; ++q, p += 3 + 2 * WT) {
+              // every word read before the lane condition (scalar loads; a
+              // read inside the divergent branch became a vector load that
+              // waited for the next tile's prefetch), then a select
               const uint32_t lgm = (uint32_t)ap[p];
               const uint64_t om = ((uint64_t)(uint32_t)ap[p + 2] << 32) | (uint32_t)ap[p + 1];
               const cpx<T> rr{aux_real<T>(ap, p + 3), aux_real<T>(ap, p + 3 + WT)};
-              if ((lg & lgm) == lgm && (base & om) == om) w = cmul(rr, w);
+              const bool on = ((lg & lgm) == lgm) & ((base & om) == om);
+              const cpx<T> wn = cmul(rr, w);
+              w.x = on ? wn.x : w.x;
+              w.y = on ? wn.y : w.y;
             }
             // one in-place complex product per amplitude (a single body: two
             // alternative bodies made the compiler keep a second copy of the
