@@ -39,7 +39,7 @@ static int default_tile_bits() {
 template <typename T>
 int tile_reg_bits();
 template <typename T>
-hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const int32_t* prog_host, bool full,
+hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const int32_t* prog_host, int body,
                             hipStream_t st);
 
 using cd = std::complex<double>;
@@ -1263,14 +1263,35 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
       }
     }
 
+    // A permutation that ends the round moves to the round header: the
+    // round's store applies it by writing each register combination to the
+    // slot of its image (the payload is the last aux segment of its record).
+    std::vector<int32_t> hdr(kRoundHeader, 0);
+    for (int k = 0; k < RB; ++k) {
+      hdr[2 + k] = (int32_t)(tile_swizzle(1u << rp.R[k], SB) * (uint32_t)(2 * sizeof(T)));
+      hdr[kHdrStore + k] = hdr[2 + k];
+    }
+    if (!recs.empty() && (recs.back().flags & LT_PERM2)) {
+      Rec& lr = recs.back();
+      const size_t na = lr.aux.size();
+      const int j0 = lr.aux[na - 3], j1 = lr.aux[na - 2], code = lr.aux[na - 1];
+      if (code == 2) {  // SWAP: the two bits trade offsets
+        hdr[kHdrStore + j0] = hdr[2 + j1];
+        hdr[kHdrStore + j1] = hdr[2 + j0];
+      } else if (code == 0) {  // CNOT, control j0: e_j0 -> e_j0 + e_j1
+        hdr[kHdrStore + j0] = hdr[2 + j0] ^ hdr[2 + j1];
+      } else {  // CNOT, control j1
+        hdr[kHdrStore + j1] = hdr[2 + j1] ^ hdr[2 + j0];
+      }
+      lr.aux.resize(na - 3);
+      lr.flags &= ~LT_PERM2;
+      if (lr.flags == 0 && lr.tab < 0) recs.pop_back();
+    }
     // round block: header, records, aux words, tables
     const size_t b0 = prog.size();
     prog[roff0 + ri] = (int32_t)(b0 - h0);
-    std::vector<int32_t> hdr(kRoundHeader, 0);
     hdr[0] = (int32_t)recs.size();
     hdr[1] = (int32_t)(tmask & ~rmask);
-    for (int k = 0; k < RB; ++k)
-      hdr[2 + k] = (int32_t)(tile_swizzle(1u << rp.R[k], SB) * (uint32_t)(2 * sizeof(T)));
     prog.insert(prog.end(), hdr.begin(), hdr.end());
     std::vector<size_t> at(recs.size());
     for (size_t i = 0; i < recs.size(); ++i) {
@@ -1314,6 +1335,24 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
     while ((prog.size() - h0) % 16) prog.push_back(0);
   }
   return true;
+}
+
+// The smallest tile-kernel body whose steps cover a pass program.
+template <typename T>
+static int program_body(const int32_t* pass) {
+  const int t = pass[0], nns = pass[2], nrounds = pass[3];
+  const int32_t* roff = pass + 4 + t + nns;
+  int body = kBodyLean;
+  for (int r = 0; r < nrounds; ++r) {
+    const int32_t* b = pass + roff[r];
+    const int32_t* rec = b + kRoundHeader;
+    for (int l = 0; l < b[0]; ++l) {
+      if (rec[0] & (LT_RAWD | LT_U2 | LT_U1)) return kBodyFull;
+      if (rec[0] & LT_PERM2) body = kBodyPerm;
+      rec += LayerRec<T>::W + ((rec[0] & LT_TAB) ? kTableWords : 0);
+    }
+  }
+  return body;
 }
 
 // Whether a pass program uses steps beyond the lean tile body (tables, CZ
@@ -1414,7 +1453,7 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
       continue;
     }
     QSV_HIP(launch_tile_pass<T>(static_cast<cpx<T>*>(s->psi), n, dprog + offs[k], prog.data() + offs[k],
-                                program_needs_full<T>(prog.data() + offs[k]), s->stream));
+                                program_body<T>(prog.data() + offs[k]), s->stream));
   }
   return QSV_OK;
 }

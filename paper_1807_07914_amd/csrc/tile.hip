@@ -141,8 +141,12 @@ __device__ __forceinline__ void table_step(cpx<T> (&a)[1 << RB], const int32_t* 
       zr = __int_as_float(tp[2 * m]);
       zi = __int_as_float(tp[2 * m + 1]);
     } else {
-      zr = __hiloint2double(tp[4 * m + 1], tp[4 * m]);
-      zi = __hiloint2double(tp[4 * m + 3], tp[4 * m + 2]);
+      // through readfirstlane: left to itself the compiler read the real
+      // parts with vector loads, whose waits covered the next tile's prefetch
+      zr = __hiloint2double(__builtin_amdgcn_readfirstlane(tp[4 * m + 1]),
+                            __builtin_amdgcn_readfirstlane(tp[4 * m]));
+      zi = __hiloint2double(__builtin_amdgcn_readfirstlane(tp[4 * m + 3]),
+                            __builtin_amdgcn_readfirstlane(tp[4 * m + 2]));
     }
     cmul(a[m], zr, zi);
   }
@@ -180,34 +184,29 @@ __device__ __forceinline__ void u2(cpx<T> (&a)[1 << RB], const M4<T>& U) {
   }
 }
 
-// CNOT / SWAP on register bits: pure register renaming
-template <typename T, int RB, int J0, int J1, int CODE>
-__device__ __forceinline__ void perm2(cpx<T> (&a)[1 << RB]) {
+// LDS offsets of the images of the register bits under a CNOT / SWAP of
+// register bits j0 < j1 (code as in LT_PERM2; code < 0: the identity): the
+// register index map is linear, so the offset of P m is the XOR of these
+// over the bits of m.
+template <int RB>
+__device__ __forceinline__ void perm_images(const uint32_t (&bofs)[RB], int code, int j0, int j1,
+                                            uint32_t (&out)[RB]) {
 #pragma unroll
-  for (int m = 0; m < (1 << RB); ++m) {
-    if (((m >> J0) & 1) || ((m >> J1) & 1)) continue;
-    const int i1 = m | (1 << J0), i2 = m | (1 << J1), i3 = m | (1 << J0) | (1 << J1);
-    if (CODE == 0) {
-      const cpx<T> x = a[i1];
-      a[i1] = a[i3];
-      a[i3] = x;
-    } else if (CODE == 1) {
-      const cpx<T> x = a[i2];
-      a[i2] = a[i3];
-      a[i3] = x;
-    } else {
-      const cpx<T> x = a[i1];
-      a[i1] = a[i2];
-      a[i2] = x;
+  for (int j = 0; j < RB; ++j) {
+    uint32_t v = bofs[j];
+    if (code == 2) {  // SWAP: the two bits trade places
+      if (j == j0) v = bofs[j1];
+      if (j == j1) v = bofs[j0];
+    } else if (code == 0) {  // CNOT, control j0: e_j0 -> e_j0 + e_j1
+      if (j == j0) v = bofs[j0] ^ bofs[j1];
+    } else if (code == 1) {  // CNOT, control j1
+      if (j == j1) v = bofs[j1] ^ bofs[j0];
     }
+    out[j] = v;
   }
 }
 
-// Dispatchers on register bits.  Each variant is an independent `if`
-// rather than one arm of an else-if chain: arms of a chain that all rewrite
-// the amplitudes are merged in one place, and the register allocator then
-// copies every amplitude on the paths that skip the step.
-// sign change of the amplitudes with register bits J and K set (CZ)
+// CZ between register bits J and K: the amplitudes with both bits set change sign
 template <typename T, int RB, int J, int K>
 __device__ __forceinline__ void cz_pair(cpx<T> (&a)[1 << RB]) {
 #pragma unroll
@@ -250,32 +249,6 @@ __device__ __forceinline__ void dispatch_u2(cpx<T> (&a)[1 << RB], int j0, int j1
   }
 }
 
-template <typename T, int RB, int J0, int J1>
-__device__ __forceinline__ void perm2_code(cpx<T> (&a)[1 << RB], int key, int code) {
-  if (key == J0 * 8 + J1) {
-    if (code == 0) perm2<T, RB, J0, J1, 0>(a);
-    if (code == 1) perm2<T, RB, J0, J1, 1>(a);
-    if (code == 2) perm2<T, RB, J0, J1, 2>(a);
-  }
-}
-
-template <typename T, int RB>
-__device__ __forceinline__ void dispatch_perm2(cpx<T> (&a)[1 << RB], int j0, int j1, int code) {
-  constexpr int H = RB > 4 ? 4 : 3;
-  const int key = j0 * 8 + j1;
-  perm2_code<T, RB, 0, 1>(a, key, code);
-  perm2_code<T, RB, 0, 2>(a, key, code);
-  perm2_code<T, RB, 0, 3>(a, key, code);
-  perm2_code<T, RB, 1, 2>(a, key, code);
-  perm2_code<T, RB, 1, 3>(a, key, code);
-  perm2_code<T, RB, 2, 3>(a, key, code);
-  if constexpr (RB > 4) {
-    perm2_code<T, RB, 0, H>(a, key, code);
-    perm2_code<T, RB, 1, H>(a, key, code);
-    perm2_code<T, RB, 2, H>(a, key, code);
-    perm2_code<T, RB, 3, H>(a, key, code);
-  }
-}
 
 // value of a diagonal operand bit that does not depend on m (free / outside)
 __device__ __forceinline__ int const_bit(int kind, int val, uint32_t lg, uint64_t base) {
@@ -309,7 +282,7 @@ __device__ __forceinline__ double aux_real<double>(const int32_t* __restrict__ a
 // tile held in LDS at `tb`.  Round headers, layer records, aux words and
 // tables are read with scalar loads (the addresses are uniform), so every
 // field lands in a scalar register.  Every round ends with a barrier.
-template <typename T, int TBMAX, int RB, bool FULL>
+template <typename T, int TBMAX, int RB, int BODY>
 __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t* __restrict__ pass, int t,
                                            int nns, uint64_t base) {
   constexpr int NR = 1 << RB;
@@ -379,6 +352,7 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
           a[i ^ (i >> 1)] = *reinterpret_cast<const cpx<T>*>(tb + ad);
         }
       }
+
 
       // A record's table follows it, so that its address does not wait for
       // a word of the record.
@@ -478,7 +452,7 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
               if (j < 0 || ((m >> j) & 1)) cmul_lane(a[m], zr, zi);
           }
         }
-        if (FULL && (flags & LT_RAWD)) {
+        if (BODY == kBodyFull && (flags & LT_RAWD)) {
           // a diagonal factor d = (1 + c) exp(i phi) per operand value, as
           // (p, q, c) triples: PHASE1 two (by the qubit's bit), DIAG2 four
           const int type = ap[p], ka = ap[p + 1], va = ap[p + 2];
@@ -520,11 +494,36 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
         QSV_ROT(3)
         QSV_ROT(4)
 #undef QSV_ROT
-        if (FULL && (flags & LT_PERM2)) {
-          dispatch_perm2<T, RB>(a, ap[p], ap[p + 1], ap[p + 2]);
+        if (BODY >= kBodyPerm && (flags & LT_PERM2)) {
+          // A CNOT or SWAP of two register bits is a linear map m -> P m of
+          // the register index.  Each amplitude goes through the group's own
+          // LDS slots (no other thread touches them during the round): a[m]
+          // is written to the slot of P m, whose address walks the images of
+          // the register bits, then every slot is read back in order.  Static
+          // register indices only: a runtime choice among register
+          // permutations made the compiler keep a second copy of the group.
+          const int j0 = ap[p], j1 = ap[p + 1], code = ap[p + 2];
           p += 3;
+          {
+            uint32_t pb[RB];
+            perm_images<RB>(bofs, code, j0, j1, pb);
+            uint32_t ad = sgb;
+            asm volatile("" : "+v"(ad));
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+              if (i > 0) ad ^= pb[__builtin_ctz(i)];
+              *reinterpret_cast<cpx<T>*>(tb + ad) = a[i ^ (i >> 1)];
+            }
+            ad = sgb;
+            asm volatile("" : "+v"(ad));
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+              if (i > 0) ad ^= bofs[__builtin_ctz(i)];
+              a[i ^ (i >> 1)] = *reinterpret_cast<const cpx<T>*>(tb + ad);
+            }
+          }
         }
-        if (FULL && (flags & LT_U2)) {
+        if (BODY == kBodyFull && (flags & LT_U2)) {
           const int j0 = ap[p], j1 = ap[p + 1];
           M4<T> U;
 #pragma unroll
@@ -533,7 +532,7 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
           p += 2 + 32 * WT;
           dispatch_u2<T, RB>(a, j0, j1, U);
         }
-        if (FULL && (flags & LT_U1)) {
+        if (BODY == kBodyFull && (flags & LT_U1)) {
           const int j = ap[p];
           M2<T> U;
 #pragma unroll
@@ -545,11 +544,16 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
       {
         // recomputed rather than kept from the load walk: 2^RB live
         // addresses would cost as many registers
+        // the store's offsets (the header's; a permutation that ends the
+        // round is folded into them)
+        uint32_t sofs[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) sofs[j] = (uint32_t)rb[kHdrStore + j];
         uint32_t ad = sgb;
         asm volatile("" : "+v"(ad));
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-          if (i > 0) ad ^= bofs[__builtin_ctz(i)];
+          if (i > 0) ad ^= sofs[__builtin_ctz(i)];
           *reinterpret_cast<cpx<T>*>(tb + ad) = a[i ^ (i >> 1)];
         }
       }
@@ -573,11 +577,13 @@ struct TileIO {
 
 // One fused tile pass over tile `tid` of the pass program `prog`; returns the
 // thread's partial of the Z-string sum (0 unless io.reduce).  Ends with a
-// barrier so that the caller can start another tile at once.  FULL = false
-// compiles only the table, magnitude, sign, per-group phase and rotation
-// steps (the host uses it for passes without the other steps): far fewer
-// registers, so that more workgroups share a compute unit.
-template <typename T, int TBMAX, int RB, bool FULL>
+// barrier so that the caller can start another tile at once.  BODY selects
+// the steps compiled in (kBodyLean: tables, magnitudes, signs, per-group
+// phases and rotations; kBodyPerm: those and register permutations;
+// kBodyFull: every step): the host picks the smallest body a pass needs,
+// since fewer registers let more workgroups share a compute unit and the
+// full body spills.
+template <typename T, int TBMAX, int RB, int BODY>
 __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int32_t* __restrict__ prog,
                                             uint64_t tid, const TileIO& io) {
   constexpr int A = VecInfo<T>::A;
@@ -629,7 +635,7 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
   __syncthreads();
 
   // ---- rounds
-  run_rounds<T, TBMAX, RB, FULL>(reinterpret_cast<char*>(tile), prog, t, nns, base);
+  run_rounds<T, TBMAX, RB, BODY>(reinterpret_cast<char*>(tile), prog, t, nns, base);
 
   // ---- Z-string sum over the tile (FP64)
   double acc = 0.0;
@@ -663,11 +669,11 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
   return acc;
 }
 
-template <typename T, int TBMAX, int RB, bool FULL, int MINWG>
+template <typename T, int TBMAX, int RB, int BODY, int MINWG>
 __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile(cpx<T>* __restrict__ psi,
                                                               const int32_t* __restrict__ prog) {
   const TileIO io{0, 1, 0, nullptr, nullptr, 0};
-  (void)tile_body<T, TBMAX, RB, FULL>(psi, prog, blockIdx.x, io);
+  (void)tile_body<T, TBMAX, RB, BODY>(psi, prog, blockIdx.x, io);
 }
 
 // A 16-byte vector of amplitudes (two complex64 or one complex128) as a
@@ -707,7 +713,7 @@ struct StageVec<double> {
 // with scalar loads only, so no wait inside them covers those vector loads
 // (which complete in order).  Used for lean passes over tiles of exactly
 // 2^TBMAX amplitudes.
-template <typename T, int TBMAX, int RB, bool FULL, int MINWG>
+template <typename T, int TBMAX, int RB, int BODY, int MINWG>
 __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile_pipe(cpx<T>* __restrict__ psi,
                                                                    const int32_t* __restrict__ prog,
                                                                    uint64_t ntiles) {
@@ -765,7 +771,7 @@ __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile_pipe(cpx<T>* __res
   if (tid + gridDim.x < ntiles) fetch(tid + gridDim.x);
   for (;;) {
     const uint64_t base = tile_base(tid);
-    run_rounds<T, TBMAX, RB, FULL>(reinterpret_cast<char*>(tile), prog, t, nns, base);
+    run_rounds<T, TBMAX, RB, BODY>(reinterpret_cast<char*>(tile), prog, t, nns, base);
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
       const uint32_t l = (uint32_t)(threadIdx.x + k * kTileThreads) * A;
@@ -865,7 +871,7 @@ __device__ __forceinline__ double batch_pass(cpx<T>* __restrict__ psi, const int
         }
       }
     }
-    run_rounds<T, TBMAX, RB, false>(reinterpret_cast<char*>(tile), prog, t, nns, base);
+    run_rounds<T, TBMAX, RB, kBodyLean>(reinterpret_cast<char*>(tile), prog, t, nns, base);
     if (io.reduce) {
       for (int l = threadIdx.x; l < (1 << t); l += kTileThreads) {
         const uint64_t g = base | segoff[(uint32_t)l >> c] | ((uint32_t)l & cmask);
@@ -938,7 +944,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_batch(cpx<T>* __restrict__ 
       const TileIO io{p == 0, p + 1 < np, p + 1 == np, zt + t0, ct + t0, (int)nt};
       if constexpr (FULL) {
         for (uint64_t tid = 0; tid < ntiles; ++tid)
-          acc += tile_body<T, TBMAX, RB, true>(scratch + soff, prog, tid, io);
+          acc += tile_body<T, TBMAX, RB, kBodyFull>(scratch + soff, prog, tid, io);
       } else {
         acc += batch_pass<T, TBMAX, RB>(scratch + soff, prog, ntiles, io);
       }
@@ -981,14 +987,14 @@ int tile_swizzle_bits() {
 // LDS buffer; with the lean body three workgroups then share a compute unit.
 
 // Workgroups of a kernel that fit the device at once (cached per device).
-template <typename T, int TB, int RB, bool FULL, int MINWG>
+template <typename T, int TB, int RB, int BODY, int MINWG>
 static int pipe_grid() {
   static int cache[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
   if (cache[dev] == 0) {
     int per_cu = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_pipe<T, TB, RB, FULL, MINWG>, kTileThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_pipe<T, TB, RB, BODY, MINWG>, kTileThreads, 0) !=
             hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return 0;
@@ -997,26 +1003,26 @@ static int pipe_grid() {
   return cache[dev];
 }
 
-template <typename T, int TB, int RB, bool FULL, int MINWG>
+template <typename T, int TB, int RB, int BODY, int MINWG>
 static hipError_t launch_pass(cpx<T>* psi, const int32_t* prog_dev, uint64_t ntiles, bool pipe, hipStream_t st) {
-  if constexpr (TB == TileCfg<T>::TBMAX && (!FULL || sizeof(T) == 4)) {
-    const int resident = pipe ? pipe_grid<T, TB, RB, FULL, MINWG>() : 0;
+  if constexpr (TB == TileCfg<T>::TBMAX && (BODY != kBodyFull || sizeof(T) == 4)) {
+    const int resident = pipe ? pipe_grid<T, TB, RB, BODY, MINWG>() : 0;
     if (resident > 0) {
       const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, (uint64_t)resident);
-      hipLaunchKernelGGL((k_tile_pipe<T, TB, RB, FULL, MINWG>), dim3(grid), dim3(kTileThreads), 0, st, psi,
+      hipLaunchKernelGGL((k_tile_pipe<T, TB, RB, BODY, MINWG>), dim3(grid), dim3(kTileThreads), 0, st, psi,
                          prog_dev, ntiles);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_tile<T, TB, RB, FULL, MINWG>), dim3((unsigned)ntiles), dim3(kTileThreads), 0, st, psi,
+  hipLaunchKernelGGL((k_tile<T, TB, RB, BODY, MINWG>), dim3((unsigned)ntiles), dim3(kTileThreads), 0, st, psi,
                      prog_dev);
   return hipGetLastError();
 }
 
 // One fused tile pass.  `prog_host` is the host copy of the pass program
-// (its header is read here).
+// (its header is read here); body is the smallest body its steps need.
 template <typename T>
-hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const int32_t* prog_host, bool full,
+hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const int32_t* prog_host, int body,
                             hipStream_t st) {
   constexpr int TB = TileCfg<T>::TBMAX, RB = TileCfg<T>::RB;
   const int t = prog_host[0], c = prog_host[1];
@@ -1027,13 +1033,15 @@ hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const i
   // full-size tiles only (for half-size tiles the extra registers and LDS
   // cost a workgroup per compute unit, more than the overlap gains); full
   // body only for complex64 (the complex128 one would spill heavily).
-  const bool pipe = (!full || sizeof(T) == 4) && !small && t - c <= tbits - SwzBits<T>::B;
+  const bool pipe = (body != kBodyFull || sizeof(T) == 4) && !small && t - c <= tbits - SwzBits<T>::B;
   if (small) {
-    if (full) return launch_pass<T, TB - 1, RB, true, 2>(psi, prog_dev, ntiles, pipe, st);
-    return launch_pass<T, TB - 1, RB, false, 3>(psi, prog_dev, ntiles, pipe, st);
+    if (body == kBodyFull) return launch_pass<T, TB - 1, RB, kBodyFull, 2>(psi, prog_dev, ntiles, pipe, st);
+    if (body == kBodyPerm) return launch_pass<T, TB - 1, RB, kBodyPerm, 3>(psi, prog_dev, ntiles, pipe, st);
+    return launch_pass<T, TB - 1, RB, kBodyLean, 3>(psi, prog_dev, ntiles, pipe, st);
   }
-  if (full) return launch_pass<T, TB, RB, true, 2>(psi, prog_dev, ntiles, pipe, st);
-  return launch_pass<T, TB, RB, false, 2>(psi, prog_dev, ntiles, pipe, st);
+  if (body == kBodyFull) return launch_pass<T, TB, RB, kBodyFull, 2>(psi, prog_dev, ntiles, pipe, st);
+  if (body == kBodyPerm) return launch_pass<T, TB, RB, kBodyPerm, 2>(psi, prog_dev, ntiles, pipe, st);
+  return launch_pass<T, TB, RB, kBodyLean, 2>(psi, prog_dev, ntiles, pipe, st);
 }
 
 template <typename T>
@@ -1062,7 +1070,7 @@ template int tile_reg_bits<float>();
 template int tile_reg_bits<double>();
 template int tile_swizzle_bits<float>();
 template int tile_swizzle_bits<double>();
-template hipError_t launch_tile_pass<float>(cpx<float>*, int, const int32_t*, const int32_t*, bool, hipStream_t);
-template hipError_t launch_tile_pass<double>(cpx<double>*, int, const int32_t*, const int32_t*, bool, hipStream_t);
+template hipError_t launch_tile_pass<float>(cpx<float>*, int, const int32_t*, const int32_t*, int, hipStream_t);
+template hipError_t launch_tile_pass<double>(cpx<double>*, int, const int32_t*, const int32_t*, int, hipStream_t);
 
 }  // namespace qsv

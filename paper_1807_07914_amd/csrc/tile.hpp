@@ -25,8 +25,13 @@
 //                 those of its bits), and in the first round block only
 //                 [kHdrTileFac] the word offset (from the start of the pass)
 //                 of the pass's tile-factor list, 0 if it has none, and
-//                 [kHdrTileFac + 1] its number of slots K; then the n_layers
-//                 layer records of
+//                 [kHdrTileFac + 1] its number of slots K; in every round
+//                 block [kHdrStore + j] the LDS byte offset the round's
+//                 store uses for register bit j: the same as [2 + j], or,
+//                 when a CNOT / SWAP of register bits ends the round, the
+//                 offset of that bit's image, so that the store writes
+//                 register combination m to the slot of P m at no cost;
+//                 then the n_layers layer records of
 //                 LayerRec<T>::W words, each followed by its table (64 words)
 //                 if it has LT_TAB; then the aux words of the records.
 //                 Offsets in a record count words from the start of its round
@@ -125,10 +130,15 @@ enum RawDiagType : int32_t { RAW_PHASE1 = 4, RAW_DIAG2 = 5 };
 enum TileOperandKind : int32_t { TK_REG = 0, TK_FREE = 1, TK_OUT = 2 };
 
 constexpr int kTileThreads = 256;
+// tile-kernel bodies: the steps compiled into a kernel variant
+constexpr int kBodyLean = 0;  // tables, CZ signs, group parities, per-group phases, rotations
+constexpr int kBodyPerm = 1;  // those and register permutations (LT_PERM2)
+constexpr int kBodyFull = 2;  // every step
 constexpr int kRoundHeader = 16;  // words of a round block header
 constexpr int kRecRot = 4;        // first rotation word of a layer record
 constexpr int kTableWords = 64;   // words of a table
 constexpr int kHdrTileFac = 8;    // round-header word of the tile-factor list offset
+constexpr int kHdrStore = 10;     // round-header words of the store's register-bit offsets
 constexpr int kMaxTileFactors = 128;  // tile-factor slots of one pass
 
 // words of a layer record: 4 + 2 * RB reals (RB = 5 floats, RB = 4 doubles)

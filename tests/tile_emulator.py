@@ -29,6 +29,7 @@ RAW_PHASE1, RAW_DIAG2 = 4, 5
 TK_REG, TK_FREE, TK_OUT = 0, 1, 2
 CFG = {"c64": dict(RB=5, SB=5, WT=1, LR=16), "c128": dict(RB=4, SB=4, WT=2, LR=24)}
 TILE_FAC_HDR, MAX_TILE_FACTORS = 8, 128  # round-header word of the tile-factor list; slot cap
+STORE_HDR = 10  # round-header words of the store's register-bit offsets
 
 
 def program(n, dtype, ops, tile=0):
@@ -328,8 +329,15 @@ def run_pass(psi, n, words, off, cfg):
                         nxt = blk[recs_at[li + 1] + 3]
                         if nxt and flags & (LT_CZF | LT_SIGN | LT_PHASEL | LT_RAWD | LT_PERM2 | LT_U2 | LT_U1):
                             assert p == nxt, (hex(flags), p, nxt)
+                # the store walks its own register-bit offsets (a permutation
+                # that ends the round is folded into them)
+                ssw = [(blk[STORE_HDR + j] & 0xffffffff) // esz for j in range(RB)]
                 for m in range(NR):
-                    lds[sg ^ lmsw[m]] = a[m]
+                    o_ = 0
+                    for j in range(RB):
+                        if (m >> j) & 1:
+                            o_ ^= ssw[j]
+                    lds[sg ^ o_] = a[m]
         for l in range(1 << t):
             psi[gidx[l]] = lds[swizzle(l, SB)]
 
