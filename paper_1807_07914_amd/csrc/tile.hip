@@ -73,6 +73,12 @@ __device__ __forceinline__ void cmul(cpx<double>& x, double zr, double zi) {
       : "s"(zr), "s"(zi));
 }
 
+// 1 / sqrt(x): the hardware reciprocal square root in single precision
+// (about one ulp, the precision of the complex64 state), an exact division
+// and square root in double precision.
+__device__ __forceinline__ float inv_sqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
+
 // The same product for a factor that differs between lanes (VGPR operands).
 __device__ __forceinline__ void cmul_lane(cpx<float>& x, float zr, float zi) {
   float t;
@@ -443,7 +449,7 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
             // rounding of the factor product cannot change the norm
             T zr = w.x, zi = w.y;
             if (unit) {
-              const T inv = T(1) / sqrt(w.x * w.x + w.y * w.y);
+              const T inv = inv_sqrt(w.x * w.x + w.y * w.y);
               zr *= inv;
               zi *= inv;
             }
