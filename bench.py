@@ -291,6 +291,8 @@ def bench_mps(np, torch, qc, qsv, circuits=10, chi_max=32, cutoff=1e-4):
             if fid is not None:
                 row[rounds]["fidelity_vs_sv"] = fid
         out[n] = row
+        print("mps grid: n=%d done (%.1f ms per circuit at %d rounds)" % (n, row[rounds]["ms_per_circuit"], rounds),
+              file=sys.stderr, flush=True)
     return out
 
 
@@ -465,6 +467,7 @@ def main():
     ap.add_argument("--copy-ref", action="store_true",
                     help="run one plain 2 GiB device copy first (reference for HBM counters)")
     ap.add_argument("--mps-circuits", type=int, default=10, help="circuits per cell of the MPS grid")
+    ap.add_argument("--mps-chi", type=int, default=32, help="bond cap of the MPS grid (at most 64)")
     ap.add_argument("--only", choices=["c3_qft30", "dense_blocks", "c4_batched", "c5_adjoint", "f1_paper_rounds", "f2_h2_sweep",
                                        "f3_mps"],
                     help="run one of the extra workloads alone and print its JSON (for profiling)")
@@ -485,7 +488,7 @@ def main():
         fn = {"c3_qft30": bench_qft30, "dense_blocks": bench_dense_blocks, "c4_batched": bench_batched, "c5_adjoint": bench_adjoint,
               "f1_paper_rounds": bench_rounds, "f2_h2_sweep": bench_h2_sweep,
               "f3_mps": bench_mps}[args.only]
-        kw = {"circuits": args.mps_circuits} if args.only == "f3_mps" else {}
+        kw = {"circuits": args.mps_circuits, "chi_max": args.mps_chi} if args.only == "f3_mps" else {}
         print(json.dumps({args.only: fn(np, torch, qc, qsv, **kw)}))
         return
 
@@ -622,7 +625,7 @@ def main():
         ex = {}
         ex["f1_paper_rounds"] = bench_rounds(np, torch, qc, qsv)
         ex["f2_h2_sweep"] = bench_h2_sweep(np, torch, qc, qsv)
-        ex["f3_mps"] = bench_mps(np, torch, qc, qsv, circuits=args.mps_circuits)
+        ex["f3_mps"] = bench_mps(np, torch, qc, qsv, circuits=args.mps_circuits, chi_max=args.mps_chi)
         result["extras"] = ex
 
     if not args.no_cpu_baseline:

@@ -97,12 +97,22 @@ typedef struct qsv_op {
  *   the circuit's output (an earlier qsv_apply_circuit of the same ops), so
  *   qsv_adjoint starts from it instead of applying the ops first; other
  *   calls require 0.
+ *   graph (qsv_apply_circuit in a fused mode only, 0 or 1): 1 = launch the
+ *   plan's tile passes as one hipGraph.  The state keeps one graph, captured
+ *   on the state's stream (which must not be the null stream) the first time
+ *   and again whenever the plan's structure, tile width or the state's
+ *   program buffer changes; other calls upload this call's program words
+ *   (the angles) and replay it.  Plans with steps that run as their own
+ *   kernels (matrices on more than two qubits, registers narrower than one
+ *   register group) are launched without a graph.  Calls with graph = 1 on
+ *   one state must not overlap a capture of its stream by the caller.
  *   Other fields are reserved and must be zero. */
 typedef struct qsv_plan_opts {
   int32_t mode;
   int32_t tile_qubits;
   int32_t state_is_output;
-  int32_t reserved[5];
+  int32_t graph;
+  int32_t reserved[4];
 } qsv_plan_opts;
 
 /* Allocate a state of n_qubits (1..QSV_MAX_QUBITS) initialised to |0...0>.
@@ -270,21 +280,24 @@ qsv_status qsv_batch_free(qsv_batch* b);
  * on the device; qubit q lives at site q.  A two-qubit gate on adjacent sites
  * contracts the two site tensors, applies the 4x4 gate, scales the rows by the
  * left bond's coefficients and splits the (2 chi_l) x (2 chi_l+2) block by a
- * one-sided Jacobi SVD in LDS; singular values not above `cutoff`, or not above
+ * one-sided Jacobi SVD (in LDS while the three bonds of the update are at
+ * most 32, else in a per-update device workspace of about 0.8 MB that the
+ * library allocates for MPSs with chi_max above 32); singular values not above `cutoff`, or not above
  * 1e-12 of the largest, are dropped, and at most chi_max are kept (at least
  * one); the state is not renormalised.  Gates on distant qubits are routed by
  * SWAP updates that bring the higher qubit next to the lower one and back.
  * One-qubit gates are folded into the next two-qubit update of their qubit.
  * Updates on disjoint sites run in one launch (one workgroup each).
  * ------------------------------------------------------------------- */
-#define QSV_MPS_MAX_CHI 32      /* largest bond dimension (LDS-resident SVD) */
+#define QSV_MPS_MAX_CHI 64      /* largest bond dimension (slot stride of the site tensors) */
 #define QSV_MPS_MAX_QUBITS 1024
 
 typedef struct qsv_mps qsv_mps;
 
 /* |0...0> on n_qubits (1..QSV_MPS_MAX_QUBITS); chi_max in 1..QSV_MPS_MAX_CHI;
  * cutoff >= 0 (the paper's default is 1e-4).  hip_stream NULL = the null
- * stream.  The library owns all device memory.  Errors: QSV_ERR_ARG,
+ * stream.  The library owns all device memory: n_qubits slots of
+ * 2 * QSV_MPS_MAX_CHI^2 complex128 entries (128 KiB each), whatever chi_max.  Errors: QSV_ERR_ARG,
  * QSV_ERR_OOM. */
 qsv_status qsv_mps_alloc(int n_qubits, int chi_max, double cutoff, void* hip_stream,
                          qsv_mps** out);

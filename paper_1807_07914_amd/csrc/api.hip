@@ -381,6 +381,8 @@ qsv_status qsv_free_state(qsv_state* s) {
   if (s->aux) (void)hipFree(s->aux);
   if (s->apbuf) (void)hipFree(s->apbuf);
   if (s->hpbuf) (void)hipFree(s->hpbuf);
+  if (s->fg_exec) (void)hipGraphExecDestroy(s->fg_exec);
+  if (s->fg_graph) (void)hipGraphDestroy(s->fg_graph);
   if (s->owns && s->psi) (void)hipFree(s->psi);
   s->magic = kDeadMagic;
   delete s;
@@ -452,7 +454,10 @@ qsv_status qsv_apply_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const q
   if (opts) o = *opts;
   if (o.mode < 0 || o.mode > 2) return fail(QSV_ERR_ARG, "mode must be 0, 1 or 2");
   if (o.state_is_output) return fail(QSV_ERR_ARG, "state_is_output applies to qsv_adjoint only");
-  for (int r = 0; r < 5; ++r)
+  if (o.graph != 0 && o.graph != 1) return fail(QSV_ERR_ARG, "graph must be 0 or 1");
+  if (o.graph && o.mode == 1) return fail(QSV_ERR_ARG, "graph applies to the fused modes only");
+  if (o.graph && !s->stream) return fail(QSV_ERR_ARG, "graph needs a state on a stream other than the null stream");
+  for (int r = 0; r < 4; ++r)
     if (o.reserved[r]) return fail(QSV_ERR_ARG, "reserved plan option fields must be zero");
   for (int i = 0; i < n_ops; ++i) {
     qsv_status st = validate_op(s, ops[i]);
@@ -1456,7 +1461,8 @@ qsv_status qsv_adjoint(qsv_state* s, const qsv_op* ops, int n_ops, const uint64_
   if (opts) o = *opts;
   if (o.mode < 0 || o.mode > 2) return fail(QSV_ERR_ARG, "mode must be 0, 1 or 2");
   if (o.state_is_output != 0 && o.state_is_output != 1) return fail(QSV_ERR_ARG, "state_is_output must be 0 or 1");
-  for (int r = 0; r < 5; ++r)
+  if (o.graph) return fail(QSV_ERR_ARG, "graph applies to qsv_apply_circuit only");
+  for (int r = 0; r < 4; ++r)
     if (o.reserved[r]) return fail(QSV_ERR_ARG, "reserved plan option fields must be zero");
   for (int i = 0; i < n_ops; ++i) {
     st = validate_op(s, ops[i]);

@@ -1373,6 +1373,52 @@ static bool program_needs_full(const int32_t* pass) {
 }
 
 // ------------------------------------------------------------- driver
+// Launch a plan whose steps are all tile passes through the state's graph:
+// capture the passes once for what their launches depend on (the signature
+// below), replay afterwards.  The program words were uploaded to dprog on
+// the same stream just before, so a replay runs this call's angles.
+template <typename T>
+static qsv_status launch_fused_graph(qsv_state* s, const Schedule& sch, const std::vector<int32_t>& prog,
+                                     const std::vector<size_t>& offs, const int32_t* dprog) {
+  std::vector<uint64_t> sig = {sizeof(T), (uint64_t)s->n, (uint64_t)(uintptr_t)s->psi, (uint64_t)(uintptr_t)dprog,
+                               (uint64_t)(uintptr_t)s->stream};
+  std::vector<int> body(sch.steps.size());
+  for (size_t k = 0; k < sch.steps.size(); ++k) {
+    const int32_t* ph = prog.data() + offs[k];
+    body[k] = program_body<T>(ph);
+    sig.insert(sig.end(), {(uint64_t)offs[k], (uint64_t)body[k], (uint64_t)ph[0], (uint64_t)ph[1]});
+  }
+  if (!s->fg_exec || sig != s->fg_sig) {
+    if (s->fg_exec) (void)hipGraphExecDestroy(s->fg_exec);
+    if (s->fg_graph) (void)hipGraphDestroy(s->fg_graph);
+    s->fg_exec = nullptr;
+    s->fg_graph = nullptr;
+    s->fg_sig.clear();
+    QSV_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (size_t k = 0; k < sch.steps.size() && e == hipSuccess; ++k)
+      e = launch_tile_pass<T>(static_cast<cpx<T>*>(s->psi), s->n, dprog + offs[k], prog.data() + offs[k], body[k],
+                              s->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(e != hipSuccess ? e : e2, "fused plan capture");
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(e3, "hipGraphInstantiate(fused plan)");
+    }
+    s->fg_graph = g;
+    s->fg_exec = x;
+    s->fg_sig = std::move(sig);
+  }
+  QSV_HIP(hipGraphLaunch(s->fg_exec, s->stream));
+  return QSV_OK;
+}
+
 template <typename T>
 static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const qsv_plan_opts& opts) {
   const int RB = tile_reg_bits<T>();
@@ -1445,6 +1491,9 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
                            s->stream));
   qsv_status st0 = ensure_workspace(s, dense_ws_bytes());
   if (st0) return st0;
+  bool all_tile = true;
+  for (const Step& st : sch->steps) all_tile = all_tile && st.tile;
+  if (opts.graph && all_tile) return launch_fused_graph<T>(s, *sch, prog, offs, dprog);
   for (size_t k = 0; k < sch->steps.size(); ++k) {
     const Step& st = sch->steps[k];
     if (!st.tile) {

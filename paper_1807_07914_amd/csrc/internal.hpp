@@ -60,6 +60,12 @@ struct qsv_state {
   void* hpbuf = nullptr;  // programs of lambda = H psi by tile passes
   size_t hpbuf_bytes = 0;
   std::vector<int32_t> hhprog;
+  // graph of the last fused plan launched with plan option graph = 1, and
+  // what its launches were made from (dtype, n, psi, program buffer, stream,
+  // then per pass: word offset, body, tile and segment bits)
+  hipGraph_t fg_graph = nullptr;
+  hipGraphExec_t fg_exec = nullptr;
+  std::vector<uint64_t> fg_sig;
   std::atomic<int> busy{0};
 };
 

@@ -12,7 +12,9 @@
 // dims[b] is its dimension.  Every slot has the fixed stride kChi, so an
 // update never moves other sites.
 //
-// One two-site update (one workgroup of 256 threads, everything in LDS):
+// One two-site update (one workgroup of 512 threads; T' and M in LDS while
+// the update's three bonds are at most 32, else in a global workspace that
+// stays in the caches):
 //   T'[(a,s'), (t',c)] = sum_{s,t} G[s'+2t', s+2t] sum_m B_l[a,s,m] B_l+1[m,t,c]
 //   M = diag(Lambda_l) T'  -- the two-site block in mixed-canonical form
 //   one-sided Jacobi on the rows of M: a unitary from the left makes the rows
@@ -43,17 +45,20 @@ namespace qsv {
 namespace {
 
 constexpr int kChi = QSV_MPS_MAX_CHI;         // slot stride and largest bond
-constexpr int kRows = 2 * kChi;               // largest row / column count of M
+constexpr int kChiL = 32;                     // largest bond of an update staged in LDS
+constexpr int kRowsL = 2 * kChiL;             // row stride of T' and M in LDS
+constexpr int kRowsG = 2 * kChi;              // row stride of T' and M in global memory
 constexpr int kSlot = 2 * kChi * kChi;        // complex entries per site slot
 constexpr int kThreads = 512;
 constexpr int kPairLanes = 16;                // lanes per Jacobi row pair (one DPP row)
+constexpr int kGroups = kThreads / kPairLanes;  // row pairs in flight per step
 constexpr int kMaxSweeps = 48;                // bound on Jacobi sweeps
 constexpr double kOrthTol = 1e-14;            // rotate while |<r_p,r_q>| > tol |r_p||r_q|
 constexpr double kZeroRel = 1e-12;            // numerical-zero rule for singular values
 constexpr double kZeroRow = 1e-13;            // rows below this fraction of |M|_F are not rotated
 constexpr uint32_t kMpsMagic = 0x5053514du;   // "MQSP"
 
-static_assert(kThreads / kPairLanes >= kRows / 2, "one lane group per row pair");
+static_assert(kGroups >= kRowsL / 2, "one lane group per row pair in the LDS path");
 static_assert(kPairLanes == 16, "the DPP group sum spans one 16-lane row");
 
 struct z2 {
@@ -103,34 +108,22 @@ __global__ void k_mps_init(z2* __restrict__ sites, double* __restrict__ lam, int
   if (i == 0) err[0] = 0;
 }
 
-// Two-site updates, one per workgroup; the jobs of one launch act on disjoint
-// sites.
-__global__ __launch_bounds__(kThreads) void k_mps_bond(z2* __restrict__ sites, double* __restrict__ lam,
-                                                        int* __restrict__ dims, const MpsJob* __restrict__ jobs,
-                                                        int chi_max, double cutoff, int* __restrict__ err) {
-  __shared__ z2 tp[kRows * kRows];   // T' (rows (a,s), columns (t,c), row stride kRows)
-  __shared__ z2 mr[kRows * kRows];   // first the staged site tensors, then M
-  __shared__ double sv[kRows];
-  __shared__ int order[kRows];
-  __shared__ int flags[kMaxSweeps];
-  __shared__ int keep_s;
-  __shared__ double red[kThreads];
-
-  const MpsJob& jb = jobs[blockIdx.x];
+// One two-site update by the workgroup, with T' and M at row stride ROWS in
+// tp and mr and the site tensors staged at sa and sb: LDS arrays for bonds up
+// to kChiL (ROWS = kRowsL), a slice of global memory (L2-resident) for larger
+// ones (ROWS = kRowsG).  The steps are the same either way.
+template <int ROWS>
+__device__ __forceinline__ void bond_update(z2* __restrict__ sites, double* __restrict__ lam, int* __restrict__ dims,
+                                            const MpsJob& jb, int cl, int cm, int cr, int chi_max, double cutoff,
+                                            z2* sa, z2* sb, z2* tp, z2* mr, double* sv, int* order, int* flags,
+                                            int* keep_s, double* red) {
   const int l = jb.site;
-  const int cl = dims[l], cm = dims[l + 1], cr = dims[l + 2];
   const int tid = threadIdx.x;
-  if (cl < 1 || cm < 1 || cr < 1 || cl > kChi || cm > kChi || cr > kChi) {  // uniform
-    if (tid == 0) err[0] = 1;
-    return;
-  }
   const int R = 2 * cl, L = 2 * cr;
   z2* A = sites + (size_t)l * kSlot;
   z2* B = A + kSlot;
 
   // stage B_l as [(2a+s) * cm + m] and B_l+1 as [(2m+t) * cr + c]
-  z2* sa = mr;
-  z2* sb = mr + kRows * kRows / 2;
   for (int i = tid; i < 2 * cl * cm; i += kThreads) {
     const int r = i / cm, m = i - r * cm;
     sa[i] = A[r * kChi + m];
@@ -158,7 +151,7 @@ __global__ __launch_bounds__(kThreads) void k_mps_bond(z2* __restrict__ sites, d
     for (int o = 0; o < 4; ++o) {
       z2 acc{0, 0};
       for (int k = 0; k < 4; ++k) zfma(acc, G[o * 4 + k], th[k]);
-      tp[(2 * a + (o & 1)) * kRows + (o >> 1) * cr + c] = acc;
+      tp[(2 * a + (o & 1)) * ROWS + (o >> 1) * cr + c] = acc;
     }
   }
   __syncthreads();
@@ -169,9 +162,9 @@ __global__ __launch_bounds__(kThreads) void k_mps_bond(z2* __restrict__ sites, d
   for (int i = tid; i < R * L; i += kThreads) {
     const int r = i / L, col = i - r * L;
     const double w = lam_l[r >> 1];
-    const z2 v = tp[r * kRows + col];
+    const z2 v = tp[r * ROWS + col];
     const z2 u{w * v.x, w * v.y};
-    mr[r * kRows + col] = u;
+    mr[r * ROWS + col] = u;
     part = fma(u.x, u.x, fma(u.y, u.y, part));
   }
   red[tid] = part;
@@ -188,23 +181,24 @@ __global__ __launch_bounds__(kThreads) void k_mps_bond(z2* __restrict__ sites, d
   const double zthr = kZeroRow * kZeroRow * red[0];
 
   // one-sided Jacobi on the rows of M, round-robin pairing: in each step
-  // every row belongs to one pair; a sweep of R-1 steps meets every pair once
+  // every row belongs to one pair; a sweep of R-1 steps meets every pair once.
+  // A lane group takes pairs grp, grp + kGroups, ... (one pair each in LDS).
   const int grp = tid / kPairLanes, lane = tid % kPairLanes;
   const int npairs = R / 2;
   for (int sw = 0; sw < kMaxSweeps; ++sw) {
     for (int step = 0; step < R - 1; ++step) {
-      if (grp < npairs) {
+      for (int pr = grp; pr < npairs; pr += kGroups) {
         int p, q;
-        if (grp == 0) {
+        if (pr == 0) {
           p = R - 1;
           q = step;
         } else {
-          p = (step + grp) % (R - 1);
-          q = (step - grp + R - 1) % (R - 1);
+          p = (step + pr) % (R - 1);
+          q = (step - pr + R - 1) % (R - 1);
         }
-        z2* rp = mr + p * kRows;
-        z2* rq = mr + q * kRows;
-        constexpr int kCols = kRows / kPairLanes;   // columns per lane at most
+        z2* rp = mr + p * ROWS;
+        z2* rq = mr + q * ROWS;
+        constexpr int kCols = ROWS / kPairLanes;   // columns per lane at most
         z2 xs[kCols], ys[kCols];
         double al = 0, be = 0, gr = 0, gi = 0;   // |r_p|^2, |r_q|^2, sum r_p conj(r_q)
 #pragma unroll
@@ -249,6 +243,9 @@ __global__ __launch_bounds__(kThreads) void k_mps_bond(z2* __restrict__ sites, d
           if (lane == 0) flags[sw] = 1;
         }
       }
+      // global-memory rows: the barrier also orders this step's writes
+      // before the next step's reads within the workgroup
+      if (ROWS == kRowsG) __threadfence_block();
       __syncthreads();
     }
     if (!flags[sw]) break;   // every thread reads the same value after the barrier
@@ -258,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void k_mps_bond(z2* __restrict__ sites, d
   for (int r = tid; r < R; r += kThreads) {
     double s2 = 0;
     for (int c = 0; c < L; ++c) {
-      const z2 v = mr[r * kRows + c];
+      const z2 v = mr[r * ROWS + c];
       s2 = fma(v.x, v.x, fma(v.y, v.y, s2));
     }
     sv[r] = sqrt(s2);
@@ -275,17 +272,17 @@ __global__ __launch_bounds__(kThreads) void k_mps_bond(z2* __restrict__ sites, d
     for (int j = 0; j < R; ++j) top = fmax(top, sv[j]);
     int cnt = 0;
     for (int j = 0; j < R; ++j) cnt += (sv[j] > cutoff) && (sv[j] > kZeroRel * top);
-    keep_s = max(1, min(cnt, min(chi_max, min(R, L))));
+    *keep_s = max(1, min(cnt, min(chi_max, min(R, L))));
   }
   __syncthreads();
-  const int k = keep_s;
+  const int k = *keep_s;
 
   // B_l+1'[j][t][c] = V^H[j][(t,c)]
   for (int i = tid; i < k * L; i += kThreads) {
     const int j = i / L, col = i - j * L;
     const int r = order[j];
     const double inv = sv[r] > 0 ? 1.0 / sv[r] : 0.0;
-    const z2 v = mr[r * kRows + col];
+    const z2 v = mr[r * ROWS + col];
     const int t = col / cr, c = col - t * cr;
     B[(2 * j + t) * kChi + c] = z2{v.x * inv, v.y * inv};
   }
@@ -294,13 +291,56 @@ __global__ __launch_bounds__(kThreads) void k_mps_bond(z2* __restrict__ sites, d
     const int r = i / k, j = i - r * k;
     const int rr = order[j];
     z2 acc{0, 0};
-    for (int col = 0; col < L; ++col) zfmac(acc, tp[r * kRows + col], mr[rr * kRows + col]);
+    for (int col = 0; col < L; ++col) zfmac(acc, tp[r * ROWS + col], mr[rr * ROWS + col]);
     const double inv = sv[rr] > 0 ? 1.0 / sv[rr] : 0.0;
     A[r * kChi + j] = z2{acc.x * inv, acc.y * inv};
   }
   double* lam_m = lam + (size_t)(l + 1) * kChi;
   for (int j = tid; j < kChi; j += kThreads) lam_m[j] = j < k ? sv[order[j]] : 0.0;
   if (tid == 0) dims[l + 1] = k;
+}
+
+// Global-memory workspace of one update (complex entries): the staged site
+// tensors, T' and M at row stride kRowsG.
+constexpr size_t kBondWsEntries = (size_t)4 * kChi * kChi + (size_t)2 * kRowsG * kRowsG;
+
+// Two-site updates, one per workgroup; the jobs of one launch act on disjoint
+// sites.  Updates whose three bonds are at most kChiL run in LDS; larger ones
+// use the job's slice of gws (kBondWsEntries entries; NULL when the MPS's
+// bond cap is at most kChiL, which keeps every bond there).
+__global__ __launch_bounds__(kThreads) void k_mps_bond(z2* __restrict__ sites, double* __restrict__ lam,
+                                                        int* __restrict__ dims, const MpsJob* __restrict__ jobs,
+                                                        int chi_max, double cutoff, int* __restrict__ err,
+                                                        z2* __restrict__ gws) {
+  __shared__ z2 ltp[kRowsL * kRowsL];   // T' in LDS (rows (a,s), columns (t,c))
+  __shared__ z2 lmr[kRowsL * kRowsL];   // first the staged site tensors, then M
+  __shared__ double sv[kRowsG];
+  __shared__ int order[kRowsG];
+  __shared__ int flags[kMaxSweeps];
+  __shared__ int keep_s;
+  __shared__ double red[kThreads];
+
+  const MpsJob& jb = jobs[blockIdx.x];
+  const int l = jb.site;
+  const int cl = dims[l], cm = dims[l + 1], cr = dims[l + 2];
+  if (cl < 1 || cm < 1 || cr < 1 || cl > kChi || cm > kChi || cr > kChi) {  // uniform
+    if (threadIdx.x == 0) err[0] = 1;
+    return;
+  }
+  if (cl <= kChiL && cm <= kChiL && cr <= kChiL) {  // uniform
+    bond_update<kRowsL>(sites, lam, dims, jb, cl, cm, cr, chi_max, cutoff, lmr, lmr + kRowsL * kRowsL / 2, ltp,
+                        lmr, sv, order, flags, &keep_s, red);
+  } else if (gws) {
+    z2* w = gws + (size_t)blockIdx.x * kBondWsEntries;
+    z2* sa = w;
+    z2* sb = sa + (size_t)2 * kChi * kChi;
+    z2* tp = sb + (size_t)2 * kChi * kChi;
+    z2* mr = tp + (size_t)kRowsG * kRowsG;
+    bond_update<kRowsG>(sites, lam, dims, jb, cl, cm, cr, chi_max, cutoff, sa, sb, tp, mr, sv, order, flags,
+                        &keep_s, red);
+  } else if (threadIdx.x == 0) {
+    err[0] = 1;
+  }
 }
 
 // One-site gates: B'[a][s'][b] = sum_s U[s'][s] B[a][s][b].
@@ -365,6 +405,8 @@ struct qsv_mps {
   int* err;
   qsv::MpsJob* jobs_dev;
   size_t jobs_cap;
+  qsv::z2* gws;       // workspaces of updates with bonds above the LDS limit
+  size_t gws_jobs;    // updates the workspace holds
   std::vector<qsv::MpsJob> jobs_host;   // source of the last upload, kept until the stream passes it
   uint64_t* idx_dev;
   qsv::z2* amp_dev;
@@ -409,6 +451,7 @@ void release(qsv_mps* m) {
   (void)hipFree(m->dims);
   (void)hipFree(m->err);
   (void)hipFree(m->jobs_dev);
+  (void)hipFree(m->gws);
   (void)hipFree(m->idx_dev);
   (void)hipFree(m->amp_dev);
 }
@@ -604,10 +647,22 @@ extern "C" qsv_status qsv_mps_apply_circuit(qsv_mps* m, const qsv_op* ops, int n
   }
   QSV_HIP(hipMemcpyAsync(m->jobs_dev, m->jobs_host.data(), m->jobs_host.size() * sizeof(MpsJob),
                          hipMemcpyHostToDevice, m->stream));
+  if (m->chi_max > kChiL) {  // bonds may outgrow LDS: one global workspace per update of a launch
+    size_t most = 0;
+    for (const auto& lc : launches) most = std::max<size_t>(most, lc.second > 0 ? (size_t)lc.second : 0);
+    if (most > m->gws_jobs) {
+      QSV_HIP(hipStreamSynchronize(m->stream));
+      (void)hipFree(m->gws);
+      m->gws = nullptr;
+      m->gws_jobs = 0;
+      QSV_HIP(hipMalloc(&m->gws, most * kBondWsEntries * sizeof(z2)));
+      m->gws_jobs = most;
+    }
+  }
   for (const auto& lc : launches) {
     if (lc.second > 0) {
       k_mps_bond<<<lc.second, kThreads, 0, m->stream>>>(m->sites, m->lam, m->dims, m->jobs_dev + lc.first,
-                                                        m->chi_max, m->cutoff, m->err);
+                                                        m->chi_max, m->cutoff, m->err, m->gws);
       m->bond_updates += lc.second;
     } else {
       k_mps_site<<<-lc.second, kThreads, 0, m->stream>>>(m->sites, m->dims, m->jobs_dev + lc.first);

@@ -41,7 +41,8 @@ class QsvOp(ctypes.Structure):
 
 class QsvPlanOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
-                ("state_is_output", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("state_is_output", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 assert ctypes.sizeof(QsvOp) == 64
@@ -263,11 +264,15 @@ class State:
         check(lib().qsv_apply_fused(self.handle, _i32(qubits), len(qubits),
                                     m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
-    def apply_circuit(self, ops, mode: str = "auto", tile_qubits: int = 0) -> None:
+    def apply_circuit(self, ops, mode: str = "auto", tile_qubits: int = 0, graph: bool = False) -> None:
+        """Apply a gate list.  graph=True launches the fused plan's passes as
+        the state's hipGraph (captured once per plan structure, replayed with
+        this call's angles); the state must be on a non-null stream."""
         ol = ops if isinstance(ops, OpList) else OpList(ops)
         opts = QsvPlanOpts()
         opts.mode = MODES[mode]
         opts.tile_qubits = int(tile_qubits)
+        opts.graph = 1 if graph else 0
         check(lib().qsv_apply_circuit(self.handle, ol.arr, ol.n, ctypes.byref(opts)))
 
     def plan_info(self, ops, tile_qubits: int = 0) -> dict:
@@ -397,7 +402,8 @@ class Batch:
             pass
 
 
-MPS_MAX_CHI = 32
+MPS_MAX_CHI = 64        # bond cap the library accepts (its slot stride)
+MPS_DEFAULT_CHI = 32    # bonds up to this size keep the whole SVD in LDS
 
 
 class MPS:
@@ -405,7 +411,7 @@ class MPS:
     coefficients per bond); qubit q lives at site q.  Gates are applied by
     two-site SVD updates with the given cutoff and bond-dimension cap."""
 
-    def __init__(self, n: int, chi_max: int = MPS_MAX_CHI, cutoff: float = 1e-4, stream=None):
+    def __init__(self, n: int, chi_max: int = MPS_DEFAULT_CHI, cutoff: float = 1e-4, stream=None):
         self.n = n
         h = ctypes.c_void_p()
         st = ctypes.c_void_p(stream.cuda_stream if stream is not None else None)

@@ -20,7 +20,8 @@ def test_library_exports_every_header_function():
 
 def test_plan_opts_layout():
     assert ctypes.sizeof(qsv.QsvPlanOpts) == 32
-    assert qsv.QsvPlanOpts.state_is_output.offset == 8 and qsv.QsvPlanOpts.reserved.offset == 12
+    assert qsv.QsvPlanOpts.state_is_output.offset == 8 and qsv.QsvPlanOpts.graph.offset == 12
+    assert qsv.QsvPlanOpts.reserved.offset == 16
 
 
 def test_op_struct_is_64_bytes():
@@ -49,7 +50,7 @@ def test_foreign_handles_rejected():
     assert b"invalid" in L.qsv_last_error()
 
 
-@pytest.mark.parametrize("n,chi,cut", [(0, 4, 1e-4), (1025, 4, 1e-4), (8, 0, 1e-4), (8, 33, 1e-4),
+@pytest.mark.parametrize("n,chi,cut", [(0, 4, 1e-4), (1025, 4, 1e-4), (8, 0, 1e-4), (8, 65, 1e-4),
                                        (8, 4, -1.0), (8, 4, float("nan")), (8, 4, float("inf"))])
 def test_mps_alloc_rejects_bad_arguments(n, chi, cut):
     # argument checks come before any device call, so they run without a GPU

@@ -47,17 +47,22 @@ def compare(m, ref, n, tol):
     return psi
 
 
-@pytest.mark.parametrize("n,seed", [(2, 1), (3, 2), (5, 3), (8, 4), (10, 5)])
-def test_exact_matches_oracles(n, seed):
+@pytest.mark.parametrize("n,seed,chi", [(2, 1, 32), (3, 2, 32), (5, 3, 32), (8, 4, 32), (10, 5, 32),
+                                        (12, 6, 64), (13, 7, 64)])
+def test_exact_matches_oracles(n, seed, chi):
+    # n = 12 reaches bond 64 in the middle (the workspace path), n = 13 keeps
+    # it there for two bonds; every smaller bond still runs in LDS
     ops = mixed_circuit(n, 12 * n, seed)
     ref = M.run(ops, n, cutoff=0.0)
-    m = gpu_mps(ops, n, 32, 0.0)
+    assert max(ref.bond_dims()) <= chi
+    m = gpu_mps(ops, n, chi, 0.0)
     psi = compare(m, ref, n, 1e-12)
     m.close()
     assert np.abs(psi - O.run(ops, n)).max() < 1e-12
 
 
-@pytest.mark.parametrize("n,chi,cutoff", [(10, 8, 1e-2), (10, 4, 0.0), (12, 32, 1e-4)])
+@pytest.mark.parametrize("n,chi,cutoff", [(10, 8, 1e-2), (10, 4, 0.0), (12, 32, 1e-4), (14, 48, 0.0),
+                                          (14, 64, 1e-4)])
 def test_truncated_matches_oracle(n, chi, cutoff):
     ops = haar_brickwork(n, 12, 100 + n + chi)
     ref = M.run(ops, n, chi_max=chi, cutoff=cutoff)
@@ -138,6 +143,6 @@ def test_edge_cases_and_errors():
     dims, lam = m.bonds()
     m.close()
     assert dims == [1] * 6 and abs(lam[3][0] - 1.0) < 1e-12
-    for bad in ((0, 4, 0.0), (4, 0, 0.0), (4, 33, 0.0), (4, 4, -1.0)):
+    for bad in ((0, 4, 0.0), (4, 0, 0.0), (4, 65, 0.0), (4, 4, -1.0)):
         with pytest.raises(QsvError):
             MPS(*bad)

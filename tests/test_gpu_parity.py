@@ -228,6 +228,28 @@ def test_sample_parity(dtype, n):
     assert got.max() < (1 << n)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [4, 20])
+def test_sample_distribution_chi2(dtype, n):
+    # shots drawn on the GPU from a fused state follow |psi|^2 of the
+    # oracle's state: Pearson chi^2 over 16 bins (all outcomes at n = 4, the
+    # top four qubits' marginal at n = 20), 15 degrees of freedom; 40 is
+    # exceeded with probability ~4e-4
+    ops = qc.random_brickwork(n, 8, 930 + n)
+    p = np.abs(O.run(ops, n)) ** 2
+    shift = n - 4
+    pb = p.reshape(16, 1 << shift).sum(axis=1)
+    u = np.random.default_rng(940 + n).random(400000)
+    s = State(n, dtype)
+    s.apply_circuit(ops)
+    got = s.sample(u)
+    s.close()
+    counts = np.bincount((got.astype(np.int64) >> shift), minlength=16)
+    assert counts.sum() == u.size
+    chi2 = float(((counts - pb * u.size) ** 2 / (pb * u.size)).sum())
+    assert chi2 < 40, chi2
+
+
 def test_ghz_and_qft_closed_forms_medium():
     n = 18
     s = State(n, "c64")
