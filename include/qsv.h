@@ -90,8 +90,9 @@ typedef struct qsv_op {
 } qsv_op;
 
 /* Execution strategy of qsv_apply_circuit.
- *   mode 0 = automatic (fused tile passes), 1 = one kernel per gate
- *   ("plain per-gate form"), 2 = fused tile passes.
+ *   mode 0 = automatic (fused tile passes; the per-gate form when the
+ *   environment has QSV_FORCE_PERGATE=1, read once per process), 1 = one
+ *   kernel per gate ("plain per-gate form"), 2 = fused tile passes.
  *   tile_qubits: qubits per LDS tile in fused mode (0 = library choice).
  *   state_is_output (qsv_adjoint only, 0 or 1): 1 = the state already holds
  *   the circuit's output (an earlier qsv_apply_circuit of the same ops), so
@@ -244,7 +245,10 @@ qsv_status qsv_sample(qsv_state* s, const double* uniforms, int n_shots, uint64_
  * runs it alone: circuits that fit one LDS tile never touch HBM, wider ones
  * stream tile passes through a scratch region owned by the batch.  Energies
  * accumulate in FP64.  tile_qubits 0 lets the autotuner time the candidate
- * tile widths on this batch and keep the fastest (cached per structure).
+ * tile widths on this batch and keep the fastest (cached per structure in
+ * the process; with QSV_AUTOTUNE_CACHE naming a file in the environment, the
+ * cache is read from that file at the first tuning and new results are
+ * appended to it, one line "<structure hash, hex> <tile qubits>" each).
  * The parameter-sweep loop of the paper's VQE listing (section V.B) is the
  * use case.  Creation allocates all device memory; runs allocate nothing.
  * Errors: QSV_ERR_ARG, QSV_ERR_UNSUPPORTED (wider gates), QSV_ERR_OOM. */

@@ -14,6 +14,8 @@
 // of it; matrices are filled in for every call.
 #include <algorithm>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -41,6 +43,8 @@ int tile_reg_bits();
 template <typename T>
 hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const int32_t* prog_host, int body,
                             hipStream_t st);
+template <typename T>
+hipError_t launch_qperm(cpx<T>* psi, int n, const int32_t* prog_dev, const int32_t* prog_host, hipStream_t st);
 
 using cd = std::complex<double>;
 
@@ -177,6 +181,7 @@ struct Round {
 struct Step {
   bool tile = true;
   int op = -1;              // fallback op (tile == false)
+  std::vector<int> inv;     // qubit-permutation pass: the involution (empty otherwise)
   std::vector<int> S;       // sorted tile qubits
   std::vector<Round> rounds;
 };
@@ -185,6 +190,7 @@ struct Schedule {
   std::vector<uint32_t> key;  // exact structure (guards against hash collisions)
   std::vector<Step> steps;
   int passes = 0;
+  bool relabeled = false;     // the steps apply the op list with its SWAPs relabeled away
 };
 
 // Dependency scan: the ops a pass over tile set S can apply, in program
@@ -355,6 +361,164 @@ static std::shared_ptr<Schedule> build_schedule(const std::vector<POp>& P, int n
     pending.swap(rest);
   }
   return sch;
+}
+
+// Contiguous low qubits of every tile (the HBM segment of c qubits): 5 for
+// complex64 (256-byte segments), 4 for complex128.  Every tile spends them,
+// so for complex64 the plan with 128-byte segments (one more qubit free per
+// tile) is taken when it needs fewer passes.  QSV_SEGMENT_QUBITS=4 or 5 in
+// the environment fixes the choice (read once per process; for measurement).
+static int env_segment_qubits() {
+  static const int v = [] {
+    const char* e = std::getenv("QSV_SEGMENT_QUBITS");
+    return (e && (e[0] == '4' || e[0] == '5') && e[1] == 0) ? e[0] - '0' : 0;
+  }();
+  return v;
+}
+static std::shared_ptr<Schedule> plan_tile_passes(const std::vector<POp>& P, int n, int t, bool f32, int RB) {
+  const int forced = env_segment_qubits();
+  int c = forced ? forced : (f32 ? 5 : 4);
+  if (!f32) c = 4;
+  if (c > t) c = t;
+  auto sch = build_schedule(P, n, t, c, RB);
+  if (f32 && !forced && c == 5) {
+    auto alt = build_schedule(P, n, t, 4, RB);
+    if (alt->passes < sch->passes) sch = alt;
+  }
+  return sch;
+}
+
+// SWAP relabeling.  A SWAP exchanges which physical bit holds which logical
+// qubit instead of moving amplitudes: lab[q] is the bit that holds logical
+// qubit q, every other op is rewritten onto lab of its qubits, and the state
+// is put back in order at the end by one permutation of the index bits,
+// out[x] = in[sigma(x)] with sigma(q) = lab[q].  Returns false when the list
+// has no SWAP.
+static bool relabel_swaps(const std::vector<qsv_op>& ops, int n, std::vector<qsv_op>& out, std::vector<int>& lab) {
+  lab.resize(n);
+  for (int q = 0; q < n; ++q) lab[q] = q;
+  out.clear();
+  bool any = false;
+  for (const qsv_op& o : ops) {
+    if (o.gate == QSV_SWAP) {
+      std::swap(lab[o.q[0]], lab[o.q[1]]);
+      any = true;
+      continue;
+    }
+    qsv_op r = o;
+    for (int j = 0; j < r.nq && j < 6; ++j) r.q[j] = lab[o.q[j]];
+    out.push_back(r);
+  }
+  return any;
+}
+
+// sigma as at most two involutions applied as passes, first a then b.  The
+// pass for v maps in to out[x] = in[v(x)], so the two give
+// out[x] = in[a(b(x))] and need a(b(q)) = sigma(q): on each cycle
+// c_0 -> c_1 -> ... of sigma, b(c_i) = c_(-i) and a(c_j) = c_(1-j) (both
+// reflections of the cycle).  An involution sigma is one pass; the identity
+// none.
+static std::vector<std::vector<int>> involution_passes(const std::vector<int>& sigma) {
+  const int n = (int)sigma.size();
+  bool ident = true, invol = true;
+  for (int q = 0; q < n; ++q) {
+    ident = ident && sigma[q] == q;
+    invol = invol && sigma[sigma[q]] == q;
+  }
+  if (ident) return {};
+  if (invol) return {sigma};
+  std::vector<int> a(n), b(n);
+  std::vector<char> seen(n, 0);
+  for (int q0 = 0; q0 < n; ++q0) {
+    if (seen[q0]) continue;
+    std::vector<int> cyc;
+    for (int q = q0; !seen[q]; q = sigma[q]) {
+      seen[q] = 1;
+      cyc.push_back(q);
+    }
+    const int k = (int)cyc.size();
+    for (int i = 0; i < k; ++i) {
+      b[cyc[i]] = cyc[(k - i) % k];
+      a[cyc[i]] = cyc[((1 - i) % k + k) % k];
+    }
+  }
+  return {a, b};
+}
+
+// The fused plan of a gate list (CNOTs expanded): tile passes and per-gate
+// steps, and, when the list has SWAPs and relabeling them away needs fewer
+// passes in all, the plan of the relabeled list followed by its
+// qubit-permutation passes.
+static std::shared_ptr<Schedule> plan_schedule(const std::vector<qsv_op>& xops, int n, int t, bool f32, int RB) {
+  std::vector<POp> P(xops.size());
+  for (size_t i = 0; i < xops.size(); ++i) P[i] = classify(xops[i]);
+  auto sch = plan_tile_passes(P, n, t, f32, RB);
+  std::vector<qsv_op> rops;
+  std::vector<int> lab;
+  if (!relabel_swaps(xops, n, rops, lab)) return sch;
+  std::vector<POp> R(rops.size());
+  for (size_t i = 0; i < rops.size(); ++i) R[i] = classify(rops[i]);
+  auto alt = plan_tile_passes(R, n, t, f32, RB);
+  const std::vector<std::vector<int>> inv = involution_passes(lab);
+  if (alt->passes + (int)inv.size() >= sch->passes) return sch;
+  for (const std::vector<int>& v : inv) {
+    Step st;
+    st.tile = false;
+    st.inv = v;
+    alt->steps.push_back(std::move(st));
+  }
+  alt->passes += (int)inv.size();
+  alt->relabeled = true;
+  return alt;
+}
+
+// The op list a schedule's steps index: the list itself, or with its SWAPs
+// relabeled away.
+static const std::vector<qsv_op>& step_ops(const Schedule& sch, const std::vector<qsv_op>& xops, int n,
+                                           std::vector<qsv_op>& buf) {
+  if (!sch.relabeled) return xops;
+  std::vector<int> lab;
+  relabel_swaps(xops, n, buf, lab);
+  return buf;
+}
+
+// Program of a qubit-permutation pass for the involution v (layout in
+// tile.hpp): S = the low c qubits, closed under v, then more of v's fixed
+// qubits and pairs, lowest first, up to QpermCfg<T>::TP qubits.
+template <typename T>
+static void emit_qperm(const std::vector<int>& v, int n, std::vector<int32_t>& prog) {
+  int t = std::min(QpermCfg<T>::TP, n);
+  int c = std::min(sizeof(T) == 4 ? 5 : 4, t);
+  std::vector<char> in(n, 0);
+  int cnt = 0;
+  for (int q = 0; q < c; ++q)
+    for (int r : {q, v[q]})
+      if (!in[r]) {
+        in[r] = 1;
+        ++cnt;
+      }
+  for (int q = 0; q < n && cnt < t; ++q) {
+    if (in[q]) continue;
+    const int need = v[q] == q ? 1 : 2;
+    if (cnt + need > t) continue;
+    in[q] = in[v[q]] = 1;
+    cnt += need;
+  }
+  t = cnt;
+  std::vector<int> S, nonS, pos(n, -1);
+  for (int q = 0; q < n; ++q) (in[q] ? S : nonS).push_back(q);
+  for (int k = 0; k < t; ++k) pos[S[k]] = k;
+  for (int i = 0; i < (int)nonS.size(); ++i) pos[nonS[i]] = i;
+  const size_t base = prog.size();
+  prog.push_back(t);
+  prog.push_back(c);
+  prog.push_back((int32_t)nonS.size());
+  prog.push_back(kPassQperm);
+  for (int q : S) prog.push_back(q);
+  for (int q : nonS) prog.push_back(q);
+  for (int q : S) prog.push_back(pos[v[q]]);
+  for (int q : nonS) prog.push_back(pos[v[q]]);
+  while ((prog.size() - base) % 16) prog.push_back(0);
 }
 
 // ------------------------------------------------------- schedule cache
@@ -1385,8 +1549,8 @@ static qsv_status launch_fused_graph(qsv_state* s, const Schedule& sch, const st
   std::vector<int> body(sch.steps.size());
   for (size_t k = 0; k < sch.steps.size(); ++k) {
     const int32_t* ph = prog.data() + offs[k];
-    body[k] = program_body<T>(ph);
-    sig.insert(sig.end(), {(uint64_t)offs[k], (uint64_t)body[k], (uint64_t)ph[0], (uint64_t)ph[1]});
+    body[k] = sch.steps[k].tile ? program_body<T>(ph) : -1;   // -1: qubit-permutation pass
+    sig.insert(sig.end(), {(uint64_t)offs[k], (uint64_t)(int64_t)body[k], (uint64_t)ph[0], (uint64_t)ph[1]});
   }
   if (!s->fg_exec || sig != s->fg_sig) {
     if (s->fg_exec) (void)hipGraphExecDestroy(s->fg_exec);
@@ -1397,8 +1561,10 @@ static qsv_status launch_fused_graph(qsv_state* s, const Schedule& sch, const st
     QSV_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (size_t k = 0; k < sch.steps.size() && e == hipSuccess; ++k)
-      e = launch_tile_pass<T>(static_cast<cpx<T>*>(s->psi), s->n, dprog + offs[k], prog.data() + offs[k], body[k],
-                              s->stream);
+      e = body[k] < 0 ? launch_qperm<T>(static_cast<cpx<T>*>(s->psi), s->n, dprog + offs[k], prog.data() + offs[k],
+                                        s->stream)
+                      : launch_tile_pass<T>(static_cast<cpx<T>*>(s->psi), s->n, dprog + offs[k],
+                                            prog.data() + offs[k], body[k], s->stream);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(s->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -1444,13 +1610,11 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
   // one workgroup per tile in the non-persistent tile kernel: the launch's
   // work-items (2^(n-t) * 256) must stay below 2^32
   if (n - t > 23) return fail(QSV_ERR_UNSUPPORTED, "tile_qubits too small for this register (over 2^23 tiles)");
-  int c = sizeof(T) == 4 ? 5 : 4;  // 256-byte contiguous segments
-  if (c > t) c = t;
-  if (t - c > TBMAX - 4) return fail(QSV_ERR_UNSUPPORTED, "tile shape exceeds segment table");
-
   std::vector<POp> P(n_ops);
   for (int i = 0; i < n_ops; ++i) P[i] = classify(ops[i]);
-  std::vector<uint32_t> key = structure_key(P, n, t, c, RB);
+  // the key carries the dtype in place of the segment width: the cached
+  // schedule holds the width the planner chose
+  std::vector<uint32_t> key = structure_key(P, n, t, sizeof(T) == 4 ? -1 : -2, RB);
   const uint64_t h = key_hash(key);
   std::shared_ptr<Schedule> sch;
   {
@@ -1459,19 +1623,27 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
     if (it != g_cache.end() && it->second->key == key) sch = it->second;
   }
   if (!sch) {
-    sch = build_schedule(P, n, t, c, RB);
+    sch = plan_schedule(xops, n, t, sizeof(T) == 4, RB);
     sch->key = std::move(key);
     std::lock_guard<std::mutex> lk(g_cache_mu);
     if (g_cache.size() > 256) g_cache.clear();
     g_cache[h] = sch;
   }
-  // materialise programs for all tile steps
+  // the ops the steps index (SWAPs relabeled away when the plan chose so)
+  std::vector<qsv_op> rbuf;
+  const std::vector<qsv_op>& sops = step_ops(*sch, xops, n, rbuf);
+  if (sch->relabeled) {
+    P.resize(sops.size());
+    for (size_t i = 0; i < sops.size(); ++i) P[i] = classify(sops[i]);
+  }
+  // materialise programs for all tile and permutation steps
   std::vector<int32_t>& prog = s->hprog;
   prog.clear();
   std::vector<size_t> offs;
   for (const Step& st : sch->steps) {
     offs.push_back(prog.size());
-    if (st.tile && !emit_pass<T>(st, P, n, c, RB, prog)) return fail(QSV_ERR_UNSUPPORTED, "a fused tile pass could not be encoded");
+    if (!st.inv.empty()) emit_qperm<T>(st.inv, n, prog);
+    if (st.tile && !emit_pass<T>(st, P, n, sch->c, RB, prog)) return fail(QSV_ERR_UNSUPPORTED, "a fused tile pass could not be encoded");
   }
   const size_t need = prog.size() * sizeof(int32_t) + 256;
   if (s->pbuf_bytes < need) {
@@ -1492,12 +1664,16 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
   qsv_status st0 = ensure_workspace(s, dense_ws_bytes());
   if (st0) return st0;
   bool all_tile = true;
-  for (const Step& st : sch->steps) all_tile = all_tile && st.tile;
+  for (const Step& st : sch->steps) all_tile = all_tile && (st.tile || !st.inv.empty());
   if (opts.graph && all_tile) return launch_fused_graph<T>(s, *sch, prog, offs, dprog);
   for (size_t k = 0; k < sch->steps.size(); ++k) {
     const Step& st = sch->steps[k];
+    if (!st.inv.empty()) {
+      QSV_HIP(launch_qperm<T>(static_cast<cpx<T>*>(s->psi), n, dprog + offs[k], prog.data() + offs[k], s->stream));
+      continue;
+    }
     if (!st.tile) {
-      qsv_status e = apply_op_pergate(s, ops[st.op], 0);
+      qsv_status e = apply_op_pergate(s, sops[st.op], 0);
       if (e) return e;
       continue;
     }
@@ -1527,8 +1703,19 @@ void plan_adjoint(const qsv_op* ops, int n_ops, int n, int t, int c, int RB, std
   }
 }
 
+// QSV_FORCE_PERGATE=1 in the environment turns the automatic mode into the
+// per-gate form (read once per process): a switch for comparing the two
+// forms, or for isolating a planner problem, without changing the caller.
+static bool force_pergate() {
+  static const bool on = [] {
+    const char* v = std::getenv("QSV_FORCE_PERGATE");
+    return v && v[0] == '1' && v[1] == 0;
+  }();
+  return on;
+}
+
 qsv_status run_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const qsv_plan_opts& opts) {
-  if (opts.mode == 1) {
+  if (opts.mode == 1 || (opts.mode == 0 && force_pergate())) {
     qsv_status st = ensure_workspace(s, dense_ws_bytes());
     if (st) return st;
     for (int i = 0; i < n_ops; ++i) {
@@ -1554,18 +1741,25 @@ qsv_status plan_program(const qsv_state* s, const qsv_op* ops, int n_ops, int ti
   const int n = s->n;
   if (n < RB) return fail(QSV_ERR_UNSUPPORTED, "register smaller than the register group");
   if (t > n) t = n;
-  int c = f ? 5 : 4;
-  if (c > t) c = t;
-  std::vector<qsv_op> xops;  // per-gate steps index this list (CNOTs expanded)
-  expand_cnots(ops, n_ops, xops);
-  ops = xops.data();
-  n_ops = (int)xops.size();
-  std::vector<POp> P(n_ops);
-  for (int i = 0; i < n_ops; ++i) P[i] = classify(ops[i]);
-  auto sch = build_schedule(P, n, t, c, RB);
+  std::vector<qsv_op> xops;  // per-gate steps index this list (CNOTs expanded; SWAPs relabeled
+  expand_cnots(ops, n_ops, xops);  // away when the plan ends in qubit-permutation passes)
+  auto sch = plan_schedule(xops, n, t, f, RB);
+  std::vector<qsv_op> rbuf;
+  const std::vector<qsv_op>& sops = step_ops(*sch, xops, n, rbuf);
+  std::vector<POp> P(sops.size());
+  for (size_t i = 0; i < sops.size(); ++i) P[i] = classify(sops[i]);
+  const int c = sch->c;
   prog.clear();
   steps.clear();
   for (const Step& st : sch->steps) {
+    if (!st.inv.empty()) {
+      steps.push_back((int64_t)prog.size());
+      if (f)
+        emit_qperm<float>(st.inv, n, prog);
+      else
+        emit_qperm<double>(st.inv, n, prog);
+      continue;
+    }
     if (!st.tile) {
       steps.push_back(-(int64_t)(1 + st.op));
       continue;
@@ -1587,15 +1781,11 @@ qsv_status plan_passes(const qsv_state* s, const qsv_op* ops, int n_ops, int til
   if (t > TBMAX || t < RB) return fail(QSV_ERR_ARG, "bad tile_qubits");
   const int n = s->n;
   if (t > n) t = n;
-  int c = f ? 5 : 4;
-  if (c > t) c = t;
   std::vector<qsv_op> xops;
   expand_cnots(ops, n_ops, xops);
-  std::vector<POp> P(xops.size());
-  for (size_t i = 0; i < xops.size(); ++i) P[i] = classify(xops[i]);
-  auto sch = build_schedule(P, n, t, c, RB);
+  auto sch = plan_schedule(xops, n, t, f, RB);
   int fb = 0;
-  for (const Step& st : sch->steps) fb += st.tile ? 0 : 1;
+  for (const Step& st : sch->steps) fb += (st.tile || !st.inv.empty()) ? 0 : 1;
   if (passes) *passes = sch->passes;
   if (fallback_ops) *fallback_ops = fb;
   return QSV_OK;
@@ -1654,6 +1844,38 @@ namespace qsv {
 static std::mutex g_batch_mu;
 static std::unordered_set<const qsv_batch*> g_batches;
 static std::unordered_map<uint64_t, int> g_tuned;  // structure hash -> tile bits
+
+// The autotuner's results persist across processes when QSV_AUTOTUNE_CACHE
+// names a file: it is read once, at the first tuning of the process, and
+// every new result is appended as a line "<structure hash, hex> <tile qubits>".
+// Unreadable lines end the read; a width outside the dtype's range is ignored
+// when it is looked up.  Callers hold g_batch_mu.
+static const char* tune_cache_path() {
+  const char* p = std::getenv("QSV_AUTOTUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+static void tuned_load_once() {
+  static bool loaded = false;
+  if (loaded) return;
+  loaded = true;
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  unsigned long long h = 0;
+  int t = 0;
+  while (std::fscanf(f, "%llx %d", &h, &t) == 2) g_tuned[(uint64_t)h] = t;
+  std::fclose(f);
+}
+static void tuned_store(uint64_t h, int t) {
+  g_tuned[h] = t;
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%016llx %d\n", (unsigned long long)h, t);
+  std::fclose(f);
+}
 
 static void batch_release_device(qsv_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -1842,8 +2064,9 @@ static qsv_status batch_create_T(qsv_batch* b, int tile_qubits) {
   const uint64_t h = key_hash(b->key);
   {
     std::lock_guard<std::mutex> lk(g_batch_mu);
+    tuned_load_once();
     auto it = g_tuned.find(h);
-    if (it != g_tuned.end()) return batch_build<T>(b, it->second);
+    if (it != g_tuned.end() && it->second >= RB && it->second <= TBMAX) return batch_build<T>(b, it->second);
   }
   int maxw = 0;
   for (int w : b->width) maxw = std::max(maxw, w);
@@ -1865,7 +2088,7 @@ static qsv_status batch_create_T(qsv_batch* b, int tile_qubits) {
   }
   {
     std::lock_guard<std::mutex> lk(g_batch_mu);
-    g_tuned[h] = best_t;
+    tuned_store(h, best_t);
   }
   if (best_t != b->tile_bits) return batch_build<T>(b, best_t);
   return QSV_OK;

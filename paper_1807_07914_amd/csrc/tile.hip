@@ -726,7 +726,7 @@ __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile_pipe(cpx<T>* __res
   constexpr int A = VecInfo<T>::A;
   constexpr int VPT = (1 << TBMAX) / A / kTileThreads;
   constexpr int SB = SwzBits<T>::B;
-  constexpr int CMIN = SwzBits<T>::B;  // every pass keeps the low CMIN qubits (fewer only below CMIN qubits)
+  constexpr int CMIN = 4;  // every pass keeps at least the low 4 qubits contiguous (128- or 256-byte segments)
   __shared__ cpx<T> tile[1 << TBMAX];
   __shared__ uint64_t segoff[1 << (TBMAX - CMIN)];
   const int t = prog[0], c = prog[1], nns = prog[2];
@@ -792,6 +792,124 @@ __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile_pipe(cpx<T>* __res
   }
 }
 
+// ------------------------------------------------------ qubit permutation
+// One HBM pass that relabels qubits by an involution sigma of the index bits:
+// out[y] = in[sigma(y)], where sigma(y) moves bit q of y to bit sigma(q).
+// The pass's qubit set S (t qubits) holds the low c qubits and is closed
+// under sigma, so sigma maps the tile (S, b) onto the tile (S, sigma(b)) and
+// local index l onto pi(l).  The pair of tiles {tid, sigma(tid)} belongs to
+// the smaller id of the two (a tile that sigma fixes is taken alone): the
+// workgroup reads both into LDS, then writes each into the other's place
+// with its local index permuted.  Every amplitude is read and written once,
+// and no other workgroup touches the pair.  Workgroups are persistent (one
+// launch of resident workgroups walks the tile ids), so the half of the ids
+// that are not pair leaders cost a test, not a workgroup dispatch.
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void k_qperm(cpx<T>* __restrict__ psi, const int32_t* __restrict__ prog) {
+  constexpr int A = VecInfo<T>::A;
+  constexpr int TP = QpermCfg<T>::TP;
+  constexpr int SB = SwzBits<T>::B;
+  constexpr int VPT = (1 << TP) / A / kTileThreads;
+  __shared__ cpx<T> lds[2][1 << TP];
+  __shared__ uint64_t segoff[1 << (TP - 4)];
+  __shared__ uint32_t pl[2][64];
+  const int t = prog[0], c = prog[1], nns = prog[2];
+  const int32_t* S = prog + 4;
+  const int32_t* nonS = S + t;
+  const int32_t* pil = nonS + nns;
+  const int32_t* pin = pil + t;
+  const int nseg = 1 << (t - c);
+  for (int h = threadIdx.x; h < nseg; h += kTileThreads) {
+    uint64_t o = 0;
+    for (int j = 0; j < t - c; ++j)
+      if ((h >> j) & 1) o |= 1ull << S[c + j];
+    segoff[h] = o;
+  }
+  // pi(l) = pl[0][l & 63] ^ pl[1][l >> 6] (a bit permutation is XOR-linear)
+  for (int v = threadIdx.x; v < 128; v += kTileThreads) {
+    const int half = v >> 6, x = v & 63;
+    uint32_t o = 0;
+    for (int k = 0; k < 6; ++k) {
+      const int b = 6 * half + k;
+      if (((x >> k) & 1) && b < t) o |= 1u << pil[b];
+    }
+    pl[half][x] = o;
+  }
+  __syncthreads();
+  const uint32_t cmask = (1u << c) - 1u;
+  const int nvec = (1 << t) / A;
+  vec16<T>* gv = reinterpret_cast<vec16<T>*>(psi);
+  const uint64_t ntiles = 1ull << nns;
+  for (uint64_t tid = blockIdx.x; tid < ntiles; tid += gridDim.x) {
+    uint64_t tid2 = 0;
+    for (int i = 0; i < nns; ++i) tid2 |= ((tid >> i) & 1ull) << pin[i];
+    if (tid2 < tid) continue;  // uniform: the partner's workgroup takes the pair
+    uint64_t base = 0, base2 = 0;
+    for (int i = 0; i < nns; ++i) {
+      base |= ((tid >> i) & 1ull) << nonS[i];
+      base2 |= ((tid2 >> i) & 1ull) << nonS[i];
+    }
+    const bool pair = tid2 != tid;
+    // all of the thread's loads in flight before the first LDS write
+    vec16<T> xs[VPT], ys[VPT];
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const int i = threadIdx.x + k * kTileThreads;
+      if (i < nvec) {
+        const uint32_t l = (uint32_t)i * A;
+        const uint64_t off = segoff[l >> c] | (l & cmask);
+        xs[k] = gv[(base | off) / A];
+        if (pair) ys[k] = gv[(base2 | off) / A];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+      const int i = threadIdx.x + k * kTileThreads;
+      if (i < nvec) {
+        const uint32_t l = (uint32_t)i * A;
+#pragma unroll
+        for (int e = 0; e < A; ++e) lds[0][tile_swizzle(l + e, SB)] = xs[k].a[e];
+        if (pair) {
+#pragma unroll
+          for (int e = 0; e < A; ++e) lds[1][tile_swizzle(l + e, SB)] = ys[k].a[e];
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nvec; i += kTileThreads) {
+      const uint32_t l = (uint32_t)i * A;
+      const uint64_t off = segoff[l >> c] | (l & cmask);
+      vec16<T> x, y;
+#pragma unroll
+      for (int e = 0; e < A; ++e) {
+        const uint32_t src = tile_swizzle(pl[0][(l + e) & 63] ^ pl[1][(l + e) >> 6], SB);
+        x.a[e] = lds[0][src];
+        if (pair) y.a[e] = lds[1][src];
+      }
+      // the partner tile takes this tile's amplitudes (a fixed tile its own)
+      gv[(base2 | off) / A] = x;
+      if (pair) gv[(base | off) / A] = y;
+    }
+    __syncthreads();  // the LDS is reused by the next pair
+  }
+}
+
+// Workgroups of k_qperm that fit the device at once (cached per device).
+template <typename T>
+static int qperm_grid() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cache[dev] == 0) {
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_qperm<T>, kTileThreads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    cache[dev] = std::max(1, per_cu * ncu);
+  }
+  return cache[dev];
+}
+
 // ------------------------------------------------------------ batches
 // Every tile of one pass of one batched circuit (state at psi), lean body,
 // by one workgroup: the segment table once per pass, and half of each
@@ -806,7 +924,7 @@ __device__ __forceinline__ double batch_pass(cpx<T>* __restrict__ psi, const int
                                              uint64_t ntiles, const TileIO& io) {
   constexpr int A = VecInfo<T>::A;
   constexpr int VPT = (1 << TBMAX) / A / kTileThreads;  // 16-byte vectors per thread
-  constexpr int PF = VPT / 2;                           // of which prefetched
+  constexpr int PF = VPT;                               // of which prefetched
   constexpr int SB = SwzBits<T>::B;
   using V = typename StageVec<T>::V;
   __shared__ cpx<T> tile[1 << TBMAX];
@@ -1039,7 +1157,7 @@ hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const i
   // full-size tiles only (for half-size tiles the extra registers and LDS
   // cost a workgroup per compute unit, more than the overlap gains); full
   // body only for complex64 (the complex128 one would spill heavily).
-  const bool pipe = (body != kBodyFull || sizeof(T) == 4) && !small && t - c <= tbits - SwzBits<T>::B;
+  const bool pipe = (body != kBodyFull || sizeof(T) == 4) && !small && t - c <= tbits - 4;
   if (small) {
     if (body == kBodyFull) return launch_pass<T, TB - 1, RB, kBodyFull, 2>(psi, prog_dev, ntiles, pipe, st);
     if (body == kBodyPerm) return launch_pass<T, TB - 1, RB, kBodyPerm, 3>(psi, prog_dev, ntiles, pipe, st);
@@ -1049,6 +1167,18 @@ hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const i
   if (body == kBodyPerm) return launch_pass<T, TB, RB, kBodyPerm, 2>(psi, prog_dev, ntiles, pipe, st);
   return launch_pass<T, TB, RB, kBodyLean, 2>(psi, prog_dev, ntiles, pipe, st);
 }
+
+// One qubit-permutation pass (program: see tile.hpp, kind kPassQperm).
+template <typename T>
+hipError_t launch_qperm(cpx<T>* psi, int n, const int32_t* prog_dev, const int32_t* prog_host, hipStream_t st) {
+  const uint64_t ntiles = 1ull << (n - prog_host[0]);
+  const int resident = qperm_grid<T>();
+  const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, (uint64_t)(resident > 0 ? resident : 1024));
+  hipLaunchKernelGGL(k_qperm<T>, dim3(grid), dim3(kTileThreads), 0, st, psi, prog_dev);
+  return hipGetLastError();
+}
+template hipError_t launch_qperm<float>(cpx<float>*, int, const int32_t*, const int32_t*, hipStream_t);
+template hipError_t launch_qperm<double>(cpx<double>*, int, const int32_t*, const int32_t*, hipStream_t);
 
 template <typename T>
 hipError_t launch_batch(cpx<T>* scratch, const int32_t* progs, const int64_t* passoff,

@@ -100,6 +100,14 @@
 //   2 outside (val = global qubit).  Reals are stored in the state's
 //   precision, one word per float, two words (low, high) per double.
 //
+// Qubit-permutation pass (n_rounds word = kPassQperm): relabels qubits by an
+// involution sigma of the qubits, out[y] = in[sigma(y)] (sigma(y) moves bit
+// q of y to bit sigma(q)), in one read and one write of the state.  S holds
+// the low c qubits and is closed under sigma; t is at most QpermCfg<T>::TP.
+//   t, c, n_nonS, kPassQperm, S[t], nonS[n_nonS], pi[t] (sigma(S[k]) =
+//   S[pi[k]]), pin[n_nonS] (sigma(nonS[i]) = nonS[pin[i]]), padded to a
+//   multiple of 16 words.
+//
 // Every step except the rare LT_RAWD / LT_U2 / LT_U1 updates the amplitudes
 // in place with FMAs whose addend is the amplitude itself.  A layer is a
 // fixed sequence of optional steps rather than one of several op kinds:
@@ -140,6 +148,15 @@ constexpr int kTableWords = 64;   // words of a table
 constexpr int kHdrTileFac = 8;    // round-header word of the tile-factor list offset
 constexpr int kHdrStore = 10;     // round-header words of the store's register-bit offsets
 constexpr int kMaxTileFactors = 128;  // tile-factor slots of one pass
+constexpr int kPassQperm = -1;        // n_rounds word of a qubit-permutation pass
+
+// Largest tile of a qubit-permutation pass: a pair of tiles takes 32 KiB of
+// LDS, so that four workgroups share a compute unit and keep enough loads
+// in flight (the low c qubits and their images need at most 2c <= 10 bits).
+template <typename T>
+struct QpermCfg {
+  static constexpr int TP = sizeof(T) == 4 ? 11 : 10;
+};
 
 // words of a layer record: 4 + 2 * RB reals (RB = 5 floats, RB = 4 doubles)
 template <typename T>

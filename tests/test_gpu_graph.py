@@ -69,3 +69,26 @@ def test_graph_argument_checks():
     got = s.to_numpy()
     s.close()
     assert np.abs(got - O.run(mixed, 12)).max() <= TOL["c64"]
+
+
+def test_graph_with_permutation_pass():
+    # a plan that ends in a qubit-permutation pass (the 22-qubit QFT's bit
+    # reversal) replays through the graph like the tile passes
+    from paper_1807_07914_amd import State
+    n = 22
+    ops = qc.qft(n)
+    s = State(n, "c64", stream=torch.cuda.Stream())
+    e = State(n, "c64")
+    for x0 in (qc.qft_input(n, 5), qc.qft_input(n, 6), 0):
+        s.set_basis(x0)
+        s.apply_circuit(ops, graph=True)
+        e.set_basis(x0)
+        e.apply_circuit(ops)
+        torch.cuda.synchronize()
+        got = s.to_numpy()
+        assert np.array_equal(got, e.to_numpy())
+        y = np.arange(0, 1 << n, 4099)
+        ref = np.exp(2j * np.pi * ((x0 * y) % (1 << n)) / (1 << n)) / 2 ** (n / 2)
+        assert np.abs(got[y] - ref).max() <= 1e-6
+    s.close()
+    e.close()

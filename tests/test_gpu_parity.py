@@ -346,6 +346,57 @@ def test_fused_families(dtype, family, small_tile):
     assert np.abs(got - ref).max() <= TOL[dtype], info
 
 
+def _swap_network(n, layers, seed):
+    rng = np.random.default_rng(seed)
+    ops = []
+    for _ in range(layers):
+        for q in range(n):
+            ops.append(qc.op("RY", q, params=(float(rng.uniform(0, 2 * np.pi)),)))
+        for q in range(0, n - 1, 2):
+            ops.append(qc.op("CZ", q, q + 1))
+        perm = rng.permutation(n)
+        for k in range(0, n - 1, 2):
+            ops.append(qc.op("SWAP", int(perm[k]), int(perm[k + 1])))
+    return ops
+
+
+def _plan_kinds(n, dtype, ops, tile=0):
+    import tile_emulator as E
+    words, steps = E.program(n, dtype, ops, tile)
+    return "".join("P" if E.is_qperm(words, int(s)) else ("T" if s >= 0 else "X") for s in steps)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,tile,seed,layers", [(8, 6, 1, 3), (10, 6, 0, 3), (12, 7, 2, 3), (18, 0, 2, 4),
+                                                (20, 9, 3, 4)])
+def test_fused_swap_relabeling(dtype, n, tile, seed, layers):
+    # SWAPs relabeled away and the state put back in order by one or two
+    # qubit-permutation passes (the plan is checked to take that route)
+    ops = _swap_network(n, layers, seed)
+    kinds = _plan_kinds(n, dtype, ops, tile)
+    if "P" not in kinds:
+        pytest.skip("the planner keeps the SWAPs for this case and dtype: " + kinds)
+    assert kinds.endswith("P") and kinds.count("P") <= 2
+    psi0 = start(n, dtype, 1300 + n)
+    ref = O.run(ops, n, psi=psi0.copy())
+    got = gpu_run(n, dtype, psi0, ops, "fused", tile_qubits=tile)
+    assert np.abs(got - ref).max() <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_fused_qft_bit_reversal_pass(dtype):
+    # 22 qubits: the QFT's swaps become one bit-reversal pass (complex64),
+    # against the oracle element by element from a random state
+    n = 22
+    ops = qc.qft(n)
+    psi0 = start(n, dtype, 1401)
+    ref = O.run(ops, n, psi=psi0.copy())
+    got = gpu_run(n, dtype, psi0, ops, "fused")
+    assert np.abs(got - ref).max() <= TOL[dtype]
+    if dtype == "c64":
+        assert _plan_kinds(n, dtype, ops) == "TTP"
+
+
 def test_fused_plan_is_reused_with_new_matrices():
     # same structure, different angles: the cached schedule must take the new values
     n = 15

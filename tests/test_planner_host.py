@@ -179,3 +179,62 @@ def test_zero_angles_keep_the_plan(dtype):
         got = E.emulate_batch_job(dtype, w0, p0, job)
         ref = O.run(zero[i], w)
         assert np.abs(got - ref).max() <= TOL[dtype]
+
+
+def swap_network(n, layers, seed):
+    """RY layers, CZ on neighbours and a random perfect matching of SWAPs per
+    layer: the SWAPs cross tile boundaries."""
+    rng = np.random.default_rng(seed)
+    ops = []
+    for _ in range(layers):
+        for q in range(n):
+            ops.append(qc.op("RY", q, params=(float(rng.uniform(0, 2 * np.pi)),)))
+        for q in range(0, n - 1, 2):
+            ops.append(qc.op("CZ", q, q + 1))
+        perm = rng.permutation(n)
+        for k in range(0, n - 1, 2):
+            ops.append(qc.op("SWAP", int(perm[k]), int(perm[k + 1])))
+    return ops
+
+
+def plan_kinds(n, dtype, ops, tile=0):
+    words, steps = E.program(n, dtype, ops, tile)
+    return "".join("P" if E.is_qperm(words, int(s)) else ("T" if s >= 0 else "X") for s in steps)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,tile,seed", [(8, 6, 0), (8, 6, 1), (9, 6, 2), (10, 7, 0), (11, 6, 1), (12, 7, 2)])
+def test_emulated_swap_relabeling(dtype, n, tile, seed):
+    # plans that relabel SWAPs away and end in one (an involution) or two
+    # qubit-permutation passes, against the oracle; a three-qubit matrix
+    # after the SWAPs checks that separate ops are relabeled too
+    ops = swap_network(n, 3, seed)
+    ops.append(qc.op("U", 0, n - 1, 2, mat=qc.haar_unitary(3, np.random.default_rng(seed))))
+    ops += swap_network(n, 1, seed + 10)
+    kinds = plan_kinds(n, dtype, ops, tile)
+    assert "P" in kinds and kinds.endswith("P") and kinds.count("P") <= 2, kinds
+    psi0 = qc.random_state(n, 40 + n)
+    ref = O.run(ops, n, psi=psi0.copy())
+    got = E.emulate(n, dtype, ops, psi0, tile)
+    assert np.abs(got - ref).max() <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype,n,tile", [("c64", 9, 6), ("c128", 10, 6), ("c64", 12, 7)])
+def test_emulated_qft_one_permutation_pass(dtype, n, tile):
+    # the QFT's final SWAPs form an involution (bit reversal): one pass
+    ops = qc.qft(n)
+    kinds = plan_kinds(n, dtype, ops, tile)
+    assert kinds.endswith("P") and kinds.count("P") == 1, kinds
+    psi0 = qc.random_state(n, 77 + n)
+    got = E.emulate(n, dtype, ops, psi0, tile)
+    assert np.abs(got - O.run(ops, n, psi=psi0.copy())).max() <= TOL[dtype]
+
+
+def test_relabeling_only_when_it_saves_passes():
+    # a SWAP inside the register group costs nothing in a pass: no relabeling
+    n = 10
+    ops = qc.random_brickwork(n, 4, 3) + [qc.op("SWAP", 0, 1)] + qc.random_brickwork(n, 2, 4)
+    assert "P" not in plan_kinds(n, "c64", ops)
+    # the 30-qubit QFT: three tile passes and the bit reversal
+    assert plan_kinds(30, "c64", qc.qft(30)) == "TTTP"
+    assert qsv.plan_info(30, "c64", qc.qft(30))["passes"] == 4

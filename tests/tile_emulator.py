@@ -355,16 +355,72 @@ def expand_cnots(ops):
     return out
 
 
+QPERM = -1   # n_rounds word of a qubit-permutation pass
+
+
+def is_qperm(words, off):
+    return off >= 0 and int(words[off + 3]) == QPERM
+
+
+def relabel_swaps(ops, n):
+    """The op list with its SWAPs relabeled away (a SWAP exchanges which bit
+    holds which qubit; later ops act on the bits of their qubits)."""
+    lab = list(range(n))
+    out = []
+    for o in ops:
+        if o.name == "SWAP":
+            a, b = o.qubits
+            lab[a], lab[b] = lab[b], lab[a]
+            continue
+        out.append(qc.op(o.name, *[lab[q] for q in o.qubits], params=o.params, mat=o.mat))
+    return out
+
+
+def qperm_sigma(words, off, n):
+    """The involution of a qubit-permutation pass, checked for the layout
+    rules: S holds the low c qubits, S and its complement are closed."""
+    t, c, nns = (int(x) for x in words[off:off + 3])
+    assert t + nns == n
+    k = off + 4
+    S = [int(x) for x in words[k:k + t]]
+    nonS = [int(x) for x in words[k + t:k + t + nns]]
+    pi = [int(x) for x in words[k + t + nns:k + 2 * t + nns]]
+    pin = [int(x) for x in words[k + 2 * t + nns:k + 2 * t + 2 * nns]]
+    assert S == sorted(S) and nonS == sorted(nonS) and sorted(S + nonS) == list(range(n))
+    assert S[:c] == list(range(c))
+    sigma = [0] * n
+    for j, q in enumerate(S):
+        sigma[q] = S[pi[j]]
+    for i, q in enumerate(nonS):
+        sigma[q] = nonS[pin[i]]
+    assert sorted(sigma) == list(range(n)) and all(sigma[sigma[q]] == q for q in range(n))
+    return sigma
+
+
+def run_qperm(psi, n, words, off):
+    """out[y] = in[sigma(y)], sigma(y) moving bit q of y to bit sigma(q)."""
+    sigma = qperm_sigma(words, off, n)
+    idx = np.arange(1 << n, dtype=np.int64)
+    src = np.zeros_like(idx)
+    for q in range(n):
+        src |= ((idx >> q) & 1) << sigma[q]
+    psi[:] = psi[src]
+
+
 def emulate(n, dtype, ops, psi0, tile=0, matrix_of=None):
     """Run the fused plan of ``ops`` on psi0 (complex128, copied)."""
     words, steps = program(n, dtype, ops, tile)
     ops = expand_cnots(list(ops))
+    if any(is_qperm(words, int(st)) for st in steps):
+        ops = relabel_swaps(ops, n)
     psi = np.array(psi0, dtype=np.complex128)
     cfg = CFG[dtype]
     for st in steps:
         if st < 0:
             o = ops[int(-st - 1)]
             _apply_dense(psi, n, list(o.qubits), np.asarray(o.mat, dtype=np.complex128))
+        elif is_qperm(words, int(st)):
+            run_qperm(psi, n, words, int(st))
         else:
             run_pass(psi, n, words, int(st), cfg)
     return psi
@@ -427,6 +483,9 @@ def op_counts(words, steps, dtype):
             add("separate")
             continue
         off = int(st)
+        if is_qperm(words, off):
+            add("qperm")
+            continue
         t, c, nns = (int(x) for x in words[off:off + 3])
         LR = CFG[dtype]["LR"]
         blocks = _round_blocks(words, off, t, nns)
