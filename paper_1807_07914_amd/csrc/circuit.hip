@@ -484,7 +484,8 @@ static const std::vector<qsv_op>& step_ops(const Schedule& sch, const std::vecto
 
 // Program of a qubit-permutation pass for the involution v (layout in
 // tile.hpp): S = the low c qubits, closed under v, then more of v's fixed
-// qubits and pairs, lowest first, up to QpermCfg<T>::TP qubits.
+// qubits and pairs, lowest first, up to QpermCfg<T>::TP qubits; the other
+// qubits in tile-id order.
 template <typename T>
 static void emit_qperm(const std::vector<int>& v, int n, std::vector<int32_t>& prog) {
   int t = std::min(QpermCfg<T>::TP, n);
@@ -505,8 +506,23 @@ static void emit_qperm(const std::vector<int>& v, int n, std::vector<int32_t>& p
     cnt += need;
   }
   t = cnt;
+  // nonS in the order of the tile id's bits: each of the lowest outside
+  // qubits next to its image, so that the tiles in flight at one time (low
+  // id bits) read and write nearby segments on both sides of the pass
   std::vector<int> S, nonS, pos(n, -1);
-  for (int q = 0; q < n; ++q) (in[q] ? S : nonS).push_back(q);
+  std::vector<char> taken(n, 0);
+  for (int q = 0; q < n; ++q) {
+    if (in[q]) {
+      S.push_back(q);
+    } else if (!taken[q]) {
+      nonS.push_back(q);
+      taken[q] = 1;
+      if (!taken[v[q]]) {
+        nonS.push_back(v[q]);
+        taken[v[q]] = 1;
+      }
+    }
+  }
   for (int k = 0; k < t; ++k) pos[S[k]] = k;
   for (int i = 0; i < (int)nonS.size(); ++i) pos[nonS[i]] = i;
   const size_t base = prog.size();

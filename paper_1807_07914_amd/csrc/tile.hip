@@ -803,7 +803,11 @@ __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile_pipe(cpx<T>* __res
 // with its local index permuted.  Every amplitude is read and written once,
 // and no other workgroup touches the pair.  Workgroups are persistent (one
 // launch of resident workgroups walks the tile ids), so the half of the ids
-// that are not pair leaders cost a test, not a workgroup dispatch.
+// that are not pair leaders cost a test, not a workgroup dispatch.  Small
+// tiles (16 KiB per pair) let eight workgroups share a compute unit; that
+// concurrency, not prefetching within a workgroup, keeps HBM busy (a
+// variant that loaded the next pair into registers during the stores ran
+// 25% slower: its joins made the compiler wait for the loads early).
 template <typename T>
 __global__ __launch_bounds__(kTileThreads) void k_qperm(cpx<T>* __restrict__ psi, const int32_t* __restrict__ prog) {
   constexpr int A = VecInfo<T>::A;

@@ -104,9 +104,10 @@
 // involution sigma of the qubits, out[y] = in[sigma(y)] (sigma(y) moves bit
 // q of y to bit sigma(q)), in one read and one write of the state.  S holds
 // the low c qubits and is closed under sigma; t is at most QpermCfg<T>::TP.
-//   t, c, n_nonS, kPassQperm, S[t], nonS[n_nonS], pi[t] (sigma(S[k]) =
-//   S[pi[k]]), pin[n_nonS] (sigma(nonS[i]) = nonS[pin[i]]), padded to a
-//   multiple of 16 words.
+//   t, c, n_nonS, kPassQperm, S[t] (ascending), nonS[n_nonS] (the qubit of
+//   each tile-id bit, in any order), pi[t] (sigma(S[k]) = S[pi[k]]),
+//   pin[n_nonS] (sigma(nonS[i]) = nonS[pin[i]]), padded to a multiple of 16
+//   words.
 //
 // Every step except the rare LT_RAWD / LT_U2 / LT_U1 updates the amplitudes
 // in place with FMAs whose addend is the amplitude itself.  A layer is a
@@ -150,12 +151,12 @@ constexpr int kHdrStore = 10;     // round-header words of the store's register-
 constexpr int kMaxTileFactors = 128;  // tile-factor slots of one pass
 constexpr int kPassQperm = -1;        // n_rounds word of a qubit-permutation pass
 
-// Largest tile of a qubit-permutation pass: a pair of tiles takes 32 KiB of
-// LDS, so that four workgroups share a compute unit and keep enough loads
-// in flight (the low c qubits and their images need at most 2c <= 10 bits).
+// Largest tile of a qubit-permutation pass: a pair of tiles takes 16 KiB of
+// LDS, so that eight workgroups share a compute unit (the low c qubits and
+// their images need at most 2c bits: 10 for complex64, 8 for complex128).
 template <typename T>
 struct QpermCfg {
-  static constexpr int TP = sizeof(T) == 4 ? 11 : 10;
+  static constexpr int TP = sizeof(T) == 4 ? 10 : 9;
 };
 
 // words of a layer record: 4 + 2 * RB reals (RB = 5 floats, RB = 4 doubles)

@@ -386,7 +386,7 @@ def qperm_sigma(words, off, n):
     nonS = [int(x) for x in words[k + t:k + t + nns]]
     pi = [int(x) for x in words[k + t + nns:k + 2 * t + nns]]
     pin = [int(x) for x in words[k + 2 * t + nns:k + 2 * t + 2 * nns]]
-    assert S == sorted(S) and nonS == sorted(nonS) and sorted(S + nonS) == list(range(n))
+    assert S == sorted(S) and sorted(S + nonS) == list(range(n))
     assert S[:c] == list(range(c))
     sigma = [0] * n
     for j, q in enumerate(S):
