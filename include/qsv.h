@@ -107,13 +107,22 @@ typedef struct qsv_op {
  *   kernels (matrices on more than two qubits, registers narrower than one
  *   register group) are launched without a graph.  Calls with graph = 1 on
  *   one state must not overlap a capture of its stream by the caller.
+ *   race_check (qsv_apply_circuit in a fused mode without graph, 0 or 1): 1
+ *   = debug mode that checks every tile and permutation pass for races:
+ *   the pass runs first out of place, from the state into a second
+ *   state-sized buffer filled with a poison pattern, then in place as
+ *   usual; an amplitude the out-of-place run left unwritten or that differs
+ *   bitwise from the in-place result fails the call with QSV_ERR_STATE
+ *   (the state then holds the plan's result up to that pass).  Synchronous
+ *   per pass; allocates the second buffer.
  *   Other fields are reserved and must be zero. */
 typedef struct qsv_plan_opts {
   int32_t mode;
   int32_t tile_qubits;
   int32_t state_is_output;
   int32_t graph;
-  int32_t reserved[4];
+  int32_t race_check;
+  int32_t reserved[3];
 } qsv_plan_opts;
 
 /* Allocate a state of n_qubits (1..QSV_MAX_QUBITS) initialised to |0...0>.

@@ -85,6 +85,25 @@ qsv_status ensure_workspace(qsv_state* s, size_t bytes) {
   return QSV_OK;
 }
 
+// Second state-sized buffer (the adjoint sweep's lambda, the race check's
+// out-of-place copy); stream-ordered like the workspace.
+qsv_status ensure_aux(qsv_state* s, const char* what) {
+  if (s->aux_bytes >= s->bytes) return QSV_OK;
+  if (s->aux) {
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    QSV_HIP(hipFree(s->aux));
+    s->aux = nullptr;
+    s->aux_bytes = 0;
+  }
+  hipError_t e = hipMalloc(&s->aux, s->bytes);
+  if (e != hipSuccess) {
+    s->aux = nullptr;
+    return hip_fail(e, what);
+  }
+  s->aux_bytes = s->bytes;
+  return QSV_OK;
+}
+
 // ------------------------------------------------------------ gate table
 using cd = std::complex<double>;
 
@@ -457,7 +476,9 @@ qsv_status qsv_apply_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const q
   if (o.graph != 0 && o.graph != 1) return fail(QSV_ERR_ARG, "graph must be 0 or 1");
   if (o.graph && o.mode == 1) return fail(QSV_ERR_ARG, "graph applies to the fused modes only");
   if (o.graph && !s->stream) return fail(QSV_ERR_ARG, "graph needs a state on a stream other than the null stream");
-  for (int r = 0; r < 4; ++r)
+  if (o.race_check != 0 && o.race_check != 1) return fail(QSV_ERR_ARG, "race_check must be 0 or 1");
+  if (o.race_check && (o.mode == 1 || o.graph)) return fail(QSV_ERR_ARG, "race_check applies to eager fused plans only");
+  for (int r = 0; r < 3; ++r)
     if (o.reserved[r]) return fail(QSV_ERR_ARG, "reserved plan option fields must be zero");
   for (int i = 0; i < n_ops; ++i) {
     qsv_status st = validate_op(s, ops[i]);
@@ -1306,20 +1327,8 @@ static qsv_status adjoint_sweep(qsv_state* s, const qsv_op* ops, int n_ops, cons
   const size_t tparts = (size_t)adj_max_grad() * 1024;  // per-workgroup sums of the tiled sweep
   qsv_status st = ensure_workspace(s, stage + (npart + (size_t)n_ops + 2 + tparts) * sizeof(double));
   if (st) return st;
-  if (s->aux_bytes < s->bytes) {
-    if (s->aux) {
-      QSV_HIP(hipStreamSynchronize(s->stream));
-      QSV_HIP(hipFree(s->aux));
-      s->aux = nullptr;
-      s->aux_bytes = 0;
-    }
-    hipError_t e = hipMalloc(&s->aux, s->bytes);
-    if (e != hipSuccess) {
-      s->aux = nullptr;
-      return hip_fail(e, "hipMalloc(adjoint buffer)");
-    }
-    s->aux_bytes = s->bytes;
-  }
+  st = ensure_aux(s, "hipMalloc(adjoint buffer)");
+  if (st) return st;
   cpx<T>* psi = static_cast<cpx<T>*>(s->psi);
   cpx<T>* lam = static_cast<cpx<T>*>(s->aux);
   double* part = reinterpret_cast<double*>(static_cast<char*>(s->ws) + stage);
@@ -1462,7 +1471,8 @@ qsv_status qsv_adjoint(qsv_state* s, const qsv_op* ops, int n_ops, const uint64_
   if (o.mode < 0 || o.mode > 2) return fail(QSV_ERR_ARG, "mode must be 0, 1 or 2");
   if (o.state_is_output != 0 && o.state_is_output != 1) return fail(QSV_ERR_ARG, "state_is_output must be 0 or 1");
   if (o.graph) return fail(QSV_ERR_ARG, "graph applies to qsv_apply_circuit only");
-  for (int r = 0; r < 4; ++r)
+  if (o.race_check) return fail(QSV_ERR_ARG, "race_check applies to qsv_apply_circuit only");
+  for (int r = 0; r < 3; ++r)
     if (o.reserved[r]) return fail(QSV_ERR_ARG, "reserved plan option fields must be zero");
   for (int i = 0; i < n_ops; ++i) {
     st = validate_op(s, ops[i]);

@@ -44,7 +44,11 @@ template <typename T>
 hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const int32_t* prog_host, int body,
                             hipStream_t st);
 template <typename T>
-hipError_t launch_qperm(cpx<T>* psi, int n, const int32_t* prog_dev, const int32_t* prog_host, hipStream_t st);
+hipError_t launch_qperm(const cpx<T>* src, cpx<T>* dst, int n, const int32_t* prog_dev, const int32_t* prog_host,
+                        hipStream_t st);
+template <typename T>
+hipError_t launch_tile_pass_oop(const cpx<T>* src, cpx<T>* dst, int n, const int32_t* prog_dev,
+                                const int32_t* prog_host, int body, hipStream_t st);
 
 using cd = std::complex<double>;
 
@@ -1577,8 +1581,8 @@ static qsv_status launch_fused_graph(qsv_state* s, const Schedule& sch, const st
     QSV_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (size_t k = 0; k < sch.steps.size() && e == hipSuccess; ++k)
-      e = body[k] < 0 ? launch_qperm<T>(static_cast<cpx<T>*>(s->psi), s->n, dprog + offs[k], prog.data() + offs[k],
-                                        s->stream)
+      e = body[k] < 0 ? launch_qperm<T>(static_cast<cpx<T>*>(s->psi), static_cast<cpx<T>*>(s->psi), s->n,
+                                        dprog + offs[k], prog.data() + offs[k], s->stream)
                       : launch_tile_pass<T>(static_cast<cpx<T>*>(s->psi), s->n, dprog + offs[k],
                                             prog.data() + offs[k], body[k], s->stream);
     hipGraph_t g = nullptr;
@@ -1598,6 +1602,58 @@ static qsv_status launch_fused_graph(qsv_state* s, const Schedule& sch, const st
     s->fg_sig = std::move(sig);
   }
   QSV_HIP(hipGraphLaunch(s->fg_exec, s->stream));
+  return QSV_OK;
+}
+
+// The race check of a fused plan (plan option race_check): every tile and
+// permutation pass runs first out of place, from the state into the second
+// state-sized buffer filled with a poison pattern, then in place as usual.
+// In place is race-free when every amplitude belongs to exactly one
+// workgroup and is read before it is written: the out-of-place run must
+// then write every amplitude (no poison left) and produce the in-place
+// result bit for bit (the same arithmetic; a read of an amplitude that
+// another workgroup had already updated would differ).  The per-gate steps
+// run as usual.  Synchronous per pass.
+template <typename T>
+static qsv_status run_race_checked(qsv_state* s, const Schedule& sch, const std::vector<qsv_op>& sops,
+                                   const std::vector<int32_t>& prog, const std::vector<size_t>& offs,
+                                   const int32_t* dprog) {
+  qsv_status st0 = ensure_aux(s, "hipMalloc(race check buffer)");
+  if (st0) return st0;
+  st0 = ensure_workspace(s, std::max(dense_ws_bytes(), (size_t)256));
+  if (st0) return st0;
+  cpx<T>* psi = static_cast<cpx<T>*>(s->psi);
+  cpx<T>* out = static_cast<cpx<T>*>(s->aux);
+  const uint64_t nvec = s->bytes / 16;
+  for (size_t k = 0; k < sch.steps.size(); ++k) {
+    const Step& st = sch.steps[k];
+    if (!st.tile && st.inv.empty()) {
+      qsv_status e = apply_op_pergate(s, sops[st.op], 0);
+      if (e) return e;
+      continue;
+    }
+    const int32_t* ph = prog.data() + offs[k];
+    // the workspace is free between steps: the counters live at its start
+    unsigned long long* counts = static_cast<unsigned long long*>(s->ws);
+    QSV_HIP(hipMemsetAsync(counts, 0, 2 * sizeof(unsigned long long), s->stream));
+    QSV_HIP(launch_poison(out, nvec, s->stream));
+    if (st.tile) {
+      const int body = program_body<T>(ph);
+      QSV_HIP(launch_tile_pass_oop<T>(psi, out, s->n, dprog + offs[k], ph, body, s->stream));
+      QSV_HIP(launch_tile_pass<T>(psi, s->n, dprog + offs[k], ph, body, s->stream));
+    } else {
+      QSV_HIP(launch_qperm<T>(psi, out, s->n, dprog + offs[k], ph, s->stream));
+      QSV_HIP(launch_qperm<T>(psi, psi, s->n, dprog + offs[k], ph, s->stream));
+    }
+    QSV_HIP(launch_race_compare(psi, out, nvec, counts, s->stream));
+    unsigned long long h[2] = {0, 0};
+    QSV_HIP(hipMemcpyAsync(h, counts, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    QSV_HIP(hipStreamSynchronize(s->stream));
+    if (h[0] || h[1])
+      return fail(QSV_ERR_STATE, "race check: pass " + std::to_string(k) + " (" + (st.tile ? "tile" : "permutation") +
+                                     ") left " + std::to_string(h[0]) + " words unwritten and " +
+                                     std::to_string(h[1]) + " words different out of place");
+  }
   return QSV_OK;
 }
 
@@ -1682,10 +1738,12 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
   bool all_tile = true;
   for (const Step& st : sch->steps) all_tile = all_tile && (st.tile || !st.inv.empty());
   if (opts.graph && all_tile) return launch_fused_graph<T>(s, *sch, prog, offs, dprog);
+  if (opts.race_check) return run_race_checked<T>(s, *sch, sops, prog, offs, dprog);
   for (size_t k = 0; k < sch->steps.size(); ++k) {
     const Step& st = sch->steps[k];
     if (!st.inv.empty()) {
-      QSV_HIP(launch_qperm<T>(static_cast<cpx<T>*>(s->psi), n, dprog + offs[k], prog.data() + offs[k], s->stream));
+      QSV_HIP(launch_qperm<T>(static_cast<cpx<T>*>(s->psi), static_cast<cpx<T>*>(s->psi), n, dprog + offs[k],
+                              prog.data() + offs[k], s->stream));
       continue;
     }
     if (!st.tile) {

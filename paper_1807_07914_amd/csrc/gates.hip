@@ -6,6 +6,8 @@
 // amplitude pairs/quartets, loads them with 16-byte vector loads where the
 // partner layout allows, applies the small matrix in registers and stores
 // back in place.  No amplitude is touched by two threads of one launch.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace qsv {
@@ -359,6 +361,55 @@ hipError_t launch_dense(cpx<T>* psi, int n, int k, const int* qubits, const cpx<
   template hipError_t launch_dense<T>(cpx<T>*, int, int, const int*, const cpx<T>*, hipStream_t);
 QSV_INST(float)
 QSV_INST(double)
+
+// ---------------------------------------------------------- race check
+// A 4-byte word pattern that no pass writes by chance (a float NaN, and two
+// of them a double NaN).
+constexpr uint32_t kPoison = 0x7FBADBADu;
+
+__global__ __launch_bounds__(kBlock) void k_poison(uint4* __restrict__ a, uint64_t nvec) {
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nvec; i += stride)
+    a[i] = uint4{kPoison, kPoison, kPoison, kPoison};
+}
+
+__global__ __launch_bounds__(kBlock) void k_race_compare(const uint4* __restrict__ a, const uint4* __restrict__ b,
+                                                         uint64_t nvec, unsigned long long* __restrict__ counts) {
+  unsigned long long unwritten = 0, differ = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nvec; i += stride) {
+    const uint4 x = a[i], y = b[i];
+    unwritten += (y.x == kPoison) + (y.y == kPoison) + (y.z == kPoison) + (y.w == kPoison);
+    differ += (x.x != y.x) + (x.y != y.y) + (x.z != y.z) + (x.w != y.w);
+  }
+  // integer sums: the order of the additions does not matter
+  for (int o = 32; o > 0; o >>= 1) {
+    unwritten += __shfl_xor(unwritten, o);
+    differ += __shfl_xor(differ, o);
+  }
+  if ((threadIdx.x & 63) == 0 && (unwritten | differ)) {
+    atomicAdd(&counts[0], unwritten);
+    atomicAdd(&counts[1], differ);
+  }
+}
+
+static unsigned race_grid(uint64_t nvec) {
+  return (unsigned)std::min<uint64_t>((nvec + kBlock - 1) / kBlock, 4096);
+}
+
+hipError_t launch_poison(void* a, uint64_t nvec, hipStream_t st) {
+  if (nvec == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_poison, dim3(race_grid(nvec)), dim3(kBlock), 0, st, static_cast<uint4*>(a), nvec);
+  return hipGetLastError();
+}
+
+hipError_t launch_race_compare(const void* a, const void* b, uint64_t nvec, unsigned long long* counts,
+                               hipStream_t st) {
+  if (nvec == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_race_compare, dim3(race_grid(nvec)), dim3(kBlock), 0, st, static_cast<const uint4*>(a),
+                     static_cast<const uint4*>(b), nvec, counts);
+  return hipGetLastError();
+}
 
 }  // namespace qsv
 

@@ -74,6 +74,15 @@ namespace qsv {
 // Grow the state's device workspace to at least `bytes` (stream-ordered:
 // waits for the stream before freeing a smaller buffer).
 qsv_status ensure_workspace(qsv_state* s, size_t bytes);
+// Grow the second state-sized buffer s->aux to the state's size.
+qsv_status ensure_aux(qsv_state* s, const char* what);
+// Race check helpers (gates.hip): fill nvec 16-byte vectors with the poison
+// pattern; count, over nvec vectors, the 4-byte words of b that still hold
+// the poison (counts[0]) and those that differ from a (counts[1]), adding to
+// counts (two zeroed unsigned 64-bit counters).
+hipError_t launch_poison(void* a, uint64_t nvec, hipStream_t st);
+hipError_t launch_race_compare(const void* a, const void* b, uint64_t nvec, unsigned long long* counts,
+                               hipStream_t st);
 
 // ---------------------------------------------------------------- launchers
 template <typename T>

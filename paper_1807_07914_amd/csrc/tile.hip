@@ -590,7 +590,7 @@ struct TileIO {
 // since fewer registers let more workgroups share a compute unit and the
 // full body spills.
 template <typename T, int TBMAX, int RB, int BODY>
-__device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int32_t* __restrict__ prog,
+__device__ __forceinline__ double tile_body(const cpx<T>* src, cpx<T>* dst, const int32_t* __restrict__ prog,
                                             uint64_t tid, const TileIO& io) {
   constexpr int A = VecInfo<T>::A;
   constexpr int NR = 1 << RB;
@@ -614,7 +614,8 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
   __syncthreads();
 
   // ---- load the tile (coalesced 16-byte vectors) into LDS
-  vec16<T>* gv = reinterpret_cast<vec16<T>*>(psi);
+  const vec16<T>* gv = reinterpret_cast<const vec16<T>*>(src);
+  vec16<T>* gw = reinterpret_cast<vec16<T>*>(dst);
   const int nvec = (1 << t) / A;
   const uint32_t cmask = (1u << c) - 1u;
   if (io.init) {
@@ -667,7 +668,7 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
 #pragma unroll
         for (int e = 0; e < A; ++e) x.a[e] = tile[tile_swizzle(l + e, SB)];
         const uint64_t g = base | segoff[l >> c] | (l & cmask);
-        gv[g / A] = x;
+        gw[g / A] = x;
       }
     }
   }
@@ -675,11 +676,15 @@ __device__ __forceinline__ double tile_body(cpx<T>* __restrict__ psi, const int3
   return acc;
 }
 
+// One workgroup per tile, reading the tile from src and writing it to dst:
+// the same pointer for a pass in place; distinct buffers for the race check
+// of the fused plans (plan option race_check), which runs each pass out of
+// place first and compares.
 template <typename T, int TBMAX, int RB, int BODY, int MINWG>
-__global__ __launch_bounds__(kTileThreads, MINWG) void k_tile(cpx<T>* __restrict__ psi,
+__global__ __launch_bounds__(kTileThreads, MINWG) void k_tile(const cpx<T>* src, cpx<T>* dst,
                                                               const int32_t* __restrict__ prog) {
   const TileIO io{0, 1, 0, nullptr, nullptr, 0};
-  (void)tile_body<T, TBMAX, RB, BODY>(psi, prog, blockIdx.x, io);
+  (void)tile_body<T, TBMAX, RB, BODY>(src, dst, prog, blockIdx.x, io);
 }
 
 // A 16-byte vector of amplitudes (two complex64 or one complex128) as a
@@ -809,7 +814,8 @@ __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile_pipe(cpx<T>* __res
 // variant that loaded the next pair into registers during the stores ran
 // 25% slower: its joins made the compiler wait for the loads early).
 template <typename T>
-__global__ __launch_bounds__(kTileThreads) void k_qperm(cpx<T>* __restrict__ psi, const int32_t* __restrict__ prog) {
+__global__ __launch_bounds__(kTileThreads) void k_qperm(const cpx<T>* src, cpx<T>* dst,
+                                                        const int32_t* __restrict__ prog) {
   constexpr int A = VecInfo<T>::A;
   constexpr int TP = QpermCfg<T>::TP;
   constexpr int SB = SwzBits<T>::B;
@@ -842,7 +848,8 @@ __global__ __launch_bounds__(kTileThreads) void k_qperm(cpx<T>* __restrict__ psi
   __syncthreads();
   const uint32_t cmask = (1u << c) - 1u;
   const int nvec = (1 << t) / A;
-  vec16<T>* gv = reinterpret_cast<vec16<T>*>(psi);
+  const vec16<T>* gv = reinterpret_cast<const vec16<T>*>(src);
+  vec16<T>* gw = reinterpret_cast<vec16<T>*>(dst);
   const uint64_t ntiles = 1ull << nns;
   for (uint64_t tid = blockIdx.x; tid < ntiles; tid += gridDim.x) {
     uint64_t tid2 = 0;
@@ -891,8 +898,8 @@ __global__ __launch_bounds__(kTileThreads) void k_qperm(cpx<T>* __restrict__ psi
         if (pair) y.a[e] = lds[1][src];
       }
       // the partner tile takes this tile's amplitudes (a fixed tile its own)
-      gv[(base2 | off) / A] = x;
-      if (pair) gv[(base | off) / A] = y;
+      gw[(base2 | off) / A] = x;
+      if (pair) gw[(base | off) / A] = y;
     }
     __syncthreads();  // the LDS is reused by the next pair
   }
@@ -1072,7 +1079,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_batch(cpx<T>* __restrict__ 
       const TileIO io{p == 0, p + 1 < np, p + 1 == np, zt + t0, ct + t0, (int)nt};
       if constexpr (FULL) {
         for (uint64_t tid = 0; tid < ntiles; ++tid)
-          acc += tile_body<T, TBMAX, RB, kBodyFull>(scratch + soff, prog, tid, io);
+          acc += tile_body<T, TBMAX, RB, kBodyFull>(scratch + soff, scratch + soff, prog, tid, io);
       } else {
         acc += batch_pass<T, TBMAX, RB>(scratch + soff, prog, ntiles, io);
       }
@@ -1142,7 +1149,16 @@ static hipError_t launch_pass(cpx<T>* psi, const int32_t* prog_dev, uint64_t nti
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_tile<T, TB, RB, BODY, MINWG>), dim3((unsigned)ntiles), dim3(kTileThreads), 0, st, psi,
+  hipLaunchKernelGGL((k_tile<T, TB, RB, BODY, MINWG>), dim3((unsigned)ntiles), dim3(kTileThreads), 0, st, psi, psi,
+                     prog_dev);
+  return hipGetLastError();
+}
+
+// The same pass out of place (src to dst), always one workgroup per tile.
+template <typename T, int TB, int RB, int BODY, int MINWG>
+static hipError_t launch_pass_oop(const cpx<T>* src, cpx<T>* dst, const int32_t* prog_dev, uint64_t ntiles,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL((k_tile<T, TB, RB, BODY, MINWG>), dim3((unsigned)ntiles), dim3(kTileThreads), 0, st, src, dst,
                      prog_dev);
   return hipGetLastError();
 }
@@ -1172,17 +1188,42 @@ hipError_t launch_tile_pass(cpx<T>* psi, int n, const int32_t* prog_dev, const i
   return launch_pass<T, TB, RB, kBodyLean, 2>(psi, prog_dev, ntiles, pipe, st);
 }
 
-// One qubit-permutation pass (program: see tile.hpp, kind kPassQperm).
+// One fused tile pass out of place (src to dst, for the race check).
 template <typename T>
-hipError_t launch_qperm(cpx<T>* psi, int n, const int32_t* prog_dev, const int32_t* prog_host, hipStream_t st) {
+hipError_t launch_tile_pass_oop(const cpx<T>* src, cpx<T>* dst, int n, const int32_t* prog_dev,
+                                const int32_t* prog_host, int body, hipStream_t st) {
+  constexpr int TB = TileCfg<T>::TBMAX, RB = TileCfg<T>::RB;
+  const int t = prog_host[0];
+  const uint64_t ntiles = 1ull << (n - t);
+  if (t <= TB - 1) {
+    if (body == kBodyFull) return launch_pass_oop<T, TB - 1, RB, kBodyFull, 2>(src, dst, prog_dev, ntiles, st);
+    if (body == kBodyPerm) return launch_pass_oop<T, TB - 1, RB, kBodyPerm, 3>(src, dst, prog_dev, ntiles, st);
+    return launch_pass_oop<T, TB - 1, RB, kBodyLean, 3>(src, dst, prog_dev, ntiles, st);
+  }
+  if (body == kBodyFull) return launch_pass_oop<T, TB, RB, kBodyFull, 2>(src, dst, prog_dev, ntiles, st);
+  if (body == kBodyPerm) return launch_pass_oop<T, TB, RB, kBodyPerm, 2>(src, dst, prog_dev, ntiles, st);
+  return launch_pass_oop<T, TB, RB, kBodyLean, 2>(src, dst, prog_dev, ntiles, st);
+}
+template hipError_t launch_tile_pass_oop<float>(const cpx<float>*, cpx<float>*, int, const int32_t*, const int32_t*,
+                                                int, hipStream_t);
+template hipError_t launch_tile_pass_oop<double>(const cpx<double>*, cpx<double>*, int, const int32_t*,
+                                                 const int32_t*, int, hipStream_t);
+
+// One qubit-permutation pass (program: see tile.hpp, kind kPassQperm).
+// src == dst for the pass in place; distinct buffers for the race check.
+template <typename T>
+hipError_t launch_qperm(const cpx<T>* src, cpx<T>* dst, int n, const int32_t* prog_dev, const int32_t* prog_host,
+                        hipStream_t st) {
   const uint64_t ntiles = 1ull << (n - prog_host[0]);
   const int resident = qperm_grid<T>();
   const unsigned grid = (unsigned)std::min<uint64_t>(ntiles, (uint64_t)(resident > 0 ? resident : 1024));
-  hipLaunchKernelGGL(k_qperm<T>, dim3(grid), dim3(kTileThreads), 0, st, psi, prog_dev);
+  hipLaunchKernelGGL(k_qperm<T>, dim3(grid), dim3(kTileThreads), 0, st, src, dst, prog_dev);
   return hipGetLastError();
 }
-template hipError_t launch_qperm<float>(cpx<float>*, int, const int32_t*, const int32_t*, hipStream_t);
-template hipError_t launch_qperm<double>(cpx<double>*, int, const int32_t*, const int32_t*, hipStream_t);
+template hipError_t launch_qperm<float>(const cpx<float>*, cpx<float>*, int, const int32_t*, const int32_t*,
+                                        hipStream_t);
+template hipError_t launch_qperm<double>(const cpx<double>*, cpx<double>*, int, const int32_t*, const int32_t*,
+                                         hipStream_t);
 
 template <typename T>
 hipError_t launch_batch(cpx<T>* scratch, const int32_t* progs, const int64_t* passoff,

@@ -42,7 +42,7 @@ class QsvOp(ctypes.Structure):
 class QsvPlanOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
                 ("state_is_output", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("race_check", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 assert ctypes.sizeof(QsvOp) == 64
@@ -264,15 +264,20 @@ class State:
         check(lib().qsv_apply_fused(self.handle, _i32(qubits), len(qubits),
                                     m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
-    def apply_circuit(self, ops, mode: str = "auto", tile_qubits: int = 0, graph: bool = False) -> None:
+    def apply_circuit(self, ops, mode: str = "auto", tile_qubits: int = 0, graph: bool = False,
+                      race_check: bool = False) -> None:
         """Apply a gate list.  graph=True launches the fused plan's passes as
         the state's hipGraph (captured once per plan structure, replayed with
-        this call's angles); the state must be on a non-null stream."""
+        this call's angles); the state must be on a non-null stream.
+        race_check=True runs every fused pass out of place into a poisoned
+        buffer first and raises QsvError if an amplitude was left unwritten
+        or differs from the in-place pass."""
         ol = ops if isinstance(ops, OpList) else OpList(ops)
         opts = QsvPlanOpts()
         opts.mode = MODES[mode]
         opts.tile_qubits = int(tile_qubits)
         opts.graph = 1 if graph else 0
+        opts.race_check = 1 if race_check else 0
         check(lib().qsv_apply_circuit(self.handle, ol.arr, ol.n, ctypes.byref(opts)))
 
     def plan_info(self, ops, tile_qubits: int = 0) -> dict:

@@ -21,7 +21,7 @@ def test_library_exports_every_header_function():
 def test_plan_opts_layout():
     assert ctypes.sizeof(qsv.QsvPlanOpts) == 32
     assert qsv.QsvPlanOpts.state_is_output.offset == 8 and qsv.QsvPlanOpts.graph.offset == 12
-    assert qsv.QsvPlanOpts.reserved.offset == 16
+    assert qsv.QsvPlanOpts.race_check.offset == 16 and qsv.QsvPlanOpts.reserved.offset == 20
 
 
 def test_op_struct_is_64_bytes():
