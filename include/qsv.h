@@ -92,7 +92,14 @@ typedef struct qsv_op {
 /* Execution strategy of qsv_apply_circuit.
  *   mode 0 = automatic (fused tile passes; the per-gate form when the
  *   environment has QSV_FORCE_PERGATE=1, read once per process), 1 = one
- *   kernel per gate ("plain per-gate form"), 2 = fused tile passes.
+ *   kernel per gate ("plain per-gate form"), 2 = fused tile passes, 3 =
+ *   fused tile passes with the tile shape (tile qubits, and the contiguous
+ *   segment qubits every tile keeps) chosen by an autotuner: the first call
+ *   of a gate structure times the candidate plans' passes on a copy of the
+ *   state (allocating a second state-sized buffer) and keeps the fastest,
+ *   per structure in the process and in the QSV_AUTOTUNE_CACHE file if the
+ *   environment names one (see qsv_batch_create); tile_qubits > 0 skips the
+ *   tuning.
  *   tile_qubits: qubits per LDS tile in fused mode (0 = library choice).
  *   state_is_output (qsv_adjoint only, 0 or 1): 1 = the state already holds
  *   the circuit's output (an earlier qsv_apply_circuit of the same ops), so

@@ -471,7 +471,7 @@ qsv_status qsv_apply_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const q
   if (n_ops > 0 && !ops) return fail(QSV_ERR_ARG, "ops is NULL");
   qsv_plan_opts o{};
   if (opts) o = *opts;
-  if (o.mode < 0 || o.mode > 2) return fail(QSV_ERR_ARG, "mode must be 0, 1 or 2");
+  if (o.mode < 0 || o.mode > 3) return fail(QSV_ERR_ARG, "mode must be 0, 1, 2 or 3");
   if (o.state_is_output) return fail(QSV_ERR_ARG, "state_is_output applies to qsv_adjoint only");
   if (o.graph != 0 && o.graph != 1) return fail(QSV_ERR_ARG, "graph must be 0 or 1");
   if (o.graph && o.mode == 1) return fail(QSV_ERR_ARG, "graph applies to the fused modes only");
@@ -1468,7 +1468,7 @@ qsv_status qsv_adjoint(qsv_state* s, const qsv_op* ops, int n_ops, const uint64_
   if (st) return st;
   qsv_plan_opts o{};
   if (opts) o = *opts;
-  if (o.mode < 0 || o.mode > 2) return fail(QSV_ERR_ARG, "mode must be 0, 1 or 2");
+  if (o.mode < 0 || o.mode > 3) return fail(QSV_ERR_ARG, "mode must be 0, 1, 2 or 3");
   if (o.state_is_output != 0 && o.state_is_output != 1) return fail(QSV_ERR_ARG, "state_is_output must be 0 or 1");
   if (o.graph) return fail(QSV_ERR_ARG, "graph applies to qsv_apply_circuit only");
   if (o.race_check) return fail(QSV_ERR_ARG, "race_check applies to qsv_apply_circuit only");

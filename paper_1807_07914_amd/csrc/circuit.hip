@@ -379,8 +379,9 @@ static int env_segment_qubits() {
   }();
   return v;
 }
-static std::shared_ptr<Schedule> plan_tile_passes(const std::vector<POp>& P, int n, int t, bool f32, int RB) {
-  const int forced = env_segment_qubits();
+static std::shared_ptr<Schedule> plan_tile_passes(const std::vector<POp>& P, int n, int t, bool f32, int RB,
+                                                  int force_c) {
+  const int forced = force_c > 0 ? force_c : env_segment_qubits();
   int c = forced ? forced : (f32 ? 5 : 4);
   if (!f32) c = 4;
   if (c > t) c = t;
@@ -453,16 +454,17 @@ static std::vector<std::vector<int>> involution_passes(const std::vector<int>& s
 // steps, and, when the list has SWAPs and relabeling them away needs fewer
 // passes in all, the plan of the relabeled list followed by its
 // qubit-permutation passes.
-static std::shared_ptr<Schedule> plan_schedule(const std::vector<qsv_op>& xops, int n, int t, bool f32, int RB) {
+static std::shared_ptr<Schedule> plan_schedule(const std::vector<qsv_op>& xops, int n, int t, bool f32, int RB,
+                                               int force_c = 0) {
   std::vector<POp> P(xops.size());
   for (size_t i = 0; i < xops.size(); ++i) P[i] = classify(xops[i]);
-  auto sch = plan_tile_passes(P, n, t, f32, RB);
+  auto sch = plan_tile_passes(P, n, t, f32, RB, force_c);
   std::vector<qsv_op> rops;
   std::vector<int> lab;
   if (!relabel_swaps(xops, n, rops, lab)) return sch;
   std::vector<POp> R(rops.size());
   for (size_t i = 0; i < rops.size(); ++i) R[i] = classify(rops[i]);
-  auto alt = plan_tile_passes(R, n, t, f32, RB);
+  auto alt = plan_tile_passes(R, n, t, f32, RB, force_c);
   const std::vector<std::vector<int>> inv = involution_passes(lab);
   if (alt->passes + (int)inv.size() >= sch->passes) return sch;
   for (const std::vector<int>& v : inv) {
@@ -1557,6 +1559,144 @@ static bool program_needs_full(const int32_t* pass) {
 }
 
 // ------------------------------------------------------------- driver
+// ------------------------------------------------------ autotuner cache
+// Choices of the autotuners by structure hash: tile qubits for a batch;
+// 100 * tile qubits + segment qubits for a single-state plan (mode 3; its
+// hashes are kept apart from the batches' by a constant mixed in).  They
+// persist across processes when QSV_AUTOTUNE_CACHE names a file: it is read
+// once, at the first tuning of the process, and every new result is
+// appended as a line "<structure hash, hex> <value>".  Unreadable lines end
+// the read; a value outside the dtype's range is ignored when it is looked
+// up.  Callers hold g_tune_mu.
+static std::mutex g_tune_mu;
+static std::unordered_map<uint64_t, int> g_tuned;
+static const char* tune_cache_path() {
+  const char* p = std::getenv("QSV_AUTOTUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+static void tuned_load_once() {
+  static bool loaded = false;
+  if (loaded) return;
+  loaded = true;
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  unsigned long long h = 0;
+  int t = 0;
+  while (std::fscanf(f, "%llx %d", &h, &t) == 2) g_tuned[(uint64_t)h] = t;
+  std::fclose(f);
+}
+static void tuned_store(uint64_t h, int t) {
+  g_tuned[h] = t;
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%016llx %d\n", (unsigned long long)h, t);
+  std::fclose(f);
+}
+
+// Single-state autotuner (plan mode 3): the candidate shapes (tile qubits
+// TBMAX and TBMAX - 1; segment qubits 5 and 4 for complex64, 4 for
+// complex128) are planned, and the tile and permutation passes of each are
+// timed once on a copy of the state in the second state-sized buffer (the
+// per-gate steps are the same in every candidate); the fastest shape is kept
+// for the structure.  Returns the tile and segment qubits to plan with.
+template <typename T>
+static qsv_status tuned_shape(qsv_state* s, const std::vector<qsv_op>& xops, int* t_out, int* c_out) {
+  const int RB = tile_reg_bits<T>(), TBMAX = tile_max_bits<T>();
+  const int n = s->n;
+  const bool f32 = sizeof(T) == 4;
+  std::vector<POp> P(xops.size());
+  for (size_t i = 0; i < xops.size(); ++i) P[i] = classify(xops[i]);
+  const uint64_t h = mix(key_hash(structure_key(P, n, 0, f32 ? -1 : -2, RB)), 0x53494e474c45ull);  // "SINGLE"
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tuned_load_once();
+    auto it = g_tuned.find(h);
+    if (it != g_tuned.end()) {
+      const int tt = it->second / 100, cc = it->second % 100;
+      if (tt >= RB && tt <= std::min(TBMAX, n) && cc >= 1 && cc <= tt && n - tt <= 23) {
+        *t_out = tt;
+        *c_out = cc;
+        return QSV_OK;
+      }
+    }
+  }
+  qsv_status st = ensure_aux(s, "hipMalloc(autotuner buffer)");
+  if (st) return st;
+  cpx<T>* scratch = static_cast<cpx<T>*>(s->aux);
+  QSV_HIP(hipMemcpyAsync(scratch, s->psi, s->bytes, hipMemcpyDeviceToDevice, s->stream));
+  hipEvent_t e0, e1;
+  QSV_HIP(hipEventCreate(&e0));
+  QSV_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_t = std::min(TBMAX, n), best_c = 0;
+  std::vector<int32_t> prog;
+  qsv_status rc = QSV_OK;
+  for (int tt = std::min(TBMAX, n); tt >= std::max(RB, std::min(TBMAX, n) - 1) && !rc; --tt) {
+    if (n - tt > 23) continue;
+    for (int cc : (f32 ? std::vector<int>{5, 4} : std::vector<int>{4})) {
+      if (cc > tt) continue;
+      auto sch = plan_schedule(xops, n, tt, f32, RB, cc);
+      std::vector<qsv_op> rbuf;
+      const std::vector<qsv_op>& sops = step_ops(*sch, xops, n, rbuf);
+      std::vector<POp> SP(sops.size());
+      for (size_t i = 0; i < sops.size(); ++i) SP[i] = classify(sops[i]);
+      prog.clear();
+      std::vector<size_t> offs;
+      bool ok = true;
+      for (const Step& stp : sch->steps) {
+        offs.push_back(prog.size());
+        if (!stp.inv.empty()) emit_qperm<T>(stp.inv, n, prog);
+        if (stp.tile) ok = ok && emit_pass<T>(stp, SP, n, sch->c, RB, prog);
+      }
+      if (!ok) continue;
+      const size_t need = prog.size() * sizeof(int32_t) + 256;
+      if (s->pbuf_bytes < need) {
+        QSV_HIP(hipStreamSynchronize(s->stream));
+        if (s->pbuf) QSV_HIP(hipFree(s->pbuf));
+        s->pbuf = nullptr;
+        s->pbuf_bytes = 0;
+        QSV_HIP(hipMalloc(&s->pbuf, need * 2));
+        s->pbuf_bytes = need * 2;
+      }
+      int32_t* dprog = static_cast<int32_t*>(s->pbuf);
+      if (!prog.empty())
+        QSV_HIP(hipMemcpyAsync(dprog, prog.data(), prog.size() * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
+      QSV_HIP(hipEventRecord(e0, s->stream));
+      for (size_t k = 0; k < sch->steps.size(); ++k) {
+        const Step& stp = sch->steps[k];
+        const int32_t* ph = prog.data() + offs[k];
+        if (!stp.inv.empty())
+          QSV_HIP(launch_qperm<T>(scratch, scratch, n, dprog + offs[k], ph, s->stream));
+        else if (stp.tile)
+          QSV_HIP(launch_tile_pass<T>(scratch, n, dprog + offs[k], ph, program_body<T>(ph), s->stream));
+      }
+      QSV_HIP(hipEventRecord(e1, s->stream));
+      QSV_HIP(hipEventSynchronize(e1));  // also keeps prog alive for the upload
+      float ms = 0;
+      QSV_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_t = tt;
+        best_c = sch->c;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best_c == 0) best_c = std::min(f32 ? 5 : 4, best_t);  // no candidate could be encoded
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tuned_store(h, 100 * best_t + best_c);
+  }
+  *t_out = best_t;
+  *c_out = best_c;
+  return QSV_OK;
+}
+
 // Launch a plan whose steps are all tile passes through the state's graph:
 // capture the passes once for what their launches depend on (the signature
 // below), replay afterwards.  The program words were uploaded to dprog on
@@ -1682,11 +1822,16 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
   // one workgroup per tile in the non-persistent tile kernel: the launch's
   // work-items (2^(n-t) * 256) must stay below 2^32
   if (n - t > 23) return fail(QSV_ERR_UNSUPPORTED, "tile_qubits too small for this register (over 2^23 tiles)");
+  int force_c = 0;  // segment qubits chosen by the autotuner (0: by the planner)
+  if (opts.mode == 3 && opts.tile_qubits == 0) {
+    qsv_status st = tuned_shape<T>(s, xops, &t, &force_c);
+    if (st) return st;
+  }
   std::vector<POp> P(n_ops);
   for (int i = 0; i < n_ops; ++i) P[i] = classify(ops[i]);
-  // the key carries the dtype in place of the segment width: the cached
-  // schedule holds the width the planner chose
-  std::vector<uint32_t> key = structure_key(P, n, t, sizeof(T) == 4 ? -1 : -2, RB);
+  // the key carries the dtype in place of the segment width when the
+  // planner chooses it (the cached schedule holds the width it chose)
+  std::vector<uint32_t> key = structure_key(P, n, t, force_c ? force_c : (sizeof(T) == 4 ? -1 : -2), RB);
   const uint64_t h = key_hash(key);
   std::shared_ptr<Schedule> sch;
   {
@@ -1695,7 +1840,7 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
     if (it != g_cache.end() && it->second->key == key) sch = it->second;
   }
   if (!sch) {
-    sch = plan_schedule(xops, n, t, sizeof(T) == 4, RB);
+    sch = plan_schedule(xops, n, t, sizeof(T) == 4, RB, force_c);
     sch->key = std::move(key);
     std::lock_guard<std::mutex> lk(g_cache_mu);
     if (g_cache.size() > 256) g_cache.clear();
@@ -1917,39 +2062,6 @@ namespace qsv {
 
 static std::mutex g_batch_mu;
 static std::unordered_set<const qsv_batch*> g_batches;
-static std::unordered_map<uint64_t, int> g_tuned;  // structure hash -> tile bits
-
-// The autotuner's results persist across processes when QSV_AUTOTUNE_CACHE
-// names a file: it is read once, at the first tuning of the process, and
-// every new result is appended as a line "<structure hash, hex> <tile qubits>".
-// Unreadable lines end the read; a width outside the dtype's range is ignored
-// when it is looked up.  Callers hold g_batch_mu.
-static const char* tune_cache_path() {
-  const char* p = std::getenv("QSV_AUTOTUNE_CACHE");
-  return (p && *p) ? p : nullptr;
-}
-static void tuned_load_once() {
-  static bool loaded = false;
-  if (loaded) return;
-  loaded = true;
-  const char* path = tune_cache_path();
-  if (!path) return;
-  FILE* f = std::fopen(path, "r");
-  if (!f) return;
-  unsigned long long h = 0;
-  int t = 0;
-  while (std::fscanf(f, "%llx %d", &h, &t) == 2) g_tuned[(uint64_t)h] = t;
-  std::fclose(f);
-}
-static void tuned_store(uint64_t h, int t) {
-  g_tuned[h] = t;
-  const char* path = tune_cache_path();
-  if (!path) return;
-  FILE* f = std::fopen(path, "a");
-  if (!f) return;
-  std::fprintf(f, "%016llx %d\n", (unsigned long long)h, t);
-  std::fclose(f);
-}
 
 static void batch_release_device(qsv_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -2137,7 +2249,7 @@ static qsv_status batch_create_T(qsv_batch* b, int tile_qubits) {
   // autotuner: candidate tile widths timed on the real batch, cached by structure
   const uint64_t h = key_hash(b->key);
   {
-    std::lock_guard<std::mutex> lk(g_batch_mu);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
     tuned_load_once();
     auto it = g_tuned.find(h);
     if (it != g_tuned.end() && it->second >= RB && it->second <= TBMAX) return batch_build<T>(b, it->second);
@@ -2161,7 +2273,7 @@ static qsv_status batch_create_T(qsv_batch* b, int tile_qubits) {
     }
   }
   {
-    std::lock_guard<std::mutex> lk(g_batch_mu);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
     tuned_store(h, best_t);
   }
   if (best_t != b->tile_bits) return batch_build<T>(b, best_t);

@@ -25,7 +25,7 @@ GATES = {
     "RX": 9, "RY": 10, "RZ": 11, "CNOT": 12, "CZ": 13, "CPHASE": 14, "SWAP": 15, "MAT": 16,
 }
 NPARAMS = {"RX": 1, "RY": 1, "RZ": 1, "CPHASE": 1}
-MODES = {"auto": 0, "pergate": 1, "fused": 2}
+MODES = {"auto": 0, "pergate": 1, "fused": 2, "tuned": 3}
 
 
 class QsvError(RuntimeError):

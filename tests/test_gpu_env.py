@@ -76,3 +76,36 @@ def test_autotune_cache_file(tmp_path):
     second = run_child(TUNE, QSV_AUTOTUNE_CACHE=path)
     assert second["tile_qubits"] == other
     assert open(path).read().split() == ["%016x" % h, str(other)]   # nothing re-tuned or appended
+
+
+TUNED = r"""
+import json, os, numpy as np, qcircuits as qc
+from paper_1807_07914_amd import State
+n = 18
+ops = qc.random_brickwork(n, 16, 6060)
+out = {}
+for mode, tile in (("tuned", 0), ("fused", 12)):
+    s = State(n, "c64")
+    s.apply_circuit(ops, mode=mode, tile_qubits=tile)
+    out[mode] = s.to_numpy()
+    s.close()
+print(json.dumps({"same_as_t12": bool(np.array_equal(out["tuned"], out["fused"]))}))
+"""
+
+
+def test_single_state_autotuner_cache_file(tmp_path):
+    # the first process times the candidate shapes and appends its choice;
+    # a later process takes a planted choice (12 tile qubits, 4 segment
+    # qubits) without timing: its result is then bit for bit the plan with
+    # that shape (segment width fixed to 4 by the environment for both)
+    path = str(tmp_path / "tune.txt")
+    run_child(TUNED, QSV_AUTOTUNE_CACHE=path)
+    words = open(path).read().split()
+    assert len(words) == 2
+    v = int(words[1])
+    assert v // 100 in (12, 13) and v % 100 in (4, 5)
+    with open(path, "w") as f:
+        f.write("%s %d\n" % (words[0], 1204))
+    second = run_child(TUNED, QSV_AUTOTUNE_CACHE=path, QSV_SEGMENT_QUBITS="4")
+    assert second["same_as_t12"]
+    assert open(path).read().split() == [words[0], "1204"]

@@ -384,6 +384,19 @@ def test_fused_swap_relabeling(dtype, n, tile, seed, layers):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n", [14, 22])
+def test_tuned_mode_matches_oracle(dtype, n):
+    # mode "tuned": the autotuner picks the tile shape on the first call of
+    # the structure (timing on a copy of the state), later calls reuse it
+    ops = qc.random_brickwork(n, 12, 1500 + n) + [qc.op("SWAP", 0, n - 1)] + qc.qft(n)
+    psi0 = start(n, dtype, 1510 + n)
+    ref = O.run(ops, n, psi=psi0.copy())
+    first = gpu_run(n, dtype, psi0, ops, "tuned")
+    assert np.abs(first - ref).max() <= TOL[dtype]
+    assert np.array_equal(gpu_run(n, dtype, psi0, ops, "tuned"), first)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 def test_fused_qft_bit_reversal_pass(dtype):
     # 22 qubits: the QFT's swaps become one bit-reversal pass (complex64),
     # against the oracle element by element from a random state
