@@ -710,6 +710,8 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
     cd r;
   };
   std::vector<std::vector<PhTerm>> tfac;  // the pass's tile-factor slots
+  std::vector<cd> ltab;                   // the pass's lane table
+  const size_t kLaneTab = kLaneTabBytes / (2 * sizeof(T));
   // diagonal work that runs between two non-diagonal ops of a round
   struct DGroup {
     bool tab = false;
@@ -1287,9 +1289,40 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
         } else {
           terms.insert(terms.end(), outside.begin(), outside.end());
         }
+        // lane-table form: every term on one free bit, none on an outside
+        // qubit; the product over the group's terms is one entry of each of
+        // two 16-entry tables indexed by the group's compact free bits
+        bool table = !terms.empty() && ltab.size() + 32 <= kLaneTab;
+        cd rk[8] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
+        const uint32_t fm = tmask & ~rmask;
+        for (const PhTerm& tm : terms) {
+          if (!table) break;
+          if (tm.om != 0 || __builtin_popcount(tm.lgm) != 1 || !(tm.lgm & fm)) {
+            table = false;
+            break;
+          }
+          const int k = __builtin_popcount(fm & (tm.lgm - 1u));
+          if (k >= 8) {
+            table = false;
+            break;
+          }
+          rk[k] *= tm.r;
+        }
         w.push_back(phl[e].first);
         w.push_back(slot);
         w.push_back(unit ? 1 : 0);
+        if (table) {
+          w.push_back(-1);
+          w.push_back((int32_t)ltab.size());
+          for (int half = 0; half < 2; ++half)
+            for (int v = 0; v < 16; ++v) {
+              cd f = 1.0;
+              for (int k = 0; k < 4; ++k)
+                if ((v >> k) & 1) f *= rk[4 * half + k];
+              ltab.push_back(f);
+            }
+          return;
+        }
         w.push_back((int32_t)terms.size());
         for (auto& tm : terms) {
           w.push_back((int32_t)tm.lgm);
@@ -1518,6 +1551,18 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
     const size_t rb0 = h0 + (size_t)prog[roff0];
     prog[rb0 + kHdrTileFac] = (int32_t)(l0 - h0);
     prog[rb0 + kHdrTileFac + 1] = (int32_t)K;
+    while ((prog.size() - h0) % 16) prog.push_back(0);
+  }
+  if (!ltab.empty()) {
+    // the lane table after the round blocks (and the tile-factor list)
+    const size_t l1 = prog.size();
+    for (const cd& f : ltab) {
+      RealWords<T>::put(f.real(), prog);
+      RealWords<T>::put(f.imag(), prog);
+    }
+    const size_t rb0 = h0 + (size_t)prog[roff0];
+    prog[rb0 + kHdrLaneTab] = (int32_t)(l1 - h0);
+    prog[rb0 + kHdrLaneTabN] = (int32_t)ltab.size();
     while ((prog.size() - h0) % 16) prog.push_back(0);
   }
   return true;

@@ -288,9 +288,29 @@ __device__ __forceinline__ double aux_real<double>(const int32_t* __restrict__ a
 // tile held in LDS at `tb`.  Round headers, layer records, aux words and
 // tables are read with scalar loads (the addresses are uniform), so every
 // field lands in a scalar register.  Every round ends with a barrier.
+// Copy a pass's lane table (see tile.hpp) into LDS; the caller's next
+// barrier publishes it.  Called before the first tile of the pass, while no
+// load of a tile is in flight (vector loads complete in order).
+template <typename T>
+__device__ __forceinline__ void stage_lane_table(const int32_t* __restrict__ pass, cpx<T>* __restrict__ lt) {
+  constexpr int WT = WordsPer<T>::W;
+  const int t = pass[0], nns = pass[2], nrounds = pass[3];
+  if (nrounds <= 0) return;
+  const int32_t* rb0 = pass + pass[4 + t + nns];
+  const int ne = rb0[kHdrLaneTabN];
+  const int32_t* e = pass + rb0[kHdrLaneTab];
+  for (int i = threadIdx.x; i < ne; i += kTileThreads)
+    lt[i] = cpx<T>{aux_real<T>(e, 2 * i * WT), aux_real<T>(e, (2 * i + 1) * WT)};
+}
+
+template <typename T>
+struct LaneTab {
+  static constexpr int N = kLaneTabBytes / (int)sizeof(cpx<T>);
+};
+
 template <typename T, int TBMAX, int RB, int BODY>
 __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t* __restrict__ pass, int t,
-                                           int nns, uint64_t base) {
+                                           int nns, uint64_t base, const cpx<T>* __restrict__ lt) {
   constexpr int NR = 1 << RB;
   constexpr int SB = SwzBits<T>::B;
   constexpr int WT = WordsPer<T>::W;
@@ -431,6 +451,12 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
             p += 4;
             cpx<T> w{T(1), T(0)};
             if (slot >= 0) w = tfac[slot];  // uniform address: one broadcast read
+            if (nt < 0) {
+              // lane-table form: the group's terms as two table entries
+              const int e0 = ap[p++];
+              const cpx<T> f = cmul(lt[e0 + (gi & 15)], lt[e0 + 16 + ((gi >> 4) & 15)]);
+              w = cmul(f, w);
+            }
             for (int q = 0; q < nt; ++q, p += 3 + 2 * WT) {
               // every word read before the lane condition (scalar loads; a
               // read inside the divergent branch became a vector load that
@@ -611,6 +637,8 @@ __device__ __forceinline__ double tile_body(const cpx<T>* src, cpx<T>* dst, cons
       if ((h >> j) & 1) o |= 1ull << S[c + j];
     segoff[h] = o;
   }
+  __shared__ cpx<T> ltab[LaneTab<T>::N];
+  stage_lane_table<T>(prog, ltab);
   __syncthreads();
 
   // ---- load the tile (coalesced 16-byte vectors) into LDS
@@ -642,7 +670,7 @@ __device__ __forceinline__ double tile_body(const cpx<T>* src, cpx<T>* dst, cons
   __syncthreads();
 
   // ---- rounds
-  run_rounds<T, TBMAX, RB, BODY>(reinterpret_cast<char*>(tile), prog, t, nns, base);
+  run_rounds<T, TBMAX, RB, BODY>(reinterpret_cast<char*>(tile), prog, t, nns, base, ltab);
 
   // ---- Z-string sum over the tile (FP64)
   double acc = 0.0;
@@ -744,6 +772,8 @@ __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile_pipe(cpx<T>* __res
       if ((h >> j) & 1) o |= 1ull << S[c + j];
     segoff[h] = o;
   }
+  __shared__ cpx<T> ltab[LaneTab<T>::N];
+  stage_lane_table<T>(prog, ltab);
   __syncthreads();
 
   // 16-byte vectors as native vector types (kept in registers)
@@ -782,7 +812,7 @@ __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile_pipe(cpx<T>* __res
   if (tid + gridDim.x < ntiles) fetch(tid + gridDim.x);
   for (;;) {
     const uint64_t base = tile_base(tid);
-    run_rounds<T, TBMAX, RB, BODY>(reinterpret_cast<char*>(tile), prog, t, nns, base);
+    run_rounds<T, TBMAX, RB, BODY>(reinterpret_cast<char*>(tile), prog, t, nns, base, ltab);
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
       const uint32_t l = (uint32_t)(threadIdx.x + k * kTileThreads) * A;
@@ -950,6 +980,8 @@ __device__ __forceinline__ double batch_pass(cpx<T>* __restrict__ psi, const int
       if ((h >> j) & 1) o |= 1ull << S[c + j];
     segoff[h] = o;
   }
+  __shared__ cpx<T> ltab[LaneTab<T>::N];
+  stage_lane_table<T>(prog, ltab);
   __syncthreads();
   V* gv = reinterpret_cast<V*>(psi);
   const int nvec = (1 << t) / A;
@@ -1006,7 +1038,7 @@ __device__ __forceinline__ double batch_pass(cpx<T>* __restrict__ psi, const int
         }
       }
     }
-    run_rounds<T, TBMAX, RB, kBodyLean>(reinterpret_cast<char*>(tile), prog, t, nns, base);
+    run_rounds<T, TBMAX, RB, kBodyLean>(reinterpret_cast<char*>(tile), prog, t, nns, base, ltab);
     if (io.reduce) {
       for (int l = threadIdx.x; l < (1 << t); l += kTileThreads) {
         const uint64_t g = base | segoff[(uint32_t)l >> c] | ((uint32_t)l & cmask);

@@ -68,7 +68,19 @@
 //                 set in the group and whose outside qubits omask are all set
 //                 in the tile, applied to the amplitudes with register bit j
 //                 set (every amplitude if j < 0).  unit = 1: every factor has
-//                 modulus 1, so w is applied as a pure phase.
+//                 modulus 1, so w is applied as a pure phase.  Lane-table
+//                 form (nt = -1): aux j, slot, unit, -1, e: every term
+//                 is on one free bit and no outside qubit, and the product
+//                 over the group's terms is L[e + (g & 15)] L[e + 16 + (g >> 4)]
+//                 with g the group's index over the free bits (bit k of g is
+//                 the k-th free local bit, ascending) and L the pass's lane
+//                 table.
+//   lane table (one per pass, optional): complex entries (r) at the word
+//                 offset in the first round's header word kHdrLaneTab (from
+//                 the pass start), their number in word kHdrLaneTabN; the
+//                 kernel copies them to LDS before its first tile, so a
+//                 per-group phase step costs two LDS reads instead of a loop
+//                 over its terms.
 //   tile-factor list (one per pass, optional): K word offsets of the entries
 //                 (from the list's start), then each entry nt,
 //                 (omask_lo, omask_hi, r)*nt.  At the start of every tile,
@@ -149,6 +161,9 @@ constexpr int kTableWords = 64;   // words of a table
 constexpr int kHdrTileFac = 8;    // round-header word of the tile-factor list offset
 constexpr int kHdrStore = 10;     // round-header words of the store's register-bit offsets
 constexpr int kMaxTileFactors = 128;  // tile-factor slots of one pass
+constexpr int kHdrLaneTab = 7;        // first round's header word of the lane-table offset
+constexpr int kHdrLaneTabN = 15;      // first round's header word of the lane-table entry count
+constexpr int kLaneTabBytes = 8192;   // LDS of a pass's lane tables (1024 complex64 / 512 complex128)
 constexpr int kPassQperm = -1;        // n_rounds word of a qubit-permutation pass
 
 // Largest tile of a qubit-permutation pass: a pair of tiles takes 16 KiB of

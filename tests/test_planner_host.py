@@ -238,3 +238,21 @@ def test_relabeling_only_when_it_saves_passes():
     # the 30-qubit QFT: three tile passes and the bit reversal
     assert plan_kinds(30, "c64", qc.qft(30)) == "TTTP"
     assert qsv.plan_info(30, "c64", qc.qft(30))["passes"] == 4
+
+
+@pytest.mark.parametrize("dtype,n", [("c64", 13), ("c128", 12)])
+def test_emulated_lane_tables_full_tile(dtype, n):
+    # a full tile has 8 free bits, so the per-group phase steps' lane tables
+    # use both of their 16-entry halves; the plan must take that form
+    ops = qc.qft(n) + qc.random_brickwork(n, 2, 91)
+    words, steps = E.program(n, dtype, ops)
+    W = [int(x) for x in words]
+    nlane = 0
+    for s in steps:
+        if s >= 0 and not E.is_qperm(words, int(s)):
+            blocks = E._round_blocks(W, int(s), W[s], W[s + 2])
+            nlane += W[blocks[0] + E.LANE_TAB_N_HDR] if blocks else 0
+    assert nlane >= 64
+    psi0 = qc.random_state(n, 300 + n)
+    got = E.emulate(n, dtype, ops, psi0)
+    assert np.abs(got - O.run(ops, n, psi=psi0.copy())).max() <= TOL[dtype]

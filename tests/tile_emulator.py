@@ -30,6 +30,8 @@ TK_REG, TK_FREE, TK_OUT = 0, 1, 2
 CFG = {"c64": dict(RB=5, SB=5, WT=1, LR=16), "c128": dict(RB=4, SB=4, WT=2, LR=24)}
 TILE_FAC_HDR, MAX_TILE_FACTORS = 8, 128  # round-header word of the tile-factor list; slot cap
 STORE_HDR = 10  # round-header words of the store's register-bit offsets
+LANE_TAB_HDR, LANE_TAB_N_HDR = 7, 15  # first round's header: lane-table offset, entries
+LANE_TAB_BYTES = 8192
 
 
 def program(n, dtype, ops, tile=0):
@@ -141,6 +143,12 @@ def run_pass(psi, n, words, off, cfg):
     blocks = _round_blocks(words, off, t, nns)
     esz = 8 * WT  # bytes per amplitude: the header holds LDS byte offsets
     # the pass's tile-factor list (pointed to by the first round's header)
+    lane = []  # the pass's lane table (complex entries)
+    if blocks:
+        lo, ne = words[blocks[0] + LANE_TAB_HDR], words[blocks[0] + LANE_TAB_N_HDR]
+        assert 0 <= ne <= LANE_TAB_BYTES // (8 * WT) and (ne == 0 or lo > 0)
+        if ne:
+            lane = _cplx(words, off + lo, WT, ne)
     tfl = []
     if blocks:
         lo, nk = words[blocks[0] + TILE_FAC_HDR], words[blocks[0] + TILE_FAC_HDR + 1]
@@ -238,6 +246,12 @@ def run_pass(psi, n, words, off, cfg):
                         p += 4
                         assert -1 <= j < RB and -1 <= slot < len(tfl) and unit in (0, 1)
                         w = tfac[slot] if slot >= 0 else 1.0 + 0j
+                        if nt == -1:  # lane-table form
+                            e0 = blk[p]
+                            p += 1
+                            assert 0 <= e0 and e0 + 32 <= len(lane)
+                            w *= lane[e0 + (gi & 15)] * lane[e0 + 16 + ((gi >> 4) & 15)]
+                            nt = 0
                         for _ in range(nt):
                             lgm = blk[p] & 0xffffffff
                             om = (blk[p + 1] & 0xffffffff) | ((blk[p + 2] & 0xffffffff) << 32)
