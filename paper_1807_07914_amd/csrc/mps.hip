@@ -93,6 +93,23 @@ __device__ __forceinline__ double dpp_sum(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
   return v + __hiloint2double(hi, lo);
 }
+// 1/sqrt(x) and 1/x for positive normal x: the hardware estimates refined
+// by two Newton steps each (the estimate's error squares per step), in
+// place of the library forms that also handle zeros, infinities and
+// denormals, which cannot occur here.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
 __device__ __forceinline__ double group_sum(double v) {
   return dpp_sum<0x140>(dpp_sum<0x141>(dpp_sum<0x4E>(dpp_sum<0xB1>(v))));
 }
@@ -225,10 +242,11 @@ __device__ __forceinline__ void bond_update(z2* __restrict__ sites, double* __re
           // The test is relative only: kept rows of small norm must still come
           // out orthonormal to the others, or the right site loses its
           // canonical form.
-          const double iag = rsqrt(g2);
+          const double iag = rsqrt_nr(g2);
           const double tau = 0.5 * (be - al) * iag;
-          const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          const double cs = rsqrt(1.0 + t * t), sn = cs * t;
+          const double u = fma(tau, tau, 1.0);
+          const double t = copysign(rcp_nr(fabs(tau) + u * rsqrt_nr(u)), tau);
+          const double cs = rsqrt_nr(fma(t, t, 1.0)), sn = cs * t;
           const double er = gr * iag, ei = gi * iag;
 #pragma unroll
           for (int k = 0; k < kCols; ++k) {
