@@ -1168,7 +1168,7 @@ static qsv_status adjoint_sweep_tiled(qsv_state* s, const qsv_op* ops, int n_ops
   std::vector<int32_t>& prog = s->ahprog;
   qsv_status bst = build_adjoint_programs<T>(n, ops, n_ops, steps, prog, launches, xops);
   if (bst) return bst;
-  const size_t need = prog.size() * sizeof(int32_t) + 256;
+  const size_t need = prog.size() * sizeof(int32_t) + kProgSlackBytes;
   if (s->apbuf_bytes < need) {
     if (s->apbuf) {
       QSV_HIP(hipStreamSynchronize(s->stream));

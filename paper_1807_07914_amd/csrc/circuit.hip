@@ -1698,7 +1698,7 @@ static qsv_status tuned_shape(qsv_state* s, const std::vector<qsv_op>& xops, int
         if (stp.tile) ok = ok && emit_pass<T>(stp, SP, n, sch->c, RB, prog);
       }
       if (!ok) continue;
-      const size_t need = prog.size() * sizeof(int32_t) + 256;
+      const size_t need = prog.size() * sizeof(int32_t) + kProgSlackBytes;
       if (s->pbuf_bytes < need) {
         QSV_HIP(hipStreamSynchronize(s->stream));
         if (s->pbuf) QSV_HIP(hipFree(s->pbuf));
@@ -1907,7 +1907,7 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
     if (!st.inv.empty()) emit_qperm<T>(st.inv, n, prog);
     if (st.tile && !emit_pass<T>(st, P, n, sch->c, RB, prog)) return fail(QSV_ERR_UNSUPPORTED, "a fused tile pass could not be encoded");
   }
-  const size_t need = prog.size() * sizeof(int32_t) + 256;
+  const size_t need = prog.size() * sizeof(int32_t) + kProgSlackBytes;
   if (s->pbuf_bytes < need) {
     if (s->pbuf) {
       QSV_HIP(hipStreamSynchronize(s->stream));
@@ -2442,7 +2442,7 @@ qsv_status qsv_batch_update(qsv_batch* b, const qsv_op* ops) {
   qsv_status st = b->dt == QSV_C64 ? batch_materialise<float>(b, b->tile_bits, true)
                                    : batch_materialise<double>(b, b->tile_bits, true);
   b->ops = keep;
-  if (!st && (b->passoff.size() != npass || b->hprog.size() > b->prog_cap))
+  if (!st && (b->passoff.size() != npass || (b->hprog.size() + kProgSlackBytes / 4) > b->prog_cap))
     st = fail(QSV_ERR_STATE, "the updated programs do not fit the batch's program buffer");
   if (!st && !b->full) {  // the captured lean kernel cannot run full-body steps
     bool need = false;

@@ -29,6 +29,12 @@ qsv_status hip_fail(hipError_t e, const char* where);
     if (e_ != hipSuccess) return ::qsv::hip_fail(e_, #call); \
   } while (0)
 
+// Bytes a device program buffer holds beyond its last word: the tile
+// kernels' layer loop reads the record after the current one before that
+// record is known to exist, so up to one record (24 words) past the
+// program's end is read.
+constexpr int kProgSlackBytes = 256;
+
 inline int max_qubits(qsv_dtype dt) { return dt == QSV_C128 ? QSV_MAX_QUBITS_C128 : QSV_MAX_QUBITS; }
 
 }  // namespace qsv

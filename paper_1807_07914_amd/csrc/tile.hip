@@ -383,13 +383,22 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
       // A record's table follows it, so that its address does not wait for
       // a word of the record.
       const int32_t* __restrict__ rec = rb + kRoundHeader;
+      int32_t wn[LR];
+#pragma unroll
+      for (int i = 0; i < LR; ++i) wn[i] = rec[i];
       for (int o = 0; o < nlayers; ++o) {
         int32_t w[LR];
 #pragma unroll
-        for (int i = 0; i < LR; ++i) w[i] = rec[i];
+        for (int i = 0; i < LR; ++i) w[i] = wn[i];
         const int flags = w[0];
         const int32_t* __restrict__ tab = rec + LR;
         rec += LR + ((flags & LT_TAB) ? kTableWords : 0);
+        // The next record's words are loaded while this layer runs.  After
+        // the last layer they are the round's aux words, the next block or
+        // the buffer's slack past the program's end (kProgSlackBytes), and
+        // are not used.
+#pragma unroll
+        for (int i = 0; i < LR; ++i) wn[i] = rec[i];
         const int32_t* __restrict__ ap = rb + w[3];  // aux words of the record
         int p = 0;
         if (flags & LT_TAB) table_step<T, RB>(a, tab);
