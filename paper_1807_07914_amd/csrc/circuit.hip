@@ -2065,8 +2065,8 @@ namespace qsv {
 
 template <typename T>
 hipError_t launch_batch(cpx<T>* scratch, const int32_t* progs, const int64_t* passoff,
-                        const int64_t* jobs, const uint64_t* zt, const double* ct, double* out,
-                        int* counter, int njobs, int grid, bool full, hipStream_t st);
+                        const int64_t* jobs, const uint64_t* zt, const uint32_t* zlt, const double* ct,
+                        double* out, int* counter, int njobs, int grid, bool full, hipStream_t st);
 
 }  // namespace qsv
 
@@ -2089,12 +2089,14 @@ struct qsv_batch {
   std::vector<int32_t> hprog;
   std::vector<uint64_t> hz;
   std::vector<double> hc;
+  std::vector<uint32_t> hzl;  // per term: its Z mask over the local bits of the circuit's last pass
   // device buffers
   int32_t* d_prog = nullptr;
   size_t prog_cap = 0;  // words allocated for d_prog (updates may change the size)
   int64_t* d_passoff = nullptr;
   int64_t* d_jobs = nullptr;
   uint64_t* d_z = nullptr;
+  uint32_t* d_zl = nullptr;
   double* d_c = nullptr;
   void* d_scratch = nullptr;
   double* d_out = nullptr;
@@ -2113,7 +2115,7 @@ static void batch_release_device(qsv_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
-  void* ptrs[] = {b->d_prog, b->d_passoff, b->d_jobs, b->d_z, b->d_c, b->d_scratch, b->d_out,
+  void* ptrs[] = {b->d_prog, b->d_passoff, b->d_jobs, b->d_z, b->d_zl, b->d_c, b->d_scratch, b->d_out,
                   b->d_counter};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -2121,6 +2123,7 @@ static void batch_release_device(qsv_batch* b) {
   b->d_passoff = nullptr;
   b->d_jobs = nullptr;
   b->d_z = nullptr;
+  b->d_zl = nullptr;
   b->d_c = nullptr;
   b->d_scratch = nullptr;
   b->d_out = nullptr;
@@ -2133,6 +2136,7 @@ static qsv_status batch_materialise(qsv_batch* b, int t, bool check_only_structu
   const int RB = tile_reg_bits<T>();
   b->hprog.clear();
   b->passoff.clear();
+  b->hzl.assign(b->hz.size(), 0u);
   std::vector<int64_t> first(b->ncirc), npass(b->ncirc);
   std::vector<int> neff(b->ncirc);
   for (int ci = 0; ci < b->ncirc; ++ci) {
@@ -2180,6 +2184,17 @@ static qsv_status batch_materialise(qsv_batch* b, int t, bool check_only_structu
       np = 1;
     }
     npass[ci] = np;
+    // the terms' Z masks over the local bits of the last pass (it reduces)
+    std::vector<int> S0;
+    const std::vector<int>* Sl = &S0;
+    if (!sch->steps.empty()) {
+      Sl = &sch->steps.back().S;
+    } else {
+      for (int q = 0; q < tc; ++q) S0.push_back(q);
+    }
+    for (int64_t k = b->term_off[ci]; k < b->term_off[ci + 1] && (size_t)k < b->hz.size(); ++k)
+      for (size_t j = 0; j < Sl->size(); ++j)
+        if ((b->hz[(size_t)k] >> (*Sl)[j]) & 1ull) b->hzl[(size_t)k] |= 1u << j;
   }
   if (check_only_structure) return QSV_OK;
   // jobs, largest first
@@ -2231,6 +2246,7 @@ static qsv_status batch_build(qsv_batch* b, int t) {
   if ((st = dalloc((void**)&b->d_passoff, b->passoff.size() * 8))) return st;
   if ((st = dalloc((void**)&b->d_jobs, b->job_words.size() * 8))) return st;
   if ((st = dalloc((void**)&b->d_z, b->hz.size() * 8))) return st;
+  if ((st = dalloc((void**)&b->d_zl, b->hzl.size() * 4))) return st;
   if ((st = dalloc((void**)&b->d_c, b->hc.size() * 8))) return st;
   if ((st = dalloc(&b->d_scratch, b->scratch_amps * sizeof(cpx<T>)))) return st;
   if ((st = dalloc((void**)&b->d_out, (size_t)b->ncirc * 8))) return st;
@@ -2240,6 +2256,7 @@ static qsv_status batch_build(qsv_batch* b, int t) {
   QSV_HIP(hipMemcpy(b->d_jobs, b->job_words.data(), b->job_words.size() * 8, hipMemcpyHostToDevice));
   if (!b->hz.empty()) {
     QSV_HIP(hipMemcpy(b->d_z, b->hz.data(), b->hz.size() * 8, hipMemcpyHostToDevice));
+    QSV_HIP(hipMemcpy(b->d_zl, b->hzl.data(), b->hzl.size() * 4, hipMemcpyHostToDevice));
     QSV_HIP(hipMemcpy(b->d_c, b->hc.data(), b->hc.size() * 8, hipMemcpyHostToDevice));
   }
   int dev = 0, cus = 0;
@@ -2252,7 +2269,7 @@ static qsv_status batch_build(qsv_batch* b, int t) {
   for (int64_t off : b->passoff) full = full || program_needs_full<T>(b->hprog.data() + off);
   b->full = full;
   hipError_t e = launch_batch<T>(static_cast<cpx<T>*>(b->d_scratch), b->d_prog, b->d_passoff,
-                                 b->d_jobs, b->d_z, b->d_c, b->d_out, b->d_counter, b->njobs,
+                                 b->d_jobs, b->d_z, b->d_zl, b->d_c, b->d_out, b->d_counter, b->njobs,
                                  b->grid, full, b->stream);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->stream, &g);

@@ -612,9 +612,85 @@ struct TileIO {
   int store;            // write the tile back to the state
   int reduce;           // accumulate the Z-string sum
   const uint64_t* z;    // Z masks of the terms (reduce)
+  const uint32_t* zl;   // the same over the pass's local bits (bit j: qubit S[j])
   const double* coef;   // coefficients (reduce)
   int nt;
 };
+
+// Z-string sum over one tile, sum_x |psi_x|^2 sum_q coef_q (-1)^popc(x & z_q),
+// in FP64, for a pass whose tile is not stored afterwards (its LDS slots are
+// reused).  Thread j owns the local indices l = j + 256 k.  The parity of
+// x & z_q splits into the tile's outside bits (uniform), the bits of j and
+// those of k, so after an in-place Walsh-Hadamard transform of the thread's
+// probabilities over k, H[m] = sum_k P[k] (-1)^popc(k & m), every term costs
+// one LDS read: coef_q * (+-1) * H[(local mask of z_q) >> 8].  Returns the
+// thread's partial.
+template <typename T, int TBMAX>
+__device__ __forceinline__ double tile_zsum(cpx<T>* __restrict__ tile, int t, uint64_t base, const TileIO& io) {
+  constexpr int SB = SwzBits<T>::B;
+  constexpr int KMAX = (1 << TBMAX) / kTileThreads;  // slots per thread: 32 (c64), 16 (c128)
+  constexpr int KL = 8;                               // transform bits done in registers at once
+  static_assert(KMAX % KL == 0, "whole register blocks per thread");
+  const uint32_t j = threadIdx.x;
+  const int kn = t > 8 ? 1 << (t - 8) : 1;  // amplitudes per thread
+  if (j >= (1u << t)) return 0.0;          // tiles under 256 amplitudes
+  auto slot = [&](int k) -> double* {
+    return reinterpret_cast<double*>(&tile[tile_swizzle(j + (uint32_t)k * kTileThreads, SB)]);
+  };
+  // the transform over the low 3 bits of k, from the amplitudes (slots past
+  // kn hold zeros, so the full-size transform gives H[m] for m < kn) ...
+#pragma unroll 1
+  for (int kh = 0; kh < KMAX / KL; ++kh) {
+    double h[KL];
+#pragma unroll
+    for (int e = 0; e < KL; ++e) {
+      const int k = kh * KL + e;
+      h[e] = 0.0;
+      if (k < kn) {
+        const cpx<T> x = tile[tile_swizzle(j + (uint32_t)k * kTileThreads, SB)];
+        h[e] = fma((double)x.x, (double)x.x, (double)x.y * (double)x.y);
+      }
+    }
+#pragma unroll
+    for (int b = 1; b < KL; b <<= 1)
+#pragma unroll
+      for (int e = 0; e < KL; ++e)
+        if (!(e & b)) {
+          const double u = h[e], v = h[e | b];
+          h[e] = u + v;
+          h[e | b] = u - v;
+        }
+#pragma unroll
+    for (int e = 0; e < KL; ++e) *slot(kh * KL + e) = h[e];
+  }
+  // ... then over the high bits, column by column
+  if constexpr (KMAX > KL) {
+#pragma unroll 1
+    for (int e = 0; e < KL; ++e) {
+      double h[KMAX / KL];
+#pragma unroll
+      for (int kh = 0; kh < KMAX / KL; ++kh) h[kh] = *slot(kh * KL + e);
+#pragma unroll
+      for (int b = 1; b < KMAX / KL; b <<= 1)
+#pragma unroll
+        for (int kh = 0; kh < KMAX / KL; ++kh)
+          if (!(kh & b)) {
+            const double u = h[kh], v = h[kh | b];
+            h[kh] = u + v;
+            h[kh | b] = u - v;
+          }
+#pragma unroll
+      for (int kh = 0; kh < KMAX / KL; ++kh) *slot(kh * KL + e) = h[kh];
+    }
+  }
+  double acc = 0.0;
+  for (int q = 0; q < io.nt; ++q) {
+    const uint32_t zl = io.zl[q];
+    const int par = (__popcll(base & io.z[q]) + __popc(j & zl & 255u)) & 1;
+    acc = fma(par ? -io.coef[q] : io.coef[q], *slot((int)(zl >> 8)), acc);
+  }
+  return acc;
+}
 
 // One fused tile pass over tile `tid` of the pass program `prog`; returns the
 // thread's partial of the Z-string sum (0 unless io.reduce).  Ends with a
@@ -683,16 +759,7 @@ __device__ __forceinline__ double tile_body(const cpx<T>* src, cpx<T>* dst, cons
 
   // ---- Z-string sum over the tile (FP64)
   double acc = 0.0;
-  if (io.reduce) {
-    for (int l = threadIdx.x; l < (1 << t); l += kTileThreads) {
-      const uint64_t g = base | segoff[(uint32_t)l >> c] | ((uint32_t)l & cmask);
-      const cpx<T> x = tile[tile_swizzle((uint32_t)l, SB)];
-      const double pr = fma((double)x.x, (double)x.x, (double)x.y * (double)x.y);
-      double f = 0.0;
-      for (int q = 0; q < io.nt; ++q) f += (__popcll(g & io.z[q]) & 1) ? -io.coef[q] : io.coef[q];
-      acc = fma(pr, f, acc);
-    }
-  }
+  if (io.reduce) acc = tile_zsum<T, TBMAX>(tile, t, base, io);  // no store follows a reduce
 
   // ---- store the tile back
   if (io.store) {
@@ -720,7 +787,7 @@ __device__ __forceinline__ double tile_body(const cpx<T>* src, cpx<T>* dst, cons
 template <typename T, int TBMAX, int RB, int BODY, int MINWG>
 __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile(const cpx<T>* src, cpx<T>* dst,
                                                               const int32_t* __restrict__ prog) {
-  const TileIO io{0, 1, 0, nullptr, nullptr, 0};
+  const TileIO io{0, 1, 0, nullptr, nullptr, nullptr, 0};
   (void)tile_body<T, TBMAX, RB, BODY>(src, dst, prog, blockIdx.x, io);
 }
 
@@ -1048,16 +1115,7 @@ __device__ __forceinline__ double batch_pass(cpx<T>* __restrict__ psi, const int
       }
     }
     run_rounds<T, TBMAX, RB, kBodyLean>(reinterpret_cast<char*>(tile), prog, t, nns, base, ltab);
-    if (io.reduce) {
-      for (int l = threadIdx.x; l < (1 << t); l += kTileThreads) {
-        const uint64_t g = base | segoff[(uint32_t)l >> c] | ((uint32_t)l & cmask);
-        const cpx<T> x = tile[tile_swizzle((uint32_t)l, SB)];
-        const double pr = fma((double)x.x, (double)x.x, (double)x.y * (double)x.y);
-        double f = 0.0;
-        for (int q = 0; q < io.nt; ++q) f += (__popcll(g & io.z[q]) & 1) ? -io.coef[q] : io.coef[q];
-        acc = fma(pr, f, acc);
-      }
-    }
+    if (io.reduce) acc += tile_zsum<T, TBMAX>(tile, t, base, io);  // no store follows a reduce
     if (io.store) {
 #pragma unroll
       for (int k = 0; k < VPT; ++k) {
@@ -1094,6 +1152,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_batch(cpx<T>* __restrict__ 
                                                          const int64_t* __restrict__ passoff,
                                                          const int64_t* __restrict__ jobs,
                                                          const uint64_t* __restrict__ zt,
+                                                         const uint32_t* __restrict__ zlt,
                                                          const double* __restrict__ ct,
                                                          double* __restrict__ out,
                                                          int* __restrict__ counter, int njobs) {
@@ -1117,7 +1176,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_batch(cpx<T>* __restrict__ 
       const int32_t* prog = progs + passoff[p0 + p];
       const int t = prog[0];
       const uint64_t ntiles = 1ull << (w - t);
-      const TileIO io{p == 0, p + 1 < np, p + 1 == np, zt + t0, ct + t0, (int)nt};
+      const TileIO io{p == 0, p + 1 < np, p + 1 == np, zt + t0, zlt + t0, ct + t0, (int)nt};
       if constexpr (FULL) {
         for (uint64_t tid = 0; tid < ntiles; ++tid)
           acc += tile_body<T, TBMAX, RB, kBodyFull>(scratch + soff, scratch + soff, prog, tid, io);
@@ -1268,23 +1327,23 @@ template hipError_t launch_qperm<double>(const cpx<double>*, cpx<double>*, int, 
 
 template <typename T>
 hipError_t launch_batch(cpx<T>* scratch, const int32_t* progs, const int64_t* passoff,
-                        const int64_t* jobs, const uint64_t* zt, const double* ct, double* out,
-                        int* counter, int njobs, int grid, bool full, hipStream_t st) {
+                        const int64_t* jobs, const uint64_t* zt, const uint32_t* zlt, const double* ct,
+                        double* out, int* counter, int njobs, int grid, bool full, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
   if (full)
     hipLaunchKernelGGL((k_batch<T, TileCfg<T>::TBMAX, TileCfg<T>::RB, true>), dim3(grid), dim3(kTileThreads),
-                       0, st, scratch, progs, passoff, jobs, zt, ct, out, counter, njobs);
+                       0, st, scratch, progs, passoff, jobs, zt, zlt, ct, out, counter, njobs);
   else  // every program of the batch uses only the lean steps
     hipLaunchKernelGGL((k_batch<T, TileCfg<T>::TBMAX, TileCfg<T>::RB, false>), dim3(grid), dim3(kTileThreads),
-                       0, st, scratch, progs, passoff, jobs, zt, ct, out, counter, njobs);
+                       0, st, scratch, progs, passoff, jobs, zt, zlt, ct, out, counter, njobs);
   return hipGetLastError();
 }
 template hipError_t launch_batch<float>(cpx<float>*, const int32_t*, const int64_t*, const int64_t*,
-                                        const uint64_t*, const double*, double*, int*, int, int, bool,
-                                        hipStream_t);
+                                        const uint64_t*, const uint32_t*, const double*, double*, int*, int,
+                                        int, bool, hipStream_t);
 template hipError_t launch_batch<double>(cpx<double>*, const int32_t*, const int64_t*,
-                                         const int64_t*, const uint64_t*, const double*, double*,
-                                         int*, int, int, bool, hipStream_t);
+                                         const int64_t*, const uint64_t*, const uint32_t*, const double*,
+                                         double*, int*, int, int, bool, hipStream_t);
 
 template int tile_max_bits<float>();
 template int tile_max_bits<double>();
