@@ -277,8 +277,12 @@ qsv_status qsv_batch_create(qsv_dtype dtype, int n_circuits, const int32_t* widt
  * (the same gates on the same qubits; an angle of 0 is a structure like any
  * other angle).  ops: host array of all circuits' ops, read during the call.
  * Paper section V.B: the optimiser's next point of the parameter sweep.
- * Errors: QSV_ERR_ARG (a different structure), QSV_ERR_STATE (freed handle,
- * or matrices that would need a tile body the captured launch lacks). */
+ * When the new programs outgrow the device program buffer or need the full
+ * tile body, the buffer grows and the launch is captured again (the only
+ * case in which an update allocates).
+ * Errors: QSV_ERR_ARG (a different structure), QSV_ERR_STATE (freed handle),
+ * QSV_ERR_OOM / QSV_ERR_HIP (the buffer could not grow: the batch then
+ * refuses runs). */
 qsv_status qsv_batch_update(qsv_batch* b, const qsv_op* ops);
 /* Launch the captured graph; energies (host, n_circuits doubles, may be
  * NULL) on return.  Paper section V.B: one energy per point of the sweep.

@@ -55,7 +55,7 @@ using cd = std::complex<double>;
 qsv_status apply_fused_block(qsv_state* s, const qsv_op& o) { return apply_op_pergate(s, o, 0); }
 
 // ------------------------------------------------------------ op classes
-enum PKind { PK_U1 = 0, PK_U2 = 1, PK_D1 = 2, PK_D2 = 3, PK_OTHER = 4, PK_NOOP = 5 };
+enum PKind { PK_U1 = 0, PK_U2 = 1, PK_D1 = 2, PK_D2 = 3, PK_OTHER = 4, PK_NOOP = 5, PK_CX = 6 };
 
 struct POp {
   int kind = PK_OTHER;
@@ -64,18 +64,17 @@ struct POp {
   bool sign = false;  // Z (D1) or CZ (D2): a pure sign pattern
   cd m[16];           // U1: 2x2, U2: 4x4 (listed order), D1: d0,d1, D2: d[4]
   uint64_t qmask = 0;
-  bool nondiag() const { return kind == PK_U1 || kind == PK_U2 || kind == PK_OTHER; }
+  bool nondiag() const { return kind == PK_U1 || kind == PK_U2 || kind == PK_OTHER || kind == PK_CX; }
 };
 
 static bool is_zero(cd z) { return z.real() == 0.0 && z.imag() == 0.0; }
 static bool is_one(cd z) { return z.real() == 1.0 && z.imag() == 0.0; }
 static bool is_mone(cd z) { return z.real() == -1.0 && z.imag() == 0.0; }
 
-// Tile passes take CNOT(c, t) as H_t CZ(c, t) H_t: the Hadamards become
-// rotations (merged with the target's neighbouring one-qubit gates) and the
-// CZ a sign step, all in the lean tile body, where the permutation step a
-// CNOT needs otherwise exists only in the full body (more registers, slower
-// per layer).  Other ops are kept as they are.
+// CNOT(c, t) as H_t CZ(c, t) H_t: the Hadamards become rotations (merged
+// with the target's neighbouring one-qubit gates) and the CZ a sign step.
+// The adjoint sweep plans CNOTs this way; the forward tile passes apply them
+// as store maps instead (classify_tile).  Other ops are kept as they are.
 void expand_cnots(const qsv_op* ops, int n_ops, std::vector<qsv_op>& out, std::vector<int>* origin) {
   out.clear();
   out.reserve((size_t)n_ops);
@@ -174,6 +173,22 @@ static POp classify(const qsv_op& o) {
   return p;
 }
 
+// The class of an op in a forward tile-pass plan: a CNOT is a permutation
+// of basis states, x_t ^= x_c.  The CNOTs that end a round (target in the
+// tile, control anywhere) compose into one affine map of the tile's local
+// index, which the round's store applies by writing each amplitude to the
+// slot of its image: no arithmetic, and a ladder of CNOTs takes no layers.
+static POp classify_tile(const qsv_op& o) {
+  if (o.gate != QSV_CNOT) return classify(o);
+  POp p;
+  p.kind = PK_CX;
+  p.nq = 2;
+  p.q[0] = o.q[0];  // control
+  p.q[1] = o.q[1];  // target
+  p.qmask = (1ull << o.q[0]) | (1ull << o.q[1]);
+  return p;
+}
+
 // kinds of the planner's per-round work items
 enum WorkType { TOP_U1 = 1, TOP_U2, TOP_SIGN, TOP_PHASE1, TOP_DIAG2, TOP_PERM2, TOP_GIVENS };
 
@@ -197,21 +212,27 @@ struct Schedule {
   bool relabeled = false;     // the steps apply the op list with its SWAPs relabeled away
 };
 
-// Dependency scan: the ops a pass over tile set S can apply, in program
-// order.  Returns the weighted count of non-diagonal ops taken.
+// Dependency scan: the ops a pass over tile set S (or a round over register
+// set S) can apply, in program order.  A CNOT needs its target in Tmask (the
+// tile).  In a round (round = true) a CNOT runs at the round's store, after
+// everything else, so later ops on its qubits other than CNOTs wait for the
+// next round.  Returns the weighted count of non-diagonal ops taken.
 static int scan(const std::vector<POp>& P, const std::vector<int>& pending, uint64_t Smask,
-                uint64_t allq, std::vector<int>* take) {
-  uint64_t bnd = 0, bd = 0;
+                uint64_t allq, std::vector<int>* take, uint64_t Tmask, bool round) {
+  uint64_t bnd = 0, bd = 0, pm = 0;
   int score = 0;
   for (int i : pending) {
     const POp& o = P[i];
     const bool nd = o.nondiag();
-    const bool blocked = (o.qmask & bnd) || (nd && (o.qmask & bd));
+    const bool cx = o.kind == PK_CX;
+    const bool blocked = (o.qmask & bnd) || (nd && (o.qmask & bd)) || (!cx && (o.qmask & pm));
     if (!blocked) {
-      const bool exe = !nd || ((o.kind == PK_U1 || o.kind == PK_U2) && (o.qmask & ~Smask) == 0);
+      const bool exe = !nd || ((o.kind == PK_U1 || o.kind == PK_U2) && (o.qmask & ~Smask) == 0) ||
+                       (cx && ((Tmask >> o.q[1]) & 1ull));
       if (exe) {
         if (take) take->push_back(i);
         if (nd) score += o.nq;
+        if (cx && round) pm |= o.qmask;
         continue;
       }
     }
@@ -255,6 +276,9 @@ static std::shared_ptr<Schedule> build_schedule(const std::vector<POp>& P, int n
         if (P[i].kind == PK_U1 || P[i].kind == PK_U2) {
           Smask |= P[i].qmask;
           break;
+        } else if (P[i].kind == PK_CX) {
+          Smask |= 1ull << P[i].q[1];
+          break;
         } else if (P[i].kind == PK_OTHER) {
           break;
         }
@@ -269,7 +293,7 @@ static std::shared_ptr<Schedule> build_schedule(const std::vector<POp>& P, int n
         int best = -1, bs = -1, bpos = 1 << 30;
         for (int q = 0; q < n; ++q) {
           if ((Smask >> q) & 1) continue;
-          const int sc = scan(P, pending, Smask | (1ull << q), allq, nullptr);
+          const int sc = scan(P, pending, Smask | (1ull << q), allq, nullptr, Smask | (1ull << q), false);
           if (sc > bs || (sc == bs && firstpos[q] < bpos)) {
             best = q;
             bs = sc;
@@ -280,7 +304,7 @@ static std::shared_ptr<Schedule> build_schedule(const std::vector<POp>& P, int n
       }
     }
     std::vector<int> take;
-    scan(P, pending, Smask, allq, &take);
+    scan(P, pending, Smask, allq, &take, Smask, false);
     if (take.empty()) {  // cannot happen: the first queued op is executable
       Step st;
       st.tile = false;
@@ -305,12 +329,18 @@ static std::shared_ptr<Schedule> build_schedule(const std::vector<POp>& P, int n
       std::vector<int> rem(take);
       while (!rem.empty()) {
         uint64_t Rg = 0;  // register qubits (global mask)
+        bool gates = false;
         for (int i : rem)
-          if (P[i].nondiag()) {
+          if (P[i].kind == PK_U1 || P[i].kind == PK_U2) {
             Rg = P[i].qmask;
+            gates = true;
+            break;
+          } else if (P[i].kind == PK_OTHER) {
             break;
           }
-        if (Rg == 0) {  // only diagonal ops left: one round takes them all
+        bool cxs = false;
+        for (int i : rem) cxs = cxs || P[i].kind == PK_CX;
+        if (!gates && !cxs) {  // only diagonal ops left: one round takes them all
           Round cur;
           for (int k = 0; k < 8; ++k) cur.R[k] = -1;
           cur.ops = rem;
@@ -322,7 +352,7 @@ static std::shared_ptr<Schedule> build_schedule(const std::vector<POp>& P, int n
           int best = -1, bs = -1;
           for (int q : st.S) {
             if ((Rg >> q) & 1) continue;
-            const int sc = scan(P, rem, Rg | (1ull << q), allq, nullptr);
+            const int sc = scan(P, rem, Rg | (1ull << q), allq, nullptr, Smask, true);
             if (sc > bs) {
               best = q;
               bs = sc;
@@ -331,7 +361,7 @@ static std::shared_ptr<Schedule> build_schedule(const std::vector<POp>& P, int n
           Rg |= 1ull << best;
         }
         Round cur;
-        scan(P, rem, Rg, allq, &cur.ops);
+        scan(P, rem, Rg, allq, &cur.ops, Smask, true);
         int k = 0;
         for (int j = 0; j < (int)st.S.size() && k < 8; ++j)
           if ((Rg >> st.S[j]) & 1) cur.R[k++] = j;
@@ -457,13 +487,13 @@ static std::vector<std::vector<int>> involution_passes(const std::vector<int>& s
 static std::shared_ptr<Schedule> plan_schedule(const std::vector<qsv_op>& xops, int n, int t, bool f32, int RB,
                                                int force_c = 0) {
   std::vector<POp> P(xops.size());
-  for (size_t i = 0; i < xops.size(); ++i) P[i] = classify(xops[i]);
+  for (size_t i = 0; i < xops.size(); ++i) P[i] = classify_tile(xops[i]);
   auto sch = plan_tile_passes(P, n, t, f32, RB, force_c);
   std::vector<qsv_op> rops;
   std::vector<int> lab;
   if (!relabel_swaps(xops, n, rops, lab)) return sch;
   std::vector<POp> R(rops.size());
-  for (size_t i = 0; i < rops.size(); ++i) R[i] = classify(rops[i]);
+  for (size_t i = 0; i < rops.size(); ++i) R[i] = classify_tile(rops[i]);
   auto alt = plan_tile_passes(R, n, t, f32, RB, force_c);
   const std::vector<std::vector<int>> inv = involution_passes(lab);
   if (alt->passes + (int)inv.size() >= sch->passes) return sch;
@@ -737,6 +767,7 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
     std::vector<NdItem> nd;
     std::vector<DGroup> g;  // g[i] runs before nd[i], g.back() after the last one
     int last[8];            // first group after the last non-diagonal op on register bit j
+    std::vector<int> cx;    // CNOTs applied by the round's store, in program order
   };
   std::vector<RPlan> plans;
 
@@ -929,6 +960,12 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
     for (int b = 0; b < 64; ++b) last_u1[b] = -1;
     for (int i : r.ops) {
       const POp& o = P[i];
+      if (o.kind == PK_CX) {  // to the store map; nothing later in the round touches its qubits
+        rp.cx.push_back(i);
+        for (int j = 0; j < 2; ++j)
+          if (lpos[o.q[j]] >= 0) last_u1[lpos[o.q[j]]] = -1;
+        continue;
+      }
       if (o.kind == PK_U1) {
         const int p = lpos[o.q[0]];
         if (last_u1[p] >= 0) {  // U <- U_new * U_old
@@ -1134,6 +1171,21 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
           else cz(o.q[0], o.q[1]);
         }
       }
+    }
+    // A CNOT target's carried factor does not commute with the store map:
+    // it is applied in this round.  A control's commutes and stays carried.
+    for (int i : rp.cx) {
+      const int p = lpos[P[i].q[1]];
+      if (pd0[p] == cd(1.0) && pd1[p] == cd(1.0)) continue;
+      const int j = regof[p];
+      if (j >= 0) {
+        tab_bit(rp, j, pd0[p], pd1[p]);
+      } else {
+        gscale *= pd0[p];
+        const cd rr = pd1[p] / pd0[p];
+        if (rr != cd(1.0)) add_term(pick(rp, 0, [&](const DGroup& g) { return has_key(g, -1); }), -1, 1u << p, 0ull, rr);
+      }
+      pd0[p] = pd1[p] = 1.0;
     }
   }
 
@@ -1490,7 +1542,47 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
       hdr[2 + k] = (int32_t)(tile_swizzle(1u << rp.R[k], SB) * (uint32_t)(2 * sizeof(T)));
       hdr[kHdrStore + k] = hdr[2 + k];
     }
-    if (!recs.empty() && (recs.back().flags & LT_PERM2)) {
+    // The store map of the round's CNOTs: local index x of a tile with
+    // outside bits o goes to A x + B o.  Row r of A (B) says which local
+    // (outside) bits local bit r of the image is the XOR of; CNOT(c, q)
+    // adds row c to row q (or outside bit c, for a control outside the tile).
+    std::vector<int32_t> mapw;
+    if (!rp.cx.empty()) {
+      std::vector<uint32_t> rowA(t);
+      std::vector<uint64_t> rowB(t, 0);
+      for (int p = 0; p < t; ++p) rowA[p] = 1u << p;
+      for (int i : rp.cx) {
+        const int pc = lpos[P[i].q[0]], pt = lpos[P[i].q[1]];
+        if (pc >= 0) {
+          rowA[pt] ^= rowA[pc];
+          rowB[pt] ^= rowB[pc];
+        } else {
+          rowB[pt] ^= 1ull << P[i].q[0];
+        }
+      }
+      auto col_ofs = [&](auto bitof) {  // swizzled LDS offset of a column
+        uint32_t v = 0;
+        for (int r = 0; r < t; ++r)
+          if (bitof(r)) v |= 1u << r;
+        return (int32_t)(tile_swizzle(v, SB) * (uint32_t)(2 * sizeof(T)));
+      };
+      for (int k = 0; k < RB; ++k) {
+        const int b = rp.R[k];
+        hdr[kHdrStore + k] = col_ofs([&](int r) { return (rowA[r] >> b) & 1u; });
+      }
+      const uint32_t fm = tmask & ~rmask;
+      for (int b = 0; b < t; ++b)
+        if ((fm >> b) & 1u) mapw.push_back(col_ofs([&](int r) { return (rowA[r] >> b) & 1u; }));
+      uint64_t outs = 0;
+      for (int r = 0; r < t; ++r) outs |= rowB[r];
+      mapw.push_back(__builtin_popcountll(outs));
+      for (int q = 0; q < 64; ++q)
+        if ((outs >> q) & 1ull) {
+          mapw.push_back(q);
+          mapw.push_back(col_ofs([&](int r) { return (rowB[r] >> q) & 1ull; }));
+        }
+    }
+    if (rp.cx.empty() && !recs.empty() && (recs.back().flags & LT_PERM2)) {
       Rec& lr = recs.back();
       const size_t na = lr.aux.size();
       const int j0 = lr.aux[na - 3], j1 = lr.aux[na - 2], code = lr.aux[na - 1];
@@ -1529,6 +1621,10 @@ static bool emit_pass(const Step& st, const std::vector<POp>& P, int n, int c, i
       if (recs[i].aux.empty()) continue;
       prog[at[i] + 3] = (int32_t)(prog.size() - b0);
       prog.insert(prog.end(), recs[i].aux.begin(), recs[i].aux.end());
+    }
+    if (!mapw.empty()) {
+      prog[b0 + kHdrMap] = (int32_t)(prog.size() - b0);
+      prog.insert(prog.end(), mapw.begin(), mapw.end());
     }
     while ((prog.size() - b0) % 16) prog.push_back(0);
   }
@@ -1654,7 +1750,7 @@ static qsv_status tuned_shape(qsv_state* s, const std::vector<qsv_op>& xops, int
   const int n = s->n;
   const bool f32 = sizeof(T) == 4;
   std::vector<POp> P(xops.size());
-  for (size_t i = 0; i < xops.size(); ++i) P[i] = classify(xops[i]);
+  for (size_t i = 0; i < xops.size(); ++i) P[i] = classify_tile(xops[i]);
   const uint64_t h = mix(key_hash(structure_key(P, n, 0, f32 ? -1 : -2, RB)), 0x53494e474c45ull);  // "SINGLE"
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1688,7 +1784,7 @@ static qsv_status tuned_shape(qsv_state* s, const std::vector<qsv_op>& xops, int
       std::vector<qsv_op> rbuf;
       const std::vector<qsv_op>& sops = step_ops(*sch, xops, n, rbuf);
       std::vector<POp> SP(sops.size());
-      for (size_t i = 0; i < sops.size(); ++i) SP[i] = classify(sops[i]);
+      for (size_t i = 0; i < sops.size(); ++i) SP[i] = classify_tile(sops[i]);
       prog.clear();
       std::vector<size_t> offs;
       bool ok = true;
@@ -1856,8 +1952,7 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
     }
     return QSV_OK;
   }
-  std::vector<qsv_op> xops;  // the list the plan and its per-gate steps refer to
-  expand_cnots(ops, n_ops, xops);
+  std::vector<qsv_op> xops(ops, ops + n_ops);  // the list the plan and its per-gate steps refer to
   ops = xops.data();
   n_ops = (int)xops.size();
   int t = opts.tile_qubits > 0 ? opts.tile_qubits : default_tile_bits<T>();
@@ -1873,7 +1968,7 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
     if (st) return st;
   }
   std::vector<POp> P(n_ops);
-  for (int i = 0; i < n_ops; ++i) P[i] = classify(ops[i]);
+  for (int i = 0; i < n_ops; ++i) P[i] = classify_tile(ops[i]);
   // the key carries the dtype in place of the segment width when the
   // planner chooses it (the cached schedule holds the width it chose)
   std::vector<uint32_t> key = structure_key(P, n, t, force_c ? force_c : (sizeof(T) == 4 ? -1 : -2), RB);
@@ -1896,7 +1991,7 @@ static qsv_status run_fused_T(qsv_state* s, const qsv_op* ops, int n_ops, const 
   const std::vector<qsv_op>& sops = step_ops(*sch, xops, n, rbuf);
   if (sch->relabeled) {
     P.resize(sops.size());
-    for (size_t i = 0; i < sops.size(); ++i) P[i] = classify(sops[i]);
+    for (size_t i = 0; i < sops.size(); ++i) P[i] = classify_tile(sops[i]);
   }
   // materialise programs for all tile and permutation steps
   std::vector<int32_t>& prog = s->hprog;
@@ -2005,13 +2100,14 @@ qsv_status plan_program(const qsv_state* s, const qsv_op* ops, int n_ops, int ti
   const int n = s->n;
   if (n < RB) return fail(QSV_ERR_UNSUPPORTED, "register smaller than the register group");
   if (t > n) t = n;
-  std::vector<qsv_op> xops;  // per-gate steps index this list (CNOTs expanded; SWAPs relabeled
-  expand_cnots(ops, n_ops, xops);  // away when the plan ends in qubit-permutation passes)
+  // per-gate steps index this list (SWAPs relabeled away when the plan ends
+  // in qubit-permutation passes)
+  std::vector<qsv_op> xops(ops, ops + n_ops);
   auto sch = plan_schedule(xops, n, t, f, RB);
   std::vector<qsv_op> rbuf;
   const std::vector<qsv_op>& sops = step_ops(*sch, xops, n, rbuf);
   std::vector<POp> P(sops.size());
-  for (size_t i = 0; i < sops.size(); ++i) P[i] = classify(sops[i]);
+  for (size_t i = 0; i < sops.size(); ++i) P[i] = classify_tile(sops[i]);
   const int c = sch->c;
   prog.clear();
   steps.clear();
@@ -2045,8 +2141,7 @@ qsv_status plan_passes(const qsv_state* s, const qsv_op* ops, int n_ops, int til
   if (t > TBMAX || t < RB) return fail(QSV_ERR_ARG, "bad tile_qubits");
   const int n = s->n;
   if (t > n) t = n;
-  std::vector<qsv_op> xops;
-  expand_cnots(ops, n_ops, xops);
+  std::vector<qsv_op> xops(ops, ops + n_ops);
   auto sch = plan_schedule(xops, n, t, f, RB);
   int fb = 0;
   for (const Step& st : sch->steps) fb += (st.tile || !st.inv.empty()) ? 0 : 1;
@@ -2146,10 +2241,9 @@ static qsv_status batch_materialise(qsv_batch* b, int t, bool check_only_structu
     int c = sizeof(T) == 4 ? 5 : 4;
     if (c > tc) c = tc;
     const int o0 = b->op_off[ci], o1 = b->op_off[ci + 1];
-    std::vector<qsv_op> xops;  // CNOTs as H CZ H, as in the single-state passes
-    expand_cnots(b->ops.data() + o0, o1 - o0, xops);
+    std::vector<qsv_op> xops(b->ops.data() + o0, b->ops.data() + o1);
     std::vector<POp> P(xops.size());
-    for (size_t i = 0; i < xops.size(); ++i) P[i] = classify(xops[i]);
+    for (size_t i = 0; i < xops.size(); ++i) P[i] = classify_tile(xops[i]);
     std::vector<uint32_t> key = structure_key(P, n, tc, c, RB);
     const uint64_t h = key_hash(key);
     std::shared_ptr<Schedule> sch;
@@ -2226,6 +2320,9 @@ static qsv_status batch_materialise(qsv_batch* b, int t, bool check_only_structu
 }
 
 template <typename T>
+static qsv_status batch_capture(qsv_batch* b);
+
+template <typename T>
 static qsv_status batch_build(qsv_batch* b, int t) {
   batch_release_device(b);
   qsv_status st = batch_materialise<T>(b, t, false);
@@ -2263,7 +2360,17 @@ static qsv_status batch_build(qsv_batch* b, int t) {
   QSV_HIP(hipGetDevice(&dev));
   QSV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   b->grid = std::max(1, std::min(b->njobs, 2 * cus));  // two 64 KiB-LDS workgroups per CU
-  // capture reset + persistent kernel once; runs replay the graph
+  return batch_capture<T>(b);
+}
+
+// Captures the counter reset and the persistent kernel (lean, or full when a
+// program needs it) into the batch's graph; runs replay it.
+template <typename T>
+static qsv_status batch_capture(qsv_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
   QSV_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   bool full = false;  // the lean kernel unless some pass needs the full tile body
   for (int64_t off : b->passoff) full = full || program_needs_full<T>(b->hprog.data() + off);
@@ -2459,31 +2566,51 @@ qsv_status qsv_batch_update(qsv_batch* b, const qsv_op* ops) {
   qsv_status st = b->dt == QSV_C64 ? batch_materialise<float>(b, b->tile_bits, true)
                                    : batch_materialise<double>(b, b->tile_bits, true);
   b->ops = keep;
-  if (!st && (b->passoff.size() != npass || (b->hprog.size() + kProgSlackBytes / 4) > b->prog_cap))
-    st = fail(QSV_ERR_STATE, "the updated programs do not fit the batch's program buffer");
-  if (!st && !b->full) {  // the captured lean kernel cannot run full-body steps
-    bool need = false;
-    for (int64_t off : b->passoff)
-      need = need || (b->dt == QSV_C64 ? program_needs_full<float>(b->hprog.data() + off)
-                                       : program_needs_full<double>(b->hprog.data() + off));
-    if (need)
-      st = fail(QSV_ERR_STATE,
-                "the updated matrices need the full tile body, which the captured launch lacks; "
-                "create a new batch");
-  }
+  if (!st && b->passoff.size() != npass)
+    st = fail(QSV_ERR_STATE, "the updated programs changed the batch's pass structure");
   if (st) {  // the batch keeps its previous programs
     b->hprog.swap(keep_prog);
     b->passoff.swap(keep_off);
     return st;
   }
+  // Angles change which tables and phases are identities, so the programs
+  // can outgrow the buffer (a batch built at angle 0 is nearly empty), and
+  // new matrices can need the full tile body: then the buffer grows and the
+  // launch is captured again.
+  bool need_full = false;
+  for (int64_t off : b->passoff)
+    need_full = need_full || (b->dt == QSV_C64 ? program_needs_full<float>(b->hprog.data() + off)
+                                               : program_needs_full<double>(b->hprog.data() + off));
+  const bool grow = b->hprog.size() + kProgSlackBytes / 4 > b->prog_cap;
+  QSV_HIP(hipStreamSynchronize(b->stream));
+  if (grow) {
+    QSV_HIP(hipFree(b->d_prog));
+    b->d_prog = nullptr;
+    b->prog_cap = b->hprog.size() * 2 + 4096;
+    hipError_t e = hipMalloc((void**)&b->d_prog, b->prog_cap * 4);
+    if (e != hipSuccess) {
+      b->d_prog = nullptr;
+      b->prog_cap = 0;
+      if (b->exec) (void)hipGraphExecDestroy(b->exec);
+      if (b->graph) (void)hipGraphDestroy(b->graph);
+      b->exec = nullptr;
+      b->graph = nullptr;
+      return hip_fail(e, "hipMalloc(batch programs)");
+    }
+  }
   QSV_HIP(hipMemcpyAsync(b->d_prog, b->hprog.data(), b->hprog.size() * 4, hipMemcpyHostToDevice, b->stream));
   QSV_HIP(hipMemcpyAsync(b->d_passoff, b->passoff.data(), npass * 8, hipMemcpyHostToDevice, b->stream));
   QSV_HIP(hipStreamSynchronize(b->stream));
+  if (grow || (need_full && !b->full)) {
+    qsv_status cs = b->dt == QSV_C64 ? batch_capture<float>(b) : batch_capture<double>(b);
+    if (cs) return cs;
+  }
   return QSV_OK;
 }
 
 qsv_status qsv_batch_run(qsv_batch* b, double* energies) {
   if (!batch_live(b)) return fail(QSV_ERR_STATE, "invalid or freed batch handle");
+  if (!b->exec) return fail(QSV_ERR_STATE, "the batch lost its launch in a failed update; create a new batch");
   QSV_HIP(hipGraphLaunch(b->exec, b->stream));
   if (energies)
     QSV_HIP(hipMemcpyAsync(energies, b->d_out, (size_t)b->ncirc * 8, hipMemcpyDeviceToHost,

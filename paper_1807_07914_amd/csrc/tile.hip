@@ -360,7 +360,13 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
     uint32_t bofs[RB];
 #pragma unroll
     for (int j = 0; j < RB; ++j) bofs[j] = (uint32_t)rb[2 + j];
-    for (int gi = threadIdx.x; gi < ng; gi += kTileThreads) {
+    // A store map moves amplitudes between register groups, so every
+    // group's load comes before any store.
+    const int moff = rb[kHdrMap];
+    static_assert((1 << (TBMAX - RB)) <= kTileThreads, "at most one register group per thread");
+    const int gi = threadIdx.x;
+    cpx<T> a[NR];
+    if (gi < ng) {
       // deposit gi into the free local bits
       uint32_t lg = 0, fm = free_mask;
       for (int bit = 0; fm; ++bit) {
@@ -369,7 +375,6 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
         fm ^= low;
       }
       const uint32_t sgb = tile_swizzle(lg, SB) * (uint32_t)sizeof(cpx<T>);
-      cpx<T> a[NR];
       {
         uint32_t ad = sgb;
 #pragma unroll
@@ -582,21 +587,44 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
           dispatch_u1<T, RB>(a, j, U);
         }
       }
-      {
-        // recomputed rather than kept from the load walk: 2^RB live
-        // addresses would cost as many registers
-        // the store's offsets (the header's; a permutation that ends the
-        // round is folded into them)
-        uint32_t sofs[RB];
-#pragma unroll
-        for (int j = 0; j < RB; ++j) sofs[j] = (uint32_t)rb[kHdrStore + j];
-        uint32_t ad = sgb;
-        asm volatile("" : "+v"(ad));
-#pragma unroll
-        for (int i = 0; i < NR; ++i) {
-          if (i > 0) ad ^= sofs[__builtin_ctz(i)];
-          *reinterpret_cast<cpx<T>*>(tb + ad) = a[i ^ (i >> 1)];
+    }
+    if (moff) __syncthreads();
+    if (gi < ng) {
+      // the offset of the group's combination 0: as loaded, or its image
+      // under the store map (those of the group's free bits and of the
+      // tile's outside bits), recomputed here rather than kept live
+      uint32_t sgs = 0;
+      if (!moff) {
+        uint32_t lg = 0, fm = free_mask;
+        for (int bit = 0; fm; ++bit) {
+          const uint32_t low = fm & (0u - fm);
+          if ((gi >> bit) & 1) lg |= low;
+          fm ^= low;
         }
+        sgs = tile_swizzle(lg, SB) * (uint32_t)sizeof(cpx<T>);
+      } else {
+        const int32_t* __restrict__ mp = rb + moff;
+        const int nf = __popc(free_mask);
+        for (int i = 0; i < nf; ++i)
+          if ((gi >> i) & 1) sgs ^= (uint32_t)mp[i];
+        const int32_t* __restrict__ ob = mp + nf;
+        const int no = ob[0];
+        for (int k = 0; k < no; ++k)
+          if ((base >> ob[1 + 2 * k]) & 1ull) sgs ^= (uint32_t)ob[2 + 2 * k];
+      }
+      // recomputed rather than kept from the load walk: 2^RB live
+      // addresses would cost as many registers
+      // the store's offsets (the header's; a permutation that ends the
+      // round is folded into them)
+      uint32_t sofs[RB];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) sofs[j] = (uint32_t)rb[kHdrStore + j];
+      uint32_t ad = sgs;
+      asm volatile("" : "+v"(ad));
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        if (i > 0) ad ^= sofs[__builtin_ctz(i)];
+        *reinterpret_cast<cpx<T>*>(tb + ad) = a[i ^ (i >> 1)];
       }
     }
     __syncthreads();

@@ -31,11 +31,23 @@
 //                 when a CNOT / SWAP of register bits ends the round, the
 //                 offset of that bit's image, so that the store writes
 //                 register combination m to the slot of P m at no cost;
-//                 then the n_layers layer records of
+//                 [kHdrMap] the word offset (from the start of the round
+//                 block) of the round's store map, 0 if it has none (see
+//                 below); then the n_layers layer records of
 //                 LayerRec<T>::W words, each followed by its table (64 words)
 //                 if it has LT_TAB; then the aux words of the records.
 //                 Offsets in a record count words from the start of its round
 //                 block.
+//   store map   : the CNOTs that end a round (targets in the tile, controls
+//                 anywhere) as one affine map of the local index, applied by
+//                 the round's store: local index x of a tile with outside
+//                 bits o goes to the slot of A x + B o over GF(2).  [kHdrStore
+//                 + j] hold the swizzled offsets of A's columns for the
+//                 register bits; the map block holds them for the free bits,
+//                 one word per bit of the free-bit mask from the lowest, then
+//                 n_out and n_out pairs (outside qubit, offset of B's column).
+//                 Amplitudes move between register groups, so the kernel
+//                 waits for every group's load before any store.
 //   layer record: [0] flags, [1] unused, [2] CZ pair set
 //                 (LT_CZR), [3] aux offset: the payloads of the steps LT_CZF,
 //                 LT_SIGN, LT_PHASEL, LT_RAWD and LT_PERM2 / LT_U2 / LT_U1
@@ -155,11 +167,12 @@ constexpr int kTileThreads = 256;
 constexpr int kBodyLean = 0;  // tables, CZ signs, group parities, per-group phases, rotations
 constexpr int kBodyPerm = 1;  // those and register permutations (LT_PERM2)
 constexpr int kBodyFull = 2;  // every step
-constexpr int kRoundHeader = 16;  // words of a round block header
+constexpr int kRoundHeader = 32;  // words of a round block header
 constexpr int kRecRot = 4;        // first rotation word of a layer record
 constexpr int kTableWords = 64;   // words of a table
 constexpr int kHdrTileFac = 8;    // round-header word of the tile-factor list offset
 constexpr int kHdrStore = 10;     // round-header words of the store's register-bit offsets
+constexpr int kHdrMap = 16;       // round-header word of the store map's offset (0: none)
 constexpr int kMaxTileFactors = 128;  // tile-factor slots of one pass
 constexpr int kHdrLaneTab = 7;        // first round's header word of the lane-table offset
 constexpr int kHdrLaneTabN = 15;      // first round's header word of the lane-table entry count

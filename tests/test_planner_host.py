@@ -124,6 +124,45 @@ def test_emulated_gate_algebra_edge_cases(dtype, n, tile, seed):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,tile,seed", [(8, 6, 1), (11, 7, 2), (12, 12, 3)])
+def test_emulated_cnot_store_maps(dtype, n, tile, seed):
+    # CNOTs between qubits at every kind of tile position (register bits,
+    # free bits, controls outside the tile), full ladders, and phases carried
+    # on a target up to its CNOT: the rounds' store maps apply them all
+    rng = np.random.default_rng(seed)
+    ops = []
+    for _ in range(5):
+        for q in range(n):
+            ops.append(qc.op("RZ", q, params=(float(rng.uniform(-3, 3)),)))
+            if rng.random() < 0.6:
+                ops.append(qc.op("RY", q, params=(float(rng.uniform(-3, 3)),)))
+        ops += [qc.op("CNOT", q, q + 1) for q in range(n - 1)]
+        for _ in range(n):
+            a, b = (int(x) for x in rng.permutation(n)[:2])
+            ops.append(qc.op("CNOT", a, b))
+        ops.append(qc.op("T", int(rng.integers(n))))
+    words, steps = E.program(n, dtype, ops, tile)
+    counts = E.op_counts(words, steps, dtype)
+    assert counts.get("maps", 0) > 0 and counts.get("separate", 0) == 0, counts
+    psi0 = qc.random_state(n, 40 + seed)
+    ref = O.run(ops, n, psi=psi0.copy())
+    got = E.emulate(n, dtype, ops, psi0, tile)
+    assert np.abs(got - ref).max() <= TOL[dtype]
+
+
+def test_cnot_ladders_take_no_layers():
+    # the paper's round family: each round's CNOT ladder is applied by store
+    # maps, so the plan has no more layers than rotation levels need
+    n = 16
+    ops = qc.paper_rounds(n, 4, 5)
+    words, steps = E.program(n, "c64", ops, 12)
+    counts = E.op_counts(words, steps, "c64")
+    ncnot = sum(o.name == "CNOT" for o in ops)
+    assert counts.get("maps", 0) > 0 and counts.get("CZR", 0) == 0 and counts.get("CZF", 0) == 0, counts
+    assert counts["layers"] < ncnot, (counts, ncnot)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 def test_emulated_sign_steps(dtype):
     # CZs between every kind of qubit position (register, free, outside):
     # pair negations, conditional Zs and group parities all appear and

@@ -19,7 +19,7 @@ import numpy as np
 import qcircuits as qc
 from paper_1807_07914_amd import qsv
 
-ROUND_HEADER = 16   # words of a round block header
+ROUND_HEADER = 32   # words of a round block header
 REC_ROT = 4         # first rotation word of a layer record
 TABLE_WORDS = 64
 LT_TAB, LT_CZR, LT_SIGN, LT_PHASEL, LT_RAWD, LT_CZF = 1, 2, 4, 8, 16, 32
@@ -30,6 +30,7 @@ TK_REG, TK_FREE, TK_OUT = 0, 1, 2
 CFG = {"c64": dict(RB=5, SB=5, WT=1, LR=16), "c128": dict(RB=4, SB=4, WT=2, LR=24)}
 TILE_FAC_HDR, MAX_TILE_FACTORS = 8, 128  # round-header word of the tile-factor list; slot cap
 STORE_HDR = 10  # round-header words of the store's register-bit offsets
+MAP_HDR = 16    # round-header word of the store map's offset (0: none)
 LANE_TAB_HDR, LANE_TAB_N_HDR = 7, 15  # first round's header: lane-table offset, entries
 LANE_TAB_BYTES = 8192
 
@@ -188,6 +189,22 @@ def run_pass(psi, n, words, off, cfg):
                 lmsw.append(o_)
             recs_at = _record_offsets(blk, nlay, LR)
             rec_end = recs_at[-1] if recs_at else ROUND_HEADER
+            moff = blk[MAP_HDR]
+            if moff:
+                # store map: one offset per free bit, then the outside
+                # controls; the kernel loads every group before any store
+                assert moff >= rec_end
+                nf = bin(free_mask).count("1")
+                fcol = [(blk[moff + i] & 0xffffffff) for i in range(nf)]
+                no = blk[moff + nf]
+                ocol = [(blk[moff + nf + 1 + 2 * k], blk[moff + nf + 2 + 2 * k] & 0xffffffff) for k in range(no)]
+                assert all(v % esz == 0 for v in fcol) and all(0 <= q < n and v % esz == 0 for q, v in ocol)
+                assert all(q not in S for q, _ in ocol)
+                obase = 0
+                for q, v in ocol:
+                    if (base >> q) & 1:
+                        obase ^= v // esz
+            stores = []
             for gi in range(1 << (t - RB)):
                 lg = pdep_mask(gi, free_mask)
                 sg = swizzle(lg, SB)
@@ -346,19 +363,30 @@ def run_pass(psi, n, words, off, cfg):
                 # the store walks its own register-bit offsets (a permutation
                 # that ends the round is folded into them)
                 ssw = [(blk[STORE_HDR + j] & 0xffffffff) // esz for j in range(RB)]
+                sgs = sg
+                if moff:
+                    sgs = obase
+                    for i in range(nf):
+                        if (gi >> i) & 1:
+                            sgs ^= fcol[i] // esz
                 for m in range(NR):
                     o_ = 0
                     for j in range(RB):
                         if (m >> j) & 1:
                             o_ ^= ssw[j]
-                    lds[sg ^ o_] = a[m]
+                    stores.append((sgs ^ o_, a[m]))
+            # every group has loaded before the first store
+            dst = [k for k, _ in stores]
+            assert len(set(dst)) == len(dst) == 1 << t, "the store must be a bijection of the tile"
+            for k, v in stores:
+                lds[k] = v
         for l in range(1 << t):
             psi[gidx[l]] = lds[swizzle(l, SB)]
 
 
 def expand_cnots(ops):
-    """The op list the library's fused plan indexes: each CNOT(c, t) taken as
-    H(t), CZ(c, t), H(t)."""
+    """The op list the library's adjoint plan indexes: each CNOT(c, t) taken
+    as H(t), CZ(c, t), H(t)."""
     out = []
     for o in ops:
         if o.name == "CNOT":
@@ -424,7 +452,7 @@ def run_qperm(psi, n, words, off):
 def emulate(n, dtype, ops, psi0, tile=0, matrix_of=None):
     """Run the fused plan of ``ops`` on psi0 (complex128, copied)."""
     words, steps = program(n, dtype, ops, tile)
-    ops = expand_cnots(list(ops))
+    ops = list(ops)
     if any(is_qperm(words, int(st)) for st in steps):
         ops = relabel_swaps(ops, n)
     psi = np.array(psi0, dtype=np.complex128)
@@ -486,7 +514,8 @@ STEP_NAMES = [(LT_TAB, "TAB"), (LT_CZR, "CZR"), (LT_CZF, "CZF"), (LT_SIGN, "SIGN
 
 def op_counts(words, steps, dtype):
     """Number of layers, blocks and steps of each kind in a plan's tile
-    programs ('ROT' counts rotations, 'ROT3' those made of three shears)."""
+    programs ('ROT' counts rotations, 'ROT3' those made of three shears,
+    'maps' the rounds whose store applies CNOTs)."""
     RB = CFG[dtype]["RB"]
     out = {}
 
@@ -505,6 +534,8 @@ def op_counts(words, steps, dtype):
         blocks = _round_blocks(words, off, t, nns)
         add("blocks", len(blocks))
         for rb in blocks:
+            if int(words[rb + MAP_HDR]):
+                add("maps")
             k = rb + ROUND_HEADER
             for li in range(int(words[rb])):
                 flags = int(words[k])
