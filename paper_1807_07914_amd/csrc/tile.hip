@@ -366,6 +366,7 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
     static_assert((1 << (TBMAX - RB)) <= kTileThreads, "at most one register group per thread");
     const int gi = threadIdx.x;
     cpx<T> a[NR];
+    uint32_t sgb = 0;  // LDS offset of the group's combination 0
     if (gi < ng) {
       // deposit gi into the free local bits
       uint32_t lg = 0, fm = free_mask;
@@ -374,7 +375,7 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
         if ((gi >> bit) & 1) lg |= low;
         fm ^= low;
       }
-      const uint32_t sgb = tile_swizzle(lg, SB) * (uint32_t)sizeof(cpx<T>);
+      sgb = tile_swizzle(lg, SB) * (uint32_t)sizeof(cpx<T>);
       {
         uint32_t ad = sgb;
 #pragma unroll
@@ -590,19 +591,12 @@ __device__ __forceinline__ void run_rounds(char* __restrict__ tb, const int32_t*
     }
     if (moff) __syncthreads();
     if (gi < ng) {
-      // the offset of the group's combination 0: as loaded, or its image
-      // under the store map (those of the group's free bits and of the
-      // tile's outside bits), recomputed here rather than kept live
-      uint32_t sgs = 0;
-      if (!moff) {
-        uint32_t lg = 0, fm = free_mask;
-        for (int bit = 0; fm; ++bit) {
-          const uint32_t low = fm & (0u - fm);
-          if ((gi >> bit) & 1) lg |= low;
-          fm ^= low;
-        }
-        sgs = tile_swizzle(lg, SB) * (uint32_t)sizeof(cpx<T>);
-      } else {
+      // the store's offset of the group's combination 0: as loaded, or its
+      // image under the store map (the XOR of the images of the group's
+      // free bits and of the tile's outside bits)
+      uint32_t sgs = sgb;
+      if (moff) {
+        sgs = 0;
         const int32_t* __restrict__ mp = rb + moff;
         const int nf = __popc(free_mask);
         for (int i = 0; i < nf; ++i)
