@@ -94,7 +94,26 @@ def fam24():
         "random_ops": qc.random_ops(n, 400, 2402, dense_k=(1, 2, 3)),
         "qft": qc.qft(n),
         "hea": qc.hea_circuit(n, rng.uniform(0, 2 * np.pi, (6, n, 2)), layers=6),
+        # CNOT ladders and CNOTs between any two qubits (controls outside
+        # the tile, targets at register and free bits): the rounds' store maps
+        "rounds": qc.paper_rounds(n, 6, 2404),
+        "cnot_mesh": cnot_mesh(n, 6, 2405),
     }
+
+
+def cnot_mesh(n, depth, seed):
+    """Per layer RY and RZ on every qubit, then CNOTs on a random pairing of
+    all qubits (either direction, any distance)."""
+    rng = np.random.default_rng(seed)
+    ops = []
+    for _ in range(depth):
+        for q in range(n):
+            ops.append(qc.op("RY", q, params=(float(rng.uniform(0, 2 * np.pi)),)))
+            ops.append(qc.op("RZ", q, params=(float(rng.uniform(0, 2 * np.pi)),)))
+        perm = rng.permutation(n)
+        for i in range(0, n - 1, 2):
+            ops.append(qc.op("CNOT", int(perm[i]), int(perm[i + 1])))
+    return ops
 
 
 @pytest.mark.timeout(600)
