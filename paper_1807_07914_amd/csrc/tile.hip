@@ -1051,11 +1051,10 @@ static int qperm_grid() {
 
 // ------------------------------------------------------------ batches
 // Every tile of one pass of one batched circuit (state at psi), lean body,
-// by one workgroup: the segment table once per pass, and half of each
-// thread's share of the next tile loading into registers while the current
-// tile's rounds run (a batch often has about one workgroup per compute unit,
-// so other workgroups do not hide the load latency; a whole tile of staging
-// would not fit the registers).  The first pass builds |0...0> in the tile
+// by one workgroup: the segment table once per pass, and each thread's share
+// of the next tile loading into registers while the current tile's rounds
+// run (a batch often has about one workgroup per compute unit, so other
+// workgroups do not hide the load latency).  The first pass builds |0...0> in the tile
 // instead of loading; the last reduces the Z-string sum instead of storing.
 // Returns the thread's partial of that sum.
 template <typename T, int TBMAX, int RB>
@@ -1086,16 +1085,19 @@ __device__ __forceinline__ double batch_pass(cpx<T>* __restrict__ psi, const int
   const uint32_t cmask = (1u << c) - 1u;
   V stage[PF];
   double acc = 0.0;
-  uint64_t nb = 0;  // base index of the tile whose first half is in stage (tile 0: 0)
+  // Every lane issues every load of the tile whose base index is b0: an
+  // index past a smaller tile repeats one of its vectors, whose value is not
+  // used.  (With the loads inside per-lane branches the compiler waited for
+  // every earlier memory operation, the previous tile's stores included,
+  // before each load, and the prefetch ran one load at a time.)
+  auto vload = [&](uint64_t b0, int k) -> V {
+    const int i = threadIdx.x + k * kTileThreads;
+    const uint32_t l = (uint32_t)(i < nvec ? i : (i & (nvec - 1))) * A;
+    return gv[(b0 | segoff[l >> c] | (l & cmask)) / A];
+  };
   if (!io.init) {
 #pragma unroll
-    for (int k = 0; k < PF; ++k) {
-      const int i = threadIdx.x + k * kTileThreads;
-      if (i < nvec) {
-        const uint32_t l = (uint32_t)i * A;
-        stage[k] = gv[(nb | segoff[l >> c] | (l & cmask)) / A];
-      }
-    }
+    for (int k = 0; k < PF; ++k) stage[k] = vload(0, k);
   }
   for (uint64_t tid = 0; tid < ntiles; ++tid) {
     uint64_t base = 0;
@@ -1110,31 +1112,17 @@ __device__ __forceinline__ double batch_pass(cpx<T>* __restrict__ psi, const int
       }
     } else {
 #pragma unroll
-      for (int k = PF; k < VPT; ++k) {  // the other half now
-        const int i = threadIdx.x + k * kTileThreads;
-        if (i < nvec) {
-          const uint32_t l = (uint32_t)i * A;
-          StageVec<T>::put(tile, SB, l, gv[(base | segoff[l >> c] | (l & cmask)) / A]);
-        }
-      }
-#pragma unroll
       for (int k = 0; k < PF; ++k) {
         const int i = threadIdx.x + k * kTileThreads;
         if (i < nvec) StageVec<T>::put(tile, SB, (uint32_t)i * A, stage[k]);
       }
     }
     __syncthreads();
-    if (!io.init && tid + 1 < ntiles) {  // first half of the next tile, in flight during the rounds
-      nb = 0;
+    if (!io.init && tid + 1 < ntiles) {  // the next tile, in flight during the rounds
+      uint64_t nb = 0;
       for (int i = 0; i < nns; ++i) nb |= (((tid + 1) >> i) & 1ull) << nonS[i];
 #pragma unroll
-      for (int k = 0; k < PF; ++k) {
-        const int i = threadIdx.x + k * kTileThreads;
-        if (i < nvec) {
-          const uint32_t l = (uint32_t)i * A;
-          stage[k] = gv[(nb | segoff[l >> c] | (l & cmask)) / A];
-        }
-      }
+      for (int k = 0; k < PF; ++k) stage[k] = vload(nb, k);
     }
     run_rounds<T, TBMAX, RB, kBodyLean>(reinterpret_cast<char*>(tile), prog, t, nns, base, ltab);
     if (io.reduce) acc += tile_zsum<T, TBMAX>(tile, t, base, io);  // no store follows a reduce
