@@ -157,6 +157,21 @@ __global__ __launch_bounds__(kAB) void k_adj_final(const double* __restrict__ pa
 constexpr int kAdjRec = 72;
 constexpr int kAdjGate = 20;
 
+// A 16-byte vector of amplitudes as a native vector type (kept in registers
+// where an array of structs of amplitudes went to scratch memory).
+template <typename T>
+struct AdjVec;
+template <>
+struct AdjVec<float> {
+  using V = float4;
+  __device__ static cpx<float> at(const V& v, int e) { return e ? cpx<float>{v.z, v.w} : cpx<float>{v.x, v.y}; }
+};
+template <>
+struct AdjVec<double> {
+  using V = double2;
+  __device__ static cpx<double> at(const V& v, int) { return cpx<double>{v.x, v.y}; }
+};
+
 template <typename T>
 struct AdjRound {
   static constexpr int K = sizeof(T) == 4 ? 4 : 3;  // register bits per round
@@ -423,20 +438,52 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
   const int nvec = (1 << t) / A;
   const uint32_t cmask = (1u << c) - 1u;
   const int half = 1 << (t - 1), full = 1 << t;
+  // Each thread's share of the next tile of both states is loaded into
+  // registers while the gates of the current one run.  Every lane issues
+  // every load (an index past a smaller tile repeats one of its vectors,
+  // whose value is not used), so that the loads go out back to back.
+  constexpr int VPT = (1 << TB) / A / kAB;
+  using V = typename AdjVec<T>::V;
+  const V* __restrict__ vp = reinterpret_cast<const V*>(psi);
+  const V* __restrict__ vl = reinterpret_cast<const V*>(lam);
+  V xs[VPT], ys[VPT];
+  auto tile_base = [&](uint64_t id) {
+    uint64_t b = 0;
+    for (int i = 0; i < nns; ++i) b |= ((id >> i) & 1ull) << nonS[i];
+    return b;
+  };
+#define QSV_ADJ_LOAD_TILE(B)                                                  \
+  _Pragma("unroll") for (int k = 0; k < VPT; ++k) {                           \
+    const int i = threadIdx.x + k * kAB;                                      \
+    const uint32_t l = (uint32_t)(i < nvec ? i : (i & (nvec - 1))) * A;       \
+    const uint64_t g = ((B) | segoff[l >> c] | (l & cmask)) / A;              \
+    xs[k] = vp[g];                                                            \
+    ys[k] = vl[g];                                                            \
+  }
+  if (blockIdx.x < ntiles) {
+    const uint64_t b0 = tile_base(blockIdx.x);
+    QSV_ADJ_LOAD_TILE(b0)
+  }
   for (uint64_t tid = blockIdx.x; tid < ntiles; tid += gridDim.x) {
-    uint64_t base = 0;
-    for (int i = 0; i < nns; ++i) base |= ((tid >> i) & 1ull) << nonS[i];
-    for (int i = threadIdx.x; i < nvec; i += kAB) {
-      const uint32_t l = (uint32_t)i * A;
-      const uint64_t g = (base | segoff[l >> c] | (l & cmask)) / A;
-      const vec16<T> x = gp[g], y = gl[g];
+    const uint64_t base = tile_base(tid);
 #pragma unroll
-      for (int e = 0; e < A; ++e) {
-        tp[swz<T>(l + e)] = x.a[e];
-        tl[swz<T>(l + e)] = y.a[e];
+    for (int k = 0; k < VPT; ++k) {
+      const int i = threadIdx.x + k * kAB;
+      if (i < nvec) {
+        const uint32_t l = (uint32_t)i * A;
+#pragma unroll
+        for (int e = 0; e < A; ++e) {
+          tp[swz<T>(l + e)] = AdjVec<T>::at(xs[k], e);
+          tl[swz<T>(l + e)] = AdjVec<T>::at(ys[k], e);
+        }
       }
     }
     __syncthreads();
+    if (tid + gridDim.x < ntiles) {
+      const uint64_t bn = tile_base(tid + gridDim.x);
+      QSV_ADJ_LOAD_TILE(bn)
+    }
+#undef QSV_ADJ_LOAD_TILE
     const int32_t* r = recs;
     for (int o = 0; o < nops; ++o, r += r[0] == 6 ? r[3] : kAdjRec) {
       const int type = r[0], ra = r[1], rb = r[2], slot = type < 4 ? r[3] : -1, gen = r[4];
