@@ -639,6 +639,34 @@ struct TileIO {
   int nt;
 };
 
+// A 16-byte vector of amplitudes (two complex64 or one complex128) as a
+// native vector type, moved between registers and the swizzled LDS tile.
+template <typename T>
+struct StageVec;
+template <>
+struct StageVec<float> {
+  using V = float4;
+  __device__ static void put(cpx<float>* tile, int sb, uint32_t l, const V& v) {
+    tile[tile_swizzle(l, sb)] = cpx<float>{v.x, v.y};
+    tile[tile_swizzle(l + 1, sb)] = cpx<float>{v.z, v.w};
+  }
+  __device__ static V get(const cpx<float>* tile, int sb, uint32_t l) {
+    const cpx<float> a = tile[tile_swizzle(l, sb)], b = tile[tile_swizzle(l + 1, sb)];
+    return V{a.x, a.y, b.x, b.y};
+  }
+};
+template <>
+struct StageVec<double> {
+  using V = double2;
+  __device__ static void put(cpx<double>* tile, int sb, uint32_t l, const V& v) {
+    tile[tile_swizzle(l, sb)] = cpx<double>{v.x, v.y};
+  }
+  __device__ static V get(const cpx<double>* tile, int sb, uint32_t l) {
+    const cpx<double> a = tile[tile_swizzle(l, sb)];
+    return V{a.x, a.y};
+  }
+};
+
 // Z-string sum over one tile, sum_x |psi_x|^2 sum_q coef_q (-1)^popc(x & z_q),
 // in FP64, for a pass whose tile is not stored afterwards (its LDS slots are
 // reused).  Thread j owns the local indices l = j + 256 k.  The parity of
@@ -762,16 +790,22 @@ __device__ __forceinline__ double tile_body(const cpx<T>* src, cpx<T>* dst, cons
         tile[tile_swizzle(l + e, SB)] = cpx<T>{(g + e == 0) ? T(1) : T(0), T(0)};
     }
   } else {
+    // every load in flight before the first LDS write; every lane issues
+    // every load (an index past a smaller tile repeats one of its vectors,
+    // whose value is not used), so the compiler does not wait after each
+    using V = typename StageVec<T>::V;
+    const V* __restrict__ gq = reinterpret_cast<const V*>(src);
+    V xs[VPT];
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
       const int i = threadIdx.x + k * kTileThreads;
-      if (i < nvec) {
-        const uint32_t l = (uint32_t)i * A;
-        const uint64_t g = base | segoff[l >> c] | (l & cmask);
-        const vec16<T> x = gv[g / A];
+      const uint32_t l = (uint32_t)(i < nvec ? i : (i & (nvec - 1))) * A;
+      xs[k] = gq[(base | segoff[l >> c] | (l & cmask)) / A];
+    }
 #pragma unroll
-        for (int e = 0; e < A; ++e) tile[tile_swizzle(l + e, SB)] = x.a[e];
-      }
+    for (int k = 0; k < VPT; ++k) {
+      const int i = threadIdx.x + k * kTileThreads;
+      if (i < nvec) StageVec<T>::put(tile, SB, (uint32_t)i * A, xs[k]);
     }
   }
   __syncthreads();
@@ -812,34 +846,6 @@ __global__ __launch_bounds__(kTileThreads, MINWG) void k_tile(const cpx<T>* src,
   const TileIO io{0, 1, 0, nullptr, nullptr, nullptr, 0};
   (void)tile_body<T, TBMAX, RB, BODY>(src, dst, prog, blockIdx.x, io);
 }
-
-// A 16-byte vector of amplitudes (two complex64 or one complex128) as a
-// native vector type, moved between registers and the swizzled LDS tile.
-template <typename T>
-struct StageVec;
-template <>
-struct StageVec<float> {
-  using V = float4;
-  __device__ static void put(cpx<float>* tile, int sb, uint32_t l, const V& v) {
-    tile[tile_swizzle(l, sb)] = cpx<float>{v.x, v.y};
-    tile[tile_swizzle(l + 1, sb)] = cpx<float>{v.z, v.w};
-  }
-  __device__ static V get(const cpx<float>* tile, int sb, uint32_t l) {
-    const cpx<float> a = tile[tile_swizzle(l, sb)], b = tile[tile_swizzle(l + 1, sb)];
-    return V{a.x, a.y, b.x, b.y};
-  }
-};
-template <>
-struct StageVec<double> {
-  using V = double2;
-  __device__ static void put(cpx<double>* tile, int sb, uint32_t l, const V& v) {
-    tile[tile_swizzle(l, sb)] = cpx<double>{v.x, v.y};
-  }
-  __device__ static V get(const cpx<double>* tile, int sb, uint32_t l) {
-    const cpx<double> a = tile[tile_swizzle(l, sb)];
-    return V{a.x, a.y};
-  }
-};
 
 // Pipelined tile pass for one state.  A persistent workgroup walks the tiles
 // blockIdx.x, blockIdx.x + gridDim.x, ...  While the rounds of one tile run,
@@ -989,29 +995,27 @@ __global__ __launch_bounds__(kTileThreads) void k_qperm(const cpx<T>* src, cpx<T
       base2 |= ((tid2 >> i) & 1ull) << nonS[i];
     }
     const bool pair = tid2 != tid;
-    // all of the thread's loads in flight before the first LDS write
-    vec16<T> xs[VPT], ys[VPT];
+    // all of the thread's loads in flight before the first LDS write; every
+    // lane issues every load (an index past a smaller tile repeats one of its
+    // vectors, whose value is not used), so the compiler does not wait after
+    // each
+    using V = typename StageVec<T>::V;
+    const V* __restrict__ gq = reinterpret_cast<const V*>(src);
+    V xs[VPT], ys[VPT];
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
       const int i = threadIdx.x + k * kTileThreads;
-      if (i < nvec) {
-        const uint32_t l = (uint32_t)i * A;
-        const uint64_t off = segoff[l >> c] | (l & cmask);
-        xs[k] = gv[(base | off) / A];
-        if (pair) ys[k] = gv[(base2 | off) / A];
-      }
+      const uint32_t l = (uint32_t)(i < nvec ? i : (i & (nvec - 1))) * A;
+      const uint64_t off = segoff[l >> c] | (l & cmask);
+      xs[k] = gq[(base | off) / A];
+      if (pair) ys[k] = gq[(base2 | off) / A];
     }
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
       const int i = threadIdx.x + k * kTileThreads;
       if (i < nvec) {
-        const uint32_t l = (uint32_t)i * A;
-#pragma unroll
-        for (int e = 0; e < A; ++e) lds[0][tile_swizzle(l + e, SB)] = xs[k].a[e];
-        if (pair) {
-#pragma unroll
-          for (int e = 0; e < A; ++e) lds[1][tile_swizzle(l + e, SB)] = ys[k].a[e];
-        }
+        StageVec<T>::put(lds[0], SB, (uint32_t)i * A, xs[k]);
+        if (pair) StageVec<T>::put(lds[1], SB, (uint32_t)i * A, ys[k]);
       }
     }
     __syncthreads();
