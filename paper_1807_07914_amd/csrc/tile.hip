@@ -750,7 +750,7 @@ __device__ __forceinline__ double tile_zsum(cpx<T>* __restrict__ tile, int t, ui
 // kBodyFull: every step): the host picks the smallest body a pass needs,
 // since fewer registers let more workgroups share a compute unit and the
 // full body spills.
-template <typename T, int TBMAX, int RB, int BODY>
+template <typename T, int TBMAX, int RB, int BODY, bool GROUPED = true>
 __device__ __forceinline__ double tile_body(const cpx<T>* src, cpx<T>* dst, const int32_t* __restrict__ prog,
                                             uint64_t tid, const TileIO& io) {
   constexpr int A = VecInfo<T>::A;
@@ -790,22 +790,28 @@ __device__ __forceinline__ double tile_body(const cpx<T>* src, cpx<T>* dst, cons
         tile[tile_swizzle(l + e, SB)] = cpx<T>{(g + e == 0) ? T(1) : T(0), T(0)};
     }
   } else {
-    // every load in flight before the first LDS write; every lane issues
-    // every load (an index past a smaller tile repeats one of its vectors,
-    // whose value is not used), so the compiler does not wait after each
+    // GROUPED: every load in flight before the first LDS write.  Every lane
+    // issues every load (an index past a smaller tile repeats one of its
+    // vectors, whose value is not used), so the compiler does not wait after
+    // each.  The batch kernel's full body has no registers to spare for a
+    // group and loads one vector at a time.
     using V = typename StageVec<T>::V;
     const V* __restrict__ gq = reinterpret_cast<const V*>(src);
-    V xs[VPT];
+    constexpr int G = GROUPED ? VPT : 1;
 #pragma unroll
-    for (int k = 0; k < VPT; ++k) {
-      const int i = threadIdx.x + k * kTileThreads;
-      const uint32_t l = (uint32_t)(i < nvec ? i : (i & (nvec - 1))) * A;
-      xs[k] = gq[(base | segoff[l >> c] | (l & cmask)) / A];
-    }
+    for (int k0 = 0; k0 < VPT; k0 += G) {
+      V xs[G];
 #pragma unroll
-    for (int k = 0; k < VPT; ++k) {
-      const int i = threadIdx.x + k * kTileThreads;
-      if (i < nvec) StageVec<T>::put(tile, SB, (uint32_t)i * A, xs[k]);
+      for (int k = 0; k < G; ++k) {
+        const int i = threadIdx.x + (k0 + k) * kTileThreads;
+        const uint32_t l = (uint32_t)(i < nvec ? i : (i & (nvec - 1))) * A;
+        xs[k] = gq[(base | segoff[l >> c] | (l & cmask)) / A];
+      }
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const int i = threadIdx.x + (k0 + k) * kTileThreads;
+        if (i < nvec) StageVec<T>::put(tile, SB, (uint32_t)i * A, xs[k]);
+      }
     }
   }
   __syncthreads();
@@ -1193,7 +1199,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_batch(cpx<T>* __restrict__ 
       const TileIO io{p == 0, p + 1 < np, p + 1 == np, zt + t0, zlt + t0, ct + t0, (int)nt};
       if constexpr (FULL) {
         for (uint64_t tid = 0; tid < ntiles; ++tid)
-          acc += tile_body<T, TBMAX, RB, kBodyFull>(scratch + soff, scratch + soff, prog, tid, io);
+          acc += tile_body<T, TBMAX, RB, kBodyFull, false>(scratch + soff, scratch + soff, prog, tid, io);
       } else {
         acc += batch_pass<T, TBMAX, RB>(scratch + soff, prog, ntiles, io);
       }
