@@ -42,9 +42,9 @@ qsv_status plan_passes(const qsv_state* s, const qsv_op* ops, int n_ops, int til
 qsv_status plan_program(const qsv_state* s, const qsv_op* ops, int n_ops, int tile_qubits,
                         std::vector<int32_t>& prog, std::vector<int64_t>& steps);
 
-// The gate list the tile planner works on: each CNOT(c, t) as H_t CZ(c, t)
-// H_t, other ops unchanged; origin (if given) receives each op's index in
-// the input list.
+// The gate list the adjoint sweep's planner works on: each CNOT(c, t) as
+// H_t CZ(c, t) H_t, other ops unchanged; origin (if given) receives each
+// op's index in the input list.
 void expand_cnots(const qsv_op* ops, int n_ops, std::vector<qsv_op>& out, std::vector<int>* origin = nullptr);
 
 // Reverse sweep of the adjoint gradient as tile passes: ops[n_ops-1] .. ops[0]
