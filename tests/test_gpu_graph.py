@@ -51,6 +51,30 @@ def test_graph_replays_match_oracle(dtype, n):
     e.close()
 
 
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_graph_replays_with_cnot_store_maps(dtype):
+    # HEA circuits (CNOT ladders, applied by the rounds' store maps) with new
+    # angles on every call: the same structure replays the captured graph
+    from paper_1807_07914_amd import State
+    n = 14
+    st = torch.cuda.Stream()
+    s = State(n, dtype, stream=st)
+    e = State(n, dtype)
+    rng = np.random.default_rng(1400)
+    for rep in range(4):
+        ops = qc.hea_circuit(n, rng.uniform(0, 2 * np.pi, (5, n, 2)), layers=5)
+        s.set_basis(0)
+        s.apply_circuit(ops, graph=True)
+        e.set_basis(0)
+        e.apply_circuit(ops)
+        torch.cuda.synchronize()
+        got = s.to_numpy()
+        assert np.abs(got - O.run(ops, n)).max() <= TOL[dtype], rep
+        assert np.array_equal(got, e.to_numpy()), rep
+    s.close()
+    e.close()
+
+
 def test_graph_argument_checks():
     from paper_1807_07914_amd import QsvError, State
     ops = circuit(12, 4, 1300)
