@@ -2242,8 +2242,16 @@ static qsv_status batch_materialise(qsv_batch* b, int t, bool check_only_structu
     if (c > tc) c = tc;
     const int o0 = b->op_off[ci], o1 = b->op_off[ci + 1];
     std::vector<qsv_op> xops(b->ops.data() + o0, b->ops.data() + o1);
+    // A circuit held in one register group (n <= RB) applies its CNOTs in
+    // registers as H CZ H: there a store map would only add rounds.
+    const bool maps = n > RB;
+    if (!maps) {
+      std::vector<qsv_op> e;
+      expand_cnots(xops.data(), (int)xops.size(), e);
+      xops.swap(e);
+    }
     std::vector<POp> P(xops.size());
-    for (size_t i = 0; i < xops.size(); ++i) P[i] = classify_tile(xops[i]);
+    for (size_t i = 0; i < xops.size(); ++i) P[i] = maps ? classify_tile(xops[i]) : classify(xops[i]);
     std::vector<uint32_t> key = structure_key(P, n, tc, c, RB);
     const uint64_t h = key_hash(key);
     std::shared_ptr<Schedule> sch;
