@@ -91,7 +91,7 @@ typedef struct qsv_op {
 
 /* Execution strategy of qsv_apply_circuit.
  *   mode 0 = automatic (fused tile passes; the per-gate form when the
- *   environment has QSV_FORCE_PERGATE=1, read once per process), 1 = one
+ *   environment has QSV_FORCE_PERGATE=1, read at first use), 1 = one
  *   kernel per gate ("plain per-gate form"), 2 = fused tile passes, 3 =
  *   fused tile passes with the tile shape (tile qubits, and the contiguous
  *   segment qubits every tile keeps) chosen by an autotuner: the first call

@@ -13,6 +13,7 @@
 // Schedules depend only on the circuit's structure and are cached by a hash
 // of it; matrices are filled in for every call.
 #include <algorithm>
+#include <atomic>
 #include <complex>
 #include <cstdio>
 #include <cstdlib>
@@ -401,12 +402,16 @@ static std::shared_ptr<Schedule> build_schedule(const std::vector<POp>& P, int n
 // complex64 (256-byte segments), 4 for complex128.  Every tile spends them,
 // so for complex64 the plan with 128-byte segments (one more qubit free per
 // tile) is taken when it needs fewer passes.  QSV_SEGMENT_QUBITS=4 or 5 in
-// the environment fixes the choice (read once per process; for measurement).
+// the environment fixes the choice (read at first use, and again after
+// qsv_debug_reload_env; for measurement).
+static std::atomic<int> g_env_segment{-1};
 static int env_segment_qubits() {
-  static const int v = [] {
+  int v = g_env_segment.load();
+  if (v < 0) {
     const char* e = std::getenv("QSV_SEGMENT_QUBITS");
-    return (e && (e[0] == '4' || e[0] == '5') && e[1] == 0) ? e[0] - '0' : 0;
-  }();
+    v = (e && (e[0] == '4' || e[0] == '5') && e[1] == 0) ? e[0] - '0' : 0;
+    g_env_segment.store(v);
+  }
   return v;
 }
 static std::shared_ptr<Schedule> plan_tile_passes(const std::vector<POp>& P, int n, int t, bool f32, int RB,
@@ -1715,10 +1720,10 @@ static const char* tune_cache_path() {
   const char* p = std::getenv("QSV_AUTOTUNE_CACHE");
   return (p && *p) ? p : nullptr;
 }
+static bool g_tune_loaded = false;
 static void tuned_load_once() {
-  static bool loaded = false;
-  if (loaded) return;
-  loaded = true;
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
   const char* path = tune_cache_path();
   if (!path) return;
   FILE* f = std::fopen(path, "r");
@@ -2063,14 +2068,18 @@ void plan_adjoint(const qsv_op* ops, int n_ops, int n, int t, int c, int RB, std
 }
 
 // QSV_FORCE_PERGATE=1 in the environment turns the automatic mode into the
-// per-gate form (read once per process): a switch for comparing the two
-// forms, or for isolating a planner problem, without changing the caller.
+// per-gate form (read at first use, and again after qsv_debug_reload_env): a
+// switch for comparing the two forms, or for isolating a planner problem,
+// without changing the caller.
+static std::atomic<int> g_env_pergate{-1};
 static bool force_pergate() {
-  static const bool on = [] {
-    const char* v = std::getenv("QSV_FORCE_PERGATE");
-    return v && v[0] == '1' && v[1] == 0;
-  }();
-  return on;
+  int v = g_env_pergate.load();
+  if (v < 0) {
+    const char* e = std::getenv("QSV_FORCE_PERGATE");
+    v = (e && e[0] == '1' && e[1] == 0) ? 1 : 0;
+    g_env_pergate.store(v);
+  }
+  return v != 0;
 }
 
 qsv_status run_circuit(qsv_state* s, const qsv_op* ops, int n_ops, const qsv_plan_opts& opts) {
@@ -2654,6 +2663,26 @@ qsv_status qsv_batch_free(qsv_batch* b) {
 }  // extern "C"
 
 extern "C" {
+
+// Host-only debug export (not in the public header): the environment
+// switches (QSV_FORCE_PERGATE, QSV_SEGMENT_QUBITS, QSV_AUTOTUNE_CACHE) are
+// read again at their next use, as in a new process: the autotuners' choices
+// and the schedule cache are dropped.  For tests that change the environment
+// within one process.  Not safe while another thread plans or tunes.
+qsv_status qsv_debug_reload_env() {
+  g_env_segment.store(-1);
+  g_env_pergate.store(-1);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+    g_tune_loaded = false;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache.clear();
+  }
+  return QSV_OK;
+}
 
 // Host-only debug export (not in the public header): the program image, pass
 // offsets and job table qsv_batch_create would upload for tile width

@@ -1,48 +1,61 @@
-"""Environment switches of the library, each in a fresh process (they are
-read once per process): QSV_FORCE_PERGATE=1 turns the automatic mode into
-the per-gate form; QSV_AUTOTUNE_CACHE persists the batch autotuner's choices
-in a file that later processes read."""
-import json
+"""Environment switches of the library, read at first use: QSV_FORCE_PERGATE=1
+turns the automatic mode into the per-gate form; QSV_AUTOTUNE_CACHE persists
+the autotuners' choices in a file that later processes read;
+QSV_SEGMENT_QUBITS fixes the segment width.  Each case sets the variables,
+makes the library read its switches again (the host-only debug export
+qsv_debug_reload_env, which also drops the autotuners' choices and the
+schedule cache, as a new process would start), runs, and restores the
+environment.  The cases run in the test process itself: no child process is
+started from a process that has the GPU open."""
+import contextlib
 import os
-import subprocess
-import sys
 
+import numpy as np
 import pytest
+
+import qcircuits as qc
 
 pytestmark = pytest.mark.gpu
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+@contextlib.contextmanager
+def switches(**kv):
+    from paper_1807_07914_amd import qsv
+    old = {k: os.environ.get(k) for k in kv}
+    try:
+        for k, v in kv.items():
+            os.environ[k] = v
+        assert qsv.lib().qsv_debug_reload_env() == 0
+        yield
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+        qsv.lib().qsv_debug_reload_env()
 
 
-def run_child(code, **env):
-    e = dict(os.environ)
-    e.update(env)
-    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=e, capture_output=True, text=True,
-                       timeout=300)
-    assert r.returncode == 0, r.stderr[-2000:]
-    return json.loads(r.stdout.strip().splitlines()[-1])
-
-
-FORCE = r"""
-import json, numpy as np, qcircuits as qc
-from paper_1807_07914_amd import State
-n = 16
-ops = qc.random_brickwork(n, 12, 4321)
-out = {}
-for mode in ("auto", "pergate", "fused"):
-    s = State(n, "c64")
-    s.apply_circuit(ops, mode=mode)
-    out[mode] = s.to_numpy()
-    s.close()
-print(json.dumps({"auto_is_pergate": bool(np.array_equal(out["auto"], out["pergate"])),
-                  "auto_is_fused": bool(np.array_equal(out["auto"], out["fused"])),
-                  "fused_is_pergate": bool(np.array_equal(out["fused"], out["pergate"]))}))
-"""
+def force_forms():
+    from paper_1807_07914_amd import State
+    n = 16
+    ops = qc.random_brickwork(n, 12, 4321)
+    out = {}
+    for mode in ("auto", "pergate", "fused"):
+        s = State(n, "c64")
+        s.apply_circuit(ops, mode=mode)
+        out[mode] = s.to_numpy()
+        s.close()
+    return {"auto_is_pergate": bool(np.array_equal(out["auto"], out["pergate"])),
+            "auto_is_fused": bool(np.array_equal(out["auto"], out["fused"])),
+            "fused_is_pergate": bool(np.array_equal(out["fused"], out["pergate"]))}
 
 
 def test_force_pergate_switch():
-    on = run_child(FORCE, QSV_FORCE_PERGATE="1")
-    off = run_child(FORCE, QSV_FORCE_PERGATE="")
+    with switches(QSV_FORCE_PERGATE="1"):
+        on = force_forms()
+    with switches(QSV_FORCE_PERGATE=""):
+        off = force_forms()
     # the fused and per-gate forms round differently on this circuit, so
     # bitwise equality names the form that ran
     assert not on["fused_is_pergate"]
@@ -50,62 +63,63 @@ def test_force_pergate_switch():
     assert off["auto_is_fused"] and not off["auto_is_pergate"]
 
 
-TUNE = r"""
-import json, numpy as np, qcircuits as qc
-from paper_1807_07914_amd import qsv
-rng = np.random.default_rng(5)
-widths = [16, 16, 15, 14]
-circs = [qc.random_brickwork(w, 6, 50 + i) for i, w in enumerate(widths)]
-terms = [[(1.0, (("Z", 0), ("Z", 1)))] for _ in widths]
-b = qsv.Batch(circs, widths, terms)
-print(json.dumps({"tile_qubits": b.info()["tile_qubits"]}))
-"""
+def batch_tile_qubits():
+    from paper_1807_07914_amd import qsv
+    widths = [16, 16, 15, 14]
+    circs = [qc.random_brickwork(w, 6, 50 + i) for i, w in enumerate(widths)]
+    terms = [[(1.0, (("Z", 0), ("Z", 1)))] for _ in widths]
+    b = qsv.Batch(circs, widths, terms)
+    t = b.info()["tile_qubits"]
+    b.close()
+    return t
 
 
 def test_autotune_cache_file(tmp_path):
     path = str(tmp_path / "tune.txt")
-    first = run_child(TUNE, QSV_AUTOTUNE_CACHE=path)
+    with switches(QSV_AUTOTUNE_CACHE=path):
+        first = batch_tile_qubits()
     lines = open(path).read().split()
-    assert len(lines) == 2 and int(lines[1]) == first["tile_qubits"]
+    assert len(lines) == 2 and int(lines[1]) == first
     h = int(lines[0], 16)
-    # a later process takes the file's choice without timing: plant another
+    # a later start takes the file's choice without timing: plant another
     # valid width for the same structure and see it used
-    other = 12 if first["tile_qubits"] != 12 else 11
+    other = 12 if first != 12 else 11
     with open(path, "w") as f:
         f.write("%016x %d\n" % (h, other))
-    second = run_child(TUNE, QSV_AUTOTUNE_CACHE=path)
-    assert second["tile_qubits"] == other
+    with switches(QSV_AUTOTUNE_CACHE=path):
+        second = batch_tile_qubits()
+    assert second == other
     assert open(path).read().split() == ["%016x" % h, str(other)]   # nothing re-tuned or appended
 
 
-TUNED = r"""
-import json, os, numpy as np, qcircuits as qc
-from paper_1807_07914_amd import State
-n = 18
-ops = qc.random_brickwork(n, 16, 6060)
-out = {}
-for mode, tile in (("tuned", 0), ("fused", 12)):
-    s = State(n, "c64")
-    s.apply_circuit(ops, mode=mode, tile_qubits=tile)
-    out[mode] = s.to_numpy()
-    s.close()
-print(json.dumps({"same_as_t12": bool(np.array_equal(out["tuned"], out["fused"]))}))
-"""
+def tuned_same_as_t12():
+    from paper_1807_07914_amd import State
+    n = 18
+    ops = qc.random_brickwork(n, 16, 6060)
+    out = {}
+    for mode, tile in (("tuned", 0), ("fused", 12)):
+        s = State(n, "c64")
+        s.apply_circuit(ops, mode=mode, tile_qubits=tile)
+        out[mode] = s.to_numpy()
+        s.close()
+    return bool(np.array_equal(out["tuned"], out["fused"]))
 
 
 def test_single_state_autotuner_cache_file(tmp_path):
-    # the first process times the candidate shapes and appends its choice;
-    # a later process takes a planted choice (12 tile qubits, 4 segment
-    # qubits) without timing: its result is then bit for bit the plan with
-    # that shape (segment width fixed to 4 by the environment for both)
+    # the first start times the candidate shapes and appends its choice; a
+    # later start takes a planted choice (12 tile qubits, 4 segment qubits)
+    # without timing: its result is then bit for bit the plan with that
+    # shape (segment width fixed to 4 by the environment for both)
     path = str(tmp_path / "tune.txt")
-    run_child(TUNED, QSV_AUTOTUNE_CACHE=path)
+    with switches(QSV_AUTOTUNE_CACHE=path):
+        tuned_same_as_t12()
     words = open(path).read().split()
     assert len(words) == 2
     v = int(words[1])
     assert v // 100 in (12, 13) and v % 100 in (4, 5)
     with open(path, "w") as f:
         f.write("%s %d\n" % (words[0], 1204))
-    second = run_child(TUNED, QSV_AUTOTUNE_CACHE=path, QSV_SEGMENT_QUBITS="4")
-    assert second["same_as_t12"]
+    with switches(QSV_AUTOTUNE_CACHE=path, QSV_SEGMENT_QUBITS="4"):
+        same = tuned_same_as_t12()
+    assert same
     assert open(path).read().split() == [words[0], "1204"]
