@@ -295,3 +295,30 @@ def test_emulated_lane_tables_full_tile(dtype, n):
     psi0 = qc.random_state(n, 300 + n)
     got = E.emulate(n, dtype, ops, psi0)
     assert np.abs(got - O.run(ops, n, psi=psi0.copy())).max() <= TOL[dtype]
+
+
+def test_environment_switches_read_again_after_reload():
+    # QSV_SEGMENT_QUBITS is read at first use; the debug export
+    # qsv_debug_reload_env makes the library read it again (and drops the
+    # schedule cache): the 30-qubit QFT needs 5 passes with 5 segment qubits
+    # and 4 with 4 (the planner's own choice)
+    import os
+    L = qsv.lib()
+    ops = qc.qft(30)
+    old = os.environ.get("QSV_SEGMENT_QUBITS")
+    try:
+        got = {}
+        for v in ("5", "4", None):
+            if v is None:
+                os.environ.pop("QSV_SEGMENT_QUBITS", None)
+            else:
+                os.environ["QSV_SEGMENT_QUBITS"] = v
+            assert L.qsv_debug_reload_env() == 0
+            got[v] = qsv.plan_info(30, "c64", ops)["passes"]
+        assert got["5"] > got["4"] and got[None] == min(got["5"], got["4"])
+    finally:
+        if old is None:
+            os.environ.pop("QSV_SEGMENT_QUBITS", None)
+        else:
+            os.environ["QSV_SEGMENT_QUBITS"] = old
+        L.qsv_debug_reload_env()
