@@ -2261,20 +2261,34 @@ static qsv_status batch_materialise(qsv_batch* b, int t, bool check_only_structu
     }
     std::vector<POp> P(xops.size());
     for (size_t i = 0; i < xops.size(); ++i) P[i] = maps ? classify_tile(xops[i]) : classify(xops[i]);
-    std::vector<uint32_t> key = structure_key(P, n, tc, c, RB);
-    const uint64_t h = key_hash(key);
-    std::shared_ptr<Schedule> sch;
-    {
-      std::lock_guard<std::mutex> lk(g_cache_mu);
-      auto it = g_cache.find(h);
-      if (it != g_cache.end() && it->second->key == key) sch = it->second;
-    }
-    if (!sch) {
-      sch = build_schedule(P, n, tc, c, RB);
-      sch->key = std::move(key);
-      std::lock_guard<std::mutex> lk(g_cache_mu);
-      if (g_cache.size() > 4096) g_cache.clear();
-      g_cache[h] = sch;
+    auto plan_c = [&](int cc) {
+      std::vector<uint32_t> key = structure_key(P, n, tc, cc, RB);
+      const uint64_t h = key_hash(key);
+      std::shared_ptr<Schedule> found;
+      {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache.find(h);
+        if (it != g_cache.end() && it->second->key == key) found = it->second;
+      }
+      if (!found) {
+        found = build_schedule(P, n, tc, cc, RB);
+        found->key = std::move(key);
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        if (g_cache.size() > 4096) g_cache.clear();
+        g_cache[h] = found;
+      }
+      return found;
+    };
+    std::shared_ptr<Schedule> sch = plan_c(c);
+    // complex64 over several tiles: 128-byte segments leave each tile one
+    // more qubit of its own, kept when that needs fewer passes (as for
+    // single states; the 19- and 20-qubit HEA circuits: 8 -> 6 and 7)
+    if (sizeof(T) == 4 && n > tc && c == 5) {
+      std::shared_ptr<Schedule> alt = plan_c(4);
+      if (alt->passes < sch->passes) {
+        sch = alt;
+        c = 4;
+      }
     }
     first[ci] = (int64_t)b->passoff.size();
     int np = 0;
