@@ -125,7 +125,8 @@ __global__ __launch_bounds__(kAB) void k_adj_final(const double* __restrict__ pa
 //
 // Program (int32 words): [0] t, [1] c, [2] n_nonS, [3] n_ops, [4] n_grad,
 // [5] offset of the op records, [6] offset of the gradient map (the
-// circuit's op index of each gradient slot), S[t] from word 8, nonS after.
+// circuit's op index of each gradient slot), [7] the number of type-7
+// records, S[t] from word 8, nonS after.
 // Op record (kAdjRec words): [0] type, [1] a, [2] b, [3] gradient slot or
 // -1, [4] generator (0 X, 1 Y, 2 Z), then complex doubles (re, im) from
 // word 8:
@@ -153,7 +154,11 @@ __global__ __launch_bounds__(kAB) void k_adj_final(const double* __restrict__ pa
 //           [0] j | shape << 4 | generator << 8, [1] gradient slot or -1,
 //           from word 4 the matrix (m00, m01, m10, m11 as re, im) in the
 //           state's precision
-// Records of types 1-5 are kAdjRec words long.
+//   7 TILE PHASE: a diagonal unitary diag(d[0], d[1]) on the qubit a
+//           outside the tile (named gates only): one phase for the whole
+//           tile, applied to both states by the tile's store; a gradient
+//           slot takes Z on a (+-Im<lambda|psi> over the tile)
+// Records of types 1-5 and 7 are kAdjRec words long.
 constexpr int kAdjRec = 72;
 constexpr int kAdjGate = 20;
 
@@ -420,6 +425,7 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
   __shared__ double gacc[kMaxAdjGrad * (kAB / 64)];
   __shared__ uint64_t segoff[256];
   const int t = prog[0], c = prog[1], nns = prog[2], nops = prog[3], ngrad = prog[4];
+  const int ntph = prog[7];  // records of tile phases (type 7)
   const int32_t* S = prog + 8;
   const int32_t* nonS = S + t;
   const int32_t* recs = prog + prog[5];
@@ -466,6 +472,13 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
   }
   for (uint64_t tid = blockIdx.x; tid < ntiles; tid += gridDim.x) {
     const uint64_t base = tile_base(tid);
+    // A diagonal unitary on a qubit outside the tile is one phase for the
+    // whole tile, the same on both states: it is multiplied into tph and
+    // applied by the store.  Its gradient term is +-Im<lambda|psi> over the
+    // tile, which the tile's other records (unitaries applied to both
+    // states) leave unchanged: the thread's share s_im is taken at the load.
+    cpx<T> tph{T(1), T(0)};
+    double s_im = 0.0;
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
       const int i = threadIdx.x + k * kAB;
@@ -473,8 +486,10 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
         const uint32_t l = (uint32_t)i * A;
 #pragma unroll
         for (int e = 0; e < A; ++e) {
-          tp[swz<T>(l + e)] = AdjVec<T>::at(xs[k], e);
-          tl[swz<T>(l + e)] = AdjVec<T>::at(ys[k], e);
+          const cpx<T> p = AdjVec<T>::at(xs[k], e), q = AdjVec<T>::at(ys[k], e);
+          tp[swz<T>(l + e)] = p;
+          tl[swz<T>(l + e)] = q;
+          if (ntph > 0) s_im += (double)q.x * (double)p.y - (double)q.y * (double)p.x;
         }
       }
     }
@@ -486,7 +501,7 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
 #undef QSV_ADJ_LOAD_TILE
     const int32_t* r = recs;
     for (int o = 0; o < nops; ++o, r += r[0] == 6 ? r[3] : kAdjRec) {
-      const int type = r[0], ra = r[1], rb = r[2], slot = type < 4 ? r[3] : -1, gen = r[4];
+      const int type = r[0], ra = r[1], rb = r[2], slot = (type < 4 || type == 7) ? r[3] : -1, gen = r[4];
       double g = 0.0;
       if (type == 1) {
         M2<T> V;
@@ -504,6 +519,10 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
           tl[swz<T>(i0)] = l0;
           tl[swz<T>(i1)] = l1;
         }
+      } else if (type == 7) {
+        const bool one = ((base >> ra) & 1ull) != 0;  // the outside qubit's value in this tile
+        tph = cmul(one ? rec_cpx<T>(r, 1) : rec_cpx<T>(r, 0), tph);
+        if (slot >= 0) g = one ? -s_im : s_im;
       } else if (type == 2) {
         const cpx<T> d0 = rec_cpx<T>(r, 0), d1 = rec_cpx<T>(r, 1), d2 = rec_cpx<T>(r, 2), d3 = rec_cpx<T>(r, 3);
         const int ka = ra >> 8, va = ra & 255;
@@ -623,6 +642,10 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
       for (int e = 0; e < A; ++e) {
         x.a[e] = tp[swz<T>(l + e)];
         y.a[e] = tl[swz<T>(l + e)];
+        if (ntph > 0) {
+          x.a[e] = cmul(tph, x.a[e]);
+          y.a[e] = cmul(tph, y.a[e]);
+        }
       }
       gp[g] = x;
       gl[g] = y;

@@ -1000,6 +1000,12 @@ static qsv_status build_adjoint_programs(int n, const qsv_op* in_ops, int n_in, 
         std::memcpy(&rec[8 + 4 * e + 2], &im, 8);
       };
       auto gen_of = [](int g) { return g == QSV_RX ? 0 : g == QSV_RY ? 1 : 2; };
+      // tile-phase records take the tile's Im<lambda|psi> from its load,
+      // which needs every op of the pass unitary: named gates only
+      bool named = true;
+      for (size_t k = k0; k < k1; ++k)
+        for (size_t kk : items[k].ks) named = named && ops[as.ops[kk]].gate != QSV_MAT;
+      int ntph = 0;
       for (size_t k = k0; k < k1; ++k) {
         const Item& item = items[k];
         std::vector<int32_t> rec(LR, 0);
@@ -1113,7 +1119,19 @@ static qsv_status build_adjoint_programs(int n, const qsv_op* in_ops, int n_in, 
         cd vals[16];
         int nv = 0;
         auto operand = [&](int q) { return lpos[q] >= 0 ? lpos[q] : ((2 << 8) | q); };
-        if (diag) {
+        const bool tile_phase = diag && o.nq == 1 && lpos[o.q[0]] < 0 && named &&
+                                std::abs(std::abs(mi[0]) - 1.0) < 1e-12 && std::abs(std::abs(mi[3]) - 1.0) < 1e-12;
+        if (tile_phase) {  // one phase per tile, applied by the store
+          rec[0] = 7;
+          rec[1] = o.q[0];
+          rec[2] = -1;
+          vals[0] = mi[0];
+          vals[1] = mi[3];
+          vals[2] = mi[0];
+          vals[3] = mi[3];
+          nv = 4;
+          ++ntph;
+        } else if (diag) {
           rec[0] = 2;
           rec[1] = operand(o.q[0]);
           rec[2] = o.nq == 2 ? operand(o.q[1]) : -1;
@@ -1149,6 +1167,7 @@ static qsv_status build_adjoint_programs(int n, const qsv_op* in_ops, int n_in, 
         prog.insert(prog.end(), rec.begin(), rec.end());
       }
       prog[off + 6] = (int32_t)(prog.size() - off);
+      prog[off + 7] = ntph;
       prog.insert(prog.end(), map.begin(), map.end());
       while (prog.size() % 8) prog.push_back(0);
       launches.push_back({(int)si, off});

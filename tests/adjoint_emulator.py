@@ -63,7 +63,8 @@ def _apply(psi, lam, n, qubits, U):
 
 
 def run_program(words, off, n, dtype, psi, lam, grads):
-    t, c, nns, nops, ngrad, roff, moff = (int(x) for x in words[off:off + 7])
+    t, c, nns, nops, ngrad, roff, moff, ntph = (int(x) for x in words[off:off + 8])
+    seen_tph = 0
     S = [int(x) for x in words[off + 8:off + 8 + t]]
     assert S[:c] == list(range(c)) and len(set(S)) == t and 0 < t <= n and nns == n - t
     slot_g = np.zeros(max(ngrad, 1))
@@ -114,6 +115,22 @@ def run_program(words, off, n, dtype, psi, lam, grads):
                 slot_g[slot] += _gen_term(lam, psi, n, S[a], gen)
                 used.add(slot)
             _apply(psi, lam, n, [S[a]], U)
+        elif typ == 7:
+            # a phase per tile: diag(d0, d1) on a qubit outside the tile; the
+            # kernel applies it at the tile's store, which gives the same
+            # states and the same gradient term as applying it here
+            q = a
+            assert q not in S and 0 <= q < n and b == -1
+            d0, d1 = _cd(rec, 8), _cd(rec, 12)
+            assert abs(abs(d0) - 1) < 1e-12 and abs(abs(d1) - 1) < 1e-12
+            bit = (idx >> q) & 1
+            if slot >= 0:
+                slot_g[slot] += float(np.sum(np.where(bit == 1, -1.0, 1.0) * (np.conj(lam) * psi).imag))
+                used.add(slot)
+            fac = np.where(bit == 1, d1, d0)
+            psi *= fac
+            lam *= fac
+            seen_tph += 1
         elif typ == 2:
             d = [_cd(rec, 8 + 4 * e) for e in range(4)]
 
@@ -151,6 +168,7 @@ def run_program(words, off, n, dtype, psi, lam, grads):
         else:
             raise AssertionError("unknown record type %d" % typ)
         r += REC_WORDS
+    assert seen_tph == ntph, "header word 7 counts the tile-phase records"
     assert sorted(used) == list(range(ngrad)), "every gradient slot taken once"
     omap = [int(x) for x in words[off + moff:off + moff + ngrad]]
     for sl, op in enumerate(omap):

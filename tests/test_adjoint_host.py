@@ -116,8 +116,10 @@ def test_program_uses_rounds_and_sign_runs():
             typ = int(words[r])
             kinds[typ] = kinds.get(typ, 0) + 1
             r += int(words[r + 3]) if typ == 6 else AE.REC_WORDS
-    # 2: diagonal gates on qubits outside a pass's tile (RZ), 5: sign runs, 6: rounds
-    assert set(kinds) <= {2, 5, 6} and kinds.get(6, 0) > 0 and kinds.get(5, 0) > 0, kinds
+    # 2: other diagonal gates (single CZs), 5: sign runs, 6: rounds, 7: phases
+    # per tile (RZ on qubits outside a pass's tile, applied by the store)
+    assert set(kinds) <= {2, 5, 6, 7} and kinds.get(6, 0) > 0 and kinds.get(5, 0) > 0, kinds
+    assert kinds.get(7, 0) > 0 and kinds.get(2, 0) < kinds[7], kinds
     assert sum(kinds.values()) < len(ops) // 3, (kinds, len(ops))
 
 
