@@ -149,6 +149,10 @@ __global__ __launch_bounds__(kAB) void k_adj_final(const double* __restrict__ pa
 //           (gates on different qubits commute, gates on one qubit keep
 //           their order), taking each rotation's term first.  [2] the gate
 //           count of each register bit, 8 bits per bit j from bit 8 j,
+//           [1] 0, or the offset from the record of a sign block (a type-5
+//           record of 8 + 2 (n_dist + n_lo + n_oo) words, padded to a
+//           multiple of 8) applied to the amplitudes as they are loaded,
+//           before the gates: a sign run that precedes the round,
 //           [3] record length in words, [4 + j] local bit j (ascending),
 //           gates from word 8 ordered by bit, kAdjGate words each:
 //           [0] j | shape << 4 | generator << 8, [1] gradient slot or -1,
@@ -397,6 +401,22 @@ __device__ __forceinline__ double round_gate(int form, int gen, bool grad, const
 
 // The gates of a round on register bit J (cnt of them, at gw, which moves
 // past them), each with its rotation's wave sum added to its slot
+// The parts of a sign run (type-5 layout at rec) fixed by the tile's base
+// index: the local bits Mo whose sign pattern is linear in this tile, and
+// the parity cpar of the outside pairs.
+__device__ __forceinline__ void sign_tile_terms(const int32_t* rec, uint64_t base, uint32_t& Mo, int& cpar) {
+  const int nd = rec[1], nlo = rec[2], noo = rec[3];
+  const int32_t* w = rec + 8;
+  for (int i = 0; i < nlo; ++i) {
+    const int oq = w[2 * nd + 2 * i + 1];
+    if (oq < 0 || ((base >> oq) & 1ull)) Mo ^= 1u << w[2 * nd + 2 * i];
+  }
+  for (int i = 0; i < noo; ++i) {
+    const int32_t* pq = w + 2 * (nd + nlo + i);
+    cpar ^= (int)((base >> pq[0]) & (base >> pq[1]) & 1ull);
+  }
+}
+
 template <typename T, int K, int J>
 __device__ __forceinline__ void round_bit(int cnt, const int32_t*& gw, cpx<T>* x, cpx<T>* y, double* gacc,
                                           int wave, int lane) {
@@ -549,6 +569,10 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
 #pragma unroll
         for (int m = 1; m < NR; ++m) off[m] = off[m & (m - 1)] | (1u << r[4 + __builtin_ctz(m)]);
         const int ngroups = full >> K;
+        const int32_t* sr = r[1] ? r + r[1] : nullptr;  // a sign run applied at the load
+        uint32_t Mo = 0;
+        int cpar = 0;
+        if (sr) sign_tile_terms(sr, base, Mo, cpar);
         for (int g0 = 0; g0 < ngroups; g0 += kAB) {  // every lane runs every group step (shuffles below)
           const int gi = g0 + (int)threadIdx.x;
           const bool valid = gi < ngroups;
@@ -564,6 +588,20 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
             x[m] = valid ? tp[swz<T>(b | off[m])] : cpx<T>{0, 0};
             y[m] = valid ? tl[swz<T>(b | off[m])] : cpx<T>{0, 0};
           }
+          if (sr) {
+            const int nd = sr[1];
+            const int32_t* w = sr + 8;
+#pragma unroll
+            for (int m = 0; m < NR; ++m) {
+              const uint32_t l = b | off[m];
+              int par = cpar + __popc(l & Mo);
+              for (int i = 0; i < nd; ++i) par += __popc(l & (l >> w[2 * i]) & (uint32_t)w[2 * i + 1]);
+              if (par & 1) {
+                x[m] = cpx<T>{-x[m].x, -x[m].y};
+                y[m] = cpx<T>{-y[m].x, -y[m].y};
+              }
+            }
+          }
           const int32_t* gw = r + 8;
           round_bit<T, K, 0>((ngate >> 0) & 255, gw, x, y, gacc, wave, lane);
           round_bit<T, K, 1>((ngate >> 8) & 255, gw, x, y, gacc, wave, lane);
@@ -578,18 +616,11 @@ __global__ __launch_bounds__(kAB) void k_adj_tile(cpx<T>* __restrict__ psi, cpx<
           }
         }
       } else if (type == 5) {
-        const int nd = ra, nlo = rb, noo = r[3];
+        const int nd = ra;
         const int32_t* w = r + 8;
         uint32_t Mo = 0;
         int cpar = 0;
-        for (int i = 0; i < nlo; ++i) {
-          const int oq = w[2 * nd + 2 * i + 1];
-          if (oq < 0 || ((base >> oq) & 1ull)) Mo ^= 1u << w[2 * nd + 2 * i];
-        }
-        for (int i = 0; i < noo; ++i) {
-          const int32_t* pq = w + 2 * (nd + nlo + i);
-          cpar ^= (int)((base >> pq[0]) & (base >> pq[1]) & 1ull);
-        }
+        sign_tile_terms(r, base, Mo, cpar);
         for (int l = threadIdx.x; l < full; l += kAB) {
           int par = cpar + __popc((uint32_t)l & Mo);
           for (int i = 0; i < nd; ++i) par += __popc((uint32_t)l & ((uint32_t)l >> w[2 * i]) & (uint32_t)w[2 * i + 1]);

@@ -982,13 +982,12 @@ static qsv_status build_adjoint_programs(int n, const qsv_op* in_ops, int n_in, 
         ++k1;
       }
       const size_t off = prog.size();
-      const int nops = (int)(k1 - k0);
       const int hdr = (8 + t + (int)nonS.size() + 7) & ~7;
       prog.resize(off + hdr, 0);
       prog[off] = t;
       prog[off + 1] = c;
       prog[off + 2] = (int)nonS.size();
-      prog[off + 3] = nops;
+      prog[off + 3] = 0;  // the record count, set once the records are out
       prog[off + 4] = ng;
       prog[off + 5] = hdr;
       for (int j = 0; j < t; ++j) prog[off + 8 + j] = as.S[j];
@@ -1005,10 +1004,22 @@ static qsv_status build_adjoint_programs(int n, const qsv_op* in_ops, int n_in, 
       bool named = true;
       for (size_t k = k0; k < k1; ++k)
         for (size_t kk : items[k].ks) named = named && ops[as.ops[kk]].gate != QSV_MAT;
-      int ntph = 0;
+      int ntph = 0, nrec = 0;
+      // A sign run is held back one item: if a register round follows it,
+      // it rides in that round as a sign block applied at the round's load,
+      // which saves the LDS pass of its own record.
+      std::vector<int32_t> psign;
+      size_t psign_len = 0;
+      auto flush_sign = [&]() {
+        if (psign.empty()) return;
+        prog.insert(prog.end(), psign.begin(), psign.end());
+        ++nrec;
+        psign.clear();
+      };
       for (size_t k = k0; k < k1; ++k) {
         const Item& item = items[k];
         std::vector<int32_t> rec(LR, 0);
+        if (item.type != 5 && item.type != 6) flush_sign();
         if (item.type == 6) {
           std::vector<int32_t> rr(8 + kGateWords * item.ks.size(), 0);
           rr[0] = 6;
@@ -1051,7 +1062,14 @@ static qsv_status build_adjoint_programs(int n, const qsv_op* in_ops, int n_in, 
             }
             std::memcpy(gw + 4, mt, sizeof(mt));
           }
+          if (!psign.empty()) {
+            rr[1] = (int32_t)rr.size();
+            rr.insert(rr.end(), psign.begin(), psign.begin() + psign_len);
+            rr[3] = (int32_t)rr.size();
+            psign.clear();
+          }
           prog.insert(prog.end(), rr.begin(), rr.end());
+          ++nrec;
           continue;
         }
         if (item.type == 5) {
@@ -1101,7 +1119,9 @@ static qsv_status build_adjoint_programs(int n, const qsv_op* in_ops, int n_in, 
           rec[2] = (int32_t)lo.size();
           rec[3] = (int32_t)oo.size();
           std::copy(w.begin(), w.end(), rec.begin() + 8);
-          prog.insert(prog.end(), rec.begin(), rec.end());
+          flush_sign();
+          psign = rec;
+          psign_len = 8 + ((w.size() + 7) & ~(size_t)7);
           continue;
         }
         const size_t kk = item.ks[0];
@@ -1165,7 +1185,10 @@ static qsv_status build_adjoint_programs(int n, const qsv_op* in_ops, int n_in, 
         if (rot && rec[0] == 3) return fail(QSV_ERR_STATE, "rotation as a 2-qubit op");
         for (int e = 0; e < nv; ++e) put_cd(rec, e, vals[e]);
         prog.insert(prog.end(), rec.begin(), rec.end());
+        ++nrec;
       }
+      flush_sign();
+      prog[off + 3] = nrec;
       prog[off + 6] = (int32_t)(prog.size() - off);
       prog[off + 7] = ntph;
       prog.insert(prog.end(), map.begin(), map.end());

@@ -62,6 +62,28 @@ def _apply(psi, lam, n, qubits, U):
     O.apply_matrix(lam, n, list(qubits), U)
 
 
+def _sign_run(rec, n, psi, lam, loc, base, idx):
+    """A sign-run block (type-5 layout) applied to both states."""
+    assert int(rec[0]) == 5
+    nd, nlo, noo = int(rec[1]), int(rec[2]), int(rec[3])
+    w = [int(x) for x in rec[8:8 + 2 * (nd + nlo + noo)]]
+    assert len(w) == 2 * (nd + nlo + noo)
+    par = np.zeros(1 << n, dtype=np.int64)
+    for i in range(nd):
+        dist, M = w[2 * i], w[2 * i + 1]
+        par += np.vectorize(lambda v: bin(v).count("1"))(loc & (loc >> dist) & M)
+    for i in range(nlo):
+        lb, oq = w[2 * (nd + i)], w[2 * (nd + i) + 1]
+        on = np.ones_like(idx) if oq < 0 else (base >> oq) & 1
+        par += on * ((loc >> lb) & 1)
+    for i in range(noo):
+        qa, qb = w[2 * (nd + nlo + i)], w[2 * (nd + nlo + i) + 1]
+        par += (base >> qa) & (base >> qb) & 1
+    sg = np.where(par & 1, -1.0, 1.0)
+    psi *= sg
+    lam *= sg
+
+
 def run_program(words, off, n, dtype, psi, lam, grads):
     t, c, nns, nops, ngrad, roff, moff, ntph = (int(x) for x in words[off:off + 8])
     seen_tph = 0
@@ -85,7 +107,12 @@ def run_program(words, off, n, dtype, psi, lam, grads):
             bits = [int(x) for x in words[r + 4:r + 4 + K]]
             assert bits == sorted(bits) and len(set(bits)) == K and max(bits) < t
             ngate = sum((counts >> (8 * j)) & 255 for j in range(K))
-            assert length == 8 + GATE_WORDS * ngate
+            soff = int(words[r + 1])
+            if soff:  # a sign run that precedes the round, applied at its load
+                assert soff == 8 + GATE_WORDS * ngate and length > soff and (length - soff) % 8 == 0
+                _sign_run(words[r + soff:r + length], n, psi, lam, loc, base, idx)
+            else:
+                assert length == 8 + GATE_WORDS * ngate
             last_j = -1
             for e in range(ngate):
                 gw = r + 8 + GATE_WORDS * e
@@ -149,22 +176,7 @@ def run_program(words, off, n, dtype, psi, lam, grads):
             assert a < b and slot < 0
             _apply(psi, lam, n, [S[a], S[b]], U)
         elif typ == 5:
-            nd, nlo, noo = a, b, slot
-            w = [int(x) for x in rec[8:8 + 2 * (nd + nlo + noo)]]
-            par = np.zeros(1 << n, dtype=np.int64)
-            for i in range(nd):
-                dist, M = w[2 * i], w[2 * i + 1]
-                par += np.vectorize(lambda v: bin(v).count("1"))(loc & (loc >> dist) & M)
-            for i in range(nlo):
-                lb, oq = w[2 * (nd + i)], w[2 * (nd + i) + 1]
-                on = np.ones_like(idx) if oq < 0 else (base >> oq) & 1
-                par += on * ((loc >> lb) & 1)
-            for i in range(noo):
-                qa, qb = w[2 * (nd + nlo + i)], w[2 * (nd + nlo + i) + 1]
-                par += (base >> qa) & (base >> qb) & 1
-            sg = np.where(par & 1, -1.0, 1.0)
-            psi *= sg
-            lam *= sg
+            _sign_run(rec, n, psi, lam, loc, base, idx)
         else:
             raise AssertionError("unknown record type %d" % typ)
         r += REC_WORDS

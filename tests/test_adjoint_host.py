@@ -102,7 +102,7 @@ def test_mixed_gates(dtype):
 
 def test_program_uses_rounds_and_sign_runs():
     # the 24-qubit gradient workload's programs hold register rounds and
-    # sign runs, not one record per gate (576 gates)
+    # sign runs (mostly inside the rounds), not one record per gate (576 gates)
     n, layers = 24, 6
     params, _ = qc.gradient_workload(n, layers, qc.SEEDS["c5"])
     ops = qc.rot_ring_ansatz(n, params, layers)
@@ -115,10 +115,14 @@ def test_program_uses_rounds_and_sign_runs():
         for _ in range(nops):
             typ = int(words[r])
             kinds[typ] = kinds.get(typ, 0) + 1
+            if typ == 6 and int(words[r + 1]):
+                kinds["6+5"] = kinds.get("6+5", 0) + 1
             r += int(words[r + 3]) if typ == 6 else AE.REC_WORDS
     # 2: other diagonal gates (single CZs), 5: sign runs, 6: rounds, 7: phases
-    # per tile (RZ on qubits outside a pass's tile, applied by the store)
-    assert set(kinds) <= {2, 5, 6, 7} and kinds.get(6, 0) > 0 and kinds.get(5, 0) > 0, kinds
+    # per tile (RZ on qubits outside a pass's tile, applied by the store);
+    # "6+5": rounds that carry the sign run before them, applied at their load
+    assert set(kinds) <= {2, 5, 6, 7, "6+5"} and kinds.get(6, 0) > 0, kinds
+    assert kinds.get("6+5", 0) > 0 and kinds.get(5, 0) < kinds["6+5"], kinds
     assert kinds.get(7, 0) > 0 and kinds.get(2, 0) < kinds[7], kinds
     assert sum(kinds.values()) < len(ops) // 3, (kinds, len(ops))
 
